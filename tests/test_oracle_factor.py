@@ -1,0 +1,224 @@
+"""Pins of the approximate-mode (SDRP) oracle.
+
+Checked against constructions independent of the oracle's own formulas:
+Pauli expectations from Kronecker-built operators, the SVD of the 2 x 2^{n-1}
+reshaped ket (epsilon is the smaller squared Schmidt coefficient, Eq. schmidt
+read with sqrt(1 - eps)), the per-rounding fidelity 1 - eps (Sec. III-B), and
+hand-solvable states.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import dense, factor
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def pauli_on(n, q, P):
+    return np.kron(np.kron(np.eye(2 ** (n - q - 1)), P), np.eye(2 ** q))
+
+
+def svd_eps(a, n, q):
+    """Smaller squared singular value of the qubit-q / rest bipartition."""
+    t = np.moveaxis(a.reshape((2,) * n), n - 1 - q, 0).reshape(2, -1)
+    s = np.linalg.svd(t, compute_uv=False)
+    return float(s[-1] ** 2)
+
+
+def random_entangled(n, seed):
+    gates = workloads.random_circuit(n, 2, seed)
+    return dense.run_circuit(dense.zero_state(n), n, gates)
+
+
+@pytest.mark.parametrize("n", [2, 4, 6])
+def test_bloch_vector_is_pauli_expectation(n):
+    a = random_entangled(n, n)
+    for q in range(n):
+        want = [np.vdot(a, pauli_on(n, q, P) @ a).real for P in (dense.X, dense.Y, dense.Z)]
+        np.testing.assert_allclose(factor.bloch(a, n, q), want, atol=1e-13)
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 7])
+def test_epsilon_is_smaller_schmidt_weight(n):
+    for seed in range(3):
+        a = random_entangled(n, 10 * n + seed)
+        for q in range(n):
+            eps = factor.epsilon(factor.bloch(a, n, q))
+            assert abs(eps - svd_eps(a, n, q)) < 1e-12
+
+
+def test_projection_fidelity_is_one_minus_eps():
+    n = 6
+    for seed in range(4):
+        a = random_entangled(n, 50 + seed)
+        for t in range(n):
+            r = factor.bloch(a, n, t)
+            eps = factor.epsilon(r)
+            phi = factor.dominant_state(r)
+            rest = factor.project_out(a, n, t, phi)
+            # the product ket phi at bit t, rest on the other bits, by index loop
+            out = np.empty(2 ** n, dtype=complex)
+            for x in range(2 ** n):
+                lo, hi = x & ((1 << t) - 1), x >> (t + 1)
+                out[x] = phi[(x >> t) & 1] * rest[lo | (hi << t)]
+            assert abs(np.vdot(out, out).real - 1.0) < 1e-12
+            assert abs(abs(np.vdot(out, a)) ** 2 - (1.0 - eps)) < 1e-12
+            # phi is the dominant eigenvector of rho_q = (I + r.sigma)/2
+            rho = 0.5 * (np.eye(2) + r[0] * dense.X + r[1] * dense.Y + r[2] * dense.Z)
+            assert abs(np.vdot(phi, rho @ phi).real - (1 + np.linalg.norm(r)) / 2) < 1e-12
+
+
+def load_golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                rows.append([float(v) for v in line.split()])
+    return rows
+
+
+def test_golden_weakly_entangled_pair():
+    """sqrt(1-e)|00> + sqrt(e)|11>: eps = e; rounding at p >= 2e leaves |00>
+    with fidelity 1-e (Eq. schmidt, Eq. sdrp, Sec. III-B)."""
+    for e, p, rounds, F_want in load_golden("sdrp_pair.txt"):
+        st = factor.FactorizedState(2)
+        amps = np.zeros(4, dtype=complex)
+        amps[0], amps[3] = math.sqrt(1 - e), math.sqrt(e)
+        st.subs = [factor.Sub([0, 1], amps)]
+        st.dirty = {0, 1}
+        n_sep = st.try_separate(p)
+        assert st.log[0].eps == pytest.approx(e, abs=1e-14)
+        assert n_sep == int(rounds)
+        assert st.F == pytest.approx(F_want, abs=1e-14)
+        if rounds:
+            np.testing.assert_allclose(st.expand(), [1, 0, 0, 0], atol=1e-14)
+            assert abs(dense.fidelity(st.expand(), amps) - (1 - e)) < 1e-14
+        else:
+            np.testing.assert_allclose(st.expand(), amps, atol=1e-15)
+
+
+def test_product_state_separates_without_loss():
+    n = 5
+    st = factor.FactorizedState(n)
+    for q in range(n):
+        st.apply_gate(("u3", q, 0.3 + q, 1.1 * q, 0.2))
+    # merge everything with CZ then undo it: a product state in one subsystem
+    for q in range(n - 1):
+        st.apply_gate(("cz", q, q + 1))
+    for q in range(n - 2, -1, -1):
+        st.apply_gate(("cz", q, q + 1))
+    assert max(st.sizes()) == n
+    exact = st.expand().copy()
+    st.dirty = set(range(n))
+    assert st.try_separate(0.0) == n - 1
+    assert st.sizes() == [1] * n
+    assert abs(st.F - 1.0) < 1e-12
+    assert abs(dense.fidelity(st.expand(), exact) - 1.0) < 1e-12
+
+
+def test_bell_rounds_only_at_p_one():
+    for p, want in [(0.0, 0), (0.5, 0), (0.99, 0), (1.0, 1)]:
+        st = factor.FactorizedState(2)
+        st.apply_gate(("h", 0))
+        st.apply_gate(("ctrl", (0,), 1, 1, math.pi, 0.0, math.pi))  # CNOT
+        assert st.try_separate(p) == want
+        if want:
+            assert st.F == pytest.approx(0.5, abs=1e-14)
+
+
+def test_fidelity_model_exact_for_disjoint_pairs():
+    """Disjoint pairs each rounded once: the neglected branches stay orthogonal,
+    so F = prod(1 - eps_j) equals |<approx|exact>|^2 (Eq. fid_model)."""
+    n = 8
+    g = np.random.default_rng(3)
+    st = factor.FactorizedState(n)
+    gates = []
+    for q in range(0, n, 2):
+        th = float(g.uniform(0.05, 0.4))
+        gates += [("u3", q, th, 0.0, 0.0), ("ctrl", (q,), 1, q + 1, math.pi, 0.0, math.pi),
+                  ("u3", q, 0.7, 0.2, 0.1), ("u3", q + 1, 1.3, 0.4, 0.9)]
+    exact = dense.run_circuit(dense.zero_state(n), n, gates)
+    st.run(gates, p=0.2)
+    assert len([a for a in st.log if a.rounded]) == n // 2
+    F_exact = dense.fidelity(st.expand(), exact)
+    assert st.F == pytest.approx(F_exact, abs=1e-12)
+    assert st.F < 0.99
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_exact_mode_matches_dense(seed):
+    """At p = 0 only numerically exact separations happen: the factorized run
+    reproduces the dense ket."""
+    n = 7
+    gates = workloads.random_circuit(n, 4, seed)
+    st = factor.FactorizedState(n).run(gates, p=0.0)
+    want = dense.run_circuit(dense.zero_state(n), n, gates)
+    assert abs(st.F - 1.0) < 1e-9
+    assert dense.fidelity(st.expand(), want) > 1 - 1e-10
+
+
+def test_merge_is_kron_and_keeps_reduced_states():
+    st = factor.FactorizedState(4)
+    for q in range(4):
+        st.apply_gate(("u3", q, 0.4 * (q + 1), 0.3, 0.2 * q))
+    st.apply_gate(("iswap", 0, 1))
+    st.apply_gate(("iswap", 2, 3))
+    before = st.expand()
+    rs = []
+    for q in range(4):
+        si, t = st.where(q)
+        S = st.subs[si]
+        rs.append(factor.bloch(S.amps, len(S.qubits), t))
+    si = st.merge(1, 3)
+    S = st.subs[si]
+    assert sorted(S.qubits) == [0, 1, 2, 3]
+    np.testing.assert_allclose(st.expand(), before, atol=1e-14)
+    for q in range(4):
+        t = S.qubits.index(q)
+        np.testing.assert_allclose(factor.bloch(S.amps, 4, t), rs[q], atol=1e-13)
+
+
+def test_eps_invariant_under_local_gates():
+    n = 5
+    a = random_entangled(n, 77)
+    eps0 = [factor.epsilon(factor.bloch(a, n, q)) for q in range(n)]
+    b = dense.apply_1q(a, n, 2, dense.u3(0.9, 0.1, 2.0))
+    b = dense.apply_matrix(b, n, [0, 4], dense.ISWAP)
+    eps1 = [factor.epsilon(factor.bloch(b, n, q)) for q in range(n)]
+    for q in (1, 2, 3):
+        assert abs(eps0[q] - eps1[q]) < 1e-12
+
+
+def test_capacity_error_leaves_state_unchanged():
+    st = factor.FactorizedState(6, max_amps=2 ** 3)
+    st.apply_gate(("h", 0))
+    st.apply_gate(("cz", 0, 1))
+    st.apply_gate(("h", 2))
+    st.apply_gate(("cz", 1, 2))
+    before = st.expand().copy()
+    sizes = st.sizes()
+    with pytest.raises(factor.CapacityError):
+        st.apply_gate(("cz", 2, 3))
+    assert st.sizes() == sizes
+    np.testing.assert_allclose(st.expand(), before, atol=0)
+
+
+def test_decisions_obey_rule_and_F_nonincreasing():
+    n = 10
+    gates = workloads.random_circuit(n, 5, 21)
+    st = factor.FactorizedState(n)
+    Fs = []
+    for g in gates:
+        st.apply_gate(g)
+        if g[0] in ("cz", "iswap"):
+            st.try_separate(0.1)
+        Fs.append(st.F)
+    assert all(b <= a + 1e-15 for a, b in zip(Fs, Fs[1:]))
+    for att in st.log:
+        assert att.rounded == (att.eps <= 0.05 + factor.TAU)
+    assert abs(dense.norm2(st.expand()) - 1) < 1e-12

@@ -1,0 +1,126 @@
+"""Seeded synthetic inputs shared by the oracle-side tests and the GPU path.
+
+This module only draws numbers: basis indices, Gaussian amplitude vectors,
+rotation angles, qubit matchings and gate-type coins. It contains none of the
+simulation arithmetic (no gate matrices, no state updates), so that the FP64
+oracle and the HIP path stay independent and can both consume the same input.
+
+Gate lists are plain tuples, one per gate:
+
+    ("h", q)                      Hadamard on qubit q
+    ("u3", q, theta, phi, lam)    U(theta, phi, lambda) of Sec. III-C
+    ("cp", c, t, theta)           controlled phase e^{i theta} on |11>
+    ("cz", a, b)                  controlled Z
+    ("iswap", a, b)               iSWAP
+    ("swap", a, b)                SWAP
+    ("ctrl", ctrls, cvals, t, theta, phi, lam)
+                                  U3 on t, active when every ctrls[j] equals
+                                  bit j of cvals (0 = anti-control)
+
+Qubit q is bit q of the amplitude index (qubit 0 is the least significant).
+All generators use numpy's PCG64 (`numpy.random.default_rng(seed)`).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+TWO_PI = 2.0 * math.pi
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.default_rng(seed)
+
+
+def basis_index(n: int, seed: int) -> int:
+    """Uniform basis index x in [0, 2^n) for the |x> input of the QFT runs."""
+    return int(rng(seed).integers(0, 2 ** n))
+
+
+def gaussian_state(n: int, seed: int) -> np.ndarray:
+    """i.i.d. complex Gaussian amplitudes, unit norm, complex128, length 2^n."""
+    g = rng(seed)
+    re = g.standard_normal(2 ** n)
+    im = g.standard_normal(2 ** n)
+    a = re + 1j * im
+    a /= np.sqrt(np.vdot(a, a).real)
+    return a
+
+
+def haar_product_angles(n: int, seed: int) -> np.ndarray:
+    """Per-qubit (theta, phi, lambda) with theta = arccos(1 - 2u), phi uniform,
+    lambda = 0: U3(theta, phi, 0)|0> is a Haar-random single-qubit state.
+    Shape (n, 3)."""
+    g = rng(seed)
+    u = g.random(n)
+    theta = np.arccos(1.0 - 2.0 * u)
+    phi = g.uniform(0.0, TWO_PI, n)
+    return np.stack([theta, phi, np.zeros(n)], axis=1)
+
+
+def haar_product_gates(n: int, seed: int) -> list:
+    """Gate list preparing the Haar-random product state from |0...0>."""
+    ang = haar_product_angles(n, seed)
+    return [("u3", q, float(ang[q, 0]), float(ang[q, 1]), float(ang[q, 2]))
+            for q in range(n)]
+
+
+def random_circuit(n: int, layers: int, seed: int, haar: bool = False) -> list:
+    """Layered random circuit: per layer, U3 on every qubit (theta, phi, lambda
+    uniform on [0, 2pi), or Haar when `haar`), then a seeded random perfect
+    matching of the qubits with CZ or iSWAP (probability 1/2 each) per pair.
+    With odd n the leftover qubit idles for that layer."""
+    g = rng(seed)
+    gates: list = []
+    for _ in range(layers):
+        ang = g.uniform(0.0, TWO_PI, (n, 3))
+        if haar:
+            ang[:, 0] = np.arccos(1.0 - 2.0 * g.random(n))
+        perm = g.permutation(n)
+        coin = g.random(n // 2) < 0.5
+        for q in range(n):
+            gates.append(("u3", q, float(ang[q, 0]), float(ang[q, 1]), float(ang[q, 2])))
+        for i in range(n // 2):
+            a, b = int(perm[2 * i]), int(perm[2 * i + 1])
+            gates.append(("cz", a, b) if coin[i] else ("iswap", a, b))
+    return gates
+
+
+def random_gate_soup(n: int, count: int, seed: int, kinds=None) -> list:
+    """Unstructured gate sequence over every gate kind, for parity tests."""
+    g = rng(seed)
+    kinds = kinds or ["h", "u3", "cp", "cz", "iswap", "swap", "ctrl"]
+    gates: list = []
+    for _ in range(count):
+        k = kinds[int(g.integers(0, len(kinds)))]
+        if k == "h":
+            gates.append(("h", int(g.integers(0, n))))
+        elif k == "u3":
+            t, p, l = g.uniform(0.0, TWO_PI, 3)
+            gates.append(("u3", int(g.integers(0, n)), float(t), float(p), float(l)))
+        elif k in ("cp", "cz", "iswap", "swap"):
+            a, b = (int(v) for v in g.choice(n, 2, replace=False))
+            if k == "cp":
+                gates.append(("cp", a, b, float(g.uniform(0.0, TWO_PI))))
+            else:
+                gates.append((k, a, b))
+        elif k == "ctrl":
+            nc = int(g.integers(1, min(3, n - 1) + 1))
+            qs = [int(v) for v in g.choice(n, nc + 1, replace=False)]
+            cv = int(g.integers(0, 2 ** nc))
+            t, p, l = g.uniform(0.0, TWO_PI, 3)
+            gates.append(("ctrl", tuple(qs[:nc]), cv, qs[nc], float(t), float(p), float(l)))
+    return gates
+
+
+def batch_widths(count: int, seed: int, low: int = 12, high: int = 20) -> list:
+    """Widths n_i = low + U{0..high-low} of a batch of small circuits."""
+    g = rng(seed)
+    return [int(low + v) for v in g.integers(0, high - low + 1, count)]
+
+
+def qft_gate_counts(n: int) -> dict:
+    """Gate counts of the n-qubit QFT circuit: n H, n(n-1)/2 controlled
+    phases and floor(n/2) SWAPs of the final bit reversal."""
+    return {"h": n, "cp": n * (n - 1) // 2, "swap": n // 2}
