@@ -1,0 +1,188 @@
+/*
+ * qs.h -- C ABI of the MI355X (gfx950) state-vector simulator.
+ *
+ * The library computes |psi_C> = C |psi_0> for an n-qubit ket stored as 2^n
+ * complex amplitudes (Sec. II of the paper: Schroedinger picture, circuits of
+ * k-local gates), including the quantum Fourier transform of Eqs. qft/dft, and
+ * the approximate mode of Sec. III (factorized ket, one-qubit Schmidt test and
+ * SDRP rounding of Eq. sdrp, fidelity model of Eq. fid_model).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Qubit q is bit q of the amplitude index; qubit 0 is the least significant.
+ *  - Every call returns an int status: QS_OK (0) or a negative QS_E_* code.
+ *    Nothing aborts, throws across the ABI or prints. After an error,
+ *    qs_last_error() returns a message for the calling thread.
+ *  - Gate calls are asynchronous on the state's stream (qs_set_stream). Calls
+ *    that return host data synchronize that stream before returning.
+ *  - Host arrays passed in are owned by the caller and are read before the
+ *    call returns; host arrays passed out are written before it returns.
+ *    Device memory of a state is owned by the state and freed by qs_free.
+ *  - Gate matrices are host double arrays, complex interleaved (re, im),
+ *    row-major. For a k-qubit matrix, row/column bit j belongs to qubits[j].
+ *  - After QS_E_DEVICE (a HIP runtime error) the state is poisoned: every
+ *    later call on it except qs_free returns QS_E_DEVICE.
+ */
+#ifndef QS_H
+#define QS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qs_state qs_state;
+
+/* amplitude storage types */
+enum { QS_C64 = 1,   /* complex float: interleaved (re, im) float32, 8 B  */
+       QS_C128 = 2   /* complex double: interleaved (re, im) float64, 16 B */ };
+
+/* status codes */
+enum {
+  QS_OK = 0,
+  QS_E_INVAL = -1,       /* bad argument: qubit out of range, duplicate qubit,
+                            NULL pointer, unknown dtype, k too large,
+                            non-finite matrix entry, size mismatch */
+  QS_E_NOMEM = -2,       /* device allocation failed; the state is unchanged */
+  QS_E_CAPACITY = -3,    /* a merge would exceed the amplitude cap; unchanged */
+  QS_E_DEVICE = -4,      /* HIP runtime error; the state is poisoned */
+  QS_E_NUMERIC = -5,     /* norm drift beyond the tolerance given to qs_check */
+  QS_E_UNSUPPORTED = -6  /* valid request this build does not serve */
+};
+
+#define QS_MAX_QUBITS 34       /* dense states: 2^34 c64 amplitudes = 128 GiB */
+#define QS_MAX_FUSED 6         /* largest k of qs_apply_fused */
+
+/* ------------------------------------------------------------ errors */
+
+/* Message of the last failing call on this thread ("" if none). The pointer
+ * stays valid until the next failing call on the same thread. */
+const char* qs_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int qs_version(void);
+
+/* ------------------------------------------------------------ memory */
+
+/* Device allocator hooks, process-wide. alloc_fn returns device memory of at
+ * least `bytes` bytes (256-B aligned) or NULL; free_fn releases it. `user` is
+ * passed through. NULL for both restores hipMalloc/hipFree. Must not be
+ * changed while any state is alive. */
+typedef void* (*qs_alloc_fn)(size_t bytes, void* user);
+typedef void (*qs_free_fn)(void* ptr, void* user);
+int qs_set_allocator(qs_alloc_fn alloc_fn, qs_free_fn free_fn, void* user);
+
+/* ------------------------------------------------------------ lifecycle */
+
+/* Dense state of n qubits (1 <= n <= QS_MAX_QUBITS) in |0...0>.
+ * dtype is QS_C64 or QS_C128. On success *out owns 2^n amplitudes of device
+ * memory. QS_E_NOMEM if the allocation fails (then *out is untouched). */
+int qs_alloc(int n, int dtype, qs_state** out);
+
+/* Release a state and its device memory (waits for its stream first).
+ * NULL is accepted and ignored. */
+int qs_free(qs_state* st);
+
+/* Bind the HIP stream (a hipStream_t passed as void*) on which every later
+ * kernel of this state is launched. Not owned; NULL means the null stream. */
+int qs_set_stream(qs_state* st, void* hip_stream);
+
+/* Wait until all work queued for this state has finished. */
+int qs_synchronize(qs_state* st);
+
+/* Number of qubits and storage type of a state. */
+int qs_info(const qs_state* st, int* n, int* dtype);
+
+/* ------------------------------------------------------------ initial states */
+
+/* |x>, 0 <= x < 2^n. Clears any pending qubit relabelling. */
+int qs_set_basis(qs_state* st, uint64_t x);
+
+/* Upload 2^n amplitudes (count must equal 2^n) from host memory; host_dtype
+ * QS_C64 or QS_C128, converted to the state's type on the device. The vector
+ * is taken as given (not renormalized). Clears any pending relabelling. */
+int qs_set_amplitudes(qs_state* st, const void* host, uint64_t count, int host_dtype);
+
+/* ------------------------------------------------------------ gates (Sec. II) */
+
+/* Any 2x2 matrix m (re00, im00, re01, im01, re10, im10, re11, im11) on qubit q:
+ * for every index pair (i, i + 2^q) with bit q of i clear,
+ * (a_i, a_{i+2^q}) <- m (a_i, a_{i+2^q}). */
+int qs_apply_1q(qs_state* st, int q, const double m[8]);
+
+/* Controlled 2x2: applies m to `target` on the amplitudes whose control bits
+ * match: bit j of ctrl_values is the required value of ctrls[j] (1 = control,
+ * 0 = anti-control, the "A" couplers of Sec. III-C). 1 <= nctrl <= 8. */
+int qs_apply_ctrl(qs_state* st, const int* ctrls, int nctrl, uint64_t ctrl_values,
+                  int target, const double m[8]);
+
+/* Controlled phase: multiplies every amplitude with bits a and b both set by
+ * e^{i theta} (the controlled R_Z-type phase of the QFT circuit, Sec. II-E). */
+int qs_apply_cphase(qs_state* st, int a, int b, double theta);
+
+/* SWAP of qubits a and b in O(1) by exchanging their labels (Table I: "SWAP
+ * gate is constant complexity"). Amplitudes are moved only when a later call
+ * needs the identity labelling (readout, QFT on a permuted range). */
+int qs_apply_swap(qs_state* st, int a, int b);
+
+/* Dense k-qubit block (1 <= k <= QS_MAX_FUSED): m is 2^k x 2^k complex
+ * (2*4^k doubles), row/column bit j <-> qubits[j]. For every assignment of the
+ * other n-k bits, the 2^k amplitudes that differ only in `qubits` are
+ * multiplied by m. Blocks of k >= 4 run on the FP32/FP64 matrix cores. */
+int qs_apply_fused(qs_state* st, const int* qubits, int k, const double* m);
+
+/* Quantum Fourier transform (Eq. dft, omega = e^{+2 pi i / N}) on qubits
+ * start .. start+len-1, including the final bit reversal (done as a
+ * relabelling). inverse != 0 applies the inverse transform. */
+int qs_qft(qs_state* st, int start, int len, int inverse);
+
+/* ------------------------------------------------------------ readout */
+
+/* All 2^n amplitudes in index order (relabelling undone), converted to
+ * out_dtype (QS_C64 or QS_C128). count must equal 2^n. Synchronizes. */
+int qs_amplitudes(qs_state* st, void* host_out, uint64_t count, int out_dtype);
+
+/* Amplitudes at m indices (each < 2^n) as complex double, interleaved
+ * (2*m doubles). Synchronizes. */
+int qs_amplitudes_gather(qs_state* st, const uint64_t* idx, uint64_t m, double* out);
+
+/* |a_x|^2 for every x in index order, accumulated in float64. count = 2^n.
+ * Synchronizes. */
+int qs_probs(qs_state* st, double* out, uint64_t count);
+
+/* Squared norm sum |a_x|^2, accumulated in float64 in a fixed reduction order
+ * (bitwise repeatable). Synchronizes. */
+int qs_norm(qs_state* st, double* out);
+
+/* QS_E_NUMERIC if |norm - 1| > tol, else QS_OK. Synchronizes. */
+int qs_check(qs_state* st, double tol);
+
+/* ------------------------------------------------------------ timing */
+
+/* Aggregated timing of one kernel kind between qs_profile_start and
+ * qs_profile_stop: number of launches, summed duration measured with HIP
+ * events on the state's stream, and summed algorithmic bytes (the bytes the
+ * operation must read plus write: 2 * 2^n amplitudes for a full sweep). */
+typedef struct {
+  char name[48];
+  uint64_t launches;
+  double total_ms;
+  double bytes;
+} qs_kernel_stat;
+
+/* Start recording every kernel launch of this state (synchronizes first;
+ * discards earlier records). Adds two event records per launch. */
+int qs_profile_start(qs_state* st);
+
+/* Stop recording, synchronize, and aggregate per kernel kind into out
+ * (at most max_out kinds, in first-launch order); *count receives the number
+ * of kinds written. */
+int qs_profile_stop(qs_state* st, qs_kernel_stat* out, int max_out, int* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QS_H */

@@ -1,0 +1,299 @@
+"""Python binding of libqs.so, the MI355X state-vector simulator.
+
+Argument marshalling only: every operation runs in the HIP kernels behind the
+C ABI declared in include/qs.h. PyTorch supplies device memory (its caching
+allocator, through the library's allocator hooks) and the stream on which the
+library launches its work. There is no CPU fallback: if the library is not
+built or no GPU is visible, `load()` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqs.so")
+
+C64, C128 = 1, 2
+OK, E_INVAL, E_NOMEM, E_CAPACITY, E_DEVICE, E_NUMERIC, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+MAX_FUSED = 6
+
+_ERRNAMES = {E_INVAL: "QS_E_INVAL", E_NOMEM: "QS_E_NOMEM", E_CAPACITY: "QS_E_CAPACITY",
+             E_DEVICE: "QS_E_DEVICE", E_NUMERIC: "QS_E_NUMERIC", E_UNSUPPORTED: "QS_E_UNSUPPORTED"}
+
+
+class QSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class CapacityError(QSError):
+    pass
+
+
+_lib = None
+_alloc_cb = None
+_free_cb = None
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+
+
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_uint64), ("total_ms", C.c_double),
+                ("bytes", C.c_double)]
+
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+# (name, restype, argtypes) of every exported entry point
+_SIGS = [
+    ("qs_last_error", C.c_char_p, []),
+    ("qs_version", C.c_int, []),
+    ("qs_set_allocator", C.c_int, [_ALLOC_FN, _FREE_FN, C.c_void_p]),
+    ("qs_alloc", C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_void_p)]),
+    ("qs_free", C.c_int, [C.c_void_p]),
+    ("qs_set_stream", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("qs_synchronize", C.c_int, [C.c_void_p]),
+    ("qs_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    ("qs_set_basis", C.c_int, [C.c_void_p, C.c_uint64]),
+    ("qs_set_amplitudes", C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_int]),
+    ("qs_apply_1q", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double)]),
+    ("qs_apply_ctrl", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.c_int, C.c_uint64, C.c_int,
+                                C.POINTER(C.c_double)]),
+    ("qs_apply_cphase", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_double]),
+    ("qs_apply_swap", C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    ("qs_apply_fused", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_double)]),
+    ("qs_qft", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
+    ("qs_amplitudes", C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_int]),
+    ("qs_amplitudes_gather", C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.c_uint64,
+                                       C.POINTER(C.c_double)]),
+    ("qs_probs", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_uint64]),
+    ("qs_norm", C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    ("qs_check", C.c_int, [C.c_void_p, C.c_double]),
+    ("qs_profile_start", C.c_int, [C.c_void_p]),
+    ("qs_profile_stop", C.c_int, [C.c_void_p, C.POINTER(KernelStat), C.c_int, C.POINTER(C.c_int)]),
+]
+
+
+def exported_names() -> list:
+    return [s[0] for s in _SIGS]
+
+
+def open_library(path: str = LIB_PATH) -> C.CDLL:
+    """dlopen libqs.so and attach prototypes (no GPU needed)."""
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run paper_2304_14969_amd.build.build()")
+    lib = C.CDLL(path)
+    for name, res, args in _SIGS:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+def load(use_torch_allocator: bool = True) -> C.CDLL:
+    """Open the library for GPU use. Raises if it is missing or no GPU is visible."""
+    global _lib, _alloc_cb, _free_cb
+    if _lib is not None:
+        return _lib
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the simulator has no CPU path")
+    lib = open_library()
+    if use_torch_allocator:
+        def _alloc(nbytes, _user):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes))
+            except RuntimeError:
+                return None
+
+        def _free(ptr, _user):
+            torch.cuda.caching_allocator_delete(ptr)
+        _alloc_cb, _free_cb = _ALLOC_FN(_alloc), _FREE_FN(_free)
+        _check(lib, lib.qs_set_allocator(_alloc_cb, _free_cb, None))
+    _lib = lib
+    return lib
+
+
+def _check(lib, rc: int):
+    if rc != OK:
+        msg = lib.qs_last_error().decode(errors="replace")
+        if rc == E_CAPACITY:
+            raise CapacityError(rc, msg)
+        raise QSError(rc, msg)
+
+
+def _dptr(arr: np.ndarray):
+    return arr.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def mat_arg(m) -> np.ndarray:
+    """Complex matrix -> contiguous float64 (re, im) interleaved, row-major."""
+    m = np.ascontiguousarray(np.asarray(m, dtype=np.complex128))
+    return np.ascontiguousarray(m.view(np.float64).reshape(-1))
+
+
+class State:
+    """A dense n-qubit ket on the GPU (owned by the library)."""
+
+    def __init__(self, n: int, dtype: int = C64, stream=None):
+        self.lib = load()
+        h = C.c_void_p()
+        _check(self.lib, self.lib.qs_alloc(n, dtype, C.byref(h)))
+        self.h = h
+        self.n = n
+        self.dtype = dtype
+        self.set_stream(stream)
+
+    # -- lifecycle
+    def set_stream(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = s
+        _check(self.lib, self.lib.qs_set_stream(self.h, C.c_void_p(s.cuda_stream)))
+
+    def free(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            _check(self.lib, self.lib.qs_free(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()
+
+    def synchronize(self):
+        _check(self.lib, self.lib.qs_synchronize(self.h))
+
+    # -- initial states
+    def set_basis(self, x: int):
+        _check(self.lib, self.lib.qs_set_basis(self.h, int(x)))
+
+    def set_amplitudes(self, a: np.ndarray):
+        a = np.ascontiguousarray(a)
+        if a.dtype == np.complex128:
+            dt = C128
+        elif a.dtype == np.complex64:
+            dt = C64
+        else:
+            raise TypeError("amplitudes must be complex64 or complex128")
+        _check(self.lib, self.lib.qs_set_amplitudes(self.h, a.ctypes.data, a.size, dt))
+
+    # -- gates
+    def apply_1q(self, q: int, m):
+        _check(self.lib, self.lib.qs_apply_1q(self.h, q, _dptr(mat_arg(m))))
+
+    def apply_ctrl(self, ctrls, cvals: int, target: int, m):
+        c = (C.c_int * len(ctrls))(*ctrls)
+        _check(self.lib, self.lib.qs_apply_ctrl(self.h, c, len(ctrls), int(cvals), target,
+                                                _dptr(mat_arg(m))))
+
+    def apply_cphase(self, a: int, b: int, theta: float):
+        _check(self.lib, self.lib.qs_apply_cphase(self.h, a, b, float(theta)))
+
+    def apply_swap(self, a: int, b: int):
+        _check(self.lib, self.lib.qs_apply_swap(self.h, a, b))
+
+    def apply_fused(self, qubits, m):
+        qs = (C.c_int * len(qubits))(*qubits)
+        _check(self.lib, self.lib.qs_apply_fused(self.h, qs, len(qubits), _dptr(mat_arg(m))))
+
+    def qft(self, start: int = 0, length: int | None = None, inverse: bool = False):
+        length = self.n - start if length is None else length
+        _check(self.lib, self.lib.qs_qft(self.h, start, length, int(bool(inverse))))
+
+    # -- readout
+    def amplitudes(self, dtype=np.complex128) -> np.ndarray:
+        out = np.empty(2 ** self.n, dtype=dtype)
+        dt = C128 if out.dtype == np.complex128 else C64
+        _check(self.lib, self.lib.qs_amplitudes(self.h, out.ctypes.data, out.size, dt))
+        return out
+
+    def gather(self, idx) -> np.ndarray:
+        idx = np.ascontiguousarray(np.asarray(idx, dtype=np.uint64))
+        out = np.empty(idx.size, dtype=np.complex128)
+        _check(self.lib, self.lib.qs_amplitudes_gather(
+            self.h, idx.ctypes.data_as(C.POINTER(C.c_uint64)), idx.size,
+            out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def probs(self) -> np.ndarray:
+        out = np.empty(2 ** self.n, dtype=np.float64)
+        _check(self.lib, self.lib.qs_probs(self.h, _dptr(out), out.size))
+        return out
+
+    def norm(self) -> float:
+        v = C.c_double()
+        _check(self.lib, self.lib.qs_norm(self.h, C.byref(v)))
+        return v.value
+
+    def check(self, tol: float):
+        _check(self.lib, self.lib.qs_check(self.h, float(tol)))
+
+    # -- timing
+    def profile_start(self):
+        _check(self.lib, self.lib.qs_profile_start(self.h))
+
+    def profile_stop(self) -> dict:
+        """{kernel: {"launches", "total_ms", "bytes"}} since profile_start."""
+        buf = (KernelStat * 64)()
+        cnt = C.c_int()
+        _check(self.lib, self.lib.qs_profile_stop(self.h, buf, 64, C.byref(cnt)))
+        return {buf[i].name.decode(): {"launches": int(buf[i].launches),
+                                       "total_ms": float(buf[i].total_ms),
+                                       "bytes": float(buf[i].bytes)} for i in range(cnt.value)}
+
+
+# ------------------------------------------------------------------ gate lists
+
+_H = np.array([[1, 1], [1, -1]], dtype=np.complex128) / math.sqrt(2.0)
+
+
+def u3_matrix(theta: float, phi: float, lam: float) -> np.ndarray:
+    """U(theta, phi, lambda) of Sec. III-C, built in float64 on the host."""
+    c, s = math.cos(theta / 2), math.sin(theta / 2)
+    return np.array([[c, -complex(math.cos(lam), math.sin(lam)) * s],
+                     [complex(math.cos(phi), math.sin(phi)) * s,
+                      complex(math.cos(phi + lam), math.sin(phi + lam)) * c]], dtype=np.complex128)
+
+
+_CZ = np.diag([1, 1, 1, -1]).astype(np.complex128)
+_ISWAP = np.array([[1, 0, 0, 0], [0, 0, 1j, 0], [0, 1j, 0, 0], [0, 0, 0, 1]], dtype=np.complex128)
+
+
+def apply_gate(st: State, g):
+    """Dispatch one gate tuple (the workloads gate-list format) to the library."""
+    k = g[0]
+    if k == "h":
+        st.apply_1q(g[1], _H)
+    elif k == "u3":
+        st.apply_1q(g[1], u3_matrix(g[2], g[3], g[4]))
+    elif k == "cp":
+        st.apply_cphase(g[1], g[2], g[3])
+    elif k == "cz":
+        st.apply_cphase(g[1], g[2], math.pi)
+    elif k == "iswap":
+        st.apply_fused([g[1], g[2]], _ISWAP)
+    elif k == "swap":
+        st.apply_swap(g[1], g[2])
+    elif k == "ctrl":
+        st.apply_ctrl(list(g[1]), g[2], g[3], u3_matrix(g[4], g[5], g[6]))
+    elif k == "mat":
+        st.apply_fused(list(g[1]), g[2])
+    else:
+        raise ValueError(f"unknown gate {k!r}")
+
+
+def run_gates(st: State, gates):
+    for g in gates:
+        apply_gate(st, g)

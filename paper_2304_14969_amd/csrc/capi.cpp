@@ -1,0 +1,618 @@
+// C ABI of the simulator: argument checks, state handles, the qubit relabel
+// map and dispatch to the HIP kernels. No simulation arithmetic happens here
+// beyond building small gate matrices and twiddle tables on the host in
+// float64 and rounding them once to the state's precision.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/qs.h"
+#include "qs_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+// ------------------------------------------------------------------ allocator
+qs_alloc_fn g_alloc = nullptr;
+qs_free_fn g_free = nullptr;
+void* g_user = nullptr;
+int g_live_states = 0;
+
+void* dev_alloc(size_t bytes) {
+  if (g_alloc) return g_alloc(bytes, g_user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void dev_free(void* p) {
+  if (!p) return;
+  if (g_free) {
+    g_free(p, g_user);
+  } else {
+    (void)hipFree(p);
+  }
+}
+
+constexpr size_t kMatBytes = size_t(2) * (1u << 6) * (1u << 6) * sizeof(double);
+constexpr uint64_t kStageAmps = uint64_t(1) << 22;  // staging chunk for host transfers
+
+}  // namespace
+
+// Per-launch timing: while enabled, every kernel launch of a state is
+// bracketed by two HIP events on the state's stream and tagged with its name
+// and algorithmic bytes.
+struct ProfRec {
+  const char* name;
+  double bytes;
+  hipEvent_t a, b;
+};
+
+struct qs_state {
+  int n = 0;
+  int dtype = QS_C64;
+  void* amps = nullptr;
+  hipStream_t stream = nullptr;
+  int perm[64];          // logical qubit -> physical bit
+  bool poisoned = false;
+  void* mat = nullptr;   // device slot for gate matrices
+  double* red = nullptr; // reduction scratch: partials + result
+  bool prof = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+uint64_t dim(const qs_state* st) { return uint64_t(1) << st->n; }
+size_t amp_bytes(int dtype) { return dtype == QS_C64 ? 8 : 16; }
+double ab(const qs_state* st) { return double(amp_bytes(st->dtype)); }
+
+int check_state(const qs_state* st) {
+  if (!st) return fail(QS_E_INVAL, "state is NULL");
+  if (st->poisoned) return fail(QS_E_DEVICE, "state is unusable after an earlier device error");
+  return QS_OK;
+}
+
+int device_error(qs_state* st, hipError_t e, const char* what) {
+  if (e == hipSuccess) return QS_OK;
+  if (st) st->poisoned = true;
+  return fail(QS_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int check_qubit(const qs_state* st, int q, const char* name) {
+  if (q < 0 || q >= st->n)
+    return fail(QS_E_INVAL, "%s %d out of range [0, %d)", name, q, st->n);
+  return QS_OK;
+}
+
+int check_finite(const double* v, size_t count) {
+  if (!v) return fail(QS_E_INVAL, "matrix pointer is NULL");
+  for (size_t i = 0; i < count; ++i)
+    if (!std::isfinite(v[i])) return fail(QS_E_INVAL, "matrix entry %zu is not finite", i);
+  return QS_OK;
+}
+
+template <typename R>
+qs::Mat2<R> to_mat2(const double m[8]) {
+  qs::Mat2<R> out;
+  for (int e = 0; e < 4; ++e) {
+    out.re[e] = static_cast<R>(m[2 * e]);
+    out.im[e] = static_cast<R>(m[2 * e + 1]);
+  }
+  return out;
+}
+
+hipEvent_t pool_event(qs_state* st) {
+  if (!st->pool.empty()) {
+    hipEvent_t e = st->pool.back();
+    st->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch when profiling is on.
+struct ProfScope {
+  qs_state* st;
+  bool on;
+  ProfScope(qs_state* s, const char* name, double bytes) : st(s), on(s->prof) {
+    if (!on) return;
+    ProfRec r{name, bytes, pool_event(st), pool_event(st)};
+    if (!r.a || !r.b) {
+      on = false;
+      return;
+    }
+    (void)hipEventRecord(r.a, st->stream);
+    st->recs.push_back(r);
+  }
+  ~ProfScope() {
+    if (on) (void)hipEventRecord(st->recs.back().b, st->stream);
+  }
+};
+
+// Physical exchange of bits pa and pb.
+int phys_swap(qs_state* st, int pa, int pb) {
+  ProfScope ps(st, "bitswap", 2.0 * std::ldexp(1.0, st->n - 1) * ab(st));
+  hipError_t e;
+  if (st->dtype == QS_C64)
+    e = qs::launch_bitswap(static_cast<float*>(st->amps), st->n, pa, pb, st->stream);
+  else
+    e = qs::launch_bitswap(static_cast<double*>(st->amps), st->n, pa, pb, st->stream);
+  return device_error(st, e, "bit swap");
+}
+
+// Move amplitudes so that logical qubit q sits at physical bit q again.
+int materialize(qs_state* st) {
+  for (int q = 0; q < st->n; ++q) {
+    if (st->perm[q] == q) continue;
+    int q2 = -1;  // logical qubit currently at physical bit q
+    for (int k = 0; k < st->n; ++k)
+      if (st->perm[k] == q) q2 = k;
+    const int p = st->perm[q];
+    int rc = phys_swap(st, p, q);
+    if (rc) return rc;
+    st->perm[q] = q;
+    st->perm[q2] = p;
+  }
+  return QS_OK;
+}
+
+void reset_perm(qs_state* st) {
+  for (int q = 0; q < 64; ++q) st->perm[q] = q;
+}
+
+int sync(qs_state* st, const char* what) {
+  return device_error(st, hipStreamSynchronize(st->stream), what);
+}
+
+
+}  // namespace
+
+extern "C" {
+
+const char* qs_last_error(void) { return g_err.c_str(); }
+
+int qs_version(void) { return 100; }
+
+int qs_set_allocator(qs_alloc_fn alloc_fn, qs_free_fn free_fn, void* user) {
+  if ((alloc_fn == nullptr) != (free_fn == nullptr))
+    return fail(QS_E_INVAL, "allocator and free function must both be set or both be NULL");
+  if (g_live_states) return fail(QS_E_INVAL, "allocator cannot change while states are alive");
+  g_alloc = alloc_fn;
+  g_free = free_fn;
+  g_user = user;
+  return QS_OK;
+}
+
+int qs_alloc(int n, int dtype, qs_state** out) {
+  if (!out) return fail(QS_E_INVAL, "out is NULL");
+  if (n < 1 || n > QS_MAX_QUBITS) return fail(QS_E_INVAL, "n = %d outside [1, %d]", n, QS_MAX_QUBITS);
+  if (dtype != QS_C64 && dtype != QS_C128) return fail(QS_E_INVAL, "unknown dtype %d", dtype);
+  qs_state* st = new qs_state();
+  st->n = n;
+  st->dtype = dtype;
+  reset_perm(st);
+  const size_t bytes = size_t(1) << n;
+  st->amps = dev_alloc(bytes * amp_bytes(dtype));
+  st->mat = dev_alloc(kMatBytes);
+  st->red = static_cast<double*>(dev_alloc(sizeof(double) * (qs::reduce_blocks(0) + 1)));
+  if (!st->amps || !st->mat || !st->red) {
+    dev_free(st->amps);
+    dev_free(st->mat);
+    dev_free(st->red);
+    delete st;
+    return fail(QS_E_NOMEM, "device allocation of %zu bytes failed", bytes * amp_bytes(dtype));
+  }
+  ++g_live_states;
+  hipError_t e = dtype == QS_C64
+                     ? qs::launch_set_basis(static_cast<float*>(st->amps), n, 0, st->stream)
+                     : qs::launch_set_basis(static_cast<double*>(st->amps), n, 0, st->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+  if (e != hipSuccess) {
+    dev_free(st->amps);
+    dev_free(st->mat);
+    dev_free(st->red);
+    delete st;
+    --g_live_states;
+    return fail(QS_E_DEVICE, "initialising the state: %s", hipGetErrorString(e));
+  }
+  *out = st;
+  return QS_OK;
+}
+
+int qs_free(qs_state* st) {
+  if (!st) return QS_OK;
+  (void)hipStreamSynchronize(st->stream);
+  dev_free(st->amps);
+  dev_free(st->mat);
+  dev_free(st->red);
+  for (auto& r : st->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : st->pool) (void)hipEventDestroy(e);
+  delete st;
+  --g_live_states;
+  return QS_OK;
+}
+
+int qs_set_stream(qs_state* st, void* hip_stream) {
+  if (int rc = check_state(st)) return rc;
+  st->stream = static_cast<hipStream_t>(hip_stream);
+  return QS_OK;
+}
+
+int qs_synchronize(qs_state* st) {
+  if (int rc = check_state(st)) return rc;
+  return sync(st, "synchronize");
+}
+
+int qs_info(const qs_state* st, int* n, int* dtype) {
+  if (!st) return fail(QS_E_INVAL, "state is NULL");
+  if (n) *n = st->n;
+  if (dtype) *dtype = st->dtype;
+  return QS_OK;
+}
+
+int qs_set_basis(qs_state* st, uint64_t x) {
+  if (int rc = check_state(st)) return rc;
+  if (x >= dim(st)) return fail(QS_E_INVAL, "basis index %llu >= 2^%d", (unsigned long long)x, st->n);
+  reset_perm(st);
+  hipError_t e = st->dtype == QS_C64
+                     ? qs::launch_set_basis(static_cast<float*>(st->amps), st->n, x, st->stream)
+                     : qs::launch_set_basis(static_cast<double*>(st->amps), st->n, x, st->stream);
+  return device_error(st, e, "set basis");
+}
+
+int qs_set_amplitudes(qs_state* st, const void* host, uint64_t count, int host_dtype) {
+  if (int rc = check_state(st)) return rc;
+  if (!host) return fail(QS_E_INVAL, "host pointer is NULL");
+  if (count != dim(st)) return fail(QS_E_INVAL, "count %llu != 2^%d", (unsigned long long)count, st->n);
+  if (host_dtype != QS_C64 && host_dtype != QS_C128) return fail(QS_E_INVAL, "unknown dtype %d", host_dtype);
+  reset_perm(st);
+  const size_t hb = amp_bytes(host_dtype), sb = amp_bytes(st->dtype);
+  if (host_dtype == st->dtype) {
+    hipError_t e = hipMemcpyAsync(st->amps, host, count * hb, hipMemcpyHostToDevice, st->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+    return device_error(st, e, "upload");
+  }
+  const uint64_t chunk = count < kStageAmps ? count : kStageAmps;
+  void* stage = dev_alloc(chunk * hb);
+  if (!stage) return fail(QS_E_NOMEM, "staging allocation failed");
+  hipError_t e = hipSuccess;
+  for (uint64_t off = 0; off < count && e == hipSuccess; off += chunk) {
+    const uint64_t c = count - off < chunk ? count - off : chunk;
+    e = hipMemcpyAsync(stage, static_cast<const char*>(host) + off * hb, c * hb,
+                       hipMemcpyHostToDevice, st->stream);
+    if (e != hipSuccess) break;
+    char* dst = static_cast<char*>(st->amps) + off * sb;
+    if (st->dtype == QS_C64)
+      e = qs::launch_convert(reinterpret_cast<float*>(dst), static_cast<const double*>(stage), c, st->stream);
+    else
+      e = qs::launch_convert(reinterpret_cast<double*>(dst), static_cast<const float*>(stage), c, st->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+  }
+  dev_free(stage);
+  return device_error(st, e, "upload");
+}
+
+// ------------------------------------------------------------------ gates
+
+int qs_apply_1q(qs_state* st, int q, const double m[8]) {
+  if (int rc = check_state(st)) return rc;
+  if (int rc = check_qubit(st, q, "qubit")) return rc;
+  if (int rc = check_finite(m, 8)) return rc;
+  const int t = st->perm[q];
+  ProfScope ps(st, "apply_1q", 2.0 * std::ldexp(1.0, st->n) * ab(st));
+  hipError_t e;
+  if (st->dtype == QS_C64)
+    e = qs::launch_apply_1q(static_cast<float*>(st->amps), st->n, t, to_mat2<float>(m), st->stream);
+  else
+    e = qs::launch_apply_1q(static_cast<double*>(st->amps), st->n, t, to_mat2<double>(m), st->stream);
+  return device_error(st, e, "apply_1q");
+}
+
+int qs_apply_ctrl(qs_state* st, const int* ctrls, int nctrl, uint64_t ctrl_values, int target,
+                  const double m[8]) {
+  if (int rc = check_state(st)) return rc;
+  if (!ctrls && nctrl > 0) return fail(QS_E_INVAL, "ctrls is NULL");
+  if (nctrl < 1 || nctrl > 8) return fail(QS_E_INVAL, "nctrl = %d outside [1, 8]", nctrl);
+  if (int rc = check_qubit(st, target, "target")) return rc;
+  if (int rc = check_finite(m, 8)) return rc;
+  if (nctrl + 1 > st->n) return fail(QS_E_INVAL, "too many qubits for n = %d", st->n);
+  qs::BitSet16 fixed{};
+  uint64_t set_mask = 0, seen = uint64_t(1) << target;
+  for (int j = 0; j < nctrl; ++j) {
+    if (int rc = check_qubit(st, ctrls[j], "control")) return rc;
+    if (seen & (uint64_t(1) << ctrls[j])) return fail(QS_E_INVAL, "qubit %d used twice", ctrls[j]);
+    seen |= uint64_t(1) << ctrls[j];
+    const int p = st->perm[ctrls[j]];
+    fixed.pos[fixed.n++] = p;
+    if ((ctrl_values >> j) & 1) set_mask |= uint64_t(1) << p;
+  }
+  const int tbit = st->perm[target];
+  fixed.pos[fixed.n++] = tbit;
+  for (int i = 1; i < fixed.n; ++i)
+    for (int j = i; j > 0 && fixed.pos[j - 1] > fixed.pos[j]; --j) std::swap(fixed.pos[j], fixed.pos[j - 1]);
+  ProfScope ps(st, "apply_ctrl", 2.0 * std::ldexp(1.0, st->n - nctrl) * ab(st));
+  hipError_t e;
+  if (st->dtype == QS_C64)
+    e = qs::launch_apply_ctrl(static_cast<float*>(st->amps), st->n, fixed, set_mask, tbit,
+                              to_mat2<float>(m), st->stream);
+  else
+    e = qs::launch_apply_ctrl(static_cast<double*>(st->amps), st->n, fixed, set_mask, tbit,
+                              to_mat2<double>(m), st->stream);
+  return device_error(st, e, "apply_ctrl");
+}
+
+int qs_apply_cphase(qs_state* st, int a, int b, double theta) {
+  if (int rc = check_state(st)) return rc;
+  if (int rc = check_qubit(st, a, "qubit a")) return rc;
+  if (int rc = check_qubit(st, b, "qubit b")) return rc;
+  if (a == b) return fail(QS_E_INVAL, "controlled phase needs two distinct qubits");
+  if (!std::isfinite(theta)) return fail(QS_E_INVAL, "theta is not finite");
+  const double cr = std::cos(theta), ci = std::sin(theta);
+  ProfScope ps(st, "cphase", 2.0 * std::ldexp(1.0, st->n - 2) * ab(st));
+  hipError_t e;
+  if (st->dtype == QS_C64)
+    e = qs::launch_cphase(static_cast<float*>(st->amps), st->n, st->perm[a], st->perm[b],
+                          float(cr), float(ci), st->stream);
+  else
+    e = qs::launch_cphase(static_cast<double*>(st->amps), st->n, st->perm[a], st->perm[b], cr, ci,
+                          st->stream);
+  return device_error(st, e, "apply_cphase");
+}
+
+int qs_apply_swap(qs_state* st, int a, int b) {
+  if (int rc = check_state(st)) return rc;
+  if (int rc = check_qubit(st, a, "qubit a")) return rc;
+  if (int rc = check_qubit(st, b, "qubit b")) return rc;
+  std::swap(st->perm[a], st->perm[b]);
+  return QS_OK;
+}
+
+int qs_apply_fused(qs_state* st, const int* qubits, int k, const double* m) {
+  if (int rc = check_state(st)) return rc;
+  if (!qubits) return fail(QS_E_INVAL, "qubits is NULL");
+  if (k < 1 || k > QS_MAX_FUSED || k > st->n)
+    return fail(QS_E_INVAL, "k = %d outside [1, min(%d, n)]", k, QS_MAX_FUSED);
+  const size_t D = size_t(1) << k;
+  if (int rc = check_finite(m, 2 * D * D)) return rc;
+  int phys[QS_MAX_FUSED];
+  uint64_t seen = 0;
+  for (int j = 0; j < k; ++j) {
+    if (int rc = check_qubit(st, qubits[j], "qubit")) return rc;
+    if (seen & (uint64_t(1) << qubits[j])) return fail(QS_E_INVAL, "qubit %d used twice", qubits[j]);
+    seen |= uint64_t(1) << qubits[j];
+    phys[j] = st->perm[qubits[j]];
+  }
+  static const char* names[] = {"", "fused1", "fused2", "fused3", "fused4", "fused5", "fused6"};
+  hipError_t e;
+  if (st->dtype == QS_C64) {
+    std::vector<float> mf(2 * D * D);
+    for (size_t i = 0; i < mf.size(); ++i) mf[i] = static_cast<float>(m[i]);
+    e = hipMemcpyAsync(st->mat, mf.data(), mf.size() * sizeof(float), hipMemcpyHostToDevice, st->stream);
+    if (e == hipSuccess) {
+      ProfScope ps(st, names[k], 2.0 * std::ldexp(1.0, st->n) * ab(st));
+      e = qs::launch_apply_fused(static_cast<float*>(st->amps), st->n, phys, k,
+                                 static_cast<const float*>(st->mat), st->stream);
+    }
+  } else {
+    e = hipMemcpyAsync(st->mat, m, 2 * D * D * sizeof(double), hipMemcpyHostToDevice, st->stream);
+    if (e == hipSuccess) {
+      ProfScope ps(st, names[k], 2.0 * std::ldexp(1.0, st->n) * ab(st));
+      e = qs::launch_apply_fused(static_cast<double*>(st->amps), st->n, phys, k,
+                                 static_cast<const double*>(st->mat), st->stream);
+    }
+  }
+  return device_error(st, e, "apply_fused");
+}
+
+int qs_qft(qs_state* st, int start, int len, int inverse) {
+  if (int rc = check_state(st)) return rc;
+  if (start < 0 || len < 1 || start + len > st->n)
+    return fail(QS_E_INVAL, "qubit range [%d, %d) outside [0, %d)", start, start + len, st->n);
+  // natural order, bit-reversed (left by an earlier transform), or anything
+  // else, which is first moved back to the identity labelling
+  bool identity = true, reversed = true;
+  for (int k = 0; k < len; ++k) {
+    identity &= st->perm[start + k] == start + k;
+    reversed &= st->perm[start + k] == start + len - 1 - k;
+  }
+  if (!identity && !reversed) {
+    if (int rc = materialize(st)) return rc;
+    reversed = false;
+  } else if (identity) {
+    reversed = false;
+  }
+  qs::QftPass plan[64];
+  const int np = st->dtype == QS_C64 ? qs::qft_plan<float>(st->n, start, len, reversed, plan, 64)
+                                     : qs::qft_plan<double>(st->n, start, len, reversed, plan, 64);
+  if (np < 0) return fail(QS_E_UNSUPPORTED, "QFT pass plan failed");
+  const int sign = inverse ? -1 : 1;
+  static const char* pass_names[] = {"qft_lds", "qft_reg1", "qft_reg2", "qft_reg3", "qft_reg4", "qft_reg5"};
+  const int T = st->n < (st->dtype == QS_C64 ? 12 : 11) ? st->n : (st->dtype == QS_C64 ? 12 : 11);
+  for (int k = 0; k < np; ++k) {
+    const int g = plan[k].hi - plan[k].lo;
+    ProfScope ps(st, plan[k].hi <= T ? pass_names[0] : pass_names[g], 2.0 * std::ldexp(1.0, st->n) * ab(st));
+    hipError_t e =
+        st->dtype == QS_C64
+            ? qs::launch_qft_pass(static_cast<float*>(st->amps), st->n, start, len, plan[k].lo,
+                                  plan[k].hi, sign, reversed, plan[k].scale, st->stream)
+            : qs::launch_qft_pass(static_cast<double*>(st->amps), st->n, start, len, plan[k].lo,
+                                  plan[k].hi, sign, reversed, plan[k].scale, st->stream);
+    if (int rc = device_error(st, e, "qft pass")) return rc;
+  }
+  // final bit reversal of the range, as a relabelling
+  for (int i = 0; i < len / 2; ++i) std::swap(st->perm[start + i], st->perm[start + len - 1 - i]);
+  return QS_OK;
+}
+
+// ------------------------------------------------------------------ profiling
+
+int qs_profile_start(qs_state* st) {
+  if (int rc = check_state(st)) return rc;
+  if (int rc = sync(st, "profile start")) return rc;
+  for (auto& r : st->recs) {
+    st->pool.push_back(r.a);
+    st->pool.push_back(r.b);
+  }
+  st->recs.clear();
+  st->prof = true;
+  return QS_OK;
+}
+
+int qs_profile_stop(qs_state* st, qs_kernel_stat* out, int max_out, int* count) {
+  if (int rc = check_state(st)) return rc;
+  if (!count || (max_out > 0 && !out)) return fail(QS_E_INVAL, "NULL output");
+  st->prof = false;
+  if (int rc = sync(st, "profile stop")) return rc;
+  int nk = 0;
+  for (auto& r : st->recs) {
+    float ms = 0.f;
+    hipError_t e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) return device_error(st, e, "event timing");
+    int k = 0;
+    while (k < nk && std::strcmp(out[k].name, r.name) != 0) ++k;
+    if (k == nk) {
+      if (nk >= max_out) continue;
+      std::memset(&out[k], 0, sizeof out[k]);
+      std::snprintf(out[k].name, sizeof out[k].name, "%s", r.name);
+      ++nk;
+    }
+    out[k].launches += 1;
+    out[k].total_ms += ms;
+    out[k].bytes += r.bytes;
+  }
+  for (auto& r : st->recs) {
+    st->pool.push_back(r.a);
+    st->pool.push_back(r.b);
+  }
+  st->recs.clear();
+  *count = nk;
+  return QS_OK;
+}
+
+// ------------------------------------------------------------------ readout
+
+int qs_amplitudes(qs_state* st, void* host_out, uint64_t count, int out_dtype) {
+  if (int rc = check_state(st)) return rc;
+  if (!host_out) return fail(QS_E_INVAL, "output pointer is NULL");
+  if (count != dim(st)) return fail(QS_E_INVAL, "count %llu != 2^%d", (unsigned long long)count, st->n);
+  if (out_dtype != QS_C64 && out_dtype != QS_C128) return fail(QS_E_INVAL, "unknown dtype %d", out_dtype);
+  if (int rc = materialize(st)) return rc;
+  const size_t ob = amp_bytes(out_dtype), sb = amp_bytes(st->dtype);
+  if (out_dtype == st->dtype) {
+    hipError_t e = hipMemcpyAsync(host_out, st->amps, count * sb, hipMemcpyDeviceToHost, st->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+    return device_error(st, e, "download");
+  }
+  const uint64_t chunk = count < kStageAmps ? count : kStageAmps;
+  void* stage = dev_alloc(chunk * ob);
+  if (!stage) return fail(QS_E_NOMEM, "staging allocation failed");
+  hipError_t e = hipSuccess;
+  for (uint64_t off = 0; off < count && e == hipSuccess; off += chunk) {
+    const uint64_t c = count - off < chunk ? count - off : chunk;
+    const char* src = static_cast<const char*>(st->amps) + off * sb;
+    if (out_dtype == QS_C128)
+      e = qs::launch_convert(static_cast<double*>(stage), reinterpret_cast<const float*>(src), c, st->stream);
+    else
+      e = qs::launch_convert(static_cast<float*>(stage), reinterpret_cast<const double*>(src), c, st->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(static_cast<char*>(host_out) + off * ob, stage, c * ob, hipMemcpyDeviceToHost, st->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+  }
+  dev_free(stage);
+  return device_error(st, e, "download");
+}
+
+int qs_amplitudes_gather(qs_state* st, const uint64_t* idx, uint64_t m, double* out) {
+  if (int rc = check_state(st)) return rc;
+  if (m == 0) return QS_OK;
+  if (!idx || !out) return fail(QS_E_INVAL, "NULL pointer");
+  for (uint64_t j = 0; j < m; ++j)
+    if (idx[j] >= dim(st)) return fail(QS_E_INVAL, "index %llu >= 2^%d", (unsigned long long)idx[j], st->n);
+  qs::Perm64 perm{};
+  perm.n = st->n;
+  for (int q = 0; q < st->n; ++q) perm.p[q] = static_cast<int8_t>(st->perm[q]);
+  uint64_t* didx = static_cast<uint64_t*>(dev_alloc(m * sizeof(uint64_t)));
+  double* dout = static_cast<double*>(dev_alloc(m * 2 * sizeof(double)));
+  if (!didx || !dout) {
+    dev_free(didx);
+    dev_free(dout);
+    return fail(QS_E_NOMEM, "staging allocation failed");
+  }
+  hipError_t e = hipMemcpyAsync(didx, idx, m * sizeof(uint64_t), hipMemcpyHostToDevice, st->stream);
+  if (e == hipSuccess)
+    e = st->dtype == QS_C64 ? qs::launch_gather(static_cast<const float*>(st->amps), didx, m, perm, dout, st->stream)
+                            : qs::launch_gather(static_cast<const double*>(st->amps), didx, m, perm, dout, st->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, dout, m * 2 * sizeof(double), hipMemcpyDeviceToHost, st->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+  dev_free(didx);
+  dev_free(dout);
+  return device_error(st, e, "gather");
+}
+
+int qs_probs(qs_state* st, double* out, uint64_t count) {
+  if (int rc = check_state(st)) return rc;
+  if (!out) return fail(QS_E_INVAL, "output pointer is NULL");
+  if (count != dim(st)) return fail(QS_E_INVAL, "count %llu != 2^%d", (unsigned long long)count, st->n);
+  if (int rc = materialize(st)) return rc;
+  const uint64_t chunk = count < kStageAmps ? count : kStageAmps;
+  double* stage = static_cast<double*>(dev_alloc(chunk * sizeof(double)));
+  if (!stage) return fail(QS_E_NOMEM, "staging allocation failed");
+  const size_t sb = amp_bytes(st->dtype);
+  hipError_t e = hipSuccess;
+  for (uint64_t off = 0; off < count && e == hipSuccess; off += chunk) {
+    const uint64_t c = count - off < chunk ? count - off : chunk;
+    const char* src = static_cast<const char*>(st->amps) + off * sb;
+    e = st->dtype == QS_C64 ? qs::launch_probs(reinterpret_cast<const float*>(src), c, stage, st->stream)
+                            : qs::launch_probs(reinterpret_cast<const double*>(src), c, stage, st->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out + off, stage, c * sizeof(double), hipMemcpyDeviceToHost, st->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+  }
+  dev_free(stage);
+  return device_error(st, e, "probs");
+}
+
+int qs_norm(qs_state* st, double* out) {
+  if (int rc = check_state(st)) return rc;
+  if (!out) return fail(QS_E_INVAL, "output pointer is NULL");
+  const int nb = qs::reduce_blocks(dim(st));
+  hipError_t e = st->dtype == QS_C64
+                     ? qs::launch_norm(static_cast<const float*>(st->amps), dim(st), st->red, st->red + nb, st->stream)
+                     : qs::launch_norm(static_cast<const double*>(st->amps), dim(st), st->red, st->red + nb, st->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, st->red + nb, sizeof(double), hipMemcpyDeviceToHost, st->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+  return device_error(st, e, "norm");
+}
+
+int qs_check(qs_state* st, double tol) {
+  double nrm = 0;
+  if (int rc = qs_norm(st, &nrm)) return rc;
+  if (!(std::fabs(nrm - 1.0) <= tol))
+    return fail(QS_E_NUMERIC, "norm %.17g differs from 1 by more than %g", nrm, tol);
+  return QS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,328 @@
+// Per-gate sweeps over the dense ket (gfx950).
+//
+// Layout: amplitudes interleaved (re, im); qubit q is bit q of the index.
+// Every kernel moves 16-byte vectors (one c128 amplitude or two adjacent c64
+// amplitudes) so each wavefront touches whole 64-byte segments; the pair
+// partner at distance 2^t sits in the same thread, so each byte is read and
+// written once per gate.
+#include "qs_internal.h"
+
+namespace qs {
+namespace {
+
+template <typename R> struct Vec16;
+template <> struct Vec16<float> { using T = float4; static constexpr int AMPS = 2; };
+template <> struct Vec16<double> { using T = double2; static constexpr int AMPS = 1; };
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ uint64_t insert_zero(uint64_t x, int pos) {
+  const uint64_t lo = x & ((uint64_t(1) << pos) - 1);
+  return lo | ((x ^ lo) << 1);
+}
+
+__device__ __forceinline__ uint64_t insert_zeros(uint64_t x, const BitSet16& b) {
+  for (int k = 0; k < b.n; ++k) x = insert_zero(x, b.pos[k]);
+  return x;
+}
+
+template <typename R>
+__device__ __forceinline__ void mat2_apply(const Mat2<R>& m, R& x0r, R& x0i, R& x1r, R& x1i) {
+  const R y0r = m.re[0] * x0r - m.im[0] * x0i + m.re[1] * x1r - m.im[1] * x1i;
+  const R y0i = m.re[0] * x0i + m.im[0] * x0r + m.re[1] * x1i + m.im[1] * x1r;
+  const R y1r = m.re[2] * x0r - m.im[2] * x0i + m.re[3] * x1r - m.im[3] * x1i;
+  const R y1i = m.re[2] * x0i + m.im[2] * x0r + m.re[3] * x1i + m.im[3] * x1r;
+  x0r = y0r; x0i = y0i; x1r = y1r; x1i = y1i;
+}
+
+inline unsigned grid_for(uint64_t units) {
+  return static_cast<unsigned>((units + kBlock - 1) / kBlock);
+}
+
+// ------------------------------------------------------------------ 1q
+// c64, target bit t >= 1: a unit is two adjacent pairs (i, i+1) x (bit t).
+__global__ void __launch_bounds__(kBlock) k_1q_f_vec(float* __restrict__ a, uint64_t units,
+                                                     int t, Mat2<float> m) {
+  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (u >= units) return;
+  const uint64_t i0 = insert_zero(u << 1, t);
+  float4* p0 = reinterpret_cast<float4*>(a + 2 * i0);
+  float4* p1 = reinterpret_cast<float4*>(a + 2 * (i0 + (uint64_t(1) << t)));
+  float4 x = *p0, y = *p1;
+  mat2_apply(m, x.x, x.y, y.x, y.y);
+  mat2_apply(m, x.z, x.w, y.z, y.w);
+  *p0 = x;
+  *p1 = y;
+}
+
+// c64, target bit 0: both amplitudes of a pair are in one 16-byte vector.
+__global__ void __launch_bounds__(kBlock) k_1q_f_bit0(float* __restrict__ a, uint64_t units,
+                                                      Mat2<float> m) {
+  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (u >= units) return;
+  float4* p = reinterpret_cast<float4*>(a + 4 * u);
+  float4 x = *p;
+  mat2_apply(m, x.x, x.y, x.z, x.w);
+  *p = x;
+}
+
+// c128: a unit is one pair.
+__global__ void __launch_bounds__(kBlock) k_1q_d(double* __restrict__ a, uint64_t units, int t,
+                                                 Mat2<double> m) {
+  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (u >= units) return;
+  const uint64_t i0 = insert_zero(u, t);
+  double2* p0 = reinterpret_cast<double2*>(a + 2 * i0);
+  double2* p1 = reinterpret_cast<double2*>(a + 2 * (i0 + (uint64_t(1) << t)));
+  double2 x = *p0, y = *p1;
+  mat2_apply(m, x.x, x.y, y.x, y.y);
+  *p0 = x;
+  *p1 = y;
+}
+
+// ------------------------------------------------------------------ controlled
+// Vector path (no fixed bit below the vector width): one unit = Vec16 amps.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_ctrl_vec(R* __restrict__ a, uint64_t units,
+                                                     BitSet16 fixed, uint64_t set_mask, int tbit,
+                                                     Mat2<R> m) {
+  using V = typename Vec16<R>::T;
+  constexpr int AP = Vec16<R>::AMPS;
+  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (u >= units) return;
+  const uint64_t i0 = insert_zeros(u * AP, fixed) | set_mask;
+  V* p0 = reinterpret_cast<V*>(a + 2 * i0);
+  V* p1 = reinterpret_cast<V*>(a + 2 * (i0 | (uint64_t(1) << tbit)));
+  V x = *p0, y = *p1;
+  if constexpr (AP == 2) {
+    mat2_apply(m, x.x, x.y, y.x, y.y);
+    mat2_apply(m, x.z, x.w, y.z, y.w);
+  } else {
+    mat2_apply(m, x.x, x.y, y.x, y.y);
+  }
+  *p0 = x;
+  *p1 = y;
+}
+
+// Scalar path (a fixed bit is bit 0): one pair per thread.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_ctrl_scalar(R* __restrict__ a, uint64_t units,
+                                                        BitSet16 fixed, uint64_t set_mask,
+                                                        int tbit, Mat2<R> m) {
+  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (u >= units) return;
+  const uint64_t i0 = insert_zeros(u, fixed) | set_mask;
+  const uint64_t i1 = i0 | (uint64_t(1) << tbit);
+  R x0r = a[2 * i0], x0i = a[2 * i0 + 1], x1r = a[2 * i1], x1i = a[2 * i1 + 1];
+  mat2_apply(m, x0r, x0i, x1r, x1i);
+  a[2 * i0] = x0r; a[2 * i0 + 1] = x0i;
+  a[2 * i1] = x1r; a[2 * i1 + 1] = x1i;
+}
+
+// ------------------------------------------------------------------ phase
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_cphase_vec(R* __restrict__ a, uint64_t units,
+                                                       BitSet16 fixed, uint64_t set_mask, R cr,
+                                                       R ci) {
+  using V = typename Vec16<R>::T;
+  constexpr int AP = Vec16<R>::AMPS;
+  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (u >= units) return;
+  const uint64_t i = insert_zeros(u * AP, fixed) | set_mask;
+  V* p = reinterpret_cast<V*>(a + 2 * i);
+  V x = *p;
+  R t;
+  t = x.x * cr - x.y * ci; x.y = x.x * ci + x.y * cr; x.x = t;
+  if constexpr (AP == 2) { t = x.z * cr - x.w * ci; x.w = x.z * ci + x.w * cr; x.z = t; }
+  *p = x;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_cphase_scalar(R* __restrict__ a, uint64_t units,
+                                                          BitSet16 fixed, uint64_t set_mask,
+                                                          R cr, R ci) {
+  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (u >= units) return;
+  const uint64_t i = insert_zeros(u, fixed) | set_mask;
+  const R xr = a[2 * i], xi = a[2 * i + 1];
+  a[2 * i] = xr * cr - xi * ci;
+  a[2 * i + 1] = xr * ci + xi * cr;
+}
+
+// ------------------------------------------------------------------ bit swap
+// Exchange the amplitudes at base|2^lo and base|2^hi (bits lo < hi).
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_bitswap_vec(R* __restrict__ a, uint64_t units,
+                                                        BitSet16 fixed, int lo, int hi) {
+  using V = typename Vec16<R>::T;
+  constexpr int AP = Vec16<R>::AMPS;
+  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (u >= units) return;
+  const uint64_t b = insert_zeros(u * AP, fixed);
+  V* p0 = reinterpret_cast<V*>(a + 2 * (b | (uint64_t(1) << lo)));
+  V* p1 = reinterpret_cast<V*>(a + 2 * (b | (uint64_t(1) << hi)));
+  const V x = *p0, y = *p1;
+  *p0 = y;
+  *p1 = x;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_bitswap_scalar(R* __restrict__ a, uint64_t units,
+                                                           BitSet16 fixed, int lo, int hi) {
+  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (u >= units) return;
+  const uint64_t b = insert_zeros(u, fixed);
+  const uint64_t i0 = b | (uint64_t(1) << lo), i1 = b | (uint64_t(1) << hi);
+  const R xr = a[2 * i0], xi = a[2 * i0 + 1];
+  a[2 * i0] = a[2 * i1];
+  a[2 * i0 + 1] = a[2 * i1 + 1];
+  a[2 * i1] = xr;
+  a[2 * i1 + 1] = xi;
+}
+
+// ------------------------------------------------------------------ setup
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_set_basis(R* __restrict__ a, uint64_t units,
+                                                      uint64_t x) {
+  using V = typename Vec16<R>::T;
+  constexpr int AP = Vec16<R>::AMPS;
+  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (u >= units) return;
+  V v{};
+  if (x / AP == u) {
+    if constexpr (AP == 2) {
+      if (x % 2 == 0) v.x = R(1); else v.z = R(1);
+    } else {
+      v.x = R(1);
+    }
+  }
+  reinterpret_cast<V*>(a)[u] = v;
+}
+
+template <typename Rd, typename Rs>
+__global__ void __launch_bounds__(kBlock) k_convert(Rd* __restrict__ d, const Rs* __restrict__ s,
+                                                    uint64_t count) {
+  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (u >= count) return;
+  d[2 * u] = static_cast<Rd>(s[2 * u]);
+  d[2 * u + 1] = static_cast<Rd>(s[2 * u + 1]);
+}
+
+BitSet16 sorted_bits(std::initializer_list<int> bits) {
+  BitSet16 b{};
+  for (int v : bits) b.pos[b.n++] = v;
+  for (int i = 1; i < b.n; ++i)
+    for (int j = i; j > 0 && b.pos[j - 1] > b.pos[j]; --j) {
+      const int t = b.pos[j];
+      b.pos[j] = b.pos[j - 1];
+      b.pos[j - 1] = t;
+    }
+  return b;
+}
+
+template <typename R>
+constexpr int log_amps() { return Vec16<R>::AMPS == 2 ? 1 : 0; }
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+template <>
+hipError_t launch_apply_1q<float>(float* a, int n, int t, const Mat2<float>& m, hipStream_t s) {
+  if (t == 0) {
+    const uint64_t units = uint64_t(1) << (n - 1);
+    hipLaunchKernelGGL(k_1q_f_bit0, dim3(grid_for(units)), dim3(kBlock), 0, s, a, units, m);
+  } else {
+    const uint64_t units = uint64_t(1) << (n - 2);
+    hipLaunchKernelGGL(k_1q_f_vec, dim3(grid_for(units)), dim3(kBlock), 0, s, a, units, t, m);
+  }
+  return hipGetLastError();
+}
+
+template <>
+hipError_t launch_apply_1q<double>(double* a, int n, int t, const Mat2<double>& m,
+                                   hipStream_t s) {
+  const uint64_t units = uint64_t(1) << (n - 1);
+  hipLaunchKernelGGL(k_1q_d, dim3(grid_for(units)), dim3(kBlock), 0, s, a, units, t, m);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_apply_ctrl(R* a, int n, const BitSet16& fixed, uint64_t set_mask, int tbit,
+                             const Mat2<R>& m, hipStream_t s) {
+  const int free_bits = n - fixed.n;
+  if (fixed.pos[0] >= log_amps<R>() && free_bits >= log_amps<R>()) {
+    const uint64_t units = (uint64_t(1) << free_bits) / Vec16<R>::AMPS;
+    hipLaunchKernelGGL(k_ctrl_vec<R>, dim3(grid_for(units)), dim3(kBlock), 0, s, a, units, fixed,
+                       set_mask, tbit, m);
+  } else {
+    const uint64_t units = uint64_t(1) << free_bits;
+    hipLaunchKernelGGL(k_ctrl_scalar<R>, dim3(grid_for(units)), dim3(kBlock), 0, s, a, units,
+                       fixed, set_mask, tbit, m);
+  }
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_cphase(R* a, int n, int qa, int qb, R cr, R ci, hipStream_t s) {
+  const BitSet16 fixed = sorted_bits({qa, qb});
+  const uint64_t set_mask = (uint64_t(1) << qa) | (uint64_t(1) << qb);
+  const int free_bits = n - 2;
+  if (fixed.pos[0] >= log_amps<R>() && free_bits >= log_amps<R>()) {
+    const uint64_t units = (uint64_t(1) << free_bits) / Vec16<R>::AMPS;
+    hipLaunchKernelGGL(k_cphase_vec<R>, dim3(grid_for(units)), dim3(kBlock), 0, s, a, units,
+                       fixed, set_mask, cr, ci);
+  } else {
+    const uint64_t units = uint64_t(1) << free_bits;
+    hipLaunchKernelGGL(k_cphase_scalar<R>, dim3(grid_for(units)), dim3(kBlock), 0, s, a, units,
+                       fixed, set_mask, cr, ci);
+  }
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_bitswap(R* a, int n, int qa, int qb, hipStream_t s) {
+  const int lo = qa < qb ? qa : qb, hi = qa < qb ? qb : qa;
+  const BitSet16 fixed = sorted_bits({lo, hi});
+  const int free_bits = n - 2;
+  if (lo >= log_amps<R>() && free_bits >= log_amps<R>()) {
+    const uint64_t units = (uint64_t(1) << free_bits) / Vec16<R>::AMPS;
+    hipLaunchKernelGGL(k_bitswap_vec<R>, dim3(grid_for(units)), dim3(kBlock), 0, s, a, units,
+                       fixed, lo, hi);
+  } else {
+    const uint64_t units = uint64_t(1) << free_bits;
+    hipLaunchKernelGGL(k_bitswap_scalar<R>, dim3(grid_for(units)), dim3(kBlock), 0, s, a, units,
+                       fixed, lo, hi);
+  }
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_set_basis(R* a, int n, uint64_t x, hipStream_t s) {
+  const uint64_t units = ((uint64_t(1) << n) + Vec16<R>::AMPS - 1) / Vec16<R>::AMPS;
+  hipLaunchKernelGGL(k_set_basis<R>, dim3(grid_for(units)), dim3(kBlock), 0, s, a, units, x);
+  return hipGetLastError();
+}
+
+template <typename Rd, typename Rs>
+hipError_t launch_convert(Rd* d, const Rs* src, uint64_t count, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<Rd, Rs>), dim3(grid_for(count)), dim3(kBlock), 0, s, d, src,
+                     count);
+  return hipGetLastError();
+}
+
+template hipError_t launch_apply_ctrl<float>(float*, int, const BitSet16&, uint64_t, int,
+                                             const Mat2<float>&, hipStream_t);
+template hipError_t launch_apply_ctrl<double>(double*, int, const BitSet16&, uint64_t, int,
+                                              const Mat2<double>&, hipStream_t);
+template hipError_t launch_cphase<float>(float*, int, int, int, float, float, hipStream_t);
+template hipError_t launch_cphase<double>(double*, int, int, int, double, double, hipStream_t);
+template hipError_t launch_bitswap<float>(float*, int, int, int, hipStream_t);
+template hipError_t launch_bitswap<double>(double*, int, int, int, hipStream_t);
+template hipError_t launch_set_basis<float>(float*, int, uint64_t, hipStream_t);
+template hipError_t launch_set_basis<double>(double*, int, uint64_t, hipStream_t);
+template hipError_t launch_convert<float, double>(float*, const double*, uint64_t, hipStream_t);
+template hipError_t launch_convert<double, double>(double*, const double*, uint64_t, hipStream_t);
+template hipError_t launch_convert<float, float>(float*, const float*, uint64_t, hipStream_t);
+template hipError_t launch_convert<double, float>(double*, const float*, uint64_t, hipStream_t);
+
+}  // namespace qs

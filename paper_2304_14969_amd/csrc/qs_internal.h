@@ -1,0 +1,97 @@
+// Internal declarations shared by the C-ABI layer and the HIP kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace qs {
+
+// A 2x2 complex matrix in the state's precision, row-major.
+template <typename R>
+struct Mat2 {
+  R re[4];
+  R im[4];
+};
+
+// Up to 16 sorted bit positions at which zero bits are inserted into a
+// compact counter to enumerate the index set of a gate.
+struct BitSet16 {
+  int n;
+  int pos[16];
+};
+
+// ---------------------------------------------------------------- gates
+// Each launcher enqueues on `s` and returns the launch status.
+template <typename R>
+hipError_t launch_apply_1q(R* amps, int n, int t, const Mat2<R>& m, hipStream_t s);
+
+// Controlled 2x2: `fixed` holds the sorted control and target bits,
+// `set_mask` the control bits that must be 1, `tbit` the target bit.
+template <typename R>
+hipError_t launch_apply_ctrl(R* amps, int n, const BitSet16& fixed, uint64_t set_mask,
+                             int tbit, const Mat2<R>& m, hipStream_t s);
+
+// Multiply amplitudes with bits a and b set by (c, s).
+template <typename R>
+hipError_t launch_cphase(R* amps, int n, int a, int b, R cr, R ci, hipStream_t s);
+
+// Physical exchange of bits a and b.
+template <typename R>
+hipError_t launch_bitswap(R* amps, int n, int a, int b, hipStream_t s);
+
+// Dense k-qubit block; `mat` is a device array of 2^k x 2^k complex values
+// (interleaved, row-major) in the state's precision, `qubits` the k bits.
+template <typename R>
+hipError_t launch_apply_fused(R* amps, int n, const int* qubits, int k, const R* mat,
+                              hipStream_t s);
+
+// ---------------------------------------------------------------- QFT passes
+// One pass of a QFT on the qubit range [start, start+len): the stages of the
+// bits [lo, hi), each a butterfly on its bit and the phase controlled by the
+// other range bits, then a multiplication by `scale`. `rev` = the range is
+// stored bit-reversed (after an earlier transform's relabelling). `sign` = +1
+// forward, -1 conjugated (inverse transform).
+struct QftPass {
+  int lo, hi;
+  double scale;
+};
+template <typename R>
+hipError_t launch_qft_pass(R* amps, int n, int start, int len, int lo, int hi, int sign, bool rev,
+                           double scale, hipStream_t s);
+
+// Pass plan in launch order; returns the number of passes (-1 if more than
+// max_passes).
+template <typename R>
+int qft_plan(int n, int start, int len, bool rev, QftPass* out, int max_passes);
+
+// ---------------------------------------------------------------- state setup
+template <typename R>
+hipError_t launch_set_basis(R* amps, int n, uint64_t x, hipStream_t s);
+
+// dst (state precision) <- src (Rs precision), count complex values.
+template <typename Rd, typename Rs>
+hipError_t launch_convert(Rd* dst, const Rs* src, uint64_t count, hipStream_t s);
+
+// ---------------------------------------------------------------- reductions
+// Squared norm in float64: partial sums per block into `partial` (nblocks
+// doubles, see reduce_blocks), then a fixed-order final sum into out[0].
+int reduce_blocks(uint64_t count);
+template <typename R>
+hipError_t launch_norm(const R* amps, uint64_t count, double* partial, double* out,
+                       hipStream_t s);
+
+// probs[x] = |a_x|^2 for x in [0, count)
+template <typename R>
+hipError_t launch_probs(const R* amps, uint64_t count, double* probs, hipStream_t s);
+
+// out[j] = a[phys(idx[j])] as complex double, phys maps logical to physical bits
+struct Perm64 {
+  int n;
+  int8_t p[64];
+};
+template <typename R>
+hipError_t launch_gather(const R* amps, const uint64_t* idx, uint64_t m, Perm64 perm,
+                         double* out, hipStream_t s);
+
+}  // namespace qs
