@@ -63,6 +63,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=27)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
+    ap.add_argument("--tune", action="append", default=[], metavar="KEY=VALUE",
+                    help="library tuning knob (qs_tune_set), repeatable")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -76,6 +78,11 @@ def main() -> int:
     import workloads
 
     qs.load()
+    tuning = {}
+    for kv in args.tune:
+        k, v = kv.split("=", 1)
+        qs.tune_set(k, int(v))
+        tuning[k] = int(v)
     n = args.n
     st = qs.State(n, qs.C64)
     a = workloads.gaussian_state(n, 0)
@@ -144,7 +151,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"exact QFT on n={n} qubits, complex64 ({2 ** n * 8 / 2 ** 30:g} GiB), "
                                "i.i.d. complex Gaussian input (seed 0), state resident in HBM",
-                   "n": n, "passes_per_qft": passes},
+                   "n": n, "passes_per_qft": passes, "tuning": tuning},
         "hbm_GBps_effective": total_bytes / (ms_per_step * 1e-3) / 1e9,
         "wall_ms_per_step": wall * 1e3 / args.steps,
         "gate_by_gate_ms": gate_by_gate_ms,

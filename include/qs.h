@@ -159,6 +159,21 @@ int qs_norm(qs_state* st, double* out);
 /* QS_E_NUMERIC if |norm - 1| > tol, else QS_OK. Synchronizes. */
 int qs_check(qs_state* st, double tol);
 
+/* ------------------------------------------------------------ tuning */
+
+/* Process-wide knobs of the kernel planners (read by later calls):
+ *   "qft.lds_bits"   bits of the contiguous LDS tile of the QFT's low pass
+ *                    (0 = default: 13 for complex64, 12 for complex128;
+ *                    larger values are clamped to the default);
+ *   "qft.high_pass"  passes above that tile: 0 = strided LDS tiles of up to
+ *                    7 bits, 1 = register passes of up to 5 bits;
+ *   "qft.threads"    thread cap of the LDS tile launches: 256 or 512 (default);
+ *   "qft.round_bits" widest in-register round inside an LDS tile: 4 (default)
+ *                    or 5.
+ * QS_E_INVAL for an unknown key or a value out of range. */
+int qs_tune_set(const char* key, int64_t value);
+int qs_tune_get(const char* key, int64_t* value);
+
 /* ------------------------------------------------------------ timing */
 
 /* Aggregated timing of one kernel kind between qs_profile_start and

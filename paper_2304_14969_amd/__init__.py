@@ -73,6 +73,8 @@ _SIGS = [
     ("qs_probs", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_uint64]),
     ("qs_norm", C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     ("qs_check", C.c_int, [C.c_void_p, C.c_double]),
+    ("qs_tune_set", C.c_int, [C.c_char_p, C.c_int64]),
+    ("qs_tune_get", C.c_int, [C.c_char_p, C.POINTER(C.c_int64)]),
     ("qs_profile_start", C.c_int, [C.c_void_p]),
     ("qs_profile_stop", C.c_int, [C.c_void_p, C.POINTER(KernelStat), C.c_int, C.POINTER(C.c_int)]),
 ]
@@ -134,6 +136,18 @@ def mat_arg(m) -> np.ndarray:
     """Complex matrix -> contiguous float64 (re, im) interleaved, row-major."""
     m = np.ascontiguousarray(np.asarray(m, dtype=np.complex128))
     return np.ascontiguousarray(m.view(np.float64).reshape(-1))
+
+
+def tune_set(key: str, value: int):
+    lib = load()
+    _check(lib, lib.qs_tune_set(key.encode(), int(value)))
+
+
+def tune_get(key: str) -> int:
+    lib = load()
+    v = C.c_int64()
+    _check(lib, lib.qs_tune_get(key.encode(), C.byref(v)))
+    return v.value
 
 
 class State:

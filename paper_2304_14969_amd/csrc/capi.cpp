@@ -31,6 +31,7 @@ qs_alloc_fn g_alloc = nullptr;
 qs_free_fn g_free = nullptr;
 void* g_user = nullptr;
 int g_live_states = 0;
+qs::QftTuning g_qft_tune;
 
 void* dev_alloc(size_t bytes) {
   if (g_alloc) return g_alloc(bytes, g_user);
@@ -193,6 +194,36 @@ extern "C" {
 const char* qs_last_error(void) { return g_err.c_str(); }
 
 int qs_version(void) { return 100; }
+
+int qs_tune_set(const char* key, int64_t value) {
+  if (!key) return fail(QS_E_INVAL, "key is NULL");
+  if (!std::strcmp(key, "qft.lds_bits")) {
+    if (value < 0 || value > 13) return fail(QS_E_INVAL, "qft.lds_bits %lld outside [0, 13]", (long long)value);
+    g_qft_tune.lds_bits = int(value);
+  } else if (!std::strcmp(key, "qft.high_pass")) {
+    if (value < 0 || value > 1) return fail(QS_E_INVAL, "qft.high_pass must be 0 or 1");
+    g_qft_tune.high_kind = int(value);
+  } else if (!std::strcmp(key, "qft.threads")) {
+    if (value != 256 && value != 512) return fail(QS_E_INVAL, "qft.threads must be 256 or 512");
+    g_qft_tune.threads = int(value);
+  } else if (!std::strcmp(key, "qft.round_bits")) {
+    if (value != 4 && value != 5) return fail(QS_E_INVAL, "qft.round_bits must be 4 or 5");
+    g_qft_tune.round_bits = int(value);
+  } else {
+    return fail(QS_E_INVAL, "unknown tuning key '%s'", key);
+  }
+  return QS_OK;
+}
+
+int qs_tune_get(const char* key, int64_t* value) {
+  if (!key || !value) return fail(QS_E_INVAL, "NULL argument");
+  if (!std::strcmp(key, "qft.lds_bits")) *value = g_qft_tune.lds_bits;
+  else if (!std::strcmp(key, "qft.high_pass")) *value = g_qft_tune.high_kind;
+  else if (!std::strcmp(key, "qft.threads")) *value = g_qft_tune.threads;
+  else if (!std::strcmp(key, "qft.round_bits")) *value = g_qft_tune.round_bits;
+  else return fail(QS_E_INVAL, "unknown tuning key '%s'", key);
+  return QS_OK;
+}
 
 int qs_set_allocator(qs_alloc_fn alloc_fn, qs_free_fn free_fn, void* user) {
   if ((alloc_fn == nullptr) != (free_fn == nullptr))
@@ -446,21 +477,24 @@ int qs_qft(qs_state* st, int start, int len, int inverse) {
     reversed = false;
   }
   qs::QftPass plan[64];
-  const int np = st->dtype == QS_C64 ? qs::qft_plan<float>(st->n, start, len, reversed, plan, 64)
-                                     : qs::qft_plan<double>(st->n, start, len, reversed, plan, 64);
+  const int np = st->dtype == QS_C64
+                     ? qs::qft_plan<float>(st->n, start, len, reversed, g_qft_tune, plan, 64)
+                     : qs::qft_plan<double>(st->n, start, len, reversed, g_qft_tune, plan, 64);
   if (np < 0) return fail(QS_E_UNSUPPORTED, "QFT pass plan failed");
   const int sign = inverse ? -1 : 1;
-  static const char* pass_names[] = {"qft_lds", "qft_reg1", "qft_reg2", "qft_reg3", "qft_reg4", "qft_reg5"};
-  const int T = st->n < (st->dtype == QS_C64 ? 12 : 11) ? st->n : (st->dtype == QS_C64 ? 12 : 11);
+  static const char* kind_names[3][8] = {
+      {"qft_lds", "qft_lds", "qft_lds", "qft_lds", "qft_lds", "qft_lds", "qft_lds", "qft_lds"},
+      {"", "qft_col1", "qft_col2", "qft_col3", "qft_col4", "qft_col5", "qft_col6", "qft_col7"},
+      {"", "qft_reg1", "qft_reg2", "qft_reg3", "qft_reg4", "qft_reg5", "", ""}};
   for (int k = 0; k < np; ++k) {
     const int g = plan[k].hi - plan[k].lo;
-    ProfScope ps(st, plan[k].hi <= T ? pass_names[0] : pass_names[g], 2.0 * std::ldexp(1.0, st->n) * ab(st));
+    ProfScope ps(st, kind_names[plan[k].kind][g & 7], 2.0 * std::ldexp(1.0, st->n) * ab(st));
     hipError_t e =
         st->dtype == QS_C64
-            ? qs::launch_qft_pass(static_cast<float*>(st->amps), st->n, start, len, plan[k].lo,
-                                  plan[k].hi, sign, reversed, plan[k].scale, st->stream)
-            : qs::launch_qft_pass(static_cast<double*>(st->amps), st->n, start, len, plan[k].lo,
-                                  plan[k].hi, sign, reversed, plan[k].scale, st->stream);
+            ? qs::launch_qft_pass(static_cast<float*>(st->amps), st->n, start, len, plan[k], sign,
+                                  reversed, g_qft_tune, st->stream)
+            : qs::launch_qft_pass(static_cast<double*>(st->amps), st->n, start, len, plan[k], sign,
+                                  reversed, g_qft_tune, st->stream);
     if (int rc = device_error(st, e, "qft pass")) return rc;
   }
   // final bit reversal of the range, as a relabelling

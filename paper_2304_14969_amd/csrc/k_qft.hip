@@ -172,80 +172,178 @@ __global__ void __launch_bounds__(kBlock) k_qft_reg(R* __restrict__ a, int n, in
   }
 }
 
-// ------------------------------------------------------------------ LDS pass
-// LDS position of tile index x: one complex of padding every 16 keeps strided
-// column reads spread over the banks.
-__device__ __forceinline__ int lds_pos(int x) { return x + (x >> 4); }
+// ------------------------------------------------------------------ LDS tiles
+// Both LDS kernels stage a tile of 2^TB amplitudes, run the pass's stages in
+// register rounds of up to 5 bits (each thread takes the 2^W amplitudes of
+// one column of the round), and write the tile back scaled. Global loads are
+// issued as a batch of 16-byte vectors before any LDS write.
 
-template <typename R, int W, bool REV>
-__device__ __forceinline__ void lds_group(Cx<R>* sm, uint64_t tile_base, int T, int start,
-                                          int len, int g0, int sign, const Roots32<R>& rt) {
-  const int g1 = g0 + W;
-  const int cols = 1 << (T - W);
-  for (int c = threadIdx.x; c < cols; c += kBlock) {
-    const int cl = c & ((1 << g0) - 1);
-    const int ch = c >> g0;
-    const int xb = (ch << g1) | cl;
+template <typename R> struct Vec16;
+template <> struct Vec16<float> { using T = float4; static constexpr int AMPS = 2; };
+template <> struct Vec16<double> { using T = double2; static constexpr int AMPS = 1; };
+
+// LDS position of tile index x; one complex of padding every 16 entries keeps
+// the strided columns of the lowest rounds on distinct banks.
+template <bool PAD>
+__device__ __forceinline__ int lds_pos(int x) { return PAD ? x + (x >> 4) : x; }
+
+// Round over the tile bits [b0, b0+W): column q owns the 2^W entries that
+// differ in those bits. Entry (tile index) -> global index via `glob`.
+template <typename R, int W, bool REV, bool PAD, int NT, typename Glob>
+__device__ __forceinline__ void tile_round(Cx<R>* sm, int TB, int b0, int start, int len,
+                                           int glo, int sign, const Roots32<R>& rt, Glob glob) {
+  const int cols = 1 << (TB - W);
+  for (int q = threadIdx.x; q < cols; q += NT) {
+    const int x0 = (q & ((1 << b0) - 1)) | ((q >> b0) << (b0 + W));
     Cx<R> v[1 << W];
 #pragma unroll
-    for (int m = 0; m < (1 << W); ++m) v[m] = sm[lds_pos(xb | (m << g0))];
-    pass_stages<R, W, REV>(v, tile_base | uint64_t(xb), start, len, g0, sign, rt);
+    for (int m = 0; m < (1 << W); ++m) v[m] = sm[lds_pos<PAD>(x0 | (m << b0))];
+    pass_stages<R, W, REV>(v, glob(x0), start, len, glo, sign, rt);
 #pragma unroll
-    for (int m = 0; m < (1 << W); ++m) sm[lds_pos(xb | (m << g0))] = v[m];
+    for (int m = 0; m < (1 << W); ++m) sm[lds_pos<PAD>(x0 | (m << b0))] = v[m];
   }
 }
 
-template <typename R, bool REV>
-__device__ __forceinline__ void lds_round(Cx<R>* sm, uint64_t tile_base, int T, int start,
-                                          int len, int g0, int w, int sign,
-                                          const Roots32<R>& rt) {
-  switch (w) {
-    case 1: lds_group<R, 1, REV>(sm, tile_base, T, start, len, g0, sign, rt); break;
-    case 2: lds_group<R, 2, REV>(sm, tile_base, T, start, len, g0, sign, rt); break;
-    case 3: lds_group<R, 3, REV>(sm, tile_base, T, start, len, g0, sign, rt); break;
-    default: lds_group<R, 4, REV>(sm, tile_base, T, start, len, g0, sign, rt); break;
+// Round count for `bits` tile bits with rounds of at most WMAX bits.
+__host__ __device__ constexpr int round_count(int bits, int wmax) {
+  return bits <= 0 ? 0 : (bits + wmax - 1) / wmax;
+}
+// Widest round of that split (the rounds are balanced).
+__host__ __device__ constexpr int round_width(int bits, int wmax) {
+  return bits <= 0 ? 0 : (bits + round_count(bits, wmax) - 1) / round_count(bits, wmax);
+}
+
+// Runs the rounds covering tile bits [b_lo, b_hi) (global bits glo_base +
+// (b - b_lo)): balanced widths <= WMAX, top-down in natural order, bottom-up
+// when bit-reversed.
+template <typename R, bool REV, bool PAD, int NT, int WMAX, typename Glob>
+__device__ __forceinline__ void tile_rounds(Cx<R>* sm, int TB, int b_lo, int b_hi, int glo_base,
+                                            int start, int len, int sign, const Roots32<R>& rt,
+                                            Glob glob) {
+  const int bits = b_hi - b_lo;
+  const int rounds = round_count(bits, WMAX);
+  for (int k = 0; k < rounds; ++k) {
+    // widths: the first (bits % rounds) rounds, counted from the top, get one more
+    const int base_w = bits / rounds, extra = bits % rounds;
+    const int kk = REV ? rounds - 1 - k : k;   // index from the top
+    int top = b_hi;
+    for (int i = 0; i < kk; ++i) top -= base_w + (i < extra ? 1 : 0);
+    const int w = base_w + (kk < extra ? 1 : 0);
+    const int b0 = top - w;
+    const int glo = glo_base + (b0 - b_lo);
+    switch (w) {
+      case 1: tile_round<R, 1, REV, PAD, NT>(sm, TB, b0, start, len, glo, sign, rt, glob); break;
+      case 2: tile_round<R, 2, REV, PAD, NT>(sm, TB, b0, start, len, glo, sign, rt, glob); break;
+      case 3: tile_round<R, 3, REV, PAD, NT>(sm, TB, b0, start, len, glo, sign, rt, glob); break;
+      case 4: tile_round<R, 4, REV, PAD, NT>(sm, TB, b0, start, len, glo, sign, rt, glob); break;
+      default:
+        if constexpr (WMAX >= 5)
+          tile_round<R, 5, REV, PAD, NT>(sm, TB, b0, start, len, glo, sign, rt, glob);
+        break;
+    }
+    __syncthreads();
   }
 }
 
-// Stages of the bits [start, hi) on a 2^T tile; hi <= T.
-template <typename R, bool REV>
-__global__ void __launch_bounds__(kBlock) k_qft_lds(R* __restrict__ a, int T, int start, int len,
-                                                    int hi, int sign, R scale, Roots32<R> rt) {
+// Contiguous tile [0, T): stages of the bits [lo, hi), hi <= T.
+template <typename R, int T, bool REV, int NT, int WMAX>
+__global__ void __launch_bounds__(NT) k_qft_lds(R* __restrict__ a, int start, int len, int lo,
+                                                int hi, int sign, R scale, Roots32<R> rt) {
   extern __shared__ unsigned char smraw[];
   Cx<R>* sm = reinterpret_cast<Cx<R>*>(smraw);
-  using V = typename Vec8<R>::T;
+  using V = typename Vec16<R>::T;
+  constexpr int AP = Vec16<R>::AMPS;
+  constexpr int NV = (1 << T) / AP / NT;  // vectors per thread
+  static_assert(NV >= 1, "tile smaller than the block");
   const uint64_t tile_base = uint64_t(blockIdx.x) << T;
-  V* p = reinterpret_cast<V*>(a) + tile_base;
-  const int tile = 1 << T;
-  for (int x = threadIdx.x; x < tile; x += kBlock) {
-    const V t = p[x];
-    sm[lds_pos(x)] = {t.x, t.y};
+  V* p = reinterpret_cast<V*>(a + 2 * tile_base);
+  V buf[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) buf[k] = p[threadIdx.x + k * NT];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int x = (threadIdx.x + k * NT) * AP;
+    if constexpr (AP == 2) {
+      sm[lds_pos<true>(x)] = {buf[k].x, buf[k].y};
+      sm[lds_pos<true>(x + 1)] = {buf[k].z, buf[k].w};
+    } else {
+      sm[lds_pos<true>(x)] = {buf[k].x, buf[k].y};
+    }
   }
   __syncthreads();
-  if constexpr (REV) {
-    // bottom-up rounds: the lowest round takes the remainder of (hi-start)/4
-    int g0 = start;
-    int first = (hi - start) % 4;
-    if (first == 0) first = 4;
-    for (int w = first; g0 < hi; g0 += w, w = 4) {
-      lds_round<R, REV>(sm, tile_base, T, start, len, g0, w, sign, rt);
-      __syncthreads();
-    }
-  } else {
-    for (int g1 = hi; g1 > start;) {
-      const int w = (g1 - start) < 4 ? (g1 - start) : 4;
-      const int g0 = g1 - w;
-      lds_round<R, REV>(sm, tile_base, T, start, len, g0, w, sign, rt);
-      __syncthreads();
-      g1 = g0;
+  tile_rounds<R, REV, true, NT, WMAX>(sm, T, lo, hi, lo, start, len, sign, rt,
+                                      [tile_base](int x) { return tile_base | uint64_t(x); });
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int x = (threadIdx.x + k * NT) * AP;
+    const Cx<R> v0 = sm[lds_pos<true>(x)];
+    if constexpr (AP == 2) {
+      const Cx<R> v1 = sm[lds_pos<true>(x + 1)];
+      buf[k] = {v0.r * scale, v0.i * scale, v1.r * scale, v1.i * scale};
+    } else {
+      buf[k] = {v0.r * scale, v0.i * scale};
     }
   }
-  for (int x = threadIdx.x; x < tile; x += kBlock) {
-    const Cx<R> v = sm[lds_pos(x)];
-    V t;
-    t.x = v.r * scale;
-    t.y = v.i * scale;
-    p[x] = t;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) p[threadIdx.x + k * NT] = buf[k];
+}
+
+// Strided tile: 2^G rows (global bits [lo, lo+G)) x 2^C contiguous columns
+// (global bits [0, C)), C <= lo. Tile index = row * 2^C + column.
+template <typename R, int G, int C, bool REV, int NT, int WMAX>
+__global__ void __launch_bounds__(NT) k_qft_col(R* __restrict__ a, int start, int len, int lo,
+                                                int sign, R scale, Roots32<R> rt) {
+  extern __shared__ unsigned char smraw[];
+  Cx<R>* sm = reinterpret_cast<Cx<R>*>(smraw);
+  using V = typename Vec16<R>::T;
+  constexpr int AP = Vec16<R>::AMPS;
+  constexpr int TB = G + C;
+  constexpr int VPR = (1 << C) / AP;        // vectors per row
+  constexpr int NV = (1 << TB) / AP / NT;   // vectors per thread
+  static_assert(NV >= 1 && VPR >= 1, "tile shape");
+  const uint64_t b = blockIdx.x;
+  const uint64_t mid = b & ((uint64_t(1) << (lo - C)) - 1);
+  const uint64_t hi = b >> (lo - C);
+  const uint64_t base = (hi << (lo + G)) | (mid << C);
+  auto glob = [base, lo](int x) {
+    return base | (uint64_t(x >> C) << lo) | uint64_t(x & ((1 << C) - 1));
+  };
+  V* p = reinterpret_cast<V*>(a);
+  V buf[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int e = threadIdx.x + k * NT;
+    buf[k] = p[glob((e / VPR) << C | (e % VPR) * AP) / AP];
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int e = threadIdx.x + k * NT;
+    const int x = ((e / VPR) << C) | (e % VPR) * AP;
+    if constexpr (AP == 2) {
+      sm[x] = {buf[k].x, buf[k].y};
+      sm[x + 1] = {buf[k].z, buf[k].w};
+    } else {
+      sm[x] = {buf[k].x, buf[k].y};
+    }
+  }
+  __syncthreads();
+  tile_rounds<R, REV, false, NT, WMAX>(sm, TB, C, TB, lo, start, len, sign, rt, glob);
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int e = threadIdx.x + k * NT;
+    const int x = ((e / VPR) << C) | (e % VPR) * AP;
+    const Cx<R> v0 = sm[x];
+    if constexpr (AP == 2) {
+      const Cx<R> v1 = sm[x + 1];
+      buf[k] = {v0.r * scale, v0.i * scale, v1.r * scale, v1.i * scale};
+    } else {
+      buf[k] = {v0.r * scale, v0.i * scale};
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int e = threadIdx.x + k * NT;
+    p[glob((e / VPR) << C | (e % VPR) * AP) / AP] = buf[k];
   }
 }
 
@@ -261,8 +359,30 @@ Roots32<R> make_roots() {
   return rt;
 }
 
-template <typename R> constexpr int tile_bits() { return sizeof(R) == 4 ? 12 : 11; }
+// Tile shapes: the contiguous tile has 2^13 complex64 / 2^12 complex128
+// entries (64 KiB plus padding); the strided tile 2^7 rows x 64 (complex64)
+// or 32 (complex128) columns (64 KiB).
+template <typename R> constexpr int lds_bits() { return sizeof(R) == 4 ? 13 : 12; }
+template <typename R> constexpr int col_bits() { return sizeof(R) == 4 ? 6 : 5; }
+constexpr int kColMax = 7;
 constexpr int kRegMax = 5;
+
+// Threads of a tile launch: at most `cap`, at most one per 16-byte vector of
+// the tile, and at most the column count of the widest round, so that no
+// thread idles in a round.
+__host__ __device__ constexpr int tile_threads(int tile_bits, int vec_per_tile, int round_bits,
+                                               int cap) {
+  int nt = cap;
+  if (nt > vec_per_tile) nt = vec_per_tile;
+  if (nt > (1 << (tile_bits - round_bits))) nt = 1 << (tile_bits - round_bits);
+  return nt < 1 ? 1 : nt;
+}
+
+template <typename K>
+void allow_lds(K kernel, size_t bytes) {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+}
 
 template <typename R, int G, bool REV>
 hipError_t launch_reg(R* a, int n, int start, int len, int lo, int sign, R scale,
@@ -274,72 +394,162 @@ hipError_t launch_reg(R* a, int n, int start, int len, int lo, int sign, R scale
   return hipGetLastError();
 }
 
+template <typename R, int G, bool REV, int CAP, int WMAX>
+hipError_t launch_col_cfg(R* a, int n, int start, int len, int lo, int sign, R scale,
+                          const Roots32<R>& rt, hipStream_t s) {
+  constexpr int C = col_bits<R>();
+  if (lo < C || n < lo + G) return hipErrorInvalidValue;
+  constexpr int NT =
+      tile_threads(G + C, (1 << (G + C)) / Vec16<R>::AMPS, round_width(G, WMAX), CAP);
+  const size_t bytes = (size_t(1) << (G + C)) * 2 * sizeof(R);
+  auto kern = k_qft_col<R, G, C, REV, NT, WMAX>;
+  allow_lds(kern, bytes);
+  const unsigned grid = static_cast<unsigned>(uint64_t(1) << (n - G - C));
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), bytes, s, a, start, len, lo, sign, scale, rt);
+  return hipGetLastError();
+}
+
+template <typename R, int T, bool REV, int CAP, int WMAX>
+hipError_t launch_lds_cfg(R* a, int n, int start, int len, int lo, int hi, int sign, R scale,
+                          const Roots32<R>& rt, hipStream_t s) {
+  constexpr int VEC = (1 << T) / Vec16<R>::AMPS > 0 ? (1 << T) / Vec16<R>::AMPS : 1;
+  constexpr int NT = tile_threads(T, VEC, WMAX < T ? WMAX : T, CAP);
+  const size_t bytes = size_t((1 << T) + ((1 << T) >> 4)) * 2 * sizeof(R);
+  auto kern = k_qft_lds<R, T, REV, NT, WMAX>;
+  allow_lds(kern, bytes);
+  const unsigned grid = static_cast<unsigned>(uint64_t(1) << (n - T));
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), bytes, s, a, start, len, lo, hi, sign, scale, rt);
+  return hipGetLastError();
+}
+
+// Launch configurations selectable by the tuning knobs: thread cap 256 or
+// 512, round width 4 or 5 (tiles of at least 2^11 entries / 2^5 rows); smaller
+// tiles always use cap 256 and rounds of 4.
+template <typename R, int G, bool REV>
+hipError_t launch_col(R* a, int n, int start, int len, int lo, int sign, R scale,
+                      const Roots32<R>& rt, const QftTuning& tune, hipStream_t s) {
+  if (G < 5 || (tune.threads < 512 && tune.round_bits < 5))
+    return launch_col_cfg<R, G, REV, 256, 4>(a, n, start, len, lo, sign, scale, rt, s);
+  if (tune.threads >= 512 && tune.round_bits >= 5)
+    return launch_col_cfg<R, G, REV, 512, 5>(a, n, start, len, lo, sign, scale, rt, s);
+  if (tune.threads >= 512)
+    return launch_col_cfg<R, G, REV, 512, 4>(a, n, start, len, lo, sign, scale, rt, s);
+  return launch_col_cfg<R, G, REV, 256, 5>(a, n, start, len, lo, sign, scale, rt, s);
+}
+
+template <typename R, int T, bool REV>
+hipError_t launch_lds_t(R* a, int n, int start, int len, int lo, int hi, int sign, R scale,
+                        const Roots32<R>& rt, const QftTuning& tune, hipStream_t s) {
+  if (T < 11 || (tune.threads < 512 && tune.round_bits < 5))
+    return launch_lds_cfg<R, T, REV, 256, 4>(a, n, start, len, lo, hi, sign, scale, rt, s);
+  if (tune.threads >= 512 && tune.round_bits >= 5)
+    return launch_lds_cfg<R, T, REV, 512, 5>(a, n, start, len, lo, hi, sign, scale, rt, s);
+  if (tune.threads >= 512)
+    return launch_lds_cfg<R, T, REV, 512, 4>(a, n, start, len, lo, hi, sign, scale, rt, s);
+  return launch_lds_cfg<R, T, REV, 256, 5>(a, n, start, len, lo, hi, sign, scale, rt, s);
+}
+
 template <typename R, bool REV>
-hipError_t launch_pass(R* a, int n, int start, int len, int lo, int hi, int sign, R scale,
-                       hipStream_t s) {
-  const Roots32<R> rt = make_roots<R>();
-  const int T = n < tile_bits<R>() ? n : tile_bits<R>();
-  if (hi <= T) {
-    if (lo != start) return hipErrorInvalidValue;
-    const size_t shmem = size_t((1 << T) + ((1 << T) >> 4)) * 2 * sizeof(R);
-    const unsigned grid = static_cast<unsigned>(uint64_t(1) << (n - T));
-    hipLaunchKernelGGL((k_qft_lds<R, REV>), dim3(grid), dim3(kBlock), shmem, s, a, T, start, len,
-                       hi, sign, scale, rt);
-    return hipGetLastError();
-  }
-  if (lo < T) return hipErrorInvalidValue;
-  switch (hi - lo) {
-    case 1: return launch_reg<R, 1, REV>(a, n, start, len, lo, sign, scale, rt, s);
-    case 2: return launch_reg<R, 2, REV>(a, n, start, len, lo, sign, scale, rt, s);
-    case 3: return launch_reg<R, 3, REV>(a, n, start, len, lo, sign, scale, rt, s);
-    case 4: return launch_reg<R, 4, REV>(a, n, start, len, lo, sign, scale, rt, s);
-    case 5: return launch_reg<R, 5, REV>(a, n, start, len, lo, sign, scale, rt, s);
+hipError_t launch_lds(R* a, int n, int T, int start, int len, int lo, int hi, int sign, R scale,
+                      const Roots32<R>& rt, const QftTuning& tune, hipStream_t s) {
+  switch (T) {
+#define QS_LDS_CASE(t) \
+  case t: return launch_lds_t<R, t, REV>(a, n, start, len, lo, hi, sign, scale, rt, tune, s);
+    QS_LDS_CASE(1) QS_LDS_CASE(2) QS_LDS_CASE(3) QS_LDS_CASE(4) QS_LDS_CASE(5) QS_LDS_CASE(6)
+    QS_LDS_CASE(7) QS_LDS_CASE(8) QS_LDS_CASE(9) QS_LDS_CASE(10) QS_LDS_CASE(11)
+    QS_LDS_CASE(12)
+#undef QS_LDS_CASE
+    case 13:
+      if constexpr (sizeof(R) == 4)
+        return launch_lds_t<R, 13, REV>(a, n, start, len, lo, hi, sign, scale, rt, tune, s);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
+}
+
+template <typename R, bool REV>
+hipError_t launch_pass(R* a, int n, int start, int len, const QftPass& ps, int sign,
+                       const QftTuning& tune, hipStream_t s) {
+  const Roots32<R> rt = make_roots<R>();
+  const R scale = R(ps.scale);
+  const int G = ps.hi - ps.lo;
+  switch (ps.kind) {
+    case QftPass::LDS:
+      return launch_lds<R, REV>(a, n, ps.tile, start, len, ps.lo, ps.hi, sign, scale, rt, tune, s);
+    case QftPass::COL:
+      switch (G) {
+        case 1: return launch_col<R, 1, REV>(a, n, start, len, ps.lo, sign, scale, rt, tune, s);
+        case 2: return launch_col<R, 2, REV>(a, n, start, len, ps.lo, sign, scale, rt, tune, s);
+        case 3: return launch_col<R, 3, REV>(a, n, start, len, ps.lo, sign, scale, rt, tune, s);
+        case 4: return launch_col<R, 4, REV>(a, n, start, len, ps.lo, sign, scale, rt, tune, s);
+        case 5: return launch_col<R, 5, REV>(a, n, start, len, ps.lo, sign, scale, rt, tune, s);
+        case 6: return launch_col<R, 6, REV>(a, n, start, len, ps.lo, sign, scale, rt, tune, s);
+        case 7: return launch_col<R, 7, REV>(a, n, start, len, ps.lo, sign, scale, rt, tune, s);
+        default: return hipErrorInvalidValue;
+      }
+    case QftPass::REG:
+      switch (G) {
+        case 1: return launch_reg<R, 1, REV>(a, n, start, len, ps.lo, sign, scale, rt, s);
+        case 2: return launch_reg<R, 2, REV>(a, n, start, len, ps.lo, sign, scale, rt, s);
+        case 3: return launch_reg<R, 3, REV>(a, n, start, len, ps.lo, sign, scale, rt, s);
+        case 4: return launch_reg<R, 4, REV>(a, n, start, len, ps.lo, sign, scale, rt, s);
+        case 5: return launch_reg<R, 5, REV>(a, n, start, len, ps.lo, sign, scale, rt, s);
+        default: return hipErrorInvalidValue;
+      }
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
 
 template <typename R>
-hipError_t launch_qft_pass(R* a, int n, int start, int len, int lo, int hi, int sign, bool rev,
-                           double scale, hipStream_t s) {
-  return rev ? launch_pass<R, true>(a, n, start, len, lo, hi, sign, R(scale), s)
-             : launch_pass<R, false>(a, n, start, len, lo, hi, sign, R(scale), s);
+hipError_t launch_qft_pass(R* a, int n, int start, int len, const QftPass& ps, int sign, bool rev,
+                           const QftTuning& tune, hipStream_t s) {
+  return rev ? launch_pass<R, true>(a, n, start, len, ps, sign, tune, s)
+             : launch_pass<R, false>(a, n, start, len, ps, sign, tune, s);
 }
 
-template hipError_t launch_qft_pass<float>(float*, int, int, int, int, int, int, bool, double,
-                                           hipStream_t);
-template hipError_t launch_qft_pass<double>(double*, int, int, int, int, int, int, bool, double,
-                                            hipStream_t);
+template hipError_t launch_qft_pass<float>(float*, int, int, int, const QftPass&, int, bool,
+                                           const QftTuning&, hipStream_t);
+template hipError_t launch_qft_pass<double>(double*, int, int, int, const QftPass&, int, bool,
+                                            const QftTuning&, hipStream_t);
 
-// Pass plan of a QFT on [start, start+len): register passes of near-equal
-// width over the bits at or above the LDS tile and one LDS pass over the bits
-// below it; top-down in natural order, bottom-up when bit-reversed. Each pass
-// gets an exact power-of-two scale, the last one also 1/sqrt(2) if len is odd.
+// Pass plan of a QFT on [start, start+len): one contiguous-tile pass over the
+// range bits below T, then passes of near-equal width (at most kColMax, or
+// kRegMax for register passes) over the bits at or above T; top-down in
+// natural order, bottom-up when bit-reversed. Each pass gets an exact
+// power-of-two scale, the last one also 1/sqrt(2) if len is odd.
 template <typename R>
-int qft_plan(int n, int start, int len, bool rev, QftPass* out, int max_passes) {
-  const int T = n < tile_bits<R>() ? n : tile_bits<R>();
+int qft_plan(int n, int start, int len, bool rev, const QftTuning& tune, QftPass* out,
+             int max_passes) {
+  int T = tune.lds_bits > 0 ? tune.lds_bits : lds_bits<R>();
+  if (T > lds_bits<R>()) T = lds_bits<R>();
+  if (T > n) T = n;
+  const bool use_reg = tune.high_kind == 1;
+  const int wmax = use_reg ? kRegMax : kColMax;
   const int top = start + len;
-  const int reg_lo = start > T ? start : T;
+  int reg_lo = start > T ? start : T;
+  if (!use_reg && reg_lo < col_bits<R>()) reg_lo = col_bits<R>();
   int np = 0;
   if (top > reg_lo) {
     const int width = top - reg_lo;
-    const int passes = (width + kRegMax - 1) / kRegMax;
+    const int passes = (width + wmax - 1) / wmax;
     int cur = top;
     for (int k = 0; k < passes; ++k) {
       const int left = passes - k;
       const int w = (cur - reg_lo + left - 1) / left;
       if (np >= max_passes) return -1;
-      out[np].lo = cur - w;
-      out[np].hi = cur;
+      out[np] = {use_reg ? QftPass::REG : QftPass::COL, cur - w, cur, 0, 1.0};
       ++np;
       cur -= w;
     }
   }
-  if (start < T) {
+  if (start < reg_lo) {
+    // the bits [start, reg_lo) lie in the contiguous tile [0, T')
+    const int hi = top < reg_lo ? top : reg_lo;
+    int Tt = hi > T ? hi : T;
     if (np >= max_passes) return -1;
-    out[np].lo = start;
-    out[np].hi = top < T ? top : T;
+    out[np] = {QftPass::LDS, start, hi, Tt, 1.0};
     ++np;
   }
   if (rev)
@@ -359,7 +569,7 @@ int qft_plan(int n, int start, int len, bool rev, QftPass* out, int max_passes) 
   return np;
 }
 
-template int qft_plan<float>(int, int, int, bool, QftPass*, int);
-template int qft_plan<double>(int, int, int, bool, QftPass*, int);
+template int qft_plan<float>(int, int, int, bool, const QftTuning&, QftPass*, int);
+template int qft_plan<double>(int, int, int, bool, const QftTuning&, QftPass*, int);
 
 }  // namespace qs

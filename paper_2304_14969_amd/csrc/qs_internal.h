@@ -49,21 +49,37 @@ hipError_t launch_apply_fused(R* amps, int n, const int* qubits, int k, const R*
 // ---------------------------------------------------------------- QFT passes
 // One pass of a QFT on the qubit range [start, start+len): the stages of the
 // bits [lo, hi), each a butterfly on its bit and the phase controlled by the
-// other range bits, then a multiplication by `scale`. `rev` = the range is
-// stored bit-reversed (after an earlier transform's relabelling). `sign` = +1
-// forward, -1 conjugated (inverse transform).
+// other range bits, then a multiplication by `scale`.
+//   LDS: contiguous tile of 2^tile amplitudes (bits [0, tile)), hi <= tile.
+//   COL: tile of 2^(hi-lo) strided rows x contiguous columns.
+//   REG: each thread holds the 2^(hi-lo) amplitudes of its group.
 struct QftPass {
+  enum Kind { LDS = 0, COL = 1, REG = 2 };
+  int kind;
   int lo, hi;
+  int tile;
   double scale;
 };
+
+// Process-wide tuning knobs of the pass planner.
+struct QftTuning {
+  int lds_bits = 0;   // contiguous tile bits (0: default per precision)
+  int high_kind = 0;  // passes above the tile: 0 strided LDS tiles, 1 registers
+  int threads = 512;  // thread cap of the LDS tile launches (256 or 512)
+  int round_bits = 4; // widest register round inside an LDS tile (4 or 5)
+};
+
+// `rev` = the range is stored bit-reversed (after an earlier transform's
+// relabelling); `sign` = +1 forward, -1 conjugated (inverse transform).
 template <typename R>
-hipError_t launch_qft_pass(R* amps, int n, int start, int len, int lo, int hi, int sign, bool rev,
-                           double scale, hipStream_t s);
+hipError_t launch_qft_pass(R* amps, int n, int start, int len, const QftPass& pass, int sign,
+                           bool rev, const QftTuning& tune, hipStream_t s);
 
 // Pass plan in launch order; returns the number of passes (-1 if more than
 // max_passes).
 template <typename R>
-int qft_plan(int n, int start, int len, bool rev, QftPass* out, int max_passes);
+int qft_plan(int n, int start, int len, bool rev, const QftTuning& tune, QftPass* out,
+             int max_passes);
 
 // ---------------------------------------------------------------- state setup
 template <typename R>

@@ -257,3 +257,28 @@ def test_error_codes(qs_lib):
         # state still usable and unchanged by the rejected calls
         assert abs(st.norm() - 1.0) < 1e-7
         st.check(1e-6)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("high_pass,lds_bits", [(0, 0), (1, 0), (0, 9), (1, 10), (0, 12), (0, 7)])
+def test_qft_pass_variants(qs_lib, dtype, high_pass, lds_bits):
+    """Every planner variant (LDS tile size, strided-LDS or register passes
+    above it) in both storage orientations."""
+    qs = qs_lib
+    n = 17
+    a = workloads.gaussian_state(n, 555)
+    qs.tune_set("qft.high_pass", high_pass)
+    qs.tune_set("qft.lds_bits", lds_bits)
+    try:
+        with fresh(qs, n, dtype, a) as st:
+            want = a
+            for inv in (False, True, False):
+                st.qft(inverse=inv)
+                want = dense.qft(want, n, inverse=inv)
+                assert_parity(st.amplitudes(), want, dtype, f"hp={high_pass} T={lds_bits}")
+            st.qft(3, 11)
+            want = dense.qft(want, n, 3, 11)
+            assert_parity(st.amplitudes(), want, dtype, "partial")
+    finally:
+        qs.tune_set("qft.high_pass", 0)
+        qs.tune_set("qft.lds_bits", 0)
