@@ -138,6 +138,53 @@ int qs_apply_fused(qs_state* st, const int* qubits, int k, const double* m);
  * relabelling). inverse != 0 applies the inverse transform. */
 int qs_qft(qs_state* st, int start, int len, int inverse);
 
+/* ------------------------------------------------------------ circuits */
+
+/* A circuit is a host-side gate list on n qubits that is fused into dense
+ * blocks of at most kmax qubits and run with one sweep per block. SWAP gates
+ * are kept as a renaming of the positions the later gates act on and end up in
+ * the state's labels (no data movement). */
+typedef struct qs_circuit qs_circuit;
+
+/* named gate kinds for qs_circuit_add_gate; two-qubit controlled kinds take
+ * qubits = {control, target}; the "A" kinds act when the control is |0>
+ * (the anti-controlled couplers of Sec. III-C) */
+enum {
+  QS_GATE_H = 1, QS_GATE_X = 2, QS_GATE_Y = 3, QS_GATE_Z = 4,
+  QS_GATE_U3 = 5,     /* params = {theta, phi, lambda}: U of Sec. III-C */
+  QS_GATE_CZ = 6, QS_GATE_ISWAP = 7,
+  QS_GATE_CP = 8,     /* params = {theta}: e^{i theta} on |11> */
+  QS_GATE_SWAP = 9, QS_GATE_CX = 10, QS_GATE_CY = 11,
+  QS_GATE_AX = 12, QS_GATE_AY = 13, QS_GATE_AZ = 14
+};
+
+/* Empty circuit on n qubits (1 <= n <= 64). */
+int qs_circuit_create(int n, qs_circuit** out);
+/* Release a circuit (waits for the device if its matrices are in use). */
+int qs_circuit_free(qs_circuit* c);
+/* Append a named gate; its matrix is built in float64. QS_E_INVAL for an
+ * unknown kind, a qubit out of range or repeated, missing or non-finite
+ * parameters. Invalidates an earlier plan. */
+int qs_circuit_add_gate(qs_circuit* c, int kind, const int* qubits, const double* params);
+/* Append a dense k-qubit matrix (1 <= k <= QS_MAX_FUSED), layout as in
+ * qs_apply_fused. */
+int qs_circuit_add_matrix(qs_circuit* c, const int* qubits, int k, const double* m);
+/* Fuse the gate list into blocks of at most kmax qubits (1..QS_MAX_FUSED;
+ * 0 = 5). Gates in order; a gate joins the open blocks it touches when their
+ * union has at most kmax qubits, otherwise those blocks are closed. Block
+ * matrices are products of the gates in float64. */
+int qs_circuit_plan(qs_circuit* c, int kmax);
+/* Gate count, block count (-1 before planning) and widest block. */
+int qs_circuit_info(const qs_circuit* c, int* ngates, int* nblocks, int* max_k);
+/* Block i of a planned circuit: its width, its positions (position p = qubit p
+ * before any SWAP of the circuit) and, if m != NULL, its 2^k x 2^k matrix
+ * (2*4^k doubles, layout as in qs_apply_fused). */
+int qs_circuit_block(const qs_circuit* c, int i, int* k, int* qubits, double* m);
+/* Apply a circuit to a state of the same width (plans it first if needed).
+ * Block matrices are uploaded once per precision and kept with the circuit.
+ * Complex64 blocks of 4-5 qubits run on the matrix cores. */
+int qs_run(qs_state* st, qs_circuit* c);
+
 /* ------------------------------------------------------------ readout */
 
 /* All 2^n amplitudes in index order (relabelling undone), converted to

@@ -8,9 +8,11 @@ built or no GPU is visible, `load()` raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import math
 import os
+import weakref
 
 import numpy as np
 
@@ -38,6 +40,20 @@ class CapacityError(QSError):
 _lib = None
 _alloc_cb = None
 _free_cb = None
+_live = weakref.WeakSet()   # states and circuits to release before interpreter teardown
+_closing = False
+
+
+def _release_all():
+    """Free every live handle while torch (the allocator behind the library's
+    hooks) is still alive; later finalizers then do nothing."""
+    global _closing
+    for obj in list(_live):
+        try:
+            obj.free()
+        except Exception:
+            pass
+    _closing = True
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 
@@ -73,6 +89,15 @@ _SIGS = [
     ("qs_probs", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_uint64]),
     ("qs_norm", C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     ("qs_check", C.c_int, [C.c_void_p, C.c_double]),
+    ("qs_circuit_create", C.c_int, [C.c_int, C.POINTER(C.c_void_p)]),
+    ("qs_circuit_free", C.c_int, [C.c_void_p]),
+    ("qs_circuit_add_gate", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    ("qs_circuit_add_matrix", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_double)]),
+    ("qs_circuit_plan", C.c_int, [C.c_void_p, C.c_int]),
+    ("qs_circuit_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    ("qs_circuit_block", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                   C.POINTER(C.c_double)]),
+    ("qs_run", C.c_int, [C.c_void_p, C.c_void_p]),
     ("qs_tune_set", C.c_int, [C.c_char_p, C.c_int64]),
     ("qs_tune_get", C.c_int, [C.c_char_p, C.POINTER(C.c_int64)]),
     ("qs_profile_start", C.c_int, [C.c_void_p]),
@@ -104,6 +129,8 @@ def load(use_torch_allocator: bool = True) -> C.CDLL:
     import torch
     if not torch.cuda.is_available():
         raise RuntimeError("no GPU visible: the simulator has no CPU path")
+    # registered after torch's own exit handlers, so it runs before them
+    atexit.register(_release_all)
     lib = open_library()
     if use_torch_allocator:
         def _alloc(nbytes, _user):
@@ -132,10 +159,89 @@ def _dptr(arr: np.ndarray):
     return arr.ctypes.data_as(C.POINTER(C.c_double))
 
 
-def mat_arg(m) -> np.ndarray:
-    """Complex matrix -> contiguous float64 (re, im) interleaved, row-major."""
+def mat_arg(m, k: int) -> np.ndarray:
+    """2^k x 2^k complex matrix -> contiguous float64 (re, im) interleaved,
+    row-major; the shape is checked because the library reads 2*4^k doubles."""
     m = np.ascontiguousarray(np.asarray(m, dtype=np.complex128))
+    if m.shape != (2 ** k, 2 ** k):
+        raise ValueError(f"matrix of shape {m.shape} for a {k}-qubit gate")
     return np.ascontiguousarray(m.view(np.float64).reshape(-1))
+
+
+GATE = {"h": 1, "x": 2, "y": 3, "z": 4, "u3": 5, "cz": 6, "iswap": 7, "cp": 8, "swap": 9,
+        "cx": 10, "cy": 11, "ax": 12, "ay": 13, "az": 14}
+
+
+class Circuit:
+    """Host-side gate list, fused into blocks by the library's planner.
+    Needs only the library, not a GPU (planning is host code)."""
+
+    def __init__(self, n: int, lib=None):
+        self.lib = lib or (_lib if _lib is not None else open_library())
+        h = C.c_void_p()
+        _check(self.lib, self.lib.qs_circuit_create(n, C.byref(h)))
+        self.h = h
+        self.n = n
+        _live.add(self)
+
+    def free(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.qs_circuit_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        if _closing:
+            return
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def add(self, kind: str, qubits, params=()):
+        q = (C.c_int * len(qubits))(*qubits)
+        p = (C.c_double * max(1, len(params)))(*params)
+        _check(self.lib, self.lib.qs_circuit_add_gate(self.h, GATE[kind], q, p))
+
+    def add_matrix(self, qubits, m):
+        q = (C.c_int * len(qubits))(*qubits)
+        _check(self.lib, self.lib.qs_circuit_add_matrix(self.h, q, len(qubits),
+                                                        _dptr(mat_arg(m, len(qubits)))))
+
+    def add_gates(self, gates):
+        """workloads gate tuples: h, u3, cp, cz, iswap, swap, mat."""
+        for g in gates:
+            k = g[0]
+            if k == "h":
+                self.add("h", [g[1]])
+            elif k == "u3":
+                self.add("u3", [g[1]], g[2:5])
+            elif k == "cp":
+                self.add("cp", [g[1], g[2]], [g[3]])
+            elif k in ("cz", "iswap", "swap", "cx", "cy", "ax", "ay", "az"):
+                self.add(k, [g[1], g[2]])
+            elif k == "mat":
+                self.add_matrix(list(g[1]), g[2])
+            else:
+                raise ValueError(f"gate {k!r} has no circuit form")
+        return self
+
+    def plan(self, kmax: int = 0):
+        _check(self.lib, self.lib.qs_circuit_plan(self.h, kmax))
+        return self
+
+    def info(self) -> dict:
+        a, b, c = C.c_int(), C.c_int(), C.c_int()
+        _check(self.lib, self.lib.qs_circuit_info(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return {"gates": a.value, "blocks": b.value, "max_k": c.value}
+
+    def block(self, i: int):
+        k = C.c_int()
+        q = (C.c_int * MAX_FUSED)()
+        _check(self.lib, self.lib.qs_circuit_block(self.h, i, C.byref(k), q, None))
+        d = 2 ** k.value
+        m = np.empty(2 * d * d, dtype=np.float64)
+        _check(self.lib, self.lib.qs_circuit_block(self.h, i, C.byref(k), q, _dptr(m)))
+        return list(q[:k.value]), m.view(np.complex128).reshape(d, d)
 
 
 def tune_set(key: str, value: int):
@@ -160,6 +266,7 @@ class State:
         self.h = h
         self.n = n
         self.dtype = dtype
+        _live.add(self)
         self.set_stream(stream)
 
     # -- lifecycle
@@ -175,6 +282,8 @@ class State:
             self.h = None
 
     def __del__(self):
+        if _closing:
+            return
         try:
             self.free()
         except Exception:
@@ -205,12 +314,12 @@ class State:
 
     # -- gates
     def apply_1q(self, q: int, m):
-        _check(self.lib, self.lib.qs_apply_1q(self.h, q, _dptr(mat_arg(m))))
+        _check(self.lib, self.lib.qs_apply_1q(self.h, q, _dptr(mat_arg(m, 1))))
 
     def apply_ctrl(self, ctrls, cvals: int, target: int, m):
         c = (C.c_int * len(ctrls))(*ctrls)
         _check(self.lib, self.lib.qs_apply_ctrl(self.h, c, len(ctrls), int(cvals), target,
-                                                _dptr(mat_arg(m))))
+                                                _dptr(mat_arg(m, 1))))
 
     def apply_cphase(self, a: int, b: int, theta: float):
         _check(self.lib, self.lib.qs_apply_cphase(self.h, a, b, float(theta)))
@@ -220,7 +329,11 @@ class State:
 
     def apply_fused(self, qubits, m):
         qs = (C.c_int * len(qubits))(*qubits)
-        _check(self.lib, self.lib.qs_apply_fused(self.h, qs, len(qubits), _dptr(mat_arg(m))))
+        _check(self.lib, self.lib.qs_apply_fused(self.h, qs, len(qubits),
+                                                 _dptr(mat_arg(m, len(qubits)))))
+
+    def run(self, circ: "Circuit"):
+        _check(self.lib, self.lib.qs_run(self.h, circ.h))
 
     def qft(self, start: int = 0, length: int | None = None, inverse: bool = False):
         length = self.n - start if length is None else length

@@ -17,7 +17,8 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqs.so")
 
-SOURCES = ["capi.cpp", "k_gates.hip", "k_qft.hip", "k_reduce.hip", "k_fused.hip"]
+SOURCES = ["capi.cpp", "k_gates.hip", "k_qft.hip", "k_reduce.hip", "k_fused.hip",
+           "k_fused_mfma.hip", "circuit.cpp"]
 
 ARCH = "gfx950"
 FLAGS = [

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/qs.h"
+#include "circuit.h"
 #include "qs_internal.h"
 
 namespace {
@@ -32,6 +33,7 @@ qs_free_fn g_free = nullptr;
 void* g_user = nullptr;
 int g_live_states = 0;
 qs::QftTuning g_qft_tune;
+int g_fused_mfma = 1;  // complex64 blocks of 4-5 qubits on the matrix cores
 
 void* dev_alloc(size_t bytes) {
   if (g_alloc) return g_alloc(bytes, g_user);
@@ -151,6 +153,31 @@ struct ProfScope {
   }
 };
 
+// Dense block on physical bits phys[0..k) with a device matrix in the state's
+// precision: complex64 blocks of 4 or 5 qubits go to the matrix cores when the
+// state holds a full tile, everything else to the vector-FMA kernel.
+hipError_t launch_block(qs_state* st, const int* phys, int k, const void* dmat) {
+  static const char* names[] = {"", "fused1", "fused2", "fused3", "fused4", "fused5", "fused6"};
+  static const char* mnames[] = {"", "", "", "", "fused4_mfma", "fused5_mfma", ""};
+  const double bytes = 2.0 * std::ldexp(1.0, st->n) * ab(st);
+  if (st->dtype == QS_C64) {
+    if (g_fused_mfma && (k == 4 || k == 5)) {
+      qs::FusedGeom geom;
+      if (qs::fused_geometry(st->n, phys, k, &geom)) {
+        ProfScope ps(st, mnames[k], bytes);
+        return qs::launch_fused_mfma(static_cast<float*>(st->amps), st->n, phys, k,
+                                     static_cast<const float*>(dmat), st->stream);
+      }
+    }
+    ProfScope ps(st, names[k], bytes);
+    return qs::launch_apply_fused(static_cast<float*>(st->amps), st->n, phys, k,
+                                  static_cast<const float*>(dmat), st->stream);
+  }
+  ProfScope ps(st, names[k], bytes);
+  return qs::launch_apply_fused(static_cast<double*>(st->amps), st->n, phys, k,
+                                static_cast<const double*>(dmat), st->stream);
+}
+
 // Physical exchange of bits pa and pb.
 int phys_swap(qs_state* st, int pa, int pb) {
   ProfScope ps(st, "bitswap", 2.0 * std::ldexp(1.0, st->n - 1) * ab(st));
@@ -186,6 +213,29 @@ int sync(qs_state* st, const char* what) {
   return device_error(st, hipStreamSynchronize(st->stream), what);
 }
 
+}  // namespace
+
+namespace qs {
+
+void set_last_error(const char* msg) { g_err = msg; }
+
+// Drops a circuit's plan and its device copies (after an edit or a re-plan).
+void circuit_invalidate(qs_circuit* c) {
+  // launches already queued may still read the matrices
+  if (c->dmat[0] || c->dmat[1]) (void)hipDeviceSynchronize();
+  for (int p = 0; p < 2; ++p) {
+    if (c->dmat[p]) dev_free(c->dmat[p]);
+    c->dmat[p] = nullptr;
+    c->off[p].clear();
+  }
+  c->planned = false;
+  c->blocks.clear();
+}
+
+}  // namespace qs
+
+namespace {
+
 
 }  // namespace
 
@@ -203,6 +253,9 @@ int qs_tune_set(const char* key, int64_t value) {
   } else if (!std::strcmp(key, "qft.high_pass")) {
     if (value < 0 || value > 1) return fail(QS_E_INVAL, "qft.high_pass must be 0 or 1");
     g_qft_tune.high_kind = int(value);
+  } else if (!std::strcmp(key, "fused.mfma")) {
+    if (value < 0 || value > 1) return fail(QS_E_INVAL, "fused.mfma must be 0 or 1");
+    g_fused_mfma = int(value);
   } else if (!std::strcmp(key, "qft.threads")) {
     if (value != 256 && value != 512) return fail(QS_E_INVAL, "qft.threads must be 256 or 512");
     g_qft_tune.threads = int(value);
@@ -220,6 +273,7 @@ int qs_tune_get(const char* key, int64_t* value) {
   if (!std::strcmp(key, "qft.lds_bits")) *value = g_qft_tune.lds_bits;
   else if (!std::strcmp(key, "qft.high_pass")) *value = g_qft_tune.high_kind;
   else if (!std::strcmp(key, "qft.threads")) *value = g_qft_tune.threads;
+  else if (!std::strcmp(key, "fused.mfma")) *value = g_fused_mfma;
   else if (!std::strcmp(key, "qft.round_bits")) *value = g_qft_tune.round_bits;
   else return fail(QS_E_INVAL, "unknown tuning key '%s'", key);
   return QS_OK;
@@ -437,25 +491,15 @@ int qs_apply_fused(qs_state* st, const int* qubits, int k, const double* m) {
     seen |= uint64_t(1) << qubits[j];
     phys[j] = st->perm[qubits[j]];
   }
-  static const char* names[] = {"", "fused1", "fused2", "fused3", "fused4", "fused5", "fused6"};
   hipError_t e;
   if (st->dtype == QS_C64) {
     std::vector<float> mf(2 * D * D);
     for (size_t i = 0; i < mf.size(); ++i) mf[i] = static_cast<float>(m[i]);
     e = hipMemcpyAsync(st->mat, mf.data(), mf.size() * sizeof(float), hipMemcpyHostToDevice, st->stream);
-    if (e == hipSuccess) {
-      ProfScope ps(st, names[k], 2.0 * std::ldexp(1.0, st->n) * ab(st));
-      e = qs::launch_apply_fused(static_cast<float*>(st->amps), st->n, phys, k,
-                                 static_cast<const float*>(st->mat), st->stream);
-    }
   } else {
     e = hipMemcpyAsync(st->mat, m, 2 * D * D * sizeof(double), hipMemcpyHostToDevice, st->stream);
-    if (e == hipSuccess) {
-      ProfScope ps(st, names[k], 2.0 * std::ldexp(1.0, st->n) * ab(st));
-      e = qs::launch_apply_fused(static_cast<double*>(st->amps), st->n, phys, k,
-                                 static_cast<const double*>(st->mat), st->stream);
-    }
   }
+  if (e == hipSuccess) e = launch_block(st, phys, k, st->mat);
   return device_error(st, e, "apply_fused");
 }
 
@@ -499,6 +543,73 @@ int qs_qft(qs_state* st, int start, int len, int inverse) {
   }
   // final bit reversal of the range, as a relabelling
   for (int i = 0; i < len / 2; ++i) std::swap(st->perm[start + i], st->perm[start + len - 1 - i]);
+  return QS_OK;
+}
+
+// ------------------------------------------------------------------ circuits
+
+int qs_circuit_free(qs_circuit* c) {
+  if (!c) return QS_OK;
+  qs::circuit_invalidate(c);
+  delete c;
+  return QS_OK;
+}
+
+// Runs a planned circuit (plans it with the default block width first if
+// needed): every block is one sweep; the circuit's SWAP renaming is then
+// folded into the state's labels.
+int qs_run(qs_state* st, qs_circuit* c) {
+  if (int rc = check_state(st)) return rc;
+  if (!c) return fail(QS_E_INVAL, "circuit is NULL");
+  if (c->n != st->n) return fail(QS_E_INVAL, "circuit has %d qubits, state %d", c->n, st->n);
+  if (!c->planned)
+    if (int rc = qs_circuit_plan(c, c->kmax)) return rc;
+  const int prec = st->dtype == QS_C64 ? 0 : 1;
+  if (!c->dmat[prec] && !c->blocks.empty()) {
+    size_t total = 0;
+    c->off[prec].clear();
+    for (const auto& b : c->blocks) {
+      c->off[prec].push_back(total);
+      total += 2 * b.m.size();
+    }
+    const size_t esz = prec == 0 ? sizeof(float) : sizeof(double);
+    void* d = dev_alloc(total * esz);
+    if (!d) return fail(QS_E_NOMEM, "allocating %zu bytes of block matrices", total * esz);
+    hipError_t e;
+    if (prec == 0) {
+      std::vector<float> h(total);
+      for (size_t bi = 0; bi < c->blocks.size(); ++bi)
+        for (size_t i = 0; i < c->blocks[bi].m.size(); ++i) {
+          h[c->off[0][bi] + 2 * i] = float(c->blocks[bi].m[i].real());
+          h[c->off[0][bi] + 2 * i + 1] = float(c->blocks[bi].m[i].imag());
+        }
+      e = hipMemcpy(d, h.data(), total * esz, hipMemcpyHostToDevice);
+    } else {
+      std::vector<double> h(total);
+      for (size_t bi = 0; bi < c->blocks.size(); ++bi)
+        for (size_t i = 0; i < c->blocks[bi].m.size(); ++i) {
+          h[c->off[1][bi] + 2 * i] = c->blocks[bi].m[i].real();
+          h[c->off[1][bi] + 2 * i + 1] = c->blocks[bi].m[i].imag();
+        }
+      e = hipMemcpy(d, h.data(), total * esz, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+      dev_free(d);
+      return device_error(st, e, "uploading block matrices");
+    }
+    c->dmat[prec] = d;
+  }
+  const size_t esz = prec == 0 ? sizeof(float) : sizeof(double);
+  for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
+    const qs::Block& b = c->blocks[bi];
+    int phys[QS_MAX_FUSED];
+    for (int j = 0; j < b.k; ++j) phys[j] = st->perm[b.q[j]];
+    const void* dm = static_cast<const char*>(c->dmat[prec]) + c->off[prec][bi] * esz;
+    if (int rc = device_error(st, launch_block(st, phys, b.k, dm), "run block")) return rc;
+  }
+  int np[64];
+  for (int q = 0; q < st->n; ++q) np[q] = st->perm[c->pos[q]];
+  for (int q = 0; q < st->n; ++q) st->perm[q] = np[q];
   return QS_OK;
 }
 

@@ -1,0 +1,313 @@
+// Circuit object and gate-fusion planner (host C++, float64).
+//
+// A random-circuit layer (Sec. III-C) is U(theta, phi, lambda) on every qubit
+// followed by two-qubit couplers; applying each gate as its own HBM sweep costs
+// one read and write of the whole ket per gate. The planner groups consecutive
+// gates that act on at most kmax distinct qubits into one dense block whose
+// matrix (the product of its gates, float64) is applied in a single sweep.
+// SWAP gates never move data: they rename the positions later gates act on,
+// and the circuit ends with that renaming applied to the state's labels
+// (Table I: SWAP by qubit label swap).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "circuit.h"
+
+namespace qs {
+
+namespace {
+
+std::vector<cd> eye(int k) {
+  const int d = 1 << k;
+  std::vector<cd> m(size_t(d) * d, cd(0, 0));
+  for (int i = 0; i < d; ++i) m[size_t(i) * d + i] = 1.0;
+  return m;
+}
+
+// U(theta, phi, lambda) of Sec. III-C.
+std::vector<cd> u3(double t, double p, double l) {
+  const double c = std::cos(t / 2), s = std::sin(t / 2);
+  return {cd(c, 0), -std::polar(1.0, l) * s, std::polar(1.0, p) * s, std::polar(1.0, p + l) * c};
+}
+
+// Two-qubit controlled 2x2: local bit 0 = control, bit 1 = target; acts when
+// the control equals `cv`.
+std::vector<cd> controlled(const std::vector<cd>& u, int cv) {
+  std::vector<cd> m = eye(2);
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) m[size_t(cv + 2 * i) * 4 + (cv + 2 * j)] = u[size_t(i) * 2 + j];
+  return m;
+}
+
+}  // namespace
+
+bool gate_matrix(int kind, int nq, const double* p, std::vector<cd>* m, int* k_out) {
+  const double r2 = 1.0 / std::sqrt(2.0);
+  const std::vector<cd> X = {0.0, 1.0, 1.0, 0.0};
+  const std::vector<cd> Y = {0.0, cd(0, -1), cd(0, 1), 0.0};
+  const std::vector<cd> Z = {1.0, 0.0, 0.0, -1.0};
+  int k = 0;
+  switch (kind) {
+    case QS_GATE_H: k = 1; *m = {r2, r2, r2, -r2}; break;
+    case QS_GATE_X: k = 1; *m = X; break;
+    case QS_GATE_Y: k = 1; *m = Y; break;
+    case QS_GATE_Z: k = 1; *m = Z; break;
+    case QS_GATE_U3: k = 1; *m = u3(p[0], p[1], p[2]); break;
+    case QS_GATE_CZ: k = 2; *m = eye(2); (*m)[15] = -1.0; break;
+    case QS_GATE_CP: k = 2; *m = eye(2); (*m)[15] = std::polar(1.0, p[0]); break;
+    case QS_GATE_ISWAP:
+      k = 2;
+      *m = eye(2);
+      (*m)[1 * 4 + 1] = 0.0; (*m)[2 * 4 + 2] = 0.0;
+      (*m)[1 * 4 + 2] = cd(0, 1); (*m)[2 * 4 + 1] = cd(0, 1);
+      break;
+    case QS_GATE_SWAP:
+      k = 2;
+      *m = eye(2);
+      (*m)[1 * 4 + 1] = 0.0; (*m)[2 * 4 + 2] = 0.0;
+      (*m)[1 * 4 + 2] = 1.0; (*m)[2 * 4 + 1] = 1.0;
+      break;
+    case QS_GATE_CX: k = 2; *m = controlled(X, 1); break;
+    case QS_GATE_CY: k = 2; *m = controlled(Y, 1); break;
+    case QS_GATE_AX: k = 2; *m = controlled(X, 0); break;
+    case QS_GATE_AY: k = 2; *m = controlled(Y, 0); break;
+    case QS_GATE_AZ: k = 2; *m = controlled(Z, 0); break;
+    default: return false;
+  }
+  if (nq != k) return false;
+  *k_out = k;
+  return true;
+}
+
+namespace {
+
+// m <- g m, where g acts on the block-local bits lp[0..gk) of a k-bit block.
+void left_apply(std::vector<cd>& m, int k, const std::vector<cd>& g, int gk, const int* lp) {
+  const int d = 1 << k, gd = 1 << gk;
+  int mask = 0;
+  for (int j = 0; j < gk; ++j) mask |= 1 << lp[j];
+  std::vector<cd> in(gd), out(gd);
+  std::vector<int> idx(gd);
+  for (int col = 0; col < d; ++col) {
+    for (int base = 0; base < d; ++base) {
+      if (base & mask) continue;
+      for (int s = 0; s < gd; ++s) {
+        int x = base;
+        for (int j = 0; j < gk; ++j) x |= ((s >> j) & 1) << lp[j];
+        idx[s] = x;
+        in[s] = m[size_t(x) * d + col];
+      }
+      for (int r = 0; r < gd; ++r) {
+        cd acc = 0.0;
+        for (int s = 0; s < gd; ++s) acc += g[size_t(r) * gd + s] * in[s];
+        out[r] = acc;
+      }
+      for (int s = 0; s < gd; ++s) m[size_t(idx[s]) * d + col] = out[s];
+    }
+  }
+}
+
+struct Open {
+  bool live = true;
+  std::vector<int> qubits;
+  std::vector<int> gates;
+};
+
+Block build_block(const Open& o, const std::vector<Gate>& gates) {
+  Block b;
+  std::vector<int> q = o.qubits;
+  std::sort(q.begin(), q.end());
+  b.k = int(q.size());
+  for (int j = 0; j < b.k; ++j) b.q[j] = q[j];
+  b.m = eye(b.k);
+  b.ngates = int(o.gates.size());
+  for (int gi : o.gates) {
+    const Gate& g = gates[gi];
+    int lp[QS_MAX_FUSED];
+    for (int j = 0; j < g.k; ++j)
+      lp[j] = int(std::lower_bound(q.begin(), q.end(), g.q[j]) - q.begin());
+    left_apply(b.m, b.k, g.m, g.k, lp);
+  }
+  return b;
+}
+
+}  // namespace
+
+std::vector<Block> fuse(const std::vector<Gate>& gates, int n, int kmax) {
+  std::vector<Open> open;
+  std::vector<int> owner(n, -1);
+  std::vector<Block> out;
+  auto emit = [&](int b) {
+    out.push_back(build_block(open[b], gates));
+    for (int q : open[b].qubits) owner[q] = -1;
+    open[b].live = false;
+  };
+  for (int gi = 0; gi < int(gates.size()); ++gi) {
+    const Gate& g = gates[gi];
+    std::vector<int> touched;
+    std::vector<int> uni(g.q, g.q + g.k);
+    for (int j = 0; j < g.k; ++j) {
+      const int b = owner[g.q[j]];
+      if (b >= 0 && std::find(touched.begin(), touched.end(), b) == touched.end()) {
+        touched.push_back(b);
+        for (int q : open[b].qubits)
+          if (std::find(uni.begin(), uni.end(), q) == uni.end()) uni.push_back(q);
+      }
+    }
+    Open nb;
+    if (int(uni.size()) <= kmax) {
+      // merge: the touched blocks act on disjoint qubits, so their gate lists
+      // may be concatenated in any order before this gate
+      std::sort(touched.begin(), touched.end());
+      for (int b : touched) {
+        nb.gates.insert(nb.gates.end(), open[b].gates.begin(), open[b].gates.end());
+        open[b].live = false;
+      }
+      nb.qubits = uni;
+    } else {
+      std::sort(touched.begin(), touched.end());
+      for (int b : touched) emit(b);
+      nb.qubits.assign(g.q, g.q + g.k);
+    }
+    nb.gates.push_back(gi);
+    open.push_back(nb);
+    for (int q : open.back().qubits) owner[q] = int(open.size()) - 1;
+  }
+  for (int b = 0; b < int(open.size()); ++b)
+    if (open[b].live) emit(b);
+  return out;
+}
+
+}  // namespace qs
+
+// ------------------------------------------------------------------ C ABI
+
+namespace qs {
+void set_last_error(const char* msg);    // capi.cpp
+void circuit_invalidate(qs_circuit* c);  // frees device copies (capi.cpp)
+}  // namespace qs
+
+namespace {
+int cfail(int code, const char* fmt, ...) {
+  char buf[256];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  qs::set_last_error(buf);
+  return code;
+}
+}  // namespace
+
+extern "C" {
+
+int qs_circuit_create(int n, qs_circuit** out) {
+  if (!out) return cfail(QS_E_INVAL, "out is NULL");
+  if (n < 1 || n > 64) return cfail(QS_E_INVAL, "n = %d outside [1, 64]", n);
+  qs_circuit* c = new qs_circuit();
+  c->n = n;
+  c->pos.resize(n);
+  for (int q = 0; q < n; ++q) c->pos[q] = q;
+  *out = c;
+  return QS_OK;
+}
+
+static int add_checked(qs_circuit* c, const int* qubits, int k, std::vector<qs::cd> m) {
+  if (!c) return cfail(QS_E_INVAL, "circuit is NULL");
+  if (!qubits) return cfail(QS_E_INVAL, "qubits is NULL");
+  if (k < 1 || k > QS_MAX_FUSED) return cfail(QS_E_INVAL, "gate on %d qubits", k);
+  for (int j = 0; j < k; ++j) {
+    if (qubits[j] < 0 || qubits[j] >= c->n)
+      return cfail(QS_E_INVAL, "qubit %d out of range [0, %d)", qubits[j], c->n);
+    for (int i = 0; i < j; ++i)
+      if (qubits[i] == qubits[j]) return cfail(QS_E_INVAL, "qubit %d used twice", qubits[j]);
+  }
+  for (const auto& v : m)
+    if (!std::isfinite(v.real()) || !std::isfinite(v.imag()))
+      return cfail(QS_E_INVAL, "non-finite matrix entry");
+  qs::circuit_invalidate(c);
+  qs::Gate g;
+  g.k = k;
+  for (int j = 0; j < k; ++j) g.q[j] = c->pos[qubits[j]];
+  g.m = std::move(m);
+  c->gates.push_back(std::move(g));
+  return QS_OK;
+}
+
+int qs_circuit_add_gate(qs_circuit* c, int kind, const int* qubits, const double* params) {
+  if (!c) return cfail(QS_E_INVAL, "circuit is NULL");
+  if (!qubits) return cfail(QS_E_INVAL, "qubits is NULL");
+  const int nq = (kind >= QS_GATE_CZ) ? 2 : 1;
+  if ((kind == QS_GATE_U3 || kind == QS_GATE_CP) && !params)
+    return cfail(QS_E_INVAL, "gate kind %d needs parameters", kind);
+  if (kind == QS_GATE_U3)
+    for (int i = 0; i < 3; ++i)
+      if (!std::isfinite(params[i])) return cfail(QS_E_INVAL, "non-finite parameter");
+  if (kind == QS_GATE_CP && !std::isfinite(params[0])) return cfail(QS_E_INVAL, "non-finite parameter");
+  std::vector<qs::cd> m;
+  int k = 0;
+  if (!qs::gate_matrix(kind, nq, params, &m, &k)) return cfail(QS_E_INVAL, "unknown gate kind %d", kind);
+  if (kind == QS_GATE_SWAP) {
+    for (int j = 0; j < 2; ++j)
+      if (qubits[j] < 0 || qubits[j] >= c->n)
+        return cfail(QS_E_INVAL, "qubit %d out of range [0, %d)", qubits[j], c->n);
+    if (qubits[0] == qubits[1]) return cfail(QS_E_INVAL, "qubit %d used twice", qubits[0]);
+    qs::circuit_invalidate(c);
+    std::swap(c->pos[qubits[0]], c->pos[qubits[1]]);
+    return QS_OK;
+  }
+  return add_checked(c, qubits, k, std::move(m));
+}
+
+int qs_circuit_add_matrix(qs_circuit* c, const int* qubits, int k, const double* m) {
+  if (!m) return cfail(QS_E_INVAL, "matrix is NULL");
+  if (k < 1 || k > QS_MAX_FUSED) return cfail(QS_E_INVAL, "gate on %d qubits", k);
+  const size_t d = size_t(1) << k;
+  std::vector<qs::cd> mm(d * d);
+  for (size_t i = 0; i < d * d; ++i) mm[i] = qs::cd(m[2 * i], m[2 * i + 1]);
+  return add_checked(c, qubits, k, std::move(mm));
+}
+
+int qs_circuit_plan(qs_circuit* c, int kmax) {
+  if (!c) return cfail(QS_E_INVAL, "circuit is NULL");
+  if (kmax == 0) kmax = 5;
+  if (kmax < 1 || kmax > QS_MAX_FUSED) return cfail(QS_E_INVAL, "kmax = %d outside [1, %d]", kmax, QS_MAX_FUSED);
+  qs::circuit_invalidate(c);
+  c->kmax = kmax;
+  c->blocks = qs::fuse(c->gates, c->n, kmax);
+  c->planned = true;
+  return QS_OK;
+}
+
+int qs_circuit_info(const qs_circuit* c, int* ngates, int* nblocks, int* max_k) {
+  if (!c) return cfail(QS_E_INVAL, "circuit is NULL");
+  if (ngates) *ngates = int(c->gates.size());
+  if (nblocks) *nblocks = c->planned ? int(c->blocks.size()) : -1;
+  if (max_k) {
+    int mk = 0;
+    for (const auto& b : c->blocks) mk = std::max(mk, b.k);
+    *max_k = mk;
+  }
+  return QS_OK;
+}
+
+int qs_circuit_block(const qs_circuit* c, int i, int* k, int* qubits, double* m) {
+  if (!c || !k) return cfail(QS_E_INVAL, "NULL argument");
+  if (!c->planned) return cfail(QS_E_INVAL, "circuit is not planned");
+  if (i < 0 || i >= int(c->blocks.size())) return cfail(QS_E_INVAL, "block %d out of range", i);
+  const qs::Block& b = c->blocks[i];
+  *k = b.k;
+  if (qubits)
+    for (int j = 0; j < b.k; ++j) qubits[j] = b.q[j];
+  if (m)
+    for (size_t e = 0; e < b.m.size(); ++e) {
+      m[2 * e] = b.m[e].real();
+      m[2 * e + 1] = b.m[e].imag();
+    }
+  return QS_OK;
+}
+
+}  // extern "C"

@@ -46,6 +46,23 @@ template <typename R>
 hipError_t launch_apply_fused(R* amps, int n, const int* qubits, int k, const R* mat,
                               hipStream_t s);
 
+// Tile geometry of a k-qubit block on the matrix cores: the tile holds the
+// contiguous low bits [0, C) and the block bits at or above C (qhi, h of
+// them); tpos[j] is the tile bit of block row bit j; lowblk lists the block
+// bits below C.
+struct FusedGeom {
+  int k, C, h, nlow;
+  int qhi[6];
+  int tpos[6];
+  int lowblk[6];
+};
+bool fused_geometry(int n, const int* qubits, int k, FusedGeom* g);
+
+// complex64 block of k = 4 or 5 qubits on v_mfma_f32_32x32x2f32; returns
+// hipErrorNotSupported when the state is too small for the tile.
+hipError_t launch_fused_mfma(float* amps, int n, const int* qubits, int k, const float* mat,
+                             hipStream_t s);
+
 // ---------------------------------------------------------------- QFT passes
 // One pass of a QFT on the qubit range [start, start+len): the stages of the
 // bits [lo, hi), each a butterfly on its bit and the phase controlled by the
