@@ -138,6 +138,75 @@ int qs_apply_fused(qs_state* st, const int* qubits, int k, const double* m);
  * relabelling). inverse != 0 applies the inverse transform. */
 int qs_qft(qs_state* st, int start, int len, int inverse);
 
+/* ------------------------------------------------------------ approximate mode (Sec. III) */
+
+/* A factorized state keeps the ket as a tensor product of kets on disjoint
+ * qubit subsets ("as factorized as possible", Sec. II-A). Each subsystem is a
+ * separate device buffer of 2^k amplitudes. A gate on qubits of different
+ * subsystems first merges them (Kronecker product; the first operand's qubits
+ * keep their bit positions). The one-qubit Schmidt test (Sec. III-A) computes
+ * the Bloch vector r of a qubit's reduced state in float64, eps = (1-|r|)/2,
+ * and, when eps <= p/2 (Eq. sdrp, plus a tolerance of 1e-6 for complex64 /
+ * 1e-12 for complex128 standing for "eps = 0 up to machine precision"),
+ * projects the qubit on the dominant eigenvector phi of its reduced state,
+ * moves it into a one-qubit subsystem and multiplies the fidelity estimate by
+ * 1 - eps (Eq. fid_model). */
+
+/* separation policies */
+enum { QS_SEP_NONE = 0,      /* only explicit qs_try_separate calls */
+       QS_SEP_AFTER_2Q = 1   /* after every multi-qubit gate */ };
+
+/* one separability attempt */
+typedef struct {
+  int32_t qubit;     /* tested qubit */
+  int32_t n_sub;     /* qubits in its subsystem when tested */
+  double eps;        /* (1 - |r|)/2 computed from the state (float64) */
+  int32_t rounded;   /* 1 if the qubit was separated */
+  int32_t reserved;
+} qs_attempt;
+
+/* Factorized state of n qubits (1 <= n <= 63), every qubit its own |0>
+ * subsystem. A merge that would exceed max_amps amplitudes returns
+ * QS_E_CAPACITY and leaves the state unchanged. */
+int qs_alloc_factorized(int n, int dtype, uint64_t max_amps, qs_state** out);
+
+/* Policy and threshold p (0 <= p <= 1) applied after gates. */
+int qs_set_separation_policy(qs_state* st, int policy, double p);
+
+/* Test the dirty qubits (those whose reduced state may have changed: both
+ * operands of every multi-qubit gate since their last test, and the other
+ * members of a subsystem that lost a qubit), lowest index first, until none
+ * is dirty. *n_separated receives the number of roundings. No-op on dense
+ * states. Synchronizes (each decision reads the statistics back). */
+int qs_try_separate(qs_state* st, double p, int* n_separated);
+
+/* Mark qubits (bit q of mask) dirty, e.g. to test a state built elsewhere. */
+int qs_mark_dirty(qs_state* st, uint64_t mask);
+
+/* Fidelity estimate F = prod (1 - eps_j) over all roundings so far
+ * (Eq. fid_model); 1.0 for dense states. */
+int qs_fidelity_estimate(const qs_state* st, double* F);
+
+/* Subsystem table: qubit_to_sub[q] (n entries) and sizes[s] (up to n
+ * entries) may be NULL; *nsub receives the number of subsystems. */
+int qs_subsystems(const qs_state* st, int* qubit_to_sub, int* sizes, int* nsub);
+/* Qubits of subsystem s in bit order (qubits[t] is stored at bit t). */
+int qs_subsystem_qubits(const qs_state* st, int s, int* qubits, int* nq);
+
+/* Record every attempt into a caller-owned array of cap entries; *count
+ * counts all attempts (it can exceed cap; entries beyond cap are dropped).
+ * NULL/NULL stops recording. The array must outlive the recording. */
+int qs_set_attempt_log(qs_state* st, qs_attempt* buf, uint64_t cap, uint64_t* count);
+
+/* Write the full ket of a factorized state into a dense state of the same
+ * width and precision (its labels are set so that readouts are in qubit
+ * order). */
+int qs_expand(qs_state* factorized, qs_state* dense);
+
+/* <a|b> of two dense states of equal width and precision, float64
+ * accumulation in a fixed order (for Eq. fid_exact). Synchronizes. */
+int qs_inner_product(qs_state* a, qs_state* b, double* re, double* im);
+
 /* ------------------------------------------------------------ circuits */
 
 /* A circuit is a host-side gate list on n qubits that is fused into dense

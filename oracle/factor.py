@@ -113,6 +113,10 @@ class FactorizedState:
     F: float = 1.0
     log: list = field(default_factory=list)
     dirty: set = field(default_factory=set)
+    # optional decision hook decide(qubit, n_sub, eps, rule) -> bool, called
+    # with the rule's own decision; used to replay another run's decisions
+    # where eps lies within rounding distance of the threshold
+    decide: object = None
 
     def __post_init__(self):
         if not self.subs:
@@ -184,7 +188,10 @@ class FactorizedState:
             return False
         r = bloch(S.amps, nq, t)
         eps = epsilon(r)
-        if eps <= p / 2.0 + self.tau:
+        rounds = eps <= p / 2.0 + self.tau
+        if self.decide is not None:
+            rounds = bool(self.decide(q, nq, eps, rounds))
+        if rounds:
             phi = dominant_state(r)
             rest = project_out(S.amps, nq, t, phi)
             others = [x for x in S.qubits if x != q]

@@ -58,6 +58,11 @@ def _release_all():
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 
 
+class Attempt(C.Structure):
+    _fields_ = [("qubit", C.c_int32), ("n_sub", C.c_int32), ("eps", C.c_double),
+                ("rounded", C.c_int32), ("reserved", C.c_int32)]
+
+
 class KernelStat(C.Structure):
     _fields_ = [("name", C.c_char * 48), ("launches", C.c_uint64), ("total_ms", C.c_double),
                 ("bytes", C.c_double)]
@@ -98,6 +103,16 @@ _SIGS = [
     ("qs_circuit_block", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                    C.POINTER(C.c_double)]),
     ("qs_run", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("qs_alloc_factorized", C.c_int, [C.c_int, C.c_int, C.c_uint64, C.POINTER(C.c_void_p)]),
+    ("qs_set_separation_policy", C.c_int, [C.c_void_p, C.c_int, C.c_double]),
+    ("qs_try_separate", C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_int)]),
+    ("qs_mark_dirty", C.c_int, [C.c_void_p, C.c_uint64]),
+    ("qs_fidelity_estimate", C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    ("qs_subsystems", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    ("qs_subsystem_qubits", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    ("qs_set_attempt_log", C.c_int, [C.c_void_p, C.POINTER(Attempt), C.c_uint64, C.POINTER(C.c_uint64)]),
+    ("qs_expand", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("qs_inner_product", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("qs_tune_set", C.c_int, [C.c_char_p, C.c_int64]),
     ("qs_tune_get", C.c_int, [C.c_char_p, C.POINTER(C.c_int64)]),
     ("qs_profile_start", C.c_int, [C.c_void_p]),
@@ -256,13 +271,23 @@ def tune_get(key: str) -> int:
     return v.value
 
 
-class State:
-    """A dense n-qubit ket on the GPU (owned by the library)."""
+SEP_NONE, SEP_AFTER_2Q = 0, 1
 
-    def __init__(self, n: int, dtype: int = C64, stream=None):
+
+class State:
+    """An n-qubit ket on the GPU (owned by the library): dense by default,
+    factorized (approximate mode) when max_amps is given."""
+
+    def __init__(self, n: int, dtype: int = C64, stream=None, factorized: bool = False,
+                 max_amps: int = 2 ** 30):
         self.lib = load()
         h = C.c_void_p()
-        _check(self.lib, self.lib.qs_alloc(n, dtype, C.byref(h)))
+        if factorized:
+            _check(self.lib, self.lib.qs_alloc_factorized(n, dtype, int(max_amps), C.byref(h)))
+        else:
+            _check(self.lib, self.lib.qs_alloc(n, dtype, C.byref(h)))
+        self.factorized = factorized
+        self._log = None
         self.h = h
         self.n = n
         self.dtype = dtype
@@ -366,6 +391,53 @@ class State:
 
     def check(self, tol: float):
         _check(self.lib, self.lib.qs_check(self.h, float(tol)))
+
+    # -- approximate mode
+    def set_policy(self, policy: int, p: float):
+        _check(self.lib, self.lib.qs_set_separation_policy(self.h, policy, float(p)))
+
+    def try_separate(self, p: float) -> int:
+        k = C.c_int()
+        _check(self.lib, self.lib.qs_try_separate(self.h, float(p), C.byref(k)))
+        return k.value
+
+    def mark_dirty(self, mask: int):
+        _check(self.lib, self.lib.qs_mark_dirty(self.h, int(mask)))
+
+    def fidelity_estimate(self) -> float:
+        v = C.c_double()
+        _check(self.lib, self.lib.qs_fidelity_estimate(self.h, C.byref(v)))
+        return v.value
+
+    def subsystems(self) -> list:
+        """Qubit lists of the subsystems, in bit order."""
+        ns = C.c_int()
+        _check(self.lib, self.lib.qs_subsystems(self.h, None, None, C.byref(ns)))
+        out = []
+        for s in range(ns.value):
+            q = (C.c_int * 64)()
+            nq = C.c_int()
+            _check(self.lib, self.lib.qs_subsystem_qubits(self.h, s, q, C.byref(nq)))
+            out.append(list(q[:nq.value]))
+        return out
+
+    def record_attempts(self, cap: int = 1 << 20):
+        """Start recording separability attempts into a buffer owned here."""
+        self._log = (Attempt * cap)()
+        self._log_count = C.c_uint64()
+        _check(self.lib, self.lib.qs_set_attempt_log(self.h, self._log, cap, C.byref(self._log_count)))
+
+    def attempts(self) -> list:
+        n = min(self._log_count.value, len(self._log)) if self._log is not None else 0
+        return [(a.qubit, a.n_sub, a.eps, bool(a.rounded)) for a in self._log[:n]]
+
+    def expand_into(self, dense: "State"):
+        _check(self.lib, self.lib.qs_expand(self.h, dense.h))
+
+    def inner(self, other: "State") -> complex:
+        re, im = C.c_double(), C.c_double()
+        _check(self.lib, self.lib.qs_inner_product(self.h, other.h, C.byref(re), C.byref(im)))
+        return complex(re.value, im.value)
 
     # -- timing
     def profile_start(self):

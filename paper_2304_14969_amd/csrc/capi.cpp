@@ -11,6 +11,7 @@
 
 #include "../../include/qs.h"
 #include "circuit.h"
+#include "factor.h"
 #include "qs_internal.h"
 
 namespace {
@@ -80,11 +81,17 @@ struct qs_state {
   bool prof = false;
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
+  qs::FactorState* fact = nullptr;  // set for factorized (approximate-mode) states
 };
 
 namespace {
 
 uint64_t dim(const qs_state* st) { return uint64_t(1) << st->n; }
+// reduction scratch of every state: norm partials or Bloch/inner partials
+size_t scratch_doubles() {
+  const size_t a = size_t(qs::reduce_blocks(0)) + 1, b = size_t(qs::factor_scratch_doubles());
+  return a > b ? a : b;
+}
 size_t amp_bytes(int dtype) { return dtype == QS_C64 ? 8 : 16; }
 double ab(const qs_state* st) { return double(amp_bytes(st->dtype)); }
 
@@ -213,11 +220,19 @@ int sync(qs_state* st, const char* what) {
   return device_error(st, hipStreamSynchronize(st->stream), what);
 }
 
+// Status of a factorized-mode call; a device error poisons the state.
+int fact_rc(qs_state* st, int rc) {
+  if (rc == QS_E_DEVICE) st->poisoned = true;
+  return rc;
+}
+
 }  // namespace
 
 namespace qs {
 
 void set_last_error(const char* msg) { g_err = msg; }
+void* device_alloc(size_t bytes) { return dev_alloc(bytes); }
+void device_free(void* p) { dev_free(p); }
 
 // Drops a circuit's plan and its device copies (after an edit or a re-plan).
 void circuit_invalidate(qs_circuit* c) {
@@ -300,7 +315,7 @@ int qs_alloc(int n, int dtype, qs_state** out) {
   const size_t bytes = size_t(1) << n;
   st->amps = dev_alloc(bytes * amp_bytes(dtype));
   st->mat = dev_alloc(kMatBytes);
-  st->red = static_cast<double*>(dev_alloc(sizeof(double) * (qs::reduce_blocks(0) + 1)));
+  st->red = static_cast<double*>(dev_alloc(sizeof(double) * scratch_doubles()));
   if (!st->amps || !st->mat || !st->red) {
     dev_free(st->amps);
     dev_free(st->mat);
@@ -325,9 +340,50 @@ int qs_alloc(int n, int dtype, qs_state** out) {
   return QS_OK;
 }
 
+int qs_alloc_factorized(int n, int dtype, uint64_t max_amps, qs_state** out) {
+  if (!out) return fail(QS_E_INVAL, "out is NULL");
+  if (n < 1 || n > 63) return fail(QS_E_INVAL, "n = %d outside [1, 63]", n);
+  if (dtype != QS_C64 && dtype != QS_C128) return fail(QS_E_INVAL, "unknown dtype %d", dtype);
+  if (max_amps < 2) return fail(QS_E_INVAL, "max_amps must be at least 2");
+  qs_state* st = new qs_state();
+  st->n = n;
+  st->dtype = dtype;
+  reset_perm(st);
+  st->mat = dev_alloc(kMatBytes);
+  st->red = static_cast<double*>(dev_alloc(sizeof(double) * scratch_doubles()));
+  if (!st->mat || !st->red) {
+    dev_free(st->mat);
+    dev_free(st->red);
+    delete st;
+    return fail(QS_E_NOMEM, "device allocation failed");
+  }
+  st->fact = new qs::FactorState();
+  st->fact->n = n;
+  st->fact->dtype = dtype;
+  st->fact->max_amps = max_amps;
+  st->fact->tau = dtype == QS_C64 ? 1e-6 : 1e-12;
+  st->fact->scratch = st->red;
+  st->fact->mat = st->mat;
+  ++g_live_states;
+  if (int rc = qs::fact_init(st->fact)) {
+    dev_free(st->mat);
+    dev_free(st->red);
+    delete st->fact;
+    delete st;
+    --g_live_states;
+    return rc;
+  }
+  *out = st;
+  return QS_OK;
+}
+
 int qs_free(qs_state* st) {
   if (!st) return QS_OK;
   (void)hipStreamSynchronize(st->stream);
+  if (st->fact) {
+    qs::fact_release(st->fact);
+    delete st->fact;
+  }
   dev_free(st->amps);
   dev_free(st->mat);
   dev_free(st->red);
@@ -344,6 +400,7 @@ int qs_free(qs_state* st) {
 int qs_set_stream(qs_state* st, void* hip_stream) {
   if (int rc = check_state(st)) return rc;
   st->stream = static_cast<hipStream_t>(hip_stream);
+  if (st->fact) st->fact->stream = st->stream;
   return QS_OK;
 }
 
@@ -362,6 +419,7 @@ int qs_info(const qs_state* st, int* n, int* dtype) {
 int qs_set_basis(qs_state* st, uint64_t x) {
   if (int rc = check_state(st)) return rc;
   if (x >= dim(st)) return fail(QS_E_INVAL, "basis index %llu >= 2^%d", (unsigned long long)x, st->n);
+  if (st->fact) return qs::fact_set_basis(st->fact, x);
   reset_perm(st);
   hipError_t e = st->dtype == QS_C64
                      ? qs::launch_set_basis(static_cast<float*>(st->amps), st->n, x, st->stream)
@@ -374,6 +432,7 @@ int qs_set_amplitudes(qs_state* st, const void* host, uint64_t count, int host_d
   if (!host) return fail(QS_E_INVAL, "host pointer is NULL");
   if (count != dim(st)) return fail(QS_E_INVAL, "count %llu != 2^%d", (unsigned long long)count, st->n);
   if (host_dtype != QS_C64 && host_dtype != QS_C128) return fail(QS_E_INVAL, "unknown dtype %d", host_dtype);
+  if (st->fact) return fail(QS_E_UNSUPPORTED, "a factorized state cannot take a dense vector");
   reset_perm(st);
   const size_t hb = amp_bytes(host_dtype), sb = amp_bytes(st->dtype);
   if (host_dtype == st->dtype) {
@@ -407,6 +466,7 @@ int qs_apply_1q(qs_state* st, int q, const double m[8]) {
   if (int rc = check_state(st)) return rc;
   if (int rc = check_qubit(st, q, "qubit")) return rc;
   if (int rc = check_finite(m, 8)) return rc;
+  if (st->fact) return fact_rc(st, qs::fact_apply(st->fact, &q, 1, m));
   const int t = st->perm[q];
   ProfScope ps(st, "apply_1q", 2.0 * std::ldexp(1.0, st->n) * ab(st));
   hipError_t e;
@@ -435,6 +495,24 @@ int qs_apply_ctrl(qs_state* st, const int* ctrls, int nctrl, uint64_t ctrl_value
     fixed.pos[fixed.n++] = p;
     if ((ctrl_values >> j) & 1) set_mask |= uint64_t(1) << p;
   }
+  if (st->fact) {
+    // controlled matrix on (ctrls..., target): m where the controls match
+    if (nctrl + 1 > QS_MAX_FUSED) return fail(QS_E_UNSUPPORTED, "factorized gates act on <= %d qubits", QS_MAX_FUSED);
+    const int k = nctrl + 1, D = 1 << k;
+    std::vector<double> full(size_t(2) * D * D, 0.0);
+    for (int i = 0; i < D; ++i) full[2 * (size_t(i) * D + i)] = 1.0;
+    const int base = int(ctrl_values & ((uint64_t(1) << nctrl) - 1)), top = 1 << nctrl;
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) {
+        const size_t e = size_t(base + i * top) * D + (base + j * top);
+        full[2 * e] = m[2 * (2 * i + j)];
+        full[2 * e + 1] = m[2 * (2 * i + j) + 1];
+      }
+    int qq[QS_MAX_FUSED];
+    for (int j = 0; j < nctrl; ++j) qq[j] = ctrls[j];
+    qq[nctrl] = target;
+    return fact_rc(st, qs::fact_apply(st->fact, qq, k, full.data()));
+  }
   const int tbit = st->perm[target];
   fixed.pos[fixed.n++] = tbit;
   for (int i = 1; i < fixed.n; ++i)
@@ -457,6 +535,14 @@ int qs_apply_cphase(qs_state* st, int a, int b, double theta) {
   if (a == b) return fail(QS_E_INVAL, "controlled phase needs two distinct qubits");
   if (!std::isfinite(theta)) return fail(QS_E_INVAL, "theta is not finite");
   const double cr = std::cos(theta), ci = std::sin(theta);
+  if (st->fact) {
+    double d[32] = {0};
+    d[0] = d[10] = d[20] = 1.0;
+    d[30] = cr;
+    d[31] = ci;
+    const int qq[2] = {a, b};
+    return fact_rc(st, qs::fact_apply(st->fact, qq, 2, d));
+  }
   ProfScope ps(st, "cphase", 2.0 * std::ldexp(1.0, st->n - 2) * ab(st));
   hipError_t e;
   if (st->dtype == QS_C64)
@@ -472,6 +558,7 @@ int qs_apply_swap(qs_state* st, int a, int b) {
   if (int rc = check_state(st)) return rc;
   if (int rc = check_qubit(st, a, "qubit a")) return rc;
   if (int rc = check_qubit(st, b, "qubit b")) return rc;
+  if (st->fact) return qs::fact_swap(st->fact, a, b);
   std::swap(st->perm[a], st->perm[b]);
   return QS_OK;
 }
@@ -491,6 +578,7 @@ int qs_apply_fused(qs_state* st, const int* qubits, int k, const double* m) {
     seen |= uint64_t(1) << qubits[j];
     phys[j] = st->perm[qubits[j]];
   }
+  if (st->fact) return fact_rc(st, qs::fact_apply(st->fact, qubits, k, m));
   hipError_t e;
   if (st->dtype == QS_C64) {
     std::vector<float> mf(2 * D * D);
@@ -505,6 +593,7 @@ int qs_apply_fused(qs_state* st, const int* qubits, int k, const double* m) {
 
 int qs_qft(qs_state* st, int start, int len, int inverse) {
   if (int rc = check_state(st)) return rc;
+  if (st->fact) return fail(QS_E_UNSUPPORTED, "the QFT runs on dense states");
   if (start < 0 || len < 1 || start + len > st->n)
     return fail(QS_E_INVAL, "qubit range [%d, %d) outside [0, %d)", start, start + len, st->n);
   // natural order, bit-reversed (left by an earlier transform), or anything
@@ -562,6 +651,20 @@ int qs_run(qs_state* st, qs_circuit* c) {
   if (int rc = check_state(st)) return rc;
   if (!c) return fail(QS_E_INVAL, "circuit is NULL");
   if (c->n != st->n) return fail(QS_E_INVAL, "circuit has %d qubits, state %d", c->n, st->n);
+  if (st->fact) {
+    // approximate mode: gate by gate, so that the separation policy runs after
+    // every multi-qubit gate; positions are the labels at the start
+    std::vector<double> m;
+    for (const auto& g : c->gates) {
+      m.resize(2 * g.m.size());
+      for (size_t i = 0; i < g.m.size(); ++i) {
+        m[2 * i] = g.m[i].real();
+        m[2 * i + 1] = g.m[i].imag();
+      }
+      if (int rc = fact_rc(st, qs::fact_apply(st->fact, g.q, g.k, m.data()))) return rc;
+    }
+    return qs::fact_relabel(st->fact, c->pos.data());
+  }
   if (!c->planned)
     if (int rc = qs_circuit_plan(c, c->kmax)) return rc;
   const int prec = st->dtype == QS_C64 ? 0 : 1;
@@ -613,6 +716,115 @@ int qs_run(qs_state* st, qs_circuit* c) {
   return QS_OK;
 }
 
+// ------------------------------------------------------------------ approximate mode
+
+int qs_set_separation_policy(qs_state* st, int policy, double p) {
+  if (int rc = check_state(st)) return rc;
+  if (!st->fact) return fail(QS_E_UNSUPPORTED, "separation applies to factorized states");
+  if (policy != QS_SEP_NONE && policy != QS_SEP_AFTER_2Q) return fail(QS_E_INVAL, "unknown policy %d", policy);
+  if (!(p >= 0.0 && p <= 1.0)) return fail(QS_E_INVAL, "p = %g outside [0, 1]", p);
+  st->fact->policy = policy;
+  st->fact->p = p;
+  return QS_OK;
+}
+
+int qs_try_separate(qs_state* st, double p, int* n_separated) {
+  if (int rc = check_state(st)) return rc;
+  if (!(p >= 0.0 && p <= 1.0)) return fail(QS_E_INVAL, "p = %g outside [0, 1]", p);
+  if (!st->fact) {
+    if (n_separated) *n_separated = 0;
+    return QS_OK;
+  }
+  return fact_rc(st, qs::fact_try_separate(st->fact, p, n_separated));
+}
+
+int qs_mark_dirty(qs_state* st, uint64_t mask) {
+  if (int rc = check_state(st)) return rc;
+  if (!st->fact) return QS_OK;
+  if (st->n < 64) mask &= (uint64_t(1) << st->n) - 1;
+  st->fact->dirty |= mask;
+  return QS_OK;
+}
+
+int qs_fidelity_estimate(const qs_state* st, double* F) {
+  if (!st || !F) return fail(QS_E_INVAL, "NULL argument");
+  *F = st->fact ? st->fact->F : 1.0;
+  return QS_OK;
+}
+
+int qs_subsystems(const qs_state* st, int* qubit_to_sub, int* sizes, int* nsub) {
+  if (!st || !nsub) return fail(QS_E_INVAL, "NULL argument");
+  if (!st->fact) {
+    if (qubit_to_sub)
+      for (int q = 0; q < st->n; ++q) qubit_to_sub[q] = 0;
+    if (sizes) sizes[0] = st->n;
+    *nsub = 1;
+    return QS_OK;
+  }
+  const auto& subs = st->fact->subs;
+  for (int s = 0; s < int(subs.size()); ++s) {
+    if (sizes) sizes[s] = subs[s].nq;
+    if (qubit_to_sub)
+      for (int t = 0; t < subs[s].nq; ++t) qubit_to_sub[subs[s].q[t]] = s;
+  }
+  *nsub = int(subs.size());
+  return QS_OK;
+}
+
+int qs_subsystem_qubits(const qs_state* st, int s, int* qubits, int* nq) {
+  if (!st || !nq) return fail(QS_E_INVAL, "NULL argument");
+  if (!st->fact) return fail(QS_E_UNSUPPORTED, "dense state");
+  if (s < 0 || s >= int(st->fact->subs.size())) return fail(QS_E_INVAL, "subsystem %d out of range", s);
+  *nq = st->fact->subs[s].nq;
+  if (qubits)
+    for (int t = 0; t < *nq; ++t) qubits[t] = st->fact->subs[s].q[t];
+  return QS_OK;
+}
+
+int qs_set_attempt_log(qs_state* st, qs_attempt* buf, uint64_t cap, uint64_t* count) {
+  if (int rc = check_state(st)) return rc;
+  if (!st->fact) return fail(QS_E_UNSUPPORTED, "attempts happen on factorized states");
+  if ((buf == nullptr) != (count == nullptr)) return fail(QS_E_INVAL, "buf and count go together");
+  st->fact->log = buf;
+  st->fact->log_cap = cap;
+  st->fact->log_count = count;
+  if (count) *count = 0;
+  return QS_OK;
+}
+
+int qs_expand(qs_state* fact, qs_state* dense) {
+  if (int rc = check_state(fact)) return rc;
+  if (int rc = check_state(dense)) return rc;
+  if (!fact->fact || dense->fact) return fail(QS_E_INVAL, "expand takes a factorized and a dense state");
+  if (fact->n != dense->n || fact->dtype != dense->dtype)
+    return fail(QS_E_INVAL, "states differ in width or precision");
+  (void)hipStreamSynchronize(dense->stream);
+  int perm[64];
+  if (int rc = fact_rc(fact, qs::fact_expand(fact->fact, dense->amps, perm))) return rc;
+  for (int q = 0; q < fact->n; ++q) dense->perm[q] = perm[q];
+  return QS_OK;
+}
+
+int qs_inner_product(qs_state* a, qs_state* b, double* re, double* im) {
+  if (int rc = check_state(a)) return rc;
+  if (int rc = check_state(b)) return rc;
+  if (!re || !im) return fail(QS_E_INVAL, "NULL output");
+  if (a->fact || b->fact) return fail(QS_E_UNSUPPORTED, "inner product of dense states");
+  if (a->n != b->n || a->dtype != b->dtype) return fail(QS_E_INVAL, "states differ in width or precision");
+  if (int rc = materialize(a)) return rc;
+  if (int rc = materialize(b)) return rc;
+  (void)hipStreamSynchronize(b->stream);
+  hipError_t e = a->dtype == QS_C64
+                     ? qs::launch_inner(static_cast<const float*>(a->amps), static_cast<const float*>(b->amps), dim(a), a->red, a->stream)
+                     : qs::launch_inner(static_cast<const double*>(a->amps), static_cast<const double*>(b->amps), dim(a), a->red, a->stream);
+  double v[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(v, a->red, sizeof v, hipMemcpyDeviceToHost, a->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
+  *re = v[0];
+  *im = v[1];
+  return device_error(a, e, "inner product");
+}
+
 // ------------------------------------------------------------------ profiling
 
 int qs_profile_start(qs_state* st) {
@@ -660,11 +872,32 @@ int qs_profile_stop(qs_state* st, qs_kernel_stat* out, int max_out, int* count) 
 
 // ------------------------------------------------------------------ readout
 
+// Dense copy of a factorized state (at most 30 qubits) for full readouts.
+static int dense_copy(qs_state* st, qs_state** out) {
+  if (st->n > 30) return fail(QS_E_UNSUPPORTED, "full readout of a factorized state needs n <= 30");
+  qs_state* d = nullptr;
+  if (int rc = qs_alloc(st->n, st->dtype, &d)) return rc;
+  d->stream = st->stream;
+  if (int rc = qs_expand(st, d)) {
+    qs_free(d);
+    return rc;
+  }
+  *out = d;
+  return QS_OK;
+}
+
 int qs_amplitudes(qs_state* st, void* host_out, uint64_t count, int out_dtype) {
   if (int rc = check_state(st)) return rc;
   if (!host_out) return fail(QS_E_INVAL, "output pointer is NULL");
   if (count != dim(st)) return fail(QS_E_INVAL, "count %llu != 2^%d", (unsigned long long)count, st->n);
   if (out_dtype != QS_C64 && out_dtype != QS_C128) return fail(QS_E_INVAL, "unknown dtype %d", out_dtype);
+  if (st->fact) {
+    qs_state* d = nullptr;
+    if (int rc = dense_copy(st, &d)) return rc;
+    const int rc = qs_amplitudes(d, host_out, count, out_dtype);
+    qs_free(d);
+    return rc;
+  }
   if (int rc = materialize(st)) return rc;
   const size_t ob = amp_bytes(out_dtype), sb = amp_bytes(st->dtype);
   if (out_dtype == st->dtype) {
@@ -697,6 +930,7 @@ int qs_amplitudes_gather(qs_state* st, const uint64_t* idx, uint64_t m, double* 
   if (!idx || !out) return fail(QS_E_INVAL, "NULL pointer");
   for (uint64_t j = 0; j < m; ++j)
     if (idx[j] >= dim(st)) return fail(QS_E_INVAL, "index %llu >= 2^%d", (unsigned long long)idx[j], st->n);
+  if (st->fact) return fact_rc(st, qs::fact_gather(st->fact, idx, m, out));
   qs::Perm64 perm{};
   perm.n = st->n;
   for (int q = 0; q < st->n; ++q) perm.p[q] = static_cast<int8_t>(st->perm[q]);
@@ -722,6 +956,13 @@ int qs_probs(qs_state* st, double* out, uint64_t count) {
   if (int rc = check_state(st)) return rc;
   if (!out) return fail(QS_E_INVAL, "output pointer is NULL");
   if (count != dim(st)) return fail(QS_E_INVAL, "count %llu != 2^%d", (unsigned long long)count, st->n);
+  if (st->fact) {
+    qs_state* d = nullptr;
+    if (int rc = dense_copy(st, &d)) return rc;
+    const int rc = qs_probs(d, out, count);
+    qs_free(d);
+    return rc;
+  }
   if (int rc = materialize(st)) return rc;
   const uint64_t chunk = count < kStageAmps ? count : kStageAmps;
   double* stage = static_cast<double*>(dev_alloc(chunk * sizeof(double)));
@@ -743,6 +984,7 @@ int qs_probs(qs_state* st, double* out, uint64_t count) {
 int qs_norm(qs_state* st, double* out) {
   if (int rc = check_state(st)) return rc;
   if (!out) return fail(QS_E_INVAL, "output pointer is NULL");
+  if (st->fact) return fact_rc(st, qs::fact_norm(st->fact, out));
   const int nb = qs::reduce_blocks(dim(st));
   hipError_t e = st->dtype == QS_C64
                      ? qs::launch_norm(static_cast<const float*>(st->amps), dim(st), st->red, st->red + nb, st->stream)

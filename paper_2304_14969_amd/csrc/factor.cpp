@@ -1,0 +1,421 @@
+// Approximate mode of Sec. III on the GPU: a ket kept as a product of
+// subsystems (Sec. II-A), the one-qubit Schmidt test through the Bloch vector
+// and the SDRP rounding of Eq. sdrp, with the fidelity model of Eq. fid_model.
+//
+// Host side: the subsystem table, the dirty-qubit schedule and the decisions
+// (float64). Device side: every pass over amplitudes (compose, gate sweeps,
+// Bloch statistics in float64, projection).
+//
+// Readings of the paper used here:
+//  * rounding condition: inclusive eps <= p/2 (Eq. sdrp), plus a tolerance tau
+//    for "eps = 0 up to machine precision" (1e-6 for complex64 amplitudes,
+//    whose eps carries ~1e-7 rounding error; 1e-12 for complex128);
+//  * the projection keeps the dominant eigenvector phi of rho_q (the result of
+//    rotating r to the |0> pole, post-selecting and rotating back), with phi_0
+//    real and >= 0, phi = |0> when r = 0; the remainder is renormalized with
+//    the weight (1 + |r|)/2 of the kept branch;
+//  * schedule: after a multi-qubit gate both operands are dirty; a rounding
+//    makes every other member of its subsystem dirty; the lowest-numbered
+//    dirty qubit is tested until none is left (no other reduced state can
+//    have changed);
+//  * merge of subsystems A (first operand's) and B: c[iA + 2^nA iB] = a b.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "factor.h"
+#include "qs_internal.h"
+
+namespace qs {
+
+void* device_alloc(size_t bytes);
+void device_free(void* p);
+void set_last_error(const char* msg);
+
+namespace {
+
+int ffail(int code, const char* fmt, ...) {
+  char buf[256];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  set_last_error(buf);
+  return code;
+}
+
+int dev_err(hipError_t e, const char* what) {
+  if (e == hipSuccess) return QS_OK;
+  return ffail(QS_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t amp_bytes(const FactorState* f) { return f->dtype == QS_C64 ? 8 : 16; }
+
+// Upload a small host vector of complex doubles as the state's precision.
+hipError_t upload(const FactorState* f, void* dst, const double* re_im, size_t count) {
+  if (f->dtype == QS_C64) {
+    std::vector<float> h(2 * count);
+    for (size_t i = 0; i < 2 * count; ++i) h[i] = float(re_im[i]);
+    return hipMemcpyAsync(dst, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice,
+                          f->stream);
+  }
+  return hipMemcpyAsync(dst, re_im, 2 * count * sizeof(double), hipMemcpyHostToDevice, f->stream);
+}
+
+int find(const FactorState* f, int q, int* t) {
+  for (int s = 0; s < int(f->subs.size()); ++s)
+    for (int b = 0; b < f->subs[s].nq; ++b)
+      if (f->subs[s].q[b] == q) {
+        if (t) *t = b;
+        return s;
+      }
+  return -1;
+}
+
+int new_single(FactorState* f, int q, const double amp[4], Sub* out) {
+  Sub s;
+  s.nq = 1;
+  s.q[0] = q;
+  s.amps = device_alloc(2 * amp_bytes(f));
+  if (!s.amps) return ffail(QS_E_NOMEM, "allocating a one-qubit subsystem");
+  if (int rc = dev_err(upload(f, s.amps, amp, 2), "upload")) {
+    device_free(s.amps);
+    return rc;
+  }
+  *out = s;
+  return QS_OK;
+}
+
+void log_attempt(FactorState* f, int q, int nsub, double eps, bool rounded) {
+  if (!f->log || !f->log_count) return;
+  if (*f->log_count < f->log_cap) {
+    qs_attempt& a = f->log[*f->log_count];
+    a.qubit = q;
+    a.n_sub = nsub;
+    a.eps = eps;
+    a.rounded = rounded ? 1 : 0;
+    a.reserved = 0;
+  }
+  ++*f->log_count;
+}
+
+// Merge subsystem ib into ia (ia's qubits keep their bits); returns the
+// index of the merged subsystem. The caller checked the capacity.
+int merge(FactorState* f, int ia, int ib, int* out) {
+  Sub& A = f->subs[ia];
+  Sub& B = f->subs[ib];
+  const int nq = A.nq + B.nq;
+  void* c = device_alloc((size_t(1) << nq) * amp_bytes(f));
+  if (!c) return ffail(QS_E_NOMEM, "allocating a %d-qubit subsystem", nq);
+  hipError_t e = f->dtype == QS_C64
+                     ? launch_compose(static_cast<float*>(c), static_cast<const float*>(A.amps),
+                                      A.nq, static_cast<const float*>(B.amps), B.nq, f->stream)
+                     : launch_compose(static_cast<double*>(c), static_cast<const double*>(A.amps),
+                                      A.nq, static_cast<const double*>(B.amps), B.nq, f->stream);
+  if (e != hipSuccess) {
+    device_free(c);
+    return dev_err(e, "compose");
+  }
+  Sub m;
+  m.nq = nq;
+  for (int t = 0; t < A.nq; ++t) m.q[t] = A.q[t];
+  for (int t = 0; t < B.nq; ++t) m.q[A.nq + t] = B.q[t];
+  m.amps = c;
+  device_free(A.amps);
+  device_free(B.amps);
+  const int lo = std::min(ia, ib), hi = std::max(ia, ib);
+  f->subs.erase(f->subs.begin() + hi);
+  f->subs.erase(f->subs.begin() + lo);
+  f->subs.push_back(m);
+  *out = int(f->subs.size()) - 1;
+  return QS_OK;
+}
+
+// One separability attempt on qubit q (Eq. sdrp); *rounded on success.
+int test_qubit(FactorState* f, int q, double p, bool* rounded) {
+  *rounded = false;
+  f->dirty &= ~(uint64_t(1) << q);
+  int t = 0;
+  const int si = find(f, q, &t);
+  if (si < 0) return ffail(QS_E_INVAL, "qubit %d not found", q);
+  Sub& S = f->subs[si];
+  if (S.nq == 1) return QS_OK;
+  hipError_t e = f->dtype == QS_C64
+                     ? launch_bloch(static_cast<const float*>(S.amps), S.nq, t, f->scratch, f->stream)
+                     : launch_bloch(static_cast<const double*>(S.amps), S.nq, t, f->scratch, f->stream);
+  double st[4];
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(st, f->scratch, sizeof st, hipMemcpyDeviceToHost, f->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+  if (int rc = dev_err(e, "bloch")) return rc;
+  // Bloch vector of rho_q (Sec. III-A, step 1) and eps = (1 - |r|)/2 (step 2)
+  const double nrm = st[2] + st[3];
+  if (!(nrm > 0.0)) return ffail(QS_E_NUMERIC, "subsystem of qubit %d has zero norm", q);
+  const double rx = 2.0 * st[0] / nrm, ry = 2.0 * st[1] / nrm, rz = (st[2] - st[3]) / nrm;
+  const double rn = std::sqrt(rx * rx + ry * ry + rz * rz);
+  const double eps = std::min(std::max((1.0 - rn) / 2.0, 0.0), 0.5);
+  if (!(eps <= p / 2.0 + f->tau)) {
+    log_attempt(f, q, S.nq, eps, false);
+    return QS_OK;
+  }
+  // dominant eigenvector phi of rho_q, phi_0 real >= 0 (steps 3-4)
+  double phi[4];
+  if (rn == 0.0) {
+    phi[0] = 1.0; phi[1] = 0.0; phi[2] = 0.0; phi[3] = 0.0;
+  } else {
+    const double th = std::acos(std::max(-1.0, std::min(1.0, rz / rn)));
+    const double az = std::atan2(ry, rx);
+    phi[0] = std::cos(th / 2.0);
+    phi[1] = 0.0;
+    phi[2] = std::cos(az) * std::sin(th / 2.0);
+    phi[3] = std::sin(az) * std::sin(th / 2.0);
+  }
+  // the kept branch carries weight (1 + |r|)/2 of the subsystem's norm
+  const double scale = 1.0 / std::sqrt(0.5 * (1.0 + rn) * nrm);
+  void* rest = device_alloc((size_t(1) << (S.nq - 1)) * amp_bytes(f));
+  if (!rest) return ffail(QS_E_NOMEM, "allocating a %d-qubit subsystem", S.nq - 1);
+  Sub single;
+  if (int rc = new_single(f, q, phi, &single)) {
+    device_free(rest);
+    return rc;
+  }
+  e = f->dtype == QS_C64
+          ? launch_decompose(static_cast<float*>(rest), static_cast<const float*>(S.amps), S.nq, t,
+                             phi, scale, f->stream)
+          : launch_decompose(static_cast<double*>(rest), static_cast<const double*>(S.amps), S.nq,
+                             t, phi, scale, f->stream);
+  if (e != hipSuccess) {
+    device_free(rest);
+    device_free(single.amps);
+    return dev_err(e, "decompose");
+  }
+  const int nsub = S.nq;
+  device_free(S.amps);
+  S.amps = rest;
+  for (int b = t; b + 1 < S.nq; ++b) S.q[b] = S.q[b + 1];
+  S.nq -= 1;
+  for (int b = 0; b < S.nq; ++b) f->dirty |= uint64_t(1) << S.q[b];
+  f->subs.push_back(single);
+  f->F *= (1.0 - eps);
+  log_attempt(f, q, nsub, eps, true);
+  *rounded = true;
+  return QS_OK;
+}
+
+}  // namespace
+
+int fact_init(FactorState* f) {
+  f->subs.clear();
+  for (int q = 0; q < f->n; ++q) {
+    const double zero[4] = {1.0, 0.0, 0.0, 0.0};
+    Sub s;
+    if (int rc = new_single(f, q, zero, &s)) {
+      fact_release(f);
+      return rc;
+    }
+    f->subs.push_back(s);
+  }
+  f->F = 1.0;
+  f->dirty = 0;
+  return dev_err(hipStreamSynchronize(f->stream), "init");
+}
+
+void fact_release(FactorState* f) {
+  (void)hipStreamSynchronize(f->stream);
+  for (auto& s : f->subs) device_free(s.amps);
+  f->subs.clear();
+}
+
+int fact_set_basis(FactorState* f, uint64_t x) {
+  fact_release(f);
+  for (int q = 0; q < f->n; ++q) {
+    const double b0[4] = {1.0, 0.0, 0.0, 0.0}, b1[4] = {0.0, 0.0, 1.0, 0.0};
+    Sub s;
+    if (int rc = new_single(f, q, ((x >> q) & 1) ? b1 : b0, &s)) return rc;
+    f->subs.push_back(s);
+  }
+  f->F = 1.0;
+  f->dirty = 0;
+  return dev_err(hipStreamSynchronize(f->stream), "set basis");
+}
+
+int fact_largest(const FactorState* f) {
+  int m = 0;
+  for (const auto& s : f->subs) m = std::max(m, s.nq);
+  return m;
+}
+
+int fact_apply(FactorState* f, const int* qubits, int k, const double* m) {
+  // capacity first, so that a refused gate leaves the state as it was
+  int distinct[QS_MAX_FUSED], nd = 0, total = 0;
+  for (int j = 0; j < k; ++j) {
+    const int s = find(f, qubits[j], nullptr);
+    if (s < 0) return ffail(QS_E_INVAL, "qubit %d not found", qubits[j]);
+    if (std::find(distinct, distinct + nd, s) == distinct + nd) {
+      distinct[nd++] = s;
+      total += f->subs[s].nq;
+    }
+  }
+  if (total >= 63 || (uint64_t(1) << total) > f->max_amps)
+    return ffail(QS_E_CAPACITY, "gate needs a %d-qubit subsystem (cap %llu amplitudes)", total,
+                 (unsigned long long)f->max_amps);
+  // merge every subsystem into the first operand's
+  int si = find(f, qubits[0], nullptr);
+  for (int j = 1; j < k; ++j) {
+    const int sj = find(f, qubits[j], nullptr);
+    if (sj != si)
+      if (int rc = merge(f, si, sj, &si)) return rc;
+  }
+  Sub& S = f->subs[si];
+  int local[QS_MAX_FUSED];
+  for (int j = 0; j < k; ++j)
+    for (int b = 0; b < S.nq; ++b)
+      if (S.q[b] == qubits[j]) local[j] = b;
+  hipError_t e;
+  if (k == 1) {
+    if (f->dtype == QS_C64) {
+      Mat2<float> mm;
+      for (int i = 0; i < 4; ++i) { mm.re[i] = float(m[2 * i]); mm.im[i] = float(m[2 * i + 1]); }
+      e = launch_apply_1q(static_cast<float*>(S.amps), S.nq, local[0], mm, f->stream);
+    } else {
+      Mat2<double> mm;
+      for (int i = 0; i < 4; ++i) { mm.re[i] = m[2 * i]; mm.im[i] = m[2 * i + 1]; }
+      e = launch_apply_1q(static_cast<double*>(S.amps), S.nq, local[0], mm, f->stream);
+    }
+  } else {
+    const size_t D = size_t(1) << k;
+    e = upload(f, f->mat, m, D * D);
+    if (e == hipSuccess)
+      e = f->dtype == QS_C64
+              ? launch_apply_fused(static_cast<float*>(S.amps), S.nq, local, k,
+                                   static_cast<const float*>(f->mat), f->stream)
+              : launch_apply_fused(static_cast<double*>(S.amps), S.nq, local, k,
+                                   static_cast<const double*>(f->mat), f->stream);
+  }
+  if (int rc = dev_err(e, "factorized gate")) return rc;
+  if (k >= 2) {
+    for (int j = 0; j < k; ++j) f->dirty |= uint64_t(1) << qubits[j];
+    if (f->policy == QS_SEP_AFTER_2Q) {
+      int nsep = 0;
+      return fact_try_separate(f, f->p, &nsep);
+    }
+  }
+  return QS_OK;
+}
+
+int fact_swap(FactorState* f, int a, int b) {
+  for (auto& s : f->subs)
+    for (int t = 0; t < s.nq; ++t) {
+      if (s.q[t] == a) s.q[t] = b;
+      else if (s.q[t] == b) s.q[t] = a;
+    }
+  const uint64_t da = (f->dirty >> a) & 1, db = (f->dirty >> b) & 1;
+  f->dirty &= ~((uint64_t(1) << a) | (uint64_t(1) << b));
+  f->dirty |= (da << b) | (db << a);
+  return QS_OK;
+}
+
+int fact_relabel(FactorState* f, const int* pos) {
+  int inv[64];
+  for (int q = 0; q < f->n; ++q) inv[pos[q]] = q;
+  uint64_t nd = 0;
+  for (int q = 0; q < f->n; ++q)
+    if ((f->dirty >> pos[q]) & 1) nd |= uint64_t(1) << q;
+  for (auto& s : f->subs)
+    for (int t = 0; t < s.nq; ++t) s.q[t] = inv[s.q[t]];
+  f->dirty = nd;
+  return QS_OK;
+}
+
+int fact_try_separate(FactorState* f, double p, int* n_separated) {
+  int count = 0;
+  while (f->dirty) {
+    const int q = __builtin_ctzll(f->dirty);
+    bool rounded = false;
+    if (int rc = test_qubit(f, q, p, &rounded)) return rc;
+    count += rounded;
+  }
+  if (n_separated) *n_separated = count;
+  return QS_OK;
+}
+
+int fact_gather(FactorState* f, const uint64_t* idx, uint64_t m, double* out) {
+  uint64_t* didx = static_cast<uint64_t*>(device_alloc(m * sizeof(uint64_t)));
+  double* dout = static_cast<double*>(device_alloc(m * 2 * sizeof(double)));
+  if (!didx || !dout) {
+    device_free(didx);
+    device_free(dout);
+    return ffail(QS_E_NOMEM, "staging allocation failed");
+  }
+  std::vector<double> ones(2 * m, 0.0);
+  for (uint64_t j = 0; j < m; ++j) ones[2 * j] = 1.0;
+  hipError_t e = hipMemcpyAsync(didx, idx, m * sizeof(uint64_t), hipMemcpyHostToDevice, f->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dout, ones.data(), m * 2 * sizeof(double), hipMemcpyHostToDevice, f->stream);
+  for (size_t s = 0; s < f->subs.size() && e == hipSuccess; ++s) {
+    Perm64 bits{};
+    bits.n = f->subs[s].nq;
+    for (int t = 0; t < bits.n; ++t) bits.p[t] = int8_t(f->subs[s].q[t]);
+    e = f->dtype == QS_C64
+            ? launch_gather_mul(static_cast<const float*>(f->subs[s].amps), didx, m, bits, dout, f->stream)
+            : launch_gather_mul(static_cast<const double*>(f->subs[s].amps), didx, m, bits, dout, f->stream);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, dout, m * 2 * sizeof(double), hipMemcpyDeviceToHost, f->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+  device_free(didx);
+  device_free(dout);
+  return dev_err(e, "factorized gather");
+}
+
+int fact_norm(FactorState* f, double* out) {
+  double prod = 1.0;
+  for (auto& s : f->subs) {
+    hipError_t e = f->dtype == QS_C64
+                       ? launch_inner(static_cast<const float*>(s.amps), static_cast<const float*>(s.amps),
+                                      uint64_t(1) << s.nq, f->scratch, f->stream)
+                       : launch_inner(static_cast<const double*>(s.amps), static_cast<const double*>(s.amps),
+                                      uint64_t(1) << s.nq, f->scratch, f->stream);
+    double v[2];
+    if (e == hipSuccess) e = hipMemcpyAsync(v, f->scratch, sizeof v, hipMemcpyDeviceToHost, f->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+    if (int rc = dev_err(e, "norm")) return rc;
+    prod *= v[0];
+  }
+  *out = prod;
+  return QS_OK;
+}
+
+int fact_expand(FactorState* f, void* dense, int* perm_out) {
+  const size_t ab = amp_bytes(f);
+  void* tmp = device_alloc((size_t(1) << f->n) * ab);
+  if (!tmp) return ffail(QS_E_NOMEM, "expansion buffer");
+  // compose subsystems one after another, alternating between two buffers so
+  // that the last compose lands in `dense`
+  const int ns = int(f->subs.size());
+  void* bufs[2] = {dense, tmp};
+  int cur = (ns - 1) % 2;  // buffer holding the running product
+  hipError_t e = hipMemcpyAsync(bufs[cur], f->subs[0].amps, (size_t(1) << f->subs[0].nq) * ab,
+                                hipMemcpyDeviceToDevice, f->stream);
+  int nq = f->subs[0].nq, bit = 0;
+  for (int t = 0; t < f->subs[0].nq; ++t) perm_out[f->subs[0].q[t]] = bit++;
+  for (int s = 1; s < ns && e == hipSuccess; ++s) {
+    const Sub& B = f->subs[s];
+    void* dst = bufs[1 - cur];
+    e = f->dtype == QS_C64
+            ? launch_compose(static_cast<float*>(dst), static_cast<const float*>(bufs[cur]), nq,
+                             static_cast<const float*>(B.amps), B.nq, f->stream)
+            : launch_compose(static_cast<double*>(dst), static_cast<const double*>(bufs[cur]), nq,
+                             static_cast<const double*>(B.amps), B.nq, f->stream);
+    for (int t = 0; t < B.nq; ++t) perm_out[B.q[t]] = bit++;
+    nq += B.nq;
+    cur = 1 - cur;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+  device_free(tmp);
+  return dev_err(e, "expand");
+}
+
+}  // namespace qs

@@ -1,0 +1,53 @@
+// Factorized ket of the approximate mode (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/qs.h"
+
+namespace qs {
+
+// One subsystem: q[t] is the qubit stored at bit t of its amplitude index.
+struct Sub {
+  int nq = 0;
+  int q[64] = {0};
+  void* amps = nullptr;  // 2^nq amplitudes, device, owned
+};
+
+struct FactorState {
+  int n = 0;
+  int dtype = QS_C64;
+  uint64_t max_amps = 0;
+  hipStream_t stream = nullptr;
+  std::vector<Sub> subs;
+  double F = 1.0;          // fidelity estimate, Eq. fid_model
+  uint64_t dirty = 0;      // qubits whose reduced state may have changed
+  int policy = QS_SEP_NONE;
+  double p = 0.0;          // SDRP threshold parameter of the policy
+  double tau = 1e-6;       // "epsilon = 0 up to machine precision"
+  qs_attempt* log = nullptr;
+  uint64_t log_cap = 0;
+  uint64_t* log_count = nullptr;
+  double* scratch = nullptr;  // device reduction scratch
+  void* mat = nullptr;        // device slot for one gate matrix
+};
+
+// All return QS_* status codes and set the thread's error message.
+int fact_init(FactorState* f);                     // n one-qubit |0> subsystems
+void fact_release(FactorState* f);                 // frees every buffer
+int fact_set_basis(FactorState* f, uint64_t x);    // n one-qubit basis states
+int fact_apply(FactorState* f, const int* qubits, int k, const double* m);
+int fact_swap(FactorState* f, int a, int b);       // relabel
+int fact_relabel(FactorState* f, const int* pos);  // label v -> q where pos[q] = v
+int fact_try_separate(FactorState* f, double p, int* n_separated);
+int fact_gather(FactorState* f, const uint64_t* idx, uint64_t m, double* out);
+int fact_norm(FactorState* f, double* out);
+// Dense copy in `dense` (2^n amplitudes of the same precision); perm_out[q]
+// receives the bit of qubit q in that copy.
+int fact_expand(FactorState* f, void* dense, int* perm_out);
+int fact_largest(const FactorState* f);
+
+}  // namespace qs

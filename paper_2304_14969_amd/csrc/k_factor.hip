@@ -1,0 +1,198 @@
+// Kernels of the factorized (approximate) mode, Sec. III.
+//
+//   compose    c[iA + 2^nA iB] = a[iA] b[iB]      (merge of two subsystems)
+//   bloch      s = sum conj(a0) a1, z0 = sum |a0|^2, z1 = sum |a1|^2 over the
+//              pairs (a0, a1) that differ in bit t, accumulated in float64 in a
+//              fixed order (the reduced state of one qubit, Sec. III-A step 1)
+//   decompose  b[u] = (conj(phi0) a[i0(u)] + conj(phi1) a[i1(u)]) * scale,
+//              i0/i1 = u with a 0/1 inserted at bit t (projection of the qubit
+//              on phi and removal of its bit, Sec. III-A steps 2-4)
+//   inner      sum conj(a) b in float64 (fidelity of Eq. fid_exact)
+//   gather_mul out[j] *= a[local index of x_j] (readout of a product state)
+#include "qs_internal.h"
+
+namespace qs {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kRedBlocks = 1024;
+
+__device__ __forceinline__ uint64_t insert_zero(uint64_t x, int pos) {
+  const uint64_t lo = x & ((uint64_t(1) << pos) - 1);
+  return lo | ((x ^ lo) << 1);
+}
+
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], double* sh) {
+  // sh holds N * kBlock doubles; fixed tree order
+#pragma unroll
+  for (int k = 0; k < N; ++k) sh[k * kBlock + threadIdx.x] = v[k];
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+#pragma unroll
+      for (int k = 0; k < N; ++k) sh[k * kBlock + threadIdx.x] += sh[k * kBlock + threadIdx.x + w];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = sh[k * kBlock];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_compose(R* __restrict__ c, const R* __restrict__ a,
+                                                    int na, const R* __restrict__ b,
+                                                    uint64_t total) {
+  const uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= total) return;
+  const uint64_t ia = i & ((uint64_t(1) << na) - 1), ib = i >> na;
+  const R ar = a[2 * ia], ai = a[2 * ia + 1], br = b[2 * ib], bi = b[2 * ib + 1];
+  c[2 * i] = ar * br - ai * bi;
+  c[2 * i + 1] = ar * bi + ai * br;
+}
+
+// partial[k * kRedBlocks + block], k = 0..3: Re s, Im s, z0, z1
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_bloch_partial(const R* __restrict__ a, uint64_t pairs,
+                                                          int t, double* __restrict__ partial) {
+  __shared__ double sh[4 * kBlock];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+  const uint64_t bit = uint64_t(1) << t;
+  for (uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x; u < pairs; u += stride) {
+    const uint64_t i0 = insert_zero(u, t), i1 = i0 | bit;
+    const double x0 = a[2 * i0], y0 = a[2 * i0 + 1], x1 = a[2 * i1], y1 = a[2 * i1 + 1];
+    v[0] += x0 * x1 + y0 * y1;  // Re conj(a0) a1
+    v[1] += x0 * y1 - y0 * x1;  // Im conj(a0) a1
+    v[2] += x0 * x0 + y0 * y0;
+    v[3] += x1 * x1 + y1 * y1;
+  }
+  block_sum<4>(v, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) partial[k * gridDim.x + blockIdx.x] = v[k];
+}
+
+template <int N>
+__global__ void __launch_bounds__(kBlock) k_sum_rows(const double* __restrict__ partial, int count,
+                                                     double* __restrict__ out) {
+  __shared__ double sh[N * kBlock];
+  double v[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = 0.0;
+  for (int i = threadIdx.x; i < count; i += kBlock)
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] += partial[k * count + i];
+  block_sum<N>(v, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < N; ++k) out[k] = v[k];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_decompose(R* __restrict__ b, const R* __restrict__ a,
+                                                      uint64_t count, int t, double p0r, double p0i,
+                                                      double p1r, double p1i, double scale) {
+  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (u >= count) return;
+  const uint64_t i0 = insert_zero(u, t), i1 = i0 | (uint64_t(1) << t);
+  const double x0 = a[2 * i0], y0 = a[2 * i0 + 1], x1 = a[2 * i1], y1 = a[2 * i1 + 1];
+  // conj(phi0) a0 + conj(phi1) a1
+  const double re = p0r * x0 + p0i * y0 + p1r * x1 + p1i * y1;
+  const double im = p0r * y0 - p0i * x0 + p1r * y1 - p1i * x1;
+  b[2 * u] = static_cast<R>(re * scale);
+  b[2 * u + 1] = static_cast<R>(im * scale);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_inner_partial(const R* __restrict__ a,
+                                                          const R* __restrict__ b, uint64_t count,
+                                                          double* __restrict__ partial) {
+  __shared__ double sh[2 * kBlock];
+  double v[2] = {0.0, 0.0};
+  const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+  for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < count; i += stride) {
+    const double ar = a[2 * i], ai = a[2 * i + 1], br = b[2 * i], bi = b[2 * i + 1];
+    v[0] += ar * br + ai * bi;
+    v[1] += ar * bi - ai * br;
+  }
+  block_sum<2>(v, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 2; ++k) partial[k * gridDim.x + blockIdx.x] = v[k];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_gather_mul(const R* __restrict__ a,
+                                                       const uint64_t* __restrict__ idx, uint64_t m,
+                                                       Perm64 bits, double* __restrict__ out) {
+  const uint64_t j = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (j >= m) return;
+  const uint64_t x = idx[j];
+  uint64_t loc = 0;
+  for (int t = 0; t < bits.n; ++t) loc |= ((x >> bits.p[t]) & 1) << t;
+  const double ar = a[2 * loc], ai = a[2 * loc + 1];
+  const double orr = out[2 * j], oi = out[2 * j + 1];
+  out[2 * j] = orr * ar - oi * ai;
+  out[2 * j + 1] = orr * ai + oi * ar;
+}
+
+unsigned blocks_for(uint64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
+unsigned red_blocks(uint64_t n) {
+  const uint64_t b = (n + kBlock - 1) / kBlock;
+  return unsigned(b < kRedBlocks ? (b > 0 ? b : 1) : kRedBlocks);
+}
+
+}  // namespace
+
+int factor_scratch_doubles() { return 4 * kRedBlocks + 8; }
+
+template <typename R>
+hipError_t launch_compose(R* c, const R* a, int na, const R* b, int nb, hipStream_t s) {
+  const uint64_t total = uint64_t(1) << (na + nb);
+  hipLaunchKernelGGL(k_compose<R>, dim3(blocks_for(total)), dim3(kBlock), 0, s, c, a, na, b, total);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_bloch(const R* a, int nq, int t, double* scratch, hipStream_t s) {
+  const uint64_t pairs = uint64_t(1) << (nq - 1);
+  const unsigned nb = red_blocks(pairs);
+  hipLaunchKernelGGL(k_bloch_partial<R>, dim3(nb), dim3(kBlock), 0, s, a, pairs, t, scratch + 8);
+  hipLaunchKernelGGL(k_sum_rows<4>, dim3(1), dim3(kBlock), 0, s, scratch + 8, int(nb), scratch);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_decompose(R* b, const R* a, int nq, int t, const double phi[4], double scale,
+                            hipStream_t s) {
+  const uint64_t count = uint64_t(1) << (nq - 1);
+  hipLaunchKernelGGL(k_decompose<R>, dim3(blocks_for(count)), dim3(kBlock), 0, s, b, a, count, t,
+                     phi[0], phi[1], phi[2], phi[3], scale);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_inner(const R* a, const R* b, uint64_t count, double* scratch, hipStream_t s) {
+  const unsigned nb = red_blocks(count);
+  hipLaunchKernelGGL(k_inner_partial<R>, dim3(nb), dim3(kBlock), 0, s, a, b, count, scratch + 8);
+  hipLaunchKernelGGL(k_sum_rows<2>, dim3(1), dim3(kBlock), 0, s, scratch + 8, int(nb), scratch);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_gather_mul(const R* a, const uint64_t* idx, uint64_t m, Perm64 bits, double* out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_mul<R>, dim3(blocks_for(m)), dim3(kBlock), 0, s, a, idx, m, bits, out);
+  return hipGetLastError();
+}
+
+#define QS_INST(R)                                                                          \
+  template hipError_t launch_compose<R>(R*, const R*, int, const R*, int, hipStream_t);     \
+  template hipError_t launch_bloch<R>(const R*, int, int, double*, hipStream_t);            \
+  template hipError_t launch_decompose<R>(R*, const R*, int, int, const double*, double,    \
+                                          hipStream_t);                                     \
+  template hipError_t launch_inner<R>(const R*, const R*, uint64_t, double*, hipStream_t);  \
+  template hipError_t launch_gather_mul<R>(const R*, const uint64_t*, uint64_t, Perm64,     \
+                                           double*, hipStream_t);
+QS_INST(float)
+QS_INST(double)
+#undef QS_INST
+
+}  // namespace qs

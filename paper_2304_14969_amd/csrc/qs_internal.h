@@ -63,6 +63,21 @@ bool fused_geometry(int n, const int* qubits, int k, FusedGeom* g);
 hipError_t launch_fused_mfma(float* amps, int n, const int* qubits, int k, const float* mat,
                              hipStream_t s);
 
+// ---------------------------------------------------------------- factorized mode
+// scratch: factor_scratch_doubles() doubles of device memory; results land in
+// scratch[0..3] (bloch: Re s, Im s, z0, z1; inner: Re, Im).
+int factor_scratch_doubles();
+template <typename R>
+hipError_t launch_compose(R* c, const R* a, int na, const R* b, int nb, hipStream_t s);
+template <typename R>
+hipError_t launch_bloch(const R* a, int nq, int t, double* scratch, hipStream_t s);
+// phi = {Re phi0, Im phi0, Re phi1, Im phi1}
+template <typename R>
+hipError_t launch_decompose(R* b, const R* a, int nq, int t, const double phi[4], double scale,
+                            hipStream_t s);
+template <typename R>
+hipError_t launch_inner(const R* a, const R* b, uint64_t count, double* scratch, hipStream_t s);
+
 // ---------------------------------------------------------------- QFT passes
 // One pass of a QFT on the qubit range [start, start+len): the stages of the
 // bits [lo, hi), each a butterfly on its bit and the phase controlled by the
@@ -126,5 +141,10 @@ struct Perm64 {
 template <typename R>
 hipError_t launch_gather(const R* amps, const uint64_t* idx, uint64_t m, Perm64 perm,
                          double* out, hipStream_t s);
+// out[j] *= a[local index of idx[j]], bit t of the local index = bit bits.p[t]
+// of idx[j]
+template <typename R>
+hipError_t launch_gather_mul(const R* a, const uint64_t* idx, uint64_t m, Perm64 bits,
+                             double* out, hipStream_t s);
 
 }  // namespace qs

@@ -1,0 +1,194 @@
+"""Approximate (SDRP) mode on the GPU against the FP64 oracle.
+
+Decisions are compared by replay: the oracle recomputes eps on its own state
+for every attempt; the two decisions must agree unless the oracle's eps lies
+within 1e-5 of the threshold p/2 (complex64 rounding can move eps by ~1e-7),
+in which case the oracle follows the GPU's decision. Then the attempt
+sequences, the fidelity estimates and the expanded kets must match."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import dense, factor
+from parity import C64, C128, assert_parity
+
+pytestmark = pytest.mark.gpu
+NEAR = 1e-5
+
+
+def gpu_run(qs, n, gates, p, dtype=C64, max_amps=2 ** 30):
+    st = qs.State(n, dtype, factorized=True, max_amps=max_amps)
+    st.set_policy(qs.SEP_AFTER_2Q, p)
+    st.record_attempts()
+    c = qs.Circuit(n).add_gates(gates)
+    st.run(c)
+    return st
+
+
+def replay(n, gates, p, attempts, eps_tol):
+    it = iter(attempts)
+    seen = []
+
+    def decide(q, nsub, eps, rule):
+        gq, gn, geps, grounded = next(it)
+        assert (gq, gn) == (q, nsub), f"attempt {len(seen)}: gpu {(gq, gn)} oracle {(q, nsub)}"
+        assert abs(geps - eps) <= eps_tol, (len(seen), geps, eps)
+        seen.append(q)
+        if abs(eps - p / 2) < NEAR:
+            return grounded
+        assert grounded == rule, (len(seen), q, eps, p)
+        return rule
+
+    ost = factor.FactorizedState(n, decide=decide)
+    ost.run(gates, p)
+    assert next(it, None) is None, "GPU made more attempts than the oracle"
+    return ost
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_exact_mode_matches_dense(qs_lib, dtype):
+    qs = qs_lib
+    n = 12
+    gates = workloads.random_circuit(n, 5, 3)
+    st = gpu_run(qs, n, gates, 0.0, dtype)
+    assert st.fidelity_estimate() > 1 - 1e-5
+    want = dense.run_circuit(dense.zero_state(n), n, gates)
+    assert_parity(st.amplitudes(), want, dtype, "factorized p=0")
+    st.free()
+
+
+@pytest.mark.parametrize("n,layers,p,seed", [(10, 6, 0.05, 1), (10, 6, 0.2, 2), (14, 5, 0.1, 3),
+                                             (14, 7, 0.3, 4), (16, 4, 0.05, 5)])
+def test_sdrp_decision_replay(qs_lib, n, layers, p, seed):
+    qs = qs_lib
+    gates = workloads.random_circuit(n, layers, seed)
+    st = gpu_run(qs, n, gates, p)
+    att = st.attempts()
+    ost = replay(n, gates, p, att, eps_tol=2e-5)
+    assert len(att) == len(ost.log)
+    assert sum(a[3] for a in att) == sum(a.rounded for a in ost.log)
+    F = st.fidelity_estimate()
+    assert abs(F - ost.F) <= 1e-5 * max(ost.F, 1e-3) + 1e-7, (F, ost.F)
+    assert sorted(len(s) for s in st.subsystems()) == ost.sizes()
+    got = st.amplitudes()
+    want = ost.expand()
+    assert_parity(got, want, C64, f"sdrp n={n} p={p}")
+    st.free()
+
+
+def test_sdrp_replay_complex128(qs_lib):
+    qs = qs_lib
+    n, p = 12, 0.15
+    gates = workloads.random_circuit(n, 6, 9)
+    st = gpu_run(qs, n, gates, p, C128)
+    att = st.attempts()
+    ost = replay(n, gates, p, att, eps_tol=1e-10)
+    assert abs(st.fidelity_estimate() - ost.F) < 1e-10
+    assert_parity(st.amplitudes(), ost.expand(), C128, "c128 sdrp")
+    st.free()
+
+
+def test_golden_pair_on_gpu(qs_lib):
+    """sqrt(1-e)|00> + sqrt(e)|11> (tests/golden/sdrp_pair.txt): eps = e, the
+    rule eps <= p/2, fidelity 1 - e."""
+    qs = qs_lib
+    rows = []
+    with open(os.path.join(os.path.dirname(__file__), "golden", "sdrp_pair.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                rows.append([float(v) for v in line.split()])
+    for e, p, rounds, F_want in rows:
+        st = qs.State(2, C128, factorized=True)
+        st.record_attempts()
+        th = 2 * math.acos(math.sqrt(1 - e))
+        st.apply_1q(0, np.array([[math.cos(th / 2), -math.sin(th / 2)],
+                                 [math.sin(th / 2), math.cos(th / 2)]]))
+        st.apply_ctrl([0], 1, 1, np.array([[0, 1], [1, 0]]))
+        assert st.try_separate(p) == int(rounds)
+        a = st.attempts()[0]
+        assert abs(a[2] - e) < 1e-12
+        assert abs(st.fidelity_estimate() - F_want) < 1e-12
+        if rounds:
+            np.testing.assert_allclose(st.amplitudes(), [1, 0, 0, 0], atol=1e-12)
+        st.free()
+
+
+def test_capacity_leaves_state_unchanged(qs_lib):
+    qs = qs_lib
+    st = qs.State(6, C64, factorized=True, max_amps=2 ** 3)
+    for q in range(4):
+        st.apply_1q(q, dense.H)
+    st.apply_cphase(0, 1, 0.7)
+    st.apply_cphase(1, 2, 0.4)
+    before = st.amplitudes()
+    sizes = sorted(len(s) for s in st.subsystems())
+    with pytest.raises(qs.CapacityError):
+        st.apply_cphase(2, 3, 0.9)
+    assert sorted(len(s) for s in st.subsystems()) == sizes
+    np.testing.assert_array_equal(st.amplitudes(), before)
+    st.apply_1q(5, dense.H)  # still usable
+    st.free()
+
+
+def test_factorized_gate_kinds_and_relabels(qs_lib):
+    qs = qs_lib
+    n = 9
+    g = np.random.default_rng(2)
+    st = qs.State(n, C64, factorized=True)
+    want = dense.zero_state(n)
+    for it in range(60):
+        kind = int(g.integers(0, 5))
+        if kind == 0:
+            q = int(g.integers(0, n))
+            m = dense.u3(*g.uniform(0, 2 * math.pi, 3))
+            st.apply_1q(q, m)
+            want = dense.apply_1q(want, n, q, m)
+        elif kind == 1:
+            a, b = (int(v) for v in g.choice(n, 2, replace=False))
+            st.apply_cphase(a, b, 0.37 * it)
+            want = dense.apply_cphase(want, n, a, b, 0.37 * it)
+        elif kind == 2:
+            a, b = (int(v) for v in g.choice(n, 2, replace=False))
+            st.apply_swap(a, b)
+            want = dense.apply_swap(want, n, a, b)
+        elif kind == 3:
+            qq = [int(v) for v in g.choice(n, 3, replace=False)]
+            m = dense.u3(*g.uniform(0, 2 * math.pi, 3))
+            st.apply_ctrl(qq[:2], 2, qq[2], m)
+            want = dense.apply_ctrl(want, n, qq[:2], 2, qq[2], m)
+        else:
+            qq = [int(v) for v in g.choice(n, 2, replace=False)]
+            st.apply_fused(qq, dense.ISWAP)
+            want = dense.apply_matrix(want, n, qq, dense.ISWAP)
+        if it % 10 == 9:
+            st.mark_dirty((1 << n) - 1)
+            st.try_separate(0.0)
+    assert_parity(st.amplitudes(), want, C64, "gate kinds")
+    idx = np.random.default_rng(0).integers(0, 2 ** n, 64)
+    np.testing.assert_allclose(st.gather(idx), want[idx], atol=2e-6)
+    assert abs(st.norm() - 1) < 1e-5
+    st.free()
+
+
+def test_fidelity_exact_pipeline(qs_lib):
+    """F_exact = |<approx|exact>|^2 (Eq. fid_exact) from GPU states equals the
+    oracle's value for the same decisions."""
+    qs = qs_lib
+    n, p = 16, 0.1
+    gates = workloads.random_circuit(n, 6, 11)
+    st = gpu_run(qs, n, gates, p)
+    ost = replay(n, gates, p, st.attempts(), eps_tol=2e-5)
+    approx = qs.State(n, C64)
+    st.expand_into(approx)
+    exact = qs.State(n, C64)
+    exact.run(qs.Circuit(n).add_gates(gates))
+    F_gpu = abs(approx.inner(exact)) ** 2
+    F_orc = dense.fidelity(ost.expand(), dense.run_circuit(dense.zero_state(n), n, gates))
+    assert abs(F_gpu - F_orc) < 2e-5, (F_gpu, F_orc)
+    assert 0 < st.fidelity_estimate() <= 1
+    for s in (st, approx, exact):
+        s.free()
