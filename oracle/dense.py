@@ -62,6 +62,8 @@ def cphase_matrix(theta: float) -> np.ndarray:
 
 
 CZ = np.diag([1.0, 1.0, 1.0, -1.0]).astype(C128)
+PAULI = {"x": X, "y": Y, "z": Z}
+COUPLERS = ("cx", "cy", "cz", "ax", "ay", "az")
 ISWAP = np.array([[1, 0, 0, 0], [0, 0, 1j, 0], [0, 1j, 0, 0], [0, 0, 0, 1]], dtype=C128)
 SWAP = np.array([[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]], dtype=C128)
 
@@ -142,6 +144,11 @@ def gate_matrix(g) -> tuple:
     if kind == "ctrl":
         ctrls = list(g[1])
         return ctrls + [g[3]], controlled_matrix(len(ctrls), g[2], u3(g[4], g[5], g[6]))
+    if kind in COUPLERS:
+        # (control, target); "c*" acts when the control is |1>, "a*" when |0>
+        # (the couplers of Sec. III-C)
+        cv = 1 if kind[0] == "c" else 0
+        return [g[1], g[2]], controlled_matrix(1, cv, PAULI[kind[1]])
     if kind == "mat":
         return list(g[1]), np.asarray(g[2], dtype=C128)
     raise ValueError(f"unknown gate {kind!r}")

@@ -42,12 +42,13 @@ template <typename R>
 __global__ void __launch_bounds__(kBlock) k_compose(R* __restrict__ c, const R* __restrict__ a,
                                                     int na, const R* __restrict__ b,
                                                     uint64_t total) {
-  const uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= total) return;
-  const uint64_t ia = i & ((uint64_t(1) << na) - 1), ib = i >> na;
-  const R ar = a[2 * ia], ai = a[2 * ia + 1], br = b[2 * ib], bi = b[2 * ib + 1];
-  c[2 * i] = ar * br - ai * bi;
-  c[2 * i + 1] = ar * bi + ai * br;
+  for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < total;
+       i += uint64_t(gridDim.x) * kBlock) {
+    const uint64_t ia = i & ((uint64_t(1) << na) - 1), ib = i >> na;
+    const R ar = a[2 * ia], ai = a[2 * ia + 1], br = b[2 * ib], bi = b[2 * ib + 1];
+    c[2 * i] = ar * br - ai * bi;
+    c[2 * i + 1] = ar * bi + ai * br;
+  }
 }
 
 // partial[k * kRedBlocks + block], k = 0..3: Re s, Im s, z0, z1
@@ -90,15 +91,16 @@ template <typename R>
 __global__ void __launch_bounds__(kBlock) k_decompose(R* __restrict__ b, const R* __restrict__ a,
                                                       uint64_t count, int t, double p0r, double p0i,
                                                       double p1r, double p1i, double scale) {
-  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (u >= count) return;
-  const uint64_t i0 = insert_zero(u, t), i1 = i0 | (uint64_t(1) << t);
-  const double x0 = a[2 * i0], y0 = a[2 * i0 + 1], x1 = a[2 * i1], y1 = a[2 * i1 + 1];
-  // conj(phi0) a0 + conj(phi1) a1
-  const double re = p0r * x0 + p0i * y0 + p1r * x1 + p1i * y1;
-  const double im = p0r * y0 - p0i * x0 + p1r * y1 - p1i * x1;
-  b[2 * u] = static_cast<R>(re * scale);
-  b[2 * u + 1] = static_cast<R>(im * scale);
+  for (uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x; u < count;
+       u += uint64_t(gridDim.x) * kBlock) {
+    const uint64_t i0 = insert_zero(u, t), i1 = i0 | (uint64_t(1) << t);
+    const double x0 = a[2 * i0], y0 = a[2 * i0 + 1], x1 = a[2 * i1], y1 = a[2 * i1 + 1];
+    // conj(phi0) a0 + conj(phi1) a1
+    const double re = p0r * x0 + p0i * y0 + p1r * x1 + p1i * y1;
+    const double im = p0r * y0 - p0i * x0 + p1r * y1 - p1i * x1;
+    b[2 * u] = static_cast<R>(re * scale);
+    b[2 * u + 1] = static_cast<R>(im * scale);
+  }
 }
 
 template <typename R>
@@ -122,18 +124,24 @@ template <typename R>
 __global__ void __launch_bounds__(kBlock) k_gather_mul(const R* __restrict__ a,
                                                        const uint64_t* __restrict__ idx, uint64_t m,
                                                        Perm64 bits, double* __restrict__ out) {
-  const uint64_t j = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (j >= m) return;
-  const uint64_t x = idx[j];
-  uint64_t loc = 0;
-  for (int t = 0; t < bits.n; ++t) loc |= ((x >> bits.p[t]) & 1) << t;
-  const double ar = a[2 * loc], ai = a[2 * loc + 1];
-  const double orr = out[2 * j], oi = out[2 * j + 1];
-  out[2 * j] = orr * ar - oi * ai;
-  out[2 * j + 1] = orr * ai + oi * ar;
+  for (uint64_t j = uint64_t(blockIdx.x) * kBlock + threadIdx.x; j < m;
+       j += uint64_t(gridDim.x) * kBlock) {
+    const uint64_t x = idx[j];
+    uint64_t loc = 0;
+    for (int t = 0; t < bits.n; ++t) loc |= ((x >> bits.p[t]) & 1) << t;
+    const double ar = a[2 * loc], ai = a[2 * loc + 1];
+    const double orr = out[2 * j], oi = out[2 * j + 1];
+    out[2 * j] = orr * ar - oi * ai;
+    out[2 * j + 1] = orr * ai + oi * ar;
+  }
 }
 
-unsigned blocks_for(uint64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
+// grid of an elementwise kernel; the kernels stride, so the grid is capped
+unsigned blocks_for(uint64_t n) {
+  const uint64_t b = (n + kBlock - 1) / kBlock;
+  const uint64_t cap = uint64_t(1) << 20;
+  return unsigned(b < cap ? (b > 0 ? b : 1) : cap);
+}
 unsigned red_blocks(uint64_t n) {
   const uint64_t b = (n + kBlock - 1) / kBlock;
   return unsigned(b < kRedBlocks ? (b > 0 ? b : 1) : kRedBlocks);

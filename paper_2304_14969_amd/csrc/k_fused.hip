@@ -35,39 +35,41 @@ __global__ void __launch_bounds__(kBlock) k_fused_vec(R* __restrict__ a, uint64_
   __shared__ Cx<R> M[D * D];
   for (int e = threadIdx.x; e < D * D; e += kBlock) M[e] = {mat[2 * e], mat[2 * e + 1]};
   __syncthreads();
-  const uint64_t g = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (g >= groups) return;
-  uint64_t base = g;
+  for (uint64_t g = uint64_t(blockIdx.x) * kBlock + threadIdx.x; g < groups;
+       g += uint64_t(gridDim.x) * kBlock) {
+    uint64_t base = g;
 #pragma unroll
-  for (int j = 0; j < K; ++j) base = insert_zero(base, b.sorted[j]);
-  uint64_t off[D];
-  Cx<R> v[D];
-#pragma unroll
-  for (int c = 0; c < D; ++c) {
-    uint64_t o = 0;
-#pragma unroll
-    for (int j = 0; j < K; ++j) o |= uint64_t((c >> j) & 1) << b.q[j];
-    off[c] = base | o;
-    v[c] = {a[2 * off[c]], a[2 * off[c] + 1]};
-  }
-#pragma unroll
-  for (int r = 0; r < D; ++r) {
-    R yr = 0, yi = 0;
+    for (int j = 0; j < K; ++j) base = insert_zero(base, b.sorted[j]);
+    uint64_t off[D];
+    Cx<R> v[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-      const Cx<R> m = M[r * D + c];
-      yr += m.r * v[c].r - m.i * v[c].i;
-      yi += m.r * v[c].i + m.i * v[c].r;
+      uint64_t o = 0;
+#pragma unroll
+      for (int j = 0; j < K; ++j) o |= uint64_t((c >> j) & 1) << b.q[j];
+      off[c] = base | o;
+      v[c] = {a[2 * off[c]], a[2 * off[c] + 1]};
     }
-    a[2 * off[r]] = yr;
-    a[2 * off[r] + 1] = yi;
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      R yr = 0, yi = 0;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const Cx<R> m = M[r * D + c];
+        yr += m.r * v[c].r - m.i * v[c].i;
+        yi += m.r * v[c].i + m.i * v[c].r;
+      }
+      a[2 * off[r]] = yr;
+      a[2 * off[r] + 1] = yi;
+    }
   }
 }
 
 template <typename R, int K>
 hipError_t launch_k(R* a, int n, const Block6& b, const R* mat, hipStream_t s) {
   const uint64_t groups = uint64_t(1) << (n - K);
-  const unsigned grid = static_cast<unsigned>((groups + kBlock - 1) / kBlock);
+  const uint64_t want = (groups + kBlock - 1) / kBlock, cap = uint64_t(1) << 20;
+  const unsigned grid = static_cast<unsigned>(want < cap ? want : cap);
   hipLaunchKernelGGL((k_fused_vec<R, K>), dim3(grid), dim3(kBlock), 0, s, a, groups, b, mat);
   return hipGetLastError();
 }

@@ -4,7 +4,8 @@
 // Every kernel moves 16-byte vectors (one c128 amplitude or two adjacent c64
 // amplitudes) so each wavefront touches whole 64-byte segments; the pair
 // partner at distance 2^t sits in the same thread, so each byte is read and
-// written once per gate.
+// written once per gate. Grids are capped and threads stride through the
+// work, so a launch never exceeds the 2^32 threads of one grid dimension.
 #include "qs_internal.h"
 
 namespace qs {
@@ -15,6 +16,7 @@ template <> struct Vec16<float> { using T = float4; static constexpr int AMPS = 
 template <> struct Vec16<double> { using T = double2; static constexpr int AMPS = 1; };
 
 constexpr int kBlock = 256;
+constexpr uint64_t kMaxGrid = uint64_t(1) << 20;
 
 __device__ __forceinline__ uint64_t insert_zero(uint64_t x, int pos) {
   const uint64_t lo = x & ((uint64_t(1) << pos) - 1);
@@ -36,48 +38,53 @@ __device__ __forceinline__ void mat2_apply(const Mat2<R>& m, R& x0r, R& x0i, R& 
 }
 
 inline unsigned grid_for(uint64_t units) {
-  return static_cast<unsigned>((units + kBlock - 1) / kBlock);
+  const uint64_t b = (units + kBlock - 1) / kBlock;
+  return static_cast<unsigned>(b < kMaxGrid ? (b > 0 ? b : 1) : kMaxGrid);
 }
+
+#define QS_STRIDE_LOOP(u, units)                                               \
+  for (uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x; u < (units); \
+       u += uint64_t(gridDim.x) * kBlock)
 
 // ------------------------------------------------------------------ 1q
 // c64, target bit t >= 1: a unit is two adjacent pairs (i, i+1) x (bit t).
 __global__ void __launch_bounds__(kBlock) k_1q_f_vec(float* __restrict__ a, uint64_t units,
                                                      int t, Mat2<float> m) {
-  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (u >= units) return;
-  const uint64_t i0 = insert_zero(u << 1, t);
-  float4* p0 = reinterpret_cast<float4*>(a + 2 * i0);
-  float4* p1 = reinterpret_cast<float4*>(a + 2 * (i0 + (uint64_t(1) << t)));
-  float4 x = *p0, y = *p1;
-  mat2_apply(m, x.x, x.y, y.x, y.y);
-  mat2_apply(m, x.z, x.w, y.z, y.w);
-  *p0 = x;
-  *p1 = y;
+  QS_STRIDE_LOOP(u, units) {
+    const uint64_t i0 = insert_zero(u << 1, t);
+    float4* p0 = reinterpret_cast<float4*>(a + 2 * i0);
+    float4* p1 = reinterpret_cast<float4*>(a + 2 * (i0 + (uint64_t(1) << t)));
+    float4 x = *p0, y = *p1;
+    mat2_apply(m, x.x, x.y, y.x, y.y);
+    mat2_apply(m, x.z, x.w, y.z, y.w);
+    *p0 = x;
+    *p1 = y;
+  }
 }
 
 // c64, target bit 0: both amplitudes of a pair are in one 16-byte vector.
 __global__ void __launch_bounds__(kBlock) k_1q_f_bit0(float* __restrict__ a, uint64_t units,
                                                       Mat2<float> m) {
-  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (u >= units) return;
-  float4* p = reinterpret_cast<float4*>(a + 4 * u);
-  float4 x = *p;
-  mat2_apply(m, x.x, x.y, x.z, x.w);
-  *p = x;
+  QS_STRIDE_LOOP(u, units) {
+    float4* p = reinterpret_cast<float4*>(a + 4 * u);
+    float4 x = *p;
+    mat2_apply(m, x.x, x.y, x.z, x.w);
+    *p = x;
+  }
 }
 
 // c128: a unit is one pair.
 __global__ void __launch_bounds__(kBlock) k_1q_d(double* __restrict__ a, uint64_t units, int t,
                                                  Mat2<double> m) {
-  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (u >= units) return;
-  const uint64_t i0 = insert_zero(u, t);
-  double2* p0 = reinterpret_cast<double2*>(a + 2 * i0);
-  double2* p1 = reinterpret_cast<double2*>(a + 2 * (i0 + (uint64_t(1) << t)));
-  double2 x = *p0, y = *p1;
-  mat2_apply(m, x.x, x.y, y.x, y.y);
-  *p0 = x;
-  *p1 = y;
+  QS_STRIDE_LOOP(u, units) {
+    const uint64_t i0 = insert_zero(u, t);
+    double2* p0 = reinterpret_cast<double2*>(a + 2 * i0);
+    double2* p1 = reinterpret_cast<double2*>(a + 2 * (i0 + (uint64_t(1) << t)));
+    double2 x = *p0, y = *p1;
+    mat2_apply(m, x.x, x.y, y.x, y.y);
+    *p0 = x;
+    *p1 = y;
+  }
 }
 
 // ------------------------------------------------------------------ controlled
@@ -88,20 +95,20 @@ __global__ void __launch_bounds__(kBlock) k_ctrl_vec(R* __restrict__ a, uint64_t
                                                      Mat2<R> m) {
   using V = typename Vec16<R>::T;
   constexpr int AP = Vec16<R>::AMPS;
-  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (u >= units) return;
-  const uint64_t i0 = insert_zeros(u * AP, fixed) | set_mask;
-  V* p0 = reinterpret_cast<V*>(a + 2 * i0);
-  V* p1 = reinterpret_cast<V*>(a + 2 * (i0 | (uint64_t(1) << tbit)));
-  V x = *p0, y = *p1;
-  if constexpr (AP == 2) {
-    mat2_apply(m, x.x, x.y, y.x, y.y);
-    mat2_apply(m, x.z, x.w, y.z, y.w);
-  } else {
-    mat2_apply(m, x.x, x.y, y.x, y.y);
+  QS_STRIDE_LOOP(u, units) {
+    const uint64_t i0 = insert_zeros(u * AP, fixed) | set_mask;
+    V* p0 = reinterpret_cast<V*>(a + 2 * i0);
+    V* p1 = reinterpret_cast<V*>(a + 2 * (i0 | (uint64_t(1) << tbit)));
+    V x = *p0, y = *p1;
+    if constexpr (AP == 2) {
+      mat2_apply(m, x.x, x.y, y.x, y.y);
+      mat2_apply(m, x.z, x.w, y.z, y.w);
+    } else {
+      mat2_apply(m, x.x, x.y, y.x, y.y);
+    }
+    *p0 = x;
+    *p1 = y;
   }
-  *p0 = x;
-  *p1 = y;
 }
 
 // Scalar path (a fixed bit is bit 0): one pair per thread.
@@ -109,14 +116,14 @@ template <typename R>
 __global__ void __launch_bounds__(kBlock) k_ctrl_scalar(R* __restrict__ a, uint64_t units,
                                                         BitSet16 fixed, uint64_t set_mask,
                                                         int tbit, Mat2<R> m) {
-  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (u >= units) return;
-  const uint64_t i0 = insert_zeros(u, fixed) | set_mask;
-  const uint64_t i1 = i0 | (uint64_t(1) << tbit);
-  R x0r = a[2 * i0], x0i = a[2 * i0 + 1], x1r = a[2 * i1], x1i = a[2 * i1 + 1];
-  mat2_apply(m, x0r, x0i, x1r, x1i);
-  a[2 * i0] = x0r; a[2 * i0 + 1] = x0i;
-  a[2 * i1] = x1r; a[2 * i1 + 1] = x1i;
+  QS_STRIDE_LOOP(u, units) {
+    const uint64_t i0 = insert_zeros(u, fixed) | set_mask;
+    const uint64_t i1 = i0 | (uint64_t(1) << tbit);
+    R x0r = a[2 * i0], x0i = a[2 * i0 + 1], x1r = a[2 * i1], x1i = a[2 * i1 + 1];
+    mat2_apply(m, x0r, x0i, x1r, x1i);
+    a[2 * i0] = x0r; a[2 * i0 + 1] = x0i;
+    a[2 * i1] = x1r; a[2 * i1 + 1] = x1i;
+  }
 }
 
 // ------------------------------------------------------------------ phase
@@ -126,27 +133,27 @@ __global__ void __launch_bounds__(kBlock) k_cphase_vec(R* __restrict__ a, uint64
                                                        R ci) {
   using V = typename Vec16<R>::T;
   constexpr int AP = Vec16<R>::AMPS;
-  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (u >= units) return;
-  const uint64_t i = insert_zeros(u * AP, fixed) | set_mask;
-  V* p = reinterpret_cast<V*>(a + 2 * i);
-  V x = *p;
-  R t;
-  t = x.x * cr - x.y * ci; x.y = x.x * ci + x.y * cr; x.x = t;
-  if constexpr (AP == 2) { t = x.z * cr - x.w * ci; x.w = x.z * ci + x.w * cr; x.z = t; }
-  *p = x;
+  QS_STRIDE_LOOP(u, units) {
+    const uint64_t i = insert_zeros(u * AP, fixed) | set_mask;
+    V* p = reinterpret_cast<V*>(a + 2 * i);
+    V x = *p;
+    R t;
+    t = x.x * cr - x.y * ci; x.y = x.x * ci + x.y * cr; x.x = t;
+    if constexpr (AP == 2) { t = x.z * cr - x.w * ci; x.w = x.z * ci + x.w * cr; x.z = t; }
+    *p = x;
+  }
 }
 
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_cphase_scalar(R* __restrict__ a, uint64_t units,
                                                           BitSet16 fixed, uint64_t set_mask,
                                                           R cr, R ci) {
-  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (u >= units) return;
-  const uint64_t i = insert_zeros(u, fixed) | set_mask;
-  const R xr = a[2 * i], xi = a[2 * i + 1];
-  a[2 * i] = xr * cr - xi * ci;
-  a[2 * i + 1] = xr * ci + xi * cr;
+  QS_STRIDE_LOOP(u, units) {
+    const uint64_t i = insert_zeros(u, fixed) | set_mask;
+    const R xr = a[2 * i], xi = a[2 * i + 1];
+    a[2 * i] = xr * cr - xi * ci;
+    a[2 * i + 1] = xr * ci + xi * cr;
+  }
 }
 
 // ------------------------------------------------------------------ bit swap
@@ -156,28 +163,28 @@ __global__ void __launch_bounds__(kBlock) k_bitswap_vec(R* __restrict__ a, uint6
                                                         BitSet16 fixed, int lo, int hi) {
   using V = typename Vec16<R>::T;
   constexpr int AP = Vec16<R>::AMPS;
-  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (u >= units) return;
-  const uint64_t b = insert_zeros(u * AP, fixed);
-  V* p0 = reinterpret_cast<V*>(a + 2 * (b | (uint64_t(1) << lo)));
-  V* p1 = reinterpret_cast<V*>(a + 2 * (b | (uint64_t(1) << hi)));
-  const V x = *p0, y = *p1;
-  *p0 = y;
-  *p1 = x;
+  QS_STRIDE_LOOP(u, units) {
+    const uint64_t b = insert_zeros(u * AP, fixed);
+    V* p0 = reinterpret_cast<V*>(a + 2 * (b | (uint64_t(1) << lo)));
+    V* p1 = reinterpret_cast<V*>(a + 2 * (b | (uint64_t(1) << hi)));
+    const V x = *p0, y = *p1;
+    *p0 = y;
+    *p1 = x;
+  }
 }
 
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_bitswap_scalar(R* __restrict__ a, uint64_t units,
                                                            BitSet16 fixed, int lo, int hi) {
-  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (u >= units) return;
-  const uint64_t b = insert_zeros(u, fixed);
-  const uint64_t i0 = b | (uint64_t(1) << lo), i1 = b | (uint64_t(1) << hi);
-  const R xr = a[2 * i0], xi = a[2 * i0 + 1];
-  a[2 * i0] = a[2 * i1];
-  a[2 * i0 + 1] = a[2 * i1 + 1];
-  a[2 * i1] = xr;
-  a[2 * i1 + 1] = xi;
+  QS_STRIDE_LOOP(u, units) {
+    const uint64_t b = insert_zeros(u, fixed);
+    const uint64_t i0 = b | (uint64_t(1) << lo), i1 = b | (uint64_t(1) << hi);
+    const R xr = a[2 * i0], xi = a[2 * i0 + 1];
+    a[2 * i0] = a[2 * i1];
+    a[2 * i0 + 1] = a[2 * i1 + 1];
+    a[2 * i1] = xr;
+    a[2 * i1 + 1] = xi;
+  }
 }
 
 // ------------------------------------------------------------------ setup
@@ -186,26 +193,26 @@ __global__ void __launch_bounds__(kBlock) k_set_basis(R* __restrict__ a, uint64_
                                                       uint64_t x) {
   using V = typename Vec16<R>::T;
   constexpr int AP = Vec16<R>::AMPS;
-  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (u >= units) return;
-  V v{};
-  if (x / AP == u) {
-    if constexpr (AP == 2) {
-      if (x % 2 == 0) v.x = R(1); else v.z = R(1);
-    } else {
-      v.x = R(1);
+  QS_STRIDE_LOOP(u, units) {
+    V v{};
+    if (x / AP == u) {
+      if constexpr (AP == 2) {
+        if (x % 2 == 0) v.x = R(1); else v.z = R(1);
+      } else {
+        v.x = R(1);
+      }
     }
+    reinterpret_cast<V*>(a)[u] = v;
   }
-  reinterpret_cast<V*>(a)[u] = v;
 }
 
 template <typename Rd, typename Rs>
 __global__ void __launch_bounds__(kBlock) k_convert(Rd* __restrict__ d, const Rs* __restrict__ s,
                                                     uint64_t count) {
-  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (u >= count) return;
-  d[2 * u] = static_cast<Rd>(s[2 * u]);
-  d[2 * u + 1] = static_cast<Rd>(s[2 * u + 1]);
+  QS_STRIDE_LOOP(u, count) {
+    d[2 * u] = static_cast<Rd>(s[2 * u]);
+    d[2 * u + 1] = static_cast<Rd>(s[2 * u + 1]);
+  }
 }
 
 BitSet16 sorted_bits(std::initializer_list<int> bits) {

@@ -150,25 +150,27 @@ template <typename R, int G, bool REV>
 __global__ void __launch_bounds__(kBlock) k_qft_reg(R* __restrict__ a, int n, int start, int len,
                                                     int lo, int sign, R scale, Roots32<R> rt) {
   using V = typename Vec8<R>::T;
-  const uint64_t r = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (r >= (uint64_t(1) << (n - G))) return;
-  const uint64_t l = r & ((uint64_t(1) << lo) - 1);
-  const uint64_t base = ((r >> lo) << (lo + G)) | l;
-  V* p = reinterpret_cast<V*>(a) + base;
-  const uint64_t stride = uint64_t(1) << lo;
-  Cx<R> v[1 << G];
+  const uint64_t total = uint64_t(1) << (n - G);
+  for (uint64_t r = uint64_t(blockIdx.x) * kBlock + threadIdx.x; r < total;
+       r += uint64_t(gridDim.x) * kBlock) {
+    const uint64_t l = r & ((uint64_t(1) << lo) - 1);
+    const uint64_t base = ((r >> lo) << (lo + G)) | l;
+    V* p = reinterpret_cast<V*>(a) + base;
+    const uint64_t stride = uint64_t(1) << lo;
+    Cx<R> v[1 << G];
 #pragma unroll
-  for (int m = 0; m < (1 << G); ++m) {
-    const V t = p[m * stride];
-    v[m] = {t.x, t.y};
-  }
-  pass_stages<R, G, REV>(v, base, start, len, lo, sign, rt);
+    for (int m = 0; m < (1 << G); ++m) {
+      const V t = p[m * stride];
+      v[m] = {t.x, t.y};
+    }
+    pass_stages<R, G, REV>(v, base, start, len, lo, sign, rt);
 #pragma unroll
-  for (int m = 0; m < (1 << G); ++m) {
-    V t;
-    t.x = v[m].r * scale;
-    t.y = v[m].i * scale;
-    p[m * stride] = t;
+    for (int m = 0; m < (1 << G); ++m) {
+      V t;
+      t.x = v[m].r * scale;
+      t.y = v[m].i * scale;
+      p[m * stride] = t;
+    }
   }
 }
 
@@ -388,7 +390,8 @@ template <typename R, int G, bool REV>
 hipError_t launch_reg(R* a, int n, int start, int len, int lo, int sign, R scale,
                       const Roots32<R>& rt, hipStream_t s) {
   const uint64_t threads = uint64_t(1) << (n - G);
-  const unsigned grid = static_cast<unsigned>((threads + kBlock - 1) / kBlock);
+  const uint64_t want = (threads + kBlock - 1) / kBlock, cap = uint64_t(1) << 20;
+  const unsigned grid = static_cast<unsigned>(want < cap ? want : cap);
   hipLaunchKernelGGL((k_qft_reg<R, G, REV>), dim3(grid), dim3(kBlock), 0, s, a, n, start, len, lo,
                      sign, scale, rt);
   return hipGetLastError();

@@ -58,23 +58,31 @@ __global__ void __launch_bounds__(kBlock) k_sum_partials(const double* __restric
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_probs(const R* __restrict__ a, uint64_t count,
                                                   double* __restrict__ pr) {
-  const uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (u >= count) return;
-  const double re = a[2 * u], im = a[2 * u + 1];
-  pr[u] = re * re + im * im;
+  for (uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x; u < count;
+       u += uint64_t(gridDim.x) * kBlock) {
+    const double re = a[2 * u], im = a[2 * u + 1];
+    pr[u] = re * re + im * im;
+  }
 }
 
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_gather(const R* __restrict__ a,
                                                    const uint64_t* __restrict__ idx, uint64_t m,
                                                    Perm64 perm, double* __restrict__ out) {
-  const uint64_t j = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (j >= m) return;
-  const uint64_t x = idx[j];
-  uint64_t y = 0;
-  for (int q = 0; q < perm.n; ++q) y |= ((x >> q) & 1) << perm.p[q];
-  out[2 * j] = a[2 * y];
-  out[2 * j + 1] = a[2 * y + 1];
+  for (uint64_t j = uint64_t(blockIdx.x) * kBlock + threadIdx.x; j < m;
+       j += uint64_t(gridDim.x) * kBlock) {
+    const uint64_t x = idx[j];
+    uint64_t y = 0;
+    for (int q = 0; q < perm.n; ++q) y |= ((x >> q) & 1) << perm.p[q];
+    out[2 * j] = a[2 * y];
+    out[2 * j + 1] = a[2 * y + 1];
+  }
+}
+
+unsigned capped_grid(uint64_t n) {
+  const uint64_t b = (n + kBlock - 1) / kBlock;
+  const uint64_t cap = uint64_t(1) << 20;
+  return unsigned(b < cap ? (b > 0 ? b : 1) : cap);
 }
 
 }  // namespace
@@ -92,7 +100,7 @@ hipError_t launch_norm(const R* a, uint64_t count, double* partial, double* out,
 
 template <typename R>
 hipError_t launch_probs(const R* a, uint64_t count, double* pr, hipStream_t s) {
-  hipLaunchKernelGGL(k_probs<R>, dim3(unsigned((count + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL(k_probs<R>, dim3(capped_grid(count)), dim3(kBlock), 0, s,
                      a, count, pr);
   return hipGetLastError();
 }
@@ -100,7 +108,7 @@ hipError_t launch_probs(const R* a, uint64_t count, double* pr, hipStream_t s) {
 template <typename R>
 hipError_t launch_gather(const R* a, const uint64_t* idx, uint64_t m, Perm64 perm, double* out,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_gather<R>, dim3(unsigned((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL(k_gather<R>, dim3(capped_grid(m)), dim3(kBlock), 0, s,
                      a, idx, m, perm, out);
   return hipGetLastError();
 }

@@ -233,3 +233,37 @@ def test_workload_generator_shapes():
     # Haar: cos(theta) uniform on [-1, 1]
     assert abs(np.mean(np.cos(ang[:, 0]))) < 0.03
     assert abs(np.mean(np.cos(ang[:, 0]) ** 2) - 1 / 3) < 0.02
+
+
+def test_couplers_by_index_loop():
+    """CX/CY/CZ act on the target when the control is 1, AX/AY/AZ when it is 0
+    (Sec. III-C)."""
+    n = 4
+    a = workloads.gaussian_state(n, 31)
+    P = {"x": dense.X, "y": dense.Y, "z": dense.Z}
+    for kind in ("cx", "cy", "cz", "ax", "ay", "az"):
+        c, t = 3, 1
+        got = dense.apply_gate(a, n, (kind, c, t))
+        want = a.copy()
+        active = 1 if kind[0] == "c" else 0
+        for x in range(2 ** n):
+            if (x >> t) & 1 or ((x >> c) & 1) != active:
+                continue
+            x1 = x | (1 << t)
+            m = P[kind[1]]
+            want[x] = m[0, 0] * a[x] + m[0, 1] * a[x1]
+            want[x1] = m[1, 0] * a[x] + m[1, 1] * a[x1]
+        np.testing.assert_allclose(got, want, atol=1e-15)
+
+
+def test_grid_circuit_structure():
+    rows, cols, layers = 3, 4, 8
+    gates = workloads.grid_circuit(rows, cols, layers, 5)
+    n = rows * cols
+    two = [g for g in gates if g[0] != "u3"]
+    assert sum(g[0] == "u3" for g in gates) == n * layers
+    for g in two:
+        a, b = g[1], g[2]
+        ra, ca, rb, cb = a // cols, a % cols, b // cols, b % cols
+        assert abs(ra - rb) + abs(ca - cb) == 1       # nearest neighbours
+        assert g[0] in ("cx", "cy", "cz", "ax", "ay", "az")

@@ -124,3 +124,45 @@ def qft_gate_counts(n: int) -> dict:
     """Gate counts of the n-qubit QFT circuit: n H, n(n-1)/2 controlled
     phases and floor(n/2) SWAPs of the final bit reversal."""
     return {"h": n, "cp": n * (n - 1) // 2, "swap": n // 2}
+
+
+# The coupling patterns of a rows x cols grid (qubit r*cols + c): A and B are
+# the horizontal edges starting at even / odd columns, C and D the vertical
+# edges starting at even / odd rows. Layer l uses pattern "ABCDCDAB"[l % 8].
+GRID_SEQUENCE = "ABCDCDAB"
+COUPLER_KINDS = ("cx", "cy", "cz", "ax", "ay", "az")
+
+
+def grid_edges(rows: int, cols: int, pattern: str) -> list:
+    edges = []
+    if pattern in "AB":
+        start = 0 if pattern == "A" else 1
+        for r in range(rows):
+            for c in range(start, cols - 1, 2):
+                edges.append((r * cols + c, r * cols + c + 1))
+    else:
+        start = 0 if pattern == "C" else 1
+        for r in range(start, rows - 1, 2):
+            for c in range(cols):
+                edges.append((r * cols + c, (r + 1) * cols + c))
+    return edges
+
+
+def grid_circuit(rows: int, cols: int, layers: int, seed: int) -> list:
+    """Layered random circuit of the paper's family (Sec. III-C): U3 with
+    theta, phi, lambda uniform on [0, 2pi) on every qubit, then a coupler
+    drawn uniformly from CX, CY, CZ, AX, AY, AZ on every nearest-neighbour
+    edge of the layer's pattern, control and target in random order."""
+    g = rng(seed)
+    n = rows * cols
+    gates: list = []
+    for layer in range(layers):
+        ang = g.uniform(0.0, TWO_PI, (n, 3))
+        for q in range(n):
+            gates.append(("u3", q, float(ang[q, 0]), float(ang[q, 1]), float(ang[q, 2])))
+        for a, b in grid_edges(rows, cols, GRID_SEQUENCE[layer % len(GRID_SEQUENCE)]):
+            kind = COUPLER_KINDS[int(g.integers(0, len(COUPLER_KINDS)))]
+            if g.random() < 0.5:
+                a, b = b, a
+            gates.append((kind, a, b))
+    return gates
