@@ -254,6 +254,37 @@ int qs_circuit_block(const qs_circuit* c, int i, int* k, int* qubits, double* m)
  * Complex64 blocks of 4-5 qubits run on the matrix cores. */
 int qs_run(qs_state* st, qs_circuit* c);
 
+/* ------------------------------------------------------------ batches */
+
+/* Many independent small kets in one device arena, each starting in |0...0>.
+ * A batched run applies one circuit per ket pass by pass: pass p applies the
+ * p-th fused block of every circuit, with one launch per distinct block width
+ * for the whole batch. */
+typedef struct qs_batch qs_batch;
+
+/* count kets of n_each[i] qubits (1..30), dtype QS_C64 or QS_C128. */
+int qs_batch_create(int count, const int* n_each, int dtype, qs_batch** out);
+int qs_batch_free(qs_batch* b);
+/* Stream of every later launch (not owned; NULL = null stream). */
+int qs_batch_set_stream(qs_batch* b, void* hip_stream);
+/* Every ket back to |0...0> (two kernels, no memset: safe to mix with graph
+ * replays). */
+int qs_batch_reset(qs_batch* b);
+/* Run circuits[i] on ket i (asynchronous). Circuits are planned with block
+ * width kmax (1..5; 0 = 4) and may not contain SWAP gates. The work tables
+ * and block matrices are uploaded before the launches. */
+int qs_batch_run(qs_batch* b, qs_circuit* const* circuits, int kmax);
+/* Record the launches of such a run into a HIP graph on the batch's stream
+ * (must not be the null stream) without running them; qs_batch_replay then
+ * launches the graph. The graph is kept until the next run or capture. */
+int qs_batch_capture(qs_batch* b, qs_circuit* const* circuits, int kmax);
+int qs_batch_replay(qs_batch* b);
+/* Launches per run of the last prepared run and arena size in amplitudes. */
+int qs_batch_info(const qs_batch* b, int* launches, uint64_t* total_amps);
+/* The 2^n_i amplitudes of ket i (out_dtype must be the batch's). Synchronizes. */
+int qs_batch_amplitudes(qs_batch* b, int i, void* host_out, uint64_t count, int out_dtype);
+int qs_batch_synchronize(qs_batch* b);
+
 /* ------------------------------------------------------------ readout */
 
 /* All 2^n amplitudes in index order (relabelling undone), converted to

@@ -113,6 +113,16 @@ _SIGS = [
     ("qs_set_attempt_log", C.c_int, [C.c_void_p, C.POINTER(Attempt), C.c_uint64, C.POINTER(C.c_uint64)]),
     ("qs_expand", C.c_int, [C.c_void_p, C.c_void_p]),
     ("qs_inner_product", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    ("qs_batch_create", C.c_int, [C.c_int, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_void_p)]),
+    ("qs_batch_free", C.c_int, [C.c_void_p]),
+    ("qs_batch_set_stream", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("qs_batch_reset", C.c_int, [C.c_void_p]),
+    ("qs_batch_run", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_int]),
+    ("qs_batch_capture", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_int]),
+    ("qs_batch_replay", C.c_int, [C.c_void_p]),
+    ("qs_batch_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_uint64)]),
+    ("qs_batch_amplitudes", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_uint64, C.c_int]),
+    ("qs_batch_synchronize", C.c_int, [C.c_void_p]),
     ("qs_tune_set", C.c_int, [C.c_char_p, C.c_int64]),
     ("qs_tune_get", C.c_int, [C.c_char_p, C.POINTER(C.c_int64)]),
     ("qs_profile_start", C.c_int, [C.c_void_p]),
@@ -257,6 +267,68 @@ class Circuit:
         m = np.empty(2 * d * d, dtype=np.float64)
         _check(self.lib, self.lib.qs_circuit_block(self.h, i, C.byref(k), q, _dptr(m)))
         return list(q[:k.value]), m.view(np.complex128).reshape(d, d)
+
+
+class Batch:
+    """Many small kets in one device arena, run pass by pass (one launch per
+    block width per pass for the whole batch)."""
+
+    def __init__(self, widths, dtype: int = C64, stream=None):
+        import torch
+        self.lib = load()
+        self.widths = list(widths)
+        self.dtype = dtype
+        arr = (C.c_int * len(self.widths))(*self.widths)
+        h = C.c_void_p()
+        _check(self.lib, self.lib.qs_batch_create(len(self.widths), arr, dtype, C.byref(h)))
+        self.h = h
+        _live.add(self)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        _check(self.lib, self.lib.qs_batch_set_stream(self.h, C.c_void_p(self.stream.cuda_stream)))
+
+    def free(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.qs_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        if _closing:
+            return
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def _circ_array(self, circuits):
+        if len(circuits) != len(self.widths):
+            raise ValueError("one circuit per ket")
+        self._keep = list(circuits)
+        return (C.c_void_p * len(circuits))(*[c.h.value for c in circuits])
+
+    def reset(self):
+        _check(self.lib, self.lib.qs_batch_reset(self.h))
+
+    def run(self, circuits, kmax: int = 0):
+        _check(self.lib, self.lib.qs_batch_run(self.h, self._circ_array(circuits), kmax))
+
+    def capture(self, circuits, kmax: int = 0):
+        _check(self.lib, self.lib.qs_batch_capture(self.h, self._circ_array(circuits), kmax))
+
+    def replay(self):
+        _check(self.lib, self.lib.qs_batch_replay(self.h))
+
+    def synchronize(self):
+        _check(self.lib, self.lib.qs_batch_synchronize(self.h))
+
+    def info(self) -> dict:
+        n, t = C.c_int(), C.c_uint64()
+        _check(self.lib, self.lib.qs_batch_info(self.h, C.byref(n), C.byref(t)))
+        return {"launches": n.value, "total_amps": t.value}
+
+    def amplitudes(self, i: int) -> np.ndarray:
+        out = np.empty(2 ** self.widths[i], dtype=np.complex64 if self.dtype == C64 else np.complex128)
+        _check(self.lib, self.lib.qs_batch_amplitudes(self.h, i, out.ctypes.data, out.size, self.dtype))
+        return out
 
 
 def tune_set(key: str, value: int):

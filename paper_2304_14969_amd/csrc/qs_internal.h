@@ -63,6 +63,25 @@ bool fused_geometry(int n, const int* qubits, int k, FusedGeom* g);
 hipError_t launch_fused_mfma(float* amps, int n, const int* qubits, int k, const float* mat,
                              hipStream_t s);
 
+// ---------------------------------------------------------------- batches
+// One item of a batched launch: block (q, row bit order; sorted ascending) on
+// the ket at amplitude offset amp_off of the arena; its tiles of 256 groups
+// start at first_tile; its matrix at complex offset mat_off.
+struct BatchItem {
+  uint64_t amp_off;
+  uint64_t first_tile;
+  uint64_t mat_off;
+  int n, k;
+  int q[6];
+  int sorted[6];
+};
+template <typename R>
+hipError_t launch_batch_fused(R* arena, const BatchItem* items, int nitems, uint64_t tiles, int k,
+                              const R* mats, hipStream_t s);
+template <typename R>
+hipError_t launch_batch_reset(R* arena, uint64_t total_amps, const uint64_t* offs, int count,
+                              hipStream_t s);
+
 // ---------------------------------------------------------------- factorized mode
 // scratch: factor_scratch_doubles() doubles of device memory; results land in
 // scratch[0..3] (bloch: Re s, Im s, z0, z1; inner: Re, Im).
