@@ -207,6 +207,55 @@ int qs_expand(qs_state* factorized, qs_state* dense);
  * accumulation in a fixed order (for Eq. fid_exact). Synchronizes. */
 int qs_inner_product(qs_state* a, qs_state* b, double* re, double* im);
 
+/* ------------------------------------------------------------ learned proposal */
+
+/* A small network scores which dirty qubits to test: 32 features per qubit
+ * -> 64 (tanh) -> 64 (tanh) -> 1 logit, score = sigmoid(logit), float32 on
+ * the GPU. Parameters: W1[32][64], b1[64], W2[64][64], b2[64], W3[64], b3,
+ * row-major with x @ W + b (6,337 floats). Training minimizes the mean
+ * binary cross-entropy with Adam, on the GPU. */
+#define QS_MLP_INPUTS 32
+#define QS_MLP_PARAMS 6337
+typedef struct qs_mlp qs_mlp;
+typedef struct {
+  uint32_t steps;   /* Adam steps */
+  uint32_t batch;   /* rows per step (0 = 256); consecutive rows, wrapping */
+  float lr, beta1, beta2, eps;
+} qs_train_cfg;
+
+int qs_mlp_create(qs_mlp** out);  /* all parameters zero */
+int qs_mlp_free(qs_mlp* net);
+int qs_mlp_set_stream(qs_mlp* net, void* hip_stream);
+int qs_mlp_set_params(qs_mlp* net, const float* host, uint64_t count);
+int qs_mlp_get_params(qs_mlp* net, float* host, uint64_t count);
+/* scores[r] = sigmoid(logit of row r of X (rows x 32)). Synchronizes. */
+int qs_mlp_forward(qs_mlp* net, const float* X, uint64_t rows, float* scores);
+/* Gradient of the mean cross-entropy of (X, y) w.r.t. the parameters (same
+ * layout as the parameters) and the loss. Synchronizes. */
+int qs_mlp_grad(qs_mlp* net, const float* X, const float* y, uint64_t rows, float* grad,
+                double* loss);
+/* cfg->steps Adam steps on minibatches of consecutive rows (the caller
+ * shuffles); *final_loss = mean loss over all rows afterwards. */
+int qs_mlp_train(qs_mlp* net, const float* X, const float* y, uint64_t rows,
+                 const qs_train_cfg* cfg, double* final_loss);
+
+/* Use `net` to choose which dirty qubits of a factorized state to test: every
+ * dirty qubit is scored from its features (qs_features layout); only those
+ * scoring >= cutoff get the exact Schmidt test, which alone decides any
+ * rounding (the fidelity estimate keeps the plain rule). Skipped qubits are
+ * deferred; before a merge that would exceed the amplitude cap, every
+ * deferred qubit gets the exact test. NULL restores the plain schedule. The
+ * network must outlive its use. */
+int qs_set_proposer(qs_state* st, qs_mlp* net, double cutoff);
+
+/* Features recorded with each attempt (rows of QS_MLP_INPUTS floats aligned
+ * with the attempt log): caller-owned buffer of cap rows; NULL stops. */
+int qs_set_feature_log(qs_state* st, float* buf, uint64_t cap);
+
+/* Number of exact tests skipped on the network's advice and of deferred
+ * qubits tested by the capacity fallback, since the state was created. */
+int qs_proposer_stats(const qs_state* st, uint64_t* skipped, uint64_t* fallback_tests);
+
 /* ------------------------------------------------------------ circuits */
 
 /* A circuit is a host-side gate list on n qubits that is fused into dense

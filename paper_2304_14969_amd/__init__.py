@@ -63,6 +63,11 @@ class Attempt(C.Structure):
                 ("rounded", C.c_int32), ("reserved", C.c_int32)]
 
 
+class TrainCfg(C.Structure):
+    _fields_ = [("steps", C.c_uint32), ("batch", C.c_uint32), ("lr", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
+
+
 class KernelStat(C.Structure):
     _fields_ = [("name", C.c_char * 48), ("launches", C.c_uint64), ("total_ms", C.c_double),
                 ("bytes", C.c_double)]
@@ -123,6 +128,19 @@ _SIGS = [
     ("qs_batch_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_uint64)]),
     ("qs_batch_amplitudes", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_uint64, C.c_int]),
     ("qs_batch_synchronize", C.c_int, [C.c_void_p]),
+    ("qs_mlp_create", C.c_int, [C.POINTER(C.c_void_p)]),
+    ("qs_mlp_free", C.c_int, [C.c_void_p]),
+    ("qs_mlp_set_stream", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("qs_mlp_set_params", C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.c_uint64]),
+    ("qs_mlp_get_params", C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.c_uint64]),
+    ("qs_mlp_forward", C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.c_uint64, C.POINTER(C.c_float)]),
+    ("qs_mlp_grad", C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_uint64,
+                              C.POINTER(C.c_float), C.POINTER(C.c_double)]),
+    ("qs_mlp_train", C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_uint64,
+                               C.POINTER(TrainCfg), C.POINTER(C.c_double)]),
+    ("qs_set_proposer", C.c_int, [C.c_void_p, C.c_void_p, C.c_double]),
+    ("qs_set_feature_log", C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.c_uint64]),
+    ("qs_proposer_stats", C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     ("qs_tune_set", C.c_int, [C.c_char_p, C.c_int64]),
     ("qs_tune_get", C.c_int, [C.c_char_p, C.POINTER(C.c_int64)]),
     ("qs_profile_start", C.c_int, [C.c_void_p]),
@@ -331,6 +349,85 @@ class Batch:
         return out
 
 
+MLP_INPUTS, MLP_PARAMS = 32, 6337
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class MLP:
+    """The separability-proposal network (parameters on the GPU)."""
+
+    def __init__(self, params=None, stream=None):
+        import torch
+        self.lib = load()
+        h = C.c_void_p()
+        _check(self.lib, self.lib.qs_mlp_create(C.byref(h)))
+        self.h = h
+        _live.add(self)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(self.lib, self.lib.qs_mlp_set_stream(self.h, C.c_void_p(s.cuda_stream)))
+        if params is not None:
+            self.set_params(params)
+
+    def free(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.qs_mlp_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        if _closing:
+            return
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def set_params(self, vec):
+        v = np.ascontiguousarray(np.asarray(vec, dtype=np.float32).reshape(-1))
+        if v.size != MLP_PARAMS:
+            raise ValueError("wrong parameter count")
+        _check(self.lib, self.lib.qs_mlp_set_params(self.h, _fptr(v), v.size))
+
+    def get_params(self) -> np.ndarray:
+        v = np.empty(MLP_PARAMS, dtype=np.float32)
+        _check(self.lib, self.lib.qs_mlp_get_params(self.h, _fptr(v), v.size))
+        return v
+
+    @staticmethod
+    def _rows(X):
+        X = np.ascontiguousarray(np.asarray(X, dtype=np.float32))
+        if X.ndim != 2 or X.shape[1] != MLP_INPUTS:
+            raise ValueError("rows of 32 features expected")
+        return X
+
+    def forward(self, X) -> np.ndarray:
+        X = self._rows(X)
+        out = np.empty(X.shape[0], dtype=np.float32)
+        _check(self.lib, self.lib.qs_mlp_forward(self.h, _fptr(X), X.shape[0], _fptr(out)))
+        return out
+
+    def grad(self, X, y):
+        X = self._rows(X)
+        y = np.ascontiguousarray(np.asarray(y, dtype=np.float32).reshape(-1))
+        g = np.empty(MLP_PARAMS, dtype=np.float32)
+        loss = C.c_double()
+        _check(self.lib, self.lib.qs_mlp_grad(self.h, _fptr(X), _fptr(y), X.shape[0], _fptr(g),
+                                              C.byref(loss)))
+        return g, loss.value
+
+    def train(self, X, y, steps: int, batch: int = 256, lr: float = 1e-3, beta1: float = 0.9,
+              beta2: float = 0.999, eps: float = 1e-8) -> float:
+        X = self._rows(X)
+        y = np.ascontiguousarray(np.asarray(y, dtype=np.float32).reshape(-1))
+        cfg = TrainCfg(steps, batch, lr, beta1, beta2, eps)
+        loss = C.c_double()
+        _check(self.lib, self.lib.qs_mlp_train(self.h, _fptr(X), _fptr(y), X.shape[0], C.byref(cfg),
+                                               C.byref(loss)))
+        return loss.value
+
+
 def tune_set(key: str, value: int):
     lib = load()
     _check(lib, lib.qs_tune_set(key.encode(), int(value)))
@@ -502,6 +599,26 @@ class State:
     def attempts(self) -> list:
         n = min(self._log_count.value, len(self._log)) if self._log is not None else 0
         return [(a.qubit, a.n_sub, a.eps, bool(a.rounded)) for a in self._log[:n]]
+
+    def record_features(self, cap: int = 1 << 20):
+        """Record the 32 proposal features of every attempt (call after
+        record_attempts; rows align with attempts())."""
+        self._feat = np.zeros((cap, MLP_INPUTS), dtype=np.float32)
+        _check(self.lib, self.lib.qs_set_feature_log(self.h, _fptr(self._feat), cap))
+
+    def features(self) -> np.ndarray:
+        n = min(self._log_count.value, len(self._feat))
+        return self._feat[:n].copy()
+
+    def set_proposer(self, net: "MLP | None", cutoff: float = 0.5):
+        self._proposer = net
+        _check(self.lib, self.lib.qs_set_proposer(self.h, net.h if net is not None else None,
+                                                  float(cutoff)))
+
+    def proposer_stats(self) -> dict:
+        a, b = C.c_uint64(), C.c_uint64()
+        _check(self.lib, self.lib.qs_proposer_stats(self.h, C.byref(a), C.byref(b)))
+        return {"skipped": a.value, "fallback_tests": b.value}
 
     def expand_into(self, dense: "State"):
         _check(self.lib, self.lib.qs_expand(self.h, dense.h))

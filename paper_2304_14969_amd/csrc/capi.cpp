@@ -825,6 +825,34 @@ int qs_inner_product(qs_state* a, qs_state* b, double* re, double* im) {
   return device_error(a, e, "inner product");
 }
 
+int qs_set_proposer(qs_state* st, qs_mlp* net, double cutoff) {
+  if (int rc = check_state(st)) return rc;
+  if (!st->fact) return fail(QS_E_UNSUPPORTED, "proposals apply to factorized states");
+  if (!(cutoff >= 0.0 && cutoff <= 1.0)) return fail(QS_E_INVAL, "cutoff %g outside [0, 1]", cutoff);
+  st->fact->proposer = net;
+  st->fact->cutoff = cutoff;
+  if (!net) {
+    st->fact->dirty |= st->fact->deferred;
+    st->fact->deferred = 0;
+  }
+  return QS_OK;
+}
+
+int qs_set_feature_log(qs_state* st, float* buf, uint64_t cap) {
+  if (int rc = check_state(st)) return rc;
+  if (!st->fact) return fail(QS_E_UNSUPPORTED, "features belong to factorized states");
+  st->fact->feat_log = buf;
+  st->fact->feat_cap = buf ? cap : 0;
+  return QS_OK;
+}
+
+int qs_proposer_stats(const qs_state* st, uint64_t* skipped, uint64_t* fallback_tests) {
+  if (!st) return fail(QS_E_INVAL, "state is NULL");
+  if (skipped) *skipped = st->fact ? st->fact->skipped : 0;
+  if (fallback_tests) *fallback_tests = st->fact ? st->fact->fallback_tests : 0;
+  return QS_OK;
+}
+
 // ------------------------------------------------------------------ profiling
 
 int qs_profile_start(qs_state* st) {

@@ -26,6 +26,7 @@
 #include <cstring>
 
 #include "factor.h"
+#include "mlp.h"
 #include "qs_internal.h"
 
 namespace qs {
@@ -33,6 +34,7 @@ namespace qs {
 void* device_alloc(size_t bytes);
 void device_free(void* p);
 void set_last_error(const char* msg);
+void note_test_impl(FactorState* f, int q, double eps, bool rounded);
 
 namespace {
 
@@ -137,11 +139,15 @@ int merge(FactorState* f, int ia, int ib, int* out) {
 int test_qubit(FactorState* f, int q, double p, bool* rounded) {
   *rounded = false;
   f->dirty &= ~(uint64_t(1) << q);
+  f->deferred &= ~(uint64_t(1) << q);
   int t = 0;
   const int si = find(f, q, &t);
   if (si < 0) return ffail(QS_E_INVAL, "qubit %d not found", q);
+  if (f->subs[si].nq == 1) return QS_OK;
+  // features as seen before the test, aligned with the attempt log
+  if (f->feat_log && f->log_count && *f->log_count < f->feat_cap)
+    fact_features(f, q, p, f->feat_log + *f->log_count * QS_MLP_INPUTS);
   Sub& S = f->subs[si];
-  if (S.nq == 1) return QS_OK;
   hipError_t e = f->dtype == QS_C64
                      ? launch_bloch(static_cast<const float*>(S.amps), S.nq, t, f->scratch, f->stream)
                      : launch_bloch(static_cast<const double*>(S.amps), S.nq, t, f->scratch, f->stream);
@@ -158,6 +164,7 @@ int test_qubit(FactorState* f, int q, double p, bool* rounded) {
   const double eps = std::min(std::max((1.0 - rn) / 2.0, 0.0), 0.5);
   if (!(eps <= p / 2.0 + f->tau)) {
     log_attempt(f, q, S.nq, eps, false);
+    note_test_impl(f, q, eps, false);
     return QS_OK;
   }
   // dominant eigenvector phi of rho_q, phi_0 real >= 0 (steps 3-4)
@@ -200,14 +207,118 @@ int test_qubit(FactorState* f, int q, double p, bool* rounded) {
   f->subs.push_back(single);
   f->F *= (1.0 - eps);
   log_attempt(f, q, nsub, eps, true);
+  note_test_impl(f, q, eps, true);
   *rounded = true;
   return QS_OK;
 }
 
+// Plain schedule: the lowest-numbered dirty qubit until none is dirty.
+int plain_separate(FactorState* f, double p, int* count) {
+  while (f->dirty) {
+    const int q = __builtin_ctzll(f->dirty);
+    bool rounded = false;
+    if (int rc = test_qubit(f, q, p, &rounded)) return rc;
+    *count += rounded;
+  }
+  return QS_OK;
+}
+
+// Learned schedule: score every dirty qubit in one forward pass, test the
+// proposals (ascending), defer the rest; repeat for qubits made dirty by a
+// rounding.
+int proposed_separate(FactorState* f, double p, int* count) {
+  std::vector<int> cand;
+  std::vector<float> X, score;
+  while (f->dirty) {
+    cand.clear();
+    for (uint64_t d = f->dirty; d; d &= d - 1) cand.push_back(__builtin_ctzll(d));
+    X.assign(cand.size() * QS_MLP_INPUTS, 0.0f);
+    for (size_t i = 0; i < cand.size(); ++i) fact_features(f, cand[i], p, &X[i * QS_MLP_INPUTS]);
+    score.assign(cand.size(), 0.0f);
+    if (int rc = mlp_scores(f->proposer, X.data(), cand.size(), score.data())) return rc;
+    for (size_t i = 0; i < cand.size(); ++i) {
+      const int q = cand[i];
+      if (!((f->dirty >> q) & 1)) continue;
+      if (score[i] >= f->cutoff) {
+        bool rounded = false;
+        if (int rc = test_qubit(f, q, p, &rounded)) return rc;
+        *count += rounded;
+      } else {
+        f->dirty &= ~(uint64_t(1) << q);
+        f->deferred |= uint64_t(1) << q;
+        ++f->skipped;
+      }
+    }
+  }
+  return QS_OK;
+}
+
+// Bookkeeping of one exact test (features of later proposals).
 }  // namespace
+
+void note_test_impl(FactorState* f, int q, double eps, bool rounded) {
+  f->eps_prev[q] = f->eps_last[q];
+  f->eps_last[q] = eps;
+  f->rounded_last[q] = rounded ? 1 : 0;
+  f->tests[q] += 1;
+  f->gates_since[q] = 0;
+  f->recent[f->recent_n % 8] = rounded ? 1 : 0;
+  f->recent_n += 1;
+  f->recent_eps = eps;
+}
+
+void fact_features(const FactorState* f, int q, double p, float* x) {
+  for (int i = 0; i < QS_MLP_INPUTS; ++i) x[i] = 0.0f;
+  auto eps_or = [](double e) { return e < 0.0 ? 0.5 : e; };
+  auto purity = [](double e) { const double r = 1.0 - 2.0 * e; return 0.5 * (1.0 + r * r); };
+  int ns = 1, nsub = int(f->subs.size()), largest = 1;
+  for (const auto& s : f->subs) {
+    largest = std::max(largest, s.nq);
+    for (int t = 0; t < s.nq; ++t)
+      if (s.q[t] == q) ns = s.nq;
+  }
+  const double el = eps_or(f->eps_last[q]), ep = eps_or(f->eps_prev[q]);
+  const int pq = f->partner[q];
+  int pns = 0;
+  if (pq >= 0)
+    for (const auto& s : f->subs)
+      for (int t = 0; t < s.nq; ++t)
+        if (s.q[t] == pq) pns = s.nq;
+  int rec = 0;
+  const int nrec = std::min(f->recent_n, 8);
+  for (int i = 0; i < nrec; ++i) rec += f->recent[i];
+  x[0] = float(ns / 32.0);
+  x[1] = float(std::log2(double(ns)) / 6.0);
+  x[2] = float(p);
+  x[3] = float(el);                      // Bloch length |r| = 1 - 2 eps
+  x[4] = float(ep);
+  x[5] = float(purity(el));              // purity of the reduced state
+  x[6] = float(purity(ep));
+  x[7] = float(f->rounded_last[q]);
+  x[8] = float(std::min(f->gates_since[q], 8) / 8.0);
+  x[9] = float(std::min(f->tests[q], 32) / 32.0);
+  x[10] = float(pq >= 0 ? eps_or(f->eps_last[pq]) : 0.5);
+  x[11] = float(purity(x[10]));
+  x[12] = float(pns / 32.0);
+  x[13] = float(f->merged_last[q]);
+  x[14] = float(nrec ? double(rec) / nrec : 0.0);
+  x[15] = float(eps_or(f->recent_eps));
+  x[16] = float(double(nsub) / f->n);
+  x[17] = float(largest / 32.0);
+  x[18] = float(el - p / 2.0);
+  x[19] = f->tests[q] == 0 ? 1.0f : 0.0f;
+  x[20] = float(std::min<uint64_t>(f->gate_count, 2000) / 2000.0);
+}
 
 int fact_init(FactorState* f) {
   f->subs.clear();
+  f->eps_last.assign(f->n, -1.0);
+  f->eps_prev.assign(f->n, -1.0);
+  f->rounded_last.assign(f->n, 0);
+  f->tests.assign(f->n, 0);
+  f->gates_since.assign(f->n, 0);
+  f->partner.assign(f->n, -1);
+  f->merged_last.assign(f->n, 0);
   for (int q = 0; q < f->n; ++q) {
     const double zero[4] = {1.0, 0.0, 0.0, 0.0};
     Sub s;
@@ -238,6 +349,14 @@ int fact_set_basis(FactorState* f, uint64_t x) {
   }
   f->F = 1.0;
   f->dirty = 0;
+  f->deferred = 0;
+  f->eps_last.assign(f->n, -1.0);
+  f->eps_prev.assign(f->n, -1.0);
+  f->rounded_last.assign(f->n, 0);
+  f->tests.assign(f->n, 0);
+  f->gates_since.assign(f->n, 0);
+  f->partner.assign(f->n, -1);
+  f->merged_last.assign(f->n, 0);
   return dev_err(hipStreamSynchronize(f->stream), "set basis");
 }
 
@@ -258,9 +377,36 @@ int fact_apply(FactorState* f, const int* qubits, int k, const double* m) {
       total += f->subs[s].nq;
     }
   }
+  if ((total >= 63 || (uint64_t(1) << total) > f->max_amps) && f->deferred) {
+    // exhaustive fallback: exact tests of every qubit the proposer skipped
+    // may shrink the subsystems enough for the merge
+    f->fallback_tests += uint64_t(__builtin_popcountll(f->deferred));
+    f->dirty |= f->deferred;
+    f->deferred = 0;
+    int nsep = 0;
+    if (int rc = plain_separate(f, f->p, &nsep)) return rc;
+    nd = 0;
+    total = 0;
+    for (int j = 0; j < k; ++j) {
+      const int s = find(f, qubits[j], nullptr);
+      if (std::find(distinct, distinct + nd, s) == distinct + nd) {
+        distinct[nd++] = s;
+        total += f->subs[s].nq;
+      }
+    }
+  }
   if (total >= 63 || (uint64_t(1) << total) > f->max_amps)
     return ffail(QS_E_CAPACITY, "gate needs a %d-qubit subsystem (cap %llu amplitudes)", total,
                  (unsigned long long)f->max_amps);
+  // bookkeeping for the proposal features
+  if (k >= 2) {
+    ++f->gate_count;
+    for (int j = 0; j < k; ++j) {
+      f->gates_since[qubits[j]] += 1;
+      f->partner[qubits[j]] = qubits[j == 0 ? 1 : 0];
+      f->merged_last[qubits[j]] = nd > 1 ? 1 : 0;
+    }
+  }
   // merge every subsystem into the first operand's
   int si = find(f, qubits[0], nullptr);
   for (int j = 1; j < k; ++j) {
@@ -311,34 +457,55 @@ int fact_swap(FactorState* f, int a, int b) {
       if (s.q[t] == a) s.q[t] = b;
       else if (s.q[t] == b) s.q[t] = a;
     }
-  const uint64_t da = (f->dirty >> a) & 1, db = (f->dirty >> b) & 1;
-  f->dirty &= ~((uint64_t(1) << a) | (uint64_t(1) << b));
-  f->dirty |= (da << b) | (db << a);
+  for (uint64_t* mask : {&f->dirty, &f->deferred}) {
+    const uint64_t da = (*mask >> a) & 1, db = (*mask >> b) & 1;
+    *mask &= ~((uint64_t(1) << a) | (uint64_t(1) << b));
+    *mask |= (da << b) | (db << a);
+  }
+  std::swap(f->eps_last[a], f->eps_last[b]);
+  std::swap(f->eps_prev[a], f->eps_prev[b]);
+  std::swap(f->rounded_last[a], f->rounded_last[b]);
+  std::swap(f->tests[a], f->tests[b]);
+  std::swap(f->gates_since[a], f->gates_since[b]);
+  std::swap(f->merged_last[a], f->merged_last[b]);
+  std::swap(f->partner[a], f->partner[b]);
+  for (int& pq : f->partner) pq = pq == a ? b : (pq == b ? a : pq);
   return QS_OK;
 }
 
 int fact_relabel(FactorState* f, const int* pos) {
   int inv[64];
   for (int q = 0; q < f->n; ++q) inv[pos[q]] = q;
-  uint64_t nd = 0;
-  for (int q = 0; q < f->n; ++q)
+  uint64_t nd = 0, nf = 0;
+  for (int q = 0; q < f->n; ++q) {
     if ((f->dirty >> pos[q]) & 1) nd |= uint64_t(1) << q;
+    if ((f->deferred >> pos[q]) & 1) nf |= uint64_t(1) << q;
+  }
   for (auto& s : f->subs)
     for (int t = 0; t < s.nq; ++t) s.q[t] = inv[s.q[t]];
   f->dirty = nd;
+  f->deferred = nf;
+  // per-qubit history follows its qubit: label v becomes inv[v]
+  auto moved = [&](auto& v) {
+    auto old = v;
+    for (int q = 0; q < f->n; ++q) v[q] = old[pos[q]];
+  };
+  moved(f->eps_last);
+  moved(f->eps_prev);
+  moved(f->rounded_last);
+  moved(f->tests);
+  moved(f->gates_since);
+  moved(f->merged_last);
+  moved(f->partner);
+  for (int& pq : f->partner) pq = pq >= 0 ? inv[pq] : pq;
   return QS_OK;
 }
 
 int fact_try_separate(FactorState* f, double p, int* n_separated) {
   int count = 0;
-  while (f->dirty) {
-    const int q = __builtin_ctzll(f->dirty);
-    bool rounded = false;
-    if (int rc = test_qubit(f, q, p, &rounded)) return rc;
-    count += rounded;
-  }
+  const int rc = f->proposer ? proposed_separate(f, p, &count) : plain_separate(f, p, &count);
   if (n_separated) *n_separated = count;
-  return QS_OK;
+  return rc;
 }
 
 int fact_gather(FactorState* f, const uint64_t* idx, uint64_t m, double* out) {

@@ -33,7 +33,24 @@ struct FactorState {
   uint64_t* log_count = nullptr;
   double* scratch = nullptr;  // device reduction scratch
   void* mat = nullptr;        // device slot for one gate matrix
+  // bookkeeping behind the proposal features (host only, no state sweeps)
+  std::vector<double> eps_last, eps_prev;  // last two measured eps (-1: none)
+  std::vector<int> rounded_last, tests, gates_since, partner, merged_last;
+  int recent[8] = {0};
+  int recent_n = 0;
+  double recent_eps = -1.0;
+  uint64_t gate_count = 0;
+  // learned proposal
+  qs_mlp* proposer = nullptr;
+  double cutoff = 0.5;
+  uint64_t deferred = 0;        // dirty qubits skipped on the network's advice
+  uint64_t skipped = 0, fallback_tests = 0;
+  float* feat_log = nullptr;
+  uint64_t feat_cap = 0;
 };
+
+// The 32 proposal features of qubit q (threshold p) from the bookkeeping.
+void fact_features(const FactorState* f, int q, double p, float* out);
 
 // All return QS_* status codes and set the thread's error message.
 int fact_init(FactorState* f);                     // n one-qubit |0> subsystems

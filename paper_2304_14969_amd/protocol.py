@@ -14,15 +14,23 @@ from . import C64, SEP_AFTER_2Q, CapacityError, Circuit, State
 
 
 def approx_run(n: int, gates, p: float, max_amps: int = 2 ** 30, dtype: int = C64,
-               record: bool = False, keep: bool = False) -> dict:
+               record: bool = False, keep: bool = False, features: bool = False,
+               proposer=None, cutoff: float = 0.5) -> dict:
     """One run; returns completion, time, fidelity estimate and table stats.
-    With keep=True the state is returned under "state" (caller frees it)."""
+    With keep=True the state is returned under "state" (caller frees it).
+    features=True also returns the proposal features of every attempt;
+    proposer= runs the learned schedule."""
     import torch
 
     st = State(n, dtype, factorized=True, max_amps=max_amps)
     st.set_policy(SEP_AFTER_2Q, p)
-    if record:
+    if record or features:
+        record = True
         st.record_attempts()
+    if features:
+        st.record_features()
+    if proposer is not None:
+        st.set_proposer(proposer, cutoff)
     circ = Circuit(n).add_gates(gates)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -41,6 +49,10 @@ def approx_run(n: int, gates, p: float, max_amps: int = 2 ** 30, dtype: int = C6
         out["attempts"] = len(att)
         out["roundings"] = sum(a[3] for a in att)
         out["log"] = att
+    if features:
+        out["features"] = st.features()
+    if proposer is not None:
+        out.update(st.proposer_stats())
     circ.free()
     if keep:
         out["state"] = st
