@@ -56,6 +56,161 @@ def cpu_baseline(n: int) -> dict:
                        f"{counts['swap']} SWAP; numpy/BLAS limited to 1 thread")}
 
 
+def _kernel_rates(prof: dict, flops_of=None) -> dict:
+    out = {}
+    for k, v in prof.items():
+        avg = v["total_ms"] / v["launches"]
+        row = {"launches": v["launches"], "avg_ms": round(avg, 4),
+               "GBps": round(v["bytes"] / v["launches"] / (avg * 1e-3) / 1e9, 1)}
+        if flops_of is not None and flops_of(k):
+            row["TFLOPs"] = round(flops_of(k) / (avg * 1e-3) / 1e12, 2)
+        out[k] = row
+    return out
+
+
+def bench_circuit(qs, workloads, torch, n: int = 32, layers: int = 10, seed: int = 0,
+                  kmax: int = 4) -> dict:
+    """Exact random circuit (U3 on every qubit, then CZ/iSWAP on a random
+    matching, per layer) fused into blocks of at most kmax qubits."""
+    st = qs.State(n, qs.C64)
+    c = qs.Circuit(n).add_gates(workloads.random_circuit(n, layers, seed)).plan(kmax)
+    st.run(c)
+    torch.cuda.synchronize()
+    st.set_basis(0)
+    st.profile_start()
+    t0 = time.perf_counter()
+    st.run(c)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = st.profile_stop()
+    norm = st.norm()
+    st.free()
+    info = c.info()
+    c.free()
+
+    def flops(name):  # complex (2^k x 2^k) times 2^n amplitudes, 8 real flops per MAC
+        for k in (4, 5):
+            if name.startswith(f"fused{k}_mfma"):
+                return 8.0 * 2 ** k * 2 ** n
+        return 0.0
+    return {"workload": f"random circuit n={n}, {layers} layers (U3 + CZ/iSWAP matching), "
+                        f"seed {seed}, complex64, blocks of <= {kmax} qubits",
+            "s": round(dt, 4), "gates": info["gates"], "sweeps": info["blocks"],
+            "norm_after": norm, "kernels": _kernel_rates(prof, flops)}
+
+
+def bench_approx(qs, workloads, protocol, np, family: str, p_cmp: float = 0.6,
+                 test_seeds=range(10), train_seeds=range(10000, 10060),
+                 train_ps=(0.7, 0.6, 0.5), min_qubits: int = 2) -> dict:
+    """54-qubit, 7-layer approximate runs: the paper's descending-p search,
+    then plain vs learned schedule at one threshold on held-out circuits."""
+    if family == "grid":
+        gen = lambda s: workloads.grid_circuit(6, 9, 7, s)  # noqa: E731
+        desc = "6x9 grid, U3 + nearest-neighbour couplers in the ABCDCDAB pattern, 7 layers"
+    else:
+        gen = lambda s: workloads.random_circuit(54, 7, s)  # noqa: E731
+        desc = "54 qubits, U3 + CZ/iSWAP on a random matching, 7 layers"
+    out = {"workload": desc + ", complex64, cap 2^30 amplitudes"}
+    search = []
+    for s in list(test_seeds)[:3]:
+        r = protocol.minimum_p(54, gen(s))
+        b = r["best"]
+        search.append({"seed": s, "p_min": b and b["p"], "F": b and b["F"],
+                       "run_s": b and round(b["time_s"], 4), "max_sub": b and b["max_sub"],
+                       "runs": r["runs"], "search_s": round(r["search_time_s"], 3)})
+    out["minimum_p"] = search
+    t0 = time.perf_counter()
+    X, y = protocol.collect_attempts(54, [gen(s) for s in train_seeds], train_ps)
+    net, cutoff, loss = protocol.train_proposer(X, y, recall=0.97)
+    out["training"] = {"rows": int(len(y)), "positive": round(float(y.mean()), 4),
+                       "loss": round(loss, 4), "cutoff": round(cutoff, 4),
+                       "collect_and_train_s": round(time.perf_counter() - t0, 2)}
+    rows = {"plain": [], "learned": []}
+    for s in test_seeds:
+        g = gen(s)
+        rows["plain"].append(protocol.approx_run(54, g, p_cmp, record=True))
+        rows["learned"].append(protocol.approx_run(54, g, p_cmp, record=True, proposer=net,
+                                                   cutoff=cutoff, min_qubits=min_qubits))
+    net.free()
+    cmp = {}
+    for k, rs in rows.items():
+        ok = [r for r in rs if r["ok"]]
+        cmp[k] = {"completed": len(ok), "of": len(rs),
+                  "time_s_mean": round(sum(r["time_s"] for r in rs) / len(rs), 4),
+                  "logF_mean": round(float(np.mean([np.log(r["F"]) for r in ok])), 3) if ok else None,
+                  "exact_tests": sum(r["attempts"] for r in rs),
+                  "roundings": sum(r["roundings"] for r in rs)}
+    cmp["p"] = p_cmp
+    cmp["learned_rule_violations"] = sum(1 for r in rows["learned"] for a in r["log"]
+                                         if a[3] and a[2] > p_cmp / 2 + 1e-6)
+    out["plain_vs_learned"] = cmp
+    return out
+
+
+def bench_batch(qs, workloads, torch, count: int = 1024, seed: int = 300, depth: int = 8) -> dict:
+    """Many small random circuits (12-20 qubits) in one arena: batched launches,
+    the same as a replayed HIP graph, and one state at a time."""
+    widths = workloads.batch_widths(count, seed)
+    circs = [qs.Circuit(n).add_gates(workloads.random_circuit(n, depth, seed * 1000 + i))
+             for i, n in enumerate(widths)]
+    b = qs.Batch(widths, qs.C64, stream=torch.cuda.Stream())  # capture needs its own stream
+    b.run(circs, 4)
+    b.synchronize()
+    t0 = time.perf_counter()
+    b.reset()
+    b.run(circs, 4)
+    b.synchronize()
+    t_run = time.perf_counter() - t0
+    b.capture(circs, 4)
+    b.reset()
+    b.replay()
+    b.synchronize()
+    t0 = time.perf_counter()
+    b.reset()
+    b.replay()
+    b.synchronize()
+    t_graph = time.perf_counter() - t0
+    info = b.info()
+    b.free()
+    for c in circs:
+        c.plan(4)
+    t0 = time.perf_counter()
+    for n, c in zip(widths, circs):
+        st = qs.State(n, qs.C64)
+        st.run(c)
+        st.free()
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - t0
+    for c in circs:
+        c.free()
+    return {"workload": f"{count} random circuits of 12-20 qubits, depth {depth}, complex64",
+            "total_amps": info["total_amps"], "launches": info["launches"],
+            "batched_s": round(t_run, 4), "graph_replay_s": round(t_graph, 4),
+            "one_by_one_s": round(t_one, 4)}
+
+
+def bench_validation(qs, workloads, protocol, n: int = 20, p: float = 0.1, seeds=range(200, 210)) -> dict:
+    """Fidelity estimate against the exact fidelity |<approx|exact>|^2 on the
+    GPU (dense run of the same circuit)."""
+    errs = []
+    for s in seeds:
+        gates = workloads.random_circuit(n, 7, s)
+        r = protocol.approx_run(n, gates, p, keep=True)
+        st = r["state"]
+        a = qs.State(n, qs.C64)
+        st.expand_into(a)
+        e = qs.State(n, qs.C64)
+        c = qs.Circuit(n).add_gates(gates)
+        e.run(c)
+        fx = abs(a.inner(e)) ** 2
+        errs.append(r["F"] - fx)
+        for x in (st, a, e, c):
+            x.free()
+    return {"workload": f"n={n}, 7 layers, p={p}, {len(errs)} circuits",
+            "rmse": round(math.sqrt(sum(x * x for x in errs) / len(errs)), 5),
+            "mean_err": round(sum(errs) / len(errs), 5)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +218,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=27)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
+    ap.add_argument("--quick", action="store_true",
+                    help="only the QFT (skip the circuit, approximate, batch and validation runs)")
     ap.add_argument("--tune", action="append", default=[], metavar="KEY=VALUE",
                     help="library tuning knob (qs_tune_set), repeatable")
     args = ap.parse_args()
@@ -163,6 +320,15 @@ def main() -> int:
                      "traffic": None},
         "cpu_baseline": None,
     }
+    if not args.quick:
+        from paper_2304_14969_amd import protocol
+        sec = {}
+        sec["circuit_n32"] = bench_circuit(qs, workloads, torch)
+        for fam in ("grid", "matching"):
+            sec[f"approx54_{fam}"] = bench_approx(qs, workloads, protocol, np, fam)
+        sec["batch1024"] = bench_batch(qs, workloads, torch)
+        sec["validation"] = bench_validation(qs, workloads, protocol)
+        out["secondary"] = sec
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(out), flush=True)

@@ -240,13 +240,25 @@ int qs_mlp_train(qs_mlp* net, const float* X, const float* y, uint64_t rows,
                  const qs_train_cfg* cfg, double* final_loss);
 
 /* Use `net` to choose which dirty qubits of a factorized state to test: every
- * dirty qubit is scored from its features (qs_features layout); only those
- * scoring >= cutoff get the exact Schmidt test, which alone decides any
- * rounding (the fidelity estimate keeps the plain rule). Skipped qubits are
- * deferred; before a merge that would exceed the amplitude cap, every
- * deferred qubit gets the exact test. NULL restores the plain schedule. The
- * network must outlive its use. */
-int qs_set_proposer(qs_state* st, qs_mlp* net, double cutoff);
+ * dirty qubit of a subsystem with at least cfg->min_qubits qubits is scored
+ * from its features (qs_features layout) and only those scoring >=
+ * cfg->cutoff get the exact Schmidt test, which alone decides any rounding
+ * (the fidelity estimate keeps the plain rule); smaller subsystems keep the
+ * plain schedule, since their exact test costs no more than a proposal.
+ * Skipped qubits are deferred; before a merge that would exceed the
+ * amplitude cap, every deferred qubit gets the exact test. With
+ * QS_PROPOSE_RETEST_ON_MERGE in cfg->flags, the deferred qubits of the
+ * subsystems a gate is about to merge are tested first, so a skipped
+ * rounding cannot make a merged subsystem larger than it has to be.
+ * net = NULL restores the plain schedule (cfg is then ignored). The network
+ * must outlive its use; cfg is copied. */
+#define QS_PROPOSE_RETEST_ON_MERGE 1
+typedef struct qs_propose_cfg {
+  double cutoff;      /* score threshold in [0, 1] */
+  int32_t flags;      /* QS_PROPOSE_* */
+  int32_t min_qubits; /* smallest subsystem whose qubits are scored, >= 2 */
+} qs_propose_cfg;
+int qs_set_proposer(qs_state* st, qs_mlp* net, const qs_propose_cfg* cfg);
 
 /* Features recorded with each attempt (rows of QS_MLP_INPUTS floats aligned
  * with the attempt log): caller-owned buffer of cap rows; NULL stops. */

@@ -138,7 +138,7 @@ _SIGS = [
                               C.POINTER(C.c_float), C.POINTER(C.c_double)]),
     ("qs_mlp_train", C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_uint64,
                                C.POINTER(TrainCfg), C.POINTER(C.c_double)]),
-    ("qs_set_proposer", C.c_int, [C.c_void_p, C.c_void_p, C.c_double]),
+    ("qs_set_proposer", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("qs_set_feature_log", C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.c_uint64]),
     ("qs_proposer_stats", C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     ("qs_tune_set", C.c_int, [C.c_char_p, C.c_int64]),
@@ -356,6 +356,23 @@ def _fptr(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_float))
 
 
+class ProposeCfg(C.Structure):
+    _fields_ = [("cutoff", C.c_double), ("flags", C.c_int32), ("min_qubits", C.c_int32)]
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    """Initial network parameters, packed W1 (32x64), b1, W2 (64x64), b2,
+    W3 (64), b3: every layer's weights and biases uniform in
+    +-1/sqrt(fan_in), drawn from a seeded PCG64 stream."""
+    g = np.random.default_rng(seed)
+    parts = []
+    for fan_in, shape in ((32, (32, 64)), (32, (64,)), (64, (64, 64)), (64, (64,)),
+                          (64, (64,)), (64, (1,))):
+        lim = 1.0 / np.sqrt(fan_in)
+        parts.append(g.uniform(-lim, lim, shape).reshape(-1))
+    return np.concatenate(parts).astype(np.float32)
+
+
 class MLP:
     """The separability-proposal network (parameters on the GPU)."""
 
@@ -441,6 +458,7 @@ def tune_get(key: str) -> int:
 
 
 SEP_NONE, SEP_AFTER_2Q = 0, 1
+PROPOSE_RETEST_ON_MERGE = 1
 
 
 class State:
@@ -610,10 +628,13 @@ class State:
         n = min(self._log_count.value, len(self._feat))
         return self._feat[:n].copy()
 
-    def set_proposer(self, net: "MLP | None", cutoff: float = 0.5):
+    def set_proposer(self, net: "MLP | None", cutoff: float = 0.5, retest_on_merge: bool = True,
+                     min_qubits: int = 2):
         self._proposer = net
+        cfg = ProposeCfg(float(cutoff), PROPOSE_RETEST_ON_MERGE if retest_on_merge else 0,
+                         int(min_qubits))
         _check(self.lib, self.lib.qs_set_proposer(self.h, net.h if net is not None else None,
-                                                  float(cutoff)))
+                                                  C.byref(cfg)))
 
     def proposer_stats(self) -> dict:
         a, b = C.c_uint64(), C.c_uint64()

@@ -351,13 +351,15 @@ int qs_alloc_factorized(int n, int dtype, uint64_t max_amps, qs_state** out) {
   reset_perm(st);
   st->mat = dev_alloc(kMatBytes);
   st->red = static_cast<double*>(dev_alloc(sizeof(double) * scratch_doubles()));
-  if (!st->mat || !st->red) {
+  double* hstat = nullptr;
+  if (!st->mat || !st->red || hipHostMalloc(reinterpret_cast<void**>(&hstat), 64 * sizeof(double)) != hipSuccess) {
     dev_free(st->mat);
     dev_free(st->red);
     delete st;
     return fail(QS_E_NOMEM, "device allocation failed");
   }
   st->fact = new qs::FactorState();
+  st->fact->hstat = hstat;
   st->fact->n = n;
   st->fact->dtype = dtype;
   st->fact->max_amps = max_amps;
@@ -368,6 +370,7 @@ int qs_alloc_factorized(int n, int dtype, uint64_t max_amps, qs_state** out) {
   if (int rc = qs::fact_init(st->fact)) {
     dev_free(st->mat);
     dev_free(st->red);
+    (void)hipHostFree(hstat);
     delete st->fact;
     delete st;
     --g_live_states;
@@ -382,6 +385,7 @@ int qs_free(qs_state* st) {
   (void)hipStreamSynchronize(st->stream);
   if (st->fact) {
     qs::fact_release(st->fact);
+    (void)hipHostFree(st->fact->hstat);
     delete st->fact;
   }
   dev_free(st->amps);
@@ -825,12 +829,22 @@ int qs_inner_product(qs_state* a, qs_state* b, double* re, double* im) {
   return device_error(a, e, "inner product");
 }
 
-int qs_set_proposer(qs_state* st, qs_mlp* net, double cutoff) {
+int qs_set_proposer(qs_state* st, qs_mlp* net, const qs_propose_cfg* cfg) {
   if (int rc = check_state(st)) return rc;
   if (!st->fact) return fail(QS_E_UNSUPPORTED, "proposals apply to factorized states");
-  if (!(cutoff >= 0.0 && cutoff <= 1.0)) return fail(QS_E_INVAL, "cutoff %g outside [0, 1]", cutoff);
+  if (net) {
+    if (!cfg) return fail(QS_E_INVAL, "cfg is NULL");
+    if (!(cfg->cutoff >= 0.0 && cfg->cutoff <= 1.0))
+      return fail(QS_E_INVAL, "cutoff %g outside [0, 1]", cfg->cutoff);
+    if (cfg->flags & ~QS_PROPOSE_RETEST_ON_MERGE)
+      return fail(QS_E_INVAL, "unknown proposer flags %#x", unsigned(cfg->flags));
+    if (cfg->min_qubits < 2 || cfg->min_qubits > 64)
+      return fail(QS_E_INVAL, "min_qubits %d outside [2, 64]", int(cfg->min_qubits));
+    st->fact->cutoff = cfg->cutoff;
+    st->fact->propose_flags = cfg->flags;
+    st->fact->propose_min = cfg->min_qubits;
+  }
   st->fact->proposer = net;
-  st->fact->cutoff = cutoff;
   if (!net) {
     st->fact->dirty |= st->fact->deferred;
     st->fact->deferred = 0;

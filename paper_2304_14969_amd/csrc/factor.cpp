@@ -151,11 +151,11 @@ int test_qubit(FactorState* f, int q, double p, bool* rounded) {
   hipError_t e = f->dtype == QS_C64
                      ? launch_bloch(static_cast<const float*>(S.amps), S.nq, t, f->scratch, f->stream)
                      : launch_bloch(static_cast<const double*>(S.amps), S.nq, t, f->scratch, f->stream);
-  double st[4];
   if (e == hipSuccess)
-    e = hipMemcpyAsync(st, f->scratch, sizeof st, hipMemcpyDeviceToHost, f->stream);
+    e = hipMemcpyAsync(f->hstat, f->scratch, 4 * sizeof(double), hipMemcpyDeviceToHost, f->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
   if (int rc = dev_err(e, "bloch")) return rc;
+  const double st[4] = {f->hstat[0], f->hstat[1], f->hstat[2], f->hstat[3]};
   // Bloch vector of rho_q (Sec. III-A, step 1) and eps = (1 - |r|)/2 (step 2)
   const double nrm = st[2] + st[3];
   if (!(nrm > 0.0)) return ffail(QS_E_NUMERIC, "subsystem of qubit %d has zero norm", q);
@@ -223,13 +223,26 @@ int plain_separate(FactorState* f, double p, int* count) {
   return QS_OK;
 }
 
-// Learned schedule: score every dirty qubit in one forward pass, test the
-// proposals (ascending), defer the rest; repeat for qubits made dirty by a
-// rounding.
+// Learned schedule: dirty qubits of subsystems smaller than propose_min get
+// the exact test directly; the others are scored in one forward pass, the
+// proposals tested (ascending) and the rest deferred; repeat for qubits made
+// dirty by a rounding.
 int proposed_separate(FactorState* f, double p, int* count) {
   std::vector<int> cand;
   std::vector<float> X, score;
   while (f->dirty) {
+    int small = -1;
+    for (uint64_t d = f->dirty; d && small < 0; d &= d - 1) {
+      const int q = __builtin_ctzll(d);
+      const int si = find(f, q, nullptr);
+      if (si >= 0 && f->subs[si].nq < f->propose_min) small = q;
+    }
+    if (small >= 0) {
+      bool rounded = false;
+      if (int rc = test_qubit(f, small, p, &rounded)) return rc;
+      *count += rounded;
+      continue;
+    }
     cand.clear();
     for (uint64_t d = f->dirty; d; d &= d - 1) cand.push_back(__builtin_ctzll(d));
     X.assign(cand.size() * QS_MLP_INPUTS, 0.0f);
@@ -377,6 +390,31 @@ int fact_apply(FactorState* f, const int* qubits, int k, const double* m) {
       total += f->subs[s].nq;
     }
   }
+  if (nd > 1 && f->deferred && (f->propose_flags & QS_PROPOSE_RETEST_ON_MERGE)) {
+    // exact tests of the skipped qubits of the subsystems about to merge
+    uint64_t mask = 0;
+    for (int j = 0; j < nd; ++j) {
+      const Sub& s = f->subs[distinct[j]];
+      for (int b = 0; b < s.nq; ++b) mask |= uint64_t(1) << s.q[b];
+    }
+    mask &= f->deferred;
+    if (mask) {
+      f->fallback_tests += uint64_t(__builtin_popcountll(mask));
+      f->deferred &= ~mask;
+      f->dirty |= mask;
+      int nsep = 0;
+      if (int rc = plain_separate(f, f->p, &nsep)) return rc;
+      nd = 0;
+      total = 0;
+      for (int j = 0; j < k; ++j) {
+        const int s = find(f, qubits[j], nullptr);
+        if (std::find(distinct, distinct + nd, s) == distinct + nd) {
+          distinct[nd++] = s;
+          total += f->subs[s].nq;
+        }
+      }
+    }
+  }
   if ((total >= 63 || (uint64_t(1) << total) > f->max_amps) && f->deferred) {
     // exhaustive fallback: exact tests of every qubit the proposer skipped
     // may shrink the subsystems enough for the merge
@@ -430,6 +468,10 @@ int fact_apply(FactorState* f, const int* qubits, int k, const double* m) {
       for (int i = 0; i < 4; ++i) { mm.re[i] = m[2 * i]; mm.im[i] = m[2 * i + 1]; }
       e = launch_apply_1q(static_cast<double*>(S.amps), S.nq, local[0], mm, f->stream);
     }
+  } else if (k == 2) {
+    e = f->dtype == QS_C64
+            ? launch_apply_small(static_cast<float*>(S.amps), S.nq, local, k, m, f->stream)
+            : launch_apply_small(static_cast<double*>(S.amps), S.nq, local, k, m, f->stream);
   } else {
     const size_t D = size_t(1) << k;
     e = upload(f, f->mat, m, D * D);

@@ -32,6 +32,7 @@ struct FactorState {
   uint64_t log_cap = 0;
   uint64_t* log_count = nullptr;
   double* scratch = nullptr;  // device reduction scratch
+  double* hstat = nullptr;    // pinned host copy of the four Bloch sums
   void* mat = nullptr;        // device slot for one gate matrix
   // bookkeeping behind the proposal features (host only, no state sweeps)
   std::vector<double> eps_last, eps_prev;  // last two measured eps (-1: none)
@@ -43,6 +44,8 @@ struct FactorState {
   // learned proposal
   qs_mlp* proposer = nullptr;
   double cutoff = 0.5;
+  int propose_flags = 0;         // QS_PROPOSE_*
+  int propose_min = 2;           // smallest subsystem scored by the network
   uint64_t deferred = 0;        // dirty qubits skipped on the network's advice
   uint64_t skipped = 0, fallback_tests = 0;
   float* feat_log = nullptr;

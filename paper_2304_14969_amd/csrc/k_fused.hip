@@ -65,6 +65,75 @@ __global__ void __launch_bounds__(kBlock) k_fused_vec(R* __restrict__ a, uint64_
   }
 }
 
+// Blocks of one or two qubits with the matrix passed by value (no upload):
+// the same arithmetic as k_fused_vec, the matrix read from kernel arguments.
+template <typename R, int K>
+struct MatArg {
+  R v[2 << (2 * K)];
+};
+
+template <typename R, int K>
+__global__ void __launch_bounds__(kBlock) k_fused_arg(R* __restrict__ a, uint64_t groups, Block6 b,
+                                                      MatArg<R, K> mat) {
+  constexpr int D = 1 << K;
+  for (uint64_t g = uint64_t(blockIdx.x) * kBlock + threadIdx.x; g < groups;
+       g += uint64_t(gridDim.x) * kBlock) {
+    uint64_t base = g;
+#pragma unroll
+    for (int j = 0; j < K; ++j) base = insert_zero(base, b.sorted[j]);
+    uint64_t off[D];
+    Cx<R> v[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      uint64_t o = 0;
+#pragma unroll
+      for (int j = 0; j < K; ++j) o |= uint64_t((c >> j) & 1) << b.q[j];
+      off[c] = base | o;
+      v[c] = {a[2 * off[c]], a[2 * off[c] + 1]};
+    }
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      R yr = 0, yi = 0;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const R mr = mat.v[2 * (r * D + c)], mi = mat.v[2 * (r * D + c) + 1];
+        yr += mr * v[c].r - mi * v[c].i;
+        yi += mr * v[c].i + mi * v[c].r;
+      }
+      a[2 * off[r]] = yr;
+      a[2 * off[r] + 1] = yi;
+    }
+  }
+}
+
+unsigned fused_grid(uint64_t groups) {
+  const uint64_t want = (groups + kBlock - 1) / kBlock, cap = uint64_t(1) << 20;
+  return static_cast<unsigned>(want < cap ? (want > 0 ? want : 1) : cap);
+}
+
+Block6 make_block(const int* qubits, int k) {
+  Block6 b{};
+  b.k = k;
+  for (int j = 0; j < k; ++j) b.q[j] = b.sorted[j] = qubits[j];
+  for (int i = 1; i < k; ++i)
+    for (int j = i; j > 0 && b.sorted[j - 1] > b.sorted[j]; --j) {
+      const int t = b.sorted[j];
+      b.sorted[j] = b.sorted[j - 1];
+      b.sorted[j - 1] = t;
+    }
+  return b;
+}
+
+template <typename R, int K>
+hipError_t launch_arg(R* a, int n, const Block6& b, const double* m, hipStream_t s) {
+  MatArg<R, K> mat;
+  for (int i = 0; i < (2 << (2 * K)); ++i) mat.v[i] = static_cast<R>(m[i]);
+  const uint64_t groups = uint64_t(1) << (n - K);
+  hipLaunchKernelGGL((k_fused_arg<R, K>), dim3(fused_grid(groups)), dim3(kBlock), 0, s, a, groups,
+                     b, mat);
+  return hipGetLastError();
+}
+
 template <typename R, int K>
 hipError_t launch_k(R* a, int n, const Block6& b, const R* mat, hipStream_t s) {
   const uint64_t groups = uint64_t(1) << (n - K);
@@ -77,17 +146,20 @@ hipError_t launch_k(R* a, int n, const Block6& b, const R* mat, hipStream_t s) {
 }  // namespace
 
 template <typename R>
+hipError_t launch_apply_small(R* a, int n, const int* qubits, int k, const double* host_mat,
+                              hipStream_t s) {
+  const Block6 b = make_block(qubits, k);
+  switch (k) {
+    case 1: return launch_arg<R, 1>(a, n, b, host_mat, s);
+    case 2: return launch_arg<R, 2>(a, n, b, host_mat, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename R>
 hipError_t launch_apply_fused(R* a, int n, const int* qubits, int k, const R* mat,
                               hipStream_t s) {
-  Block6 b{};
-  b.k = k;
-  for (int j = 0; j < k; ++j) b.q[j] = b.sorted[j] = qubits[j];
-  for (int i = 1; i < k; ++i)
-    for (int j = i; j > 0 && b.sorted[j - 1] > b.sorted[j]; --j) {
-      const int t = b.sorted[j];
-      b.sorted[j] = b.sorted[j - 1];
-      b.sorted[j - 1] = t;
-    }
+  const Block6 b = make_block(qubits, k);
   switch (k) {
     case 1: return launch_k<R, 1>(a, n, b, mat, s);
     case 2: return launch_k<R, 2>(a, n, b, mat, s);
@@ -101,6 +173,10 @@ hipError_t launch_apply_fused(R* a, int n, const int* qubits, int k, const R* ma
 
 template hipError_t launch_apply_fused<float>(float*, int, const int*, int, const float*,
                                               hipStream_t);
+template hipError_t launch_apply_small<float>(float*, int, const int*, int, const double*,
+                                              hipStream_t);
+template hipError_t launch_apply_small<double>(double*, int, const int*, int, const double*,
+                                               hipStream_t);
 template hipError_t launch_apply_fused<double>(double*, int, const int*, int, const double*,
                                                hipStream_t);
 

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstring>
 #include <vector>
 
 #include "mlp.h"
@@ -16,6 +17,8 @@ void set_last_error(const char* msg);
 }  // namespace qs
 
 namespace {
+
+constexpr int kScoreRowsFloats = qs::kScoreRows * (QS_MLP_INPUTS + 1);
 
 int mfail(int code, const char* fmt, ...) {
   char buf[256];
@@ -63,6 +66,23 @@ namespace qs {
 // scores[r] = sigmoid(logit) of the rows of host X (rows x 32); synchronizes.
 int mlp_scores(qs_mlp* net, const float* X, uint64_t rows, float* scores) {
   if (rows == 0) return QS_OK;
+  if (rows <= uint64_t(kScoreRows)) {
+    // the usual case (the dirty qubits of one separation round): staged
+    // through pinned host memory, no allocation
+    float* hz = net->hscore + kScoreRows * QS_MLP_INPUTS;
+    float* dz = net->dscore + kScoreRows * QS_MLP_INPUTS;
+    std::memcpy(net->hscore, X, rows * QS_MLP_INPUTS * sizeof(float));
+    hipError_t e = hipMemcpyAsync(net->dscore, net->hscore, rows * QS_MLP_INPUTS * sizeof(float),
+                                  hipMemcpyHostToDevice, net->stream);
+    if (e == hipSuccess)
+      e = launch_mlp_forward(net->P, net->dscore, int(rows), dz, nullptr, nullptr, net->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hz, dz, rows * sizeof(float), hipMemcpyDeviceToHost, net->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
+    if (int rc = merr(e, "network forward")) return rc;
+    for (uint64_t r = 0; r < rows; ++r) scores[r] = 1.0f / (1.0f + std::exp(-hz[r]));
+    return QS_OK;
+  }
   Scratch s;
   if (!s.alloc(rows)) return mfail(QS_E_NOMEM, "network scratch");
   hipError_t e = hipMemcpyAsync(s.X, X, rows * QS_MLP_INPUTS * sizeof(float), hipMemcpyHostToDevice,
@@ -91,6 +111,14 @@ int qs_mlp_create(qs_mlp** out) {
     delete n;
     return mfail(QS_E_NOMEM, "network parameters");
   }
+  const size_t score_floats = size_t(kScoreRowsFloats);
+  n->dscore = static_cast<float*>(qs::device_alloc(score_floats * sizeof(float)));
+  if (!n->dscore || hipHostMalloc(reinterpret_cast<void**>(&n->hscore), score_floats * sizeof(float)) != hipSuccess) {
+    qs::device_free(n->dscore);
+    qs::device_free(blk);
+    delete n;
+    return mfail(QS_E_NOMEM, "network scoring buffers");
+  }
   n->block = blk;
   n->P = static_cast<float*>(blk);
   n->M = n->P + np;
@@ -99,6 +127,8 @@ int qs_mlp_create(qs_mlp** out) {
   std::vector<float> zero(size_t(4) * np, 0.0f);
   hipError_t e = hipMemcpy(blk, zero.data(), zero.size() * sizeof(float), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
+    qs::device_free(n->dscore);
+    (void)hipHostFree(n->hscore);
     qs::device_free(blk);
     delete n;
     return merr(e, "network init");
@@ -111,6 +141,8 @@ int qs_mlp_free(qs_mlp* n) {
   if (!n) return QS_OK;
   (void)hipStreamSynchronize(n->stream);
   qs::device_free(n->block);
+  qs::device_free(n->dscore);
+  (void)hipHostFree(n->hscore);
   delete n;
   return QS_OK;
 }

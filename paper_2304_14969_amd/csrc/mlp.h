@@ -12,9 +12,12 @@ struct qs_mlp {
   float* V = nullptr;
   float* G = nullptr;
   hipStream_t stream = nullptr;
+  float* dscore = nullptr;  // device rows for scoring: kScoreRows x 32 inputs, then logits
+  float* hscore = nullptr;  // pinned host staging of the same layout
 };
 
 namespace qs {
+constexpr int kScoreRows = 64;  // rows scored through the pinned staging
 int mlp_param_count();
 hipError_t launch_mlp_forward(const float* P, const float* X, int rows, float* logit, float* H1,
                               float* H2, hipStream_t s);

@@ -45,6 +45,11 @@ hipError_t launch_bitswap(R* amps, int n, int a, int b, hipStream_t s);
 template <typename R>
 hipError_t launch_apply_fused(R* amps, int n, const int* qubits, int k, const R* mat,
                               hipStream_t s);
+// The same for k <= 2 with the host matrix (FP64, interleaved, row-major)
+// cast to R and passed in the kernel arguments: no device copy of it.
+template <typename R>
+hipError_t launch_apply_small(R* amps, int n, const int* qubits, int k, const double* host_mat,
+                              hipStream_t s);
 
 // Tile geometry of a k-qubit block on the matrix cores: the tile holds the
 // contiguous low bits [0, C) and the block bits at or above C (qhi, h of

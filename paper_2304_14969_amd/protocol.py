@@ -10,12 +10,15 @@ from __future__ import annotations
 
 import time
 
-from . import C64, SEP_AFTER_2Q, CapacityError, Circuit, State
+import numpy as np
+
+from . import C64, MLP, SEP_AFTER_2Q, CapacityError, Circuit, State, mlp_init
 
 
 def approx_run(n: int, gates, p: float, max_amps: int = 2 ** 30, dtype: int = C64,
                record: bool = False, keep: bool = False, features: bool = False,
-               proposer=None, cutoff: float = 0.5) -> dict:
+               proposer=None, cutoff: float = 0.5, retest_on_merge: bool = True,
+               min_qubits: int = 2) -> dict:
     """One run; returns completion, time, fidelity estimate and table stats.
     With keep=True the state is returned under "state" (caller frees it).
     features=True also returns the proposal features of every attempt;
@@ -30,7 +33,7 @@ def approx_run(n: int, gates, p: float, max_amps: int = 2 ** 30, dtype: int = C6
     if features:
         st.record_features()
     if proposer is not None:
-        st.set_proposer(proposer, cutoff)
+        st.set_proposer(proposer, cutoff, retest_on_merge, min_qubits)
     circ = Circuit(n).add_gates(gates)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -81,3 +84,29 @@ def minimum_p(n: int, gates, max_amps: int = 2 ** 30, step: float = 0.025,
         best = r
         k += 1
     return {"best": best, "runs": runs, "search_time_s": total}
+
+
+def collect_attempts(n: int, circuits, ps, max_amps: int = 2 ** 30, dtype: int = C64):
+    """Training data for the proposal network: the features of every exact
+    test the plain schedule makes on each circuit at each threshold in ps,
+    labelled 1 where the test rounded."""
+    X, y = [], []
+    for gates in circuits:
+        for p in ps:
+            r = approx_run(n, gates, p, max_amps=max_amps, dtype=dtype, features=True)
+            X.append(r["features"])
+            y.append(np.array([a[3] for a in r["log"]], dtype=np.float32))
+    return np.concatenate(X), np.concatenate(y)
+
+
+def train_proposer(X, y, steps: int = 3000, batch: int = 256, lr: float = 3e-3,
+                   seed: int = 0, recall: float = 0.95):
+    """Train a network on shuffled (X, y) with the library's GPU kernels and
+    pick the cutoff: the largest score that still proposes a fraction
+    `recall` of the training roundings. Returns (net, cutoff, final loss)."""
+    order = np.random.default_rng(seed).permutation(len(y))
+    net = MLP(mlp_init(seed))
+    loss = net.train(X[order], y[order], steps=steps, batch=min(batch, len(y)), lr=lr)
+    pos = np.sort(net.forward(X[y > 0.5]))
+    cutoff = float(pos[int(np.floor((1.0 - recall) * len(pos)))]) if len(pos) else 0.5
+    return net, cutoff, loss
