@@ -376,8 +376,10 @@ int qs_check(qs_state* st, double tol);
  *   "qft.high_pass"  passes above that tile: 0 = strided LDS tiles of up to
  *                    7 bits, 1 = register passes of up to 5 bits;
  *   "qft.threads"    thread cap of the LDS tile launches: 256 or 512 (default);
- *   "qft.round_bits" widest in-register round inside an LDS tile: 4 (default)
- *                    or 5.
+ *   "qft.round_bits" widest in-register round inside an LDS tile: 4 or 5
+ *                    (default);
+ *   "fused.mfma"     1 (default): complex64 blocks of 4 or 5 qubits run on the
+ *                    matrix cores when their geometry fits; 0: vector FMA.
  * QS_E_INVAL for an unknown key or a value out of range. */
 int qs_tune_set(const char* key, int64_t value);
 int qs_tune_get(const char* key, int64_t* value);

@@ -206,6 +206,32 @@ def qft(a, n, start=0, length=None, inverse=False):
     return run_circuit(a, n, qft_gates(n, start, length, inverse))
 
 
+def dft_entries(a, n, js, chunk: int = 1 << 22) -> np.ndarray:
+    """Single outputs of the transform straight from its definition, Eq. dft
+    with the printed + sign: y_j = N^{-1/2} sum_k x_k e^{+2 pi i j k / N}, for
+    each j in js (for spot checks at sizes where the circuit is too slow).
+    The phase j k mod N is taken in exact integer arithmetic."""
+    a = np.asarray(a, dtype=np.complex128)
+    N = 1 << n
+    out = np.empty(len(js), dtype=np.complex128)
+    for t, j in enumerate(js):
+        acc = 0.0 + 0.0j
+        for k0 in range(0, N, chunk):
+            k = np.arange(k0, min(N, k0 + chunk), dtype=np.int64)
+            ph = ((int(j) * k) % N).astype(np.float64) * (2.0 * np.pi / N)
+            acc += np.dot(a[k0:k0 + len(k)], np.exp(1j * ph))
+        out[t] = acc / np.sqrt(N)
+    return out
+
+
+def qft_basis_entries(n, x, js) -> np.ndarray:
+    """The transform of the basis state |x>: 2^{-n/2} e^{2 pi i x j / 2^n}."""
+    N = 1 << n
+    j = np.asarray(js, dtype=np.int64)
+    ph = ((int(x) * j) % N).astype(np.float64) * (2.0 * np.pi / N)
+    return np.exp(1j * ph) / np.sqrt(N)
+
+
 # ---------------------------------------------------------------- readout
 
 

@@ -277,6 +277,7 @@ int qs_tune_set(const char* key, int64_t value) {
   } else if (!std::strcmp(key, "qft.round_bits")) {
     if (value != 4 && value != 5) return fail(QS_E_INVAL, "qft.round_bits must be 4 or 5");
     g_qft_tune.round_bits = int(value);
+
   } else {
     return fail(QS_E_INVAL, "unknown tuning key '%s'", key);
   }

@@ -122,7 +122,7 @@ struct QftTuning {
   int lds_bits = 0;   // contiguous tile bits (0: default per precision)
   int high_kind = 0;  // passes above the tile: 0 strided LDS tiles, 1 registers
   int threads = 512;  // thread cap of the LDS tile launches (256 or 512)
-  int round_bits = 4; // widest register round inside an LDS tile (4 or 5)
+  int round_bits = 5; // widest register round inside an LDS tile (4 or 5)
 };
 
 // `rev` = the range is stored bit-reversed (after an earlier transform's

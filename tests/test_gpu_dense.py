@@ -282,3 +282,4 @@ def test_qft_pass_variants(qs_lib, dtype, high_pass, lds_bits):
     finally:
         qs.tune_set("qft.high_pass", 0)
         qs.tune_set("qft.lds_bits", 0)
+

@@ -159,6 +159,23 @@ def test_qft_ghz_closed_form(n):
     np.testing.assert_allclose(dense.qft(dense.ghz_state(n), n), want, atol=1e-13)
 
 
+@pytest.mark.parametrize("n", [3, 8, 11])
+def test_dft_entries_match_fft_and_circuit(n):
+    """The per-output definition used for spot checks at large n agrees with
+    numpy's inverse FFT (and, for small n, with the gate circuit); the chunked
+    sum and the integer phase reduction give the same entries."""
+    a = workloads.gaussian_state(n, 300 + n)
+    js = list(range(2 ** n)) if n <= 8 else [0, 1, 2 ** n - 1, 77, 1234]
+    got = dense.dft_entries(a, n, js, chunk=64)
+    want = (np.fft.ifft(a) * math.sqrt(2 ** n))[js]
+    np.testing.assert_allclose(got, want, atol=1e-12)
+    if n <= 8:
+        np.testing.assert_allclose(got, dense.qft(a, n), atol=1e-12)
+    x = workloads.basis_index(n, 9)
+    np.testing.assert_allclose(dense.qft_basis_entries(n, x, js),
+                               dense.dft_entries(dense.basis_state(n, x), n, js), atol=1e-13)
+
+
 def test_qft_zero_is_uniform():
     n = 7
     np.testing.assert_allclose(dense.qft(dense.zero_state(n), n),
