@@ -25,6 +25,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM bytes per launch of the QFT pass kernels, from two rocprofv3 --pmc runs
+# of `bench.py --quick` (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
+# scaled by what the counter reads for a copy of a known 1 GiB
+# (`bench.py --calibrate-copy`: FETCH_SIZE reads 0.5000 of the bytes copied,
+# WRITE_SIZE 1.0000). Valid only for the kernel source they were taken on.
+TRAFFIC_SOURCE = os.path.join(ROOT, "paper_2304_14969_amd", "csrc", "k_qft.hip")
+TRAFFIC = {"sha256": None, "bytes_per_launch": {}}
+
+
+def measured_traffic(kernel: str):
+    import hashlib
+    if TRAFFIC["sha256"] is None:
+        return None
+    with open(TRAFFIC_SOURCE, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != TRAFFIC["sha256"]:
+            return None
+    return TRAFFIC["bytes_per_launch"].get(kernel)
 METRIC = "exact QFT-27 seconds & HBM GB/s; 54q×7-layer approx time at equal fidelity"
 
 
@@ -101,7 +119,7 @@ def bench_circuit(qs, workloads, torch, n: int = 32, layers: int = 10, seed: int
 
 def bench_approx(qs, workloads, protocol, np, family: str, p_cmp: float = 0.6,
                  test_seeds=range(10), train_seeds=range(10000, 10060),
-                 train_ps=(0.7, 0.6, 0.5), min_qubits: int = 2) -> dict:
+                 train_ps=(0.7, 0.6, 0.5), min_qubits: int = 12) -> dict:
     """54-qubit, 7-layer approximate runs: the paper's descending-p search,
     then plain vs learned schedule at one threshold on held-out circuits."""
     if family == "grid":
@@ -220,6 +238,12 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     ap.add_argument("--quick", action="store_true",
                     help="only the QFT (skip the circuit, approximate, batch and validation runs)")
+    ap.add_argument("--section", action="append", default=[],
+                    choices=["circuit", "approx", "batch", "validation"],
+                    help="run only these secondary sections (repeatable; default: all)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy one 1-GiB device buffer into another three times (the known-size "
+                         "reference for the HBM byte counters) and exit")
     ap.add_argument("--tune", action="append", default=[], metavar="KEY=VALUE",
                     help="library tuning knob (qs_tune_set), repeatable")
     args = ap.parse_args()
@@ -230,6 +254,16 @@ def main() -> int:
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        src = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": src.numel() * 4,
+                          "bytes_written": dst.numel() * 4, "launches": 3}), flush=True)
+        return 0
 
     import paper_2304_14969_amd as qs
     import workloads
@@ -317,17 +351,22 @@ def main() -> int:
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms,
-                     "traffic": None},
+                     "traffic": measured_traffic(dom_name)},
         "cpu_baseline": None,
     }
     if not args.quick:
         from paper_2304_14969_amd import protocol
         sec = {}
-        sec["circuit_n32"] = bench_circuit(qs, workloads, torch)
-        for fam in ("grid", "matching"):
-            sec[f"approx54_{fam}"] = bench_approx(qs, workloads, protocol, np, fam)
-        sec["batch1024"] = bench_batch(qs, workloads, torch)
-        sec["validation"] = bench_validation(qs, workloads, protocol)
+        want = set(args.section) or {"circuit", "approx", "batch", "validation"}
+        if "circuit" in want:
+            sec["circuit_n32"] = bench_circuit(qs, workloads, torch)
+        if "approx" in want:
+            for fam in ("grid", "matching"):
+                sec[f"approx54_{fam}"] = bench_approx(qs, workloads, protocol, np, fam)
+        if "batch" in want:
+            sec["batch1024"] = bench_batch(qs, workloads, torch)
+        if "validation" in want:
+            sec["validation"] = bench_validation(qs, workloads, protocol)
         out["secondary"] = sec
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n)

@@ -353,7 +353,12 @@ int qs_alloc_factorized(int n, int dtype, uint64_t max_amps, qs_state** out) {
   st->mat = dev_alloc(kMatBytes);
   st->red = static_cast<double*>(dev_alloc(sizeof(double) * scratch_doubles()));
   double* hstat = nullptr;
-  if (!st->mat || !st->red || hipHostMalloc(reinterpret_cast<void**>(&hstat), 64 * sizeof(double)) != hipSuccess) {
+  double* dstat = nullptr;
+  if (!st->mat || !st->red ||
+      hipHostMalloc(reinterpret_cast<void**>(&hstat), 64 * sizeof(double), hipHostMallocMapped) !=
+          hipSuccess ||
+      hipHostGetDevicePointer(reinterpret_cast<void**>(&dstat), hstat, 0) != hipSuccess) {
+    if (hstat) (void)hipHostFree(hstat);
     dev_free(st->mat);
     dev_free(st->red);
     delete st;
@@ -361,6 +366,7 @@ int qs_alloc_factorized(int n, int dtype, uint64_t max_amps, qs_state** out) {
   }
   st->fact = new qs::FactorState();
   st->fact->hstat = hstat;
+  st->fact->dstat = dstat;
   st->fact->n = n;
   st->fact->dtype = dtype;
   st->fact->max_amps = max_amps;
@@ -369,6 +375,7 @@ int qs_alloc_factorized(int n, int dtype, uint64_t max_amps, qs_state** out) {
   st->fact->mat = st->mat;
   ++g_live_states;
   if (int rc = qs::fact_init(st->fact)) {
+    qs::fact_drain(st->fact);
     dev_free(st->mat);
     dev_free(st->red);
     (void)hipHostFree(hstat);
@@ -385,7 +392,7 @@ int qs_free(qs_state* st) {
   if (!st) return QS_OK;
   (void)hipStreamSynchronize(st->stream);
   if (st->fact) {
-    qs::fact_release(st->fact);
+    qs::fact_drain(st->fact);
     (void)hipHostFree(st->fact->hstat);
     delete st->fact;
   }

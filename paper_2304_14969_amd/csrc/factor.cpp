@@ -76,14 +76,38 @@ int find(const FactorState* f, int q, int* t) {
   return -1;
 }
 
+// Subsystem buffers: small ones are recycled through the state's pool (work
+// on a state is ordered on its stream, so a returned buffer can be handed out
+// again at once); larger ones go back to the allocator.
+void* sub_alloc(FactorState* f, int nq) {
+  if (nq <= FactorState::kPoolQubits && !f->pool[nq].empty()) {
+    void* p = f->pool[nq].back();
+    f->pool[nq].pop_back();
+    return p;
+  }
+  return device_alloc((size_t(1) << nq) * amp_bytes(f));
+}
+
+void sub_free(FactorState* f, int nq, void* p) {
+  if (!p) return;
+  if (nq <= FactorState::kPoolQubits) {
+    f->pool[nq].push_back(p);
+    return;
+  }
+  device_free(p);
+}
+
 int new_single(FactorState* f, int q, const double amp[4], Sub* out) {
   Sub s;
   s.nq = 1;
   s.q[0] = q;
-  s.amps = device_alloc(2 * amp_bytes(f));
+  s.amps = sub_alloc(f, 1);
   if (!s.amps) return ffail(QS_E_NOMEM, "allocating a one-qubit subsystem");
-  if (int rc = dev_err(upload(f, s.amps, amp, 2), "upload")) {
-    device_free(s.amps);
+  const hipError_t e = f->dtype == QS_C64
+                           ? launch_store_single(static_cast<float*>(s.amps), amp, f->stream)
+                           : launch_store_single(static_cast<double*>(s.amps), amp, f->stream);
+  if (int rc = dev_err(e, "one-qubit subsystem")) {
+    sub_free(f, 1, s.amps);
     return rc;
   }
   *out = s;
@@ -109,7 +133,7 @@ int merge(FactorState* f, int ia, int ib, int* out) {
   Sub& A = f->subs[ia];
   Sub& B = f->subs[ib];
   const int nq = A.nq + B.nq;
-  void* c = device_alloc((size_t(1) << nq) * amp_bytes(f));
+  void* c = sub_alloc(f, nq);
   if (!c) return ffail(QS_E_NOMEM, "allocating a %d-qubit subsystem", nq);
   hipError_t e = f->dtype == QS_C64
                      ? launch_compose(static_cast<float*>(c), static_cast<const float*>(A.amps),
@@ -117,7 +141,7 @@ int merge(FactorState* f, int ia, int ib, int* out) {
                      : launch_compose(static_cast<double*>(c), static_cast<const double*>(A.amps),
                                       A.nq, static_cast<const double*>(B.amps), B.nq, f->stream);
   if (e != hipSuccess) {
-    device_free(c);
+    sub_free(f, nq, c);
     return dev_err(e, "compose");
   }
   Sub m;
@@ -125,8 +149,8 @@ int merge(FactorState* f, int ia, int ib, int* out) {
   for (int t = 0; t < A.nq; ++t) m.q[t] = A.q[t];
   for (int t = 0; t < B.nq; ++t) m.q[A.nq + t] = B.q[t];
   m.amps = c;
-  device_free(A.amps);
-  device_free(B.amps);
+  sub_free(f, A.nq, A.amps);
+  sub_free(f, B.nq, B.amps);
   const int lo = std::min(ia, ib), hi = std::max(ia, ib);
   f->subs.erase(f->subs.begin() + hi);
   f->subs.erase(f->subs.begin() + lo);
@@ -149,10 +173,10 @@ int test_qubit(FactorState* f, int q, double p, bool* rounded) {
     fact_features(f, q, p, f->feat_log + *f->log_count * QS_MLP_INPUTS);
   Sub& S = f->subs[si];
   hipError_t e = f->dtype == QS_C64
-                     ? launch_bloch(static_cast<const float*>(S.amps), S.nq, t, f->scratch, f->stream)
-                     : launch_bloch(static_cast<const double*>(S.amps), S.nq, t, f->scratch, f->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(f->hstat, f->scratch, 4 * sizeof(double), hipMemcpyDeviceToHost, f->stream);
+                     ? launch_bloch(static_cast<const float*>(S.amps), S.nq, t, f->scratch,
+                                    f->dstat, f->stream)
+                     : launch_bloch(static_cast<const double*>(S.amps), S.nq, t, f->scratch,
+                                    f->dstat, f->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
   if (int rc = dev_err(e, "bloch")) return rc;
   const double st[4] = {f->hstat[0], f->hstat[1], f->hstat[2], f->hstat[3]};
@@ -181,11 +205,11 @@ int test_qubit(FactorState* f, int q, double p, bool* rounded) {
   }
   // the kept branch carries weight (1 + |r|)/2 of the subsystem's norm
   const double scale = 1.0 / std::sqrt(0.5 * (1.0 + rn) * nrm);
-  void* rest = device_alloc((size_t(1) << (S.nq - 1)) * amp_bytes(f));
+  void* rest = sub_alloc(f, S.nq - 1);
   if (!rest) return ffail(QS_E_NOMEM, "allocating a %d-qubit subsystem", S.nq - 1);
   Sub single;
   if (int rc = new_single(f, q, phi, &single)) {
-    device_free(rest);
+    sub_free(f, S.nq - 1, rest);
     return rc;
   }
   e = f->dtype == QS_C64
@@ -194,12 +218,12 @@ int test_qubit(FactorState* f, int q, double p, bool* rounded) {
           : launch_decompose(static_cast<double*>(rest), static_cast<const double*>(S.amps), S.nq,
                              t, phi, scale, f->stream);
   if (e != hipSuccess) {
-    device_free(rest);
-    device_free(single.amps);
+    sub_free(f, S.nq - 1, rest);
+    sub_free(f, 1, single.amps);
     return dev_err(e, "decompose");
   }
   const int nsub = S.nq;
-  device_free(S.amps);
+  sub_free(f, S.nq, S.amps);
   S.amps = rest;
   for (int b = t; b + 1 < S.nq; ++b) S.q[b] = S.q[b + 1];
   S.nq -= 1;
@@ -348,8 +372,16 @@ int fact_init(FactorState* f) {
 
 void fact_release(FactorState* f) {
   (void)hipStreamSynchronize(f->stream);
-  for (auto& s : f->subs) device_free(s.amps);
+  for (auto& s : f->subs) sub_free(f, s.nq, s.amps);
   f->subs.clear();
+}
+
+void fact_drain(FactorState* f) {
+  fact_release(f);
+  for (auto& v : f->pool) {
+    for (void* p : v) device_free(p);
+    v.clear();
+  }
 }
 
 int fact_set_basis(FactorState* f, uint64_t x) {

@@ -32,7 +32,11 @@ struct FactorState {
   uint64_t log_cap = 0;
   uint64_t* log_count = nullptr;
   double* scratch = nullptr;  // device reduction scratch
-  double* hstat = nullptr;    // pinned host copy of the four Bloch sums
+  double* hstat = nullptr;    // pinned, mapped host buffer of the four Bloch sums
+  double* dstat = nullptr;    // its device address
+  // recycled subsystem buffers of at most kPoolQubits qubits, by qubit count
+  static constexpr int kPoolQubits = 20;
+  std::vector<void*> pool[kPoolQubits + 1];
   void* mat = nullptr;        // device slot for one gate matrix
   // bookkeeping behind the proposal features (host only, no state sweeps)
   std::vector<double> eps_last, eps_prev;  // last two measured eps (-1: none)
@@ -57,7 +61,8 @@ void fact_features(const FactorState* f, int q, double p, float* out);
 
 // All return QS_* status codes and set the thread's error message.
 int fact_init(FactorState* f);                     // n one-qubit |0> subsystems
-void fact_release(FactorState* f);                 // frees every buffer
+void fact_release(FactorState* f);                 // returns every subsystem buffer
+void fact_drain(FactorState* f);                   // frees the recycled buffers too
 int fact_set_basis(FactorState* f, uint64_t x);    // n one-qubit basis states
 int fact_apply(FactorState* f, const int* qubits, int k, const double* m);
 int fact_swap(FactorState* f, int a, int b);       // relabel

@@ -72,6 +72,37 @@ __global__ void __launch_bounds__(kBlock) k_bloch_partial(const R* __restrict__ 
     for (int k = 0; k < 4; ++k) partial[k * gridDim.x + blockIdx.x] = v[k];
 }
 
+// The whole reduction in one workgroup (small subsystems): the same sums in
+// a fixed order, written straight to `out`.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_bloch_small(const R* __restrict__ a, uint64_t pairs,
+                                                        int t, double* __restrict__ out) {
+  __shared__ double sh[4 * kBlock];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const uint64_t bit = uint64_t(1) << t;
+  for (uint64_t u = threadIdx.x; u < pairs; u += kBlock) {
+    const uint64_t i0 = insert_zero(u, t), i1 = i0 | bit;
+    const double x0 = a[2 * i0], y0 = a[2 * i0 + 1], x1 = a[2 * i1], y1 = a[2 * i1 + 1];
+    v[0] += x0 * x1 + y0 * y1;
+    v[1] += x0 * y1 - y0 * x1;
+    v[2] += x0 * x0 + y0 * y0;
+    v[3] += x1 * x1 + y1 * y1;
+  }
+  block_sum<4>(v, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) out[k] = v[k];
+}
+
+template <typename R>
+__global__ void k_store_single(R* __restrict__ dst, R a0r, R a0i, R a1r, R a1i) {
+  if (threadIdx.x == 0) {
+    dst[0] = a0r;
+    dst[1] = a0i;
+    dst[2] = a1r;
+    dst[3] = a1i;
+  }
+}
+
 template <int N>
 __global__ void __launch_bounds__(kBlock) k_sum_rows(const double* __restrict__ partial, int count,
                                                      double* __restrict__ out) {
@@ -158,12 +189,26 @@ hipError_t launch_compose(R* c, const R* a, int na, const R* b, int nb, hipStrea
   return hipGetLastError();
 }
 
+// Subsystems of up to 2^14 pairs are reduced by one workgroup in one launch.
+constexpr uint64_t kSmallPairs = uint64_t(1) << 14;
+
 template <typename R>
-hipError_t launch_bloch(const R* a, int nq, int t, double* scratch, hipStream_t s) {
+hipError_t launch_bloch(const R* a, int nq, int t, double* scratch, double* out, hipStream_t s) {
   const uint64_t pairs = uint64_t(1) << (nq - 1);
+  if (pairs <= kSmallPairs) {
+    hipLaunchKernelGGL(k_bloch_small<R>, dim3(1), dim3(kBlock), 0, s, a, pairs, t, out);
+    return hipGetLastError();
+  }
   const unsigned nb = red_blocks(pairs);
   hipLaunchKernelGGL(k_bloch_partial<R>, dim3(nb), dim3(kBlock), 0, s, a, pairs, t, scratch + 8);
-  hipLaunchKernelGGL(k_sum_rows<4>, dim3(1), dim3(kBlock), 0, s, scratch + 8, int(nb), scratch);
+  hipLaunchKernelGGL(k_sum_rows<4>, dim3(1), dim3(kBlock), 0, s, scratch + 8, int(nb), out);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_store_single(R* dst, const double amp[4], hipStream_t s) {
+  hipLaunchKernelGGL(k_store_single<R>, dim3(1), dim3(64), 0, s, dst, R(amp[0]), R(amp[1]),
+                     R(amp[2]), R(amp[3]));
   return hipGetLastError();
 }
 
@@ -193,7 +238,8 @@ hipError_t launch_gather_mul(const R* a, const uint64_t* idx, uint64_t m, Perm64
 
 #define QS_INST(R)                                                                          \
   template hipError_t launch_compose<R>(R*, const R*, int, const R*, int, hipStream_t);     \
-  template hipError_t launch_bloch<R>(const R*, int, int, double*, hipStream_t);            \
+  template hipError_t launch_bloch<R>(const R*, int, int, double*, double*, hipStream_t);   \
+  template hipError_t launch_store_single<R>(R*, const double*, hipStream_t);               \
   template hipError_t launch_decompose<R>(R*, const R*, int, int, const double*, double,    \
                                           hipStream_t);                                     \
   template hipError_t launch_inner<R>(const R*, const R*, uint64_t, double*, hipStream_t);  \

@@ -50,6 +50,31 @@ __global__ void __launch_bounds__(kBlock) k_mlp_forward(const float* __restrict_
   logit[r] = z;
 }
 
+// Scoring of a few rows: one wavefront per row, lane j owns hidden unit j of
+// both layers (weight columns read coalesced), the output dot product summed
+// across the wavefront in a fixed butterfly order. X and logit may live in
+// mapped host memory.
+__global__ void __launch_bounds__(kH) k_mlp_score(const float* __restrict__ P,
+                                                  const float* __restrict__ X,
+                                                  float* __restrict__ logit) {
+  __shared__ float x[kIn], h1[kH];
+  const int r = blockIdx.x, j = threadIdx.x;
+  if (j < kIn) x[j] = X[size_t(r) * kIn + j];
+  __syncthreads();
+  float s = P[oB1 + j];
+#pragma unroll 8
+  for (int i = 0; i < kIn; ++i) s += x[i] * P[oW1 + i * kH + j];
+  h1[j] = tanhf(s);
+  __syncthreads();
+  float s2 = P[oB2 + j];
+#pragma unroll 8
+  for (int i = 0; i < kH; ++i) s2 += h1[i] * P[oW2 + i * kH + j];
+  float v = tanhf(s2) * P[oW3 + j];
+#pragma unroll
+  for (int off = kH / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kH);
+  if (j == 0) logit[r] = v + P[oB3];
+}
+
 // Per-row backward of the mean binary cross-entropy over `rows` rows:
 // dz3 = (sigmoid(z) - y)/rows, dz2 = dz3 W3 * (1 - h2^2), dz1 = (dz2 W2^T) * (1 - h1^2).
 __global__ void __launch_bounds__(kBlock) k_mlp_delta(const float* __restrict__ P,
@@ -143,6 +168,12 @@ unsigned blocks(int n) { return unsigned((n + kBlock - 1) / kBlock); }
 }  // namespace
 
 int mlp_param_count() { return kParams; }
+
+hipError_t launch_mlp_score(const float* P, const float* X, int rows, float* logit,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_score, dim3(rows), dim3(kH), 0, s, P, X, logit);
+  return hipGetLastError();
+}
 
 hipError_t launch_mlp_forward(const float* P, const float* X, int rows, float* logit, float* H1,
                               float* H2, hipStream_t s) {

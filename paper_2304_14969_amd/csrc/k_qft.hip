@@ -248,9 +248,12 @@ __device__ __forceinline__ void tile_rounds(Cx<R>* sm, int TB, int b_lo, int b_h
 }
 
 // Contiguous tile [0, T): stages of the bits [lo, hi), hi <= T.
+// Two workgroups of a complex64 tile (2 x 68 KiB) share a CU; the bound of
+// two waves per SIMD (at most 256 VGPRs) keeps both resident.
 template <typename R, int T, bool REV, int NT, int WMAX>
-__global__ void __launch_bounds__(NT) k_qft_lds(R* __restrict__ a, int start, int len, int lo,
-                                                int hi, int sign, R scale, Roots32<R> rt) {
+__global__ void __launch_bounds__(NT, sizeof(R) == 4 ? 2 : 1)
+    k_qft_lds(R* __restrict__ a, int start, int len, int lo, int hi, int sign, R scale,
+              Roots32<R> rt) {
   extern __shared__ unsigned char smraw[];
   Cx<R>* sm = reinterpret_cast<Cx<R>*>(smraw);
   using V = typename Vec16<R>::T;
@@ -443,7 +446,9 @@ hipError_t launch_col(R* a, int n, int start, int len, int lo, int sign, R scale
 template <typename R, int T, bool REV>
 hipError_t launch_lds_t(R* a, int n, int start, int len, int lo, int hi, int sign, R scale,
                         const Roots32<R>& rt, const QftTuning& tune, hipStream_t s) {
-  if (T < 11 || (tune.threads < 512 && tune.round_bits < 5))
+  // complex128 stays at rounds of 4 bits: 32 double-precision amplitudes per
+  // thread would leave one wave per SIMD
+  if (T < 11 || sizeof(R) == 8 || (tune.threads < 512 && tune.round_bits < 5))
     return launch_lds_cfg<R, T, REV, 256, 4>(a, n, start, len, lo, hi, sign, scale, rt, s);
   if (tune.threads >= 512 && tune.round_bits >= 5)
     return launch_lds_cfg<R, T, REV, 512, 5>(a, n, start, len, lo, hi, sign, scale, rt, s);

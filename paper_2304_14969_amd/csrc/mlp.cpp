@@ -67,17 +67,12 @@ namespace qs {
 int mlp_scores(qs_mlp* net, const float* X, uint64_t rows, float* scores) {
   if (rows == 0) return QS_OK;
   if (rows <= uint64_t(kScoreRows)) {
-    // the usual case (the dirty qubits of one separation round): staged
-    // through pinned host memory, no allocation
+    // the usual case (the dirty qubits of one separation round): the kernel
+    // reads the rows from and writes the logits to mapped pinned memory
     float* hz = net->hscore + kScoreRows * QS_MLP_INPUTS;
     float* dz = net->dscore + kScoreRows * QS_MLP_INPUTS;
     std::memcpy(net->hscore, X, rows * QS_MLP_INPUTS * sizeof(float));
-    hipError_t e = hipMemcpyAsync(net->dscore, net->hscore, rows * QS_MLP_INPUTS * sizeof(float),
-                                  hipMemcpyHostToDevice, net->stream);
-    if (e == hipSuccess)
-      e = launch_mlp_forward(net->P, net->dscore, int(rows), dz, nullptr, nullptr, net->stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(hz, dz, rows * sizeof(float), hipMemcpyDeviceToHost, net->stream);
+    hipError_t e = launch_mlp_score(net->P, net->dscore, int(rows), dz, net->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
     if (int rc = merr(e, "network forward")) return rc;
     for (uint64_t r = 0; r < rows; ++r) scores[r] = 1.0f / (1.0f + std::exp(-hz[r]));
@@ -112,9 +107,10 @@ int qs_mlp_create(qs_mlp** out) {
     return mfail(QS_E_NOMEM, "network parameters");
   }
   const size_t score_floats = size_t(kScoreRowsFloats);
-  n->dscore = static_cast<float*>(qs::device_alloc(score_floats * sizeof(float)));
-  if (!n->dscore || hipHostMalloc(reinterpret_cast<void**>(&n->hscore), score_floats * sizeof(float)) != hipSuccess) {
-    qs::device_free(n->dscore);
+  if (hipHostMalloc(reinterpret_cast<void**>(&n->hscore), score_floats * sizeof(float),
+                    hipHostMallocMapped) != hipSuccess ||
+      hipHostGetDevicePointer(reinterpret_cast<void**>(&n->dscore), n->hscore, 0) != hipSuccess) {
+    if (n->hscore) (void)hipHostFree(n->hscore);
     qs::device_free(blk);
     delete n;
     return mfail(QS_E_NOMEM, "network scoring buffers");
@@ -127,7 +123,6 @@ int qs_mlp_create(qs_mlp** out) {
   std::vector<float> zero(size_t(4) * np, 0.0f);
   hipError_t e = hipMemcpy(blk, zero.data(), zero.size() * sizeof(float), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
-    qs::device_free(n->dscore);
     (void)hipHostFree(n->hscore);
     qs::device_free(blk);
     delete n;
@@ -141,7 +136,6 @@ int qs_mlp_free(qs_mlp* n) {
   if (!n) return QS_OK;
   (void)hipStreamSynchronize(n->stream);
   qs::device_free(n->block);
-  qs::device_free(n->dscore);
   (void)hipHostFree(n->hscore);
   delete n;
   return QS_OK;

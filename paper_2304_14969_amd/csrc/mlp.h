@@ -12,8 +12,8 @@ struct qs_mlp {
   float* V = nullptr;
   float* G = nullptr;
   hipStream_t stream = nullptr;
-  float* dscore = nullptr;  // device rows for scoring: kScoreRows x 32 inputs, then logits
-  float* hscore = nullptr;  // pinned host staging of the same layout
+  float* hscore = nullptr;  // pinned, mapped: kScoreRows x 32 inputs, then kScoreRows logits
+  float* dscore = nullptr;  // its device address
 };
 
 namespace qs {
@@ -21,6 +21,9 @@ constexpr int kScoreRows = 64;  // rows scored through the pinned staging
 int mlp_param_count();
 hipError_t launch_mlp_forward(const float* P, const float* X, int rows, float* logit, float* H1,
                               float* H2, hipStream_t s);
+// One wavefront per row; X and logit may be mapped host memory.
+hipError_t launch_mlp_score(const float* P, const float* X, int rows, float* logit,
+                            hipStream_t s);
 hipError_t launch_mlp_backward(const float* P, const float* X, const float* y, int rows,
                                const float* z, const float* H1, const float* H2, float* D3,
                                float* D2, float* D1, float* L, float* G, hipStream_t s);

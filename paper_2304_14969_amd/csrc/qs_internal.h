@@ -88,13 +88,18 @@ hipError_t launch_batch_reset(R* arena, uint64_t total_amps, const uint64_t* off
                               hipStream_t s);
 
 // ---------------------------------------------------------------- factorized mode
-// scratch: factor_scratch_doubles() doubles of device memory; results land in
-// scratch[0..3] (bloch: Re s, Im s, z0, z1; inner: Re, Im).
+// scratch: factor_scratch_doubles() doubles of device memory; inner products
+// land in scratch[0..1] (Re, Im).
 int factor_scratch_doubles();
 template <typename R>
 hipError_t launch_compose(R* c, const R* a, int na, const R* b, int nb, hipStream_t s);
+// Bloch sums of the qubit at bit t (Re s, Im s, z0, z1) written to out[0..3],
+// which may be host memory mapped into the device address space.
 template <typename R>
-hipError_t launch_bloch(const R* a, int nq, int t, double* scratch, hipStream_t s);
+hipError_t launch_bloch(const R* a, int nq, int t, double* scratch, double* out, hipStream_t s);
+// A one-qubit subsystem: the two amplitudes amp = {Re a0, Im a0, Re a1, Im a1}.
+template <typename R>
+hipError_t launch_store_single(R* dst, const double amp[4], hipStream_t s);
 // phi = {Re phi0, Im phi0, Re phi1, Im phi1}
 template <typename R>
 hipError_t launch_decompose(R* b, const R* a, int nq, int t, const double phi[4], double scale,

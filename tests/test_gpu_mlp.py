@@ -25,6 +25,9 @@ def test_forward_and_gradient_match_oracle(qs_lib):
     rel = np.linalg.norm(grad - gw) / np.linalg.norm(gw)
     assert rel < 1e-4, rel
     assert abs(loss - omlp.loss(params, X, y)) < 1e-5
+    # a few rows (the scoring path of the proposal, one wavefront per row)
+    few = net.forward(X[:40])
+    np.testing.assert_allclose(few, want[:40], atol=2e-6, rtol=1e-5)
     # the gradient is a real descent direction: a small step lowers the loss
     step = omlp.unflatten(omlp.flatten(params) - 0.05 * grad.astype(np.float64))
     assert omlp.loss(step, X, y) < omlp.loss(params, X, y)
