@@ -32,7 +32,8 @@ HBM_PEAK_GBS = 8000.0
 # (`bench.py --calibrate-copy`: FETCH_SIZE reads 0.5000 of the bytes copied,
 # WRITE_SIZE 1.0000). Valid only for the kernel source they were taken on.
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_2304_14969_amd", "csrc", "k_qft.hip")
-TRAFFIC = {"sha256": None, "bytes_per_launch": {}}
+TRAFFIC = {"sha256": "0e0fad793fcc55b2d1f38950b3470a471ca5914dd67b493fb5c93961ad42c0a2",
+           "bytes_per_launch": {"qft_col7": 2147578349, "qft_lds": 2147697273}}
 
 
 def measured_traffic(kernel: str):
@@ -314,6 +315,20 @@ def main() -> int:
     # sanity: norm preserved after all the transforms
     norm = st.norm()
 
+    # a device-to-device copy of 1 GiB: the bandwidth a plain streaming kernel
+    # reaches on this card (context for the roofline fraction)
+    src = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbps = 5 * 2 * src.numel() * 4 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
+
     # gate-by-gate QFT for comparison (27 H, 351 CP, 13 relabels)
     st.set_amplitudes(workloads.gaussian_state(n, 0))
     gates = [g for g in _qft_gates(n)]
@@ -344,6 +359,7 @@ def main() -> int:
                                "i.i.d. complex Gaussian input (seed 0), state resident in HBM",
                    "n": n, "passes_per_qft": passes, "tuning": tuning},
         "hbm_GBps_effective": total_bytes / (ms_per_step * 1e-3) / 1e9,
+        "hbm_copy_GBps": copy_gbps,
         "wall_ms_per_step": wall * 1e3 / args.steps,
         "gate_by_gate_ms": gate_by_gate_ms,
         "norm_after": norm,

@@ -378,6 +378,10 @@ int qs_check(qs_state* st, double tol);
  *   "qft.threads"    thread cap of the LDS tile launches: 256 or 512 (default);
  *   "qft.round_bits" widest in-register round inside an LDS tile: 4 or 5
  *                    (default);
+ *   "factor.multi_test" 1 (default): the plain separability schedule
+ *                    measures the lowest dirty qubit together with the next
+ *                    dirty qubits of its subsystem (up to 5, none skipped) in
+ *                    one sweep; 0: one sweep per qubit. Same decisions;
  *   "fused.mfma"     1 (default): complex64 blocks of 4 or 5 qubits run on the
  *                    matrix cores when their geometry fits; 0: vector FMA.
  * QS_E_INVAL for an unknown key or a value out of range. */

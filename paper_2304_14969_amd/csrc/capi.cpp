@@ -277,6 +277,9 @@ int qs_tune_set(const char* key, int64_t value) {
   } else if (!std::strcmp(key, "qft.round_bits")) {
     if (value != 4 && value != 5) return fail(QS_E_INVAL, "qft.round_bits must be 4 or 5");
     g_qft_tune.round_bits = int(value);
+  } else if (!std::strcmp(key, "factor.multi_test")) {
+    if (value < 0 || value > 1) return fail(QS_E_INVAL, "factor.multi_test must be 0 or 1");
+    qs::g_multi_test = int(value);
 
   } else {
     return fail(QS_E_INVAL, "unknown tuning key '%s'", key);
@@ -291,6 +294,7 @@ int qs_tune_get(const char* key, int64_t* value) {
   else if (!std::strcmp(key, "qft.threads")) *value = g_qft_tune.threads;
   else if (!std::strcmp(key, "fused.mfma")) *value = g_fused_mfma;
   else if (!std::strcmp(key, "qft.round_bits")) *value = g_qft_tune.round_bits;
+  else if (!std::strcmp(key, "factor.multi_test")) *value = qs::g_multi_test;
   else return fail(QS_E_INVAL, "unknown tuning key '%s'", key);
   return QS_OK;
 }

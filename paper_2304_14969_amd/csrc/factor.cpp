@@ -31,6 +31,8 @@
 
 namespace qs {
 
+int g_multi_test = 1;
+
 void* device_alloc(size_t bytes);
 void device_free(void* p);
 void set_last_error(const char* msg);
@@ -54,6 +56,8 @@ int dev_err(hipError_t e, const char* what) {
 }
 
 size_t amp_bytes(const FactorState* f) { return f->dtype == QS_C64 ? 8 : 16; }
+
+constexpr int kMultiTest = 5;  // qubits per multi-qubit Bloch sweep
 
 // Upload a small host vector of complex doubles as the state's precision.
 hipError_t upload(const FactorState* f, void* dst, const double* re_im, size_t count) {
@@ -159,27 +163,12 @@ int merge(FactorState* f, int ia, int ib, int* out) {
   return QS_OK;
 }
 
-// One separability attempt on qubit q (Eq. sdrp); *rounded on success.
-int test_qubit(FactorState* f, int q, double p, bool* rounded) {
+// The decision on qubit q at bit t of subsystem si from its Bloch sums
+// st = {Re s, Im s, z0, z1} (Sec. III-A, Eq. sdrp); *rounded on success.
+int decide_qubit(FactorState* f, int q, int si, int t, const double st[4], double p,
+                 bool* rounded) {
   *rounded = false;
-  f->dirty &= ~(uint64_t(1) << q);
-  f->deferred &= ~(uint64_t(1) << q);
-  int t = 0;
-  const int si = find(f, q, &t);
-  if (si < 0) return ffail(QS_E_INVAL, "qubit %d not found", q);
-  if (f->subs[si].nq == 1) return QS_OK;
-  // features as seen before the test, aligned with the attempt log
-  if (f->feat_log && f->log_count && *f->log_count < f->feat_cap)
-    fact_features(f, q, p, f->feat_log + *f->log_count * QS_MLP_INPUTS);
   Sub& S = f->subs[si];
-  hipError_t e = f->dtype == QS_C64
-                     ? launch_bloch(static_cast<const float*>(S.amps), S.nq, t, f->scratch,
-                                    f->dstat, f->stream)
-                     : launch_bloch(static_cast<const double*>(S.amps), S.nq, t, f->scratch,
-                                    f->dstat, f->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
-  if (int rc = dev_err(e, "bloch")) return rc;
-  const double st[4] = {f->hstat[0], f->hstat[1], f->hstat[2], f->hstat[3]};
   // Bloch vector of rho_q (Sec. III-A, step 1) and eps = (1 - |r|)/2 (step 2)
   const double nrm = st[2] + st[3];
   if (!(nrm > 0.0)) return ffail(QS_E_NUMERIC, "subsystem of qubit %d has zero norm", q);
@@ -212,7 +201,8 @@ int test_qubit(FactorState* f, int q, double p, bool* rounded) {
     sub_free(f, S.nq - 1, rest);
     return rc;
   }
-  e = f->dtype == QS_C64
+  const hipError_t e =
+      f->dtype == QS_C64
           ? launch_decompose(static_cast<float*>(rest), static_cast<const float*>(S.amps), S.nq, t,
                              phi, scale, f->stream)
           : launch_decompose(static_cast<double*>(rest), static_cast<const double*>(S.amps), S.nq,
@@ -236,35 +226,133 @@ int test_qubit(FactorState* f, int q, double p, bool* rounded) {
   return QS_OK;
 }
 
-// Plain schedule: the lowest-numbered dirty qubit until none is dirty.
+// Bookkeeping shared by every exact test: the qubit leaves the dirty and
+// deferred sets, and its features (as seen before the test) are logged.
+void begin_test(FactorState* f, int q, double p) {
+  f->dirty &= ~(uint64_t(1) << q);
+  f->deferred &= ~(uint64_t(1) << q);
+  if (f->feat_log && f->log_count && *f->log_count < f->feat_cap)
+    fact_features(f, q, p, f->feat_log + *f->log_count * QS_MLP_INPUTS);
+}
+
+// One separability attempt on qubit q (Eq. sdrp); *rounded on success.
+int test_qubit(FactorState* f, int q, double p, bool* rounded) {
+  *rounded = false;
+  int t = 0;
+  const int si = find(f, q, &t);
+  if (si < 0) return ffail(QS_E_INVAL, "qubit %d not found", q);
+  if (f->subs[si].nq == 1) {
+    f->dirty &= ~(uint64_t(1) << q);
+    f->deferred &= ~(uint64_t(1) << q);
+    return QS_OK;
+  }
+  begin_test(f, q, p);
+  const Sub& S = f->subs[si];
+  hipError_t e = f->dtype == QS_C64
+                     ? launch_bloch(static_cast<const float*>(S.amps), S.nq, t, f->scratch,
+                                    f->dstat, f->stream)
+                     : launch_bloch(static_cast<const double*>(S.amps), S.nq, t, f->scratch,
+                                    f->dstat, f->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+  if (int rc = dev_err(e, "bloch")) return rc;
+  const double st[4] = {f->hstat[0], f->hstat[1], f->hstat[2], f->hstat[3]};
+  return decide_qubit(f, q, si, t, st, p, rounded);
+}
+
+// G >= 2 dirty qubits of subsystem si (ascending global numbers, local bits
+// ts): their Bloch sums in one sweep, then the decisions in order, stopping
+// at the first rounding (which changes the subsystem; the rest stay dirty).
+// The decisions are those of testing the qubits one after another.
+int test_batch(FactorState* f, int si, const int* qs_, const int* ts, int G, double p,
+               int* count) {
+  int order[kMultiTest], bits[kMultiTest];
+  for (int i = 0; i < G; ++i) order[i] = i;
+  std::sort(order, order + G, [ts](int x, int y) { return ts[x] < ts[y]; });
+  for (int i = 0; i < G; ++i) bits[i] = ts[order[i]];
+  const Sub& S = f->subs[si];
+  hipError_t e = f->dtype == QS_C64
+                     ? launch_bloch_multi(static_cast<const float*>(S.amps), S.nq, bits, G,
+                                          f->scratch, f->dstat, f->stream)
+                     : launch_bloch_multi(static_cast<const double*>(S.amps), S.nq, bits, G,
+                                          f->scratch, f->dstat, f->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+  if (int rc = dev_err(e, "bloch")) return rc;
+  double st[kMultiTest][4];
+  for (int i = 0; i < G; ++i)
+    for (int k = 0; k < 4; ++k) st[order[i]][k] = f->hstat[4 * i + k];
+  for (int i = 0; i < G; ++i) {
+    begin_test(f, qs_[i], p);
+    bool rounded = false;
+    if (int rc = decide_qubit(f, qs_[i], si, ts[i], st[i], p, &rounded)) return rc;
+    if (rounded) {
+      *count += 1;
+      break;
+    }
+  }
+  return QS_OK;
+}
+
+// Exact test of the lowest qubit of `mask` (dirty qubits only) and, with
+// multi-qubit sweeps on, of the next ones of `mask` in ascending order while
+// they share its subsystem (up to kMultiTest). *rounded if one was rounded.
+int test_lowest(FactorState* f, uint64_t mask, double p, int* count, bool* rounded) {
+  *rounded = false;
+  mask &= f->dirty;
+  if (!mask) return QS_OK;
+  const int q = __builtin_ctzll(mask);
+  int t = 0;
+  const int si = find(f, q, &t);
+  if (si < 0) return ffail(QS_E_INVAL, "qubit %d not found", q);
+  int bq[kMultiTest] = {q}, bt[kMultiTest] = {t}, G = 1;
+  if (g_multi_test && f->subs[si].nq > 1) {
+    for (uint64_t d = mask & (mask - 1); d && G < kMultiTest; d &= d - 1) {
+      const int q2 = __builtin_ctzll(d);
+      int t2 = 0;
+      if (find(f, q2, &t2) != si) break;
+      bq[G] = q2;
+      bt[G] = t2;
+      ++G;
+    }
+  }
+  const int before = *count;
+  if (G == 1) {
+    bool r = false;
+    if (int rc = test_qubit(f, q, p, &r)) return rc;
+    *count += r;
+  } else if (int rc = test_batch(f, si, bq, bt, G, p, count)) {
+    return rc;
+  }
+  *rounded = *count > before;
+  return QS_OK;
+}
+
+// Plain schedule: the lowest-numbered dirty qubit until none is dirty (with
+// multi-qubit sweeps, the next dirty qubits of its subsystem alongside).
 int plain_separate(FactorState* f, double p, int* count) {
   while (f->dirty) {
-    const int q = __builtin_ctzll(f->dirty);
     bool rounded = false;
-    if (int rc = test_qubit(f, q, p, &rounded)) return rc;
-    *count += rounded;
+    if (int rc = test_lowest(f, f->dirty, p, count, &rounded)) return rc;
   }
   return QS_OK;
 }
 
 // Learned schedule: dirty qubits of subsystems smaller than propose_min get
 // the exact test directly; the others are scored in one forward pass, the
-// proposals tested (ascending) and the rest deferred; repeat for qubits made
-// dirty by a rounding.
+// rest deferred and the proposals tested in ascending order until one is
+// rounded, after which the qubits made dirty are scored again.
 int proposed_separate(FactorState* f, double p, int* count) {
   std::vector<int> cand;
   std::vector<float> X, score;
   while (f->dirty) {
-    int small = -1;
-    for (uint64_t d = f->dirty; d && small < 0; d &= d - 1) {
+    uint64_t small = 0;
+    for (uint64_t d = f->dirty; d; d &= d - 1) {
       const int q = __builtin_ctzll(d);
       const int si = find(f, q, nullptr);
-      if (si >= 0 && f->subs[si].nq < f->propose_min) small = q;
+      if (si >= 0 && f->subs[si].nq < f->propose_min) small |= uint64_t(1) << q;
     }
-    if (small >= 0) {
+    if (small) {
       bool rounded = false;
-      if (int rc = test_qubit(f, small, p, &rounded)) return rc;
-      *count += rounded;
+      if (int rc = test_lowest(f, small, p, count, &rounded)) return rc;
       continue;
     }
     cand.clear();
@@ -273,18 +361,21 @@ int proposed_separate(FactorState* f, double p, int* count) {
     for (size_t i = 0; i < cand.size(); ++i) fact_features(f, cand[i], p, &X[i * QS_MLP_INPUTS]);
     score.assign(cand.size(), 0.0f);
     if (int rc = mlp_scores(f->proposer, X.data(), cand.size(), score.data())) return rc;
+    uint64_t prop = 0;
     for (size_t i = 0; i < cand.size(); ++i) {
-      const int q = cand[i];
-      if (!((f->dirty >> q) & 1)) continue;
+      const uint64_t bit = uint64_t(1) << cand[i];
       if (score[i] >= f->cutoff) {
-        bool rounded = false;
-        if (int rc = test_qubit(f, q, p, &rounded)) return rc;
-        *count += rounded;
+        prop |= bit;
       } else {
-        f->dirty &= ~(uint64_t(1) << q);
-        f->deferred |= uint64_t(1) << q;
+        f->dirty &= ~bit;
+        f->deferred |= bit;
         ++f->skipped;
       }
+    }
+    while (prop & f->dirty) {
+      bool rounded = false;
+      if (int rc = test_lowest(f, prop, p, count, &rounded)) return rc;
+      if (rounded) break;
     }
   }
   return QS_OK;

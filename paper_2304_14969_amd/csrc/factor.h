@@ -56,6 +56,10 @@ struct FactorState {
   uint64_t feat_cap = 0;
 };
 
+// Process-wide: measure several dirty qubits of one subsystem per sweep (1,
+// default) or one qubit per sweep (0). Decisions are the same either way.
+extern int g_multi_test;
+
 // The 32 proposal features of qubit q (threshold p) from the bookkeeping.
 void fact_features(const FactorState* f, int q, double p, float* out);
 

@@ -16,6 +16,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kRedBlocks = 1024;
+constexpr int kMaxMulti = 5;  // qubits per multi-qubit Bloch sweep
 
 __device__ __forceinline__ uint64_t insert_zero(uint64_t x, int pos) {
   const uint64_t lo = x & ((uint64_t(1) << pos) - 1);
@@ -91,6 +92,61 @@ __global__ void __launch_bounds__(kBlock) k_bloch_small(const R* __restrict__ a,
   block_sum<4>(v, sh);
   if (threadIdx.x == 0)
     for (int k = 0; k < 4; ++k) out[k] = v[k];
+}
+
+// The Bloch sums of G qubits of one subsystem in one sweep. Each thread
+// gathers the 2^G amplitudes that differ only in the target bits (ascending
+// in `bits`) and adds, for every target j, the pairs that differ in bit j.
+// Output row 4j+k (k = Re s, Im s, z0, z1) of `partial` per workgroup, or of
+// `out` directly when the launch has one workgroup.
+struct Bits8 {
+  int b[8];
+};
+
+template <typename R, int G>
+__global__ void __launch_bounds__(kBlock) k_bloch_multi(const R* __restrict__ a, uint64_t groups,
+                                                        Bits8 bits, double* __restrict__ partial,
+                                                        double* __restrict__ out) {
+  constexpr int D = 1 << G;
+  __shared__ double sh[4 * G * kBlock];
+  double v[4 * G];
+#pragma unroll
+  for (int k = 0; k < 4 * G; ++k) v[k] = 0.0;
+  const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+  for (uint64_t g = uint64_t(blockIdx.x) * kBlock + threadIdx.x; g < groups; g += stride) {
+    uint64_t base = g;
+#pragma unroll
+    for (int j = 0; j < G; ++j) base = insert_zero(base, bits.b[j]);
+    R x[D], y[D];
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+      uint64_t o = base;
+#pragma unroll
+      for (int j = 0; j < G; ++j) o |= uint64_t((m >> j) & 1) << bits.b[j];
+      x[m] = a[2 * o];
+      y[m] = a[2 * o + 1];
+    }
+#pragma unroll
+    for (int j = 0; j < G; ++j)
+#pragma unroll
+      for (int m = 0; m < D; ++m) {
+        if (m & (1 << j)) continue;
+        const int m1 = m | (1 << j);
+        const double x0 = x[m], y0 = y[m], x1 = x[m1], y1 = y[m1];
+        v[4 * j + 0] += x0 * x1 + y0 * y1;
+        v[4 * j + 1] += x0 * y1 - y0 * x1;
+        v[4 * j + 2] += x0 * x0 + y0 * y0;
+        v[4 * j + 3] += x1 * x1 + y1 * y1;
+      }
+  }
+  block_sum<4 * G>(v, sh);
+  if (threadIdx.x == 0) {
+    if (gridDim.x == 1) {
+      for (int k = 0; k < 4 * G; ++k) out[k] = v[k];
+    } else {
+      for (int k = 0; k < 4 * G; ++k) partial[k * gridDim.x + blockIdx.x] = v[k];
+    }
+  }
 }
 
 template <typename R>
@@ -180,7 +236,7 @@ unsigned red_blocks(uint64_t n) {
 
 }  // namespace
 
-int factor_scratch_doubles() { return 4 * kRedBlocks + 8; }
+int factor_scratch_doubles() { return 4 * kMaxMulti * kRedBlocks + 8; }
 
 template <typename R>
 hipError_t launch_compose(R* c, const R* a, int na, const R* b, int nb, hipStream_t s) {
@@ -203,6 +259,38 @@ hipError_t launch_bloch(const R* a, int nq, int t, double* scratch, double* out,
   hipLaunchKernelGGL(k_bloch_partial<R>, dim3(nb), dim3(kBlock), 0, s, a, pairs, t, scratch + 8);
   hipLaunchKernelGGL(k_sum_rows<4>, dim3(1), dim3(kBlock), 0, s, scratch + 8, int(nb), out);
   return hipGetLastError();
+}
+
+template <typename R, int G>
+hipError_t launch_multi_g(const R* a, int nq, const int* bits, double* scratch, double* out,
+                          hipStream_t s) {
+  Bits8 b{};
+  for (int j = 0; j < G; ++j) b.b[j] = bits[j];
+  const uint64_t groups = uint64_t(1) << (nq - G);
+  // one workgroup for small subsystems (same bound in amplitudes as the
+  // one-qubit path), else the partial sums of up to kRedBlocks workgroups
+  if ((groups << G) <= 2 * kSmallPairs) {
+    hipLaunchKernelGGL((k_bloch_multi<R, G>), dim3(1), dim3(kBlock), 0, s, a, groups, b, nullptr,
+                       out);
+    return hipGetLastError();
+  }
+  const unsigned nb = red_blocks(groups);
+  hipLaunchKernelGGL((k_bloch_multi<R, G>), dim3(nb), dim3(kBlock), 0, s, a, groups, b,
+                     scratch + 8, nullptr);
+  hipLaunchKernelGGL(k_sum_rows<4 * G>, dim3(1), dim3(kBlock), 0, s, scratch + 8, int(nb), out);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_bloch_multi(const R* a, int nq, const int* bits, int G, double* scratch,
+                              double* out, hipStream_t s) {
+  switch (G) {
+    case 2: return launch_multi_g<R, 2>(a, nq, bits, scratch, out, s);
+    case 3: return launch_multi_g<R, 3>(a, nq, bits, scratch, out, s);
+    case 4: return launch_multi_g<R, 4>(a, nq, bits, scratch, out, s);
+    case 5: return launch_multi_g<R, 5>(a, nq, bits, scratch, out, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <typename R>
@@ -240,6 +328,8 @@ hipError_t launch_gather_mul(const R* a, const uint64_t* idx, uint64_t m, Perm64
   template hipError_t launch_compose<R>(R*, const R*, int, const R*, int, hipStream_t);     \
   template hipError_t launch_bloch<R>(const R*, int, int, double*, double*, hipStream_t);   \
   template hipError_t launch_store_single<R>(R*, const double*, hipStream_t);               \
+  template hipError_t launch_bloch_multi<R>(const R*, int, const int*, int, double*, double*, \
+                                            hipStream_t);                                   \
   template hipError_t launch_decompose<R>(R*, const R*, int, int, const double*, double,    \
                                           hipStream_t);                                     \
   template hipError_t launch_inner<R>(const R*, const R*, uint64_t, double*, hipStream_t);  \

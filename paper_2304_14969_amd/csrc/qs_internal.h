@@ -97,6 +97,11 @@ hipError_t launch_compose(R* c, const R* a, int na, const R* b, int nb, hipStrea
 // which may be host memory mapped into the device address space.
 template <typename R>
 hipError_t launch_bloch(const R* a, int nq, int t, double* scratch, double* out, hipStream_t s);
+// Bloch sums of G = 2..5 qubits (local bits `bits`, ascending) in one sweep:
+// out[4j .. 4j+3] for bits[j].
+template <typename R>
+hipError_t launch_bloch_multi(const R* a, int nq, const int* bits, int G, double* scratch,
+                              double* out, hipStream_t s);
 // A one-qubit subsystem: the two amplitudes amp = {Re a0, Im a0, Re a1, Im a1}.
 template <typename R>
 hipError_t launch_store_single(R* dst, const double amp[4], hipStream_t s);

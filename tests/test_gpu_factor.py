@@ -192,3 +192,32 @@ def test_fidelity_exact_pipeline(qs_lib):
     assert 0 < st.fidelity_estimate() <= 1
     for s in (st, approx, exact):
         s.free()
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_multi_qubit_sweeps_keep_the_decisions(qs_lib, dtype):
+    """Measuring several dirty qubits of a subsystem in one sweep gives the
+    attempt sequence of one sweep per qubit (same qubits, sizes and decisions;
+    eps equal up to summation order)."""
+    qs = qs_lib
+    n = 16
+    saved = qs.tune_get("factor.multi_test")
+    logs, fs = [], []
+    try:
+        for multi in (0, 1):
+            qs.tune_set("factor.multi_test", multi)
+            for gates, p in ((workloads.grid_circuit(4, 4, 6, 2), 0.3),
+                             (workloads.random_circuit(n, 6, 8), 0.2)):
+                st = gpu_run(qs, n, gates, p, dtype)
+                logs.append(st.attempts())
+                fs.append(st.fidelity_estimate())
+                st.free()
+    finally:
+        qs.tune_set("factor.multi_test", saved)
+    tol = 1e-9 if dtype == C128 else 1e-6
+    for a, b in zip(logs[:2], logs[2:]):
+        assert len(a) == len(b) and len(a) > 20
+        assert [(x[0], x[1], x[3]) for x in a] == [(x[0], x[1], x[3]) for x in b]
+        assert max(abs(x[2] - y[2]) for x, y in zip(a, b)) <= tol
+    for fa, fb in zip(fs[:2], fs[2:]):
+        assert abs(fa - fb) <= 1e-9 * max(1.0, fa) + tol

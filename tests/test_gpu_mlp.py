@@ -104,7 +104,9 @@ def test_proposer_gate_below_min_size_is_plain(qs_lib):
                             min_qubits=13)
     assert b["skipped"] == 0
     assert [(q, n, r) for q, n, _, r in a["log"]] == [(q, n, r) for q, n, _, r in b["log"]]
-    assert b["F"] == a["F"]
+    # the plain schedule may measure several qubits per sweep (another
+    # summation order): F agrees to rounding
+    assert abs(b["F"] - a["F"]) <= 1e-12 * a["F"]
     with pytest.raises(qs.QSError):
         st = qs.State(4, factorized=True, max_amps=16)
         try:
