@@ -90,32 +90,49 @@ def _kernel_rates(prof: dict, flops_of=None) -> dict:
 def bench_circuit(qs, workloads, torch, n: int = 32, layers: int = 10, seed: int = 0,
                   kmax: int = 4) -> dict:
     """Exact random circuit (U3 on every qubit, then CZ/iSWAP on a random
-    matching, per layer) fused into blocks of at most kmax qubits."""
+    matching, per layer): tile passes (several gates per HBM sweep, rounds of
+    dense 4-qubit blocks on the matrix cores), and for comparison one sweep
+    per fused block of at most kmax qubits."""
+    gates = workloads.random_circuit(n, layers, seed)
     st = qs.State(n, qs.C64)
-    c = qs.Circuit(n).add_gates(workloads.random_circuit(n, layers, seed)).plan(kmax)
-    st.run(c)
-    torch.cuda.synchronize()
-    st.set_basis(0)
-    st.profile_start()
-    t0 = time.perf_counter()
-    st.run(c)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = st.profile_stop()
-    norm = st.norm()
+    out = {"workload": f"random circuit n={n}, {layers} layers (U3 + CZ/iSWAP matching), "
+                       f"seed {seed}, complex64", "gates": len(gates)}
+    for mode in ("tiles", "blocks"):
+        c = qs.Circuit(n).add_gates(gates)
+        if mode == "tiles":
+            c.use_tiles()
+            ti = c.tile_info(qs.C64)
+        else:
+            c.plan(kmax)
+        st.set_basis(0)
+        st.run(c)
+        torch.cuda.synchronize()
+        st.set_basis(0)
+        st.profile_start()
+        t0 = time.perf_counter()
+        st.run(c)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = st.profile_stop()
+        norm = st.norm()
+        if mode == "tiles":
+            def flops(name, rounds=ti["rounds"], passes=ti["passes"]):
+                # dense 16x16 complex blocks: 8 x 16 real flops per amplitude per round
+                return 8.0 * 16 * 2 ** n * rounds / passes if name == "tile_mfma" else 0.0
+            out["tiles"] = {"s": round(dt, 4), "sweeps": ti["passes"], "rounds": ti["rounds"],
+                            "norm_after": norm, "kernels": _kernel_rates(prof, flops)}
+        else:
+            def flops(name):  # complex (2^k x 2^k) times 2^n amplitudes, 8 real flops per MAC
+                for k in (4, 5):
+                    if name.startswith(f"fused{k}_mfma"):
+                        return 8.0 * 2 ** k * 2 ** n
+                return 0.0
+            out[f"blocks_k{kmax}"] = {"s": round(dt, 4), "sweeps": c.info()["blocks"],
+                                      "norm_after": norm, "kernels": _kernel_rates(prof, flops)}
+        c.free()
     st.free()
-    info = c.info()
-    c.free()
-
-    def flops(name):  # complex (2^k x 2^k) times 2^n amplitudes, 8 real flops per MAC
-        for k in (4, 5):
-            if name.startswith(f"fused{k}_mfma"):
-                return 8.0 * 2 ** k * 2 ** n
-        return 0.0
-    return {"workload": f"random circuit n={n}, {layers} layers (U3 + CZ/iSWAP matching), "
-                        f"seed {seed}, complex64, blocks of <= {kmax} qubits",
-            "s": round(dt, 4), "gates": info["gates"], "sweeps": info["blocks"],
-            "norm_after": norm, "kernels": _kernel_rates(prof, flops)}
+    out["s"] = out["tiles"]["s"]
+    return out
 
 
 def bench_approx(qs, workloads, protocol, np, family: str, p_cmp: float = 0.6,

@@ -304,6 +304,21 @@ int qs_circuit_add_matrix(qs_circuit* c, const int* qubits, int k, const double*
  * union has at most kmax qubits, otherwise those blocks are closed. Block
  * matrices are products of the gates in float64. */
 int qs_circuit_plan(qs_circuit* c, int kmax);
+
+/* Run this circuit on dense states as tile passes (on != 0) instead of
+ * fused blocks. A pass reads and writes the ket once for every one- and
+ * two-qubit gate it holds: a tile is the contiguous low bits (6 for
+ * complex64, 5 for complex128) plus 7 bits chosen per pass, and the passes
+ * are planned on the state's physical bits at the first run (re-planned when
+ * the state's labelling differs). Gates too wide for a round (more than 4
+ * qubits with "tile.mfma" on, more than 2 otherwise or for complex128) run
+ * as dense blocks between passes. States with fewer qubits than a tile (13 / 12) use
+ * fused blocks. Same results as the block path up to float rounding order. */
+int qs_circuit_use_tiles(qs_circuit* c, int on);
+/* Tile plan of the circuit for a state in the identity labelling: passes,
+ * dense blocks and register rounds (any pointer may be NULL).
+ * QS_E_UNSUPPORTED if the circuit has fewer qubits than a tile. */
+int qs_circuit_tile_info(const qs_circuit* c, int dtype, int* passes, int* blocks, int* rounds);
 /* Gate count, block count (-1 before planning) and widest block. */
 int qs_circuit_info(const qs_circuit* c, int* ngates, int* nblocks, int* max_k);
 /* Block i of a planned circuit: its width, its positions (position p = qubit p
@@ -382,6 +397,10 @@ int qs_check(qs_state* st, double tol);
  *                    measures the lowest dirty qubit together with the next
  *                    dirty qubits of its subsystem (up to 5, none skipped) in
  *                    one sweep; 0: one sweep per qubit. Same decisions;
+ *   "tile.mfma"      1 (default): complex64 tile passes run their rounds as
+ *                    dense 4-qubit blocks on the matrix cores (any gate of at
+ *                    most 4 qubits joins a pass); 0: one- and two-qubit gates
+ *                    applied one by one in registers;
  *   "fused.mfma"     1 (default): complex64 blocks of 4 or 5 qubits run on the
  *                    matrix cores when their geometry fits; 0: vector FMA.
  * QS_E_INVAL for an unknown key or a value out of range. */

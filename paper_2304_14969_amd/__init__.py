@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "libqs.so")
 C64, C128 = 1, 2
 OK, E_INVAL, E_NOMEM, E_CAPACITY, E_DEVICE, E_NUMERIC, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 MAX_FUSED = 6
+MAX_QUBITS = 34
 
 _ERRNAMES = {E_INVAL: "QS_E_INVAL", E_NOMEM: "QS_E_NOMEM", E_CAPACITY: "QS_E_CAPACITY",
              E_DEVICE: "QS_E_DEVICE", E_NUMERIC: "QS_E_NUMERIC", E_UNSUPPORTED: "QS_E_UNSUPPORTED"}
@@ -103,6 +104,9 @@ _SIGS = [
     ("qs_circuit_free", C.c_int, [C.c_void_p]),
     ("qs_circuit_add_gate", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     ("qs_circuit_add_matrix", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_double)]),
+    ("qs_circuit_use_tiles", C.c_int, [C.c_void_p, C.c_int]),
+    ("qs_circuit_tile_info", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int),
+                                       C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     ("qs_circuit_plan", C.c_int, [C.c_void_p, C.c_int]),
     ("qs_circuit_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     ("qs_circuit_block", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
@@ -276,6 +280,16 @@ class Circuit:
         a, b, c = C.c_int(), C.c_int(), C.c_int()
         _check(self.lib, self.lib.qs_circuit_info(self.h, C.byref(a), C.byref(b), C.byref(c)))
         return {"gates": a.value, "blocks": b.value, "max_k": c.value}
+
+    def use_tiles(self, on: bool = True):
+        _check(self.lib, self.lib.qs_circuit_use_tiles(self.h, int(bool(on))))
+        return self
+
+    def tile_info(self, dtype: int = C64) -> dict:
+        a, b, c = C.c_int(), C.c_int(), C.c_int()
+        _check(self.lib, self.lib.qs_circuit_tile_info(self.h, dtype, C.byref(a), C.byref(b),
+                                                       C.byref(c)))
+        return {"passes": a.value, "blocks": b.value, "rounds": c.value}
 
     def block(self, i: int):
         k = C.c_int()

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libqs.so")
 
 SOURCES = ["capi.cpp", "k_gates.hip", "k_qft.hip", "k_reduce.hip", "k_fused.hip",
            "k_fused_mfma.hip", "circuit.cpp", "k_factor.hip", "factor.cpp",
-           "k_batch.hip", "batch.cpp", "k_mlp.hip", "mlp.cpp"]
+           "k_batch.hip", "batch.cpp", "k_mlp.hip", "k_tile.hip", "mlp.cpp"]
 
 ARCH = "gfx950"
 FLAGS = [

@@ -35,6 +35,7 @@ void* g_user = nullptr;
 int g_live_states = 0;
 qs::QftTuning g_qft_tune;
 int g_fused_mfma = 1;  // complex64 blocks of 4-5 qubits on the matrix cores
+int g_tile_mfma = 1;   // complex64 tile passes with dense rounds on the matrix cores
 
 void* dev_alloc(size_t bytes) {
   if (g_alloc) return g_alloc(bytes, g_user);
@@ -237,11 +238,15 @@ void device_free(void* p) { dev_free(p); }
 // Drops a circuit's plan and its device copies (after an edit or a re-plan).
 void circuit_invalidate(qs_circuit* c) {
   // launches already queued may still read the matrices
-  if (c->dmat[0] || c->dmat[1]) (void)hipDeviceSynchronize();
+  if (c->dmat[0] || c->dmat[1] || c->tcache[0].dev || c->tcache[1].dev) (void)hipDeviceSynchronize();
   for (int p = 0; p < 2; ++p) {
     if (c->dmat[p]) dev_free(c->dmat[p]);
     c->dmat[p] = nullptr;
     c->off[p].clear();
+    if (c->tcache[p].dev) dev_free(c->tcache[p].dev);
+    c->tcache[p].dev = nullptr;
+    c->tcache[p].key.clear();
+    c->tcache[p].plan = qs::TilePlan();
   }
   c->planned = false;
   c->blocks.clear();
@@ -277,6 +282,9 @@ int qs_tune_set(const char* key, int64_t value) {
   } else if (!std::strcmp(key, "qft.round_bits")) {
     if (value != 4 && value != 5) return fail(QS_E_INVAL, "qft.round_bits must be 4 or 5");
     g_qft_tune.round_bits = int(value);
+  } else if (!std::strcmp(key, "tile.mfma")) {
+    if (value < 0 || value > 1) return fail(QS_E_INVAL, "tile.mfma must be 0 or 1");
+    g_tile_mfma = int(value);
   } else if (!std::strcmp(key, "factor.multi_test")) {
     if (value < 0 || value > 1) return fail(QS_E_INVAL, "factor.multi_test must be 0 or 1");
     qs::g_multi_test = int(value);
@@ -295,6 +303,7 @@ int qs_tune_get(const char* key, int64_t* value) {
   else if (!std::strcmp(key, "fused.mfma")) *value = g_fused_mfma;
   else if (!std::strcmp(key, "qft.round_bits")) *value = g_qft_tune.round_bits;
   else if (!std::strcmp(key, "factor.multi_test")) *value = qs::g_multi_test;
+  else if (!std::strcmp(key, "tile.mfma")) *value = g_tile_mfma;
   else return fail(QS_E_INVAL, "unknown tuning key '%s'", key);
   return QS_OK;
 }
@@ -660,9 +669,133 @@ int qs_circuit_free(qs_circuit* c) {
   return QS_OK;
 }
 
-// Runs a planned circuit (plans it with the default block width first if
-// needed): every block is one sweep; the circuit's SWAP renaming is then
-// folded into the state's labels.
+namespace {
+
+// The tile plan of circuit c for the state's precision and current labelling
+// (planned on physical bits), uploaded once and cached in the circuit.
+int tile_plan_for(qs_state* st, qs_circuit* c, qs_circuit::TileCache** out) {
+  const int prec = st->dtype == QS_C64 ? 0 : 1;
+  qs_circuit::TileCache& tc = c->tcache[prec];
+  std::vector<int> key(st->perm, st->perm + st->n);
+  if (tc.dev && tc.key == key && tc.plan.dense == (st->dtype == QS_C64 && g_tile_mfma)) {
+    *out = &tc;
+    return QS_OK;
+  }
+  if (tc.dev) {
+    (void)hipDeviceSynchronize();  // queued passes may still read the old tables
+    dev_free(tc.dev);
+    tc.dev = nullptr;
+  }
+  std::vector<qs::Gate> phys = c->gates;
+  for (auto& g : phys)
+    for (int j = 0; j < g.k; ++j) g.q[j] = st->perm[g.q[j]];
+  const bool dense = st->dtype == QS_C64 && g_tile_mfma;
+  tc.plan = qs::plan_tiles(phys, st->n, qs::tile_low_bits(st->dtype), qs::kTileRowBits, 4, dense);
+  const qs::TilePlan& pl = tc.plan;
+  std::vector<int32_t> tab;
+  for (size_t ri = 0; ri < pl.rounds.size(); ++ri) {
+    const auto& r = pl.rounds[ri];
+    tab.push_back(r.bits[0] | (r.bits[1] << 8) | (r.bits[2] << 16) | (r.bits[3] << 24));
+    tab.push_back(dense ? int32_t(ri * 1024) : r.g0);
+    tab.push_back(r.ng);
+    tab.push_back(0);
+  }
+  const size_t gates_at = tab.size() * sizeof(int32_t);
+  if (!dense)
+    for (const auto& g : pl.gates) {
+      tab.push_back(g.kind | (g.j1 << 4) | (g.j2 << 8));
+      tab.push_back(int32_t(2 * g.mat));
+    }
+  const size_t esz = prec == 0 ? sizeof(float) : sizeof(double);
+  const size_t mats_at = (tab.size() * sizeof(int32_t) + 255) / 256 * 256;
+  // dense rounds: each round's 32x32 real embedding in lane order, then the
+  // matrices of the block steps; sparse rounds: every matrix as is
+  const size_t emb = dense ? pl.rounds.size() * 1024 * sizeof(float) : 0;
+  const size_t total = mats_at + emb + 2 * pl.mats.size() * esz;
+  std::vector<unsigned char> host(total, 0);
+  std::memcpy(host.data(), tab.data(), tab.size() * sizeof(int32_t));
+  if (dense) {
+    std::vector<float> A(1024);
+    for (size_t ri = 0; ri < pl.rounds.size(); ++ri) {
+      const qs::cd* u = pl.mats.data() + pl.rounds[ri].mat;
+      for (int ks = 0; ks < 16; ++ks)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int row = lane & 31, pp = lane >> 5;  // Uemb[row][2 ks + pp]
+          const qs::cd x = u[(row >> 1) * 16 + ks];
+          const double v = (row & 1) == 0 ? (pp == 0 ? x.real() : -x.imag())
+                                          : (pp == 0 ? x.imag() : x.real());
+          A[ks * 64 + lane] = float(v);
+        }
+      std::memcpy(host.data() + mats_at + ri * 1024 * sizeof(float), A.data(), 1024 * sizeof(float));
+    }
+  }
+  for (size_t i = 0; i < pl.mats.size(); ++i) {
+    if (prec == 0) {
+      const float v[2] = {float(pl.mats[i].real()), float(pl.mats[i].imag())};
+      std::memcpy(host.data() + mats_at + emb + 2 * i * esz, v, sizeof v);
+    } else {
+      const double v[2] = {pl.mats[i].real(), pl.mats[i].imag()};
+      std::memcpy(host.data() + mats_at + emb + 2 * i * esz, v, sizeof v);
+    }
+  }
+  void* d = dev_alloc(std::max<size_t>(total, 256));
+  if (!d) return fail(QS_E_NOMEM, "allocating %zu bytes of tile tables", total);
+  const hipError_t e = hipMemcpy(d, host.data(), total, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    dev_free(d);
+    return device_error(st, e, "uploading tile tables");
+  }
+  tc.dev = d;
+  tc.key = key;
+  tc.gates_off = gates_at;
+  tc.mats_off = mats_at + emb;  // block-step matrices (and sparse-round matrices)
+  tc.emb_off = mats_at;
+  *out = &tc;
+  return QS_OK;
+}
+
+int run_tiles(qs_state* st, qs_circuit* c) {
+  qs_circuit::TileCache* tc = nullptr;
+  if (int rc = tile_plan_for(st, c, &tc)) return rc;
+  const char* base = static_cast<const char*>(tc->dev);
+  const double bytes = 2.0 * std::ldexp(1.0, st->n) * ab(st);
+  for (const auto& stp : tc->plan.steps) {
+    hipError_t e;
+    if (stp.block) {
+      const void* dm = base + tc->mats_off + 2 * stp.mat * (st->dtype == QS_C64 ? 4 : 8);
+      e = launch_block(st, stp.blk.q, stp.blk.k, dm);
+    } else {
+      qs::TileRows rows;
+      for (int j = 0; j < qs::kTileRowBits; ++j) rows.b[j] = stp.hb[j];
+      const void* rd = base + size_t(stp.r0) * 4 * sizeof(int32_t);
+      const void* gt = base + tc->gates_off;
+      if (tc->plan.dense) {
+        ProfScope ps(st, "tile_mfma", bytes);
+        e = qs::launch_tile_mfma(static_cast<float*>(st->amps), st->n, rows, rd, stp.nr,
+                                 reinterpret_cast<const float*>(base + tc->emb_off), st->stream);
+      } else {
+        ProfScope ps(st, "tile_pass", bytes);
+        e = st->dtype == QS_C64
+                ? qs::launch_tile_pass(static_cast<float*>(st->amps), st->n, rows, rd, stp.nr, gt,
+                                       reinterpret_cast<const float*>(base + tc->mats_off),
+                                       st->stream)
+                : qs::launch_tile_pass(static_cast<double*>(st->amps), st->n, rows, rd, stp.nr, gt,
+                                       reinterpret_cast<const double*>(base + tc->mats_off),
+                                       st->stream);
+      }
+    }
+    if (int rc = device_error(st, e, "tile pass")) return rc;
+  }
+  return QS_OK;
+}
+
+}  // namespace
+
+// Runs a circuit on a dense state as tile passes (when chosen and the state
+// has at least one tile's bits) or as planned blocks (planned with the
+// default block width first if needed), one sweep each; the circuit's SWAP
+// renaming is then folded into the state's labels. Factorized states apply
+// the gates one by one.
 int qs_run(qs_state* st, qs_circuit* c) {
   if (int rc = check_state(st)) return rc;
   if (!c) return fail(QS_E_INVAL, "circuit is NULL");
@@ -680,6 +813,14 @@ int qs_run(qs_state* st, qs_circuit* c) {
       if (int rc = fact_rc(st, qs::fact_apply(st->fact, g.q, g.k, m.data()))) return rc;
     }
     return qs::fact_relabel(st->fact, c->pos.data());
+  }
+  if (c->tiles && !c->gates.empty() &&
+      st->n >= qs::tile_low_bits(st->dtype) + qs::kTileRowBits) {
+    if (int rc = run_tiles(st, c)) return rc;
+    int np[64];
+    for (int q = 0; q < st->n; ++q) np[q] = st->perm[c->pos[q]];
+    for (int q = 0; q < st->n; ++q) st->perm[q] = np[q];
+    return QS_OK;
   }
   if (!c->planned)
     if (int rc = qs_circuit_plan(c, c->kmax)) return rc;

@@ -181,6 +181,174 @@ std::vector<Block> fuse(const std::vector<Gate>& gates, int n, int kmax) {
   return out;
 }
 
+namespace {
+
+// The gates of `sel` (indices into `qb`, the qubit lists) taken in rounds of
+// the dependence order: each call returns the gates of one group whose
+// qubits, together with `fixed`, need at most `budget` extra qubits; `done`
+// marks the gates already taken. Qubits in `fixed` are free.
+struct DagCursor {
+  const std::vector<std::vector<int>>* qb = nullptr;
+  std::vector<std::vector<int>> per_qubit;  // gate positions (into sel) per qubit
+  std::vector<size_t> next;                 // per qubit: index into per_qubit
+  std::vector<char> done;
+  size_t remaining = 0;
+
+  DagCursor(const std::vector<std::vector<int>>& q, int nq) : qb(&q), per_qubit(nq), next(nq, 0) {
+    for (size_t i = 0; i < q.size(); ++i)
+      for (int x : q[i]) per_qubit[x].push_back(int(i));
+    done.assign(q.size(), 0);
+    remaining = q.size();
+  }
+  bool at_front(int i) const {
+    for (int x : (*qb)[i])
+      if (next[x] >= per_qubit[x].size() || per_qubit[x][next[x]] != i) return false;
+    return true;
+  }
+  void take(int i) {
+    done[i] = 1;
+    --remaining;
+    for (int x : (*qb)[i]) ++next[x];
+  }
+  // the front in circuit order
+  std::vector<int> front() const {
+    std::vector<int> f;
+    for (size_t x = 0; x < per_qubit.size(); ++x)
+      if (next[x] < per_qubit[x].size()) {
+        const int i = per_qubit[x][next[x]];
+        if (at_front(i) && std::find(f.begin(), f.end(), i) == f.end()) f.push_back(i);
+      }
+    std::sort(f.begin(), f.end());
+    return f;
+  }
+};
+
+// Greedy group: front gates (circuit order) whose qubits outside `fixed`
+// fit, with the qubits already chosen, in `budget`; `eligible` filters.
+template <typename Eligible>
+std::vector<int> take_group(DagCursor& dag, const std::vector<char>& fixed, int budget,
+                            std::vector<int>* chosen, Eligible eligible) {
+  std::vector<int> out;
+  bool progress = true;
+  while (progress) {
+    progress = false;
+    for (int i : dag.front()) {
+      if (!eligible(i)) continue;
+      std::vector<int> need;
+      for (int x : (*dag.qb)[i])
+        if (!fixed[x] && std::find(chosen->begin(), chosen->end(), x) == chosen->end())
+          need.push_back(x);
+      if (int(chosen->size() + need.size()) > budget) continue;
+      chosen->insert(chosen->end(), need.begin(), need.end());
+      dag.take(i);
+      out.push_back(i);
+      progress = true;
+    }
+  }
+  return out;
+}
+
+}  // namespace
+
+TilePlan plan_tiles(const std::vector<Gate>& gates, int n, int C, int H, int W, bool dense) {
+  TilePlan plan;
+  plan.C = C;
+  plan.H = H;
+  plan.W = W;
+  plan.dense = dense;
+  std::vector<std::vector<int>> qb(gates.size());
+  for (size_t i = 0; i < gates.size(); ++i) qb[i].assign(gates[i].q, gates[i].q + gates[i].k);
+  DagCursor dag(qb, n);
+  std::vector<char> low(n, 0);
+  for (int q = 0; q < C && q < n; ++q) low[q] = 1;
+  const int max_k = dense ? W : 2;
+  auto small = [&](int i) { return gates[i].k <= max_k; };
+  while (dag.remaining) {
+    std::vector<int> hi;
+    const std::vector<int> pass = take_group(dag, low, H, &hi, small);
+    if (pass.empty()) {
+      // only gates on more than two qubits at the front: the first one as a block
+      const int i = dag.front().front();
+      dag.take(i);
+      TileStep st;
+      st.block = true;
+      st.ngates = 1;
+      std::vector<int> q(gates[i].q, gates[i].q + gates[i].k);
+      std::vector<int> order(q.size());
+      for (size_t j = 0; j < q.size(); ++j) order[j] = int(j);
+      std::sort(q.begin(), q.end());
+      st.blk.k = gates[i].k;
+      for (int j = 0; j < st.blk.k; ++j) st.blk.q[j] = q[j];
+      st.blk.ngates = 1;
+      st.blk.m = eye(st.blk.k);
+      int lp[QS_MAX_FUSED];
+      for (int j = 0; j < gates[i].k; ++j)
+        lp[j] = int(std::lower_bound(q.begin(), q.end(), gates[i].q[j]) - q.begin());
+      left_apply(st.blk.m, st.blk.k, gates[i].m, gates[i].k, lp);
+      st.mat = plan.mats.size();
+      plan.mats.insert(plan.mats.end(), st.blk.m.begin(), st.blk.m.end());
+      plan.steps.push_back(std::move(st));
+      continue;
+    }
+    // row bits: the chosen ones, completed with the lowest unused high bits
+    for (int q = C; q < n && int(hi.size()) < H; ++q)
+      if (std::find(hi.begin(), hi.end(), q) == hi.end()) hi.push_back(q);
+    std::sort(hi.begin(), hi.end());
+    std::vector<int> tbit(n, -1);  // physical bit -> tile bit
+    for (int q = 0; q < C; ++q) tbit[q] = q;
+    for (int j = 0; j < H; ++j) tbit[hi[j]] = C + j;
+    TileStep st;
+    for (int j = 0; j < H; ++j) st.hb[j] = hi[j];
+    st.r0 = int(plan.rounds.size());
+    st.ngates = int(pass.size());
+    // rounds: the same greedy grouping on tile bits, W bits each
+    std::vector<std::vector<int>> tq(pass.size());
+    for (size_t i = 0; i < pass.size(); ++i)
+      for (int x : qb[pass[i]]) tq[i].push_back(tbit[x]);
+    DagCursor rd(tq, C + H);
+    const std::vector<char> none(C + H, 0);
+    while (rd.remaining) {
+      std::vector<int> rb;
+      const std::vector<int> grp = take_group(rd, none, W, &rb, [](int) { return true; });
+      for (int b = 0; b < C + H && int(rb.size()) < W; ++b)
+        if (std::find(rb.begin(), rb.end(), b) == rb.end()) rb.push_back(b);
+      std::sort(rb.begin(), rb.end());
+      TileRound r;
+      for (int j = 0; j < W; ++j) r.bits[j] = rb[j];
+      r.g0 = int(plan.gates.size());
+      r.ng = int(grp.size());
+      if (dense) {
+        // the product of the round's gates on its W bits (local bit j = rb[j])
+        std::vector<cd> u = eye(W);
+        for (int gi : grp) {
+          const Gate& g = gates[pass[gi]];
+          int lp[QS_MAX_FUSED];
+          for (int j = 0; j < g.k; ++j)
+            lp[j] = int(std::find(rb.begin(), rb.end(), tq[gi][j]) - rb.begin());
+          left_apply(u, W, g.m, g.k, lp);
+        }
+        r.mat = plan.mats.size();
+        plan.mats.insert(plan.mats.end(), u.begin(), u.end());
+      } else {
+        for (int gi : grp) {
+          const Gate& g = gates[pass[gi]];
+          TileGate tg;
+          tg.kind = g.k;
+          tg.j1 = int(std::find(rb.begin(), rb.end(), tq[gi][0]) - rb.begin());
+          tg.j2 = g.k == 2 ? int(std::find(rb.begin(), rb.end(), tq[gi][1]) - rb.begin()) : 0;
+          tg.mat = plan.mats.size();
+          plan.mats.insert(plan.mats.end(), g.m.begin(), g.m.end());
+          plan.gates.push_back(tg);
+        }
+      }
+      plan.rounds.push_back(r);
+    }
+    st.nr = int(plan.rounds.size()) - st.r0;
+    plan.steps.push_back(st);
+  }
+  return plan;
+}
+
 }  // namespace qs
 
 // ------------------------------------------------------------------ C ABI
@@ -279,6 +447,24 @@ int qs_circuit_plan(qs_circuit* c, int kmax) {
   c->kmax = kmax;
   c->blocks = qs::fuse(c->gates, c->n, kmax);
   c->planned = true;
+  return QS_OK;
+}
+
+int qs_circuit_use_tiles(qs_circuit* c, int on) {
+  if (!c) return cfail(QS_E_INVAL, "circuit is NULL");
+  c->tiles = on != 0;
+  return QS_OK;
+}
+
+int qs_circuit_tile_info(const qs_circuit* c, int dtype, int* passes, int* blocks, int* rounds) {
+  if (!c) return cfail(QS_E_INVAL, "circuit is NULL");
+  if (dtype != QS_C64 && dtype != QS_C128) return cfail(QS_E_INVAL, "unknown dtype %d", dtype);
+  const int C = dtype == QS_C64 ? 6 : 5;
+  if (c->n < C + 7) return cfail(QS_E_UNSUPPORTED, "%d qubits: fewer than one tile (%d)", c->n, C + 7);
+  const qs::TilePlan pl = qs::plan_tiles(c->gates, c->n, C, 7, 4, dtype == QS_C64);
+  if (passes) *passes = pl.passes();
+  if (blocks) *blocks = int(pl.steps.size()) - pl.passes();
+  if (rounds) *rounds = int(pl.rounds.size());
   return QS_OK;
 }
 

@@ -36,6 +36,54 @@ bool gate_matrix(int kind, int nq, const double* params, std::vector<cd>* m, int
 // Blocks are emitted in an order that keeps every qubit's gates in order.
 std::vector<Block> fuse(const std::vector<Gate>& gates, int n, int kmax);
 
+// ---- tile passes
+// A pass loads a tile of 2^(C+H) amplitudes: the contiguous low bits [0, C)
+// and H chosen bits (rows), runs rounds of gates on it and stores it back,
+// one HBM read and write for every gate it holds. A round gathers, per
+// thread, the 2^W amplitudes that differ in W tile bits and applies the
+// round's one- and two-qubit gates to them in registers.
+struct TileGate {
+  int kind = 1;      // 1: one-qubit (j1); 2: two-qubit (row bit 0 = j1, bit 1 = j2)
+  int j1 = 0, j2 = 0;
+  size_t mat = 0;    // offset of the matrix in TilePlan::mats (complex entries)
+};
+struct TileRound {
+  int bits[4] = {0, 0, 0, 0};  // tile bits of the round, ascending
+  int g0 = 0, ng = 0;          // its gates in TilePlan::gates (sparse rounds)
+  size_t mat = 0;              // dense rounds: offset of the 16x16 product in mats
+};
+struct TileStep {
+  bool block = false;  // a dense block (a gate on more than two qubits), not a pass
+  int hb[8] = {0};     // pass: the H row bits (physical, ascending)
+  int r0 = 0, nr = 0;  // pass: its rounds
+  int ngates = 0;
+  Block blk;           // block step, on physical bits
+  size_t mat = 0;      // block step: offset of its matrix
+};
+struct TilePlan {
+  int C = 0, H = 0, W = 0;
+  bool dense = false;  // rounds are dense W-qubit blocks (any gate of <= W qubits)
+  std::vector<TileStep> steps;
+  std::vector<TileRound> rounds;
+  std::vector<TileGate> gates;
+  std::vector<cd> mats;
+  int passes() const {
+    int p = 0;
+    for (const auto& s : steps) p += s.block ? 0 : 1;
+    return p;
+  }
+};
+
+// Plans `gates` (on physical bits, in circuit order) into tile passes for a
+// state of n >= C + H qubits. Greedy over the gate dependence order: a pass
+// takes every gate at the front whose qubits fit in the low bits plus at
+// most H other bits, in circuit order, until none fits. Rounds are formed
+// the same way within a pass with W bits each. Sparse rounds (dense =
+// false) hold gates of one or two qubits; dense rounds hold any gate of at
+// most W qubits and carry the product of their gates. Larger gates run as
+// dense blocks between passes.
+TilePlan plan_tiles(const std::vector<Gate>& gates, int n, int C, int H, int W, bool dense);
+
 }  // namespace qs
 
 struct qs_circuit {
@@ -48,4 +96,12 @@ struct qs_circuit {
   // device copies of the block matrices, per precision (owned)
   void* dmat[2] = {nullptr, nullptr};
   std::vector<size_t> off[2];   // element offset of each block's matrix
+  // tile passes (dense runs), planned per precision and physical labelling
+  bool tiles = false;
+  struct TileCache {
+    std::vector<int> key;  // physical bit of every virtual position
+    qs::TilePlan plan;
+    void* dev = nullptr;   // rounds, gates, matrices (owned)
+    size_t gates_off = 0, mats_off = 0, emb_off = 0;  // byte offsets in dev
+  } tcache[2];
 };

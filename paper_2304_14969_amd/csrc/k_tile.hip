@@ -1,0 +1,336 @@
+// Tile passes of a planned circuit: one HBM read and write of the ket for all
+// the gates of a pass.
+//
+// A tile is 2^(C+H) amplitudes: the contiguous low bits [0, C) (rows of 2^C
+// amplitudes, 512 bytes) and H row bits chosen by the planner (complex64:
+// C = 6, H = 7, 64 KiB; complex128: C = 5, H = 7, 64 KiB). The tile is staged
+// in LDS (one complex of padding every 16 entries) and transformed round by
+// round, each round acting on 4 tile bits. Complex64 rounds are dense 4-qubit
+// blocks on the matrix cores (k_tile_mfma); complex128 rounds (k_tile_pass)
+// gather, per thread, the 16 amplitudes that differ in the round's bits and
+// apply the round's one- and two-qubit gates in registers (the gate's bits
+// inside the round select a compile-time form).
+#include "qs_internal.h"
+
+namespace qs {
+namespace {
+
+constexpr int kW = 4;
+constexpr int kV = 1 << kW;  // amplitudes per thread in a round
+
+template <typename R> struct Cx { R r, i; };
+template <typename R> struct Vec16;
+template <> struct Vec16<float> { using T = float4; static constexpr int AMPS = 2; };
+template <> struct Vec16<double> { using T = double2; static constexpr int AMPS = 1; };
+
+__device__ __forceinline__ uint64_t insert_zero(uint64_t x, int pos) {
+  const uint64_t lo = x & ((uint64_t(1) << pos) - 1);
+  return lo | ((x ^ lo) << 1);
+}
+__device__ __forceinline__ int lds_pos(int x) { return x + (x >> 4); }
+
+template <typename R>
+__device__ __forceinline__ Cx<R> cmac(Cx<R> acc, Cx<R> a, Cx<R> b) {
+  return {acc.r + a.r * b.r - a.i * b.i, acc.i + a.r * b.i + a.i * b.r};
+}
+
+// 2x2 matrix (row-major, interleaved) on round bit J.
+template <typename R, int J>
+__device__ __forceinline__ void apply1(Cx<R> (&v)[kV], const R* __restrict__ m) {
+  const Cx<R> m00{m[0], m[1]}, m01{m[2], m[3]}, m10{m[4], m[5]}, m11{m[6], m[7]};
+#pragma unroll
+  for (int x = 0; x < kV; ++x) {
+    if (x & (1 << J)) continue;
+    const Cx<R> a = v[x], b = v[x | (1 << J)];
+    v[x] = cmac(cmac(Cx<R>{0, 0}, m00, a), m01, b);
+    v[x | (1 << J)] = cmac(cmac(Cx<R>{0, 0}, m10, a), m11, b);
+  }
+}
+
+// 4x4 matrix: row/column bit 0 on round bit J1, bit 1 on round bit J2.
+template <typename R, int J1, int J2>
+__device__ __forceinline__ void apply2(Cx<R> (&v)[kV], const R* __restrict__ m) {
+  Cx<R> M[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) M[e] = {m[2 * e], m[2 * e + 1]};
+#pragma unroll
+  for (int x = 0; x < kV; ++x) {
+    if (x & ((1 << J1) | (1 << J2))) continue;
+    int idx[4];
+    Cx<R> in[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      idx[c] = x | ((c & 1) << J1) | ((c >> 1) << J2);
+      in[c] = v[idx[c]];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      Cx<R> y{0, 0};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) y = cmac(y, M[4 * r + c], in[c]);
+      v[idx[r]] = y;
+    }
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void apply_gate(Cx<R> (&v)[kV], int code, const R* __restrict__ m) {
+  const int kind = code & 15, j1 = (code >> 4) & 15, j2 = (code >> 8) & 15;
+  if (kind == 1) {
+    switch (j1) {
+      case 0: apply1<R, 0>(v, m); break;
+      case 1: apply1<R, 1>(v, m); break;
+      case 2: apply1<R, 2>(v, m); break;
+      default: apply1<R, 3>(v, m); break;
+    }
+    return;
+  }
+  switch (j1 * 4 + j2) {
+    case 1: apply2<R, 0, 1>(v, m); break;
+    case 2: apply2<R, 0, 2>(v, m); break;
+    case 3: apply2<R, 0, 3>(v, m); break;
+    case 4: apply2<R, 1, 0>(v, m); break;
+    case 6: apply2<R, 1, 2>(v, m); break;
+    case 7: apply2<R, 1, 3>(v, m); break;
+    case 8: apply2<R, 2, 0>(v, m); break;
+    case 9: apply2<R, 2, 1>(v, m); break;
+    case 11: apply2<R, 2, 3>(v, m); break;
+    case 12: apply2<R, 3, 0>(v, m); break;
+    case 13: apply2<R, 3, 1>(v, m); break;
+    default: apply2<R, 3, 2>(v, m); break;
+  }
+}
+
+template <typename R, int C, int H>
+__global__ void __launch_bounds__(1 << (C + H - kW))
+    k_tile_pass(R* __restrict__ a, TileRows rows, const int4* __restrict__ rounds, int nrounds,
+                const int2* __restrict__ gates, const R* __restrict__ mats) {
+  constexpr int TB = C + H;
+  constexpr int NT = 1 << (TB - kW);
+  using V = typename Vec16<R>::T;
+  constexpr int AP = Vec16<R>::AMPS;
+  constexpr int VPR = (1 << C) / AP;       // 16-byte vectors per row
+  constexpr int NV = (1 << TB) / AP / NT;  // vectors per thread
+  extern __shared__ unsigned char smraw[];
+  Cx<R>* sm = reinterpret_cast<Cx<R>*>(smraw);
+  // tile base: the workgroup index spread over the bits outside the tile
+  uint64_t base = uint64_t(blockIdx.x) << C;
+#pragma unroll
+  for (int j = 0; j < H; ++j) base = insert_zero(base, rows.b[j]);
+  auto glob = [&](int row, int col) {
+    uint64_t g = base | uint64_t(col);
+#pragma unroll
+    for (int j = 0; j < H; ++j) g |= uint64_t((row >> j) & 1) << rows.b[j];
+    return g;
+  };
+  V* p = reinterpret_cast<V*>(a);
+  V buf[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int e = threadIdx.x + k * NT;
+    buf[k] = p[glob(e / VPR, (e % VPR) * AP) / AP];
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int e = threadIdx.x + k * NT;
+    const int x = ((e / VPR) << C) | (e % VPR) * AP;
+    if constexpr (AP == 2) {
+      sm[lds_pos(x)] = {buf[k].x, buf[k].y};
+      sm[lds_pos(x + 1)] = {buf[k].z, buf[k].w};
+    } else {
+      sm[lds_pos(x)] = {buf[k].x, buf[k].y};
+    }
+  }
+  __syncthreads();
+  for (int r = 0; r < nrounds; ++r) {
+    const int4 rd = rounds[r];
+    const int b0 = rd.x & 255, b1 = (rd.x >> 8) & 255, b2 = (rd.x >> 16) & 255,
+              b3 = (rd.x >> 24) & 255;
+    int x0 = threadIdx.x;
+    x0 = int(insert_zero(uint64_t(x0), b0));
+    x0 = int(insert_zero(uint64_t(x0), b1));
+    x0 = int(insert_zero(uint64_t(x0), b2));
+    x0 = int(insert_zero(uint64_t(x0), b3));
+    int pos[kV];
+    Cx<R> v[kV];
+#pragma unroll
+    for (int m = 0; m < kV; ++m) {
+      pos[m] = lds_pos(x0 | ((m & 1) << b0) | (((m >> 1) & 1) << b1) | (((m >> 2) & 1) << b2) |
+                       (((m >> 3) & 1) << b3));
+      v[m] = sm[pos[m]];
+    }
+    for (int g = rd.y; g < rd.y + rd.z; ++g) {
+      const int2 gg = gates[g];
+      apply_gate<R>(v, gg.x, mats + gg.y);
+    }
+#pragma unroll
+    for (int m = 0; m < kV; ++m) sm[pos[m]] = v[m];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int e = threadIdx.x + k * NT;
+    const int x = ((e / VPR) << C) | (e % VPR) * AP;
+    V o;
+    const Cx<R> v0 = sm[lds_pos(x)];
+    if constexpr (AP == 2) {
+      const Cx<R> v1 = sm[lds_pos(x + 1)];
+      o = {v0.r, v0.i, v1.r, v1.i};
+    } else {
+      o = {v0.r, v0.i};
+    }
+    p[glob(e / VPR, (e % VPR) * AP) / AP] = o;
+  }
+}
+
+// Complex64 passes whose rounds are dense 4-qubit blocks on the FP32 matrix
+// cores. A round multiplies the 16 amplitudes of every group (the other 9
+// tile bits) by the round's 16x16 complex matrix U, as a real GEMM on the
+// interleaved embedding [[Re U, -Im U], [Im U, Re U]] with
+// v_mfma_f32_32x32x2f32: a wavefront takes 32 groups at a time (lane % 32 =
+// group, lane / 32 = real or imaginary part), one K-step per input amplitude.
+// `amats` holds each round's embedding in lane order: entry ks * 64 + lane =
+// Uemb[lane % 32][2 ks + lane / 32].
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+template <int C, int H>
+__global__ void __launch_bounds__(1 << (C + H - kW))
+    k_tile_mfma(float* __restrict__ a, TileRows rows, const int4* __restrict__ rounds,
+                int nrounds, const float* __restrict__ amats) {
+  constexpr int TB = C + H;
+  constexpr int NT = 1 << (TB - kW);
+  constexpr int VPR = (1 << C) / 2;        // float4 vectors per row
+  constexpr int NV = (1 << TB) / 2 / NT;   // vectors per thread
+  constexpr int CHUNKS = (1 << (TB - kW)) / 32 / (NT / 64);  // 32-group chunks per wave
+  extern __shared__ unsigned char smraw[];
+  float2* sm = reinterpret_cast<float2*>(smraw);
+  const float* smf = reinterpret_cast<const float*>(smraw);
+  // tile base: the workgroup index spread over the bits outside the tile
+  uint64_t base = uint64_t(blockIdx.x) << C;
+#pragma unroll
+  for (int j = 0; j < H; ++j) base = insert_zero(base, rows.b[j]);
+  auto glob = [&](int row, int col) {
+    uint64_t g = base | uint64_t(col);
+#pragma unroll
+    for (int j = 0; j < H; ++j) g |= uint64_t((row >> j) & 1) << rows.b[j];
+    return g;
+  };
+  float4* p4 = reinterpret_cast<float4*>(a);
+  {
+    float4 buf[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int e = threadIdx.x + k * NT;
+      buf[k] = p4[glob(e / VPR, (e % VPR) * 2) / 2];
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int e = threadIdx.x + k * NT;
+      const int x = ((e / VPR) << C) | (e % VPR) * 2;
+      sm[lds_pos(x)] = make_float2(buf[k].x, buf[k].y);
+      sm[lds_pos(x + 1)] = make_float2(buf[k].z, buf[k].w);
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, p = lane >> 5;
+  // this lane's part of the first round's embedded matrix, loaded with the tile
+  float A[kV];
+#pragma unroll
+  for (int ks = 0; ks < kV; ++ks) A[ks] = amats[rounds[0].y + ks * 64 + lane];
+  __syncthreads();
+  for (int r = 0; r < nrounds; ++r) {
+    const int4 rd = rounds[r];
+    const int b0 = rd.x & 255, b1 = (rd.x >> 8) & 255, b2 = (rd.x >> 16) & 255,
+              b3 = (rd.x >> 24) & 255;
+    // the next round's matrix is loaded while this round computes
+    float An[kV];
+    const int offn = rounds[r + 1 < nrounds ? r + 1 : r].y;
+#pragma unroll
+    for (int ks = 0; ks < kV; ++ks) An[ks] = amats[offn + ks * 64 + lane];
+    int dep[kV];  // LDS offset of round-local index m (the round bits and padding)
+#pragma unroll
+    for (int m = 0; m < kV; ++m)
+      dep[m] = lds_pos(((m & 1) << b0) | (((m >> 1) & 1) << b1) | (((m >> 2) & 1) << b2) |
+                       (((m >> 3) & 1) << b3));
+#pragma unroll
+    for (int ch = 0; ch < CHUNKS; ++ch) {
+      int x0 = (wave * CHUNKS + ch) * 32 + (lane & 31);
+      x0 = int(insert_zero(uint64_t(x0), b0));
+      x0 = int(insert_zero(uint64_t(x0), b1));
+      x0 = int(insert_zero(uint64_t(x0), b2));
+      x0 = int(insert_zero(uint64_t(x0), b3));
+      const int px = lds_pos(x0);  // the round bits and the rest are disjoint
+      f32x16 acc = f32x16{};
+#pragma unroll
+      for (int ks = 0; ks < kV; ++ks)
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[ks], smf[2 * (px + dep[ks]) + p], acc, 0, 0,
+                                                   0);
+      // D layout: register e -> row 8 (e / 4) + 4 p + e % 4 of the embedded
+      // output; e even and e + 1 are the real and imaginary part of one row
+#pragma unroll
+      for (int e = 0; e < 16; e += 2) {
+        const int i = 8 * (e >> 2) + 4 * p + (e & 3);
+        sm[px + dep[i >> 1]] = make_float2(acc[e], acc[e + 1]);
+      }
+    }
+#pragma unroll
+    for (int ks = 0; ks < kV; ++ks) A[ks] = An[ks];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int e = threadIdx.x + k * NT;
+    const int x = ((e / VPR) << C) | (e % VPR) * 2;
+    const float2 v0 = sm[lds_pos(x)], v1 = sm[lds_pos(x + 1)];
+    p4[glob(e / VPR, (e % VPR) * 2) / 2] = make_float4(v0.x, v0.y, v1.x, v1.y);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_tile_mfma(float* a, int n, const TileRows& rows, const void* rounds, int nrounds,
+                            const float* amats, hipStream_t s) {
+  constexpr int C = 6, H = kTileRowBits, TB = C + H;
+  if (n < TB) return hipErrorInvalidValue;
+  for (int j = 0; j < H; ++j)
+    if (rows.b[j] < C || rows.b[j] >= n || (j > 0 && rows.b[j] <= rows.b[j - 1]))
+      return hipErrorInvalidValue;
+  if (nrounds < 1) return hipErrorInvalidValue;
+  const size_t bytes = size_t((1 << TB) + ((1 << TB) >> 4)) * sizeof(float2);
+  auto kern = k_tile_mfma<C, H>;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  hipLaunchKernelGGL(kern, dim3(unsigned(uint64_t(1) << (n - TB))), dim3(1 << (TB - kW)), bytes,
+                     s, a, rows, static_cast<const int4*>(rounds), nrounds, amats);
+  return hipGetLastError();
+}
+
+// complex64 (dtype 1): rows of 64 amplitudes; complex128: 32 (512 bytes either way)
+int tile_low_bits(int dtype) { return dtype == 1 ? 6 : 5; }
+
+template <typename R>
+hipError_t launch_tile_pass(R* a, int n, const TileRows& rows, const void* rounds, int nrounds,
+                            const void* gates, const R* mats, hipStream_t s) {
+  constexpr int C = sizeof(R) == 4 ? 6 : 5;
+  constexpr int H = kTileRowBits;
+  constexpr int TB = C + H;
+  if (n < TB) return hipErrorInvalidValue;
+  for (int j = 0; j < H; ++j)
+    if (rows.b[j] < C || rows.b[j] >= n || (j > 0 && rows.b[j] <= rows.b[j - 1]))
+      return hipErrorInvalidValue;
+  const size_t bytes = size_t((1 << TB) + ((1 << TB) >> 4)) * 2 * sizeof(R);
+  auto kern = k_tile_pass<R, C, H>;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  const unsigned grid = unsigned(uint64_t(1) << (n - TB));
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(1 << (TB - kW)), bytes, s, a, rows,
+                     static_cast<const int4*>(rounds), nrounds, static_cast<const int2*>(gates),
+                     mats);
+  return hipGetLastError();
+}
+
+template hipError_t launch_tile_pass<float>(float*, int, const TileRows&, const void*, int,
+                                            const void*, const float*, hipStream_t);
+template hipError_t launch_tile_pass<double>(double*, int, const TileRows&, const void*, int,
+                                             const void*, const double*, hipStream_t);
+
+}  // namespace qs

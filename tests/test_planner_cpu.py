@@ -93,3 +93,35 @@ def test_block_count_random_layers(qs):
     c = qs.Circuit(n).add_gates(workloads.random_circuit(n, 10, 0)).plan(5)
     info = c.info()
     assert info["blocks"] * 3 < info["gates"]
+
+
+def test_tile_plan_counts(qs):
+    """Tile-pass planning is host code too: a 10-layer random circuit on 32
+    qubits needs far fewer passes than gates (each pass holds every gate that
+    fits a tile of the 6 low bits plus 7 others); a gate wider than a round
+    (complex64 dense rounds: 4 qubits; complex128: 2) becomes a dense block
+    between passes; a state smaller than a tile has no tile plan."""
+    n = 32
+    c = qs.Circuit(n).add_gates(workloads.random_circuit(n, 10, 0))
+    info = c.tile_info(qs.C64)
+    assert info["blocks"] == 0
+    assert 10 <= info["passes"] <= 60
+    assert info["rounds"] >= info["passes"]
+    c128 = c.tile_info(qs.C128)
+    assert c128["passes"] >= info["passes"]  # one low bit fewer in the tile
+    g3 = dense.u3(0.1, 0.2, 0.3)
+    m3 = np.kron(np.kron(g3, g3), dense.H)
+    c3 = qs.Circuit(16).add_gates(workloads.random_circuit(16, 3, 1)
+                                  + [("mat", [2, 9, 14], m3)]
+                                  + workloads.random_circuit(16, 2, 2))
+    assert c3.tile_info(qs.C64)["blocks"] == 0
+    assert c3.tile_info(qs.C128)["blocks"] == 1
+    m5 = np.kron(m3, np.kron(g3, g3))
+    c5 = qs.Circuit(16).add_gates(workloads.random_circuit(16, 2, 3)
+                                  + [("mat", [0, 4, 7, 11, 15], m5)])
+    assert c5.tile_info(qs.C64)["blocks"] == 1
+    c5.free()
+    with pytest.raises(qs.QSError):
+        qs.Circuit(12).add_gates(workloads.random_circuit(12, 2, 0)).tile_info(qs.C64)
+    for x in (c, c3):
+        x.free()
