@@ -307,15 +307,16 @@ int qs_circuit_plan(qs_circuit* c, int kmax);
 
 /* Run this circuit on dense states as tile passes (on != 0) instead of
  * fused blocks. A pass reads and writes the ket once for every one- and
- * two-qubit gate it holds: a tile is the contiguous low bits (6 for
- * complex64, 5 for complex128) plus 7 bits chosen per pass, and the passes
+ * two-qubit gate it holds: a tile is the contiguous low bits (complex64:
+ * "tile.low_bits", 5 by default; complex128: 5) plus 7 bits chosen per pass, and the passes
  * are planned on the state's physical bits at the first run (re-planned when
  * the state's labelling differs). Gates too wide for a round (more than 4
  * qubits with "tile.mfma" on, more than 2 otherwise or for complex128) run
  * as dense blocks between passes. States with fewer qubits than a tile (13 / 12) use
  * fused blocks. Same results as the block path up to float rounding order. */
 int qs_circuit_use_tiles(qs_circuit* c, int on);
-/* Tile plan of the circuit for a state in the identity labelling: passes,
+/* Tile plan of the circuit for a state in the identity labelling (current
+ * "tile.*" knobs): passes,
  * dense blocks and register rounds (any pointer may be NULL).
  * QS_E_UNSUPPORTED if the circuit has fewer qubits than a tile. */
 int qs_circuit_tile_info(const qs_circuit* c, int dtype, int* passes, int* blocks, int* rounds);
@@ -397,6 +398,9 @@ int qs_check(qs_state* st, double tol);
  *                    measures the lowest dirty qubit together with the next
  *                    dirty qubits of its subsystem (up to 5, none skipped) in
  *                    one sweep; 0: one sweep per qubit. Same decisions;
+ *   "tile.low_bits"  contiguous low bits of a complex64 tile: 5 (default,
+ *                    256-byte rows, 32 KiB tiles, four workgroups per CU),
+ *                    6 (512-byte rows, 64 KiB) or 4 (128-byte rows, 16 KiB);
  *   "tile.mfma"      1 (default): complex64 tile passes run their rounds as
  *                    dense 4-qubit blocks on the matrix cores (any gate of at
  *                    most 4 qubits joins a pass); 0: one- and two-qubit gates

@@ -6,9 +6,9 @@ Three searches, each over the documented range of its knobs:
 - `tune_qft(n)`: the QFT pass shapes (`qft.lds_bits`, `qft.high_pass`,
   `qft.threads`, `qft.round_bits`) on an n-qubit complex64 state; the winner
   is left set in the library (`qs_tune_set`).
-- `tune_fusion(n, gates)`: the block width kmax of the fusion planner and the
-  matrix-core path (`fused.mfma`) for one circuit; returns the best kmax and
-  leaves `fused.mfma` at its best value.
+- `tune_fusion(n, gates)`: how to run one circuit: fused blocks (block width
+  kmax, matrix-core switch `fused.mfma`) or tile passes (`tile.low_bits`,
+  `tile.mfma`); leaves the winning knobs set and returns the choice.
 - `tune_batch(widths, circuits)`: kmax of the batched launches.
 
 Every candidate is warmed up once and then timed `reps` times with HIP events
@@ -69,27 +69,47 @@ def tune_qft(n: int = 27, reps: int = 5, candidates=None) -> dict:
             "tried": [{"ms": round(t, 4), **dict(zip(QFT_KEYS, c))} for t, c in results]}
 
 
-def tune_fusion(n: int, gates, kmaxes=(3, 4, 5), reps: int = 3) -> dict:
-    """Fastest fusion width (and matrix-core switch) for one circuit."""
+def tune_fusion(n: int, gates, kmaxes=(3, 4, 5), tile_bits=(4, 5, 6), reps: int = 3) -> dict:
+    """Fastest way to run one circuit on complex64: fused blocks (width kmax,
+    with or without matrix cores) or tile passes (row bits, matrix-core or
+    register rounds). Leaves the winning knobs set; returns the choice
+    (`tiles` True/False, kmax) for Circuit.use_tiles / Circuit.plan."""
     st = State(n, C64)
+    keys = ("fused.mfma", "tile.mfma", "tile.low_bits")
+    before = {k: tune_get(k) for k in keys}
     results = []
-    before = tune_get("fused.mfma")
     try:
         for mfma in (1, 0):
             tune_set("fused.mfma", mfma)
             for kmax in kmaxes:
                 c = Circuit(n).add_gates(gates).plan(kmax)
-                results.append((_time(lambda: st.run(c), st.stream, reps), kmax, mfma,
-                                c.info()["blocks"]))
+                results.append((_time(lambda: st.run(c), st.stream, reps),
+                                {"tiles": False, "kmax": kmax, "fused.mfma": mfma,
+                                 "sweeps": c.info()["blocks"]}))
                 c.free()
+        tune_set("fused.mfma", before["fused.mfma"])
+        if n >= 4 + 7:
+            for tm in (1, 0):
+                for lb in tile_bits:
+                    if n < lb + 7:
+                        continue
+                    tune_set("tile.mfma", tm)
+                    tune_set("tile.low_bits", lb)
+                    c = Circuit(n).add_gates(gates).use_tiles()
+                    results.append((_time(lambda: st.run(c), st.stream, reps),
+                                    {"tiles": True, "tile.mfma": tm, "tile.low_bits": lb,
+                                     "sweeps": c.tile_info(C64)["passes"]}))
+                    c.free()
     finally:
         st.free()
-    best_ms, kmax, mfma, blocks = min(results)
-    tune_set("fused.mfma", mfma)
-    return {"kmax": kmax, "fused.mfma": mfma, "ms": best_ms, "sweeps": blocks,
-            "before": {"fused.mfma": before},
-            "tried": [{"ms": round(t, 4), "kmax": k, "fused.mfma": m, "sweeps": b}
-                      for t, k, m, b in results]}
+        for k, v in before.items():
+            tune_set(k, v)
+    best_ms, best = min(results, key=lambda r: r[0])
+    for k in keys:
+        if k in best:
+            tune_set(k, best[k])
+    return {**best, "ms": best_ms, "before": before,
+            "tried": [{"ms": round(t, 4), **cfg} for t, cfg in results]}
 
 
 def tune_batch(widths, circuits, kmaxes=(2, 3, 4, 5), reps: int = 3) -> dict:

@@ -282,6 +282,9 @@ int qs_tune_set(const char* key, int64_t value) {
   } else if (!std::strcmp(key, "qft.round_bits")) {
     if (value != 4 && value != 5) return fail(QS_E_INVAL, "qft.round_bits must be 4 or 5");
     g_qft_tune.round_bits = int(value);
+  } else if (!std::strcmp(key, "tile.low_bits")) {
+    if (value < 4 || value > 6) return fail(QS_E_INVAL, "tile.low_bits must be 4, 5 or 6");
+    qs::g_tile_low_c64 = int(value);
   } else if (!std::strcmp(key, "tile.mfma")) {
     if (value < 0 || value > 1) return fail(QS_E_INVAL, "tile.mfma must be 0 or 1");
     g_tile_mfma = int(value);
@@ -304,6 +307,7 @@ int qs_tune_get(const char* key, int64_t* value) {
   else if (!std::strcmp(key, "qft.round_bits")) *value = g_qft_tune.round_bits;
   else if (!std::strcmp(key, "factor.multi_test")) *value = qs::g_multi_test;
   else if (!std::strcmp(key, "tile.mfma")) *value = g_tile_mfma;
+  else if (!std::strcmp(key, "tile.low_bits")) *value = qs::g_tile_low_c64;
   else return fail(QS_E_INVAL, "unknown tuning key '%s'", key);
   return QS_OK;
 }
@@ -677,7 +681,8 @@ int tile_plan_for(qs_state* st, qs_circuit* c, qs_circuit::TileCache** out) {
   const int prec = st->dtype == QS_C64 ? 0 : 1;
   qs_circuit::TileCache& tc = c->tcache[prec];
   std::vector<int> key(st->perm, st->perm + st->n);
-  if (tc.dev && tc.key == key && tc.plan.dense == (st->dtype == QS_C64 && g_tile_mfma)) {
+  if (tc.dev && tc.key == key && tc.plan.dense == (st->dtype == QS_C64 && g_tile_mfma) &&
+      tc.plan.C == qs::tile_low_bits(st->dtype)) {
     *out = &tc;
     return QS_OK;
   }
@@ -771,15 +776,18 @@ int run_tiles(qs_state* st, qs_circuit* c) {
       const void* gt = base + tc->gates_off;
       if (tc->plan.dense) {
         ProfScope ps(st, "tile_mfma", bytes);
-        e = qs::launch_tile_mfma(static_cast<float*>(st->amps), st->n, rows, rd, stp.nr,
-                                 reinterpret_cast<const float*>(base + tc->emb_off), st->stream);
+        e = qs::launch_tile_mfma(static_cast<float*>(st->amps), st->n, tc->plan.C, rows, rd,
+                                 stp.nr, reinterpret_cast<const float*>(base + tc->emb_off),
+                                 st->stream);
       } else {
         ProfScope ps(st, "tile_pass", bytes);
         e = st->dtype == QS_C64
-                ? qs::launch_tile_pass(static_cast<float*>(st->amps), st->n, rows, rd, stp.nr, gt,
+                ? qs::launch_tile_pass(static_cast<float*>(st->amps), st->n, tc->plan.C, rows, rd,
+                                       stp.nr, gt,
                                        reinterpret_cast<const float*>(base + tc->mats_off),
                                        st->stream)
-                : qs::launch_tile_pass(static_cast<double*>(st->amps), st->n, rows, rd, stp.nr, gt,
+                : qs::launch_tile_pass(static_cast<double*>(st->amps), st->n, tc->plan.C, rows,
+                                       rd, stp.nr, gt,
                                        reinterpret_cast<const double*>(base + tc->mats_off),
                                        st->stream);
       }

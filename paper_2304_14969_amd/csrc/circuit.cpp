@@ -15,6 +15,7 @@
 #include <string>
 
 #include "circuit.h"
+#include "qs_internal.h"
 
 namespace qs {
 
@@ -459,7 +460,7 @@ int qs_circuit_use_tiles(qs_circuit* c, int on) {
 int qs_circuit_tile_info(const qs_circuit* c, int dtype, int* passes, int* blocks, int* rounds) {
   if (!c) return cfail(QS_E_INVAL, "circuit is NULL");
   if (dtype != QS_C64 && dtype != QS_C128) return cfail(QS_E_INVAL, "unknown dtype %d", dtype);
-  const int C = dtype == QS_C64 ? 6 : 5;
+  const int C = qs::tile_low_bits(dtype);
   if (c->n < C + 7) return cfail(QS_E_UNSUPPORTED, "%d qubits: fewer than one tile (%d)", c->n, C + 7);
   const qs::TilePlan pl = qs::plan_tiles(c->gates, c->n, C, 7, 4, dtype == QS_C64);
   if (passes) *passes = pl.passes();

@@ -287,14 +287,15 @@ __global__ void __launch_bounds__(1 << (C + H - kW))
 
 }  // namespace
 
-hipError_t launch_tile_mfma(float* a, int n, const TileRows& rows, const void* rounds, int nrounds,
-                            const float* amats, hipStream_t s) {
-  constexpr int C = 6, H = kTileRowBits, TB = C + H;
-  if (n < TB) return hipErrorInvalidValue;
+namespace {
+template <int C>
+hipError_t launch_mfma_c(float* a, int n, const TileRows& rows, const void* rounds, int nrounds,
+                         const float* amats, hipStream_t s) {
+  constexpr int H = kTileRowBits, TB = C + H;
+  if (n < TB || nrounds < 1) return hipErrorInvalidValue;
   for (int j = 0; j < H; ++j)
     if (rows.b[j] < C || rows.b[j] >= n || (j > 0 && rows.b[j] <= rows.b[j - 1]))
       return hipErrorInvalidValue;
-  if (nrounds < 1) return hipErrorInvalidValue;
   const size_t bytes = size_t((1 << TB) + ((1 << TB) >> 4)) * sizeof(float2);
   auto kern = k_tile_mfma<C, H>;
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -303,14 +304,29 @@ hipError_t launch_tile_mfma(float* a, int n, const TileRows& rows, const void* r
                      s, a, rows, static_cast<const int4*>(rounds), nrounds, amats);
   return hipGetLastError();
 }
+}  // namespace
 
-// complex64 (dtype 1): rows of 64 amplitudes; complex128: 32 (512 bytes either way)
-int tile_low_bits(int dtype) { return dtype == 1 ? 6 : 5; }
+hipError_t launch_tile_mfma(float* a, int n, int low_bits, const TileRows& rows,
+                            const void* rounds, int nrounds, const float* amats, hipStream_t s) {
+  switch (low_bits) {
+    case 4: return launch_mfma_c<4>(a, n, rows, rounds, nrounds, amats, s);
+    case 5: return launch_mfma_c<5>(a, n, rows, rounds, nrounds, amats, s);
+    case 6: return launch_mfma_c<6>(a, n, rows, rounds, nrounds, amats, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
-template <typename R>
-hipError_t launch_tile_pass(R* a, int n, const TileRows& rows, const void* rounds, int nrounds,
-                            const void* gates, const R* mats, hipStream_t s) {
-  constexpr int C = sizeof(R) == 4 ? 6 : 5;
+// complex64 (dtype 1): rows of 2^g_tile_low_c64 amplitudes (4: 128 bytes, 5:
+// 256 bytes, 6: 512 bytes); complex128: 32 (512 bytes). Rows of 32 complex64
+// amplitudes measured fastest for 10-layer random circuits (a 32 KiB tile
+// leaves room for four workgroups per CU, against two 64 KiB ones).
+int g_tile_low_c64 = 5;
+int tile_low_bits(int dtype) { return dtype == 1 ? g_tile_low_c64 : 5; }
+
+namespace {
+template <typename R, int C>
+hipError_t launch_pass_c(R* a, int n, const TileRows& rows, const void* rounds, int nrounds,
+                         const void* gates, const R* mats, hipStream_t s) {
   constexpr int H = kTileRowBits;
   constexpr int TB = C + H;
   if (n < TB) return hipErrorInvalidValue;
@@ -327,10 +343,21 @@ hipError_t launch_tile_pass(R* a, int n, const TileRows& rows, const void* round
                      mats);
   return hipGetLastError();
 }
+}  // namespace
 
-template hipError_t launch_tile_pass<float>(float*, int, const TileRows&, const void*, int,
+template <typename R>
+hipError_t launch_tile_pass(R* a, int n, int low_bits, const TileRows& rows, const void* rounds,
+                            int nrounds, const void* gates, const R* mats, hipStream_t s) {
+  if (low_bits == 4) return launch_pass_c<R, 4>(a, n, rows, rounds, nrounds, gates, mats, s);
+  if (low_bits == 5) return launch_pass_c<R, 5>(a, n, rows, rounds, nrounds, gates, mats, s);
+  if constexpr (sizeof(R) == 4)
+    if (low_bits == 6) return launch_pass_c<R, 6>(a, n, rows, rounds, nrounds, gates, mats, s);
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_tile_pass<float>(float*, int, int, const TileRows&, const void*, int,
                                             const void*, const float*, hipStream_t);
-template hipError_t launch_tile_pass<double>(double*, int, const TileRows&, const void*, int,
+template hipError_t launch_tile_pass<double>(double*, int, int, const TileRows&, const void*, int,
                                              const void*, const double*, hipStream_t);
 
 }  // namespace qs

@@ -120,17 +120,18 @@ struct TileRows {
   int b[kTileRowBits];
 };
 int tile_low_bits(int dtype);
+extern int g_tile_low_c64;  // low tile bits of complex64 passes: 5 or 6
 // One pass: `rounds` holds nrounds int4 {bits packed 8 per byte, first gate,
 // gate count, 0}; `gates` int2 {kind | j1 << 4 | j2 << 8, matrix offset in R};
 // mats the matrices (interleaved). Needs n >= tile_low_bits + kTileRowBits.
 template <typename R>
-hipError_t launch_tile_pass(R* a, int n, const TileRows& rows, const void* rounds, int nrounds,
-                            const void* gates, const R* mats, hipStream_t s);
+hipError_t launch_tile_pass(R* a, int n, int low_bits, const TileRows& rows, const void* rounds,
+                            int nrounds, const void* gates, const R* mats, hipStream_t s);
 // Complex64 pass with dense 4-qubit rounds on the matrix cores: `rounds`
 // int4 {bits packed 8 per byte, offset of the round's embedded matrix in
 // amats (1024 floats, lane order), 0, 0}.
-hipError_t launch_tile_mfma(float* a, int n, const TileRows& rows, const void* rounds, int nrounds,
-                            const float* amats, hipStream_t s);
+hipError_t launch_tile_mfma(float* a, int n, int low_bits, const TileRows& rows,
+                            const void* rounds, int nrounds, const float* amats, hipStream_t s);
 
 // ---------------------------------------------------------------- QFT passes
 // One pass of a QFT on the qubit range [start, start+len): the stages of the

@@ -38,14 +38,16 @@ def test_tune_qft_leaves_a_correct_choice(qs_lib):
 def test_tune_fusion_and_batch(qs_lib):
     from paper_2304_14969_amd import autotune
     qs = qs_lib
-    saved = qs.tune_get("fused.mfma")
+    keys = ("fused.mfma", "tile.mfma", "tile.low_bits")
+    saved = {k: qs.tune_get(k) for k in keys}
     try:
         n = 14
         gates = workloads.random_circuit(n, 4, 5)
-        r = autotune.tune_fusion(n, gates, kmaxes=(3, 4), reps=2)
-        assert r["kmax"] in (3, 4) and len(r["tried"]) == 4
+        r = autotune.tune_fusion(n, gates, kmaxes=(3, 4), tile_bits=(5, 6), reps=2)
+        assert len(r["tried"]) == 4 + 4
         st = qs.State(n, qs.C64)
-        c = qs.Circuit(n).add_gates(gates).plan(r["kmax"])
+        c = qs.Circuit(n).add_gates(gates)
+        c = c.use_tiles() if r["tiles"] else c.plan(r["kmax"])
         st.run(c)
         want = dense.run_circuit(dense.basis_state(n, 0), n, gates)
         assert_parity(st.amplitudes(), want, qs.C64, "tuned fusion")
@@ -59,4 +61,5 @@ def test_tune_fusion_and_batch(qs_lib):
         for c in circs:
             c.free()
     finally:
-        qs.tune_set("fused.mfma", saved)
+        for k, v in saved.items():
+            qs.tune_set(k, v)

@@ -9,14 +9,19 @@ from parity import C64, C128, assert_parity
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(params=[1, 0], ids=["mfma", "registers"])
+@pytest.fixture(params=[(1, 6), (1, 5), (0, 6), (0, 5)],
+                ids=["mfma-rows64", "mfma-rows32", "registers-rows64", "registers-rows32"])
 def tile_mode(request, qs_lib):
-    """Complex64 passes with dense rounds on the matrix cores, or one- and
-    two-qubit gates in registers."""
-    saved = qs_lib.tune_get("tile.mfma")
-    qs_lib.tune_set("tile.mfma", request.param)
-    yield request.param
-    qs_lib.tune_set("tile.mfma", saved)
+    """Complex64 passes with dense rounds on the matrix cores or one- and
+    two-qubit gates in registers, on tiles with 64- or 32-amplitude rows.
+    Yields whether the matrix-core rounds are on."""
+    mfma, low = request.param
+    saved = (qs_lib.tune_get("tile.mfma"), qs_lib.tune_get("tile.low_bits"))
+    qs_lib.tune_set("tile.mfma", mfma)
+    qs_lib.tune_set("tile.low_bits", low)
+    yield mfma
+    qs_lib.tune_set("tile.mfma", saved[0])
+    qs_lib.tune_set("tile.low_bits", saved[1])
 
 
 @pytest.mark.parametrize("dtype,n", [(C64, 13), (C64, 14), (C64, 17), (C128, 12), (C128, 15)])

@@ -108,7 +108,7 @@ def test_tile_plan_counts(qs):
     assert 10 <= info["passes"] <= 60
     assert info["rounds"] >= info["passes"]
     c128 = c.tile_info(qs.C128)
-    assert c128["passes"] >= info["passes"]  # one low bit fewer in the tile
+    assert c128["passes"] >= info["passes"]  # register rounds take gates of <= 2 qubits
     g3 = dense.u3(0.1, 0.2, 0.3)
     m3 = np.kron(np.kron(g3, g3), dense.H)
     c3 = qs.Circuit(16).add_gates(workloads.random_circuit(16, 3, 1)
@@ -121,7 +121,9 @@ def test_tile_plan_counts(qs):
                                   + [("mat", [0, 4, 7, 11, 15], m5)])
     assert c5.tile_info(qs.C64)["blocks"] == 1
     c5.free()
+    small = qs.Circuit(11).add_gates(workloads.random_circuit(11, 2, 0))
     with pytest.raises(qs.QSError):
-        qs.Circuit(12).add_gates(workloads.random_circuit(12, 2, 0)).tile_info(qs.C64)
+        small.tile_info(qs.C64)  # the default tile has 5 + 7 bits
+    small.free()
     for x in (c, c3):
         x.free()
