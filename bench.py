@@ -32,8 +32,9 @@ HBM_PEAK_GBS = 8000.0
 # (`bench.py --calibrate-copy`: FETCH_SIZE reads 0.5000 of the bytes copied,
 # WRITE_SIZE 1.0000). Valid only for the kernel source they were taken on.
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_2304_14969_amd", "csrc", "k_qft.hip")
-TRAFFIC = {"sha256": "0e0fad793fcc55b2d1f38950b3470a471ca5914dd67b493fb5c93961ad42c0a2",
-           "bytes_per_launch": {"qft_col7": 2147578349, "qft_lds": 2147697273}}
+TRAFFIC = {"sha256": "71bb88caf54716efdeb3576baa8214650392af9f932f731ddd9e0781cbeb7dbf",
+           "bytes_per_launch": {"qft_col8": 2147600082, "qft_col7": 2147570387,
+                                "qft_lds": 2147587282}}
 
 
 def measured_traffic(kernel: str):

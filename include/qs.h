@@ -386,18 +386,20 @@ int qs_check(qs_state* st, double tol);
 /* ------------------------------------------------------------ tuning */
 
 /* Process-wide knobs of the kernel planners (read by later calls):
- *   "qft.lds_bits"   bits of the contiguous LDS tile of the QFT's low pass
- *                    (0 = default: 13 for complex64, 12 for complex128;
- *                    larger values are clamped to the default);
- *   "qft.high_pass"  passes above that tile: 0 = strided LDS tiles of up to
- *                    7 bits, 1 = register passes of up to 5 bits;
+ *   "qft.lds_bits"   bits of the contiguous LDS tile of the QFT's low pass:
+ *                    12 (default), or up to 13 for complex64 / 12 for
+ *                    complex128 (0 = that largest size; larger values are
+ *                    clamped to it);
+ *   "qft.high_pass"  passes above that tile: 0 = strided LDS tiles, 1 =
+ *                    register passes of up to 5 bits;
+ *   "qft.col_max"    most bits of one strided LDS pass: 8 (default; 256-byte
+ *                    rows) or 7 (512-byte rows), both 64 KiB tiles; a 7-bit
+ *                    pass always has 512-byte rows unless qft.col_rows = 1;
+ *   "qft.col_rows"   1: strided passes of 7 bits use 256-byte rows (32 KiB
+ *                    tiles); 0 (default): 512-byte rows;
  *   "qft.threads"    thread cap of the LDS tile launches: 256 or 512 (default);
- *   "qft.round_bits" widest in-register round inside an LDS tile: 4 or 5
- *                    (default);
- *   "factor.multi_test" 1 (default): the plain separability schedule
- *                    measures the lowest dirty qubit together with the next
- *                    dirty qubits of its subsystem (up to 5, none skipped) in
- *                    one sweep; 0: one sweep per qubit. Same decisions;
+ *   "qft.round_bits" widest in-register round inside an LDS tile: 4 (default)
+ *                    or 5 (complex64 only);
  *   "tile.low_bits"  contiguous low bits of a complex64 tile: 5 (default,
  *                    256-byte rows, 32 KiB tiles, four workgroups per CU),
  *                    6 (512-byte rows, 64 KiB) or 4 (128-byte rows, 16 KiB);
@@ -405,6 +407,10 @@ int qs_check(qs_state* st, double tol);
  *                    dense 4-qubit blocks on the matrix cores (any gate of at
  *                    most 4 qubits joins a pass); 0: one- and two-qubit gates
  *                    applied one by one in registers;
+ *   "factor.multi_test" 1 (default): the plain separability schedule
+ *                    measures the lowest dirty qubit together with the next
+ *                    dirty qubits of its subsystem (up to 5, none skipped) in
+ *                    one sweep; 0: one sweep per qubit. Same decisions;
  *   "fused.mfma"     1 (default): complex64 blocks of 4 or 5 qubits run on the
  *                    matrix cores when their geometry fits; 0: vector FMA.
  * QS_E_INVAL for an unknown key or a value out of range. */

@@ -4,8 +4,8 @@ and keeps the fastest.
 Three searches, each over the documented range of its knobs:
 
 - `tune_qft(n)`: the QFT pass shapes (`qft.lds_bits`, `qft.high_pass`,
-  `qft.threads`, `qft.round_bits`) on an n-qubit complex64 state; the winner
-  is left set in the library (`qs_tune_set`).
+  `qft.threads`, `qft.round_bits`, `qft.col_max`) on an n-qubit complex64
+  state; the winner is left set in the library (`qs_tune_set`).
 - `tune_fusion(n, gates)`: how to run one circuit: fused blocks (block width
   kmax, matrix-core switch `fused.mfma`) or tile passes (`tile.low_bits`,
   `tile.mfma`); leaves the winning knobs set and returns the choice.
@@ -23,7 +23,7 @@ import statistics
 
 from . import C64, Batch, Circuit, State, tune_get, tune_set
 
-QFT_KEYS = ("qft.lds_bits", "qft.high_pass", "qft.threads", "qft.round_bits")
+QFT_KEYS = ("qft.lds_bits", "qft.high_pass", "qft.threads", "qft.round_bits", "qft.col_max")
 
 
 def _time(fn, stream, reps: int) -> float:
@@ -43,10 +43,11 @@ def _time(fn, stream, reps: int) -> float:
 
 
 def qft_candidates(n: int):
-    """The pass-shape grid: contiguous tile bits (0 = automatic), strided-LDS or
-    register passes above it, thread cap and in-register round width."""
+    """The pass-shape grid: contiguous tile bits (0 = the largest), strided-LDS
+    or register passes above it, thread cap, in-register round width, and the
+    widest strided pass (7 bits with 512-byte rows, 8 with 256-byte rows)."""
     lds = [0] + [b for b in (11, 12) if b <= n]
-    return list(itertools.product(lds, (0, 1), (256, 512), (4, 5)))
+    return list(itertools.product(lds, (0, 1), (256, 512), (4, 5), (7, 8)))
 
 
 def tune_qft(n: int = 27, reps: int = 5, candidates=None) -> dict:

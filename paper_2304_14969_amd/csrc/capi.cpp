@@ -282,6 +282,12 @@ int qs_tune_set(const char* key, int64_t value) {
   } else if (!std::strcmp(key, "qft.round_bits")) {
     if (value != 4 && value != 5) return fail(QS_E_INVAL, "qft.round_bits must be 4 or 5");
     g_qft_tune.round_bits = int(value);
+  } else if (!std::strcmp(key, "qft.col_rows")) {
+    if (value < 0 || value > 1) return fail(QS_E_INVAL, "qft.col_rows must be 0 or 1");
+    g_qft_tune.col_rows = int(value);
+  } else if (!std::strcmp(key, "qft.col_max")) {
+    if (value != 7 && value != 8) return fail(QS_E_INVAL, "qft.col_max must be 7 or 8");
+    g_qft_tune.col_max = int(value);
   } else if (!std::strcmp(key, "tile.low_bits")) {
     if (value < 4 || value > 6) return fail(QS_E_INVAL, "tile.low_bits must be 4, 5 or 6");
     qs::g_tile_low_c64 = int(value);
@@ -307,6 +313,8 @@ int qs_tune_get(const char* key, int64_t* value) {
   else if (!std::strcmp(key, "qft.round_bits")) *value = g_qft_tune.round_bits;
   else if (!std::strcmp(key, "factor.multi_test")) *value = qs::g_multi_test;
   else if (!std::strcmp(key, "tile.mfma")) *value = g_tile_mfma;
+  else if (!std::strcmp(key, "qft.col_max")) *value = g_qft_tune.col_max;
+  else if (!std::strcmp(key, "qft.col_rows")) *value = g_qft_tune.col_rows;
   else if (!std::strcmp(key, "tile.low_bits")) *value = qs::g_tile_low_c64;
   else return fail(QS_E_INVAL, "unknown tuning key '%s'", key);
   return QS_OK;
@@ -644,13 +652,16 @@ int qs_qft(qs_state* st, int start, int len, int inverse) {
                      : qs::qft_plan<double>(st->n, start, len, reversed, g_qft_tune, plan, 64);
   if (np < 0) return fail(QS_E_UNSUPPORTED, "QFT pass plan failed");
   const int sign = inverse ? -1 : 1;
-  static const char* kind_names[3][8] = {
-      {"qft_lds", "qft_lds", "qft_lds", "qft_lds", "qft_lds", "qft_lds", "qft_lds", "qft_lds"},
-      {"", "qft_col1", "qft_col2", "qft_col3", "qft_col4", "qft_col5", "qft_col6", "qft_col7"},
-      {"", "qft_reg1", "qft_reg2", "qft_reg3", "qft_reg4", "qft_reg5", "", ""}};
+  static const char* kind_names[3][9] = {
+      {"qft_lds", "qft_lds", "qft_lds", "qft_lds", "qft_lds", "qft_lds", "qft_lds", "qft_lds",
+       "qft_lds"},
+      {"", "qft_col1", "qft_col2", "qft_col3", "qft_col4", "qft_col5", "qft_col6", "qft_col7",
+       "qft_col8"},
+      {"", "qft_reg1", "qft_reg2", "qft_reg3", "qft_reg4", "qft_reg5", "", "", ""}};
   for (int k = 0; k < np; ++k) {
-    const int g = plan[k].hi - plan[k].lo;
-    ProfScope ps(st, kind_names[plan[k].kind][g & 7], 2.0 * std::ldexp(1.0, st->n) * ab(st));
+    const int g = plan[k].kind == qs::QftPass::LDS ? 0 : plan[k].hi - plan[k].lo;
+    ProfScope ps(st, kind_names[plan[k].kind][g <= 8 ? g : 0],
+                 2.0 * std::ldexp(1.0, st->n) * ab(st));
     hipError_t e =
         st->dtype == QS_C64
             ? qs::launch_qft_pass(static_cast<float*>(st->amps), st->n, start, len, plan[k], sign,

@@ -369,7 +369,8 @@ Roots32<R> make_roots() {
 // or 32 (complex128) columns (64 KiB).
 template <typename R> constexpr int lds_bits() { return sizeof(R) == 4 ? 13 : 12; }
 template <typename R> constexpr int col_bits() { return sizeof(R) == 4 ? 6 : 5; }
-constexpr int kColMax = 7;
+constexpr int kColMax = 7;   // strided pass bits with 512-byte rows
+constexpr int kColMax8 = 8;  // with 256-byte rows (knob qft.col_max)
 constexpr int kRegMax = 5;
 
 // Threads of a tile launch: at most `cap`, at most one per 16-byte vector of
@@ -400,10 +401,9 @@ hipError_t launch_reg(R* a, int n, int start, int len, int lo, int sign, R scale
   return hipGetLastError();
 }
 
-template <typename R, int G, bool REV, int CAP, int WMAX>
+template <typename R, int G, int C, bool REV, int CAP, int WMAX>
 hipError_t launch_col_cfg(R* a, int n, int start, int len, int lo, int sign, R scale,
                           const Roots32<R>& rt, hipStream_t s) {
-  constexpr int C = col_bits<R>();
   if (lo < C || n < lo + G) return hipErrorInvalidValue;
   constexpr int NT =
       tile_threads(G + C, (1 << (G + C)) / Vec16<R>::AMPS, round_width(G, WMAX), CAP);
@@ -419,7 +419,7 @@ template <typename R, int T, bool REV, int CAP, int WMAX>
 hipError_t launch_lds_cfg(R* a, int n, int start, int len, int lo, int hi, int sign, R scale,
                           const Roots32<R>& rt, hipStream_t s) {
   constexpr int VEC = (1 << T) / Vec16<R>::AMPS > 0 ? (1 << T) / Vec16<R>::AMPS : 1;
-  constexpr int NT = tile_threads(T, VEC, WMAX < T ? WMAX : T, CAP);
+  constexpr int NT = tile_threads(T, VEC, round_width(T, WMAX), CAP);
   const size_t bytes = size_t((1 << T) + ((1 << T) >> 4)) * 2 * sizeof(R);
   auto kern = k_qft_lds<R, T, REV, NT, WMAX>;
   allow_lds(kern, bytes);
@@ -431,16 +431,31 @@ hipError_t launch_lds_cfg(R* a, int n, int start, int len, int lo, int hi, int s
 // Launch configurations selectable by the tuning knobs: thread cap 256 or
 // 512, round width 4 or 5 (tiles of at least 2^11 entries / 2^5 rows); smaller
 // tiles always use cap 256 and rounds of 4.
+template <typename R, int G, int C, bool REV>
+hipError_t launch_col_c(R* a, int n, int start, int len, int lo, int sign, R scale,
+                        const Roots32<R>& rt, const QftTuning& tune, hipStream_t s) {
+  if (G < 5 || (tune.threads < 512 && tune.round_bits < 5))
+    return launch_col_cfg<R, G, C, REV, 256, 4>(a, n, start, len, lo, sign, scale, rt, s);
+  if (tune.threads >= 512 && tune.round_bits >= 5)
+    return launch_col_cfg<R, G, C, REV, 512, 5>(a, n, start, len, lo, sign, scale, rt, s);
+  if (tune.threads >= 512)
+    return launch_col_cfg<R, G, C, REV, 512, 4>(a, n, start, len, lo, sign, scale, rt, s);
+  return launch_col_cfg<R, G, C, REV, 256, 5>(a, n, start, len, lo, sign, scale, rt, s);
+}
+
+// Strided tiles of 2^G rows x 2^C columns: 512-byte rows (64 KiB at G = 7),
+// or 256-byte rows for G = 8 (64 KiB) and, with qft.col_rows = 1, for G = 7
+// (32 KiB, more workgroups per CU).
 template <typename R, int G, bool REV>
 hipError_t launch_col(R* a, int n, int start, int len, int lo, int sign, R scale,
                       const Roots32<R>& rt, const QftTuning& tune, hipStream_t s) {
-  if (G < 5 || (tune.threads < 512 && tune.round_bits < 5))
-    return launch_col_cfg<R, G, REV, 256, 4>(a, n, start, len, lo, sign, scale, rt, s);
-  if (tune.threads >= 512 && tune.round_bits >= 5)
-    return launch_col_cfg<R, G, REV, 512, 5>(a, n, start, len, lo, sign, scale, rt, s);
-  if (tune.threads >= 512)
-    return launch_col_cfg<R, G, REV, 512, 4>(a, n, start, len, lo, sign, scale, rt, s);
-  return launch_col_cfg<R, G, REV, 256, 5>(a, n, start, len, lo, sign, scale, rt, s);
+  constexpr int CB = col_bits<R>();
+  if constexpr (G == 8)
+    return launch_col_c<R, G, CB - 1, REV>(a, n, start, len, lo, sign, scale, rt, tune, s);
+  if constexpr (G == 7)
+    if (tune.col_rows == 1)
+      return launch_col_c<R, G, CB - 1, REV>(a, n, start, len, lo, sign, scale, rt, tune, s);
+  return launch_col_c<R, G, CB, REV>(a, n, start, len, lo, sign, scale, rt, tune, s);
 }
 
 template <typename R, int T, bool REV>
@@ -493,6 +508,7 @@ hipError_t launch_pass(R* a, int n, int start, int len, const QftPass& ps, int s
         case 5: return launch_col<R, 5, REV>(a, n, start, len, ps.lo, sign, scale, rt, tune, s);
         case 6: return launch_col<R, 6, REV>(a, n, start, len, ps.lo, sign, scale, rt, tune, s);
         case 7: return launch_col<R, 7, REV>(a, n, start, len, ps.lo, sign, scale, rt, tune, s);
+        case 8: return launch_col<R, 8, REV>(a, n, start, len, ps.lo, sign, scale, rt, tune, s);
         default: return hipErrorInvalidValue;
       }
     case QftPass::REG:
@@ -534,7 +550,7 @@ int qft_plan(int n, int start, int len, bool rev, const QftTuning& tune, QftPass
   if (T > lds_bits<R>()) T = lds_bits<R>();
   if (T > n) T = n;
   const bool use_reg = tune.high_kind == 1;
-  const int wmax = use_reg ? kRegMax : kColMax;
+  const int wmax = use_reg ? kRegMax : (tune.col_max == 8 ? kColMax8 : kColMax);
   const int top = start + len;
   int reg_lo = start > T ? start : T;
   if (!use_reg && reg_lo < col_bits<R>()) reg_lo = col_bits<R>();

@@ -16,7 +16,7 @@ def test_tune_qft_leaves_a_correct_choice(qs_lib):
     keys = autotune.QFT_KEYS
     saved = {k: qs.tune_get(k) for k in keys}
     try:
-        cands = [(0, 0, 512, 4), (12, 1, 256, 5), (11, 0, 256, 4)]
+        cands = [(0, 0, 512, 4, 7), (12, 1, 256, 5, 8), (11, 0, 256, 4, 8)]
         r = autotune.tune_qft(n, reps=2, candidates=cands)
         assert len(r["tried"]) == 3
         assert tuple(r["best"][k] for k in keys) in cands

@@ -260,13 +260,15 @@ def test_error_codes(qs_lib):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("high_pass,lds_bits", [(0, 0), (1, 0), (0, 9), (1, 10), (0, 12), (0, 7)])
+@pytest.mark.parametrize("high_pass,lds_bits", [(0, 0), (1, 0), (0, 9), (1, 10), (0, 12), (0, 7),
+                                               (0, 13)])
 def test_qft_pass_variants(qs_lib, dtype, high_pass, lds_bits):
     """Every planner variant (LDS tile size, strided-LDS or register passes
     above it) in both storage orientations."""
     qs = qs_lib
     n = 17
     a = workloads.gaussian_state(n, 555)
+    saved = {k: qs.tune_get(k) for k in ("qft.high_pass", "qft.lds_bits")}
     qs.tune_set("qft.high_pass", high_pass)
     qs.tune_set("qft.lds_bits", lds_bits)
     try:
@@ -280,6 +282,37 @@ def test_qft_pass_variants(qs_lib, dtype, high_pass, lds_bits):
             want = dense.qft(want, n, 3, 11)
             assert_parity(st.amplitudes(), want, dtype, "partial")
     finally:
-        qs.tune_set("qft.high_pass", 0)
-        qs.tune_set("qft.lds_bits", 0)
+        for k, v in saved.items():
+            qs.tune_set(k, v)
 
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,lds_bits,col_rows", [(19, 11, 0), (20, 12, 1), (22, 11, 1),
+                                                 (21, 0, 1)])
+def test_qft_eight_bit_strided_passes(qs_lib, dtype, n, lds_bits, col_rows):
+    """Strided passes of 8 row bits (256-byte rows) above a smaller contiguous
+    tile: sampled outputs against the oracle's DFT entries (Eq. dft), then
+    QFT^2 = index negation (natural and bit-reversed storage) and the
+    inverse transforms back to the input."""
+    qs = qs_lib
+    a = workloads.gaussian_state(n, 900 + n)
+    N = 2 ** n
+    js = np.random.default_rng(n).integers(0, N, 48)
+    saved = {k: qs.tune_get(k) for k in ("qft.col_max", "qft.lds_bits", "qft.col_rows")}
+    qs.tune_set("qft.col_max", 8)
+    qs.tune_set("qft.lds_bits", lds_bits)
+    qs.tune_set("qft.col_rows", col_rows)
+    try:
+        with fresh(qs, n, dtype, a) as st:
+            st.qft()
+            assert_parity(st.gather(js.astype(np.uint64)), dense.dft_entries(a, n, js), dtype,
+                          f"col8 n={n} T={lds_bits}")
+            st.qft()
+            assert_parity(st.amplitudes(), a[(-np.arange(N)) % N], dtype, "QFT^2")
+            st.qft(inverse=True)
+            st.qft(inverse=True)
+            assert_parity(st.amplitudes(), a, dtype, "roundtrip")
+    finally:
+        for k, v in saved.items():
+            qs.tune_set(k, v)

@@ -27,6 +27,7 @@ def test_qft27_basis_state_closed_form(qs_lib, high_pass):
     """Strided-LDS passes above the contiguous tile (bench.py's configuration)
     and register passes."""
     qs = qs_lib
+    saved = qs.tune_get("qft.high_pass")
     qs.tune_set("qft.high_pass", high_pass)
     try:
         x = workloads.basis_index(N27, 0)
@@ -41,7 +42,7 @@ def test_qft27_basis_state_closed_form(qs_lib, high_pass):
             assert err.max() / np.abs(want).max() <= 1e-4, err.max()
             assert abs(st.norm() - 1.0) < 1e-5
     finally:
-        qs.tune_set("qft.high_pass", 0)
+        qs.tune_set("qft.high_pass", saved)
 
 
 def test_qft27_gaussian_spot_checks_and_roundtrip(qs_lib):
