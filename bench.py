@@ -185,30 +185,38 @@ def bench_approx(qs, workloads, protocol, np, family: str, p_cmp: float = 0.6,
 
 
 def bench_batch(qs, workloads, torch, count: int = 1024, seed: int = 300, depth: int = 8) -> dict:
-    """Many small random circuits (12-20 qubits) in one arena: batched launches,
-    the same as a replayed HIP graph, and one state at a time."""
+    """Many small random circuits (12-20 qubits) in one arena: batched tile
+    passes (one launch per pass index over all kets), batched fused blocks
+    (one launch per block width per pass), each eager and as a replayed HIP
+    graph, and one state at a time."""
     widths = workloads.batch_widths(count, seed)
     circs = [qs.Circuit(n).add_gates(workloads.random_circuit(n, depth, seed * 1000 + i))
              for i, n in enumerate(widths)]
-    b = qs.Batch(widths, qs.C64, stream=torch.cuda.Stream())  # capture needs its own stream
-    b.run(circs, 4)
-    b.synchronize()
-    t0 = time.perf_counter()
-    b.reset()
-    b.run(circs, 4)
-    b.synchronize()
-    t_run = time.perf_counter() - t0
-    b.capture(circs, 4)
-    b.reset()
-    b.replay()
-    b.synchronize()
-    t0 = time.perf_counter()
-    b.reset()
-    b.replay()
-    b.synchronize()
-    t_graph = time.perf_counter() - t0
-    info = b.info()
-    b.free()
+    out = {"workload": f"{count} random circuits of 12-20 qubits, depth {depth}, complex64"}
+    for mode in ("tiles", "blocks"):
+        b = qs.Batch(widths, qs.C64, stream=torch.cuda.Stream())  # capture needs its own stream
+        b.use_tiles(mode == "tiles")
+        b.run(circs, 4)
+        b.synchronize()
+        t0 = time.perf_counter()
+        b.reset()
+        b.run(circs, 4)
+        b.synchronize()
+        t_run = time.perf_counter() - t0
+        b.capture(circs, 4)
+        b.reset()
+        b.replay()
+        b.synchronize()
+        t0 = time.perf_counter()
+        b.reset()
+        b.replay()
+        b.synchronize()
+        t_graph = time.perf_counter() - t0
+        info = b.info()
+        b.free()
+        out[mode] = {"launches": info["launches"], "batched_s": round(t_run, 4),
+                     "graph_replay_s": round(t_graph, 4)}
+        out["total_amps"] = info["total_amps"]
     for c in circs:
         c.plan(4)
     t0 = time.perf_counter()
@@ -217,13 +225,10 @@ def bench_batch(qs, workloads, torch, count: int = 1024, seed: int = 300, depth:
         st.run(c)
         st.free()
     torch.cuda.synchronize()
-    t_one = time.perf_counter() - t0
+    out["one_by_one_s"] = round(time.perf_counter() - t0, 4)
     for c in circs:
         c.free()
-    return {"workload": f"{count} random circuits of 12-20 qubits, depth {depth}, complex64",
-            "total_amps": info["total_amps"], "launches": info["launches"],
-            "batched_s": round(t_run, 4), "graph_replay_s": round(t_graph, 4),
-            "one_by_one_s": round(t_one, 4)}
+    return out
 
 
 def bench_validation(qs, workloads, protocol, n: int = 20, p: float = 0.1, seeds=range(200, 210)) -> dict:

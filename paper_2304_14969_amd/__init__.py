@@ -129,6 +129,7 @@ _SIGS = [
     ("qs_batch_run", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_int]),
     ("qs_batch_capture", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_int]),
     ("qs_batch_replay", C.c_int, [C.c_void_p]),
+    ("qs_batch_use_tiles", C.c_int, [C.c_void_p, C.c_int]),
     ("qs_batch_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_uint64)]),
     ("qs_batch_amplitudes", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_uint64, C.c_int]),
     ("qs_batch_synchronize", C.c_int, [C.c_void_p]),
@@ -351,6 +352,10 @@ class Batch:
 
     def synchronize(self):
         _check(self.lib, self.lib.qs_batch_synchronize(self.h))
+
+    def use_tiles(self, on: bool = True):
+        _check(self.lib, self.lib.qs_batch_use_tiles(self.h, int(bool(on))))
+        return self
 
     def info(self) -> dict:
         n, t = C.c_int(), C.c_uint64()

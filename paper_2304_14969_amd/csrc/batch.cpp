@@ -42,7 +42,8 @@ struct Launch {
   size_t item0;  // first item of this launch in the item table
   int nitems;
   uint64_t tiles;
-  int k;
+  int k;             // block launches: block width
+  bool tile = false; // a batched tile pass (items in the tile-item table)
 };
 
 }  // namespace
@@ -59,6 +60,15 @@ struct qs_batch {
   // tables of the last prepared run
   qs::BatchItem* d_items = nullptr;
   void* d_mats = nullptr;
+  bool tiles = false;                 // complex64 kets of >= 12 qubits as tile passes
+  qs::TileItem* d_titems = nullptr;   // tile items of every pass launch
+  // what the prepared tables were built from: the circuits, their generations,
+  // kmax and the tile switch (a run with the same reuses them)
+  std::vector<std::pair<const qs_circuit*, uint64_t>> built_from;
+  int built_kmax = 0;
+  bool built_tiles = false;
+  void* d_tdata = nullptr;            // round table, then the embedded round matrices
+  size_t tmats_off = 0;               // byte offset of the matrices in d_tdata
   std::vector<Launch> launches;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -76,13 +86,100 @@ void drop_run(qs_batch* b) {
   b->graph = nullptr;
   qs::device_free(b->d_items);
   qs::device_free(b->d_mats);
+  qs::device_free(b->d_titems);
+  qs::device_free(b->d_tdata);
   b->d_items = nullptr;
   b->d_mats = nullptr;
+  b->d_titems = nullptr;
+  b->d_tdata = nullptr;
   b->launches.clear();
+  b->built_from.clear();
 }
 
-// Builds and uploads the pass tables of a run (synchronous upload).
+// Tile passes for the kets that take them: one launch per pass index over
+// every ket that has that pass. Fills use_tile; false if nothing to do.
+int prepare_tiles(qs_batch* b, qs_circuit* const* circs, std::vector<char>* use_tile) {
+  use_tile->assign(b->count, 0);
+  if (!b->tiles || b->dtype != QS_C64) return QS_OK;
+  constexpr int C = qs::kBatchTileLow, H = qs::kTileRowBits;
+  std::vector<const qs::TilePlan*> plans(b->count, nullptr);
+  size_t maxp = 0;
+  for (int i = 0; i < b->count; ++i) {
+    qs_circuit* c = circs[i];
+    if (b->n[i] < C + H || c->gates.empty()) continue;
+    if (!c->bplan_ok || c->bplan.C != C) {
+      c->bplan = qs::plan_tiles(c->gates, b->n[i], C, H, 4, true);
+      c->bplan_ok = true;
+    }
+    plans[i] = &c->bplan;
+    bool ok = true;
+    for (const auto& st : plans[i]->steps) ok = ok && !st.block;
+    if (!ok) continue;
+    (*use_tile)[i] = 1;
+    maxp = std::max(maxp, plans[i]->steps.size());
+  }
+  if (!maxp) return QS_OK;
+  // rounds of every ket, in ket order; round_base[i] = first round of ket i
+  std::vector<int32_t> rtab;
+  std::vector<float> emb;
+  std::vector<int> round_base(b->count, 0);
+  int nround = 0;
+  for (int i = 0; i < b->count; ++i) {
+    if (!(*use_tile)[i]) continue;
+    round_base[i] = nround;
+    for (const auto& r : plans[i]->rounds) {
+      rtab.push_back(r.bits[0] | (r.bits[1] << 8) | (r.bits[2] << 16) | (r.bits[3] << 24));
+      rtab.push_back(nround * 1024);
+      rtab.push_back(0);
+      rtab.push_back(0);
+      emb.resize(size_t(nround + 1) * 1024);
+      qs::embed_round(plans[i]->mats.data() + r.mat, emb.data() + size_t(nround) * 1024);
+      ++nround;
+    }
+  }
+  std::vector<qs::TileItem> items;
+  for (size_t p = 0; p < maxp; ++p) {
+    Launch L{items.size(), 0, 0, 0, true};
+    for (int i = 0; i < b->count; ++i) {
+      if (!(*use_tile)[i] || p >= plans[i]->steps.size()) continue;
+      const qs::TileStep& st = plans[i]->steps[p];
+      qs::TileItem it{};
+      it.amp_off = b->off[i];
+      it.first_tile = L.tiles;
+      for (int j = 0; j < H; ++j) it.rows.b[j] = st.hb[j];
+      it.r0 = round_base[i] + st.r0;
+      it.nr = st.nr;
+      items.push_back(it);
+      L.tiles += uint64_t(1) << (b->n[i] - C - H);
+      ++L.nitems;
+    }
+    if (L.nitems) b->launches.push_back(L);
+  }
+  const size_t rbytes = (rtab.size() * sizeof(int32_t) + 255) / 256 * 256;
+  b->tmats_off = rbytes;
+  b->d_titems = static_cast<qs::TileItem*>(qs::device_alloc(items.size() * sizeof(qs::TileItem)));
+  b->d_tdata = qs::device_alloc(rbytes + emb.size() * sizeof(float));
+  if (!b->d_titems || !b->d_tdata) return bfail(QS_E_NOMEM, "batch tile tables");
+  std::vector<unsigned char> host(rbytes + emb.size() * sizeof(float), 0);
+  std::memcpy(host.data(), rtab.data(), rtab.size() * sizeof(int32_t));
+  std::memcpy(host.data() + rbytes, emb.data(), emb.size() * sizeof(float));
+  hipError_t e = hipMemcpy(b->d_titems, items.data(), items.size() * sizeof(qs::TileItem),
+                           hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_tdata, host.data(), host.size(), hipMemcpyHostToDevice);
+  return berr(e, "batch tile table upload");
+}
+
+// Builds and uploads the pass tables of a run (synchronous upload), unless
+// the tables in place were built from the same, unchanged circuits.
 int prepare(qs_batch* b, qs_circuit* const* circs, int kmax) {
+  if (!b->built_from.empty() && b->built_kmax == kmax && b->built_tiles == b->tiles &&
+      !b->exec) {
+    bool same = true;
+    for (int i = 0; i < b->count && same; ++i)
+      same = circs[i] == b->built_from[i].first &&
+             circs[i]->generation == b->built_from[i].second;
+    if (same) return QS_OK;
+  }
   for (int i = 0; i < b->count; ++i) {
     qs_circuit* c = circs[i];
     if (!c) return bfail(QS_E_INVAL, "circuit %d is NULL", i);
@@ -95,11 +192,17 @@ int prepare(qs_batch* b, qs_circuit* const* circs, int kmax) {
       if (blk.k > 5) return bfail(QS_E_UNSUPPORTED, "batched blocks have at most 5 qubits");
   }
   drop_run(b);
-  // matrices: every block of every circuit
+  std::vector<char> use_tile;
+  if (int rc = prepare_tiles(b, circs, &use_tile)) {
+    drop_run(b);
+    return rc;
+  }
+  // matrices: every block of every circuit that runs as blocks
   std::vector<std::vector<uint64_t>> moff(b->count);
   uint64_t mtotal = 0;
   size_t maxblocks = 0;
   for (int i = 0; i < b->count; ++i) {
+    if (use_tile[i]) continue;
     for (const auto& blk : circs[i]->blocks) {
       moff[i].push_back(mtotal);
       mtotal += blk.m.size();
@@ -111,6 +214,7 @@ int prepare(qs_batch* b, qs_circuit* const* circs, int kmax) {
     for (int k = 1; k <= 5; ++k) {
       Launch L{items.size(), 0, 0, k};
       for (int i = 0; i < b->count; ++i) {
+        if (use_tile[i]) continue;
         const auto& blocks = circs[i]->blocks;
         if (p >= blocks.size() || blocks[p].k != k) continue;
         qs::BatchItem it{};
@@ -144,7 +248,7 @@ int prepare(qs_batch* b, qs_circuit* const* circs, int kmax) {
     if (b->dtype == QS_C64) {
       std::vector<float> h(2 * mtotal);
       for (int i = 0; i < b->count; ++i)
-        for (size_t p = 0; p < circs[i]->blocks.size(); ++p) {
+        for (size_t p = 0; !use_tile[i] && p < circs[i]->blocks.size(); ++p) {
           const auto& m = circs[i]->blocks[p].m;
           for (size_t j = 0; j < m.size(); ++j) {
             h[2 * (moff[i][p] + j)] = float(m[j].real());
@@ -155,7 +259,7 @@ int prepare(qs_batch* b, qs_circuit* const* circs, int kmax) {
     } else {
       std::vector<double> h(2 * mtotal);
       for (int i = 0; i < b->count; ++i)
-        for (size_t p = 0; p < circs[i]->blocks.size(); ++p) {
+        for (size_t p = 0; !use_tile[i] && p < circs[i]->blocks.size(); ++p) {
           const auto& m = circs[i]->blocks[p].m;
           for (size_t j = 0; j < m.size(); ++j) {
             h[2 * (moff[i][p] + j)] = m[j].real();
@@ -169,11 +273,23 @@ int prepare(qs_batch* b, qs_circuit* const* circs, int kmax) {
     drop_run(b);
     return berr(e, "batch table upload");
   }
+  b->built_from.clear();
+  for (int i = 0; i < b->count; ++i) b->built_from.emplace_back(circs[i], circs[i]->generation);
+  b->built_kmax = kmax;
+  b->built_tiles = b->tiles;
   return QS_OK;
 }
 
 hipError_t enqueue(qs_batch* b) {
   for (const Launch& L : b->launches) {
+    if (L.tile) {
+      const hipError_t e = qs::launch_tile_mfma_batch(
+          static_cast<float*>(b->arena), b->d_titems + L.item0, L.nitems, L.tiles, b->d_tdata,
+          reinterpret_cast<const float*>(static_cast<const char*>(b->d_tdata) + b->tmats_off),
+          b->stream);
+      if (e != hipSuccess) return e;
+      continue;
+    }
     hipError_t e =
         b->dtype == QS_C64
             ? qs::launch_batch_fused(static_cast<float*>(b->arena), b->d_items + L.item0, L.nitems,
@@ -292,6 +408,13 @@ int qs_batch_replay(qs_batch* b) {
   if (!b) return bfail(QS_E_INVAL, "batch is NULL");
   if (!b->exec) return bfail(QS_E_INVAL, "no captured run");
   return berr(hipGraphLaunch(b->exec, b->stream), "graph launch");
+}
+
+int qs_batch_use_tiles(qs_batch* b, int on) {
+  if (!b) return bfail(QS_E_INVAL, "batch is NULL");
+  drop_run(b);
+  b->tiles = on != 0;
+  return QS_OK;
 }
 
 int qs_batch_info(const qs_batch* b, int* launches, uint64_t* total_amps) {

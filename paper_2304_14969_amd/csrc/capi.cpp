@@ -2,6 +2,7 @@
 // map and dispatch to the HIP kernels. No simulation arithmetic happens here
 // beyond building small gate matrices and twiddle tables on the host in
 // float64 and rounding them once to the state's precision.
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -236,6 +237,14 @@ void* device_alloc(size_t bytes) { return dev_alloc(bytes); }
 void device_free(void* p) { dev_free(p); }
 
 // Drops a circuit's plan and its device copies (after an edit or a re-plan).
+// Process-wide generation numbers: a circuit gets a fresh one when created
+// and whenever its gate list changes, so (address, generation) identifies
+// one gate list even when a freed circuit's address is reused.
+uint64_t next_generation() {
+  static std::atomic<uint64_t> gen{0};
+  return ++gen;
+}
+
 void circuit_invalidate(qs_circuit* c) {
   // launches already queued may still read the matrices
   if (c->dmat[0] || c->dmat[1] || c->tcache[0].dev || c->tcache[1].dev) (void)hipDeviceSynchronize();
@@ -250,6 +259,9 @@ void circuit_invalidate(qs_circuit* c) {
   }
   c->planned = false;
   c->blocks.clear();
+  c->bplan_ok = false;
+  c->bplan = qs::TilePlan();
+  c->generation = next_generation();
 }
 
 }  // namespace qs
@@ -733,15 +745,7 @@ int tile_plan_for(qs_state* st, qs_circuit* c, qs_circuit::TileCache** out) {
   if (dense) {
     std::vector<float> A(1024);
     for (size_t ri = 0; ri < pl.rounds.size(); ++ri) {
-      const qs::cd* u = pl.mats.data() + pl.rounds[ri].mat;
-      for (int ks = 0; ks < 16; ++ks)
-        for (int lane = 0; lane < 64; ++lane) {
-          const int row = lane & 31, pp = lane >> 5;  // Uemb[row][2 ks + pp]
-          const qs::cd x = u[(row >> 1) * 16 + ks];
-          const double v = (row & 1) == 0 ? (pp == 0 ? x.real() : -x.imag())
-                                          : (pp == 0 ? x.imag() : x.real());
-          A[ks * 64 + lane] = float(v);
-        }
+      qs::embed_round(pl.mats.data() + pl.rounds[ri].mat, A.data());
       std::memcpy(host.data() + mats_at + ri * 1024 * sizeof(float), A.data(), 1024 * sizeof(float));
     }
   }

@@ -350,6 +350,17 @@ TilePlan plan_tiles(const std::vector<Gate>& gates, int n, int C, int H, int W, 
   return plan;
 }
 
+void embed_round(const cd* u, float* out) {
+  for (int ks = 0; ks < 16; ++ks)
+    for (int lane = 0; lane < 64; ++lane) {
+      const int row = lane & 31, pp = lane >> 5;
+      const cd x = u[(row >> 1) * 16 + ks];
+      const double v = (row & 1) == 0 ? (pp == 0 ? x.real() : -x.imag())
+                                      : (pp == 0 ? x.imag() : x.real());
+      out[ks * 64 + lane] = float(v);
+    }
+}
+
 }  // namespace qs
 
 // ------------------------------------------------------------------ C ABI
@@ -357,6 +368,7 @@ TilePlan plan_tiles(const std::vector<Gate>& gates, int n, int C, int H, int W, 
 namespace qs {
 void set_last_error(const char* msg);    // capi.cpp
 void circuit_invalidate(qs_circuit* c);  // frees device copies (capi.cpp)
+uint64_t next_generation();              // capi.cpp
 }  // namespace qs
 
 namespace {
@@ -378,6 +390,7 @@ int qs_circuit_create(int n, qs_circuit** out) {
   if (n < 1 || n > 64) return cfail(QS_E_INVAL, "n = %d outside [1, 64]", n);
   qs_circuit* c = new qs_circuit();
   c->n = n;
+  c->generation = qs::next_generation();
   c->pos.resize(n);
   for (int q = 0; q < n; ++q) c->pos[q] = q;
   *out = c;

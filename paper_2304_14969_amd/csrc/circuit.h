@@ -84,10 +84,17 @@ struct TilePlan {
 // dense blocks between passes.
 TilePlan plan_tiles(const std::vector<Gate>& gates, int n, int C, int H, int W, bool dense);
 
+// The operand a matrix-core round reads: the 32 x 32 real embedding
+// [[Re U, -Im U], [Im U, Re U]] (interleaved rows and columns) of a 16 x 16
+// complex round matrix u, in lane order: out[ks * 64 + lane] =
+// Uemb[lane % 32][2 ks + lane / 32].
+void embed_round(const cd* u, float* out);
+
 }  // namespace qs
 
 struct qs_circuit {
   int n = 0;
+  uint64_t generation = 0;      // bumped whenever the gate list changes
   std::vector<qs::Gate> gates;  // on virtual positions (SWAPs already folded)
   std::vector<int> pos;         // logical qubit -> virtual position after all SWAPs
   int kmax = 5;
@@ -104,4 +111,8 @@ struct qs_circuit {
     void* dev = nullptr;   // rounds, gates, matrices (owned)
     size_t gates_off = 0, mats_off = 0, emb_off = 0;  // byte offsets in dev
   } tcache[2];
+  // host plan for batched runs (identity labelling, dense rounds); cleared
+  // with the other plans when the circuit changes
+  bool bplan_ok = false;
+  qs::TilePlan bplan;
 };

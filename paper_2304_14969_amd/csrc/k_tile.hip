@@ -193,10 +193,13 @@ __global__ void __launch_bounds__(1 << (C + H - kW))
 // Uemb[lane % 32][2 ks + lane / 32].
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+// One tile of a matrix-core pass: `base` is the global index of tile entry 0
+// (zeros at the low bits and the row bits), `rows` the row bits.
 template <int C, int H>
-__global__ void __launch_bounds__(1 << (C + H - kW))
-    k_tile_mfma(float* __restrict__ a, TileRows rows, const int4* __restrict__ rounds,
-                int nrounds, const float* __restrict__ amats) {
+__device__ __forceinline__ void tile_mfma_body(float* __restrict__ a, uint64_t base,
+                                               const TileRows& rows,
+                                               const int4* __restrict__ rounds, int nrounds,
+                                               const float* __restrict__ amats) {
   constexpr int TB = C + H;
   constexpr int NT = 1 << (TB - kW);
   constexpr int VPR = (1 << C) / 2;        // float4 vectors per row
@@ -205,10 +208,6 @@ __global__ void __launch_bounds__(1 << (C + H - kW))
   extern __shared__ unsigned char smraw[];
   float2* sm = reinterpret_cast<float2*>(smraw);
   const float* smf = reinterpret_cast<const float*>(smraw);
-  // tile base: the workgroup index spread over the bits outside the tile
-  uint64_t base = uint64_t(blockIdx.x) << C;
-#pragma unroll
-  for (int j = 0; j < H; ++j) base = insert_zero(base, rows.b[j]);
   auto glob = [&](int row, int col) {
     uint64_t g = base | uint64_t(col);
 #pragma unroll
@@ -285,6 +284,37 @@ __global__ void __launch_bounds__(1 << (C + H - kW))
   }
 }
 
+template <int C, int H>
+__global__ void __launch_bounds__(1 << (C + H - kW))
+    k_tile_mfma(float* __restrict__ a, TileRows rows, const int4* __restrict__ rounds,
+                int nrounds, const float* __restrict__ amats) {
+  // tile base: the workgroup index spread over the bits outside the tile
+  uint64_t base = uint64_t(blockIdx.x) << C;
+#pragma unroll
+  for (int j = 0; j < H; ++j) base = insert_zero(base, rows.b[j]);
+  tile_mfma_body<C, H>(a, base, rows, rounds, nrounds, amats);
+}
+
+// Many kets at once: workgroup -> item by binary search over the items'
+// first tiles; each item is one pass of one ket of the arena.
+template <int C, int H>
+__global__ void __launch_bounds__(1 << (C + H - kW))
+    k_tile_mfma_batch(float* __restrict__ arena, const TileItem* __restrict__ items, int nitems,
+                      const int4* __restrict__ rounds, const float* __restrict__ amats) {
+  int lo = 0, hi = nitems - 1;
+  const uint64_t b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].first_tile <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const TileItem& it = items[lo];
+  uint64_t base = (b - it.first_tile) << C;
+#pragma unroll
+  for (int j = 0; j < H; ++j) base = insert_zero(base, it.rows.b[j]);
+  tile_mfma_body<C, H>(arena + 2 * it.amp_off, base, it.rows, rounds + it.r0, it.nr, amats);
+}
+
 }  // namespace
 
 namespace {
@@ -353,6 +383,19 @@ hipError_t launch_tile_pass(R* a, int n, int low_bits, const TileRows& rows, con
   if constexpr (sizeof(R) == 4)
     if (low_bits == 6) return launch_pass_c<R, 6>(a, n, rows, rounds, nrounds, gates, mats, s);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_tile_mfma_batch(float* arena, const TileItem* items, int nitems, uint64_t tiles,
+                                  const void* rounds, const float* amats, hipStream_t s) {
+  constexpr int C = kBatchTileLow, H = kTileRowBits, TB = C + H;
+  if (nitems < 1 || tiles < 1 || tiles > 0x7fffffffu) return hipErrorInvalidValue;
+  const size_t bytes = size_t((1 << TB) + ((1 << TB) >> 4)) * sizeof(float2);
+  auto kern = k_tile_mfma_batch<C, H>;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  hipLaunchKernelGGL(kern, dim3(unsigned(tiles)), dim3(1 << (TB - kW)), bytes, s, arena, items,
+                     nitems, static_cast<const int4*>(rounds), amats);
+  return hipGetLastError();
 }
 
 template hipError_t launch_tile_pass<float>(float*, int, int, const TileRows&, const void*, int,

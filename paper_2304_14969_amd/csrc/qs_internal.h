@@ -127,6 +127,19 @@ extern int g_tile_low_c64;  // low tile bits of complex64 passes: 5 or 6
 template <typename R>
 hipError_t launch_tile_pass(R* a, int n, int low_bits, const TileRows& rows, const void* rounds,
                             int nrounds, const void* gates, const R* mats, hipStream_t s);
+// Batched complex64 tile passes: one item = one pass of one ket of an arena
+// of n >= kBatchTileLow + kTileRowBits qubits; items sorted by first_tile,
+// the tiles of item i are [first_tile_i, first_tile_{i+1}); its rounds are
+// rounds[r0 .. r0 + nr) (int4 as for launch_tile_mfma).
+constexpr int kBatchTileLow = 5;
+struct TileItem {
+  uint64_t amp_off;     // amplitude offset of the ket in the arena
+  uint64_t first_tile;  // first workgroup of the item
+  TileRows rows;
+  int r0, nr;
+};
+hipError_t launch_tile_mfma_batch(float* arena, const TileItem* items, int nitems, uint64_t tiles,
+                                  const void* rounds, const float* amats, hipStream_t s);
 // Complex64 pass with dense 4-qubit rounds on the matrix cores: `rounds`
 // int4 {bits packed 8 per byte, offset of the round's embedded matrix in
 // amats (1024 floats, lane order), 0, 0}.

@@ -76,3 +76,108 @@ def test_batch_1024_circuits(qs_lib):
         a = b.amplitudes(i).astype(np.complex128)
         assert abs(np.vdot(a, a).real - 1) < 1e-4
     b.free()
+
+
+def test_batch_tiles_match_oracle_and_blocks(qs_lib):
+    """Tile passes for the kets of >= 12 qubits, block launches for the
+    smaller ones, in one arena: every ket against the oracle; a complex128
+    batch with tiles on keeps its block launches."""
+    qs = qs_lib
+    widths = [6, 12, 13, 9, 14, 12, 15, 11, 16]
+    gl, circs = circuits_for(qs, widths, 5, 61)
+    b = qs.Batch(widths, C64).use_tiles()
+    b.run(circs)
+    tiled = b.info()["launches"]
+    for i, (n, g) in enumerate(zip(widths, gl)):
+        assert_parity(b.amplitudes(i), dense.run_circuit(dense.zero_state(n), n, g), C64,
+                      f"ket {i} n={n}")
+    b.use_tiles(False)
+    b.reset()
+    b.run(circs)
+    assert tiled < b.info()["launches"]
+    b.free()
+    b2 = qs.Batch(widths, C128).use_tiles()
+    b2.run(circs)
+    for i, (n, g) in enumerate(zip(widths, gl)):
+        assert_parity(b2.amplitudes(i), dense.run_circuit(dense.zero_state(n), n, g), C128,
+                      f"c128 ket {i}")
+    b2.free()
+
+
+def test_batch_tiles_graph_replays(qs_lib):
+    import torch
+    qs = qs_lib
+    widths = workloads.batch_widths(24, 5, low=12, high=16)
+    gl, circs = circuits_for(qs, widths, 6, 9)
+    side = torch.cuda.Stream()
+    b = qs.Batch(widths, C64, stream=side).use_tiles()
+    b.capture(circs)
+    want = [dense.run_circuit(dense.zero_state(n), n, g) for n, g in zip(widths, gl)]
+    first = None
+    for rep in range(3):
+        b.reset()
+        b.replay()
+        b.synchronize()
+        x = torch.ones(1 << 20, device="cuda").sum().item()
+        assert x == float(1 << 20)
+        got = [b.amplitudes(i) for i in range(len(widths))]
+        if first is None:
+            first = got
+            for i, n in enumerate(widths):
+                assert_parity(got[i], want[i], C64, f"ket {i} n={n}")
+        else:
+            for a, c in zip(first, got):
+                np.testing.assert_array_equal(a, c)
+    b.free()
+
+
+def test_batch_1024_circuits_tiles(qs_lib):
+    """The 1024-circuit batch with tile passes: a few launches per pass index;
+    sampled kets against the oracle, every ket normalized."""
+    qs = qs_lib
+    widths = workloads.batch_widths(1024, 300)
+    gl, circs = circuits_for(qs, widths, 8, 300)
+    b = qs.Batch(widths, C64).use_tiles()
+    b.run(circs)
+    b.synchronize()
+    assert b.info()["launches"] <= 20
+    for i in [i for i, n in enumerate(widths) if n <= 13][:3]:
+        n = widths[i]
+        assert_parity(b.amplitudes(i), dense.run_circuit(dense.zero_state(n), n, gl[i]), C64,
+                      f"ket {i}")
+    for i in range(0, 1024, 61):
+        a = b.amplitudes(i).astype(np.complex128)
+        assert abs(np.vdot(a, a).real - 1) < 1e-4
+    b.free()
+
+
+@pytest.mark.parametrize("tiles", [False, True])
+def test_batch_tables_follow_circuit_changes(qs_lib, tiles):
+    """A run with the same, unchanged circuits reuses the prepared tables; a
+    changed circuit, or new circuits (even at a freed circuit's address), is
+    prepared again."""
+    qs = qs_lib
+    widths = [12, 13, 10]
+    gl, circs = circuits_for(qs, widths, 3, 71)
+    b = qs.Batch(widths, C64).use_tiles(tiles)
+    for _ in range(2):
+        b.reset()
+        b.run(circs)
+    for i, (n, g) in enumerate(zip(widths, gl)):
+        assert_parity(b.amplitudes(i), dense.run_circuit(dense.zero_state(n), n, g), C64, "same")
+    extra = [("h", 2), ("cx", 2, 7), ("u3", 9, 0.4, 0.5, 0.6)]
+    circs[1].add_gates(extra)
+    gl[1] = gl[1] + extra
+    b.reset()
+    b.run(circs)
+    for i, (n, g) in enumerate(zip(widths, gl)):
+        assert_parity(b.amplitudes(i), dense.run_circuit(dense.zero_state(n), n, g), C64,
+                      "changed")
+    for c in circs:
+        c.free()
+    gl2, circs2 = circuits_for(qs, widths, 3, 72)
+    b.reset()
+    b.run(circs2)
+    for i, (n, g) in enumerate(zip(widths, gl2)):
+        assert_parity(b.amplitudes(i), dense.run_circuit(dense.zero_state(n), n, g), C64, "new")
+    b.free()
