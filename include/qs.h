@@ -418,6 +418,10 @@ int qs_check(qs_state* st, double tol);
  *                    measures the lowest dirty qubit together with the next
  *                    dirty qubits of its subsystem (up to 5, none skipped) in
  *                    one sweep; 0: one sweep per qubit. Same decisions;
+ *   "factor.batch_1q" 1 (default): qs_run on a factorized state applies each
+ *                    run of consecutive one-qubit gates in one launch over
+ *                    the subsystems of at most 2^12 amplitudes (one
+ *                    workgroup per subsystem); 0: one launch per gate;
  *   "fused.mfma"     1 (default): complex64 blocks of 4 or 5 qubits run on the
  *                    matrix cores when their geometry fits; 0: vector FMA.
  * QS_E_INVAL for an unknown key or a value out of range. */

@@ -32,6 +32,7 @@
 namespace qs {
 
 int g_multi_test = 1;
+int g_batch_1q = 1;
 
 void* device_alloc(size_t bytes);
 void device_free(void* p);
@@ -469,6 +470,13 @@ void fact_release(FactorState* f) {
 
 void fact_drain(FactorState* f) {
   fact_release(f);
+  for (int i = 0; i < FactorState::kRingSlots; ++i) {
+    if (f->ring_ev[i]) (void)hipEventDestroy(f->ring_ev[i]);
+    if (f->ring_host[i]) (void)hipHostFree(f->ring_host[i]);
+    f->ring_ev[i] = nullptr;
+    f->ring_host[i] = f->ring_dev[i] = nullptr;
+    f->ring_used[i] = false;
+  }
   for (auto& v : f->pool) {
     for (void* p : v) device_free(p);
     v.clear();
@@ -614,6 +622,120 @@ int fact_apply(FactorState* f, const int* qubits, int k, const double* m) {
     }
   }
   return QS_OK;
+}
+
+namespace {
+
+// A free ring slot (waits for the launch that last used it); host and device
+// addresses of its table memory.
+int ring_slot(FactorState* f, void** host, void** dev) {
+  const int i = f->ring_next;
+  f->ring_next = (i + 1) % FactorState::kRingSlots;
+  if (!f->ring_host[i]) {
+    if (hipHostMalloc(&f->ring_host[i], FactorState::kSlotBytes, hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer(&f->ring_dev[i], f->ring_host[i], 0) != hipSuccess ||
+        hipEventCreateWithFlags(&f->ring_ev[i], hipEventDisableTiming) != hipSuccess)
+      return ffail(QS_E_NOMEM, "pinned table slot");
+  } else if (f->ring_used[i]) {
+    if (int rc = dev_err(hipEventSynchronize(f->ring_ev[i]), "table slot")) return rc;
+  }
+  *host = f->ring_host[i];
+  *dev = f->ring_dev[i];
+  return i;
+}
+
+template <typename R>
+int apply_1q_run(FactorState* f, const int* qubits, const double* m, int count) {
+  // the gates of each small subsystem, in circuit order
+  std::vector<int> item_of(f->subs.size(), -1);
+  std::vector<std::vector<int>> per_item;
+  std::vector<int> item_sub;
+  for (int i = 0; i < count; ++i) {
+    int t = 0;
+    const int si = find(f, qubits[i], &t);
+    if (si < 0) return ffail(QS_E_INVAL, "qubit %d not found", qubits[i]);
+    Sub& S = f->subs[si];
+    if (S.nq > kFact1qMaxQubits) {
+      Mat2<R> mm;
+      for (int e = 0; e < 4; ++e) {
+        mm.re[e] = R(m[8 * i + 2 * e]);
+        mm.im[e] = R(m[8 * i + 2 * e + 1]);
+      }
+      if (int rc = dev_err(launch_apply_1q(static_cast<R*>(S.amps), S.nq, t, mm, f->stream),
+                           "factorized gate"))
+        return rc;
+      continue;
+    }
+    if (item_of[si] < 0) {
+      item_of[si] = int(per_item.size());
+      per_item.emplace_back();
+      item_sub.push_back(si);
+    }
+    per_item[item_of[si]].push_back(i);
+  }
+  // Tables in slots: up to kItems items at the start, their gates after. An
+  // item whose gates do not all fit continues in the next launch, which the
+  // stream runs after this one, so every subsystem sees its gates in order.
+  constexpr size_t kItems = 512;
+  constexpr size_t kGatesAt = kItems * sizeof(Fact1qItem<R>);
+  constexpr size_t kGates = (FactorState::kSlotBytes - kGatesAt) / sizeof(Fact1qGate<R>);
+  static_assert(kGatesAt % 64 == 0 && kGates >= 64, "slot layout");
+  size_t j = 0, o = 0;  // next item, and how many of its gates are already out
+  while (j < per_item.size()) {
+    void *host = nullptr, *dev = nullptr;
+    const int slot = ring_slot(f, &host, &dev);
+    if (slot < 0) return slot;
+    auto* items = static_cast<Fact1qItem<R>*>(host);
+    auto* gates = reinterpret_cast<Fact1qGate<R>*>(static_cast<char*>(host) + kGatesAt);
+    size_t nit = 0, ng = 0;
+    int max_nq = 1;
+    while (j < per_item.size() && nit < kItems && ng < kGates) {
+      const Sub& S = f->subs[item_sub[j]];
+      max_nq = std::max(max_nq, S.nq);
+      const std::vector<int>& list = per_item[j];
+      const size_t take = std::min(list.size() - o, kGates - ng);
+      Fact1qItem<R>& it = items[nit++];
+      it.amps = static_cast<R*>(S.amps);
+      it.nq = S.nq;
+      it.g0 = int(ng);
+      it.ng = int(take);
+      it.pad = 0;
+      for (size_t x = 0; x < take; ++x) {
+        const int gi = list[o + x];
+        int t = 0;
+        find(f, qubits[gi], &t);
+        Fact1qGate<R>& gt = gates[ng++];
+        for (int e = 0; e < 8; ++e) gt.m[e] = R(m[8 * gi + e]);
+        gt.t = t;
+        gt.pad = 0;
+      }
+      o += take;
+      if (o == list.size()) {
+        ++j;
+        o = 0;
+      }
+    }
+    hipError_t e = launch_fact_1q_batch(
+        static_cast<const Fact1qItem<R>*>(dev), int(nit),
+        reinterpret_cast<const Fact1qGate<R>*>(static_cast<char*>(dev) + kGatesAt), max_nq,
+        f->stream);
+    if (e == hipSuccess) e = hipEventRecord(f->ring_ev[slot], f->stream);
+    if (int rc = dev_err(e, "batched one-qubit gates")) return rc;
+    f->ring_used[slot] = true;
+  }
+  return QS_OK;
+}
+
+}  // namespace
+
+int fact_apply_1q_run(FactorState* f, const int* qubits, const double* m, int count) {
+  if (!g_batch_1q || count < 2) {
+    for (int i = 0; i < count; ++i)
+      if (int rc = fact_apply(f, qubits + i, 1, m + 8 * i)) return rc;
+    return QS_OK;
+  }
+  return f->dtype == QS_C64 ? apply_1q_run<float>(f, qubits, m, count)
+                            : apply_1q_run<double>(f, qubits, m, count);
 }
 
 int fact_swap(FactorState* f, int a, int b) {

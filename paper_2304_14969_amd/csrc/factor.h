@@ -34,6 +34,15 @@ struct FactorState {
   double* scratch = nullptr;  // device reduction scratch
   double* hstat = nullptr;    // pinned, mapped host buffer of the four Bloch sums
   double* dstat = nullptr;    // its device address
+  // mapped pinned slots for the tables of batched one-qubit gates; a slot is
+  // reused only after the event recorded behind its launch has completed
+  static constexpr int kRingSlots = 4;
+  static constexpr size_t kSlotBytes = size_t(64) << 10;
+  void* ring_host[kRingSlots] = {nullptr};
+  void* ring_dev[kRingSlots] = {nullptr};
+  hipEvent_t ring_ev[kRingSlots] = {nullptr};
+  bool ring_used[kRingSlots] = {false};
+  int ring_next = 0;
   // recycled subsystem buffers of at most kPoolQubits qubits, by qubit count
   static constexpr int kPoolQubits = 20;
   std::vector<void*> pool[kPoolQubits + 1];
@@ -59,6 +68,9 @@ struct FactorState {
 // Process-wide: measure several dirty qubits of one subsystem per sweep (1,
 // default) or one qubit per sweep (0). Decisions are the same either way.
 extern int g_multi_test;
+// Process-wide: runs of consecutive one-qubit gates in one launch over the
+// small subsystems (1, default) or one launch per gate (0).
+extern int g_batch_1q;
 
 // The 32 proposal features of qubit q (threshold p) from the bookkeeping.
 void fact_features(const FactorState* f, int q, double p, float* out);
@@ -69,6 +81,11 @@ void fact_release(FactorState* f);                 // returns every subsystem bu
 void fact_drain(FactorState* f);                   // frees the recycled buffers too
 int fact_set_basis(FactorState* f, uint64_t x);    // n one-qubit basis states
 int fact_apply(FactorState* f, const int* qubits, int k, const double* m);
+// count one-qubit gates in order: gate i on qubits[i] with the 2x2 matrix
+// m + 8 i (interleaved, row-major). Subsystems of at most 2^12 amplitudes get
+// one workgroup each in a single launch that applies their gates in order;
+// larger subsystems get one launch per gate.
+int fact_apply_1q_run(FactorState* f, const int* qubits, const double* m, int count);
 int fact_swap(FactorState* f, int a, int b);       // relabel
 int fact_relabel(FactorState* f, const int* pos);  // label v -> q where pos[q] = v
 int fact_try_separate(FactorState* f, double p, int* n_separated);

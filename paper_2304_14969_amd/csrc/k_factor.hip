@@ -149,6 +149,34 @@ __global__ void __launch_bounds__(kBlock) k_bloch_multi(const R* __restrict__ a,
   }
 }
 
+// One workgroup per item: the item's subsystem (at most 2^12 amplitudes) is
+// staged in LDS, its gates are applied there in order, and it is stored back.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_fact_1q_batch(const Fact1qItem<R>* __restrict__ items,
+                                                          const Fact1qGate<R>* __restrict__ gates) {
+  extern __shared__ __align__(16) char fact_lds[];
+  R* sh = reinterpret_cast<R*>(fact_lds);
+  const Fact1qItem<R> it = items[blockIdx.x];
+  const uint32_t words = uint32_t(2) << it.nq, pairs = uint32_t(1) << (it.nq - 1);
+  for (uint32_t i = threadIdx.x; i < words; i += kBlock) sh[i] = it.amps[i];
+  __syncthreads();
+  for (int g = it.g0; g < it.g0 + it.ng; ++g) {
+    const Fact1qGate<R> gt = gates[g];
+    const uint32_t bit = uint32_t(1) << gt.t, low = bit - 1;
+    for (uint32_t u = threadIdx.x; u < pairs; u += kBlock) {
+      const uint32_t i0 = ((u & ~low) << 1) | (u & low), i1 = i0 | bit;
+      const R x0 = sh[2 * i0], y0 = sh[2 * i0 + 1];
+      const R x1 = sh[2 * i1], y1 = sh[2 * i1 + 1];
+      sh[2 * i0] = gt.m[0] * x0 - gt.m[1] * y0 + gt.m[2] * x1 - gt.m[3] * y1;
+      sh[2 * i0 + 1] = gt.m[0] * y0 + gt.m[1] * x0 + gt.m[2] * y1 + gt.m[3] * x1;
+      sh[2 * i1] = gt.m[4] * x0 - gt.m[5] * y0 + gt.m[6] * x1 - gt.m[7] * y1;
+      sh[2 * i1 + 1] = gt.m[4] * y0 + gt.m[5] * x0 + gt.m[6] * y1 + gt.m[7] * x1;
+    }
+    __syncthreads();  // the next gate reads what this one wrote
+  }
+  for (uint32_t i = threadIdx.x; i < words; i += kBlock) it.amps[i] = sh[i];
+}
+
 template <typename R>
 __global__ void k_store_single(R* __restrict__ dst, R a0r, R a0i, R a1r, R a1i) {
   if (threadIdx.x == 0) {
@@ -294,6 +322,16 @@ hipError_t launch_bloch_multi(const R* a, int nq, const int* bits, int G, double
 }
 
 template <typename R>
+hipError_t launch_fact_1q_batch(const Fact1qItem<R>* items, int nitems, const Fact1qGate<R>* gates,
+                                int max_nq, hipStream_t s) {
+  if (nitems < 1) return hipSuccess;
+  if (max_nq < 1 || max_nq > kFact1qMaxQubits) return hipErrorInvalidValue;
+  const size_t lds = (size_t(2) << max_nq) * sizeof(R);
+  hipLaunchKernelGGL(k_fact_1q_batch<R>, dim3(nitems), dim3(kBlock), lds, s, items, gates);
+  return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_store_single(R* dst, const double amp[4], hipStream_t s) {
   hipLaunchKernelGGL(k_store_single<R>, dim3(1), dim3(64), 0, s, dst, R(amp[0]), R(amp[1]),
                      R(amp[2]), R(amp[3]));
@@ -328,6 +366,8 @@ hipError_t launch_gather_mul(const R* a, const uint64_t* idx, uint64_t m, Perm64
   template hipError_t launch_compose<R>(R*, const R*, int, const R*, int, hipStream_t);     \
   template hipError_t launch_bloch<R>(const R*, int, int, double*, double*, hipStream_t);   \
   template hipError_t launch_store_single<R>(R*, const double*, hipStream_t);               \
+  template hipError_t launch_fact_1q_batch<R>(const Fact1qItem<R>*, int, const Fact1qGate<R>*, int, \
+                                              hipStream_t);                                 \
   template hipError_t launch_bloch_multi<R>(const R*, int, const int*, int, double*, double*, \
                                             hipStream_t);                                   \
   template hipError_t launch_decompose<R>(R*, const R*, int, int, const double*, double,    \

@@ -102,6 +102,24 @@ hipError_t launch_bloch(const R* a, int nq, int t, double* scratch, double* out,
 template <typename R>
 hipError_t launch_bloch_multi(const R* a, int nq, const int* bits, int G, double* scratch,
                               double* out, hipStream_t s);
+// One-qubit gates on many small subsystems in one launch: workgroup i applies
+// the gates gates[items[i].g0 .. + ng) in order to subsystem items[i], held in
+// LDS meanwhile. Every item has 1 <= nq <= max_nq <= kFact1qMaxQubits. Both
+// tables may live in mapped host memory.
+constexpr int kFact1qMaxQubits = 12;
+template <typename R>
+struct Fact1qItem {
+  R* amps;
+  int nq, g0, ng, pad;
+};
+template <typename R>
+struct Fact1qGate {
+  R m[8];  // 2x2 matrix, row-major, interleaved
+  int t, pad;
+};
+template <typename R>
+hipError_t launch_fact_1q_batch(const Fact1qItem<R>* items, int nitems, const Fact1qGate<R>* gates,
+                                int max_nq, hipStream_t s);
 // A one-qubit subsystem: the two amplitudes amp = {Re a0, Im a0, Re a1, Im a1}.
 template <typename R>
 hipError_t launch_store_single(R* dst, const double amp[4], hipStream_t s);

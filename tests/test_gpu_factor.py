@@ -221,3 +221,45 @@ def test_multi_qubit_sweeps_keep_the_decisions(qs_lib, dtype):
         assert max(abs(x[2] - y[2]) for x, y in zip(a, b)) <= tol
     for fa, fb in zip(fs[:2], fs[2:]):
         assert abs(fa - fb) <= 1e-9 * max(1.0, fa) + tol
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_batched_one_qubit_runs(qs_lib, dtype):
+    """Runs of one-qubit gates in one launch over the small subsystems (held in
+    LDS) and per-gate launches on the large ones: the ket of a state with a
+    13-qubit subsystem and three one-qubit ones after a run of 2000 one-qubit
+    gates (more than one table slot holds, so items continue in a second
+    launch) matches the dense oracle; decisions of SDRP runs, whose many short
+    runs cycle through every table slot, are those of one launch per gate."""
+    qs = qs_lib
+    n = 16
+    g = np.random.default_rng(21)
+    gates = [("h", 0)] + [("cx", q, q + 1) for q in range(12)]
+    for _ in range(2000):
+        gates.append(("u3", int(g.integers(0, n)), *g.uniform(0, 2 * math.pi, 3)))
+    saved = qs.tune_get("factor.batch_1q")
+    try:
+        qs.tune_set("factor.batch_1q", 1)
+        st = gpu_run(qs, n, gates, 0.0, dtype)
+        assert sorted(len(s) for s in st.subsystems()) == [1, 1, 1, 13]
+        want = dense.run_circuit(dense.zero_state(n), n, gates)
+        assert_parity(st.amplitudes(), want, dtype, "2000 one-qubit gates")
+        st.free()
+        logs, amps = [], []
+        for batch in (0, 1):
+            qs.tune_set("factor.batch_1q", batch)
+            for gl, p in ((workloads.grid_circuit(4, 4, 8, 3), 0.3),
+                          (workloads.random_circuit(n, 8, 12), 0.2)):
+                st = gpu_run(qs, n, gl, p, dtype)
+                logs.append(st.attempts())
+                amps.append(st.amplitudes())
+                st.free()
+    finally:
+        qs.tune_set("factor.batch_1q", saved)
+    tol = 1e-9 if dtype == C128 else 2e-5
+    for a, b in zip(logs[:2], logs[2:]):
+        assert len(a) == len(b) and len(a) > 20
+        assert [(x[0], x[1], x[3]) for x in a] == [(x[0], x[1], x[3]) for x in b]
+        assert max(abs(x[2] - y[2]) for x, y in zip(a, b)) <= tol
+    for x, y in zip(amps[:2], amps[2:]):
+        assert np.abs(x - y).max() <= (1e-12 if dtype == C128 else 1e-5)
