@@ -418,6 +418,14 @@ int qs_check(qs_state* st, double tol);
  *                    measures the lowest dirty qubit together with the next
  *                    dirty qubits of its subsystem (up to 5, none skipped) in
  *                    one sweep; 0: one sweep per qubit. Same decisions;
+ *   "factor.defer"   1 (default): in qs_run on a factorized state with the
+ *                    plain schedule after every multi-qubit gate (no
+ *                    proposer, no feature log), the tests due after a gate
+ *                    wait until a later gate touches that subsystem or the
+ *                    run ends; pending tests of many subsystems share one
+ *                    launch and one synchronization. Decisions, the attempt
+ *                    log order and F are those of testing at once; 0: test
+ *                    right after every gate;
  *   "factor.batch_1q" 1 (default): qs_run on a factorized state applies each
  *                    run of consecutive one-qubit gates in one launch over
  *                    the subsystems of at most 2^12 amplitudes (one

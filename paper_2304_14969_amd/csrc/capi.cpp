@@ -306,6 +306,9 @@ int qs_tune_set(const char* key, int64_t value) {
   } else if (!std::strcmp(key, "tile.mfma")) {
     if (value < 0 || value > 1) return fail(QS_E_INVAL, "tile.mfma must be 0 or 1");
     g_tile_mfma = int(value);
+  } else if (!std::strcmp(key, "factor.defer")) {
+    if (value < 0 || value > 1) return fail(QS_E_INVAL, "factor.defer must be 0 or 1");
+    qs::g_defer_sep = int(value);
   } else if (!std::strcmp(key, "factor.batch_1q")) {
     if (value < 0 || value > 1) return fail(QS_E_INVAL, "factor.batch_1q must be 0 or 1");
     qs::g_batch_1q = int(value);
@@ -328,6 +331,7 @@ int qs_tune_get(const char* key, int64_t* value) {
   else if (!std::strcmp(key, "qft.round_bits")) *value = g_qft_tune.round_bits;
   else if (!std::strcmp(key, "factor.multi_test")) *value = qs::g_multi_test;
   else if (!std::strcmp(key, "factor.batch_1q")) *value = qs::g_batch_1q;
+  else if (!std::strcmp(key, "factor.defer")) *value = qs::g_defer_sep;
   else if (!std::strcmp(key, "tile.mfma")) *value = g_tile_mfma;
   else if (!std::strcmp(key, "qft.col_max")) *value = g_qft_tune.col_max;
   else if (!std::strcmp(key, "qft.col_rows")) *value = g_qft_tune.col_rows;
@@ -396,7 +400,8 @@ int qs_alloc_factorized(int n, int dtype, uint64_t max_amps, qs_state** out) {
   double* hstat = nullptr;
   double* dstat = nullptr;
   if (!st->mat || !st->red ||
-      hipHostMalloc(reinterpret_cast<void**>(&hstat), 64 * sizeof(double), hipHostMallocMapped) !=
+      hipHostMalloc(reinterpret_cast<void**>(&hstat),
+                    qs::FactorState::kStatDoubles * sizeof(double), hipHostMallocMapped) !=
           hipSuccess ||
       hipHostGetDevicePointer(reinterpret_cast<void**>(&dstat), hstat, 0) != hipSuccess) {
     if (hstat) (void)hipHostFree(hstat);
@@ -829,39 +834,45 @@ int qs_run(qs_state* st, qs_circuit* c) {
   if (c->n != st->n) return fail(QS_E_INVAL, "circuit has %d qubits, state %d", c->n, st->n);
   if (st->fact) {
     // approximate mode: gate by gate, so that the separation policy runs after
-    // every multi-qubit gate; positions are the labels at the start
-    // runs of one-qubit gates go together (one launch over the small
-    // subsystems); a one-qubit gate never changes any qubit's eps
+    // every multi-qubit gate; positions are the labels at the start. Runs of
+    // one-qubit gates go together (one launch over the small subsystems; a
+    // one-qubit gate never changes any qubit's eps), and with the plain
+    // schedule the tests wait until a gate touches their subsystem, so that
+    // the tests pending on many subsystems share one launch.
+    qs::FactorState* f = st->fact;
     std::vector<double> m;
     std::vector<int> q1;
     std::vector<double> m1;
-    auto flush = [&]() -> int {
+    auto flush_1q = [&]() -> int {
       if (q1.empty()) return QS_OK;
-      const int rc = fact_rc(st, qs::fact_apply_1q_run(st->fact, q1.data(), m1.data(),
-                                                       int(q1.size())));
+      const int rc = qs::fact_apply_1q_run(f, q1.data(), m1.data(), int(q1.size()));
       q1.clear();
       m1.clear();
       return rc;
     };
-    for (const auto& g : c->gates) {
-      if (g.k == 1) {
-        q1.push_back(g.q[0]);
-        for (int e = 0; e < 4; ++e) {
-          m1.push_back(g.m[e].real());
-          m1.push_back(g.m[e].imag());
+    auto apply_all = [&]() -> int {
+      for (const auto& g : c->gates) {
+        if (g.k == 1) {
+          q1.push_back(g.q[0]);
+          for (int e = 0; e < 4; ++e) {
+            m1.push_back(g.m[e].real());
+            m1.push_back(g.m[e].imag());
+          }
+          continue;
         }
-        continue;
+        if (int rc = flush_1q()) return rc;
+        m.resize(2 * g.m.size());
+        for (size_t i = 0; i < g.m.size(); ++i) {
+          m[2 * i] = g.m[i].real();
+          m[2 * i + 1] = g.m[i].imag();
+        }
+        if (int rc = qs::fact_apply(f, g.q, g.k, m.data())) return rc;
       }
-      if (int rc = flush()) return rc;
-      m.resize(2 * g.m.size());
-      for (size_t i = 0; i < g.m.size(); ++i) {
-        m[2 * i] = g.m[i].real();
-        m[2 * i + 1] = g.m[i].imag();
-      }
-      if (int rc = fact_rc(st, qs::fact_apply(st->fact, g.q, g.k, m.data()))) return rc;
-    }
-    if (int rc = flush()) return rc;
-    return qs::fact_relabel(st->fact, c->pos.data());
+      return flush_1q();
+    };
+    qs::fact_begin_run(f);
+    if (int rc = fact_rc(st, qs::fact_end_run(f, apply_all()))) return rc;
+    return fact_rc(st, qs::fact_relabel(f, c->pos.data()));
   }
   if (c->tiles && !c->gates.empty() &&
       st->n >= qs::tile_low_bits(st->dtype) + qs::kTileRowBits) {

@@ -33,6 +33,7 @@ namespace qs {
 
 int g_multi_test = 1;
 int g_batch_1q = 1;
+int g_defer_sep = 1;
 
 void* device_alloc(size_t bytes);
 void device_free(void* p);
@@ -59,6 +60,13 @@ int dev_err(hipError_t e, const char* what) {
 size_t amp_bytes(const FactorState* f) { return f->dtype == QS_C64 ? 8 : 16; }
 
 constexpr int kMultiTest = 5;  // qubits per multi-qubit Bloch sweep
+
+int flush_pending(FactorState* f);
+int ring_slot(FactorState* f, void** host, void** dev);
+int launch_queue(FactorState* f);
+
+// Does any of the k qubits lie in a subsystem with dirty qubits?
+bool touches_dirty(const FactorState* f, const int* qubits, int k);
 
 // Upload a small host vector of complex doubles as the state's precision.
 hipError_t upload(const FactorState* f, void* dst, const double* re_im, size_t count) {
@@ -95,6 +103,10 @@ void* sub_alloc(FactorState* f, int nq) {
 
 void sub_free(FactorState* f, int nq, void* p) {
   if (!p) return;
+  if (!f->qops.empty()) {  // a queued operation may still read it
+    f->late_free.push_back({nq, p});
+    return;
+  }
   if (nq <= FactorState::kPoolQubits) {
     f->pool[nq].push_back(p);
     return;
@@ -164,6 +176,19 @@ int merge(FactorState* f, int ia, int ib, int* out) {
   return QS_OK;
 }
 
+// The outcome of one test: bookkeeping for the proposal features, then the
+// log entry and the fidelity factor (Eq. fid_model), held back while deferred
+// tests run so that they follow the order of the gates.
+void record(FactorState* f, int q, int nsub, double eps, bool rounded) {
+  note_test_impl(f, q, eps, rounded);
+  if (f->flushing) {
+    f->pend.push_back({f->cur_phase, q, nsub, eps, rounded});
+    return;
+  }
+  if (rounded) f->F *= (1.0 - eps);
+  log_attempt(f, q, nsub, eps, rounded);
+}
+
 // The decision on qubit q at bit t of subsystem si from its Bloch sums
 // st = {Re s, Im s, z0, z1} (Sec. III-A, Eq. sdrp); *rounded on success.
 int decide_qubit(FactorState* f, int q, int si, int t, const double st[4], double p,
@@ -177,8 +202,7 @@ int decide_qubit(FactorState* f, int q, int si, int t, const double st[4], doubl
   const double rn = std::sqrt(rx * rx + ry * ry + rz * rz);
   const double eps = std::min(std::max((1.0 - rn) / 2.0, 0.0), 0.5);
   if (!(eps <= p / 2.0 + f->tau)) {
-    log_attempt(f, q, S.nq, eps, false);
-    note_test_impl(f, q, eps, false);
+    record(f, q, S.nq, eps, false);
     return QS_OK;
   }
   // dominant eigenvector phi of rho_q, phi_0 real >= 0 (steps 3-4)
@@ -198,16 +222,35 @@ int decide_qubit(FactorState* f, int q, int si, int t, const double st[4], doubl
   void* rest = sub_alloc(f, S.nq - 1);
   if (!rest) return ffail(QS_E_NOMEM, "allocating a %d-qubit subsystem", S.nq - 1);
   Sub single;
-  if (int rc = new_single(f, q, phi, &single)) {
+  if (f->defer) {  // queued: the projection and the new subsystem in one operation
+    single.nq = 1;
+    single.q[0] = q;
+    single.amps = sub_alloc(f, 1);
+    if (!single.amps) {
+      sub_free(f, S.nq - 1, rest);
+      return ffail(QS_E_NOMEM, "allocating a one-qubit subsystem");
+    }
+    FactorState::QOp op;
+    op.kind = 1;
+    op.a = S.amps;
+    op.c = rest;
+    op.single = single.amps;
+    op.na = S.nq;
+    op.t0 = t;
+    for (int i = 0; i < 4; ++i) op.phi[i] = phi[i];
+    op.scale = scale;
+    f->qops.push_back(op);
+  } else if (int rc = new_single(f, q, phi, &single)) {
     sub_free(f, S.nq - 1, rest);
     return rc;
   }
-  const hipError_t e =
-      f->dtype == QS_C64
-          ? launch_decompose(static_cast<float*>(rest), static_cast<const float*>(S.amps), S.nq, t,
-                             phi, scale, f->stream)
-          : launch_decompose(static_cast<double*>(rest), static_cast<const double*>(S.amps), S.nq,
-                             t, phi, scale, f->stream);
+  hipError_t e = hipSuccess;
+  if (!f->defer)
+    e = f->dtype == QS_C64
+            ? launch_decompose(static_cast<float*>(rest), static_cast<const float*>(S.amps), S.nq,
+                               t, phi, scale, f->stream)
+            : launch_decompose(static_cast<double*>(rest), static_cast<const double*>(S.amps),
+                               S.nq, t, phi, scale, f->stream);
   if (e != hipSuccess) {
     sub_free(f, S.nq - 1, rest);
     sub_free(f, 1, single.amps);
@@ -220,9 +263,7 @@ int decide_qubit(FactorState* f, int q, int si, int t, const double st[4], doubl
   S.nq -= 1;
   for (int b = 0; b < S.nq; ++b) f->dirty |= uint64_t(1) << S.q[b];
   f->subs.push_back(single);
-  f->F *= (1.0 - eps);
-  log_attempt(f, q, nsub, eps, true);
-  note_test_impl(f, q, eps, true);
+  record(f, q, nsub, eps, true);
   *rounded = true;
   return QS_OK;
 }
@@ -464,6 +505,10 @@ int fact_init(FactorState* f) {
 
 void fact_release(FactorState* f) {
   (void)hipStreamSynchronize(f->stream);
+  f->qops.clear();  // only left behind by a device error
+  std::vector<std::pair<int, void*>> late;
+  late.swap(f->late_free);
+  for (const auto& b : late) sub_free(f, b.first, b.second);
   for (auto& s : f->subs) sub_free(f, s.nq, s.amps);
   f->subs.clear();
 }
@@ -510,7 +555,68 @@ int fact_largest(const FactorState* f) {
   return m;
 }
 
+namespace {
+
+// Deferred mode, a two-qubit gate: the merge (when the qubits lie in two
+// subsystems) and the gate become one queued operation; the subsystem table
+// changes at once, as merge() changes it. The capacity was checked.
+int queue_gate2(FactorState* f, const int* qubits, const double* m) {
+  ++f->gate_count;
+  const int si = find(f, qubits[0], nullptr), sj = find(f, qubits[1], nullptr);
+  for (int j = 0; j < 2; ++j) {
+    f->gates_since[qubits[j]] += 1;
+    f->partner[qubits[j]] = qubits[1 - j];
+    f->merged_last[qubits[j]] = si != sj ? 1 : 0;
+  }
+  FactorState::QOp op;
+  for (int i = 0; i < 32; ++i) op.m[i] = m[i];
+  int target = si;
+  if (si != sj) {
+    const Sub A = f->subs[si], B = f->subs[sj];
+    const int nq = A.nq + B.nq;
+    void* c = sub_alloc(f, nq);
+    if (!c) return ffail(QS_E_NOMEM, "allocating a %d-qubit subsystem", nq);
+    Sub M;
+    M.nq = nq;
+    for (int t = 0; t < A.nq; ++t) M.q[t] = A.q[t];
+    for (int t = 0; t < B.nq; ++t) M.q[A.nq + t] = B.q[t];
+    M.amps = c;
+    op.a = A.amps;
+    op.b = B.amps;
+    op.c = c;
+    op.na = A.nq;
+    op.nb = B.nq;
+    f->qops.push_back(op);  // queued first, so that the frees below wait for it
+    sub_free(f, A.nq, A.amps);
+    sub_free(f, B.nq, B.amps);
+    const int lo = std::min(si, sj), hi = std::max(si, sj);
+    f->subs.erase(f->subs.begin() + hi);
+    f->subs.erase(f->subs.begin() + lo);
+    f->subs.push_back(M);
+    target = int(f->subs.size()) - 1;
+  } else {
+    const Sub& S = f->subs[si];
+    op.a = op.c = S.amps;
+    op.na = S.nq;
+    f->qops.push_back(op);
+  }
+  Sub& S = f->subs[target];
+  FactorState::QOp& q = f->qops.back();
+  for (int b = 0; b < S.nq; ++b) {
+    if (S.q[b] == qubits[0]) q.t0 = b;
+    if (S.q[b] == qubits[1]) q.t1 = b;
+  }
+  for (int j = 0; j < 2; ++j) f->dirty |= uint64_t(1) << qubits[j];
+  S.phase = ++f->phase_next;
+  return QS_OK;
+}
+
+}  // namespace
+
 int fact_apply(FactorState* f, const int* qubits, int k, const double* m) {
+  // deferred tests on the subsystems this gate touches come first
+  if (f->defer && f->dirty && touches_dirty(f, qubits, k))
+    if (int rc = flush_pending(f)) return rc;
   // capacity first, so that a refused gate leaves the state as it was
   int distinct[QS_MAX_FUSED], nd = 0, total = 0;
   for (int j = 0; j < k; ++j) {
@@ -567,6 +673,8 @@ int fact_apply(FactorState* f, const int* qubits, int k, const double* m) {
   if (total >= 63 || (uint64_t(1) << total) > f->max_amps)
     return ffail(QS_E_CAPACITY, "gate needs a %d-qubit subsystem (cap %llu amplitudes)", total,
                  (unsigned long long)f->max_amps);
+  if (f->defer && k == 2) return queue_gate2(f, qubits, m);
+  if (int rc = launch_queue(f)) return rc;
   // bookkeeping for the proposal features
   if (k >= 2) {
     ++f->gate_count;
@@ -616,6 +724,10 @@ int fact_apply(FactorState* f, const int* qubits, int k, const double* m) {
   if (int rc = dev_err(e, "factorized gate")) return rc;
   if (k >= 2) {
     for (int j = 0; j < k; ++j) f->dirty |= uint64_t(1) << qubits[j];
+    if (f->policy == QS_SEP_AFTER_2Q && f->defer) {
+      S.phase = ++f->phase_next;
+      return QS_OK;
+    }
     if (f->policy == QS_SEP_AFTER_2Q) {
       int nsep = 0;
       return fact_try_separate(f, f->p, &nsep);
@@ -642,6 +754,207 @@ int ring_slot(FactorState* f, void** host, void** dev) {
   *host = f->ring_host[i];
   *dev = f->ring_dev[i];
   return i;
+}
+
+bool touches_dirty(const FactorState* f, const int* qubits, int k) {
+  for (int j = 0; j < k; ++j) {
+    const int si = find(f, qubits[j], nullptr);
+    if (si < 0) continue;
+    const Sub& S = f->subs[si];
+    for (int b = 0; b < S.nq; ++b)
+      if ((f->dirty >> S.q[b]) & 1) return true;
+  }
+  return false;
+}
+
+// One round of deferred tests: for every subsystem with dirty qubits, up to
+// kMultiTest of them (the lowest, ascending). Sweeps of subsystems of at most
+// 2^kBlochBatchQubits amplitudes share one launch; larger ones keep their own
+// launches; then one synchronization. The sums are those the one-at-a-time
+// sweeps compute (same kernels' order), so the decisions are too.
+template <typename R>
+int flush_round(FactorState* f, bool* any) {
+  if (int rc = launch_queue(f)) return rc;  // the sweeps read the queued results
+  struct Item {
+    int si, G;
+    int q[kMultiTest], t[kMultiTest];  // ascending qubit number
+  };
+  std::vector<Item> items;
+  for (int si = 0; si < int(f->subs.size()); ++si) {
+    const Sub& S = f->subs[si];
+    int qd[64], td[64], nd = 0;
+    for (int b = 0; b < S.nq; ++b)
+      if ((f->dirty >> S.q[b]) & 1) {
+        qd[nd] = S.q[b];
+        td[nd++] = b;
+      }
+    if (!nd) continue;
+    if (S.nq == 1) {  // nothing to separate from
+      f->dirty &= ~(uint64_t(1) << S.q[0]);
+      f->deferred &= ~(uint64_t(1) << S.q[0]);
+      continue;
+    }
+    int ord[64];
+    for (int i = 0; i < nd; ++i) ord[i] = i;
+    std::sort(ord, ord + nd, [&](int x, int y) { return qd[x] < qd[y]; });
+    Item it{};
+    it.si = si;
+    it.G = std::min(nd, g_multi_test ? kMultiTest : 1);
+    for (int i = 0; i < it.G; ++i) {
+      it.q[i] = qd[ord[i]];
+      it.t[i] = td[ord[i]];
+    }
+    items.push_back(it);
+  }
+  *any = !items.empty();
+  if (items.empty()) return QS_OK;
+  constexpr int kRow = 4 * kMultiTest;  // stat doubles per item
+  if (int(items.size()) * kRow > FactorState::kStatDoubles)
+    return ffail(QS_E_UNSUPPORTED, "too many pending subsystems (%zu)", items.size());
+  // kernel bit order (ascending local bit) of every item
+  int bits[64][kMultiTest], pos[64][kMultiTest];
+  for (size_t i = 0; i < items.size(); ++i) {
+    const Item& it = items[i];
+    int o[kMultiTest];
+    for (int j = 0; j < it.G; ++j) o[j] = j;
+    std::sort(o, o + it.G, [&](int x, int y) { return it.t[x] < it.t[y]; });
+    for (int j = 0; j < it.G; ++j) {
+      bits[i][j] = it.t[o[j]];
+      pos[i][o[j]] = j;  // row of qubit j in the kernel's output
+    }
+  }
+  // small subsystems: one launch over a table in a pinned slot
+  void *host = nullptr, *dev = nullptr;
+  int slot = -1, nsmall = 0;
+  for (size_t i = 0; i < items.size(); ++i) {
+    const Sub& S = f->subs[items[i].si];
+    if (S.nq > kBlochBatchQubits) continue;
+    if (slot < 0) {
+      slot = ring_slot(f, &host, &dev);
+      if (slot < 0) return slot;
+    }
+    BlochItem<R>& b = static_cast<BlochItem<R>*>(host)[nsmall++];
+    b.amps = static_cast<const R*>(S.amps);
+    b.nq = S.nq;
+    b.G = items[i].G;
+    for (int j = 0; j < kMultiTest; ++j) b.bits[j] = j < b.G ? bits[i][j] : 0;
+    b.out = int(i) * kRow;
+  }
+  hipError_t e = hipSuccess;
+  if (nsmall) {
+    e = launch_bloch_batch(static_cast<const BlochItem<R>*>(dev), nsmall, f->dstat, f->stream);
+    if (e == hipSuccess) e = hipEventRecord(f->ring_ev[slot], f->stream);
+    if (e == hipSuccess) f->ring_used[slot] = true;
+  }
+  for (size_t i = 0; i < items.size() && e == hipSuccess; ++i) {
+    const Sub& S = f->subs[items[i].si];
+    if (S.nq <= kBlochBatchQubits) continue;
+    const R* a = static_cast<const R*>(S.amps);
+    e = items[i].G == 1
+            ? launch_bloch(a, S.nq, bits[i][0], f->scratch, f->dstat + i * kRow, f->stream)
+            : launch_bloch_multi(a, S.nq, bits[i], items[i].G, f->scratch, f->dstat + i * kRow,
+                                 f->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+  if (int rc = dev_err(e, "bloch")) return rc;
+  // decisions per subsystem, ascending qubit number, stopping at a rounding
+  for (size_t i = 0; i < items.size(); ++i) {
+    const Item& it = items[i];
+    f->cur_phase = f->subs[it.si].phase;
+    for (int j = 0; j < it.G; ++j) {
+      const double* st = f->hstat + i * kRow + 4 * pos[i][j];
+      const double sums[4] = {st[0], st[1], st[2], st[3]};
+      begin_test(f, it.q[j], f->p);
+      bool rounded = false;
+      if (int rc = decide_qubit(f, it.q[j], it.si, it.t[j], sums, f->p, &rounded)) return rc;
+      if (rounded) break;
+    }
+  }
+  return QS_OK;
+}
+
+template <typename R>
+int launch_queue_t(FactorState* f) {
+  constexpr size_t kPerSlot = FactorState::kSlotBytes / sizeof(FactOp<R>);
+  std::vector<const FactorState::QOp*> small, large;
+  for (const auto& op : f->qops)
+    (op.na + op.nb <= kFactOpQubits ? small : large).push_back(&op);
+  hipError_t e = hipSuccess;
+  for (size_t i = 0; i < small.size() && e == hipSuccess; i += kPerSlot) {
+    void *host = nullptr, *dev = nullptr;
+    const int slot = ring_slot(f, &host, &dev);
+    if (slot < 0) return slot;
+    const size_t cnt = std::min(kPerSlot, small.size() - i);
+    auto* ops = static_cast<FactOp<R>*>(host);
+    for (size_t j = 0; j < cnt; ++j) {
+      const FactorState::QOp& q = *small[i + j];
+      FactOp<R>& o = ops[j];
+      o.a = static_cast<const R*>(q.a);
+      o.b = static_cast<const R*>(q.b);
+      o.c = static_cast<R*>(q.c);
+      o.single = static_cast<R*>(q.single);
+      o.kind = q.kind;
+      o.na = q.na;
+      o.nb = q.nb;
+      o.t0 = q.t0;
+      o.t1 = q.t1;
+      o.pad = 0;
+      for (int k = 0; k < 4; ++k) o.phi[k] = q.phi[k];
+      o.scale = q.scale;
+      for (int k = 0; k < 32; ++k) o.m[k] = R(q.m[k]);
+    }
+    e = launch_fact_ops(static_cast<const FactOp<R>*>(dev), int(cnt), f->stream);
+    if (e == hipSuccess) e = hipEventRecord(f->ring_ev[slot], f->stream);
+    if (e == hipSuccess) f->ring_used[slot] = true;
+  }
+  for (size_t i = 0; i < large.size() && e == hipSuccess; ++i) {
+    const FactorState::QOp& q = *large[i];
+    if (q.kind == 1) {
+      e = launch_decompose(static_cast<R*>(q.c), static_cast<const R*>(q.a), q.na, q.t0, q.phi,
+                           q.scale, f->stream);
+      if (e == hipSuccess) e = launch_store_single(static_cast<R*>(q.single), q.phi, f->stream);
+      continue;
+    }
+    const int loc[2] = {q.t0, q.t1};
+    if (q.nb > 0)
+      e = launch_compose(static_cast<R*>(q.c), static_cast<const R*>(q.a), q.na,
+                         static_cast<const R*>(q.b), q.nb, f->stream);
+    if (e == hipSuccess)
+      e = launch_apply_small(static_cast<R*>(q.c), q.na + q.nb, loc, 2, q.m, f->stream);
+  }
+  return dev_err(e, "queued subsystem operations");
+}
+
+// Launches the queued operations, then returns the buffers freed meanwhile.
+int launch_queue(FactorState* f) {
+  if (f->qops.empty()) return QS_OK;
+  const int rc = f->dtype == QS_C64 ? launch_queue_t<float>(f) : launch_queue_t<double>(f);
+  f->qops.clear();
+  std::vector<std::pair<int, void*>> late;
+  late.swap(f->late_free);
+  for (const auto& b : late) sub_free(f, b.first, b.second);
+  return rc;
+}
+
+// Runs every deferred test, then logs the attempts and applies the fidelity
+// factors in the order of the gates that caused them.
+int flush_pending(FactorState* f) {
+  f->flushing = true;
+  int rc = QS_OK;
+  for (bool any = true; any && f->dirty && rc == QS_OK;)
+    rc = f->dtype == QS_C64 ? flush_round<float>(f, &any) : flush_round<double>(f, &any);
+  if (rc == QS_OK) rc = launch_queue(f);  // the last projections
+  f->flushing = false;
+  std::stable_sort(f->pend.begin(), f->pend.end(),
+                   [](const FactorState::Decision& a, const FactorState::Decision& b) {
+                     return a.phase < b.phase;
+                   });
+  for (const auto& d : f->pend) {
+    if (d.rounded) f->F *= (1.0 - d.eps);
+    log_attempt(f, d.q, d.nsub, d.eps, d.rounded);
+  }
+  f->pend.clear();
+  return rc;
 }
 
 template <typename R>
@@ -729,6 +1042,9 @@ int apply_1q_run(FactorState* f, const int* qubits, const double* m, int count) 
 }  // namespace
 
 int fact_apply_1q_run(FactorState* f, const int* qubits, const double* m, int count) {
+  if (f->defer && f->dirty && touches_dirty(f, qubits, count))
+    if (int rc = flush_pending(f)) return rc;
+  if (int rc = launch_queue(f)) return rc;
   if (!g_batch_1q || count < 2) {
     for (int i = 0; i < count; ++i)
       if (int rc = fact_apply(f, qubits + i, 1, m + 8 * i)) return rc;
@@ -738,7 +1054,30 @@ int fact_apply_1q_run(FactorState* f, const int* qubits, const double* m, int co
                             : apply_1q_run<double>(f, qubits, m, count);
 }
 
+void fact_begin_run(FactorState* f) {
+  f->defer = g_defer_sep && f->policy == QS_SEP_AFTER_2Q && !f->proposer && !f->feat_log &&
+             !f->dirty;
+}
+
+int fact_end_run(FactorState* f, int rc) {
+  int frc = QS_OK;
+  if (f->defer && rc != QS_E_DEVICE) {
+    if (f->dirty) frc = flush_pending(f);
+    if (frc == QS_OK) frc = launch_queue(f);
+  }
+  if (!f->qops.empty()) {  // a device error: nothing more runs on this state
+    f->qops.clear();
+    std::vector<std::pair<int, void*>> late;
+    late.swap(f->late_free);
+    for (const auto& b : late) sub_free(f, b.first, b.second);
+  }
+  f->defer = false;
+  return rc != QS_OK ? rc : frc;
+}
+
 int fact_swap(FactorState* f, int a, int b) {
+  if (f->defer && f->dirty)
+    if (int rc = flush_pending(f)) return rc;
   for (auto& s : f->subs)
     for (int t = 0; t < s.nq; ++t) {
       if (s.q[t] == a) s.q[t] = b;
@@ -761,6 +1100,8 @@ int fact_swap(FactorState* f, int a, int b) {
 }
 
 int fact_relabel(FactorState* f, const int* pos) {
+  if (f->defer && f->dirty)
+    if (int rc = flush_pending(f)) return rc;
   int inv[64];
   for (int q = 0; q < f->n; ++q) inv[pos[q]] = q;
   uint64_t nd = 0, nf = 0;

@@ -15,6 +15,7 @@ struct Sub {
   int nq = 0;
   int q[64] = {0};
   void* amps = nullptr;  // 2^nq amplitudes, device, owned
+  uint64_t phase = 0;    // deferred separation: the gate its dirty qubits wait on
 };
 
 struct FactorState {
@@ -32,8 +33,42 @@ struct FactorState {
   uint64_t log_cap = 0;
   uint64_t* log_count = nullptr;
   double* scratch = nullptr;  // device reduction scratch
-  double* hstat = nullptr;    // pinned, mapped host buffer of the four Bloch sums
+  // pinned, mapped host buffer of Bloch sums: 4 per target qubit, up to 5
+  // targets for each of up to 32 subsystems (those of two qubits or more)
+  static constexpr int kStatDoubles = 32 * 4 * 5;
+  double* hstat = nullptr;
   double* dstat = nullptr;    // its device address
+  // Deferred separation (plain schedule inside qs_run): the tests due after a
+  // multi-qubit gate wait until a later gate touches that subsystem or the run
+  // ends, and the tests pending on many subsystems then share one launch and
+  // one synchronization. A subsystem's tests read only its own amplitudes, so
+  // the decisions are those of testing at once; the attempts are logged, and
+  // F updated, in the order of the gates that caused them.
+  struct Decision {
+    uint64_t phase;
+    int q, nsub;
+    double eps;
+    bool rounded;
+  };
+  bool defer = false;
+  bool flushing = false;
+  uint64_t phase_next = 0, cur_phase = 0;
+  std::vector<Decision> pend;
+  // While deferring, merges with their two-qubit gate and projections are
+  // queued and launched together at the next point that reads device data.
+  // No queued operation reads another's output (a gate on a subsystem whose
+  // tests are pending runs those tests first, which launches the queue), and
+  // buffers freed meanwhile return to the pool only after the launch.
+  struct QOp {
+    int kind = 0;  // 0: merge (nb > 0) or in place (nb = 0), then the gate; 1: projection
+    void *a = nullptr, *b = nullptr, *c = nullptr, *single = nullptr;
+    int na = 0, nb = 0, t0 = 0, t1 = 0;
+    double phi[4] = {0, 0, 0, 0};
+    double scale = 1.0;
+    double m[32] = {0};
+  };
+  std::vector<QOp> qops;
+  std::vector<std::pair<int, void*>> late_free;
   // mapped pinned slots for the tables of batched one-qubit gates; a slot is
   // reused only after the event recorded behind its launch has completed
   static constexpr int kRingSlots = 4;
@@ -71,6 +106,9 @@ extern int g_multi_test;
 // Process-wide: runs of consecutive one-qubit gates in one launch over the
 // small subsystems (1, default) or one launch per gate (0).
 extern int g_batch_1q;
+// Process-wide: deferred separation in qs_run (1, default) or the tests
+// right after every multi-qubit gate (0). Decisions are the same either way.
+extern int g_defer_sep;
 
 // The 32 proposal features of qubit q (threshold p) from the bookkeeping.
 void fact_features(const FactorState* f, int q, double p, float* out);
@@ -86,6 +124,13 @@ int fact_apply(FactorState* f, const int* qubits, int k, const double* m);
 // one workgroup each in a single launch that applies their gates in order;
 // larger subsystems get one launch per gate.
 int fact_apply_1q_run(FactorState* f, const int* qubits, const double* m, int count);
+// A circuit run: fact_begin_run turns deferred separation on when the plain
+// schedule runs after every multi-qubit gate (no proposer, no feature log, no
+// dirty qubit left from before); fact_end_run runs the pending tests and turns
+// it off. fact_end_run returns rc when it is an error (after the pending tests,
+// unless rc is a device error), else its own status.
+void fact_begin_run(FactorState* f);
+int fact_end_run(FactorState* f, int rc);
 int fact_swap(FactorState* f, int a, int b);       // relabel
 int fact_relabel(FactorState* f, const int* pos);  // label v -> q where pos[q] = v
 int fact_try_separate(FactorState* f, double p, int* n_separated);

@@ -39,17 +39,38 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double* sh) {
   for (int k = 0; k < N; ++k) v[k] = sh[k * kBlock];
 }
 
+// Amplitude i of a (x) b, a's qubits at the low na bits.
+template <typename R>
+__device__ __forceinline__ void compose_at(const R* __restrict__ a, int na,
+                                           const R* __restrict__ b, uint64_t i, R& re, R& im) {
+  const uint64_t ia = i & ((uint64_t(1) << na) - 1), ib = i >> na;
+  const R ar = a[2 * ia], ai = a[2 * ia + 1], br = b[2 * ib], bi = b[2 * ib + 1];
+  re = ar * br - ai * bi;
+  im = ar * bi + ai * br;
+}
+
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_compose(R* __restrict__ c, const R* __restrict__ a,
                                                     int na, const R* __restrict__ b,
                                                     uint64_t total) {
   for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < total;
-       i += uint64_t(gridDim.x) * kBlock) {
-    const uint64_t ia = i & ((uint64_t(1) << na) - 1), ib = i >> na;
-    const R ar = a[2 * ia], ai = a[2 * ia + 1], br = b[2 * ib], bi = b[2 * ib + 1];
-    c[2 * i] = ar * br - ai * bi;
-    c[2 * i + 1] = ar * bi + ai * br;
-  }
+       i += uint64_t(gridDim.x) * kBlock)
+    compose_at(a, na, b, i, c[2 * i], c[2 * i + 1]);
+}
+
+// Output u of the projection of the qubit at bit t on phi (with the kept
+// branch's scale).
+template <typename R>
+__device__ __forceinline__ void decompose_at(R* __restrict__ b, const R* __restrict__ a,
+                                             uint64_t u, int t, double p0r, double p0i,
+                                             double p1r, double p1i, double scale) {
+  const uint64_t i0 = insert_zero(u, t), i1 = i0 | (uint64_t(1) << t);
+  const double x0 = a[2 * i0], y0 = a[2 * i0 + 1], x1 = a[2 * i1], y1 = a[2 * i1 + 1];
+  // conj(phi0) a0 + conj(phi1) a1
+  const double re = p0r * x0 + p0i * y0 + p1r * x1 + p1i * y1;
+  const double im = p0r * y0 - p0i * x0 + p1r * y1 - p1i * x1;
+  b[2 * u] = static_cast<R>(re * scale);
+  b[2 * u + 1] = static_cast<R>(im * scale);
 }
 
 // partial[k * kRedBlocks + block], k = 0..3: Re s, Im s, z0, z1
@@ -103,17 +124,16 @@ struct Bits8 {
   int b[8];
 };
 
+// Adds, for every thread-owned group g = first, first + stride, ... < groups,
+// the 2^G amplitudes that differ only in the target bits (ascending in
+// `bits`): for every target j, the pairs that differ in bit j go to row 4j+k
+// of v (k = Re s, Im s, z0, z1).
 template <typename R, int G>
-__global__ void __launch_bounds__(kBlock) k_bloch_multi(const R* __restrict__ a, uint64_t groups,
-                                                        Bits8 bits, double* __restrict__ partial,
-                                                        double* __restrict__ out) {
+__device__ __forceinline__ void bloch_accumulate(const R* __restrict__ a, uint64_t groups,
+                                                 const Bits8& bits, uint64_t first,
+                                                 uint64_t stride, double (&v)[4 * G]) {
   constexpr int D = 1 << G;
-  __shared__ double sh[4 * G * kBlock];
-  double v[4 * G];
-#pragma unroll
-  for (int k = 0; k < 4 * G; ++k) v[k] = 0.0;
-  const uint64_t stride = uint64_t(gridDim.x) * kBlock;
-  for (uint64_t g = uint64_t(blockIdx.x) * kBlock + threadIdx.x; g < groups; g += stride) {
+  for (uint64_t g = first; g < groups; g += stride) {
     uint64_t base = g;
 #pragma unroll
     for (int j = 0; j < G; ++j) base = insert_zero(base, bits.b[j]);
@@ -139,6 +159,18 @@ __global__ void __launch_bounds__(kBlock) k_bloch_multi(const R* __restrict__ a,
         v[4 * j + 3] += x1 * x1 + y1 * y1;
       }
   }
+}
+
+template <typename R, int G>
+__global__ void __launch_bounds__(kBlock) k_bloch_multi(const R* __restrict__ a, uint64_t groups,
+                                                        Bits8 bits, double* __restrict__ partial,
+                                                        double* __restrict__ out) {
+  __shared__ double sh[4 * G * kBlock];
+  double v[4 * G];
+#pragma unroll
+  for (int k = 0; k < 4 * G; ++k) v[k] = 0.0;
+  bloch_accumulate<R, G>(a, groups, bits, uint64_t(blockIdx.x) * kBlock + threadIdx.x,
+                         uint64_t(gridDim.x) * kBlock, v);
   block_sum<4 * G>(v, sh);
   if (threadIdx.x == 0) {
     if (gridDim.x == 1) {
@@ -146,6 +178,38 @@ __global__ void __launch_bounds__(kBlock) k_bloch_multi(const R* __restrict__ a,
     } else {
       for (int k = 0; k < 4 * G; ++k) partial[k * gridDim.x + blockIdx.x] = v[k];
     }
+  }
+}
+
+// One workgroup per item (a subsystem of at most 2^15 amplitudes and its G
+// target bits): the sums of a one-workgroup k_bloch_multi (k_bloch_small for
+// G = 1, the same order), written to out[item.out + 4j + k].
+template <typename R, int G>
+__device__ __forceinline__ void bloch_item(const BlochItem<R>& it, double* sh,
+                                           double* __restrict__ out) {
+  Bits8 bits{};
+#pragma unroll
+  for (int j = 0; j < G; ++j) bits.b[j] = it.bits[j];
+  double v[4 * G];
+#pragma unroll
+  for (int k = 0; k < 4 * G; ++k) v[k] = 0.0;
+  bloch_accumulate<R, G>(it.amps, uint64_t(1) << (it.nq - G), bits, threadIdx.x, kBlock, v);
+  block_sum<4 * G>(v, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4 * G; ++k) out[it.out + k] = v[k];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_bloch_batch(const BlochItem<R>* __restrict__ items,
+                                                        double* __restrict__ out) {
+  __shared__ double sh[4 * kMaxMulti * kBlock];
+  const BlochItem<R> it = items[blockIdx.x];
+  switch (it.G) {
+    case 1: bloch_item<R, 1>(it, sh, out); break;
+    case 2: bloch_item<R, 2>(it, sh, out); break;
+    case 3: bloch_item<R, 3>(it, sh, out); break;
+    case 4: bloch_item<R, 4>(it, sh, out); break;
+    default: bloch_item<R, 5>(it, sh, out); break;
   }
 }
 
@@ -207,14 +271,58 @@ __global__ void __launch_bounds__(kBlock) k_decompose(R* __restrict__ b, const R
                                                       uint64_t count, int t, double p0r, double p0i,
                                                       double p1r, double p1i, double scale) {
   for (uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x; u < count;
-       u += uint64_t(gridDim.x) * kBlock) {
-    const uint64_t i0 = insert_zero(u, t), i1 = i0 | (uint64_t(1) << t);
-    const double x0 = a[2 * i0], y0 = a[2 * i0 + 1], x1 = a[2 * i1], y1 = a[2 * i1 + 1];
-    // conj(phi0) a0 + conj(phi1) a1
-    const double re = p0r * x0 + p0i * y0 + p1r * x1 + p1i * y1;
-    const double im = p0r * y0 - p0i * x0 + p1r * y1 - p1i * x1;
-    b[2 * u] = static_cast<R>(re * scale);
-    b[2 * u + 1] = static_cast<R>(im * scale);
+       u += uint64_t(gridDim.x) * kBlock)
+    decompose_at(b, a, u, t, p0r, p0i, p1r, p1i, scale);
+}
+
+// One workgroup per operation (see FactOp). The merge-and-gate form computes
+// the composed amplitudes as k_compose does and the 4x4 product as the
+// two-qubit argument-matrix kernel does, in the same order.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_fact_ops(const FactOp<R>* __restrict__ ops) {
+  const FactOp<R> op = ops[blockIdx.x];  // the table may be in host memory: read it once
+  if (op.kind == 1) {
+    const uint64_t count = uint64_t(1) << (op.na - 1);
+    for (uint64_t u = threadIdx.x; u < count; u += kBlock)
+      decompose_at(op.c, op.a, u, op.t0, op.phi[0], op.phi[1], op.phi[2], op.phi[3], op.scale);
+    if (threadIdx.x == 0) {
+      op.single[0] = static_cast<R>(op.phi[0]);
+      op.single[1] = static_cast<R>(op.phi[1]);
+      op.single[2] = static_cast<R>(op.phi[2]);
+      op.single[3] = static_cast<R>(op.phi[3]);
+    }
+    return;
+  }
+  const int n = op.na + op.nb;
+  const int lo = min(op.t0, op.t1), hi = max(op.t0, op.t1);
+  const uint64_t groups = uint64_t(1) << (n - 2);
+  const R* m = op.m;
+  for (uint64_t g = threadIdx.x; g < groups; g += kBlock) {
+    const uint64_t base = insert_zero(insert_zero(g, lo), hi);
+    uint64_t off[4];
+    R vr[4], vi[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      off[c] = base | (uint64_t(c & 1) << op.t0) | (uint64_t(c >> 1) << op.t1);
+      if (op.nb > 0) {
+        compose_at(op.a, op.na, op.b, off[c], vr[c], vi[c]);
+      } else {
+        vr[c] = op.a[2 * off[c]];
+        vi[c] = op.a[2 * off[c] + 1];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      R yr = 0, yi = 0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const R mr = m[2 * (r * 4 + c)], mi = m[2 * (r * 4 + c) + 1];
+        yr += mr * vr[c] - mi * vi[c];
+        yi += mr * vi[c] + mi * vr[c];
+      }
+      op.c[2 * off[r]] = yr;
+      op.c[2 * off[r] + 1] = yi;
+    }
   }
 }
 
@@ -332,6 +440,20 @@ hipError_t launch_fact_1q_batch(const Fact1qItem<R>* items, int nitems, const Fa
 }
 
 template <typename R>
+hipError_t launch_fact_ops(const FactOp<R>* ops, int nops, hipStream_t s) {
+  if (nops < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_fact_ops<R>, dim3(nops), dim3(kBlock), 0, s, ops);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_bloch_batch(const BlochItem<R>* items, int nitems, double* out, hipStream_t s) {
+  if (nitems < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_bloch_batch<R>, dim3(nitems), dim3(kBlock), 0, s, items, out);
+  return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_store_single(R* dst, const double amp[4], hipStream_t s) {
   hipLaunchKernelGGL(k_store_single<R>, dim3(1), dim3(64), 0, s, dst, R(amp[0]), R(amp[1]),
                      R(amp[2]), R(amp[3]));
@@ -366,6 +488,8 @@ hipError_t launch_gather_mul(const R* a, const uint64_t* idx, uint64_t m, Perm64
   template hipError_t launch_compose<R>(R*, const R*, int, const R*, int, hipStream_t);     \
   template hipError_t launch_bloch<R>(const R*, int, int, double*, double*, hipStream_t);   \
   template hipError_t launch_store_single<R>(R*, const double*, hipStream_t);               \
+  template hipError_t launch_bloch_batch<R>(const BlochItem<R>*, int, double*, hipStream_t); \
+  template hipError_t launch_fact_ops<R>(const FactOp<R>*, int, hipStream_t);               \
   template hipError_t launch_fact_1q_batch<R>(const Fact1qItem<R>*, int, const Fact1qGate<R>*, int, \
                                               hipStream_t);                                 \
   template hipError_t launch_bloch_multi<R>(const R*, int, const int*, int, double*, double*, \

@@ -102,6 +102,46 @@ hipError_t launch_bloch(const R* a, int nq, int t, double* scratch, double* out,
 template <typename R>
 hipError_t launch_bloch_multi(const R* a, int nq, const int* bits, int G, double* scratch,
                               double* out, hipStream_t s);
+// The Bloch sums of several subsystems in one launch, one workgroup each:
+// item i reads 2^nq amplitudes (nq <= kBlochBatchQubits) and writes, for each
+// of its G (1..5) target bits (ascending, distinct, < nq), the four sums
+// Re s, Im s, z0, z1 to out[item.out + 4j ..]. The item table may live in
+// mapped host memory.
+constexpr int kBlochBatchQubits = 15;
+template <typename R>
+struct BlochItem {
+  const R* amps;
+  int nq, G;
+  int bits[5];
+  int out;
+};
+template <typename R>
+hipError_t launch_bloch_batch(const BlochItem<R>* items, int nitems, double* out, hipStream_t s);
+// Independent operations on many small subsystems in one launch, one
+// workgroup each (the large ones go through the single-operation launchers,
+// whose arithmetic these repeat term for term):
+//   kind 0, nb > 0: c = a (x) b (a's qubits at the low na bits), then the 4x4
+//                   matrix m on local bits t0 (row bit 0) and t1 (row bit 1)
+//   kind 0, nb = 0: the matrix on a in place (c == a)
+//   kind 1:         c[u] = (conj(phi0) a[i0(u)] + conj(phi1) a[i1(u)]) scale,
+//                   i0/i1 = u with 0/1 inserted at bit t0 (na qubits in a),
+//                   and single = phi (the new one-qubit subsystem)
+// Every operation reads and writes at most 2^kFactOpQubits amplitudes; no
+// operation of a launch reads what another one writes.
+constexpr int kFactOpQubits = 15;
+template <typename R>
+struct FactOp {
+  const R* a;
+  const R* b;
+  R* c;
+  R* single;
+  int kind, na, nb, t0, t1, pad;
+  double phi[4];
+  double scale;
+  R m[32];  // 4x4, row-major, interleaved
+};
+template <typename R>
+hipError_t launch_fact_ops(const FactOp<R>* ops, int nops, hipStream_t s);
 // One-qubit gates on many small subsystems in one launch: workgroup i applies
 // the gates gates[items[i].g0 .. + ng) in order to subsystem items[i], held in
 // LDS meanwhile. Every item has 1 <= nq <= max_nq <= kFact1qMaxQubits. Both

@@ -263,3 +263,64 @@ def test_batched_one_qubit_runs(qs_lib, dtype):
         assert max(abs(x[2] - y[2]) for x, y in zip(a, b)) <= tol
     for x, y in zip(amps[:2], amps[2:]):
         assert np.abs(x - y).max() <= (1e-12 if dtype == C128 else 1e-5)
+
+
+def _run_mode(qs, n, gates, p, dtype, defer, max_amps=2 ** 30, dirty=0):
+    saved = qs.tune_get("factor.defer")
+    qs.tune_set("factor.defer", defer)
+    try:
+        st = qs.State(n, dtype, factorized=True, max_amps=max_amps)
+        st.set_policy(qs.SEP_AFTER_2Q, p)
+        st.record_attempts()
+        if dirty:
+            st.mark_dirty(dirty)
+        err = None
+        try:
+            st.run(qs.Circuit(n).add_gates(gates))
+        except qs.CapacityError as e:
+            err = e
+        out = (st.attempts(), st.fidelity_estimate(), sorted(sorted(s) for s in st.subsystems()),
+               st.amplitudes(), err is not None)
+        st.free()
+        return out
+    finally:
+        qs.tune_set("factor.defer", saved)
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_deferred_tests_keep_the_sequence(qs_lib, dtype):
+    """Tests that wait until a gate touches their subsystem (and then share one
+    launch with the tests pending elsewhere) give the attempt log of testing
+    right after every gate: same qubits, sizes, eps (the same sums) and
+    decisions in the same order, the same F and the same subsystems."""
+    qs = qs_lib
+    n = 16
+    cases = [(workloads.grid_circuit(4, 4, 8, 3), 0.3), (workloads.random_circuit(n, 8, 12), 0.2),
+             (workloads.random_circuit(n, 6, 5), 0.05)]
+    for gates, p in cases:
+        a = _run_mode(qs, n, gates, p, dtype, 0)
+        b = _run_mode(qs, n, gates, p, dtype, 1)
+        assert len(a[0]) > 20 and a[0] == b[0]
+        assert a[1] == b[1] and a[2] == b[2]
+        assert np.abs(a[3] - b[3]).max() <= (1e-12 if dtype == C128 else 1e-6)
+        ost = replay(n, gates, p, b[0], eps_tol=2e-5 if dtype == C64 else 1e-10)
+        assert abs(b[1] - ost.F) <= 1e-5 * max(ost.F, 1e-3) + 1e-7
+
+
+def test_deferred_tests_capacity_and_leftover_dirty(qs_lib):
+    """A merge refused for capacity in the middle of a run, and a run that
+    starts with dirty qubits left from before (which turns deferral off for
+    that run): the same log, F and subsystems as testing at once."""
+    qs = qs_lib
+    n = 12
+    gates = workloads.random_circuit(n, 8, 31)
+    a = _run_mode(qs, n, gates, 0.02, C64, 0, max_amps=2 ** 6)
+    b = _run_mode(qs, n, gates, 0.02, C64, 1, max_amps=2 ** 6)
+    assert a[4] and b[4], "the cap should be reached"
+    assert a[0] == b[0] and a[1] == b[1] and a[2] == b[2]
+    assert np.abs(a[3] - b[3]).max() <= 1e-6
+    pre = [("h", q) for q in range(n)] + [("cz", 0, 1), ("cz", 2, 3)]
+    for defer in (0, 1):
+        a = _run_mode(qs, n, pre + gates, 0.3, C64, 0, dirty=(1 << n) - 1)
+        b = _run_mode(qs, n, pre + gates, 0.3, C64, defer, dirty=(1 << n) - 1)
+        assert a[0] == b[0] and a[1] == b[1] and a[2] == b[2]
