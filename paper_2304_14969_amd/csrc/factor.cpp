@@ -183,6 +183,7 @@ void record(FactorState* f, int q, int nsub, double eps, bool rounded) {
   note_test_impl(f, q, eps, rounded);
   if (f->flushing) {
     f->pend.push_back({f->cur_phase, q, nsub, eps, rounded});
+    if (f->feat_log) f->pend_feat.insert(f->pend_feat.end(), f->cur_feat, f->cur_feat + QS_MLP_INPUTS);
     return;
   }
   if (rounded) f->F *= (1.0 - eps);
@@ -273,7 +274,11 @@ int decide_qubit(FactorState* f, int q, int si, int t, const double st[4], doubl
 void begin_test(FactorState* f, int q, double p) {
   f->dirty &= ~(uint64_t(1) << q);
   f->deferred &= ~(uint64_t(1) << q);
-  if (f->feat_log && f->log_count && *f->log_count < f->feat_cap)
+  f->prop &= ~(uint64_t(1) << q);
+  if (!f->feat_log || !f->log_count) return;
+  if (f->flushing)
+    fact_features(f, q, p, f->cur_feat);  // logged with the attempt, in gate order
+  else if (*f->log_count < f->feat_cap)
     fact_features(f, q, p, f->feat_log + *f->log_count * QS_MLP_INPUTS);
 }
 
@@ -557,6 +562,29 @@ int fact_largest(const FactorState* f) {
 
 namespace {
 
+// Exact tests, without the proposer, of the qubits of `mask` (skipped by the
+// proposer earlier): at once, or (deferred mode) after the pending tests, in
+// a flush of their own that logs them after every earlier gate's attempts.
+int exact_retest(FactorState* f, uint64_t mask) {
+  if (!f->defer) {
+    f->dirty |= mask;
+    int nsep = 0;
+    return plain_separate(f, f->p, &nsep);
+  }
+  if (f->dirty)
+    if (int rc = flush_pending(f)) return rc;
+  f->dirty |= mask;
+  const uint64_t phase = ++f->phase_next;
+  for (auto& S : f->subs)
+    for (int b = 0; b < S.nq; ++b)
+      if ((mask >> S.q[b]) & 1) {
+        S.plain = true;
+        S.phase = phase;
+        break;
+      }
+  return flush_pending(f);
+}
+
 // Deferred mode, a two-qubit gate: the merge (when the qubits lie in two
 // subsystems) and the gate become one queued operation; the subsystem table
 // changes at once, as merge() changes it. The capacity was checked.
@@ -638,9 +666,7 @@ int fact_apply(FactorState* f, const int* qubits, int k, const double* m) {
     if (mask) {
       f->fallback_tests += uint64_t(__builtin_popcountll(mask));
       f->deferred &= ~mask;
-      f->dirty |= mask;
-      int nsep = 0;
-      if (int rc = plain_separate(f, f->p, &nsep)) return rc;
+      if (int rc = exact_retest(f, mask)) return rc;
       nd = 0;
       total = 0;
       for (int j = 0; j < k; ++j) {
@@ -652,14 +678,16 @@ int fact_apply(FactorState* f, const int* qubits, int k, const double* m) {
       }
     }
   }
-  if ((total >= 63 || (uint64_t(1) << total) > f->max_amps) && f->deferred) {
+  const bool over = total >= 63 || (uint64_t(1) << total) > f->max_amps;
+  if (over && f->defer && f->dirty)  // every skip the fallback must see happens first
+    if (int rc = flush_pending(f)) return rc;
+  if (over && f->deferred) {
     // exhaustive fallback: exact tests of every qubit the proposer skipped
     // may shrink the subsystems enough for the merge
     f->fallback_tests += uint64_t(__builtin_popcountll(f->deferred));
-    f->dirty |= f->deferred;
+    const uint64_t mask = f->deferred;
     f->deferred = 0;
-    int nsep = 0;
-    if (int rc = plain_separate(f, f->p, &nsep)) return rc;
+    if (int rc = exact_retest(f, mask)) return rc;
     nd = 0;
     total = 0;
     for (int j = 0; j < k; ++j) {
@@ -779,12 +807,42 @@ int flush_round(FactorState* f, bool* any) {
     int si, G;
     int q[kMultiTest], t[kMultiTest];  // ascending qubit number
   };
+  // learned schedule: the subsystems of at least propose_min qubits (not
+  // under a plain retest) send their unscored dirty qubits to the network;
+  // the ones below the cutoff leave the dirty set (deferred)
+  auto learned = [f](const Sub& S) {
+    return f->proposer && !S.plain && S.nq >= f->propose_min;
+  };
+  if (f->proposer) {
+    std::vector<int> cand;
+    for (const Sub& S : f->subs)
+      if (learned(S))
+        for (int b = 0; b < S.nq; ++b)
+          if (((f->dirty & ~f->prop) >> S.q[b]) & 1) cand.push_back(S.q[b]);
+    if (!cand.empty()) {
+      std::vector<float> X(cand.size() * QS_MLP_INPUTS), score(cand.size());
+      for (size_t i = 0; i < cand.size(); ++i)
+        fact_features(f, cand[i], f->p, &X[i * QS_MLP_INPUTS]);
+      if (int rc = mlp_scores(f->proposer, X.data(), cand.size(), score.data())) return rc;
+      for (size_t i = 0; i < cand.size(); ++i) {
+        const uint64_t bit = uint64_t(1) << cand[i];
+        if (score[i] >= f->cutoff) {
+          f->prop |= bit;
+        } else {
+          f->dirty &= ~bit;
+          f->deferred |= bit;
+          ++f->skipped;
+        }
+      }
+    }
+  }
   std::vector<Item> items;
   for (int si = 0; si < int(f->subs.size()); ++si) {
     const Sub& S = f->subs[si];
+    const uint64_t want = learned(S) ? (f->dirty & f->prop) : f->dirty;
     int qd[64], td[64], nd = 0;
     for (int b = 0; b < S.nq; ++b)
-      if ((f->dirty >> S.q[b]) & 1) {
+      if ((want >> S.q[b]) & 1) {
         qd[nd] = S.q[b];
         td[nd++] = b;
       }
@@ -867,7 +925,11 @@ int flush_round(FactorState* f, bool* any) {
       begin_test(f, it.q[j], f->p);
       bool rounded = false;
       if (int rc = decide_qubit(f, it.q[j], it.si, it.t[j], sums, f->p, &rounded)) return rc;
-      if (rounded) break;
+      if (rounded) {  // the subsystem's remaining qubits are dirty and unscored again
+        const Sub& S = f->subs[it.si];
+        for (int b = 0; b < S.nq; ++b) f->prop &= ~(uint64_t(1) << S.q[b]);
+        break;
+      }
     }
   }
   return QS_OK;
@@ -945,15 +1007,22 @@ int flush_pending(FactorState* f) {
     rc = f->dtype == QS_C64 ? flush_round<float>(f, &any) : flush_round<double>(f, &any);
   if (rc == QS_OK) rc = launch_queue(f);  // the last projections
   f->flushing = false;
-  std::stable_sort(f->pend.begin(), f->pend.end(),
-                   [](const FactorState::Decision& a, const FactorState::Decision& b) {
-                     return a.phase < b.phase;
-                   });
-  for (const auto& d : f->pend) {
+  for (auto& S : f->subs) S.plain = false;
+  std::vector<size_t> order(f->pend.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [f](size_t a, size_t b) { return f->pend[a].phase < f->pend[b].phase; });
+  const bool feats = f->feat_log && f->pend_feat.size() == f->pend.size() * QS_MLP_INPUTS;
+  for (size_t i : order) {
+    const FactorState::Decision& d = f->pend[i];
+    if (feats && f->log_count && *f->log_count < f->feat_cap)
+      std::memcpy(f->feat_log + *f->log_count * QS_MLP_INPUTS, &f->pend_feat[i * QS_MLP_INPUTS],
+                  QS_MLP_INPUTS * sizeof(float));
     if (d.rounded) f->F *= (1.0 - d.eps);
     log_attempt(f, d.q, d.nsub, d.eps, d.rounded);
   }
   f->pend.clear();
+  f->pend_feat.clear();
   return rc;
 }
 
@@ -1055,8 +1124,8 @@ int fact_apply_1q_run(FactorState* f, const int* qubits, const double* m, int co
 }
 
 void fact_begin_run(FactorState* f) {
-  f->defer = g_defer_sep && f->policy == QS_SEP_AFTER_2Q && !f->proposer && !f->feat_log &&
-             !f->dirty;
+  f->defer = g_defer_sep && f->policy == QS_SEP_AFTER_2Q && !f->dirty;
+  f->prop = 0;
 }
 
 int fact_end_run(FactorState* f, int rc) {

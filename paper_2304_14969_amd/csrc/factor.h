@@ -16,6 +16,7 @@ struct Sub {
   int q[64] = {0};
   void* amps = nullptr;  // 2^nq amplitudes, device, owned
   uint64_t phase = 0;    // deferred separation: the gate its dirty qubits wait on
+  bool plain = false;    // deferred separation: exact tests without the proposer
 };
 
 struct FactorState {
@@ -54,6 +55,9 @@ struct FactorState {
   bool flushing = false;
   uint64_t phase_next = 0, cur_phase = 0;
   std::vector<Decision> pend;
+  std::vector<float> pend_feat;         // features of each held-back attempt (feature log on)
+  float cur_feat[QS_MLP_INPUTS] = {0};  // features of the attempt being decided
+  uint64_t prop = 0;                    // learned schedule: scored, proposed, not yet tested
   // While deferring, merges with their two-qubit gate and projections are
   // queued and launched together at the next point that reads device data.
   // No queued operation reads another's output (a gate on a subsystem whose
@@ -124,9 +128,9 @@ int fact_apply(FactorState* f, const int* qubits, int k, const double* m);
 // one workgroup each in a single launch that applies their gates in order;
 // larger subsystems get one launch per gate.
 int fact_apply_1q_run(FactorState* f, const int* qubits, const double* m, int count);
-// A circuit run: fact_begin_run turns deferred separation on when the plain
-// schedule runs after every multi-qubit gate (no proposer, no feature log, no
-// dirty qubit left from before); fact_end_run runs the pending tests and turns
+// A circuit run: fact_begin_run turns deferred separation on when the
+// separation runs after every multi-qubit gate and no dirty qubit is left from
+// before; fact_end_run runs the pending tests and turns
 // it off. fact_end_run returns rc when it is an error (after the pending tests,
 // unless rc is a device error), else its own status.
 void fact_begin_run(FactorState* f);

@@ -114,3 +114,65 @@ def test_proposer_gate_below_min_size_is_plain(qs_lib):
         finally:
             st.free()
     net.free()
+
+
+def _with_defer(qs, value, fn):
+    saved = qs.tune_get("factor.defer")
+    qs.tune_set("factor.defer", value)
+    try:
+        return fn()
+    finally:
+        qs.tune_set("factor.defer", saved)
+
+
+def test_deferred_learned_schedule_cutoff_zero_is_plain(qs_lib):
+    """With every qubit proposed (cutoff 0) the learned schedule is the plain
+    one; with deferred tests too the logs agree exactly."""
+    from paper_2304_14969_amd import protocol
+    qs = qs_lib
+    net = qs.MLP(qs.mlp_init(5))
+    gates = workloads.grid_circuit(4, 4, 7, 8)
+    for defer in (0, 1):
+        a = _with_defer(qs, defer, lambda: protocol.approx_run(16, gates, 0.3, record=True))
+        b = _with_defer(qs, defer, lambda: protocol.approx_run(16, gates, 0.3, record=True,
+                                                               proposer=net, cutoff=0.0))
+        assert b["skipped"] == 0 and len(a["log"]) > 20
+        assert a["log"] == b["log"] and a["F"] == b["F"]
+    net.free()
+
+
+@pytest.mark.parametrize("max_amps", [2 ** 30, 2 ** 9])
+def test_deferred_learned_retests_match_immediate(qs_lib, max_amps):
+    """A network that proposes nothing (cutoff 1; its logits are far from
+    saturating the sigmoid): every exact test is a
+    retest of skipped qubits, before a merge or (at the small cap) in the
+    exhaustive fallback. Deferred and immediate tests make the same attempts
+    (the order inside one retest may differ), the same F and the same
+    outcome; every rounding obeys eps <= p/2 and F is the product of the
+    rounded attempts' 1 - eps."""
+    from paper_2304_14969_amd import protocol
+    qs = qs_lib
+    net = qs.MLP(qs.mlp_init(6))
+    gates = workloads.random_circuit(16, 7, 19)
+    runs = [_with_defer(qs, d, lambda: protocol.approx_run(16, gates, 0.2, max_amps=max_amps,
+                                                           record=True, proposer=net,
+                                                           cutoff=1.0))
+            for d in (0, 1)]
+    a, b = runs
+    assert a["ok"] == b["ok"]
+    assert a["skipped"] > 0 and a["fallback_tests"] > 0
+    # a retest may measure its qubits in other groups (other summation
+    # orders): eps agrees to rounding
+    la, lb = sorted(a["log"]), sorted(b["log"])
+    assert [(q, n, r) for q, n, _, r in la] == [(q, n, r) for q, n, _, r in lb]
+    assert max(abs(x[2] - y[2]) for x, y in zip(la, lb)) <= 1e-12
+    assert (a["skipped"], a["fallback_tests"]) == (b["skipped"], b["fallback_tests"])
+    for r in runs:
+        prod = 1.0
+        for q, nsub, eps, rounded in r["log"]:
+            if rounded:
+                assert eps <= 0.1 + 1e-6
+                prod *= 1.0 - eps
+        assert abs(r["F"] - prod) <= 1e-12 * prod
+    assert abs(a["F"] - b["F"]) <= 1e-12 * a["F"]
+    net.free()
