@@ -426,6 +426,9 @@ int qs_check(qs_state* st, double tol);
  *                    launch and one synchronization. Decisions, the attempt
  *                    log order and F are those of testing at once; 0: test
  *                    right after every gate;
+ *   "factor.tile_1q" 1 (default): in those runs, the one-qubit gates on a
+ *                    subsystem of 2^13 amplitudes or more run as tile passes
+ *                    (a few sweeps for all of them); 0: one sweep per gate;
  *   "factor.batch_1q" 1 (default): qs_run on a factorized state applies each
  *                    run of consecutive one-qubit gates in one launch over
  *                    the subsystems of at most 2^12 amplitudes (one

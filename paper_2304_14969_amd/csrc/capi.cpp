@@ -306,6 +306,9 @@ int qs_tune_set(const char* key, int64_t value) {
   } else if (!std::strcmp(key, "tile.mfma")) {
     if (value < 0 || value > 1) return fail(QS_E_INVAL, "tile.mfma must be 0 or 1");
     g_tile_mfma = int(value);
+  } else if (!std::strcmp(key, "factor.tile_1q")) {
+    if (value < 0 || value > 1) return fail(QS_E_INVAL, "factor.tile_1q must be 0 or 1");
+    qs::g_tile_1q = int(value);
   } else if (!std::strcmp(key, "factor.defer")) {
     if (value < 0 || value > 1) return fail(QS_E_INVAL, "factor.defer must be 0 or 1");
     qs::g_defer_sep = int(value);
@@ -332,6 +335,7 @@ int qs_tune_get(const char* key, int64_t* value) {
   else if (!std::strcmp(key, "factor.multi_test")) *value = qs::g_multi_test;
   else if (!std::strcmp(key, "factor.batch_1q")) *value = qs::g_batch_1q;
   else if (!std::strcmp(key, "factor.defer")) *value = qs::g_defer_sep;
+  else if (!std::strcmp(key, "factor.tile_1q")) *value = qs::g_tile_1q;
   else if (!std::strcmp(key, "tile.mfma")) *value = g_tile_mfma;
   else if (!std::strcmp(key, "qft.col_max")) *value = g_qft_tune.col_max;
   else if (!std::strcmp(key, "qft.col_rows")) *value = g_qft_tune.col_rows;
@@ -728,45 +732,10 @@ int tile_plan_for(qs_state* st, qs_circuit* c, qs_circuit::TileCache** out) {
     for (int j = 0; j < g.k; ++j) g.q[j] = st->perm[g.q[j]];
   const bool dense = st->dtype == QS_C64 && g_tile_mfma;
   tc.plan = qs::plan_tiles(phys, st->n, qs::tile_low_bits(st->dtype), qs::kTileRowBits, 4, dense);
-  const qs::TilePlan& pl = tc.plan;
-  std::vector<int32_t> tab;
-  for (size_t ri = 0; ri < pl.rounds.size(); ++ri) {
-    const auto& r = pl.rounds[ri];
-    tab.push_back(r.bits[0] | (r.bits[1] << 8) | (r.bits[2] << 16) | (r.bits[3] << 24));
-    tab.push_back(dense ? int32_t(ri * 1024) : r.g0);
-    tab.push_back(r.ng);
-    tab.push_back(0);
-  }
-  const size_t gates_at = tab.size() * sizeof(int32_t);
-  if (!dense)
-    for (const auto& g : pl.gates) {
-      tab.push_back(g.kind | (g.j1 << 4) | (g.j2 << 8));
-      tab.push_back(int32_t(2 * g.mat));
-    }
-  const size_t esz = prec == 0 ? sizeof(float) : sizeof(double);
-  const size_t mats_at = (tab.size() * sizeof(int32_t) + 255) / 256 * 256;
-  // dense rounds: each round's 32x32 real embedding in lane order, then the
-  // matrices of the block steps; sparse rounds: every matrix as is
-  const size_t emb = dense ? pl.rounds.size() * 1024 * sizeof(float) : 0;
-  const size_t total = mats_at + emb + 2 * pl.mats.size() * esz;
-  std::vector<unsigned char> host(total, 0);
-  std::memcpy(host.data(), tab.data(), tab.size() * sizeof(int32_t));
-  if (dense) {
-    std::vector<float> A(1024);
-    for (size_t ri = 0; ri < pl.rounds.size(); ++ri) {
-      qs::embed_round(pl.mats.data() + pl.rounds[ri].mat, A.data());
-      std::memcpy(host.data() + mats_at + ri * 1024 * sizeof(float), A.data(), 1024 * sizeof(float));
-    }
-  }
-  for (size_t i = 0; i < pl.mats.size(); ++i) {
-    if (prec == 0) {
-      const float v[2] = {float(pl.mats[i].real()), float(pl.mats[i].imag())};
-      std::memcpy(host.data() + mats_at + emb + 2 * i * esz, v, sizeof v);
-    } else {
-      const double v[2] = {pl.mats[i].real(), pl.mats[i].imag()};
-      std::memcpy(host.data() + mats_at + emb + 2 * i * esz, v, sizeof v);
-    }
-  }
+  std::vector<unsigned char> host;
+  size_t gates_at = 0, mats_at = 0, emb_at = 0;
+  qs::tile_tables(tc.plan, prec == 0, &host, &gates_at, &mats_at, &emb_at);
+  const size_t total = host.size();
   void* d = dev_alloc(std::max<size_t>(total, 256));
   if (!d) return fail(QS_E_NOMEM, "allocating %zu bytes of tile tables", total);
   const hipError_t e = hipMemcpy(d, host.data(), total, hipMemcpyHostToDevice);
@@ -777,8 +746,8 @@ int tile_plan_for(qs_state* st, qs_circuit* c, qs_circuit::TileCache** out) {
   tc.dev = d;
   tc.key = key;
   tc.gates_off = gates_at;
-  tc.mats_off = mats_at + emb;  // block-step matrices (and sparse-round matrices)
-  tc.emb_off = mats_at;
+  tc.mats_off = mats_at;  // block-step matrices (and sparse-round matrices)
+  tc.emb_off = emb_at;
   *out = &tc;
   return QS_OK;
 }

@@ -9,6 +9,7 @@
 // and the circuit ends with that renaming applied to the state's labels
 // (Table I: SWAP by qubit label swap).
 #include <algorithm>
+#include <cstring>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -348,6 +349,53 @@ TilePlan plan_tiles(const std::vector<Gate>& gates, int n, int C, int H, int W, 
     plan.steps.push_back(st);
   }
   return plan;
+}
+
+void tile_tables(const TilePlan& pl, bool c64, std::vector<unsigned char>* out, size_t* gates_off,
+                 size_t* mats_off, size_t* emb_off) {
+  const bool dense = pl.dense;
+  std::vector<int32_t> tab;
+  for (size_t ri = 0; ri < pl.rounds.size(); ++ri) {
+    const auto& r = pl.rounds[ri];
+    tab.push_back(r.bits[0] | (r.bits[1] << 8) | (r.bits[2] << 16) | (r.bits[3] << 24));
+    tab.push_back(dense ? int32_t(ri * 1024) : r.g0);
+    tab.push_back(r.ng);
+    tab.push_back(0);
+  }
+  const size_t gates_at = tab.size() * sizeof(int32_t);
+  if (!dense)
+    for (const auto& g : pl.gates) {
+      tab.push_back(g.kind | (g.j1 << 4) | (g.j2 << 8));
+      tab.push_back(int32_t(2 * g.mat));
+    }
+  const size_t esz = c64 ? sizeof(float) : sizeof(double);
+  const size_t emb_at = (tab.size() * sizeof(int32_t) + 255) / 256 * 256;
+  // dense rounds: each round's 32x32 real embedding in lane order, then the
+  // matrices of the block steps; sparse rounds: every matrix as is
+  const size_t emb = dense ? pl.rounds.size() * 1024 * sizeof(float) : 0;
+  const size_t total = emb_at + emb + 2 * pl.mats.size() * esz;
+  out->assign(total, 0);
+  unsigned char* host = out->data();
+  std::memcpy(host, tab.data(), tab.size() * sizeof(int32_t));
+  if (dense) {
+    std::vector<float> A(1024);
+    for (size_t ri = 0; ri < pl.rounds.size(); ++ri) {
+      embed_round(pl.mats.data() + pl.rounds[ri].mat, A.data());
+      std::memcpy(host + emb_at + ri * 1024 * sizeof(float), A.data(), 1024 * sizeof(float));
+    }
+  }
+  for (size_t i = 0; i < pl.mats.size(); ++i) {
+    if (c64) {
+      const float v[2] = {float(pl.mats[i].real()), float(pl.mats[i].imag())};
+      std::memcpy(host + emb_at + emb + 2 * i * esz, v, sizeof v);
+    } else {
+      const double v[2] = {pl.mats[i].real(), pl.mats[i].imag()};
+      std::memcpy(host + emb_at + emb + 2 * i * esz, v, sizeof v);
+    }
+  }
+  *gates_off = gates_at;
+  *emb_off = emb_at;
+  *mats_off = emb_at + emb;
 }
 
 void embed_round(const cd* u, float* out) {

@@ -84,6 +84,15 @@ struct TilePlan {
 // dense blocks between passes.
 TilePlan plan_tiles(const std::vector<Gate>& gates, int n, int C, int H, int W, bool dense);
 
+// The device tables of a plan, as one byte image: per round an int4 {bits
+// packed by byte, first gate (sparse) or embedding offset in floats (dense),
+// gate count, 0}; per gate (sparse) an int2 {kind | j1 << 4 | j2 << 8, offset
+// of its matrix in reals}; at emb_off (dense) the rounds' 32 x 32 embeddings
+// in lane order (float); at mats_off the plan's matrices (float or double
+// pairs). Offsets are bytes from the start.
+void tile_tables(const TilePlan& pl, bool c64, std::vector<unsigned char>* out, size_t* gates_off,
+                 size_t* mats_off, size_t* emb_off);
+
 // The operand a matrix-core round reads: the 32 x 32 real embedding
 // [[Re U, -Im U], [Im U, Re U]] (interleaved rows and columns) of a 16 x 16
 // complex round matrix u, in lane order: out[ks * 64 + lane] =

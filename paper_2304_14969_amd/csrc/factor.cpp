@@ -25,6 +25,7 @@
 #include <cstdio>
 #include <cstring>
 
+#include "circuit.h"
 #include "factor.h"
 #include "mlp.h"
 #include "qs_internal.h"
@@ -34,6 +35,7 @@ namespace qs {
 int g_multi_test = 1;
 int g_batch_1q = 1;
 int g_defer_sep = 1;
+int g_tile_1q = 1;
 
 void* device_alloc(size_t bytes);
 void device_free(void* p);
@@ -531,6 +533,9 @@ void fact_drain(FactorState* f) {
     for (void* p : v) device_free(p);
     v.clear();
   }
+  device_free(f->tile_dev);
+  f->tile_dev = nullptr;
+  f->tile_cap = 0;
 }
 
 int fact_set_basis(FactorState* f, uint64_t x) {
@@ -585,9 +590,9 @@ int exact_retest(FactorState* f, uint64_t mask) {
   return flush_pending(f);
 }
 
-// Deferred mode, a two-qubit gate: the merge (when the qubits lie in two
-// subsystems) and the gate become one queued operation; the subsystem table
-// changes at once, as merge() changes it. The capacity was checked.
+// A two-qubit gate: the merge (when the qubits lie in two subsystems) and the
+// gate become one queued operation; the subsystem table changes at once, as
+// merge() changes it. The capacity was checked.
 int queue_gate2(FactorState* f, const int* qubits, const double* m) {
   ++f->gate_count;
   const int si = find(f, qubits[0], nullptr), sj = find(f, qubits[1], nullptr);
@@ -701,7 +706,14 @@ int fact_apply(FactorState* f, const int* qubits, int k, const double* m) {
   if (total >= 63 || (uint64_t(1) << total) > f->max_amps)
     return ffail(QS_E_CAPACITY, "gate needs a %d-qubit subsystem (cap %llu amplitudes)", total,
                  (unsigned long long)f->max_amps);
-  if (f->defer && k == 2) return queue_gate2(f, qubits, m);
+  if (k == 2) {  // merge and gate in one operation, queued or launched at once
+    if (int rc = queue_gate2(f, qubits, m)) return rc;
+    if (f->defer) return QS_OK;
+    if (int rc = launch_queue(f)) return rc;
+    if (f->policy != QS_SEP_AFTER_2Q) return QS_OK;
+    int nsep = 0;
+    return fact_try_separate(f, f->p, &nsep);
+  }
   if (int rc = launch_queue(f)) return rc;
   // bookkeeping for the proposal features
   if (k >= 2) {
@@ -735,10 +747,6 @@ int fact_apply(FactorState* f, const int* qubits, int k, const double* m) {
       for (int i = 0; i < 4; ++i) { mm.re[i] = m[2 * i]; mm.im[i] = m[2 * i + 1]; }
       e = launch_apply_1q(static_cast<double*>(S.amps), S.nq, local[0], mm, f->stream);
     }
-  } else if (k == 2) {
-    e = f->dtype == QS_C64
-            ? launch_apply_small(static_cast<float*>(S.amps), S.nq, local, k, m, f->stream)
-            : launch_apply_small(static_cast<double*>(S.amps), S.nq, local, k, m, f->stream);
   } else {
     const size_t D = size_t(1) << k;
     e = upload(f, f->mat, m, D * D);
@@ -977,12 +985,8 @@ int launch_queue_t(FactorState* f) {
       if (e == hipSuccess) e = launch_store_single(static_cast<R*>(q.single), q.phi, f->stream);
       continue;
     }
-    const int loc[2] = {q.t0, q.t1};
-    if (q.nb > 0)
-      e = launch_compose(static_cast<R*>(q.c), static_cast<const R*>(q.a), q.na,
-                         static_cast<const R*>(q.b), q.nb, f->stream);
-    if (e == hipSuccess)
-      e = launch_apply_small(static_cast<R*>(q.c), q.na + q.nb, loc, 2, q.m, f->stream);
+    e = launch_merge_gate(static_cast<R*>(q.c), static_cast<const R*>(q.a), q.na,
+                          static_cast<const R*>(q.b), q.nb, q.t0, q.t1, q.m, f->stream);
   }
   return dev_err(e, "queued subsystem operations");
 }
@@ -1026,26 +1030,102 @@ int flush_pending(FactorState* f) {
   return rc;
 }
 
+// The one-qubit gates `list` (indices into qubits/m, in order) on the large
+// subsystem si: as tile passes when it holds a whole tile (each pass reads
+// and writes the subsystem once for all the gates on its 12 tile bits), else
+// one launch per gate. Plan tables go to a device buffer of the state through
+// a pinned slot.
+template <typename R>
+int large_1q_run(FactorState* f, int si, const int* qubits, const double* m,
+                 const std::vector<int>& list) {
+  const Sub& S = f->subs[si];
+  R* amps = static_cast<R*>(S.amps);
+  constexpr int kLow = 5;  // tile low bits (both precisions)
+  auto local_bit = [&S](int q) {
+    for (int b = 0; b < S.nq; ++b)
+      if (S.q[b] == q) return b;
+    return -1;
+  };
+  if (g_tile_1q && list.size() >= 2 && S.nq >= kLow + kTileRowBits) {
+    std::vector<Gate> gl(list.size());
+    for (size_t i = 0; i < list.size(); ++i) {
+      Gate& g = gl[i];
+      g.k = 1;
+      g.q[0] = local_bit(qubits[list[i]]);
+      g.m.resize(4);
+      for (int e = 0; e < 4; ++e)
+        g.m[e] = cd(m[8 * list[i] + 2 * e], m[8 * list[i] + 2 * e + 1]);
+    }
+    const TilePlan pl = plan_tiles(gl, S.nq, kLow, kTileRowBits, 4, false);
+    std::vector<unsigned char> tab;
+    size_t goff = 0, moff = 0, eoff = 0;
+    tile_tables(pl, sizeof(R) == 4, &tab, &goff, &moff, &eoff);
+    if (tab.size() <= FactorState::kSlotBytes) {
+      if (tab.size() > f->tile_cap) {
+        if (int rc = dev_err(hipStreamSynchronize(f->stream), "tile tables")) return rc;
+        device_free(f->tile_dev);
+        f->tile_cap = 0;
+        f->tile_dev = device_alloc(FactorState::kSlotBytes);
+        if (!f->tile_dev) return ffail(QS_E_NOMEM, "tile tables");
+        f->tile_cap = FactorState::kSlotBytes;
+      }
+      void *host = nullptr, *dev = nullptr;
+      const int slot = ring_slot(f, &host, &dev);
+      if (slot < 0) return slot;
+      std::memcpy(host, tab.data(), tab.size());
+      hipError_t e =
+          hipMemcpyAsync(f->tile_dev, host, tab.size(), hipMemcpyHostToDevice, f->stream);
+      if (e == hipSuccess) e = hipEventRecord(f->ring_ev[slot], f->stream);
+      if (e == hipSuccess) f->ring_used[slot] = true;
+      const char* base = static_cast<const char*>(f->tile_dev);
+      for (const TileStep& st : pl.steps) {
+        if (e != hipSuccess) break;
+        if (st.block) {  // not made from one-qubit gates
+          e = hipErrorInvalidValue;
+          break;
+        }
+        TileRows rows;
+        for (int j = 0; j < kTileRowBits; ++j) rows.b[j] = st.hb[j];
+        e = launch_tile_pass(amps, S.nq, kLow, rows, base + size_t(st.r0) * 4 * sizeof(int32_t),
+                             st.nr, base + goff, reinterpret_cast<const R*>(base + moff),
+                             f->stream);
+      }
+      return dev_err(e, "one-qubit tile passes");
+    }
+  }
+  for (int i : list) {
+    Mat2<R> mm;
+    for (int e = 0; e < 4; ++e) {
+      mm.re[e] = R(m[8 * i + 2 * e]);
+      mm.im[e] = R(m[8 * i + 2 * e + 1]);
+    }
+    if (int rc = dev_err(launch_apply_1q(amps, S.nq, local_bit(qubits[i]), mm, f->stream),
+                         "factorized gate"))
+      return rc;
+  }
+  return QS_OK;
+}
+
 template <typename R>
 int apply_1q_run(FactorState* f, const int* qubits, const double* m, int count) {
   // the gates of each small subsystem, in circuit order
   std::vector<int> item_of(f->subs.size(), -1);
   std::vector<std::vector<int>> per_item;
   std::vector<int> item_sub;
+  std::vector<int> large_of(f->subs.size(), -1);
+  std::vector<std::vector<int>> per_large;  // the gates of each large subsystem
+  std::vector<int> large_sub;
   for (int i = 0; i < count; ++i) {
     int t = 0;
     const int si = find(f, qubits[i], &t);
     if (si < 0) return ffail(QS_E_INVAL, "qubit %d not found", qubits[i]);
-    Sub& S = f->subs[si];
-    if (S.nq > kFact1qMaxQubits) {
-      Mat2<R> mm;
-      for (int e = 0; e < 4; ++e) {
-        mm.re[e] = R(m[8 * i + 2 * e]);
-        mm.im[e] = R(m[8 * i + 2 * e + 1]);
+    if (f->subs[si].nq > kFact1qMaxQubits) {
+      if (large_of[si] < 0) {
+        large_of[si] = int(per_large.size());
+        per_large.emplace_back();
+        large_sub.push_back(si);
       }
-      if (int rc = dev_err(launch_apply_1q(static_cast<R*>(S.amps), S.nq, t, mm, f->stream),
-                           "factorized gate"))
-        return rc;
+      per_large[large_of[si]].push_back(i);
       continue;
     }
     if (item_of[si] < 0) {
@@ -1105,6 +1185,8 @@ int apply_1q_run(FactorState* f, const int* qubits, const double* m, int count) 
     if (int rc = dev_err(e, "batched one-qubit gates")) return rc;
     f->ring_used[slot] = true;
   }
+  for (size_t l = 0; l < per_large.size(); ++l)
+    if (int rc = large_1q_run<R>(f, large_sub[l], qubits, m, per_large[l])) return rc;
   return QS_OK;
 }
 

@@ -82,6 +82,10 @@ struct FactorState {
   hipEvent_t ring_ev[kRingSlots] = {nullptr};
   bool ring_used[kRingSlots] = {false};
   int ring_next = 0;
+  // device copy of the tile-pass tables of the last one-qubit run on a large
+  // subsystem (rewritten in stream order)
+  void* tile_dev = nullptr;
+  size_t tile_cap = 0;
   // recycled subsystem buffers of at most kPoolQubits qubits, by qubit count
   static constexpr int kPoolQubits = 20;
   std::vector<void*> pool[kPoolQubits + 1];
@@ -113,6 +117,9 @@ extern int g_batch_1q;
 // Process-wide: deferred separation in qs_run (1, default) or the tests
 // right after every multi-qubit gate (0). Decisions are the same either way.
 extern int g_defer_sep;
+// Process-wide: one-qubit runs on subsystems of more than 2^12 amplitudes as
+// tile passes (1, default) or one launch per gate (0).
+extern int g_tile_1q;
 
 // The 32 proposal features of qubit q (threshold p) from the bookkeeping.
 void fact_features(const FactorState* f, int q, double p, float* out);

@@ -275,6 +275,47 @@ __global__ void __launch_bounds__(kBlock) k_decompose(R* __restrict__ b, const R
     decompose_at(b, a, u, t, p0r, p0i, p1r, p1i, scale);
 }
 
+// Group g of the merge-and-gate operation: the four amplitudes that differ in
+// local bits t0 and t1 of a (x) b (or of a alone when nb = 0), composed as
+// k_compose does, times the 4x4 matrix m in the order of the two-qubit
+// argument-matrix kernel, written to c.
+template <typename R>
+__device__ __forceinline__ void merge_gate_group(const R* a, int na, const R* __restrict__ b,
+                                                 int nb, R* c, int t0, int t1,
+                                                 const R* __restrict__ m, uint64_t g) {
+  const int lo = min(t0, t1), hi = max(t0, t1);
+  const uint64_t base = insert_zero(insert_zero(g, lo), hi);
+  uint64_t off[4];
+  R vr[4], vi[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    off[k] = base | (uint64_t(k & 1) << t0) | (uint64_t(k >> 1) << t1);
+    if (nb > 0) {
+      compose_at(a, na, b, off[k], vr[k], vi[k]);
+    } else {
+      vr[k] = a[2 * off[k]];
+      vi[k] = a[2 * off[k] + 1];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    R yr = 0, yi = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const R mr = m[2 * (r * 4 + k)], mi = m[2 * (r * 4 + k) + 1];
+      yr += mr * vr[k] - mi * vi[k];
+      yi += mr * vi[k] + mi * vr[k];
+    }
+    c[2 * off[r]] = yr;
+    c[2 * off[r] + 1] = yi;
+  }
+}
+
+template <typename R>
+struct MatArg4 {
+  R v[32];
+};
+
 // One workgroup per operation (see FactOp). The merge-and-gate form computes
 // the composed amplitudes as k_compose does and the 4x4 product as the
 // two-qubit argument-matrix kernel does, in the same order.
@@ -293,37 +334,20 @@ __global__ void __launch_bounds__(kBlock) k_fact_ops(const FactOp<R>* __restrict
     }
     return;
   }
-  const int n = op.na + op.nb;
-  const int lo = min(op.t0, op.t1), hi = max(op.t0, op.t1);
-  const uint64_t groups = uint64_t(1) << (n - 2);
-  const R* m = op.m;
-  for (uint64_t g = threadIdx.x; g < groups; g += kBlock) {
-    const uint64_t base = insert_zero(insert_zero(g, lo), hi);
-    uint64_t off[4];
-    R vr[4], vi[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      off[c] = base | (uint64_t(c & 1) << op.t0) | (uint64_t(c >> 1) << op.t1);
-      if (op.nb > 0) {
-        compose_at(op.a, op.na, op.b, off[c], vr[c], vi[c]);
-      } else {
-        vr[c] = op.a[2 * off[c]];
-        vi[c] = op.a[2 * off[c] + 1];
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      R yr = 0, yi = 0;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const R mr = m[2 * (r * 4 + c)], mi = m[2 * (r * 4 + c) + 1];
-        yr += mr * vr[c] - mi * vi[c];
-        yi += mr * vi[c] + mi * vr[c];
-      }
-      op.c[2 * off[r]] = yr;
-      op.c[2 * off[r] + 1] = yi;
-    }
-  }
+  const uint64_t groups = uint64_t(1) << (op.na + op.nb - 2);
+  for (uint64_t g = threadIdx.x; g < groups; g += kBlock)
+    merge_gate_group(op.a, op.na, op.b, op.nb, op.c, op.t0, op.t1, op.m, g);
+}
+
+// The merge-and-gate operation over a grid (large subsystems).
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_merge_gate(const R* a, int na,
+                                                       const R* __restrict__ b, int nb, R* c,
+                                                       int t0, int t1, MatArg4<R> m) {
+  const uint64_t groups = uint64_t(1) << (na + nb - 2);
+  for (uint64_t g = uint64_t(blockIdx.x) * kBlock + threadIdx.x; g < groups;
+       g += uint64_t(gridDim.x) * kBlock)
+    merge_gate_group(a, na, b, nb, c, t0, t1, m.v, g);
 }
 
 template <typename R>
@@ -440,6 +464,20 @@ hipError_t launch_fact_1q_batch(const Fact1qItem<R>* items, int nitems, const Fa
 }
 
 template <typename R>
+hipError_t launch_merge_gate(R* c, const R* a, int na, const R* b, int nb, int t0, int t1,
+                             const double m[32], hipStream_t s) {
+  if (na < 1 || nb < 0 || na + nb < 2 || t0 == t1 || t0 < 0 || t1 < 0 || t0 >= na + nb ||
+      t1 >= na + nb)
+    return hipErrorInvalidValue;
+  MatArg4<R> mat;
+  for (int i = 0; i < 32; ++i) mat.v[i] = static_cast<R>(m[i]);
+  const uint64_t groups = uint64_t(1) << (na + nb - 2);
+  hipLaunchKernelGGL(k_merge_gate<R>, dim3(blocks_for(groups)), dim3(kBlock), 0, s, a, na, b, nb,
+                     c, t0, t1, mat);
+  return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_fact_ops(const FactOp<R>* ops, int nops, hipStream_t s) {
   if (nops < 1) return hipSuccess;
   hipLaunchKernelGGL(k_fact_ops<R>, dim3(nops), dim3(kBlock), 0, s, ops);
@@ -490,6 +528,8 @@ hipError_t launch_gather_mul(const R* a, const uint64_t* idx, uint64_t m, Perm64
   template hipError_t launch_store_single<R>(R*, const double*, hipStream_t);               \
   template hipError_t launch_bloch_batch<R>(const BlochItem<R>*, int, double*, hipStream_t); \
   template hipError_t launch_fact_ops<R>(const FactOp<R>*, int, hipStream_t);               \
+  template hipError_t launch_merge_gate<R>(R*, const R*, int, const R*, int, int, int,      \
+                                           const double*, hipStream_t);                     \
   template hipError_t launch_fact_1q_batch<R>(const Fact1qItem<R>*, int, const Fact1qGate<R>*, int, \
                                               hipStream_t);                                 \
   template hipError_t launch_bloch_multi<R>(const R*, int, const int*, int, double*, double*, \

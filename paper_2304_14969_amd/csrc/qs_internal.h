@@ -142,6 +142,12 @@ struct FactOp {
 };
 template <typename R>
 hipError_t launch_fact_ops(const FactOp<R>* ops, int nops, hipStream_t s);
+// The kind-0 operation of FactOp over a grid, for any size: c = a (x) b (or a
+// in place when nb = 0, c == a), then the 4x4 matrix m (interleaved,
+// row-major, converted to R) on local bits t0, t1.
+template <typename R>
+hipError_t launch_merge_gate(R* c, const R* a, int na, const R* b, int nb, int t0, int t1,
+                             const double m[32], hipStream_t s);
 // One-qubit gates on many small subsystems in one launch: workgroup i applies
 // the gates gates[items[i].g0 .. + ng) in order to subsystem items[i], held in
 // LDS meanwhile. Every item has 1 <= nq <= max_nq <= kFact1qMaxQubits. Both

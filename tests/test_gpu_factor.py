@@ -324,3 +324,27 @@ def test_deferred_tests_capacity_and_leftover_dirty(qs_lib):
         a = _run_mode(qs, n, pre + gates, 0.3, C64, 0, dirty=(1 << n) - 1)
         b = _run_mode(qs, n, pre + gates, 0.3, C64, defer, dirty=(1 << n) - 1)
         assert a[0] == b[0] and a[1] == b[1] and a[2] == b[2]
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_large_subsystem_paths(qs_lib, dtype):
+    """Subsystems past the one-workgroup bounds: merges with their gate over a
+    grid (17 and 18 qubits), and one-qubit runs on a 17-qubit subsystem as tile
+    passes or one sweep per gate; both ways match the dense oracle."""
+    qs = qs_lib
+    n = 18
+    g = np.random.default_rng(33)
+    layer = lambda: [("u3", q, *g.uniform(0, 2 * math.pi, 3)) for q in range(n)]
+    gates = [("h", q) for q in range(n)] + [("cz", q, q + 1) for q in range(16)]
+    gates += layer() + layer() + layer() + [("cz", 16, 17)] + layer() + [("iswap", 3, 11)] + layer()
+    want = dense.run_circuit(dense.zero_state(n), n, gates)
+    saved = qs.tune_get("factor.tile_1q")
+    try:
+        for tile in (1, 0):
+            qs.tune_set("factor.tile_1q", tile)
+            st = gpu_run(qs, n, gates, 0.0, dtype)
+            assert sorted(len(s) for s in st.subsystems()) == [18]
+            assert_parity(st.amplitudes(), want, dtype, f"tile_1q={tile}")
+            st.free()
+    finally:
+        qs.tune_set("factor.tile_1q", saved)
