@@ -162,9 +162,21 @@ def bench_approx(qs, workloads, protocol, np, family: str, p_cmp: float = 0.6,
     out["training"] = {"rows": int(len(y)), "positive": round(float(y.mean()), 4),
                        "loss": round(loss, 4), "cutoff": round(cutoff, 4),
                        "collect_and_train_s": round(time.perf_counter() - t0, 2)}
-    rows = {"plain": [], "learned": []}
+    # "plain_per_gate": the paper's form, every gate and every test launched
+    # and synchronized on its own; "plain": the same decisions with tests
+    # deferred and batched; "learned": batched, with the proposal network
+    per_gate = {"factor.defer": 0, "factor.batch_1q": 0, "factor.tile_1q": 0}
+    rows = {"plain_per_gate": [], "plain": [], "learned": []}
     for s in test_seeds:
         g = gen(s)
+        saved = {k: qs.tune_get(k) for k in per_gate}
+        for k, v in per_gate.items():
+            qs.tune_set(k, v)
+        try:
+            rows["plain_per_gate"].append(protocol.approx_run(54, g, p_cmp, record=True))
+        finally:
+            for k, v in saved.items():
+                qs.tune_set(k, v)
         rows["plain"].append(protocol.approx_run(54, g, p_cmp, record=True))
         rows["learned"].append(protocol.approx_run(54, g, p_cmp, record=True, proposer=net,
                                                    cutoff=cutoff, min_qubits=min_qubits))
@@ -173,7 +185,8 @@ def bench_approx(qs, workloads, protocol, np, family: str, p_cmp: float = 0.6,
     for k, rs in rows.items():
         ok = [r for r in rs if r["ok"]]
         cmp[k] = {"completed": len(ok), "of": len(rs),
-                  "time_s_mean": round(sum(r["time_s"] for r in rs) / len(rs), 4),
+                  "time_s_mean": round(sum(r["time_s"] for r in rs) / len(rs), 5),
+                  "time_s_median": round(float(np.median([r["time_s"] for r in rs])), 5),
                   "logF_mean": round(float(np.mean([np.log(r["F"]) for r in ok])), 3) if ok else None,
                   "exact_tests": sum(r["attempts"] for r in rs),
                   "roundings": sum(r["roundings"] for r in rs)}
