@@ -215,6 +215,14 @@ __device__ __forceinline__ void tile_mfma_body(float* __restrict__ a, uint64_t b
     return g;
   };
   float4* p4 = reinterpret_cast<float4*>(a);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, p = lane >> 5;
+  // this lane's part of the first round's embedded matrix, issued before the
+  // tile so that its latency hides behind the tile's (the scheduling barrier
+  // keeps the compiler from sinking these loads to their first use)
+  float A[kV];
+#pragma unroll
+  for (int ks = 0; ks < kV; ++ks) A[ks] = amats[rounds[0].y + ks * 64 + lane];
+  __builtin_amdgcn_sched_barrier(0);
   {
     float4 buf[NV];
 #pragma unroll
@@ -222,6 +230,10 @@ __device__ __forceinline__ void tile_mfma_body(float* __restrict__ a, uint64_t b
       const int e = threadIdx.x + k * NT;
       buf[k] = p4[glob(e / VPR, (e % VPR) * 2) / 2];
     }
+    // an empty use of the matrix after the tile loads are issued: it anchors
+    // the matrix loads ahead of them (they complete first, in order)
+#pragma unroll
+    for (int ks = 0; ks < kV; ++ks) asm volatile("" ::"v"(A[ks]));
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       const int e = threadIdx.x + k * NT;
@@ -230,21 +242,19 @@ __device__ __forceinline__ void tile_mfma_body(float* __restrict__ a, uint64_t b
       sm[lds_pos(x + 1)] = make_float2(buf[k].z, buf[k].w);
     }
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, p = lane >> 5;
-  // this lane's part of the first round's embedded matrix, loaded with the tile
-  float A[kV];
-#pragma unroll
-  for (int ks = 0; ks < kV; ++ks) A[ks] = amats[rounds[0].y + ks * 64 + lane];
   __syncthreads();
   for (int r = 0; r < nrounds; ++r) {
     const int4 rd = rounds[r];
     const int b0 = rd.x & 255, b1 = (rd.x >> 8) & 255, b2 = (rd.x >> 16) & 255,
               b3 = (rd.x >> 24) & 255;
-    // the next round's matrix is loaded while this round computes
+    // the next round's matrix is loaded while this round computes (kept here
+    // by the scheduling barrier; left to itself the compiler sinks the loads
+    // to the end of the round and the next round waits for them)
     float An[kV];
     const int offn = rounds[r + 1 < nrounds ? r + 1 : r].y;
 #pragma unroll
     for (int ks = 0; ks < kV; ++ks) An[ks] = amats[offn + ks * 64 + lane];
+    __builtin_amdgcn_sched_barrier(0);
     int dep[kV];  // LDS offset of round-local index m (the round bits and padding)
 #pragma unroll
     for (int m = 0; m < kV; ++m)
@@ -327,14 +337,16 @@ hipError_t launch_mfma_c(float* a, int n, const TileRows& rows, const void* roun
     if (rows.b[j] < C || rows.b[j] >= n || (j > 0 && rows.b[j] <= rows.b[j - 1]))
       return hipErrorInvalidValue;
   const size_t bytes = size_t((1 << TB) + ((1 << TB) >> 4)) * sizeof(float2);
+  const uint64_t tiles = uint64_t(1) << (n - TB);
   auto kern = k_tile_mfma<C, H>;
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
-  hipLaunchKernelGGL(kern, dim3(unsigned(uint64_t(1) << (n - TB))), dim3(1 << (TB - kW)), bytes,
-                     s, a, rows, static_cast<const int4*>(rounds), nrounds, amats);
+  hipLaunchKernelGGL(kern, dim3(unsigned(tiles)), dim3(1 << (TB - kW)), bytes, s, a, rows,
+                     static_cast<const int4*>(rounds), nrounds, amats);
   return hipGetLastError();
 }
 }  // namespace
+
 
 hipError_t launch_tile_mfma(float* a, int n, int low_bits, const TileRows& rows,
                             const void* rounds, int nrounds, const float* amats, hipStream_t s) {

@@ -16,12 +16,13 @@ def tile_mode(request, qs_lib):
     two-qubit gates in registers, on tiles with 64- or 32-amplitude rows.
     Yields whether the matrix-core rounds are on."""
     mfma, low = request.param
-    saved = (qs_lib.tune_get("tile.mfma"), qs_lib.tune_get("tile.low_bits"))
-    qs_lib.tune_set("tile.mfma", mfma)
-    qs_lib.tune_set("tile.low_bits", low)
+    keys = ("tile.mfma", "tile.low_bits")
+    saved = [qs_lib.tune_get(k) for k in keys]
+    for k, v in zip(keys, (mfma, low)):
+        qs_lib.tune_set(k, v)
     yield mfma
-    qs_lib.tune_set("tile.mfma", saved[0])
-    qs_lib.tune_set("tile.low_bits", saved[1])
+    for k, v in zip(keys, saved):
+        qs_lib.tune_set(k, v)
 
 
 @pytest.mark.parametrize("dtype,n", [(C64, 13), (C64, 14), (C64, 17), (C128, 12), (C128, 15)])
