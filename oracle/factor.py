@@ -29,6 +29,25 @@ Readings (each also listed with the design notes):
   * The phase of phi is fixed by phi_0 real and >= 0; at |r| = 0, phi = |0>.
   * A merge of subsystems A (first operand's) and B is kron(b, a): A's qubits
     keep their bit positions and B's follow.
+
+Two-qubit rounding. The paper states only that the technique generalizes to
+(at least) two-qubit subsystems (Sec. III-A, after Fig. 2); it gives no rule
+or schedule. Reading used here (an opt-in policy; the benchmarks use the
+one-qubit form):
+  * For a pair B = {a, b} of one subsystem S with at least three qubits, rho_B
+    is the 4x4 reduced density matrix; its largest eigenvalue lambda is the
+    weight of the dominant Schmidt term, and eps_B = 1 - lambda (for a single
+    qubit this is exactly (1 - |r|)/2). The pair is rounded when
+    eps_B <= p/2 + tau: S is projected on the dominant eigenvector phi of
+    rho_B, the pair becomes its own subsystem [a, b] with amplitudes phi
+    (index bit 0 = a, bit 1 = b), the normalized remainder <phi| psi stays in
+    S, and F is multiplied by 1 - eps_B.
+  * Schedule: after a two-qubit gate on (a, b) and the one-qubit tests it
+    causes, if a and b still share a subsystem of at least three qubits, the
+    pair is tested once; a rounding makes the rest of S dirty, whose one-qubit
+    tests then run.
+  * The phase of phi is fixed by its first component of magnitude above 1e-9
+    being real and positive; the expanded ket does not depend on it.
 """
 from __future__ import annotations
 
@@ -53,6 +72,7 @@ class Attempt:
     n_sub: int
     eps: float
     rounded: bool
+    pair: int = -1  # the second qubit of a two-qubit attempt
 
 
 @dataclass
@@ -100,6 +120,41 @@ def project_out(amps: np.ndarray, nq: int, t: int, phi: np.ndarray) -> np.ndarra
     steps 3-4). Its index is the subsystem index with bit t removed."""
     v = amps.reshape(2 ** (nq - t - 1), 2, 2 ** t)
     b = (np.conj(phi[0]) * v[:, 0, :] + np.conj(phi[1]) * v[:, 1, :]).reshape(-1)
+    return b / math.sqrt(float(np.vdot(b, b).real))
+
+
+def pair_density(amps: np.ndarray, nq: int, t1: int, t2: int) -> np.ndarray:
+    """Reduced density matrix of the qubits at bits t1, t2 (t1 != t2): row and
+    column index m = bit t1 + 2 bit t2; rho[m, m'] = sum over the other bits of
+    a[.., m] conj(a[.., m']), divided by the squared norm."""
+    v = amps.reshape([2] * nq)  # axis k is bit nq - 1 - k
+    ax1, ax2 = nq - 1 - t1, nq - 1 - t2
+    # move bit t2 then bit t1 to the last two axes: flattened index 2 b2 + b1
+    v = np.moveaxis(v, [ax2, ax1], [nq - 2, nq - 1]).reshape(-1, 4)
+    rho = v.T @ v.conj()
+    return rho / np.trace(rho).real
+
+
+def pair_dominant(rho: np.ndarray) -> tuple:
+    """(eps_B, phi): eps_B = 1 - the largest eigenvalue of rho (clipped to
+    [0, 3/4]) and phi its unit eigenvector, phase-fixed as in the module
+    notes (numpy's Hermitian eigensolver)."""
+    w, vecs = np.linalg.eigh(rho)
+    phi = vecs[:, -1].astype(C128)
+    big = np.abs(phi) > 1e-9 * np.abs(phi).max()
+    k = int(np.argmax(big))
+    phi = phi * (abs(phi[k]) / phi[k])
+    return float(min(max(1.0 - w[-1], 0.0), 0.75)), phi
+
+
+def project_out_pair(amps: np.ndarray, nq: int, t1: int, t2: int,
+                     phi: np.ndarray) -> np.ndarray:
+    """Remainder <phi|_B psi on the other nq-2 qubits, normalized; its index is
+    the subsystem index with bits t1 and t2 removed (in order)."""
+    v = amps.reshape([2] * nq)
+    ax1, ax2 = nq - 1 - t1, nq - 1 - t2
+    v = np.moveaxis(v, [ax2, ax1], [nq - 2, nq - 1]).reshape(-1, 4)
+    b = v @ phi.conj()
     return b / math.sqrt(float(np.vdot(b, b).real))
 
 
@@ -204,6 +259,32 @@ class FactorizedState:
         self.log.append(Attempt(q, nq, eps, False))
         return False
 
+    def test_pair(self, qa: int, qb: int, p: float) -> bool:
+        """One two-qubit attempt on (qa, qb) (the reading in the module notes).
+        Returns True if the pair was rounded into its own subsystem."""
+        sa, ta = self.where(qa)
+        sb, tb = self.where(qb)
+        if sa != sb or qa == qb:
+            return False
+        S = self.subs[sa]
+        nq = len(S.qubits)
+        if nq < 3:
+            return False
+        eps, phi = pair_dominant(pair_density(S.amps, nq, ta, tb))
+        rounds = eps <= p / 2.0 + self.tau
+        if self.decide is not None:
+            rounds = bool(self.decide(qa, nq, eps, rounds))
+        self.log.append(Attempt(qa, nq, eps, rounds, pair=qb))
+        if not rounds:
+            return False
+        rest = project_out_pair(S.amps, nq, ta, tb, phi)
+        others = [x for x in S.qubits if x not in (qa, qb)]
+        S.qubits, S.amps = others, rest
+        self.subs.append(Sub([qa, qb], phi))
+        self.F *= (1.0 - eps)
+        self.dirty.update(others)
+        return True
+
     def try_separate(self, p: float) -> int:
         """Test dirty qubits, lowest index first, until none is dirty."""
         count = 0
@@ -212,12 +293,16 @@ class FactorizedState:
             count += int(self.test_qubit(q, p))
         return count
 
-    def run(self, gates, p: float):
-        """Apply a gate list, testing separability after every multi-qubit gate."""
+    def run(self, gates, p: float, pairs: bool = False):
+        """Apply a gate list, testing separability after every multi-qubit gate
+        (and, with pairs=True, the two-qubit rounding after two-qubit gates)."""
         for g in gates:
             self.apply_gate(g)
-            if len(dense.gate_matrix(g)[0]) >= 2:
+            qubits = dense.gate_matrix(g)[0]
+            if len(qubits) >= 2:
                 self.try_separate(p)
+                if pairs and len(qubits) == 2 and self.test_pair(qubits[0], qubits[1], p):
+                    self.try_separate(p)
         return self
 
     # -------------------------------------------------------------- readout

@@ -138,3 +138,53 @@ def test_dropped_tanh_derivative_is_caught(monkeypatch):
         return g
     monkeypatch.setattr(mlp, "backward", bad)
     _fails(tm.test_gradient_matches_central_differences, 0)
+
+
+# ------------------------------------------------------------ two-qubit rounding
+import test_oracle_pairs as tp  # noqa: E402
+
+
+def test_pair_density_without_conjugate_is_caught(monkeypatch):
+    def bad(amps, nq, t1, t2):
+        v = amps.reshape([2] * nq)
+        ax1, ax2 = nq - 1 - t1, nq - 1 - t2
+        v = np.moveaxis(v, [ax2, ax1], [nq - 2, nq - 1]).reshape(-1, 4)
+        rho = v.T @ v  # conjugate dropped
+        return rho / np.trace(rho)
+    monkeypatch.setattr(factor, "pair_density", bad)
+    _fails(tp.test_pair_density_by_definition, 3, 1)
+
+
+def test_pair_bits_in_the_wrong_order_are_caught(monkeypatch):
+    good = factor.pair_density
+    monkeypatch.setattr(factor, "pair_density", lambda a, n, t1, t2: good(a, n, t2, t1))
+    _fails(tp.test_pair_density_by_definition, 0, 4)
+
+
+def test_smallest_eigenvalue_as_eps_is_caught(monkeypatch):
+    def bad(rho):
+        w, vecs = np.linalg.eigh(rho)
+        return float(w[0]), vecs[:, -1].astype(complex)
+    monkeypatch.setattr(factor, "pair_dominant", bad)
+    _fails(tp.test_pair_spectrum_is_schmidt_weights, 1)
+
+
+def test_projection_on_the_weakest_term_is_caught(monkeypatch):
+    good = factor.pair_dominant
+
+    def bad(rho):
+        eps, _ = good(rho)
+        return eps, np.linalg.eigh(rho)[1][:, 0].astype(complex)
+    monkeypatch.setattr(factor, "pair_dominant", bad)
+    _fails(tp.test_projection_overlap_is_dominant_weight, 0)
+
+
+def test_projection_without_conjugate_phi_is_caught(monkeypatch):
+    def bad(amps, nq, t1, t2, phi):
+        v = amps.reshape([2] * nq)
+        ax1, ax2 = nq - 1 - t1, nq - 1 - t2
+        v = np.moveaxis(v, [ax2, ax1], [nq - 2, nq - 1]).reshape(-1, 4)
+        b = v @ phi
+        return b / math.sqrt(float(np.vdot(b, b).real))
+    monkeypatch.setattr(factor, "project_out_pair", bad)
+    _fails(tp.test_projection_overlap_is_dominant_weight, 1)
