@@ -153,16 +153,18 @@ int qs_qft(qs_state* st, int start, int len, int inverse);
  * 1 - eps (Eq. fid_model). */
 
 /* separation policies */
-enum { QS_SEP_NONE = 0,      /* only explicit qs_try_separate calls */
-       QS_SEP_AFTER_2Q = 1   /* after every multi-qubit gate */ };
+enum { QS_SEP_NONE = 0,           /* only explicit qs_try_separate calls */
+       QS_SEP_AFTER_2Q = 1,       /* after every multi-qubit gate */
+       QS_SEP_AFTER_2Q_PAIRS = 2  /* as 1, then the two-qubit rounding of the
+                                     operands of every two-qubit gate */ };
 
 /* one separability attempt */
 typedef struct {
-  int32_t qubit;     /* tested qubit */
+  int32_t qubit;     /* tested qubit (the first of a pair) */
   int32_t n_sub;     /* qubits in its subsystem when tested */
-  double eps;        /* (1 - |r|)/2 computed from the state (float64) */
-  int32_t rounded;   /* 1 if the qubit was separated */
-  int32_t reserved;
+  double eps;        /* (1 - |r|)/2, or 1 - lambda_max for a pair (float64) */
+  int32_t rounded;   /* 1 if the qubit (pair) was separated */
+  int32_t pair;      /* 0: one-qubit attempt; else 1 + the pair's second qubit */
 } qs_attempt;
 
 /* Factorized state of n qubits (1 <= n <= 63), every qubit its own |0>
@@ -179,6 +181,19 @@ int qs_set_separation_policy(qs_state* st, int policy, double p);
  * is dirty. *n_separated receives the number of roundings. No-op on dense
  * states. Synchronizes (each decision reads the statistics back). */
 int qs_try_separate(qs_state* st, double p, int* n_separated);
+
+/* Two-qubit rounding (Sec. III-A mentions the generalization of the rounding
+ * to two-qubit subsystems without a rule; this is the reading used): when qa
+ * and qb share a subsystem S of three or more qubits, rho_B is their 4x4
+ * reduced density matrix (float64 sums, index m = bit of qa + 2 bit of qb),
+ * eps_B = 1 - its largest eigenvalue (host Jacobi, float64). At eps_B <= p/2
+ * (+ the same tolerance as above) S is projected on the dominant eigenvector
+ * phi, the pair becomes a subsystem of its own (qa at bit 0, amplitudes phi),
+ * the rest of S is marked dirty and F is multiplied by 1 - eps_B; *rounded
+ * is set to 1. Qubits in different subsystems, or a subsystem of two qubits:
+ * no test, *rounded = 0. The attempt is logged with pair = 1 + qb. QS_E_INVAL
+ * on a dense state, equal or out-of-range qubits. Synchronizes. */
+int qs_try_separate_pair(qs_state* st, int qa, int qb, double p, int* rounded);
 
 /* Mark qubits (bit q of mask) dirty, e.g. to test a state built elsewhere. */
 int qs_mark_dirty(qs_state* st, uint64_t mask);

@@ -61,7 +61,7 @@ _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 
 class Attempt(C.Structure):
     _fields_ = [("qubit", C.c_int32), ("n_sub", C.c_int32), ("eps", C.c_double),
-                ("rounded", C.c_int32), ("reserved", C.c_int32)]
+                ("rounded", C.c_int32), ("pair", C.c_int32)]
 
 
 class TrainCfg(C.Structure):
@@ -115,6 +115,8 @@ _SIGS = [
     ("qs_alloc_factorized", C.c_int, [C.c_int, C.c_int, C.c_uint64, C.POINTER(C.c_void_p)]),
     ("qs_set_separation_policy", C.c_int, [C.c_void_p, C.c_int, C.c_double]),
     ("qs_try_separate", C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_int)]),
+    ("qs_try_separate_pair", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_double,
+                                       C.POINTER(C.c_int)]),
     ("qs_mark_dirty", C.c_int, [C.c_void_p, C.c_uint64]),
     ("qs_fidelity_estimate", C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     ("qs_subsystems", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
@@ -476,7 +478,7 @@ def tune_get(key: str) -> int:
     return v.value
 
 
-SEP_NONE, SEP_AFTER_2Q = 0, 1
+SEP_NONE, SEP_AFTER_2Q, SEP_AFTER_2Q_PAIRS = 0, 1, 2
 PROPOSE_RETEST_ON_MERGE = 1
 
 
@@ -607,6 +609,13 @@ class State:
         _check(self.lib, self.lib.qs_try_separate(self.h, float(p), C.byref(k)))
         return k.value
 
+    def try_separate_pair(self, qa: int, qb: int, p: float) -> bool:
+        """The two-qubit rounding of (qa, qb); True if the pair was split off."""
+        r = C.c_int()
+        _check(self.lib, self.lib.qs_try_separate_pair(self.h, int(qa), int(qb), float(p),
+                                                       C.byref(r)))
+        return bool(r.value)
+
     def mark_dirty(self, mask: int):
         _check(self.lib, self.lib.qs_mark_dirty(self.h, int(mask)))
 
@@ -635,7 +644,10 @@ class State:
 
     def attempts(self) -> list:
         n = min(self._log_count.value, len(self._log)) if self._log is not None else 0
-        return [(a.qubit, a.n_sub, a.eps, bool(a.rounded)) for a in self._log[:n]]
+        # one-qubit attempts: (qubit, n_sub, eps, rounded); two-qubit ones
+        # (the pair rounding) carry the second qubit as a fifth entry
+        return [(a.qubit, a.n_sub, a.eps, bool(a.rounded)) if a.pair == 0 else
+                (a.qubit, a.n_sub, a.eps, bool(a.rounded), a.pair - 1) for a in self._log[:n]]
 
     def record_features(self, cap: int = 1 << 20):
         """Record the 32 proposal features of every attempt (call after

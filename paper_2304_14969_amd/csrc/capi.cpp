@@ -907,10 +907,23 @@ int qs_run(qs_state* st, qs_circuit* c) {
 int qs_set_separation_policy(qs_state* st, int policy, double p) {
   if (int rc = check_state(st)) return rc;
   if (!st->fact) return fail(QS_E_UNSUPPORTED, "separation applies to factorized states");
-  if (policy != QS_SEP_NONE && policy != QS_SEP_AFTER_2Q) return fail(QS_E_INVAL, "unknown policy %d", policy);
+  if (policy != QS_SEP_NONE && policy != QS_SEP_AFTER_2Q && policy != QS_SEP_AFTER_2Q_PAIRS)
+    return fail(QS_E_INVAL, "unknown policy %d", policy);
   if (!(p >= 0.0 && p <= 1.0)) return fail(QS_E_INVAL, "p = %g outside [0, 1]", p);
   st->fact->policy = policy;
   st->fact->p = p;
+  return QS_OK;
+}
+
+int qs_try_separate_pair(qs_state* st, int qa, int qb, double p, int* rounded) {
+  if (int rc = check_state(st)) return rc;
+  if (!st->fact) return fail(QS_E_INVAL, "the pair rounding applies to factorized states");
+  if (qa < 0 || qb < 0 || qa >= st->n || qb >= st->n || qa == qb)
+    return fail(QS_E_INVAL, "bad pair (%d, %d)", qa, qb);
+  if (!(p >= 0.0 && p <= 1.0)) return fail(QS_E_INVAL, "p = %g outside [0, 1]", p);
+  bool r = false;
+  if (int rc = fact_rc(st, qs::fact_test_pair(st->fact, qa, qb, p, &r))) return rc;
+  if (rounded) *rounded = r ? 1 : 0;
   return QS_OK;
 }
 

@@ -133,7 +133,7 @@ int new_single(FactorState* f, int q, const double amp[4], Sub* out) {
   return QS_OK;
 }
 
-void log_attempt(FactorState* f, int q, int nsub, double eps, bool rounded) {
+void log_attempt(FactorState* f, int q, int nsub, double eps, bool rounded, int partner = -1) {
   if (!f->log || !f->log_count) return;
   if (*f->log_count < f->log_cap) {
     qs_attempt& a = f->log[*f->log_count];
@@ -141,9 +141,52 @@ void log_attempt(FactorState* f, int q, int nsub, double eps, bool rounded) {
     a.n_sub = nsub;
     a.eps = eps;
     a.rounded = rounded ? 1 : 0;
-    a.reserved = 0;
+    a.pair = partner + 1;
   }
   ++*f->log_count;
+}
+
+// Eigen-decomposition of a real symmetric 8x8 matrix by cyclic Jacobi
+// rotations (float64): w[k] and column k of V. Used on the real embedding
+// [[Re H, -Im H], [Im H, Re H]] of a 4x4 Hermitian H, whose spectrum is H's
+// with every eigenvalue twice; an eigenvector (x; y) gives H (x + i y) =
+// lambda (x + i y).
+void jacobi8(double A[8][8], double w[8], double V[8][8]) {
+  for (int i = 0; i < 8; ++i)
+    for (int j = 0; j < 8; ++j) V[i][j] = i == j ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < 8; ++i)
+      for (int j = 0; j < 8; ++j) {
+        tot += A[i][j] * A[i][j];
+        if (i != j) off += A[i][j] * A[i][j];
+      }
+    if (off <= 1e-30 * tot) break;
+    for (int p = 0; p < 7; ++p)
+      for (int q = p + 1; q < 8; ++q) {
+        if (A[p][q] == 0.0) continue;
+        // rotation that zeroes A[p][q] (the smaller-angle root)
+        const double th = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < 8; ++k) {  // columns p, q
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 8; ++k) {  // rows p, q
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < 8; ++k) {
+          const double vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - sn * vkq;
+          V[k][q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  for (int i = 0; i < 8; ++i) w[i] = A[i][i];
 }
 
 // Merge subsystem ib into ia (ia's qubits keep their bits); returns the
@@ -565,6 +608,121 @@ int fact_largest(const FactorState* f) {
   return m;
 }
 
+int fact_test_pair(FactorState* f, int qa, int qb, double p, bool* rounded) {
+  *rounded = false;
+  int ta = 0, tb = 0;
+  const int sa = find(f, qa, &ta), sb = find(f, qb, &tb);
+  if (sa < 0 || sb < 0 || qa == qb) return ffail(QS_E_INVAL, "bad pair (%d, %d)", qa, qb);
+  if (sa != sb || f->subs[sa].nq < 3) return QS_OK;  // nothing to split off
+  if (int rc = launch_queue(f)) return rc;
+  const Sub& S0 = f->subs[sa];
+  hipError_t e = f->dtype == QS_C64
+                     ? launch_pair_rho(static_cast<const float*>(S0.amps), S0.nq, ta, tb,
+                                       f->scratch, f->dstat, f->stream)
+                     : launch_pair_rho(static_cast<const double*>(S0.amps), S0.nq, ta, tb,
+                                       f->scratch, f->dstat, f->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+  if (int rc = dev_err(e, "pair density")) return rc;
+  // H = rho (unnormalized), index m = bit ta + 2 bit tb
+  double hr[4][4], hi[4][4];
+  const double* st = f->hstat;
+  const double tr = st[0] + st[1] + st[2] + st[3];
+  if (!(tr > 0.0)) return ffail(QS_E_NUMERIC, "subsystem of qubit %d has zero norm", qa);
+  for (int m = 0; m < 4; ++m) {
+    hr[m][m] = st[m] / tr;
+    hi[m][m] = 0.0;
+  }
+  int k = 4;
+  for (int m = 0; m < 4; ++m)
+    for (int mp = m + 1; mp < 4; ++mp) {
+      hr[m][mp] = st[k] / tr;
+      hi[m][mp] = st[k + 1] / tr;
+      hr[mp][m] = hr[m][mp];
+      hi[mp][m] = -hi[m][mp];
+      k += 2;
+    }
+  double A[8][8], w[8], V[8][8];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      A[i][j] = hr[i][j];
+      A[i][j + 4] = -hi[i][j];
+      A[i + 4][j] = hi[i][j];
+      A[i + 4][j + 4] = hr[i][j];
+    }
+  jacobi8(A, w, V);
+  int top = 0;
+  for (int i = 1; i < 8; ++i)
+    if (w[i] > w[top]) top = i;
+  const double lam = w[top];
+  const double eps = std::min(std::max(1.0 - lam, 0.0), 0.75);
+  const Sub& S = f->subs[sa];
+  const int nq = S.nq;
+  if (!(eps <= p / 2.0 + f->tau)) {
+    log_attempt(f, qa, nq, eps, false, qb);
+    return QS_OK;
+  }
+  // phi = x + i y from the top eigenvector, unit norm, phase: its first
+  // component of magnitude above 1e-9 of the largest made real and positive
+  double phi[8], mag = 0.0, big = 0.0;
+  for (int m = 0; m < 4; ++m) {
+    phi[2 * m] = V[m][top];
+    phi[2 * m + 1] = V[m + 4][top];
+    mag += phi[2 * m] * phi[2 * m] + phi[2 * m + 1] * phi[2 * m + 1];
+  }
+  mag = std::sqrt(mag);
+  for (double& x : phi) x /= mag;
+  for (int m = 0; m < 4; ++m) big = std::max(big, std::hypot(phi[2 * m], phi[2 * m + 1]));
+  for (int m = 0; m < 4; ++m) {
+    const double r = std::hypot(phi[2 * m], phi[2 * m + 1]);
+    if (r > 1e-9 * big) {
+      const double cr = phi[2 * m] / r, ci = -phi[2 * m + 1] / r;  // conj of the unit phase
+      for (int j = 0; j < 4; ++j) {
+        const double x = phi[2 * j], y = phi[2 * j + 1];
+        phi[2 * j] = x * cr - y * ci;
+        phi[2 * j + 1] = x * ci + y * cr;
+      }
+      break;
+    }
+  }
+  // <phi|psi> has squared norm lam * tr
+  const double scale = 1.0 / std::sqrt(lam * tr);
+  void* rest = sub_alloc(f, nq - 2);
+  void* pair = sub_alloc(f, 2);
+  if (!rest || !pair) {
+    sub_free(f, nq - 2, rest);
+    sub_free(f, 2, pair);
+    return ffail(QS_E_NOMEM, "allocating the pair's subsystems");
+  }
+  e = f->dtype == QS_C64
+          ? launch_decompose_pair(static_cast<float*>(rest), static_cast<const float*>(S.amps),
+                                  nq, ta, tb, phi, scale, static_cast<float*>(pair), f->stream)
+          : launch_decompose_pair(static_cast<double*>(rest), static_cast<const double*>(S.amps),
+                                  nq, ta, tb, phi, scale, static_cast<double*>(pair), f->stream);
+  if (e != hipSuccess) {
+    sub_free(f, nq - 2, rest);
+    sub_free(f, 2, pair);
+    return dev_err(e, "pair projection");
+  }
+  Sub P;
+  P.nq = 2;
+  P.q[0] = qa;
+  P.q[1] = qb;
+  P.amps = pair;
+  Sub& T = f->subs[sa];
+  sub_free(f, T.nq, T.amps);
+  T.amps = rest;
+  int w2 = 0;
+  for (int b = 0; b < T.nq; ++b)
+    if (T.q[b] != qa && T.q[b] != qb) T.q[w2++] = T.q[b];
+  T.nq = w2;
+  for (int b = 0; b < T.nq; ++b) f->dirty |= uint64_t(1) << T.q[b];
+  f->subs.push_back(P);
+  f->F *= (1.0 - eps);
+  log_attempt(f, qa, nq, eps, true, qb);
+  *rounded = true;
+  return QS_OK;
+}
+
 namespace {
 
 // Exact tests, without the proposer, of the qubits of `mask` (skipped by the
@@ -710,9 +868,13 @@ int fact_apply(FactorState* f, const int* qubits, int k, const double* m) {
     if (int rc = queue_gate2(f, qubits, m)) return rc;
     if (f->defer) return QS_OK;
     if (int rc = launch_queue(f)) return rc;
-    if (f->policy != QS_SEP_AFTER_2Q) return QS_OK;
+    if (f->policy == QS_SEP_NONE) return QS_OK;
     int nsep = 0;
-    return fact_try_separate(f, f->p, &nsep);
+    if (int rc = fact_try_separate(f, f->p, &nsep)) return rc;
+    if (f->policy != QS_SEP_AFTER_2Q_PAIRS) return QS_OK;
+    bool paired = false;
+    if (int rc = fact_test_pair(f, qubits[0], qubits[1], f->p, &paired)) return rc;
+    return paired ? fact_try_separate(f, f->p, &nsep) : QS_OK;
   }
   if (int rc = launch_queue(f)) return rc;
   // bookkeeping for the proposal features
@@ -764,7 +926,7 @@ int fact_apply(FactorState* f, const int* qubits, int k, const double* m) {
       S.phase = ++f->phase_next;
       return QS_OK;
     }
-    if (f->policy == QS_SEP_AFTER_2Q) {
+    if (f->policy != QS_SEP_NONE) {
       int nsep = 0;
       return fact_try_separate(f, f->p, &nsep);
     }

@@ -145,6 +145,11 @@ int fact_end_run(FactorState* f, int rc);
 int fact_swap(FactorState* f, int a, int b);       // relabel
 int fact_relabel(FactorState* f, const int* pos);  // label v -> q where pos[q] = v
 int fact_try_separate(FactorState* f, double p, int* n_separated);
+// The two-qubit rounding of qubits qa, qb when they share a subsystem of three
+// or more qubits (no test otherwise): eps_B = 1 - the largest eigenvalue of
+// their reduced density matrix; at eps_B <= p/2 (+ tau) the pair becomes its
+// own subsystem (qa at bit 0) and the rest of its old subsystem is dirty.
+int fact_test_pair(FactorState* f, int qa, int qb, double p, bool* rounded);
 int fact_gather(FactorState* f, const uint64_t* idx, uint64_t m, double* out);
 int fact_norm(FactorState* f, double* out);
 // Dense copy in `dense` (2^n amplitudes of the same precision); perm_out[q]

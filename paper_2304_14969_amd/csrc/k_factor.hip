@@ -123,6 +123,9 @@ __global__ void __launch_bounds__(kBlock) k_bloch_small(const R* __restrict__ a,
 struct Bits8 {
   int b[8];
 };
+struct PairPhi {
+  double v[8];  // phi_m, m = 0..3, interleaved
+};
 
 // Adds, for every thread-owned group g = first, first + stride, ... < groups,
 // the 2^G amplitudes that differ only in the target bits (ascending in
@@ -316,6 +319,81 @@ struct MatArg4 {
   R v[32];
 };
 
+// The 4x4 reduced density matrix of the qubits at bits t1 != t2, unnormalized:
+// over the groups g of amplitudes that differ only in those bits (a_m, m =
+// bit t1 + 2 bit t2), sums of a_m conj(a_m') in float64. Row k of the output:
+// k < 4: rho_kk; then (Re, Im) of rho_01, rho_02, rho_03, rho_12, rho_13,
+// rho_23. Per workgroup in `partial` (rows of gridDim.x), or straight to
+// `out` when the launch has one workgroup.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_pair_rho(const R* __restrict__ a, uint64_t groups,
+                                                     int t1, int t2, double* __restrict__ partial,
+                                                     double* __restrict__ out) {
+  __shared__ double sh[16 * kBlock];
+  double v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = 0.0;
+  const int lo = min(t1, t2), hi = max(t1, t2);
+  for (uint64_t g = uint64_t(blockIdx.x) * kBlock + threadIdx.x; g < groups;
+       g += uint64_t(gridDim.x) * kBlock) {
+    const uint64_t base = insert_zero(insert_zero(g, lo), hi);
+    double xr[4], xi[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const uint64_t o = base | (uint64_t(m & 1) << t1) | (uint64_t(m >> 1) << t2);
+      xr[m] = a[2 * o];
+      xi[m] = a[2 * o + 1];
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] += xr[m] * xr[m] + xi[m] * xi[m];
+    int k = 4;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int mp = m + 1; mp < 4; ++mp) {
+        // a_m conj(a_mp)
+        v[k++] += xr[m] * xr[mp] + xi[m] * xi[mp];
+        v[k++] += xi[m] * xr[mp] - xr[m] * xi[mp];
+      }
+  }
+  block_sum<16>(v, sh);
+  if (threadIdx.x == 0) {
+    if (gridDim.x == 1) {
+      for (int k = 0; k < 16; ++k) out[k] = v[k];
+    } else {
+      for (int k = 0; k < 16; ++k) partial[k * gridDim.x + blockIdx.x] = v[k];
+    }
+  }
+}
+
+// b[u] = scale * sum_m conj(phi_m) a[u with bits t1, t2 set to m] (m = bit t1
+// + 2 bit t2), u over the indices with the two bits removed; and the pair's
+// own subsystem `pair` = phi (4 amplitudes, bit 0 = t1's qubit).
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_decompose_pair(R* __restrict__ b,
+                                                           const R* __restrict__ a,
+                                                           uint64_t count, int t1, int t2,
+                                                           PairPhi phi, double scale,
+                                                           R* __restrict__ pair) {
+  const int lo = min(t1, t2), hi = max(t1, t2);
+  for (uint64_t u = uint64_t(blockIdx.x) * kBlock + threadIdx.x; u < count;
+       u += uint64_t(gridDim.x) * kBlock) {
+    const uint64_t base = insert_zero(insert_zero(u, lo), hi);
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const uint64_t o = base | (uint64_t(m & 1) << t1) | (uint64_t(m >> 1) << t2);
+      const double x = a[2 * o], y = a[2 * o + 1];
+      const double pr = phi.v[2 * m], pi = phi.v[2 * m + 1];
+      re += pr * x + pi * y;  // conj(phi_m) a
+      im += pr * y - pi * x;
+    }
+    b[2 * u] = static_cast<R>(re * scale);
+    b[2 * u + 1] = static_cast<R>(im * scale);
+  }
+  if (blockIdx.x == 0 && threadIdx.x < 8) pair[threadIdx.x] = static_cast<R>(phi.v[threadIdx.x]);
+}
+
 // One workgroup per operation (see FactOp). The merge-and-gate form computes
 // the composed amplitudes as k_compose does and the 4x4 product as the
 // two-qubit argument-matrix kernel does, in the same order.
@@ -464,6 +542,35 @@ hipError_t launch_fact_1q_batch(const Fact1qItem<R>* items, int nitems, const Fa
 }
 
 template <typename R>
+hipError_t launch_pair_rho(const R* a, int nq, int t1, int t2, double* scratch, double* out,
+                           hipStream_t s) {
+  if (nq < 2 || t1 == t2 || t1 < 0 || t2 < 0 || t1 >= nq || t2 >= nq) return hipErrorInvalidValue;
+  const uint64_t groups = uint64_t(1) << (nq - 2);
+  if ((groups << 2) <= 2 * kSmallPairs) {
+    hipLaunchKernelGGL(k_pair_rho<R>, dim3(1), dim3(kBlock), 0, s, a, groups, t1, t2, nullptr,
+                       out);
+    return hipGetLastError();
+  }
+  const unsigned nb = red_blocks(groups);
+  hipLaunchKernelGGL(k_pair_rho<R>, dim3(nb), dim3(kBlock), 0, s, a, groups, t1, t2, scratch + 8,
+                     nullptr);
+  hipLaunchKernelGGL(k_sum_rows<16>, dim3(1), dim3(kBlock), 0, s, scratch + 8, int(nb), out);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_decompose_pair(R* b, const R* a, int nq, int t1, int t2, const double phi[8],
+                                 double scale, R* pair, hipStream_t s) {
+  if (nq < 3 || t1 == t2 || t1 < 0 || t2 < 0 || t1 >= nq || t2 >= nq) return hipErrorInvalidValue;
+  PairPhi ph;
+  for (int i = 0; i < 8; ++i) ph.v[i] = phi[i];
+  const uint64_t count = uint64_t(1) << (nq - 2);
+  hipLaunchKernelGGL(k_decompose_pair<R>, dim3(blocks_for(count)), dim3(kBlock), 0, s, b, a,
+                     count, t1, t2, ph, scale, pair);
+  return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_merge_gate(R* c, const R* a, int na, const R* b, int nb, int t0, int t1,
                              const double m[32], hipStream_t s) {
   if (na < 1 || nb < 0 || na + nb < 2 || t0 == t1 || t0 < 0 || t1 < 0 || t0 >= na + nb ||
@@ -528,6 +635,10 @@ hipError_t launch_gather_mul(const R* a, const uint64_t* idx, uint64_t m, Perm64
   template hipError_t launch_store_single<R>(R*, const double*, hipStream_t);               \
   template hipError_t launch_bloch_batch<R>(const BlochItem<R>*, int, double*, hipStream_t); \
   template hipError_t launch_fact_ops<R>(const FactOp<R>*, int, hipStream_t);               \
+  template hipError_t launch_pair_rho<R>(const R*, int, int, int, double*, double*,         \
+                                         hipStream_t);                                      \
+  template hipError_t launch_decompose_pair<R>(R*, const R*, int, int, int, const double*,  \
+                                               double, R*, hipStream_t);                    \
   template hipError_t launch_merge_gate<R>(R*, const R*, int, const R*, int, int, int,      \
                                            const double*, hipStream_t);                     \
   template hipError_t launch_fact_1q_batch<R>(const Fact1qItem<R>*, int, const Fact1qGate<R>*, int, \

@@ -102,6 +102,18 @@ hipError_t launch_bloch(const R* a, int nq, int t, double* scratch, double* out,
 template <typename R>
 hipError_t launch_bloch_multi(const R* a, int nq, const int* bits, int G, double* scratch,
                               double* out, hipStream_t s);
+// Two-qubit rounding: the unnormalized 4x4 reduced density matrix of the
+// qubits at bits t1 != t2 of a subsystem of nq >= 2 qubits, in float64, to
+// out[16] (rho_00..rho_33, then Re/Im of rho_01, 02, 03, 12, 13, 23; index m
+// = bit t1 + 2 bit t2); scratch as for launch_bloch.
+template <typename R>
+hipError_t launch_pair_rho(const R* a, int nq, int t1, int t2, double* scratch, double* out,
+                           hipStream_t s);
+// b (nq - 2 qubits) = scale * <phi| a over bits t1, t2 (the two bits removed,
+// the others in order), and pair (2 qubits) = phi; nq >= 3.
+template <typename R>
+hipError_t launch_decompose_pair(R* b, const R* a, int nq, int t1, int t2, const double phi[8],
+                                 double scale, R* pair, hipStream_t s);
 // The Bloch sums of several subsystems in one launch, one workgroup each:
 // item i reads 2^nq amplitudes (nq <= kBlochBatchQubits) and writes, for each
 // of its G (1..5) target bits (ascending, distinct, < nq), the four sums

@@ -1,0 +1,140 @@
+"""Two-qubit rounding on the GPU against the FP64 oracle (the reading of the
+generalization noted in Sec. III-A, in oracle/factor.py): eps_B of explicit
+pair tests, decision replays of runs with the pair policy (both precisions),
+and a pair inside a subsystem past the one-workgroup bound."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import dense, factor
+from parity import C64, C128, assert_parity
+
+pytestmark = pytest.mark.gpu
+NEAR = 1e-5
+
+
+def oracle_after(n, gates):
+    st = factor.FactorizedState(n)
+    for g in gates:
+        st.apply_gate(g)
+    st.dirty.clear()
+    return st
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_explicit_pair_tests_match_the_oracle(qs_lib, dtype):
+    """A weakly entangled pair: H(0), CX(0,2), qubits 1, 3, 4 entangled, then a
+    small rotation of qubit 1 controlled by qubit 2 and two U3 gates; eps_B of
+    (0, 2) and of other pairs, rounded at a p just above it and not at a p
+    just below, against the oracle's eigh-based value and state."""
+    qs = qs_lib
+    n = 5
+    ry = lambda t: dense.u3(t, 0.0, 0.0)  # noqa: E731
+    gates = [("h", 0), ("cx", 0, 2), ("h", 3), ("cz", 3, 4), ("cx", 4, 1),
+             ("mat", [2, 1], dense.controlled_matrix(1, 1, ry(0.35))),
+             ("u3", 1, 0.2, 0.3, 0.1), ("u3", 4, 0.7, 0.1, 0.4)]
+    tol = 1e-6 if dtype == C64 else 1e-12
+    for qa, qb in ((0, 2), (2, 0), (1, 3), (0, 4)):
+        ost = oracle_after(n, gates)
+        si, ta = ost.where(qa)
+        sj, tb = ost.where(qb)
+        if si != sj or len(ost.subs[si].qubits) < 3:
+            continue
+        S = ost.subs[si]
+        rho = factor.pair_density(S.amps, len(S.qubits), ta, tb)
+        w = np.linalg.eigvalsh(rho)
+        if w[-1] - w[-2] < 1e-6 or 2 * w[-1] < 1.0 + 1e-3:
+            continue  # a degenerate top eigenvalue has no unique projection
+        eps, _ = factor.pair_dominant(rho)
+        for p, want in ((2 * eps + 1e-4, True), (max(2 * eps - 1e-4, 0.0), False)):
+            st = qs.State(n, dtype, factorized=True)
+            st.record_attempts()
+            st.run(qs.Circuit(n).add_gates(gates))
+            got = st.try_separate_pair(qa, qb, p)
+            att = st.attempts()[-1]
+            assert len(att) == 5 and att[4] == qb and att[0] == qa
+            assert abs(att[2] - eps) <= tol, (qa, qb, att, eps)
+            assert got == want
+            o = oracle_after(n, gates)
+            o.test_pair(qa, qb, p)
+            assert abs(st.fidelity_estimate() - o.F) <= tol
+            assert sorted(map(sorted, st.subsystems())) == sorted(sorted(s.qubits) for s in o.subs)
+            assert_parity(st.amplitudes(), o.expand(), dtype, f"pair ({qa},{qb}) p={p}")
+            st.free()
+
+
+def replay_pairs(n, gates, p, attempts, eps_tol):
+    it = iter(attempts)
+    seen = []
+
+    def decide(q, nsub, eps, rule):
+        g = next(it)
+        assert (g[0], g[1]) == (q, nsub), f"attempt {len(seen)}: gpu {g[:2]} oracle {(q, nsub)}"
+        assert abs(g[2] - eps) <= eps_tol, (len(seen), g, eps)
+        seen.append(g)
+        if abs(eps - p / 2) < NEAR:
+            return g[3]
+        assert g[3] == rule, (len(seen), g, eps, p)
+        return rule
+
+    ost = factor.FactorizedState(n, decide=decide)
+    ost.run(gates, p, pairs=True)
+    assert next(it, None) is None, "GPU made more attempts than the oracle"
+    for g, o in zip(seen, ost.log):
+        assert (len(g) == 5) == (o.pair >= 0) and (len(g) < 5 or g[4] == o.pair)
+    return ost
+
+
+@pytest.mark.parametrize("dtype,n,layers,p,seed", [(C64, 12, 6, 0.2, 1), (C64, 14, 6, 0.3, 2),
+                                                   (C128, 12, 6, 0.25, 3)])
+def test_pair_policy_replay(qs_lib, dtype, n, layers, p, seed):
+    qs = qs_lib
+    gates = workloads.random_circuit(n, layers, seed)
+    st = qs.State(n, dtype, factorized=True)
+    st.set_policy(qs.SEP_AFTER_2Q_PAIRS, p)
+    st.record_attempts()
+    st.run(qs.Circuit(n).add_gates(gates))
+    att = st.attempts()
+    assert any(len(a) == 5 for a in att)
+    ost = replay_pairs(n, gates, p, att, 2e-5 if dtype == C64 else 1e-10)
+    assert abs(st.fidelity_estimate() - ost.F) <= 1e-5 * max(ost.F, 1e-3) + 1e-7
+    assert sorted(len(s) for s in st.subsystems()) == ost.sizes()
+    assert_parity(st.amplitudes(), ost.expand(), dtype, f"pairs n={n} p={p}")
+    st.free()
+
+
+def test_pair_in_a_large_subsystem(qs_lib):
+    """An 18-qubit subsystem (past the one-workgroup bound): the pair density
+    goes through partial sums; eps_B and the projected ket match the oracle."""
+    qs = qs_lib
+    n = 18
+    g = np.random.default_rng(8)
+    gates = [("h", q) for q in range(n)] + [("cz", q, q + 1) for q in range(n - 1)]
+    gates += [("u3", q, *g.uniform(0, 2 * math.pi, 3)) for q in range(n)]
+    ost = oracle_after(n, gates)
+    S = ost.subs[ost.where(5)[0]]
+    eps, _ = factor.pair_dominant(factor.pair_density(S.amps, n, S.qubits.index(5),
+                                                      S.qubits.index(6)))
+    st = qs.State(n, C64, factorized=True)
+    st.record_attempts()
+    st.run(qs.Circuit(n).add_gates(gates))
+    assert st.try_separate_pair(5, 6, 1.0) == (eps <= 0.5)
+    assert abs(st.attempts()[-1][2] - eps) < 1e-6
+    ost.test_pair(5, 6, 1.0)
+    assert_parity(st.amplitudes(), ost.expand(), C64, "pair in 18 qubits")
+    st.free()
+
+
+def test_pair_argument_errors(qs_lib):
+    qs = qs_lib
+    st = qs.State(4, C64, factorized=True)
+    for qa, qb in ((0, 0), (-1, 2), (1, 4)):
+        with pytest.raises(qs.QSError):
+            st.try_separate_pair(qa, qb, 0.5)
+    assert st.try_separate_pair(0, 1, 1.0) is False  # different subsystems: no test
+    with qs.State(4, C64) as d:
+        with pytest.raises(qs.QSError):
+            d.try_separate_pair(0, 1, 0.5)
+    st.free()
