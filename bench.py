@@ -197,6 +197,42 @@ def bench_approx(qs, workloads, protocol, np, family: str, p_cmp: float = 0.6,
     return out
 
 
+def bench_pairs(qs, workloads, np, torch, n: int = 54, layers: int = 7, seeds=range(5)) -> dict:
+    """Entangled pairs weakly coupled along a chain (the workload of the
+    two-qubit rounding): the one-qubit schedule against the pair policy at
+    several thresholds, amplitude cap 2^30."""
+    out = {"workload": f"{n}-qubit chain of entangled pairs, {layers} layers (U3, weak controlled "
+                       "RY between neighbouring pairs, CNOT inside pairs), complex64, cap 2^30"}
+    for name, policy, p in (("single_p0.05", qs.SEP_AFTER_2Q, 0.05),
+                            ("single_p0.1", qs.SEP_AFTER_2Q, 0.1),
+                            ("single_p0.2", qs.SEP_AFTER_2Q, 0.2),
+                            ("pairs_p0.05", qs.SEP_AFTER_2Q_PAIRS, 0.05),
+                            ("pairs_p0.1", qs.SEP_AFTER_2Q_PAIRS, 0.1)):
+        rows = []
+        for s in seeds:
+            st = qs.State(n, qs.C64, factorized=True, max_amps=2 ** 30)
+            st.set_policy(policy, p)
+            c = qs.Circuit(n).add_gates(workloads.pair_chain_circuit(n, layers, s))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ok = True
+            try:
+                st.run(c)
+            except qs.CapacityError:
+                ok = False
+            torch.cuda.synchronize()
+            rows.append({"ok": ok, "t": time.perf_counter() - t0, "F": st.fidelity_estimate(),
+                         "max_sub": max(len(x) for x in st.subsystems())})
+            st.free()
+            c.free()
+        ok = [r for r in rows if r["ok"]]
+        out[name] = {"completed": len(ok), "of": len(rows),
+                     "time_s_median": round(float(np.median([r["t"] for r in rows])), 5),
+                     "F_mean": round(float(np.mean([r["F"] for r in ok])), 4) if ok else None,
+                     "max_sub_max": max(r["max_sub"] for r in rows)}
+    return out
+
+
 def bench_batch(qs, workloads, torch, count: int = 1024, seed: int = 300, depth: int = 8) -> dict:
     """Many small random circuits (12-20 qubits) in one arena: batched tile
     passes (one launch per pass index over all kets), batched fused blocks
@@ -276,7 +312,7 @@ def main() -> int:
     ap.add_argument("--quick", action="store_true",
                     help="only the QFT (skip the circuit, approximate, batch and validation runs)")
     ap.add_argument("--section", action="append", default=[],
-                    choices=["circuit", "approx", "batch", "validation"],
+                    choices=["circuit", "approx", "pairs", "batch", "validation"],
                     help="run only these secondary sections (repeatable; default: all)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy one 1-GiB device buffer into another three times (the known-size "
@@ -409,12 +445,14 @@ def main() -> int:
     if not args.quick:
         from paper_2304_14969_amd import protocol
         sec = {}
-        want = set(args.section) or {"circuit", "approx", "batch", "validation"}
+        want = set(args.section) or {"circuit", "approx", "pairs", "batch", "validation"}
         if "circuit" in want:
             sec["circuit_n32"] = bench_circuit(qs, workloads, torch)
         if "approx" in want:
             for fam in ("grid", "matching"):
                 sec[f"approx54_{fam}"] = bench_approx(qs, workloads, protocol, np, fam)
+        if "pairs" in want:
+            sec["pair_chain54"] = bench_pairs(qs, workloads, np, torch)
         if "batch" in want:
             sec["batch1024"] = bench_batch(qs, workloads, torch)
         if "validation" in want:

@@ -300,7 +300,10 @@ enum {
   QS_GATE_CZ = 6, QS_GATE_ISWAP = 7,
   QS_GATE_CP = 8,     /* params = {theta}: e^{i theta} on |11> */
   QS_GATE_SWAP = 9, QS_GATE_CX = 10, QS_GATE_CY = 11,
-  QS_GATE_AX = 12, QS_GATE_AY = 13, QS_GATE_AZ = 14
+  QS_GATE_AX = 12, QS_GATE_AY = 13, QS_GATE_AZ = 14,
+  QS_GATE_CU3 = 15    /* qubits {control, target}, params = {theta, phi, lambda,
+                         v}: U3 on the target when the control equals v (1, or
+                         0 for an anti-control), identity otherwise */
 };
 
 /* Empty circuit on n qubits (1 <= n <= 64). */

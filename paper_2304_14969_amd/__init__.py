@@ -219,7 +219,7 @@ def mat_arg(m, k: int) -> np.ndarray:
 
 
 GATE = {"h": 1, "x": 2, "y": 3, "z": 4, "u3": 5, "cz": 6, "iswap": 7, "cp": 8, "swap": 9,
-        "cx": 10, "cy": 11, "ax": 12, "ay": 13, "az": 14}
+        "cx": 10, "cy": 11, "ax": 12, "ay": 13, "az": 14, "cu3": 15}
 
 
 class Circuit:
@@ -258,7 +258,8 @@ class Circuit:
                                                         _dptr(mat_arg(m, len(qubits)))))
 
     def add_gates(self, gates):
-        """workloads gate tuples: h, u3, cp, cz, iswap, swap, mat."""
+        """workloads gate tuples: h, u3, cp, cz, iswap, swap, cx-type, mat, and
+        ctrl with one control (a controlled U3)."""
         for g in gates:
             k = g[0]
             if k == "h":
@@ -271,6 +272,9 @@ class Circuit:
                 self.add(k, [g[1], g[2]])
             elif k == "mat":
                 self.add_matrix(list(g[1]), g[2])
+            elif k == "ctrl" and len(g[1]) == 1:
+                # ("ctrl", [c], cval, t, theta, phi, lam): controlled U3
+                self.add("cu3", [g[1][0], g[3]], [g[4], g[5], g[6], float(g[2] & 1)])
             else:
                 raise ValueError(f"gate {k!r} has no circuit form")
         return self

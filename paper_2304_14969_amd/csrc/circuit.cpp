@@ -77,6 +77,11 @@ bool gate_matrix(int kind, int nq, const double* p, std::vector<cd>* m, int* k_o
     case QS_GATE_AX: k = 2; *m = controlled(X, 0); break;
     case QS_GATE_AY: k = 2; *m = controlled(Y, 0); break;
     case QS_GATE_AZ: k = 2; *m = controlled(Z, 0); break;
+    case QS_GATE_CU3:
+      if (p[3] != 0.0 && p[3] != 1.0) return false;
+      k = 2;
+      *m = controlled(u3(p[0], p[1], p[2]), int(p[3]));
+      break;
     default: return false;
   }
   if (nq != k) return false;
@@ -471,11 +476,13 @@ int qs_circuit_add_gate(qs_circuit* c, int kind, const int* qubits, const double
   if (!c) return cfail(QS_E_INVAL, "circuit is NULL");
   if (!qubits) return cfail(QS_E_INVAL, "qubits is NULL");
   const int nq = (kind >= QS_GATE_CZ) ? 2 : 1;
-  if ((kind == QS_GATE_U3 || kind == QS_GATE_CP) && !params)
+  if ((kind == QS_GATE_U3 || kind == QS_GATE_CP || kind == QS_GATE_CU3) && !params)
     return cfail(QS_E_INVAL, "gate kind %d needs parameters", kind);
-  if (kind == QS_GATE_U3)
+  if (kind == QS_GATE_U3 || kind == QS_GATE_CU3)
     for (int i = 0; i < 3; ++i)
       if (!std::isfinite(params[i])) return cfail(QS_E_INVAL, "non-finite parameter");
+  if (kind == QS_GATE_CU3 && params[3] != 0.0 && params[3] != 1.0)
+    return cfail(QS_E_INVAL, "control value %g is not 0 or 1", params[3]);
   if (kind == QS_GATE_CP && !std::isfinite(params[0])) return cfail(QS_E_INVAL, "non-finite parameter");
   std::vector<qs::cd> m;
   int k = 0;

@@ -105,6 +105,26 @@ def test_pair_policy_replay(qs_lib, dtype, n, layers, p, seed):
     st.free()
 
 
+@pytest.mark.parametrize("p,seed", [(0.05, 3), (0.1, 4)])
+def test_pair_chain_replay(qs_lib, p, seed):
+    """The workload the pair rounding is for: entangled pairs weakly coupled
+    along a chain; the GPU repeats the oracle's decisions, pairs are split off."""
+    qs = qs_lib
+    n = 12
+    gates = workloads.pair_chain_circuit(n, 5, seed)
+    st = qs.State(n, C64, factorized=True)
+    st.set_policy(qs.SEP_AFTER_2Q_PAIRS, p)
+    st.record_attempts()
+    st.run(qs.Circuit(n).add_gates(gates))
+    att = st.attempts()
+    assert sum(1 for a in att if len(a) == 5 and a[3]) > 0
+    ost = replay_pairs(n, gates, p, att, 2e-5)
+    assert abs(st.fidelity_estimate() - ost.F) <= 1e-5 * ost.F + 1e-7
+    assert sorted(len(s) for s in st.subsystems()) == ost.sizes()
+    assert_parity(st.amplitudes(), ost.expand(), C64, f"pair chain p={p}")
+    st.free()
+
+
 def test_pair_in_a_large_subsystem(qs_lib):
     """An 18-qubit subsystem (past the one-workgroup bound): the pair density
     goes through partial sums; eps_B and the projected ket match the oracle."""

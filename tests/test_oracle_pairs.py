@@ -139,3 +139,22 @@ def test_pair_policy_run_invariants():
     st0 = factor.FactorizedState(10).run(gates, 0.0, pairs=True)
     exact = dense.run_circuit(dense.zero_state(10), 10, gates)
     assert abs(abs(np.vdot(st0.expand(), exact)) - 1) < 1e-10
+
+
+def test_pair_chain_is_what_pairs_are_for():
+    """Entangled pairs weakly coupled along a chain (workloads.pair_chain_circuit):
+    each pair qubit is far from a product state, so the one-qubit rounding at
+    p = 0.05 lets the chain merge into one subsystem, while the two-qubit
+    rounding splits every pair off; F stays the product of 1 - eps."""
+    import workloads
+    gates = workloads.pair_chain_circuit(12, 5, 3)
+    single = factor.FactorizedState(12).run(gates, 0.05)
+    pairs = factor.FactorizedState(12).run(gates, 0.05, pairs=True)
+    assert max(single.sizes()) == 12
+    assert pairs.sizes() == [2] * 6
+    assert sum(1 for a in pairs.log if a.pair >= 0 and a.rounded) > 0
+    prod = 1.0
+    for a in pairs.log:
+        if a.rounded:
+            prod *= 1 - a.eps
+    assert abs(pairs.F - prod) < 1e-12 and 0.9 < pairs.F < 1.0

@@ -166,3 +166,28 @@ def grid_circuit(rows: int, cols: int, layers: int, seed: int) -> list:
                 a, b = b, a
             gates.append((kind, a, b))
     return gates
+
+
+def pair_chain_circuit(n: int, layers: int, seed: int, theta_max: float = 0.3) -> list:
+    """Entangled pairs (2k, 2k+1) weakly coupled along a chain: first H on
+    every even qubit and a CNOT into its partner; then per layer a U3 on every
+    qubit (angles uniform in [0, 2 pi)), the CNOT inside pair 0, and for k = 0,
+    2, 4, ...: a controlled RY(theta) from qubit k+1 to k+2 (theta uniform in
+    [0, theta_max)) followed by the CNOT inside the pair (k+2, k+3). The pairs
+    stay strongly entangled inside and weakly with each other: the workload of
+    the two-qubit rounding (n even)."""
+    if n % 2:
+        raise ValueError("pair chains need an even number of qubits")
+    g = rng(seed)
+    cx = lambda c, t: ("ctrl", [c], 1, t, math.pi, 0.0, math.pi)  # noqa: E731  U3(pi,0,pi) = X
+    gates = []
+    for k in range(0, n, 2):
+        gates += [("h", k), cx(k, k + 1)]
+    for _ in range(layers):
+        ang = g.uniform(0.0, TWO_PI, (n, 3))
+        gates += [("u3", q, float(ang[q, 0]), float(ang[q, 1]), float(ang[q, 2])) for q in range(n)]
+        th = g.uniform(0.0, theta_max, n // 2)
+        gates.append(cx(0, 1))
+        for k in range(0, n - 2, 2):
+            gates += [("ctrl", [k + 1], 1, k + 2, float(th[k // 2]), 0.0, 0.0), cx(k + 2, k + 3)]
+    return gates
