@@ -135,7 +135,12 @@ int qs_apply_fused(qs_state* st, const int* qubits, int k, const double* m);
 
 /* Quantum Fourier transform (Eq. dft, omega = e^{+2 pi i / N}) on qubits
  * start .. start+len-1, including the final bit reversal (done as a
- * relabelling). inverse != 0 applies the inverse transform. */
+ * relabelling). inverse != 0 applies the inverse transform. Dense states run
+ * multi-stage passes; factorized states run the QFT circuit gate by gate
+ * (H, then the controlled phases of each stage, then the reversing SWAPs as
+ * relabels; the inverse reversed with negated angles) under the state's
+ * separation policy, where the Z-eigenstate shortcut keeps a basis input a
+ * product state. */
 int qs_qft(qs_state* st, int start, int len, int inverse);
 
 /* ------------------------------------------------------------ approximate mode (Sec. III) */
@@ -282,6 +287,16 @@ int qs_set_feature_log(qs_state* st, float* buf, uint64_t cap);
 /* Number of exact tests skipped on the network's advice and of deferred
  * qubits tested by the capacity fallback, since the state was created. */
 int qs_proposer_stats(const qs_state* st, uint64_t* skipped, uint64_t* fallback_tests);
+
+/* Unobservable shortcut (Sec. II-B, "factor.unobservable"): a multi-qubit
+ * gate on a factorized state whose operand is a one-qubit subsystem in a Z
+ * eigenstate (a float64 host copy of its amplitudes puts at most 1e-24 of the
+ * weight on the other basis state) that the gate keeps (every matrix entry
+ * from that value to the other is exactly zero) is restricted to that value:
+ * a controlled gate on |0> disappears, on |1> it acts on its target alone, a
+ * controlled phase becomes a phase gate; no merge happens and no test is
+ * due. *count receives the number of operands dropped so far. */
+int qs_shortcut_count(const qs_state* st, uint64_t* count);
 
 /* ------------------------------------------------------------ circuits */
 
@@ -436,6 +451,8 @@ int qs_check(qs_state* st, double tol);
  *                    measures the lowest dirty qubit together with the next
  *                    dirty qubits of its subsystem (up to 5, none skipped) in
  *                    one sweep; 0: one sweep per qubit. Same decisions;
+ *   "factor.unobservable" 1 (default): the Z-eigenstate shortcut described at
+ *                    qs_shortcut_count; 0: every gate merges its operands;
  *   "factor.defer"   1 (default): in qs_run on a factorized state with the
  *                    plain schedule after every multi-qubit gate (no
  *                    proposer, no feature log), the tests due after a gate

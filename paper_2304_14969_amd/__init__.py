@@ -117,6 +117,7 @@ _SIGS = [
     ("qs_try_separate", C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_int)]),
     ("qs_try_separate_pair", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_double,
                                        C.POINTER(C.c_int)]),
+    ("qs_shortcut_count", C.c_int, [C.c_void_p, C.POINTER(C.c_uint64)]),
     ("qs_mark_dirty", C.c_int, [C.c_void_p, C.c_uint64]),
     ("qs_fidelity_estimate", C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     ("qs_subsystems", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
@@ -619,6 +620,12 @@ class State:
         _check(self.lib, self.lib.qs_try_separate_pair(self.h, int(qa), int(qb), float(p),
                                                        C.byref(r)))
         return bool(r.value)
+
+    def shortcut_count(self) -> int:
+        """Operands dropped by the Z-eigenstate shortcut so far."""
+        v = C.c_uint64()
+        _check(self.lib, self.lib.qs_shortcut_count(self.h, C.byref(v)))
+        return v.value
 
     def mark_dirty(self, mask: int):
         _check(self.lib, self.lib.qs_mark_dirty(self.h, int(mask)))

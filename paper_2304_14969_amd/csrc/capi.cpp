@@ -2,6 +2,7 @@
 // map and dispatch to the HIP kernels. No simulation arithmetic happens here
 // beyond building small gate matrices and twiddle tables on the host in
 // float64 and rounding them once to the state's precision.
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -309,6 +310,9 @@ int qs_tune_set(const char* key, int64_t value) {
   } else if (!std::strcmp(key, "factor.tile_1q")) {
     if (value < 0 || value > 1) return fail(QS_E_INVAL, "factor.tile_1q must be 0 or 1");
     qs::g_tile_1q = int(value);
+  } else if (!std::strcmp(key, "factor.unobservable")) {
+    if (value < 0 || value > 1) return fail(QS_E_INVAL, "factor.unobservable must be 0 or 1");
+    qs::g_unobservable = int(value);
   } else if (!std::strcmp(key, "factor.defer")) {
     if (value < 0 || value > 1) return fail(QS_E_INVAL, "factor.defer must be 0 or 1");
     qs::g_defer_sep = int(value);
@@ -335,6 +339,7 @@ int qs_tune_get(const char* key, int64_t* value) {
   else if (!std::strcmp(key, "factor.multi_test")) *value = qs::g_multi_test;
   else if (!std::strcmp(key, "factor.batch_1q")) *value = qs::g_batch_1q;
   else if (!std::strcmp(key, "factor.defer")) *value = qs::g_defer_sep;
+  else if (!std::strcmp(key, "factor.unobservable")) *value = qs::g_unobservable;
   else if (!std::strcmp(key, "factor.tile_1q")) *value = qs::g_tile_1q;
   else if (!std::strcmp(key, "tile.mfma")) *value = g_tile_mfma;
   else if (!std::strcmp(key, "qft.col_max")) *value = g_qft_tune.col_max;
@@ -653,11 +658,45 @@ int qs_apply_fused(qs_state* st, const int* qubits, int k, const double* m) {
   return device_error(st, e, "apply_fused");
 }
 
+// The QFT circuit gate by gate on a factorized state: for j from the top of
+// the range down, H(j) then CP(m, j, pi / 2^(j - m)) for m from j - 1 down,
+// then the reversing SWAPs (relabels); the inverse is the reversed sequence
+// with negated angles. With the Z-eigenstate shortcut a basis input stays a
+// product state (every CP has a control still in a Z eigenstate).
+int qft_factorized(qs_state* st, int start, int len, int inverse) {
+  qs_circuit* c = nullptr;
+  if (int rc = qs_circuit_create(st->n, &c)) return rc;
+  struct G {
+    int kind, a, b;
+    double th;
+  };
+  std::vector<G> seq;
+  for (int j = start + len - 1; j >= start; --j) {
+    seq.push_back({QS_GATE_H, j, 0, 0.0});
+    for (int m = j - 1; m >= start; --m)
+      seq.push_back({QS_GATE_CP, m, j, M_PI / std::ldexp(1.0, j - m)});
+  }
+  for (int i = 0; i < len / 2; ++i) seq.push_back({QS_GATE_SWAP, start + i, start + len - 1 - i, 0.0});
+  if (inverse) {
+    std::reverse(seq.begin(), seq.end());
+    for (auto& g : seq) g.th = -g.th;
+  }
+  int rc = QS_OK;
+  for (const auto& g : seq) {
+    const int q[2] = {g.a, g.b};
+    rc = qs_circuit_add_gate(c, g.kind, q, &g.th);
+    if (rc) break;
+  }
+  if (rc == QS_OK) rc = qs_run(st, c);
+  qs_circuit_free(c);
+  return rc;
+}
+
 int qs_qft(qs_state* st, int start, int len, int inverse) {
   if (int rc = check_state(st)) return rc;
-  if (st->fact) return fail(QS_E_UNSUPPORTED, "the QFT runs on dense states");
   if (start < 0 || len < 1 || start + len > st->n)
     return fail(QS_E_INVAL, "qubit range [%d, %d) outside [0, %d)", start, start + len, st->n);
+  if (st->fact) return qft_factorized(st, start, len, inverse);
   // natural order, bit-reversed (left by an earlier transform), or anything
   // else, which is first moved back to the identity labelling
   bool identity = true, reversed = true;
@@ -1052,6 +1091,13 @@ int qs_set_feature_log(qs_state* st, float* buf, uint64_t cap) {
   if (!st->fact) return fail(QS_E_UNSUPPORTED, "features belong to factorized states");
   st->fact->feat_log = buf;
   st->fact->feat_cap = buf ? cap : 0;
+  return QS_OK;
+}
+
+int qs_shortcut_count(const qs_state* st, uint64_t* count) {
+  if (int rc = check_state(st)) return rc;
+  if (!count) return fail(QS_E_INVAL, "count is NULL");
+  *count = st->fact ? st->fact->shortcuts : 0;
   return QS_OK;
 }
 

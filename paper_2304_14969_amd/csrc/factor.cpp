@@ -36,6 +36,7 @@ int g_multi_test = 1;
 int g_batch_1q = 1;
 int g_defer_sep = 1;
 int g_tile_1q = 1;
+int g_unobservable = 1;
 
 void* device_alloc(size_t bytes);
 void device_free(void* p);
@@ -120,6 +121,8 @@ int new_single(FactorState* f, int q, const double amp[4], Sub* out) {
   Sub s;
   s.nq = 1;
   s.q[0] = q;
+  s.known = true;
+  for (int i = 0; i < 4; ++i) s.h[i] = amp[i];
   s.amps = sub_alloc(f, 1);
   if (!s.amps) return ffail(QS_E_NOMEM, "allocating a one-qubit subsystem");
   const hipError_t e = f->dtype == QS_C64
@@ -271,6 +274,8 @@ int decide_qubit(FactorState* f, int q, int si, int t, const double st[4], doubl
   if (f->defer) {  // queued: the projection and the new subsystem in one operation
     single.nq = 1;
     single.q[0] = q;
+    single.known = true;
+    for (int i = 0; i < 4; ++i) single.h[i] = phi[i];
     single.amps = sub_alloc(f, 1);
     if (!single.amps) {
       sub_free(f, S.nq - 1, rest);
@@ -305,6 +310,7 @@ int decide_qubit(FactorState* f, int q, int si, int t, const double st[4], doubl
   const int nsub = S.nq;
   sub_free(f, S.nq, S.amps);
   S.amps = rest;
+  S.known = false;
   for (int b = t; b + 1 < S.nq; ++b) S.q[b] = S.q[b + 1];
   S.nq -= 1;
   for (int b = 0; b < S.nq; ++b) f->dirty |= uint64_t(1) << S.q[b];
@@ -711,6 +717,7 @@ int fact_test_pair(FactorState* f, int qa, int qb, double p, bool* rounded) {
   Sub& T = f->subs[sa];
   sub_free(f, T.nq, T.amps);
   T.amps = rest;
+  T.known = false;
   int w2 = 0;
   for (int b = 0; b < T.nq; ++b)
     if (T.q[b] != qa && T.q[b] != qb) T.q[w2++] = T.q[b];
@@ -804,7 +811,96 @@ int queue_gate2(FactorState* f, const int* qubits, const double* m) {
 
 }  // namespace
 
+namespace {
+
+// h <- m h for the host copy of a one-qubit subsystem (m: 2x2, interleaved).
+void mirror_1q(Sub& S, const double* m) {
+  if (S.nq != 1 || !S.known) return;
+  const double a0r = S.h[0], a0i = S.h[1], a1r = S.h[2], a1i = S.h[3];
+  S.h[0] = m[0] * a0r - m[1] * a0i + m[2] * a1r - m[3] * a1i;
+  S.h[1] = m[0] * a0i + m[1] * a0r + m[2] * a1i + m[3] * a1r;
+  S.h[2] = m[4] * a0r - m[5] * a0i + m[6] * a1r - m[7] * a1i;
+  S.h[3] = m[4] * a0i + m[5] * a0r + m[6] * a1i + m[7] * a1r;
+}
+
+// Is qubit q a one-qubit subsystem in a Z eigenstate (up to a relative weight
+// of 1e-24 on the other basis state)? *v receives the eigenvalue's bit.
+bool z_eigenstate(const FactorState* f, int q, int* v) {
+  const int si = find(f, q, nullptr);
+  if (si < 0) return false;
+  const Sub& S = f->subs[si];
+  if (S.nq != 1 || !S.known) return false;
+  const double p0 = S.h[0] * S.h[0] + S.h[1] * S.h[1], p1 = S.h[2] * S.h[2] + S.h[3] * S.h[3];
+  if (p1 <= 1e-24 * (p0 + p1)) {
+    *v = 0;
+    return true;
+  }
+  if (p0 <= 1e-24 * (p0 + p1)) {
+    *v = 1;
+    return true;
+  }
+  return false;
+}
+
+// Restricts the k-qubit gate m (2^k x 2^k, interleaved) to value v of its
+// local bit j, if the gate keeps that value (every entry from a column with
+// bit j = v to a row with bit j != v is exactly zero): out is the (k-1)-qubit
+// gate on the other bits, in order. False (out untouched) otherwise.
+bool restrict_gate(const std::vector<double>& m, int k, int j, int v, std::vector<double>* out) {
+  const int d = 1 << k;
+  for (int r = 0; r < d; ++r) {
+    if (((r >> j) & 1) == v) continue;
+    for (int c = 0; c < d; ++c)
+      if (((c >> j) & 1) == v && (m[2 * (r * d + c)] != 0.0 || m[2 * (r * d + c) + 1] != 0.0))
+        return false;
+  }
+  const int dr = d / 2;
+  auto ins = [j, v](int x) {
+    const int lo = x & ((1 << j) - 1);
+    return lo | (v << j) | ((x >> j) << (j + 1));
+  };
+  out->assign(size_t(2) * dr * dr, 0.0);
+  for (int r = 0; r < dr; ++r)
+    for (int c = 0; c < dr; ++c) {
+      const size_t src = size_t(ins(r)) * d + ins(c);
+      (*out)[2 * (r * dr + c)] = m[2 * src];
+      (*out)[2 * (r * dr + c) + 1] = m[2 * src + 1];
+    }
+  return true;
+}
+
+bool is_identity(const std::vector<double>& m, int k) {
+  const int d = 1 << k;
+  for (int r = 0; r < d; ++r)
+    for (int c = 0; c < d; ++c)
+      if (m[2 * (r * d + c)] != (r == c ? 1.0 : 0.0) || m[2 * (r * d + c) + 1] != 0.0) return false;
+  return true;
+}
+
+}  // namespace
+
 int fact_apply(FactorState* f, const int* qubits, int k, const double* m) {
+  // unobservable shortcut (Sec. II-B): operands in a Z eigenstate that the
+  // gate keeps are dropped from it, so they need no merge
+  if (k >= 2 && g_unobservable) {
+    int qq[QS_MAX_FUSED], kq = k;
+    for (int j = 0; j < k; ++j) qq[j] = qubits[j];
+    std::vector<double> mm(m, m + (size_t(2) << (2 * k))), red;
+    bool changed = false;
+    for (int j = 0; j < kq && kq > 1;) {
+      int v = 0;
+      if (z_eigenstate(f, qq[j], &v) && restrict_gate(mm, kq, j, v, &red)) {
+        mm.swap(red);
+        for (int t = j; t + 1 < kq; ++t) qq[t] = qq[t + 1];
+        --kq;
+        changed = true;
+        ++f->shortcuts;
+        continue;
+      }
+      ++j;
+    }
+    if (changed) return is_identity(mm, kq) ? QS_OK : fact_apply(f, qq, kq, mm.data());
+  }
   // deferred tests on the subsystems this gate touches come first
   if (f->defer && f->dirty && touches_dirty(f, qubits, k))
     if (int rc = flush_pending(f)) return rc;
@@ -900,6 +996,7 @@ int fact_apply(FactorState* f, const int* qubits, int k, const double* m) {
       if (S.q[b] == qubits[j]) local[j] = b;
   hipError_t e;
   if (k == 1) {
+    mirror_1q(S, m);
     if (f->dtype == QS_C64) {
       Mat2<float> mm;
       for (int i = 0; i < 4; ++i) { mm.re[i] = float(m[2 * i]); mm.im[i] = float(m[2 * i + 1]); }
@@ -1281,6 +1378,7 @@ int apply_1q_run(FactorState* f, const int* qubits, const double* m, int count) 
     int t = 0;
     const int si = find(f, qubits[i], &t);
     if (si < 0) return ffail(QS_E_INVAL, "qubit %d not found", qubits[i]);
+    mirror_1q(f->subs[si], m + 8 * i);
     if (f->subs[si].nq > kFact1qMaxQubits) {
       if (large_of[si] < 0) {
         large_of[si] = int(per_large.size());

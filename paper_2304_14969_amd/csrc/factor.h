@@ -17,6 +17,11 @@ struct Sub {
   void* amps = nullptr;  // 2^nq amplitudes, device, owned
   uint64_t phase = 0;    // deferred separation: the gate its dirty qubits wait on
   bool plain = false;    // deferred separation: exact tests without the proposer
+  // one-qubit subsystems: a float64 host copy of the two amplitudes when they
+  // are known (set at creation from host values, kept through one-qubit
+  // gates); it decides the Z-eigenstate shortcuts
+  bool known = false;
+  double h[4] = {0, 0, 0, 0};
 };
 
 struct FactorState {
@@ -104,6 +109,7 @@ struct FactorState {
   int propose_min = 2;           // smallest subsystem scored by the network
   uint64_t deferred = 0;        // dirty qubits skipped on the network's advice
   uint64_t skipped = 0, fallback_tests = 0;
+  uint64_t shortcuts = 0;  // operands dropped by the Z-eigenstate shortcut
   float* feat_log = nullptr;
   uint64_t feat_cap = 0;
 };
@@ -120,6 +126,11 @@ extern int g_defer_sep;
 // Process-wide: one-qubit runs on subsystems of more than 2^12 amplitudes as
 // tile passes (1, default) or one launch per gate (0).
 extern int g_tile_1q;
+// Process-wide: the unobservable shortcuts (1, default): a multi-qubit gate
+// whose operand is a one-qubit subsystem in a Z eigenstate that the gate
+// keeps is restricted to that value (a controlled gate on |0> disappears, on
+// |1> it becomes a gate on the target), so no merge happens; 0: off.
+extern int g_unobservable;
 
 // The 32 proposal features of qubit q (threshold p) from the bookkeeping.
 void fact_features(const FactorState* f, int q, double p, float* out);
