@@ -658,12 +658,62 @@ int qs_apply_fused(qs_state* st, const int* qubits, int k, const double* m) {
   return device_error(st, e, "apply_fused");
 }
 
+// The multi-stage passes of the QFT on bits [start, start + len) of a dense
+// vector of nq qubits at amps (the state's own or a subsystem's), stored in
+// natural or bit-reversed order; no relabelling.
+int qft_passes(qs_state* st, void* amps, int nq, int start, int len, bool reversed, int inverse) {
+  qs::QftPass plan[64];
+  const int np = st->dtype == QS_C64
+                     ? qs::qft_plan<float>(nq, start, len, reversed, g_qft_tune, plan, 64)
+                     : qs::qft_plan<double>(nq, start, len, reversed, g_qft_tune, plan, 64);
+  if (np < 0) return fail(QS_E_UNSUPPORTED, "QFT pass plan failed");
+  const int sign = inverse ? -1 : 1;
+  static const char* kind_names[3][9] = {
+      {"qft_lds", "qft_lds", "qft_lds", "qft_lds", "qft_lds", "qft_lds", "qft_lds", "qft_lds",
+       "qft_lds"},
+      {"", "qft_col1", "qft_col2", "qft_col3", "qft_col4", "qft_col5", "qft_col6", "qft_col7",
+       "qft_col8"},
+      {"", "qft_reg1", "qft_reg2", "qft_reg3", "qft_reg4", "qft_reg5", "", "", ""}};
+  for (int k = 0; k < np; ++k) {
+    const int g = plan[k].kind == qs::QftPass::LDS ? 0 : plan[k].hi - plan[k].lo;
+    ProfScope ps(st, kind_names[plan[k].kind][g <= 8 ? g : 0],
+                 2.0 * std::ldexp(1.0, nq) * ab(st));
+    hipError_t e =
+        st->dtype == QS_C64
+            ? qs::launch_qft_pass(static_cast<float*>(amps), nq, start, len, plan[k], sign,
+                                  reversed, g_qft_tune, st->stream)
+            : qs::launch_qft_pass(static_cast<double*>(amps), nq, start, len, plan[k], sign,
+                                  reversed, g_qft_tune, st->stream);
+    if (int rc = device_error(st, e, "qft pass")) return rc;
+  }
+  return QS_OK;
+}
+
 // The QFT circuit gate by gate on a factorized state: for j from the top of
 // the range down, H(j) then CP(m, j, pi / 2^(j - m)) for m from j - 1 down,
 // then the reversing SWAPs (relabels); the inverse is the reversed sequence
 // with negated angles. With the Z-eigenstate shortcut a basis input stays a
 // product state (every CP has a control still in a Z eigenstate).
 int qft_factorized(qs_state* st, int start, int len, int inverse) {
+  // With no separation policy (an exact run) and the whole range inside one
+  // subsystem as a block of consecutive local bits (ascending, or descending
+  // as a previous transform leaves it), the gate sequence equals the dense
+  // multi-stage passes on that subsystem's buffer, then the reversal as a
+  // relabelling of the block.
+  int t0 = 0;
+  bool descending = false;
+  qs::FactorState* f = st->fact;
+  if (f->policy == QS_SEP_NONE) {
+    const int si = qs::fact_block(f, start, len, &t0, &descending);
+    if (si >= 0) {
+      if (int rc = fact_rc(st, qs::fact_sync(f))) return rc;
+      qs::Sub& S = f->subs[si];
+      if (int rc = qft_passes(st, S.amps, S.nq, t0, len, descending, inverse)) return rc;
+      for (int i = 0; i < len / 2; ++i) std::swap(S.q[t0 + i], S.q[t0 + len - 1 - i]);
+      S.known = false;
+      return QS_OK;
+    }
+  }
   qs_circuit* c = nullptr;
   if (int rc = qs_circuit_create(st->n, &c)) return rc;
   struct G {
@@ -710,30 +760,7 @@ int qs_qft(qs_state* st, int start, int len, int inverse) {
   } else if (identity) {
     reversed = false;
   }
-  qs::QftPass plan[64];
-  const int np = st->dtype == QS_C64
-                     ? qs::qft_plan<float>(st->n, start, len, reversed, g_qft_tune, plan, 64)
-                     : qs::qft_plan<double>(st->n, start, len, reversed, g_qft_tune, plan, 64);
-  if (np < 0) return fail(QS_E_UNSUPPORTED, "QFT pass plan failed");
-  const int sign = inverse ? -1 : 1;
-  static const char* kind_names[3][9] = {
-      {"qft_lds", "qft_lds", "qft_lds", "qft_lds", "qft_lds", "qft_lds", "qft_lds", "qft_lds",
-       "qft_lds"},
-      {"", "qft_col1", "qft_col2", "qft_col3", "qft_col4", "qft_col5", "qft_col6", "qft_col7",
-       "qft_col8"},
-      {"", "qft_reg1", "qft_reg2", "qft_reg3", "qft_reg4", "qft_reg5", "", "", ""}};
-  for (int k = 0; k < np; ++k) {
-    const int g = plan[k].kind == qs::QftPass::LDS ? 0 : plan[k].hi - plan[k].lo;
-    ProfScope ps(st, kind_names[plan[k].kind][g <= 8 ? g : 0],
-                 2.0 * std::ldexp(1.0, st->n) * ab(st));
-    hipError_t e =
-        st->dtype == QS_C64
-            ? qs::launch_qft_pass(static_cast<float*>(st->amps), st->n, start, len, plan[k], sign,
-                                  reversed, g_qft_tune, st->stream)
-            : qs::launch_qft_pass(static_cast<double*>(st->amps), st->n, start, len, plan[k], sign,
-                                  reversed, g_qft_tune, st->stream);
-    if (int rc = device_error(st, e, "qft pass")) return rc;
-  }
+  if (int rc = qft_passes(st, st->amps, st->n, start, len, reversed, inverse)) return rc;
   // final bit reversal of the range, as a relabelling
   for (int i = 0; i < len / 2; ++i) std::swap(st->perm[start + i], st->perm[start + len - 1 - i]);
   return QS_OK;

@@ -1465,6 +1465,24 @@ int fact_apply_1q_run(FactorState* f, const int* qubits, const double* m, int co
                             : apply_1q_run<double>(f, qubits, m, count);
 }
 
+int fact_block(const FactorState* f, int start, int len, int* t0, bool* descending) {
+  if (len < 2) return -1;
+  int ta = 0, tb = 0;
+  const int si = find(f, start, &ta);
+  if (si < 0 || find(f, start + len - 1, &tb) != si) return -1;
+  const Sub& S = f->subs[si];
+  const bool up = tb == ta + len - 1, down = ta == tb + len - 1;
+  if (!up && !down) return -1;
+  const int lo = up ? ta : tb;
+  for (int i = 0; i < len; ++i)
+    if (S.q[lo + i] != (up ? start + i : start + len - 1 - i)) return -1;
+  *t0 = lo;
+  *descending = down;
+  return si;
+}
+
+int fact_sync(FactorState* f) { return launch_queue(f); }
+
 void fact_begin_run(FactorState* f) {
   f->defer = g_defer_sep && f->policy == QS_SEP_AFTER_2Q && !f->dirty;
   f->prop = 0;

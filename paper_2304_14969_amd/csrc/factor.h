@@ -153,6 +153,12 @@ int fact_apply_1q_run(FactorState* f, const int* qubits, const double* m, int co
 // unless rc is a device error), else its own status.
 void fact_begin_run(FactorState* f);
 int fact_end_run(FactorState* f, int rc);
+// The subsystem holding qubits start .. start+len-1 at consecutive local bits
+// t0 .. t0+len-1, in ascending (qubit start at t0) or descending order, with
+// len >= 2; -1 if there is none.
+int fact_block(const FactorState* f, int start, int len, int* t0, bool* descending);
+// Launches whatever is queued (device buffers are then current on the stream).
+int fact_sync(FactorState* f);
 int fact_swap(FactorState* f, int a, int b);       // relabel
 int fact_relabel(FactorState* f, const int* pos);  // label v -> q where pos[q] = v
 int fact_try_separate(FactorState* f, double p, int* n_separated);

@@ -110,3 +110,27 @@ def test_qft_of_entangled_factorized_states(qs_lib, dtype):
             want = dense.run_circuit(ket, n, dense.qft_gates(n, start, length, inverse))
             assert_parity(st.amplitudes(), want, dtype, f"qft [{start},{start + length}) inv={inverse}")
             st.free()
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_qft_twice_on_a_ghz_subsystem(qs_lib, dtype):
+    """GHZ built by a CNOT chain lies in one subsystem with its qubits at
+    ascending local bits: the factorized QFT runs the dense passes on that
+    buffer; the second transform finds the block descending (the relabelled
+    reversal of the first) and runs the passes in the other orientation."""
+    qs = qs_lib
+    n = 14
+    gates = [("h", 0)] + [("cx", q, q + 1) for q in range(n - 1)]
+    ket = dense.run_circuit(dense.zero_state(n), n, gates)
+    st = qs.State(n, dtype, factorized=True)
+    st.run(qs.Circuit(n).add_gates(gates))
+    st.profile_start()
+    st.qft()
+    want = dense.qft(ket, n)
+    assert_parity(st.amplitudes(), want, dtype, "qft of ghz")
+    st.qft(2, 9, inverse=True)
+    prof = st.profile_stop()
+    assert any(k.startswith("qft_") for k in prof), prof
+    want = dense.run_circuit(want, n, dense.qft_gates(n, 2, 9, True))
+    assert_parity(st.amplitudes(), want, dtype, "inverse qft on a sub-range")
+    st.free()
