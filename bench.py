@@ -233,6 +233,44 @@ def bench_pairs(qs, workloads, np, torch, n: int = 54, layers: int = 7, seeds=ra
     return out
 
 
+def bench_qft_factorized(qs, workloads, np, torch) -> dict:
+    """QFT on factorized states (the inputs of Fig. 1): |0...0> and basis
+    states, which the Z-eigenstate shortcut keeps a product of one-qubit
+    subsystems, and a GHZ state, whose single subsystem runs the dense passes."""
+    out = {"workload": "QFT on factorized complex64 states: |0...0>, |x> (x from the seed), GHZ"}
+    for n in (27, 63):
+        for kind in ("zero", "basis"):
+            ts = []
+            for rep in range(5):
+                st = qs.State(n, qs.C64, factorized=True)
+                if kind == "basis":
+                    st.set_basis(workloads.basis_index(n, rep))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st.qft()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+                nsub = len(st.subsystems())
+                st.free()
+            out[f"{kind}_n{n}"] = {"ms_median": round(float(np.median(ts[1:])) * 1e3, 3),
+                                   "subsystems_after": nsub}
+    n = 27
+    ts = []
+    for rep in range(3):
+        st = qs.State(n, qs.C64, factorized=True)
+        c = qs.Circuit(n).add_gates([("h", 0)] + [("cx", q, q + 1) for q in range(n - 1)])
+        st.run(c)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.qft()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+        st.free()
+        c.free()
+    out[f"ghz_n{n}"] = {"ms_median": round(float(np.median(ts)) * 1e3, 3)}
+    return out
+
+
 def bench_batch(qs, workloads, torch, count: int = 1024, seed: int = 300, depth: int = 8) -> dict:
     """Many small random circuits (12-20 qubits) in one arena: batched tile
     passes (one launch per pass index over all kets), batched fused blocks
@@ -312,7 +350,7 @@ def main() -> int:
     ap.add_argument("--quick", action="store_true",
                     help="only the QFT (skip the circuit, approximate, batch and validation runs)")
     ap.add_argument("--section", action="append", default=[],
-                    choices=["circuit", "approx", "pairs", "batch", "validation"],
+                    choices=["circuit", "approx", "pairs", "qft_factorized", "batch", "validation"],
                     help="run only these secondary sections (repeatable; default: all)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy one 1-GiB device buffer into another three times (the known-size "
@@ -445,7 +483,8 @@ def main() -> int:
     if not args.quick:
         from paper_2304_14969_amd import protocol
         sec = {}
-        want = set(args.section) or {"circuit", "approx", "pairs", "batch", "validation"}
+        want = set(args.section) or {"circuit", "approx", "pairs", "qft_factorized", "batch",
+                                     "validation"}
         if "circuit" in want:
             sec["circuit_n32"] = bench_circuit(qs, workloads, torch)
         if "approx" in want:
@@ -453,6 +492,8 @@ def main() -> int:
                 sec[f"approx54_{fam}"] = bench_approx(qs, workloads, protocol, np, fam)
         if "pairs" in want:
             sec["pair_chain54"] = bench_pairs(qs, workloads, np, torch)
+        if "qft_factorized" in want:
+            sec["qft_factorized"] = bench_qft_factorized(qs, workloads, np, torch)
         if "batch" in want:
             sec["batch1024"] = bench_batch(qs, workloads, torch)
         if "validation" in want:
