@@ -227,15 +227,18 @@ int merge(FactorState* f, int ia, int ib, int* out) {
 // The outcome of one test: bookkeeping for the proposal features, then the
 // log entry and the fidelity factor (Eq. fid_model), held back while deferred
 // tests run so that they follow the order of the gates.
-void record(FactorState* f, int q, int nsub, double eps, bool rounded) {
-  note_test_impl(f, q, eps, rounded);
+void record(FactorState* f, int q, int nsub, double eps, bool rounded, int partner = -1) {
+  if (partner < 0) note_test_impl(f, q, eps, rounded);
   if (f->flushing) {
-    f->pend.push_back({f->cur_phase, q, nsub, eps, rounded});
-    if (f->feat_log) f->pend_feat.insert(f->pend_feat.end(), f->cur_feat, f->cur_feat + QS_MLP_INPUTS);
+    f->pend.push_back({f->cur_phase, q, nsub, eps, rounded, partner});
+    if (f->feat_log) {
+      if (partner >= 0) std::fill(f->cur_feat, f->cur_feat + QS_MLP_INPUTS, 0.0f);
+      f->pend_feat.insert(f->pend_feat.end(), f->cur_feat, f->cur_feat + QS_MLP_INPUTS);
+    }
     return;
   }
   if (rounded) f->F *= (1.0 - eps);
-  log_attempt(f, q, nsub, eps, rounded);
+  log_attempt(f, q, nsub, eps, rounded, partner);
 }
 
 // The decision on qubit q at bit t of subsystem si from its Bloch sums
@@ -614,24 +617,13 @@ int fact_largest(const FactorState* f) {
   return m;
 }
 
-int fact_test_pair(FactorState* f, int qa, int qb, double p, bool* rounded) {
+// The two-qubit decision on qa (bit ta) and qb (bit tb) of subsystem sa from
+// the unnormalized pair density sums st[16] (layout of launch_pair_rho).
+int decide_pair(FactorState* f, int sa, int qa, int qb, int ta, int tb, const double* st, double p,
+                bool* rounded) {
   *rounded = false;
-  int ta = 0, tb = 0;
-  const int sa = find(f, qa, &ta), sb = find(f, qb, &tb);
-  if (sa < 0 || sb < 0 || qa == qb) return ffail(QS_E_INVAL, "bad pair (%d, %d)", qa, qb);
-  if (sa != sb || f->subs[sa].nq < 3) return QS_OK;  // nothing to split off
-  if (int rc = launch_queue(f)) return rc;
-  const Sub& S0 = f->subs[sa];
-  hipError_t e = f->dtype == QS_C64
-                     ? launch_pair_rho(static_cast<const float*>(S0.amps), S0.nq, ta, tb,
-                                       f->scratch, f->dstat, f->stream)
-                     : launch_pair_rho(static_cast<const double*>(S0.amps), S0.nq, ta, tb,
-                                       f->scratch, f->dstat, f->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
-  if (int rc = dev_err(e, "pair density")) return rc;
   // H = rho (unnormalized), index m = bit ta + 2 bit tb
   double hr[4][4], hi[4][4];
-  const double* st = f->hstat;
   const double tr = st[0] + st[1] + st[2] + st[3];
   if (!(tr > 0.0)) return ffail(QS_E_NUMERIC, "subsystem of qubit %d has zero norm", qa);
   for (int m = 0; m < 4; ++m) {
@@ -664,7 +656,7 @@ int fact_test_pair(FactorState* f, int qa, int qb, double p, bool* rounded) {
   const Sub& S = f->subs[sa];
   const int nq = S.nq;
   if (!(eps <= p / 2.0 + f->tau)) {
-    log_attempt(f, qa, nq, eps, false, qb);
+    record(f, qa, nq, eps, false, qb);
     return QS_OK;
   }
   // phi = x + i y from the top eigenvector, unit norm, phase: its first
@@ -699,7 +691,7 @@ int fact_test_pair(FactorState* f, int qa, int qb, double p, bool* rounded) {
     sub_free(f, 2, pair);
     return ffail(QS_E_NOMEM, "allocating the pair's subsystems");
   }
-  e = f->dtype == QS_C64
+  const hipError_t e = f->dtype == QS_C64
           ? launch_decompose_pair(static_cast<float*>(rest), static_cast<const float*>(S.amps),
                                   nq, ta, tb, phi, scale, static_cast<float*>(pair), f->stream)
           : launch_decompose_pair(static_cast<double*>(rest), static_cast<const double*>(S.amps),
@@ -724,10 +716,29 @@ int fact_test_pair(FactorState* f, int qa, int qb, double p, bool* rounded) {
   T.nq = w2;
   for (int b = 0; b < T.nq; ++b) f->dirty |= uint64_t(1) << T.q[b];
   f->subs.push_back(P);
-  f->F *= (1.0 - eps);
-  log_attempt(f, qa, nq, eps, true, qb);
+  record(f, qa, nq, eps, true, qb);
   *rounded = true;
   return QS_OK;
+}
+
+int fact_test_pair(FactorState* f, int qa, int qb, double p, bool* rounded) {
+  *rounded = false;
+  int ta = 0, tb = 0;
+  const int sa = find(f, qa, &ta), sb = find(f, qb, &tb);
+  if (sa < 0 || sb < 0 || qa == qb) return ffail(QS_E_INVAL, "bad pair (%d, %d)", qa, qb);
+  if (sa != sb || f->subs[sa].nq < 3) return QS_OK;  // nothing to split off
+  if (int rc = launch_queue(f)) return rc;
+  const Sub& S0 = f->subs[sa];
+  hipError_t e = f->dtype == QS_C64
+                     ? launch_pair_rho(static_cast<const float*>(S0.amps), S0.nq, ta, tb,
+                                       f->scratch, f->dstat, f->stream)
+                     : launch_pair_rho(static_cast<const double*>(S0.amps), S0.nq, ta, tb,
+                                       f->scratch, f->dstat, f->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+  if (int rc = dev_err(e, "pair density")) return rc;
+  double st[16];
+  for (int i = 0; i < 16; ++i) st[i] = f->hstat[i];
+  return decide_pair(f, sa, qa, qb, ta, tb, st, p, rounded);
 }
 
 namespace {
@@ -806,6 +817,10 @@ int queue_gate2(FactorState* f, const int* qubits, const double* m) {
   }
   for (int j = 0; j < 2; ++j) f->dirty |= uint64_t(1) << qubits[j];
   S.phase = ++f->phase_next;
+  if (f->policy == QS_SEP_AFTER_2Q_PAIRS) {  // its pair test follows its one-qubit tests
+    S.pend_a = qubits[0];
+    S.pend_b = qubits[1];
+  }
   return QS_OK;
 }
 
@@ -1019,7 +1034,7 @@ int fact_apply(FactorState* f, const int* qubits, int k, const double* m) {
   if (int rc = dev_err(e, "factorized gate")) return rc;
   if (k >= 2) {
     for (int j = 0; j < k; ++j) f->dirty |= uint64_t(1) << qubits[j];
-    if (f->policy == QS_SEP_AFTER_2Q && f->defer) {
+    if (f->policy != QS_SEP_NONE && f->defer) {
       S.phase = ++f->phase_next;
       return QS_OK;
     }
@@ -1051,6 +1066,12 @@ int ring_slot(FactorState* f, void** host, void** dev) {
   return i;
 }
 
+uint64_t sub_mask(const Sub& S) {
+  uint64_t m = 0;
+  for (int b = 0; b < S.nq; ++b) m |= uint64_t(1) << S.q[b];
+  return m;
+}
+
 bool touches_dirty(const FactorState* f, const int* qubits, int k) {
   for (int j = 0; j < k; ++j) {
     const int si = find(f, qubits[j], nullptr);
@@ -1071,8 +1092,8 @@ template <typename R>
 int flush_round(FactorState* f, bool* any) {
   if (int rc = launch_queue(f)) return rc;  // the sweeps read the queued results
   struct Item {
-    int si, G;
-    int q[kMultiTest], t[kMultiTest];  // ascending qubit number
+    int si, G;                         // G = 0: the subsystem's pending pair test
+    int q[kMultiTest], t[kMultiTest];  // ascending qubit number (pair: q[0..1], t[0..1])
   };
   // learned schedule: the subsystems of at least propose_min qubits (not
   // under a plain retest) send their unscored dirty qubits to the network;
@@ -1113,6 +1134,28 @@ int flush_round(FactorState* f, bool* any) {
         qd[nd] = S.q[b];
         td[nd++] = b;
       }
+    if (!nd && S.pend_a >= 0 && !(f->dirty & sub_mask(S))) {
+      // the one-qubit tests are done: the pair test its gate made due, when
+      // both operands still share this subsystem of three or more qubits
+      int ta = -1, tb = -1;
+      for (int b = 0; b < S.nq; ++b) {
+        if (S.q[b] == S.pend_a) ta = b;
+        if (S.q[b] == S.pend_b) tb = b;
+      }
+      if (ta >= 0 && tb >= 0 && S.nq >= 3) {
+        Item it{};
+        it.si = si;
+        it.G = 0;
+        it.q[0] = S.pend_a;
+        it.q[1] = S.pend_b;
+        it.t[0] = ta;
+        it.t[1] = tb;
+        items.push_back(it);
+      } else {
+        f->subs[si].pend_a = f->subs[si].pend_b = -1;
+      }
+      continue;
+    }
     if (!nd) continue;
     if (S.nq == 1) {  // nothing to separate from
       f->dirty &= ~(uint64_t(1) << S.q[0]);
@@ -1140,6 +1183,7 @@ int flush_round(FactorState* f, bool* any) {
   int bits[64][kMultiTest], pos[64][kMultiTest];
   for (size_t i = 0; i < items.size(); ++i) {
     const Item& it = items[i];
+    if (it.G == 0) continue;
     int o[kMultiTest];
     for (int j = 0; j < it.G; ++j) o[j] = j;
     std::sort(o, o + it.G, [&](int x, int y) { return it.t[x] < it.t[y]; });
@@ -1153,7 +1197,7 @@ int flush_round(FactorState* f, bool* any) {
   int slot = -1, nsmall = 0;
   for (size_t i = 0; i < items.size(); ++i) {
     const Sub& S = f->subs[items[i].si];
-    if (S.nq > kBlochBatchQubits) continue;
+    if (items[i].G == 0 || S.nq > kBlochBatchQubits) continue;
     if (slot < 0) {
       slot = ring_slot(f, &host, &dev);
       if (slot < 0) return slot;
@@ -1173,8 +1217,13 @@ int flush_round(FactorState* f, bool* any) {
   }
   for (size_t i = 0; i < items.size() && e == hipSuccess; ++i) {
     const Sub& S = f->subs[items[i].si];
-    if (S.nq <= kBlochBatchQubits) continue;
     const R* a = static_cast<const R*>(S.amps);
+    if (items[i].G == 0) {
+      e = launch_pair_rho(a, S.nq, items[i].t[0], items[i].t[1], f->scratch, f->dstat + i * kRow,
+                          f->stream);
+      continue;
+    }
+    if (S.nq <= kBlochBatchQubits) continue;
     e = items[i].G == 1
             ? launch_bloch(a, S.nq, bits[i][0], f->scratch, f->dstat + i * kRow, f->stream)
             : launch_bloch_multi(a, S.nq, bits[i], items[i].G, f->scratch, f->dstat + i * kRow,
@@ -1186,6 +1235,14 @@ int flush_round(FactorState* f, bool* any) {
   for (size_t i = 0; i < items.size(); ++i) {
     const Item& it = items[i];
     f->cur_phase = f->subs[it.si].phase;
+    if (it.G == 0) {
+      f->subs[it.si].pend_a = f->subs[it.si].pend_b = -1;
+      bool rounded = false;
+      if (int rc = decide_pair(f, it.si, it.q[0], it.q[1], it.t[0], it.t[1], f->hstat + i * kRow,
+                               f->p, &rounded))
+        return rc;
+      continue;
+    }
     for (int j = 0; j < it.G; ++j) {
       const double* st = f->hstat + i * kRow + 4 * pos[i][j];
       const double sums[4] = {st[0], st[1], st[2], st[3]};
@@ -1266,7 +1323,7 @@ int launch_queue(FactorState* f) {
 int flush_pending(FactorState* f) {
   f->flushing = true;
   int rc = QS_OK;
-  for (bool any = true; any && f->dirty && rc == QS_OK;)
+  for (bool any = true; any && rc == QS_OK;)  // until no test (one-qubit or pair) is due
     rc = f->dtype == QS_C64 ? flush_round<float>(f, &any) : flush_round<double>(f, &any);
   if (rc == QS_OK) rc = launch_queue(f);  // the last projections
   f->flushing = false;
@@ -1282,7 +1339,7 @@ int flush_pending(FactorState* f) {
       std::memcpy(f->feat_log + *f->log_count * QS_MLP_INPUTS, &f->pend_feat[i * QS_MLP_INPUTS],
                   QS_MLP_INPUTS * sizeof(float));
     if (d.rounded) f->F *= (1.0 - d.eps);
-    log_attempt(f, d.q, d.nsub, d.eps, d.rounded);
+    log_attempt(f, d.q, d.nsub, d.eps, d.rounded, d.partner);
   }
   f->pend.clear();
   f->pend_feat.clear();
@@ -1484,7 +1541,8 @@ int fact_block(const FactorState* f, int start, int len, int* t0, bool* descendi
 int fact_sync(FactorState* f) { return launch_queue(f); }
 
 void fact_begin_run(FactorState* f) {
-  f->defer = g_defer_sep && f->policy == QS_SEP_AFTER_2Q && !f->dirty;
+  f->defer = g_defer_sep &&
+             (f->policy == QS_SEP_AFTER_2Q || f->policy == QS_SEP_AFTER_2Q_PAIRS) && !f->dirty;
   f->prop = 0;
 }
 

@@ -17,6 +17,7 @@ struct Sub {
   void* amps = nullptr;  // 2^nq amplitudes, device, owned
   uint64_t phase = 0;    // deferred separation: the gate its dirty qubits wait on
   bool plain = false;    // deferred separation: exact tests without the proposer
+  int pend_a = -1, pend_b = -1;  // deferred pair policy: the pair test its gate made due
   // one-qubit subsystems: a float64 host copy of the two amplitudes when they
   // are known (set at creation from host values, kept through one-qubit
   // gates); it decides the Z-eigenstate shortcuts
@@ -55,6 +56,7 @@ struct FactorState {
     int q, nsub;
     double eps;
     bool rounded;
+    int partner;  // a pair attempt's second qubit, else -1
   };
   bool defer = false;
   bool flushing = false;

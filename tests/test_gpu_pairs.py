@@ -170,3 +170,35 @@ def test_pair_argument_errors(qs_lib):
         with pytest.raises(qs.QSError):
             d.try_separate_pair(0, 1, 0.5)
     st.free()
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_deferred_pair_tests_keep_the_sequence(qs_lib, dtype):
+    """With tests deferred, a subsystem's pair test waits behind its one-qubit
+    tests and shares the round's launch with other subsystems' sweeps; the
+    log (one- and two-qubit attempts), F and the subsystems equal those of
+    testing right after every gate."""
+    qs = qs_lib
+    n = 14
+    out = {}
+    saved = qs.tune_get("factor.defer")
+    try:
+        for defer in (0, 1):
+            qs.tune_set("factor.defer", defer)
+            rows = []
+            for gates, p in ((workloads.pair_chain_circuit(n, 5, 7), 0.05),
+                             (workloads.random_circuit(n, 6, 9), 0.3)):
+                st = qs.State(n, dtype, factorized=True)
+                st.set_policy(qs.SEP_AFTER_2Q_PAIRS, p)
+                st.record_attempts()
+                st.run(qs.Circuit(n).add_gates(gates))
+                rows.append((st.attempts(), st.fidelity_estimate(),
+                             sorted(sorted(x) for x in st.subsystems()), st.amplitudes()))
+                st.free()
+            out[defer] = rows
+    finally:
+        qs.tune_set("factor.defer", saved)
+    for a, b in zip(out[0], out[1]):
+        assert any(len(x) == 5 for x in a[0])
+        assert a[0] == b[0] and a[1] == b[1] and a[2] == b[2]
+        assert np.abs(a[3] - b[3]).max() <= (1e-12 if dtype == C128 else 1e-6)
