@@ -110,3 +110,50 @@ def train_proposer(X, y, steps: int = 3000, batch: int = 256, lr: float = 3e-3,
     pos = np.sort(net.forward(X[y > 0.5]))
     cutoff = float(pos[int(np.floor((1.0 - recall) * len(pos)))]) if len(pos) else 0.5
     return net, cutoff, loss
+
+
+# width x depth sets of the fidelity-model validation (Appendix: Table of RMSE
+# per subset), with the grid each width is laid out on (a line for 19)
+VALIDATION_SETS = ((6, 6), (12, 6), (18, 6), (12, 12), (18, 12), (18, 18), (15, 15), (19, 10))
+VALIDATION_GRIDS = {6: (2, 3), 12: (3, 4), 15: (3, 5), 18: (3, 6), 19: (1, 19)}
+
+
+def validation_grid(make_circuit, sets=VALIDATION_SETS, circuits: int = 10, step: float = 0.025,
+                    seed0: int = 20000, dtype: int = C64) -> dict:
+    """The fidelity model against the gold standard (Appendix, Eq. rmse):
+    for every width x depth set, `circuits` circuits from
+    make_circuit(rows, cols, depth, seed) on that width's grid; each runs once
+    exactly (dense) and once in the approximate mode for every p on 0, step,
+    ..., 1, and each run is one observation (F, F_exact = |<approx|exact>|^2).
+    Returns the RMSE per set and overall, the observation count and the mean
+    signed error F - F_exact."""
+    import math
+
+    ps = [round(k * step, 10) for k in range(int(round(1.0 / step)) + 1)]
+    per_set, all_err = {}, []
+    for width, depth in sets:
+        rows, cols = VALIDATION_GRIDS[width]
+        errs = []
+        for c in range(circuits):
+            gates = make_circuit(rows, cols, depth, seed0 + 1000 * width + 100 * depth + c)
+            circ = Circuit(width).add_gates(gates)
+            exact = State(width, dtype)
+            exact.run(circ)
+            approx = State(width, dtype)
+            for p in ps:
+                st = State(width, dtype, factorized=True)
+                st.set_policy(SEP_AFTER_2Q, p)
+                st.run(circ)
+                st.expand_into(approx)
+                fx = abs(approx.inner(exact)) ** 2
+                errs.append(st.fidelity_estimate() - fx)
+                st.free()
+            approx.free()
+            exact.free()
+            circ.free()
+        per_set[f"{width}x{depth}"] = round(math.sqrt(sum(e * e for e in errs) / len(errs)), 5)
+        all_err += errs
+    return {"rmse_per_set": per_set,
+            "rmse_overall": round(math.sqrt(sum(e * e for e in all_err) / len(all_err)), 5),
+            "mean_err": round(sum(all_err) / len(all_err), 5),
+            "observations": len(all_err), "circuits_per_set": circuits, "p_step": step}
