@@ -318,6 +318,40 @@ def bench_batch(qs, workloads, torch, count: int = 1024, seed: int = 300, depth:
     return out
 
 
+def bench_depth_sweep(workloads, protocol, circuits: int = 10) -> dict:
+    """Fig. 3's experiment: 54 qubits on the 6x9 grid, depths 1 to 10, the
+    mean fidelity estimate at the smallest p that completes (cap 2^30)."""
+    t0 = time.perf_counter()
+    depths = {}
+    for d in range(1, 11):
+        depths.update(protocol.depth_sweep(workloads.grid_circuit, 6, 9, [d], circuits))
+        print(f"depth sweep: depth {d} done, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
+    return {"workload": f"54-qubit 6x9 grid, paper's family, {circuits} circuits per depth, "
+                        "descending-p search, cap 2^30 amplitudes, complex64",
+            "depths": depths, "wall_s": round(time.perf_counter() - t0, 1)}
+
+
+def bench_heat_maps(workloads, protocol, circuits: int = 5) -> dict:
+    """The appendix heat maps: mean fidelity estimate over p and depth at
+    widths 25 (5x5), 36 (6x6) and 49 (7x7)."""
+    t0 = time.perf_counter()
+    ps = [round(0.1 * k, 3) for k in range(0, 11)]
+    out = {"workload": f"paper's family on 5x5, 6x6, 7x7 grids, depths 1-14, p 0 ... 1 step 0.1, "
+                       f"{circuits} circuits per cell, cap 2^30, complex64"}
+    for rows in (5, 6, 7):
+        F, fails = {}, {}
+        for d in range(1, 15):
+            r = protocol.heat_map(workloads.grid_circuit, rows, rows, [d], ps, circuits)
+            F.update(r["F_mean"])
+            fails.update(r["capacity_failures"])
+            print(f"heat map: width {rows * rows} depth {d} done, {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+        out[f"width{rows * rows}"] = {"F_mean": F, "capacity_failures": fails}
+    out["wall_s"] = round(time.perf_counter() - t0, 1)
+    return out
+
+
 def bench_validation(qs, workloads, protocol, circuits: int = 25) -> dict:
     """The fidelity model against the gold standard over the paper's
     validation sets (Appendix: widths x depths 6x6 ... 19x10, p from 0 to 1
@@ -340,7 +374,8 @@ def main() -> int:
     ap.add_argument("--quick", action="store_true",
                     help="only the QFT (skip the circuit, approximate, batch and validation runs)")
     ap.add_argument("--section", action="append", default=[],
-                    choices=["circuit", "approx", "pairs", "qft_factorized", "batch", "validation"],
+                    choices=["circuit", "approx", "pairs", "qft_factorized", "batch", "validation",
+                             "depth_sweep", "heat_maps"],
                     help="run only these secondary sections (repeatable; default: all)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy one 1-GiB device buffer into another three times (the known-size "
@@ -488,6 +523,11 @@ def main() -> int:
             sec["batch1024"] = bench_batch(qs, workloads, torch)
         if "validation" in want:
             sec["validation"] = bench_validation(qs, workloads, protocol)
+        # long sweeps (minutes), only when asked for by name
+        if "depth_sweep" in args.section:
+            sec["depth_sweep54"] = bench_depth_sweep(workloads, protocol)
+        if "heat_maps" in args.section:
+            sec["heat_maps"] = bench_heat_maps(workloads, protocol)
         out["secondary"] = sec
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n)

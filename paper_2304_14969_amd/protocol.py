@@ -157,3 +157,46 @@ def validation_grid(make_circuit, sets=VALIDATION_SETS, circuits: int = 10, step
             "rmse_overall": round(math.sqrt(sum(e * e for e in all_err) / len(all_err)), 5),
             "mean_err": round(sum(all_err) / len(all_err), 5),
             "observations": len(all_err), "circuits_per_set": circuits, "p_step": step}
+
+
+def depth_sweep(make_circuit, rows: int, cols: int, depths, circuits: int = 10,
+                max_amps: int = 2 ** 30, seed0: int = 30000, dtype: int = C64) -> dict:
+    """Achievable fidelity against depth (the experiment of Fig. 3): for each
+    depth, `circuits` circuits from make_circuit(rows, cols, depth, seed), the
+    descending-p search of each, and the mean, median and spread of the
+    fidelity estimate at the smallest completed p (0 where even p = 1 fails)."""
+    out = {}
+    for d in depths:
+        Fs, pmin, secs = [], [], 0.0
+        for c in range(circuits):
+            r = minimum_p(rows * cols, make_circuit(rows, cols, d, seed0 + 100 * d + c),
+                          max_amps=max_amps, dtype=dtype)
+            b = r["best"]
+            Fs.append(b["F"] if b else 0.0)
+            pmin.append(b["p"] if b else None)
+            secs += r["search_time_s"]
+        ok = [p for p in pmin if p is not None]
+        out[str(d)] = {"F_mean": float(np.mean(Fs)), "F_median": float(np.median(Fs)),
+                       "F_max": float(np.max(Fs)),
+                       "p_min_mean": float(np.mean(ok)) if ok else None,
+                       "search_s": round(secs, 3)}
+    return out
+
+
+def heat_map(make_circuit, rows: int, cols: int, depths, ps, circuits: int = 5,
+             max_amps: int = 2 ** 30, seed0: int = 40000, dtype: int = C64) -> dict:
+    """Fidelity over threshold and depth (the heat maps of the appendix): the
+    mean fidelity estimate of `circuits` circuits for every (p, depth), with
+    runs that hit the amplitude cap counted as 0 and reported separately."""
+    grid, fails = {}, {}
+    for d in depths:
+        gates = [make_circuit(rows, cols, d, seed0 + 100 * d + c) for c in range(circuits)]
+        for p in ps:
+            Fs, nf = [], 0
+            for g in gates:
+                r = approx_run(rows * cols, g, p, max_amps=max_amps, dtype=dtype)
+                Fs.append(r["F"] if r["ok"] else 0.0)
+                nf += 0 if r["ok"] else 1
+            grid[f"{p:g},{d}"] = float(np.mean(Fs))
+            fails[f"{p:g},{d}"] = nf
+    return {"F_mean": grid, "capacity_failures": fails, "circuits": circuits}
