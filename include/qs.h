@@ -451,6 +451,10 @@ int qs_check(qs_state* st, double tol);
  *                    measures the lowest dirty qubit together with the next
  *                    dirty qubits of its subsystem (up to 5, none skipped) in
  *                    one sweep; 0: one sweep per qubit. Same decisions;
+ *   "factor.kernarg_tables" 1 (default): the tables of the batched launches
+ *                    of the factorized mode (sweeps, merges, projections,
+ *                    one-qubit runs) travel in the kernel arguments when they
+ *                    fit; 0: always read from mapped host memory;
  *   "factor.unobservable" 1 (default): the Z-eigenstate shortcut described at
  *                    qs_shortcut_count; 0: every gate merges its operands;
  *   "factor.defer"   1 (default): in qs_run on a factorized state with the

@@ -37,6 +37,7 @@ int g_batch_1q = 1;
 int g_defer_sep = 1;
 int g_tile_1q = 1;
 int g_unobservable = 1;
+int g_kernarg_tables = 1;
 
 void* device_alloc(size_t bytes);
 void device_free(void* p);
@@ -1211,7 +1212,8 @@ int flush_round(FactorState* f, bool* any) {
   }
   hipError_t e = hipSuccess;
   if (nsmall) {
-    e = launch_bloch_batch(static_cast<const BlochItem<R>*>(dev), nsmall, f->dstat, f->stream);
+    e = launch_bloch_batch(static_cast<const BlochItem<R>*>(host),
+                           static_cast<const BlochItem<R>*>(dev), nsmall, f->dstat, f->stream);
     if (e == hipSuccess) e = hipEventRecord(f->ring_ev[slot], f->stream);
     if (e == hipSuccess) f->ring_used[slot] = true;
   }
@@ -1289,7 +1291,8 @@ int launch_queue_t(FactorState* f) {
       o.scale = q.scale;
       for (int k = 0; k < 32; ++k) o.m[k] = R(q.m[k]);
     }
-    e = launch_fact_ops(static_cast<const FactOp<R>*>(dev), int(cnt), f->stream);
+    e = launch_fact_ops(static_cast<const FactOp<R>*>(host), static_cast<const FactOp<R>*>(dev),
+                        int(cnt), f->stream);
     if (e == hipSuccess) e = hipEventRecord(f->ring_ev[slot], f->stream);
     if (e == hipSuccess) f->ring_used[slot] = true;
   }
@@ -1495,9 +1498,9 @@ int apply_1q_run(FactorState* f, const int* qubits, const double* m, int count) 
       }
     }
     hipError_t e = launch_fact_1q_batch(
-        static_cast<const Fact1qItem<R>*>(dev), int(nit),
-        reinterpret_cast<const Fact1qGate<R>*>(static_cast<char*>(dev) + kGatesAt), max_nq,
-        f->stream);
+        items, static_cast<const Fact1qItem<R>*>(dev), int(nit), gates,
+        reinterpret_cast<const Fact1qGate<R>*>(static_cast<char*>(dev) + kGatesAt), int(ng),
+        max_nq, f->stream);
     if (e == hipSuccess) e = hipEventRecord(f->ring_ev[slot], f->stream);
     if (int rc = dev_err(e, "batched one-qubit gates")) return rc;
     f->ring_used[slot] = true;

@@ -203,10 +203,8 @@ __device__ __forceinline__ void bloch_item(const BlochItem<R>& it, double* sh,
 }
 
 template <typename R>
-__global__ void __launch_bounds__(kBlock) k_bloch_batch(const BlochItem<R>* __restrict__ items,
-                                                        double* __restrict__ out) {
-  __shared__ double sh[4 * kMaxMulti * kBlock];
-  const BlochItem<R> it = items[blockIdx.x];
+__device__ __forceinline__ void bloch_dispatch(const BlochItem<R>& it, double* sh,
+                                               double* __restrict__ out) {
   switch (it.G) {
     case 1: bloch_item<R, 1>(it, sh, out); break;
     case 2: bloch_item<R, 2>(it, sh, out); break;
@@ -216,19 +214,37 @@ __global__ void __launch_bounds__(kBlock) k_bloch_batch(const BlochItem<R>* __re
   }
 }
 
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_bloch_batch(const BlochItem<R>* __restrict__ items,
+                                                        double* __restrict__ out) {
+  __shared__ double sh[4 * kMaxMulti * kBlock];
+  const BlochItem<R> it = items[blockIdx.x];
+  bloch_dispatch(it, sh, out);
+}
+
+// The same with the item table in the kernel arguments (no table reads from
+// host memory over the bus).
+template <typename R>
+struct BlochArgs {
+  BlochItem<R> it[kBlochArgItems];
+};
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_bloch_batch_arg(BlochArgs<R> args,
+                                                            double* __restrict__ out) {
+  __shared__ double sh[4 * kMaxMulti * kBlock];
+  const BlochItem<R> it = args.it[blockIdx.x];
+  bloch_dispatch(it, sh, out);
+}
+
 // One workgroup per item: the item's subsystem (at most 2^12 amplitudes) is
 // staged in LDS, its gates are applied there in order, and it is stored back.
-template <typename R>
-__global__ void __launch_bounds__(kBlock) k_fact_1q_batch(const Fact1qItem<R>* __restrict__ items,
-                                                          const Fact1qGate<R>* __restrict__ gates) {
-  extern __shared__ __align__(16) char fact_lds[];
-  R* sh = reinterpret_cast<R*>(fact_lds);
-  const Fact1qItem<R> it = items[blockIdx.x];
+template <typename R, typename GateAt>
+__device__ __forceinline__ void fact_1q_item(const Fact1qItem<R>& it, GateAt gate_at, R* sh) {
   const uint32_t words = uint32_t(2) << it.nq, pairs = uint32_t(1) << (it.nq - 1);
   for (uint32_t i = threadIdx.x; i < words; i += kBlock) sh[i] = it.amps[i];
   __syncthreads();
   for (int g = it.g0; g < it.g0 + it.ng; ++g) {
-    const Fact1qGate<R> gt = gates[g];
+    const Fact1qGate<R> gt = gate_at(g);
     const uint32_t bit = uint32_t(1) << gt.t, low = bit - 1;
     for (uint32_t u = threadIdx.x; u < pairs; u += kBlock) {
       const uint32_t i0 = ((u & ~low) << 1) | (u & low), i1 = i0 | bit;
@@ -242,6 +258,27 @@ __global__ void __launch_bounds__(kBlock) k_fact_1q_batch(const Fact1qItem<R>* _
     __syncthreads();  // the next gate reads what this one wrote
   }
   for (uint32_t i = threadIdx.x; i < words; i += kBlock) it.amps[i] = sh[i];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_fact_1q_batch(const Fact1qItem<R>* __restrict__ items,
+                                                          const Fact1qGate<R>* __restrict__ gates) {
+  extern __shared__ __align__(16) char fact_lds[];
+  const Fact1qItem<R> it = items[blockIdx.x];
+  fact_1q_item(it, [gates](int g) { return gates[g]; }, reinterpret_cast<R*>(fact_lds));
+}
+
+// The same with both tables in the kernel arguments.
+template <typename R>
+struct Fact1qArgs {
+  Fact1qItem<R> items[kFact1qArgItems];
+  Fact1qGate<R> gates[fact1q_arg_gates<R>()];
+};
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_fact_1q_batch_arg(Fact1qArgs<R> args) {
+  extern __shared__ __align__(16) char fact_lds[];
+  const Fact1qItem<R> it = args.items[blockIdx.x];
+  fact_1q_item(it, [&args](int g) { return args.gates[g]; }, reinterpret_cast<R*>(fact_lds));
 }
 
 template <typename R>
@@ -398,8 +435,7 @@ __global__ void __launch_bounds__(kBlock) k_decompose_pair(R* __restrict__ b,
 // the composed amplitudes as k_compose does and the 4x4 product as the
 // two-qubit argument-matrix kernel does, in the same order.
 template <typename R>
-__global__ void __launch_bounds__(kBlock) k_fact_ops(const FactOp<R>* __restrict__ ops) {
-  const FactOp<R> op = ops[blockIdx.x];  // the table may be in host memory: read it once
+__device__ __forceinline__ void fact_op(const FactOp<R>& op) {
   if (op.kind == 1) {
     const uint64_t count = uint64_t(1) << (op.na - 1);
     for (uint64_t u = threadIdx.x; u < count; u += kBlock)
@@ -415,6 +451,23 @@ __global__ void __launch_bounds__(kBlock) k_fact_ops(const FactOp<R>* __restrict
   const uint64_t groups = uint64_t(1) << (op.na + op.nb - 2);
   for (uint64_t g = threadIdx.x; g < groups; g += kBlock)
     merge_gate_group(op.a, op.na, op.b, op.nb, op.c, op.t0, op.t1, op.m, g);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_fact_ops(const FactOp<R>* __restrict__ ops) {
+  const FactOp<R> op = ops[blockIdx.x];  // the table may be in host memory: read it once
+  fact_op(op);
+}
+
+// The same with the operations in the kernel arguments.
+template <typename R>
+struct OpsArgs {
+  FactOp<R> op[fact_arg_ops<R>()];
+};
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_fact_ops_arg(OpsArgs<R> args) {
+  const FactOp<R> op = args.op[blockIdx.x];
+  fact_op(op);
 }
 
 // The merge-and-gate operation over a grid (large subsystems).
@@ -532,11 +585,20 @@ hipError_t launch_bloch_multi(const R* a, int nq, const int* bits, int G, double
 }
 
 template <typename R>
-hipError_t launch_fact_1q_batch(const Fact1qItem<R>* items, int nitems, const Fact1qGate<R>* gates,
-                                int max_nq, hipStream_t s) {
+hipError_t launch_fact_1q_batch(const Fact1qItem<R>* host_items, const Fact1qItem<R>* items,
+                                int nitems, const Fact1qGate<R>* host_gates,
+                                const Fact1qGate<R>* gates, int ngates, int max_nq,
+                                hipStream_t s) {
   if (nitems < 1) return hipSuccess;
   if (max_nq < 1 || max_nq > kFact1qMaxQubits) return hipErrorInvalidValue;
   const size_t lds = (size_t(2) << max_nq) * sizeof(R);
+  if (g_kernarg_tables && nitems <= kFact1qArgItems && ngates <= fact1q_arg_gates<R>()) {
+    Fact1qArgs<R> args;
+    for (int i = 0; i < nitems; ++i) args.items[i] = host_items[i];
+    for (int i = 0; i < ngates; ++i) args.gates[i] = host_gates[i];
+    hipLaunchKernelGGL(k_fact_1q_batch_arg<R>, dim3(nitems), dim3(kBlock), lds, s, args);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_fact_1q_batch<R>, dim3(nitems), dim3(kBlock), lds, s, items, gates);
   return hipGetLastError();
 }
@@ -585,15 +647,29 @@ hipError_t launch_merge_gate(R* c, const R* a, int na, const R* b, int nb, int t
 }
 
 template <typename R>
-hipError_t launch_fact_ops(const FactOp<R>* ops, int nops, hipStream_t s) {
+hipError_t launch_fact_ops(const FactOp<R>* host_ops, const FactOp<R>* ops, int nops,
+                           hipStream_t s) {
   if (nops < 1) return hipSuccess;
+  if (g_kernarg_tables && nops <= fact_arg_ops<R>()) {
+    OpsArgs<R> args;
+    for (int i = 0; i < nops; ++i) args.op[i] = host_ops[i];
+    hipLaunchKernelGGL(k_fact_ops_arg<R>, dim3(nops), dim3(kBlock), 0, s, args);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_fact_ops<R>, dim3(nops), dim3(kBlock), 0, s, ops);
   return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_bloch_batch(const BlochItem<R>* items, int nitems, double* out, hipStream_t s) {
+hipError_t launch_bloch_batch(const BlochItem<R>* host_items, const BlochItem<R>* items,
+                              int nitems, double* out, hipStream_t s) {
   if (nitems < 1) return hipSuccess;
+  if (g_kernarg_tables && nitems <= kBlochArgItems) {
+    BlochArgs<R> args;
+    for (int i = 0; i < nitems; ++i) args.it[i] = host_items[i];
+    hipLaunchKernelGGL(k_bloch_batch_arg<R>, dim3(nitems), dim3(kBlock), 0, s, args, out);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_bloch_batch<R>, dim3(nitems), dim3(kBlock), 0, s, items, out);
   return hipGetLastError();
 }
@@ -633,16 +709,18 @@ hipError_t launch_gather_mul(const R* a, const uint64_t* idx, uint64_t m, Perm64
   template hipError_t launch_compose<R>(R*, const R*, int, const R*, int, hipStream_t);     \
   template hipError_t launch_bloch<R>(const R*, int, int, double*, double*, hipStream_t);   \
   template hipError_t launch_store_single<R>(R*, const double*, hipStream_t);               \
-  template hipError_t launch_bloch_batch<R>(const BlochItem<R>*, int, double*, hipStream_t); \
-  template hipError_t launch_fact_ops<R>(const FactOp<R>*, int, hipStream_t);               \
+  template hipError_t launch_bloch_batch<R>(const BlochItem<R>*, const BlochItem<R>*, int,   \
+                                            double*, hipStream_t);                          \
+  template hipError_t launch_fact_ops<R>(const FactOp<R>*, const FactOp<R>*, int, hipStream_t); \
   template hipError_t launch_pair_rho<R>(const R*, int, int, int, double*, double*,         \
                                          hipStream_t);                                      \
   template hipError_t launch_decompose_pair<R>(R*, const R*, int, int, int, const double*,  \
                                                double, R*, hipStream_t);                    \
   template hipError_t launch_merge_gate<R>(R*, const R*, int, const R*, int, int, int,      \
                                            const double*, hipStream_t);                     \
-  template hipError_t launch_fact_1q_batch<R>(const Fact1qItem<R>*, int, const Fact1qGate<R>*, int, \
-                                              hipStream_t);                                 \
+  template hipError_t launch_fact_1q_batch<R>(const Fact1qItem<R>*, const Fact1qItem<R>*, int, \
+                                              const Fact1qGate<R>*, const Fact1qGate<R>*, int, \
+                                              int, hipStream_t);                            \
   template hipError_t launch_bloch_multi<R>(const R*, int, const int*, int, double*, double*, \
                                             hipStream_t);                                   \
   template hipError_t launch_decompose<R>(R*, const R*, int, int, const double*, double,    \

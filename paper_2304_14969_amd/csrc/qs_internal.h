@@ -127,8 +127,15 @@ struct BlochItem {
   int bits[5];
   int out;
 };
+// host_items: the same table in host memory; up to kBlochArgItems items travel
+// in the kernel arguments instead of being read through `items`.
+constexpr int kBlochArgItems = 64;
 template <typename R>
-hipError_t launch_bloch_batch(const BlochItem<R>* items, int nitems, double* out, hipStream_t s);
+hipError_t launch_bloch_batch(const BlochItem<R>* host_items, const BlochItem<R>* items,
+                              int nitems, double* out, hipStream_t s);
+// Process-wide: small operation tables in the kernel arguments (1, default) or
+// always read from mapped host memory (0).
+extern int g_kernarg_tables;
 // Independent operations on many small subsystems in one launch, one
 // workgroup each (the large ones go through the single-operation launchers,
 // whose arithmetic these repeat term for term):
@@ -152,8 +159,14 @@ struct FactOp {
   double scale;
   R m[32];  // 4x4, row-major, interleaved
 };
+// Operations per launch that fit the kernel arguments (under 4 KiB).
 template <typename R>
-hipError_t launch_fact_ops(const FactOp<R>* ops, int nops, hipStream_t s);
+constexpr int fact_arg_ops() {
+  return int(3584 / sizeof(FactOp<R>));
+}
+template <typename R>
+hipError_t launch_fact_ops(const FactOp<R>* host_ops, const FactOp<R>* ops, int nops,
+                           hipStream_t s);
 // The kind-0 operation of FactOp over a grid, for any size: c = a (x) b (or a
 // in place when nb = 0, c == a), then the 4x4 matrix m (interleaved,
 // row-major, converted to R) on local bits t0, t1.
@@ -175,9 +188,19 @@ struct Fact1qGate {
   R m[8];  // 2x2 matrix, row-major, interleaved
   int t, pad;
 };
+// host_items / host_gates: the same tables in host memory; small ones travel
+// in the kernel arguments (up to kFact1qArgItems items and
+// fact1q_arg_gates<R>() gates, under 4 KiB).
+constexpr int kFact1qArgItems = 32;
 template <typename R>
-hipError_t launch_fact_1q_batch(const Fact1qItem<R>* items, int nitems, const Fact1qGate<R>* gates,
-                                int max_nq, hipStream_t s);
+constexpr int fact1q_arg_gates() {
+  return int((3584 - kFact1qArgItems * sizeof(Fact1qItem<R>)) / sizeof(Fact1qGate<R>));
+}
+template <typename R>
+hipError_t launch_fact_1q_batch(const Fact1qItem<R>* host_items, const Fact1qItem<R>* items,
+                                int nitems, const Fact1qGate<R>* host_gates,
+                                const Fact1qGate<R>* gates, int ngates, int max_nq,
+                                hipStream_t s);
 // A one-qubit subsystem: the two amplitudes amp = {Re a0, Im a0, Re a1, Im a1}.
 template <typename R>
 hipError_t launch_store_single(R* dst, const double amp[4], hipStream_t s);

@@ -359,3 +359,25 @@ def test_large_subsystem_paths(qs_lib, dtype):
             st.free()
     finally:
         qs.tune_set("factor.tile_1q", saved)
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_tables_in_kernel_arguments_or_host_memory(qs_lib, dtype):
+    """Small operation tables (batched sweeps, merges, projections, one-qubit
+    runs) travel in the kernel arguments or are read from mapped host memory:
+    the same kernels' arithmetic either way, so identical logs and kets."""
+    qs = qs_lib
+    n = 16
+    gates = workloads.grid_circuit(4, 4, 8, 5)
+    saved = qs.tune_get("factor.kernarg_tables")
+    out = []
+    try:
+        for k in (0, 1):
+            qs.tune_set("factor.kernarg_tables", k)
+            st = gpu_run(qs, n, gates, 0.3, dtype)
+            out.append((st.attempts(), st.fidelity_estimate(), st.amplitudes()))
+            st.free()
+    finally:
+        qs.tune_set("factor.kernarg_tables", saved)
+    assert len(out[0][0]) > 20 and out[0][0] == out[1][0] and out[0][1] == out[1][1]
+    np.testing.assert_array_equal(out[0][2], out[1][2])
