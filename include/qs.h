@@ -451,6 +451,10 @@ int qs_check(qs_state* st, double tol);
  *                    measures the lowest dirty qubit together with the next
  *                    dirty qubits of its subsystem (up to 5, none skipped) in
  *                    one sweep; 0: one sweep per qubit. Same decisions;
+ *   "factor.done_flag" 1 (default): a round of batched sweeps of small
+ *                    subsystems is waited for by a completion flag its last
+ *                    workgroup writes to mapped host memory; 0: by a stream
+ *                    synchronization;
  *   "factor.kernarg_tables" 1 (default): the tables of the batched launches
  *                    of the factorized mode (sweeps, merges, projections,
  *                    one-qubit runs) travel in the kernel arguments when they

@@ -38,6 +38,7 @@ int g_defer_sep = 1;
 int g_tile_1q = 1;
 int g_unobservable = 1;
 int g_kernarg_tables = 1;
+int g_done_flag = 1;
 
 void* device_alloc(size_t bytes);
 void device_free(void* p);
@@ -589,6 +590,9 @@ void fact_drain(FactorState* f) {
   device_free(f->tile_dev);
   f->tile_dev = nullptr;
   f->tile_cap = 0;
+  if (f->sig_host) (void)hipHostFree(f->sig_host);
+  device_free(f->sig_count);
+  f->sig_host = f->sig_dev = f->sig_count = nullptr;
 }
 
 int fact_set_basis(FactorState* f, uint64_t x) {
@@ -1084,6 +1088,51 @@ bool touches_dirty(const FactorState* f, const int* qubits, int k) {
   return false;
 }
 
+// The completion signal's memory, made on first use (false if unavailable:
+// the caller synchronizes the stream instead).
+bool signal_ready(FactorState* f) {
+  if (f->sig_host) return true;
+  void* h = nullptr;
+  void* d = nullptr;
+  if (hipHostMalloc(&h, 64, hipHostMallocMapped) != hipSuccess) return false;
+  if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+    (void)hipHostFree(h);
+    return false;
+  }
+  auto* c = static_cast<unsigned*>(device_alloc(sizeof(unsigned)));
+  if (!c || hipMemsetAsync(c, 0, sizeof(unsigned), f->stream) != hipSuccess ||
+      hipStreamSynchronize(f->stream) != hipSuccess) {
+    device_free(c);
+    (void)hipHostFree(h);
+    return false;
+  }
+  *static_cast<volatile unsigned*>(h) = 0;
+  f->sig_host = static_cast<unsigned*>(h);
+  f->sig_dev = static_cast<unsigned*>(d);
+  f->sig_count = c;
+  f->sig_total = 0;
+  f->sig_seq = 0;
+  return true;
+}
+
+// Waits until the flag shows `seq`; every few thousand polls the stream is
+// queried, so that an error, or a stream that finished without the signal,
+// ends the wait.
+int wait_signal(FactorState* f, unsigned seq) {
+  for (uint64_t i = 1;; ++i) {
+    if (__atomic_load_n(static_cast<volatile unsigned*>(f->sig_host), __ATOMIC_ACQUIRE) == seq)
+      return QS_OK;
+    if ((i & 4095) == 0) {
+      const hipError_t q = hipStreamQuery(f->stream);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) return dev_err(q, "bloch");
+      if (__atomic_load_n(static_cast<volatile unsigned*>(f->sig_host), __ATOMIC_ACQUIRE) == seq)
+        return QS_OK;
+      return ffail(QS_E_DEVICE, "batched sweep finished without its completion signal");
+    }
+  }
+}
+
 // One round of deferred tests: for every subsystem with dirty qubits, up to
 // kMultiTest of them (the lowest, ascending). Sweeps of subsystems of at most
 // 2^kBlochBatchQubits amplitudes share one launch; larger ones keep their own
@@ -1193,7 +1242,12 @@ int flush_round(FactorState* f, bool* any) {
       pos[i][o[j]] = j;  // row of qubit j in the kernel's output
     }
   }
-  // small subsystems: one launch over a table in a pinned slot
+  // small subsystems: one launch over a table in a pinned slot; when that
+  // launch is the whole round, its completion flag replaces the stream sync
+  bool only_small = true;
+  for (const Item& it : items)
+    if (it.G == 0 || f->subs[it.si].nq > kBlochBatchQubits) only_small = false;
+  const bool signal = only_small && g_done_flag && signal_ready(f);
   void *host = nullptr, *dev = nullptr;
   int slot = -1, nsmall = 0;
   for (size_t i = 0; i < items.size(); ++i) {
@@ -1211,9 +1265,19 @@ int flush_round(FactorState* f, bool* any) {
     b.out = int(i) * kRow;
   }
   hipError_t e = hipSuccess;
+  unsigned seq = 0;
   if (nsmall) {
+    unsigned* counter = nullptr;
+    unsigned target = 0;
+    if (signal) {
+      seq = ++f->sig_seq;
+      f->sig_total += unsigned(nsmall);
+      counter = f->sig_count;
+      target = f->sig_total;
+    }
     e = launch_bloch_batch(static_cast<const BlochItem<R>*>(host),
-                           static_cast<const BlochItem<R>*>(dev), nsmall, f->dstat, f->stream);
+                           static_cast<const BlochItem<R>*>(dev), nsmall, f->dstat, counter,
+                           f->sig_dev, target, seq, f->stream);
     if (e == hipSuccess) e = hipEventRecord(f->ring_ev[slot], f->stream);
     if (e == hipSuccess) f->ring_used[slot] = true;
   }
@@ -1231,8 +1295,12 @@ int flush_round(FactorState* f, bool* any) {
             : launch_bloch_multi(a, S.nq, bits[i], items[i].G, f->scratch, f->dstat + i * kRow,
                                  f->stream);
   }
-  if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
   if (int rc = dev_err(e, "bloch")) return rc;
+  if (signal && nsmall) {
+    if (int rc = wait_signal(f, seq)) return rc;
+  } else if (int rc = dev_err(hipStreamSynchronize(f->stream), "bloch")) {
+    return rc;
+  }
   // decisions per subsystem, ascending qubit number, stopping at a rounding
   for (size_t i = 0; i < items.size(); ++i) {
     const Item& it = items[i];

@@ -89,6 +89,12 @@ struct FactorState {
   hipEvent_t ring_ev[kRingSlots] = {nullptr};
   bool ring_used[kRingSlots] = {false};
   int ring_next = 0;
+  // completion signal of the batched sweeps: a device counter, a host-mapped
+  // flag the last workgroup sets to the launch's sequence number
+  unsigned* sig_count = nullptr;
+  unsigned* sig_host = nullptr;
+  unsigned* sig_dev = nullptr;
+  unsigned sig_total = 0, sig_seq = 0;
   // device copy of the tile-pass tables of the last one-qubit run on a large
   // subsystem (rewritten in stream order)
   void* tile_dev = nullptr;
@@ -133,6 +139,9 @@ extern int g_tile_1q;
 // keeps is restricted to that value (a controlled gate on |0> disappears, on
 // |1> it becomes a gate on the target), so no merge happens; 0: off.
 extern int g_unobservable;
+// Process-wide: wait for batched sweeps by their completion flag (1, default)
+// or by synchronizing the stream (0).
+extern int g_done_flag;
 
 // The 32 proposal features of qubit q (threshold p) from the bookkeeping.
 void fact_features(const FactorState* f, int q, double p, float* out);

@@ -214,12 +214,34 @@ __device__ __forceinline__ void bloch_dispatch(const BlochItem<R>& it, double* s
   }
 }
 
+// Completion signal of a batched launch (sig.counter == nullptr: none): every
+// workgroup's thread 0, after writing its sums, makes them visible to the host
+// and counts itself on a device counter; the workgroup that brings the count
+// to sig.target stores sig.seq into the host-mapped flag (plain vector stores
+// and a vector atomic on device memory).
+struct DoneSignal {
+  unsigned* counter;
+  unsigned* flag;
+  unsigned target, seq;
+};
+
+__device__ __forceinline__ void signal_done(const DoneSignal& sig) {
+  if (sig.counter == nullptr || threadIdx.x != 0) return;
+  __threadfence_system();
+  const unsigned old = atomicAdd(sig.counter, 1u);
+  if (old + 1u == sig.target) {
+    __threadfence_system();
+    *reinterpret_cast<volatile unsigned*>(sig.flag) = sig.seq;
+  }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_bloch_batch(const BlochItem<R>* __restrict__ items,
-                                                        double* __restrict__ out) {
+                                                        double* __restrict__ out, DoneSignal sig) {
   __shared__ double sh[4 * kMaxMulti * kBlock];
   const BlochItem<R> it = items[blockIdx.x];
   bloch_dispatch(it, sh, out);
+  signal_done(sig);
 }
 
 // The same with the item table in the kernel arguments (no table reads from
@@ -230,10 +252,12 @@ struct BlochArgs {
 };
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_bloch_batch_arg(BlochArgs<R> args,
-                                                            double* __restrict__ out) {
+                                                            double* __restrict__ out,
+                                                            DoneSignal sig) {
   __shared__ double sh[4 * kMaxMulti * kBlock];
   const BlochItem<R> it = args.it[blockIdx.x];
   bloch_dispatch(it, sh, out);
+  signal_done(sig);
 }
 
 // One workgroup per item: the item's subsystem (at most 2^12 amplitudes) is
@@ -662,15 +686,17 @@ hipError_t launch_fact_ops(const FactOp<R>* host_ops, const FactOp<R>* ops, int 
 
 template <typename R>
 hipError_t launch_bloch_batch(const BlochItem<R>* host_items, const BlochItem<R>* items,
-                              int nitems, double* out, hipStream_t s) {
+                              int nitems, double* out, unsigned* counter, unsigned* flag,
+                              unsigned target, unsigned seq, hipStream_t s) {
   if (nitems < 1) return hipSuccess;
+  const DoneSignal sig{counter, flag, target, seq};
   if (g_kernarg_tables && nitems <= kBlochArgItems) {
     BlochArgs<R> args;
     for (int i = 0; i < nitems; ++i) args.it[i] = host_items[i];
-    hipLaunchKernelGGL(k_bloch_batch_arg<R>, dim3(nitems), dim3(kBlock), 0, s, args, out);
+    hipLaunchKernelGGL(k_bloch_batch_arg<R>, dim3(nitems), dim3(kBlock), 0, s, args, out, sig);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_bloch_batch<R>, dim3(nitems), dim3(kBlock), 0, s, items, out);
+  hipLaunchKernelGGL(k_bloch_batch<R>, dim3(nitems), dim3(kBlock), 0, s, items, out, sig);
   return hipGetLastError();
 }
 
@@ -710,7 +736,8 @@ hipError_t launch_gather_mul(const R* a, const uint64_t* idx, uint64_t m, Perm64
   template hipError_t launch_bloch<R>(const R*, int, int, double*, double*, hipStream_t);   \
   template hipError_t launch_store_single<R>(R*, const double*, hipStream_t);               \
   template hipError_t launch_bloch_batch<R>(const BlochItem<R>*, const BlochItem<R>*, int,   \
-                                            double*, hipStream_t);                          \
+                                            double*, unsigned*, unsigned*, unsigned,        \
+                                            unsigned, hipStream_t);                         \
   template hipError_t launch_fact_ops<R>(const FactOp<R>*, const FactOp<R>*, int, hipStream_t); \
   template hipError_t launch_pair_rho<R>(const R*, int, int, int, double*, double*,         \
                                          hipStream_t);                                      \

@@ -130,9 +130,15 @@ struct BlochItem {
 // host_items: the same table in host memory; up to kBlochArgItems items travel
 // in the kernel arguments instead of being read through `items`.
 constexpr int kBlochArgItems = 64;
+// counter (device) / flag (host-mapped): when counter is not null, the
+// workgroup that completes the launch's count, target = the counter's value
+// before the launch + nitems, stores seq into *flag after every sum is
+// visible to the host (a completion signal that needs no stream
+// synchronization).
 template <typename R>
 hipError_t launch_bloch_batch(const BlochItem<R>* host_items, const BlochItem<R>* items,
-                              int nitems, double* out, hipStream_t s);
+                              int nitems, double* out, unsigned* counter, unsigned* flag,
+                              unsigned target, unsigned seq, hipStream_t s);
 // Process-wide: small operation tables in the kernel arguments (1, default) or
 // always read from mapped host memory (0).
 extern int g_kernarg_tables;

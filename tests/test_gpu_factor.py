@@ -381,3 +381,27 @@ def test_tables_in_kernel_arguments_or_host_memory(qs_lib, dtype):
         qs.tune_set("factor.kernarg_tables", saved)
     assert len(out[0][0]) > 20 and out[0][0] == out[1][0] and out[0][1] == out[1][1]
     np.testing.assert_array_equal(out[0][2], out[1][2])
+
+
+def test_completion_flag_or_stream_sync(qs_lib):
+    """Batched sweeps waited for by their completion flag or by a stream
+    synchronization: the same results (the flag is set only after every sum
+    is visible), over many rounds in a row."""
+    qs = qs_lib
+    n = 16
+    saved = qs.tune_get("factor.done_flag")
+    out = []
+    try:
+        for k in (0, 1):
+            qs.tune_set("factor.done_flag", k)
+            rows = []
+            for seed in range(3):
+                st = gpu_run(qs, n, workloads.random_circuit(n, 8, 60 + seed), 0.3)
+                rows.append((st.attempts(), st.fidelity_estimate(), st.amplitudes()))
+                st.free()
+            out.append(rows)
+    finally:
+        qs.tune_set("factor.done_flag", saved)
+    for a, b in zip(*out):
+        assert len(a[0]) > 20 and a[0] == b[0] and a[1] == b[1]
+        np.testing.assert_array_equal(a[2], b[2])
