@@ -451,6 +451,10 @@ int qs_check(qs_state* st, double tol);
  *                    measures the lowest dirty qubit together with the next
  *                    dirty qubits of its subsystem (up to 5, none skipped) in
  *                    one sweep; 0: one sweep per qubit. Same decisions;
+ *   "factor.fuse_ops" 1 (default): queued merges and projections run in the
+ *                    launch of the sweeps that read their results (each in
+ *                    the workgroup that then sweeps its output); 0: in a
+ *                    launch of their own first;
  *   "factor.done_flag" 1 (default): a round of batched sweeps of small
  *                    subsystems is waited for by a completion flag its last
  *                    workgroup writes to mapped host memory; 0: by a stream

@@ -310,6 +310,9 @@ int qs_tune_set(const char* key, int64_t value) {
   } else if (!std::strcmp(key, "factor.tile_1q")) {
     if (value < 0 || value > 1) return fail(QS_E_INVAL, "factor.tile_1q must be 0 or 1");
     qs::g_tile_1q = int(value);
+  } else if (!std::strcmp(key, "factor.fuse_ops")) {
+    if (value < 0 || value > 1) return fail(QS_E_INVAL, "factor.fuse_ops must be 0 or 1");
+    qs::g_fuse_ops = int(value);
   } else if (!std::strcmp(key, "factor.done_flag")) {
     if (value < 0 || value > 1) return fail(QS_E_INVAL, "factor.done_flag must be 0 or 1");
     qs::g_done_flag = int(value);
@@ -348,6 +351,7 @@ int qs_tune_get(const char* key, int64_t* value) {
   else if (!std::strcmp(key, "factor.unobservable")) *value = qs::g_unobservable;
   else if (!std::strcmp(key, "factor.kernarg_tables")) *value = qs::g_kernarg_tables;
   else if (!std::strcmp(key, "factor.done_flag")) *value = qs::g_done_flag;
+  else if (!std::strcmp(key, "factor.fuse_ops")) *value = qs::g_fuse_ops;
   else if (!std::strcmp(key, "factor.tile_1q")) *value = qs::g_tile_1q;
   else if (!std::strcmp(key, "tile.mfma")) *value = g_tile_mfma;
   else if (!std::strcmp(key, "qft.col_max")) *value = g_qft_tune.col_max;

@@ -39,6 +39,7 @@ int g_tile_1q = 1;
 int g_unobservable = 1;
 int g_kernarg_tables = 1;
 int g_done_flag = 1;
+int g_fuse_ops = 1;
 
 void* device_alloc(size_t bytes);
 void device_free(void* p);
@@ -65,10 +66,15 @@ int dev_err(hipError_t e, const char* what) {
 size_t amp_bytes(const FactorState* f) { return f->dtype == QS_C64 ? 8 : 16; }
 
 constexpr int kMultiTest = 5;  // qubits per multi-qubit Bloch sweep
+// most items of one sweep round (the stat buffer holds 4 sums per target)
+constexpr int kMaxSweepItems = FactorState::kStatDoubles / (4 * kMultiTest);
 
 int flush_pending(FactorState* f);
 int ring_slot(FactorState* f, void** host, void** dev);
 int launch_queue(FactorState* f);
+void finish_queue(FactorState* f);
+template <typename R>
+void fill_op(const FactorState::QOp& q, FactOp<R>* o);
 
 // Does any of the k qubits lie in a subsystem with dirty qubits?
 bool touches_dirty(const FactorState* f, const int* qubits, int k);
@@ -1140,7 +1146,6 @@ int wait_signal(FactorState* f, unsigned seq) {
 // sweeps compute (same kernels' order), so the decisions are too.
 template <typename R>
 int flush_round(FactorState* f, bool* any) {
-  if (int rc = launch_queue(f)) return rc;  // the sweeps read the queued results
   struct Item {
     int si, G;                         // G = 0: the subsystem's pending pair test
     int q[kMultiTest], t[kMultiTest];  // ascending qubit number (pair: q[0..1], t[0..1])
@@ -1248,6 +1253,30 @@ int flush_round(FactorState* f, bool* any) {
   for (const Item& it : items)
     if (it.G == 0 || f->subs[it.si].nq > kBlochBatchQubits) only_small = false;
   const bool signal = only_small && g_done_flag && signal_ready(f);
+  // The queued operations (the merges and projections that produced the
+  // subsystems about to be swept) run in the sweep's launch when every one of
+  // them writes a small subsystem of this round, which it then precedes in
+  // its workgroup; otherwise they are launched first.
+  constexpr size_t kOpsAt = 2048;  // byte offset of the operations in the slot
+  static_assert(kOpsAt >= size_t(kMaxSweepItems) * sizeof(BlochItem<R>), "slot layout");
+  std::vector<int> op_of(items.size(), -1);
+  bool fuse = g_fuse_ops && only_small && !f->qops.empty() &&
+              f->qops.size() <= (FactorState::kSlotBytes - kOpsAt) / sizeof(FactOp<R>);
+  for (size_t k = 0; fuse && k < f->qops.size(); ++k) {
+    const FactorState::QOp& q = f->qops[k];
+    int hit = -1;
+    for (size_t i = 0; i < items.size() && hit < 0; ++i)
+      if (f->subs[items[i].si].amps == q.c) hit = int(i);
+    if (q.na + q.nb > kFactOpQubits || hit < 0 || op_of[hit] >= 0) {
+      fuse = false;
+      break;
+    }
+    op_of[hit] = int(k);
+  }
+  if (!fuse) {
+    if (int rc = launch_queue(f)) return rc;  // the sweeps read the queued results
+    std::fill(op_of.begin(), op_of.end(), -1);
+  }
   void *host = nullptr, *dev = nullptr;
   int slot = -1, nsmall = 0;
   for (size_t i = 0; i < items.size(); ++i) {
@@ -1263,6 +1292,12 @@ int flush_round(FactorState* f, bool* any) {
     b.G = items[i].G;
     for (int j = 0; j < kMultiTest; ++j) b.bits[j] = j < b.G ? bits[i][j] : 0;
     b.out = int(i) * kRow;
+    b.op = op_of[i];
+  }
+  FactOp<R>* hops = nullptr;
+  if (fuse) {
+    hops = reinterpret_cast<FactOp<R>*>(static_cast<char*>(host) + kOpsAt);
+    for (size_t k = 0; k < f->qops.size(); ++k) fill_op(f->qops[k], &hops[k]);
   }
   hipError_t e = hipSuccess;
   unsigned seq = 0;
@@ -1275,11 +1310,17 @@ int flush_round(FactorState* f, bool* any) {
       counter = f->sig_count;
       target = f->sig_total;
     }
-    e = launch_bloch_batch(static_cast<const BlochItem<R>*>(host),
-                           static_cast<const BlochItem<R>*>(dev), nsmall, f->dstat, counter,
-                           f->sig_dev, target, seq, f->stream);
+    e = fuse ? launch_ops_bloch(static_cast<const BlochItem<R>*>(host),
+                                static_cast<const BlochItem<R>*>(dev), nsmall, hops,
+                                reinterpret_cast<const FactOp<R>*>(static_cast<char*>(dev) + kOpsAt),
+                                int(f->qops.size()), f->dstat, counter, f->sig_dev, target, seq,
+                                f->stream)
+             : launch_bloch_batch(static_cast<const BlochItem<R>*>(host),
+                                  static_cast<const BlochItem<R>*>(dev), nsmall, f->dstat, counter,
+                                  f->sig_dev, target, seq, f->stream);
     if (e == hipSuccess) e = hipEventRecord(f->ring_ev[slot], f->stream);
     if (e == hipSuccess) f->ring_used[slot] = true;
+    if (fuse) finish_queue(f);  // launched; buffers freed meanwhile go back
   }
   for (size_t i = 0; i < items.size() && e == hipSuccess; ++i) {
     const Sub& S = f->subs[items[i].si];
@@ -1330,6 +1371,32 @@ int flush_round(FactorState* f, bool* any) {
 }
 
 template <typename R>
+void fill_op(const FactorState::QOp& q, FactOp<R>* o) {
+  o->a = static_cast<const R*>(q.a);
+  o->b = static_cast<const R*>(q.b);
+  o->c = static_cast<R*>(q.c);
+  o->single = static_cast<R*>(q.single);
+  o->kind = q.kind;
+  o->na = q.na;
+  o->nb = q.nb;
+  o->t0 = q.t0;
+  o->t1 = q.t1;
+  o->pad = 0;
+  for (int k = 0; k < 4; ++k) o->phi[k] = q.phi[k];
+  o->scale = q.scale;
+  for (int k = 0; k < 32; ++k) o->m[k] = R(q.m[k]);
+}
+
+// The queue has been launched: forget it, and return the buffers freed while
+// it was pending.
+void finish_queue(FactorState* f) {
+  f->qops.clear();
+  std::vector<std::pair<int, void*>> late;
+  late.swap(f->late_free);
+  for (const auto& b : late) sub_free(f, b.first, b.second);
+}
+
+template <typename R>
 int launch_queue_t(FactorState* f) {
   constexpr size_t kPerSlot = FactorState::kSlotBytes / sizeof(FactOp<R>);
   std::vector<const FactorState::QOp*> small, large;
@@ -1342,23 +1409,7 @@ int launch_queue_t(FactorState* f) {
     if (slot < 0) return slot;
     const size_t cnt = std::min(kPerSlot, small.size() - i);
     auto* ops = static_cast<FactOp<R>*>(host);
-    for (size_t j = 0; j < cnt; ++j) {
-      const FactorState::QOp& q = *small[i + j];
-      FactOp<R>& o = ops[j];
-      o.a = static_cast<const R*>(q.a);
-      o.b = static_cast<const R*>(q.b);
-      o.c = static_cast<R*>(q.c);
-      o.single = static_cast<R*>(q.single);
-      o.kind = q.kind;
-      o.na = q.na;
-      o.nb = q.nb;
-      o.t0 = q.t0;
-      o.t1 = q.t1;
-      o.pad = 0;
-      for (int k = 0; k < 4; ++k) o.phi[k] = q.phi[k];
-      o.scale = q.scale;
-      for (int k = 0; k < 32; ++k) o.m[k] = R(q.m[k]);
-    }
+    for (size_t j = 0; j < cnt; ++j) fill_op(*small[i + j], &ops[j]);
     e = launch_fact_ops(static_cast<const FactOp<R>*>(host), static_cast<const FactOp<R>*>(dev),
                         int(cnt), f->stream);
     if (e == hipSuccess) e = hipEventRecord(f->ring_ev[slot], f->stream);
@@ -1382,10 +1433,7 @@ int launch_queue_t(FactorState* f) {
 int launch_queue(FactorState* f) {
   if (f->qops.empty()) return QS_OK;
   const int rc = f->dtype == QS_C64 ? launch_queue_t<float>(f) : launch_queue_t<double>(f);
-  f->qops.clear();
-  std::vector<std::pair<int, void*>> late;
-  late.swap(f->late_free);
-  for (const auto& b : late) sub_free(f, b.first, b.second);
+  finish_queue(f);
   return rc;
 }
 

@@ -142,6 +142,9 @@ extern int g_unobservable;
 // Process-wide: wait for batched sweeps by their completion flag (1, default)
 // or by synchronizing the stream (0).
 extern int g_done_flag;
+// Process-wide: queued operations run in the launch of the sweeps that read
+// their results (1, default) or in a launch of their own (0).
+extern int g_fuse_ops;
 
 // The 32 proposal features of qubit q (threshold p) from the bookkeeping.
 void fact_features(const FactorState* f, int q, double p, float* out);

@@ -671,6 +671,59 @@ hipError_t launch_merge_gate(R* c, const R* a, int na, const R* b, int nb, int t
 }
 
 template <typename R>
+__global__ void __launch_bounds__(kBlock) k_ops_bloch(const BlochItem<R>* __restrict__ items,
+                                                      const FactOp<R>* __restrict__ ops,
+                                                      double* __restrict__ out, DoneSignal sig) {
+  __shared__ double sh[4 * kMaxMulti * kBlock];
+  const BlochItem<R> it = items[blockIdx.x];
+  if (it.op >= 0) {
+    const FactOp<R> op = ops[it.op];
+    fact_op(op);
+    __syncthreads();  // the sweep reads what the operation wrote
+  }
+  bloch_dispatch(it, sh, out);
+  signal_done(sig);
+}
+
+template <typename R>
+struct OpsBlochArgs {
+  BlochItem<R> it[kFusedItems];
+  FactOp<R> op[fused_arg_ops<R>()];
+};
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_ops_bloch_arg(OpsBlochArgs<R> args,
+                                                          double* __restrict__ out,
+                                                          DoneSignal sig) {
+  __shared__ double sh[4 * kMaxMulti * kBlock];
+  const BlochItem<R> it = args.it[blockIdx.x];
+  if (it.op >= 0) {
+    const FactOp<R> op = args.op[it.op];
+    fact_op(op);
+    __syncthreads();  // the sweep reads what the operation wrote
+  }
+  bloch_dispatch(it, sh, out);
+  signal_done(sig);
+}
+
+template <typename R>
+hipError_t launch_ops_bloch(const BlochItem<R>* host_items, const BlochItem<R>* items, int nitems,
+                            const FactOp<R>* host_ops, const FactOp<R>* ops, int nops,
+                            double* out, unsigned* counter, unsigned* flag, unsigned target,
+                            unsigned seq, hipStream_t s) {
+  if (nitems < 1) return hipSuccess;
+  const DoneSignal sig{counter, flag, target, seq};
+  if (g_kernarg_tables && nitems <= kFusedItems && nops <= fused_arg_ops<R>()) {
+    OpsBlochArgs<R> args;
+    for (int i = 0; i < nitems; ++i) args.it[i] = host_items[i];
+    for (int i = 0; i < nops; ++i) args.op[i] = host_ops[i];
+    hipLaunchKernelGGL(k_ops_bloch_arg<R>, dim3(nitems), dim3(kBlock), 0, s, args, out, sig);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_ops_bloch<R>, dim3(nitems), dim3(kBlock), 0, s, items, ops, out, sig);
+  return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_fact_ops(const FactOp<R>* host_ops, const FactOp<R>* ops, int nops,
                            hipStream_t s) {
   if (nops < 1) return hipSuccess;
@@ -739,6 +792,10 @@ hipError_t launch_gather_mul(const R* a, const uint64_t* idx, uint64_t m, Perm64
                                             double*, unsigned*, unsigned*, unsigned,        \
                                             unsigned, hipStream_t);                         \
   template hipError_t launch_fact_ops<R>(const FactOp<R>*, const FactOp<R>*, int, hipStream_t); \
+  template hipError_t launch_ops_bloch<R>(const BlochItem<R>*, const BlochItem<R>*, int,     \
+                                          const FactOp<R>*, const FactOp<R>*, int, double*,  \
+                                          unsigned*, unsigned*, unsigned, unsigned,          \
+                                          hipStream_t);                                      \
   template hipError_t launch_pair_rho<R>(const R*, int, int, int, double*, double*,         \
                                          hipStream_t);                                      \
   template hipError_t launch_decompose_pair<R>(R*, const R*, int, int, int, const double*,  \

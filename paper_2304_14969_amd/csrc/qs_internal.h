@@ -126,6 +126,7 @@ struct BlochItem {
   int nq, G;
   int bits[5];
   int out;
+  int op;  // launch_ops_bloch: the operation to run on amps first, or -1
 };
 // host_items: the same table in host memory; up to kBlochArgItems items travel
 // in the kernel arguments instead of being read through `items`.
@@ -165,10 +166,28 @@ struct FactOp {
   double scale;
   R m[32];  // 4x4, row-major, interleaved
 };
+// Queued operations and the sweeps that read their results in one launch:
+// workgroup i first runs ops[items[i].op] (when >= 0; its output is
+// items[i].amps), then, after a barrier, the sweep of items[i], as
+// launch_bloch_batch (same completion signal). Every operation belongs to
+// exactly one item. Up to kFusedItems items and fused_arg_ops<R>() operations
+// travel in the kernel arguments; larger tables are read through items/ops.
+constexpr int kFusedItems = 16;
+template <typename R>
+constexpr int fused_arg_ops();
+template <typename R>
+hipError_t launch_ops_bloch(const BlochItem<R>* host_items, const BlochItem<R>* items, int nitems,
+                            const FactOp<R>* host_ops, const FactOp<R>* ops, int nops,
+                            double* out, unsigned* counter, unsigned* flag, unsigned target,
+                            unsigned seq, hipStream_t s);
 // Operations per launch that fit the kernel arguments (under 4 KiB).
 template <typename R>
 constexpr int fact_arg_ops() {
   return int(3584 / sizeof(FactOp<R>));
+}
+template <typename R>
+constexpr int fused_arg_ops() {
+  return int((3584 - kFusedItems * sizeof(BlochItem<R>)) / sizeof(FactOp<R>));
 }
 template <typename R>
 hipError_t launch_fact_ops(const FactOp<R>* host_ops, const FactOp<R>* ops, int nops,

@@ -405,3 +405,29 @@ def test_completion_flag_or_stream_sync(qs_lib):
     for a, b in zip(*out):
         assert len(a[0]) > 20 and a[0] == b[0] and a[1] == b[1]
         np.testing.assert_array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_operations_fused_with_their_sweeps(qs_lib, dtype):
+    """Queued merges and projections run in the launch of the sweeps that
+    read their results, or in a launch of their own: identical logs and kets
+    (the same device functions in the same order per subsystem)."""
+    qs = qs_lib
+    n = 16
+    saved = qs.tune_get("factor.fuse_ops")
+    out = []
+    try:
+        for k in (0, 1):
+            qs.tune_set("factor.fuse_ops", k)
+            rows = []
+            for gates, p in ((workloads.grid_circuit(4, 4, 8, 6), 0.3),
+                             (workloads.random_circuit(n, 8, 77), 0.2)):
+                st = gpu_run(qs, n, gates, p, dtype)
+                rows.append((st.attempts(), st.fidelity_estimate(), st.amplitudes()))
+                st.free()
+            out.append(rows)
+    finally:
+        qs.tune_set("factor.fuse_ops", saved)
+    for a, b in zip(*out):
+        assert len(a[0]) > 20 and a[0] == b[0] and a[1] == b[1]
+        np.testing.assert_array_equal(a[2], b[2])
