@@ -890,30 +890,50 @@ int qs_run(qs_state* st, qs_circuit* c) {
     std::vector<double> m;
     std::vector<int> q1;
     std::vector<double> m1;
+    // The host copies of one-qubit subsystems follow each one-qubit gate as it
+    // is queued (so that the Z-eigenstate shortcut sees the circuit's state);
+    // a gate the shortcut reduces to one qubit joins the queued run.
     auto flush_1q = [&]() -> int {
       if (q1.empty()) return QS_OK;
+      f->mirrors_ahead = true;
       const int rc = qs::fact_apply_1q_run(f, q1.data(), m1.data(), int(q1.size()));
+      f->mirrors_ahead = false;
       q1.clear();
       m1.clear();
       return rc;
     };
+    auto push_1q = [&](int q, const double* g8) -> int {
+      // the tests due on q's subsystem run before any gate after them, so
+      // that a qubit they split off starts its host copy before this gate
+      if (qs::fact_pending_on(f, &q, 1))
+        if (int rc = qs::fact_settle(f)) return rc;
+      q1.push_back(q);
+      m1.insert(m1.end(), g8, g8 + 8);
+      qs::fact_mirror_1q(f, q, g8);
+      return QS_OK;
+    };
     auto apply_all = [&]() -> int {
       for (const auto& g : c->gates) {
-        if (g.k == 1) {
-          q1.push_back(g.q[0]);
-          for (int e = 0; e < 4; ++e) {
-            m1.push_back(g.m[e].real());
-            m1.push_back(g.m[e].imag());
-          }
-          continue;
-        }
-        if (int rc = flush_1q()) return rc;
         m.resize(2 * g.m.size());
         for (size_t i = 0; i < g.m.size(); ++i) {
           m[2 * i] = g.m[i].real();
           m[2 * i + 1] = g.m[i].imag();
         }
-        if (int rc = qs::fact_apply(f, g.q, g.k, m.data())) return rc;
+        int qq[QS_MAX_FUSED], k = g.k;
+        for (int j = 0; j < k; ++j) qq[j] = g.q[j];
+        if (k >= 2) {
+          if (qs::fact_pending_on(f, qq, k)) {  // the tests due before this gate
+            if (int rc = flush_1q()) return rc;
+            if (int rc = qs::fact_settle(f)) return rc;
+          }
+          if (qs::fact_reduce(f, qq, &k, &m) && k == 0) continue;
+        }
+        if (k == 1) {
+          if (int rc = push_1q(qq[0], m.data())) return rc;
+          continue;
+        }
+        if (int rc = flush_1q()) return rc;
+        if (int rc = qs::fact_apply(f, qq, k, m.data())) return rc;
       }
       return flush_1q();
     };

@@ -842,6 +842,7 @@ namespace {
 // h <- m h for the host copy of a one-qubit subsystem (m: 2x2, interleaved).
 void mirror_1q(Sub& S, const double* m) {
   if (S.nq != 1 || !S.known) return;
+  // (callers skip this while the host copies already include the gate)
   const double a0r = S.h[0], a0i = S.h[1], a1r = S.h[2], a1i = S.h[3];
   S.h[0] = m[0] * a0r - m[1] * a0i + m[2] * a1r - m[3] * a1i;
   S.h[1] = m[0] * a0i + m[1] * a0r + m[2] * a1i + m[3] * a1r;
@@ -905,31 +906,50 @@ bool is_identity(const std::vector<double>& m, int k) {
 
 }  // namespace
 
+void fact_mirror_1q(FactorState* f, int q, const double* m) {
+  const int si = find(f, q, nullptr);
+  if (si >= 0) mirror_1q(f->subs[si], m);
+}
+
+bool fact_reduce(FactorState* f, int* qubits, int* k, std::vector<double>* m) {
+  if (*k < 2 || !g_unobservable) return false;
+  std::vector<double> red;
+  bool changed = false;
+  for (int j = 0; j < *k && *k > 1;) {
+    int v = 0;
+    if (z_eigenstate(f, qubits[j], &v) && restrict_gate(*m, *k, j, v, &red)) {
+      m->swap(red);
+      for (int t = j; t + 1 < *k; ++t) qubits[t] = qubits[t + 1];
+      --*k;
+      changed = true;
+      ++f->shortcuts;
+      continue;
+    }
+    ++j;
+  }
+  if (changed && is_identity(*m, *k)) *k = 0;
+  return changed;
+}
+
+bool fact_pending_on(const FactorState* f, const int* qubits, int k) {
+  return f->defer && f->dirty && touches_dirty(f, qubits, k);
+}
+
+int fact_settle(FactorState* f) { return f->defer && f->dirty ? flush_pending(f) : QS_OK; }
+
 int fact_apply(FactorState* f, const int* qubits, int k, const double* m) {
+  // deferred tests on the subsystems this gate touches come first (they may
+  // split an operand off into a basis state the shortcut below can use)
+  if (fact_pending_on(f, qubits, k))
+    if (int rc = flush_pending(f)) return rc;
   // unobservable shortcut (Sec. II-B): operands in a Z eigenstate that the
   // gate keeps are dropped from it, so they need no merge
   if (k >= 2 && g_unobservable) {
     int qq[QS_MAX_FUSED], kq = k;
     for (int j = 0; j < k; ++j) qq[j] = qubits[j];
-    std::vector<double> mm(m, m + (size_t(2) << (2 * k))), red;
-    bool changed = false;
-    for (int j = 0; j < kq && kq > 1;) {
-      int v = 0;
-      if (z_eigenstate(f, qq[j], &v) && restrict_gate(mm, kq, j, v, &red)) {
-        mm.swap(red);
-        for (int t = j; t + 1 < kq; ++t) qq[t] = qq[t + 1];
-        --kq;
-        changed = true;
-        ++f->shortcuts;
-        continue;
-      }
-      ++j;
-    }
-    if (changed) return is_identity(mm, kq) ? QS_OK : fact_apply(f, qq, kq, mm.data());
+    std::vector<double> mm(m, m + (size_t(2) << (2 * k)));
+    if (fact_reduce(f, qq, &kq, &mm)) return kq == 0 ? QS_OK : fact_apply(f, qq, kq, mm.data());
   }
-  // deferred tests on the subsystems this gate touches come first
-  if (f->defer && f->dirty && touches_dirty(f, qubits, k))
-    if (int rc = flush_pending(f)) return rc;
   // capacity first, so that a refused gate leaves the state as it was
   int distinct[QS_MAX_FUSED], nd = 0, total = 0;
   for (int j = 0; j < k; ++j) {
@@ -1022,7 +1042,7 @@ int fact_apply(FactorState* f, const int* qubits, int k, const double* m) {
       if (S.q[b] == qubits[j]) local[j] = b;
   hipError_t e;
   if (k == 1) {
-    mirror_1q(S, m);
+    if (!f->mirrors_ahead) mirror_1q(S, m);
     if (f->dtype == QS_C64) {
       Mat2<float> mm;
       for (int i = 0; i < 4; ++i) { mm.re[i] = float(m[2 * i]); mm.im[i] = float(m[2 * i + 1]); }
@@ -1554,7 +1574,7 @@ int apply_1q_run(FactorState* f, const int* qubits, const double* m, int count) 
     int t = 0;
     const int si = find(f, qubits[i], &t);
     if (si < 0) return ffail(QS_E_INVAL, "qubit %d not found", qubits[i]);
-    mirror_1q(f->subs[si], m + 8 * i);
+    if (!f->mirrors_ahead) mirror_1q(f->subs[si], m + 8 * i);
     if (f->subs[si].nq > kFact1qMaxQubits) {
       if (large_of[si] < 0) {
         large_of[si] = int(per_large.size());

@@ -118,6 +118,9 @@ struct FactorState {
   uint64_t deferred = 0;        // dirty qubits skipped on the network's advice
   uint64_t skipped = 0, fallback_tests = 0;
   uint64_t shortcuts = 0;  // operands dropped by the Z-eigenstate shortcut
+  // set while the one-qubit gates being applied are already in the host
+  // copies of the one-qubit subsystems (qs_run updates them as it queues)
+  bool mirrors_ahead = false;
   float* feat_log = nullptr;
   uint64_t feat_cap = 0;
 };
@@ -173,6 +176,17 @@ int fact_end_run(FactorState* f, int rc);
 int fact_block(const FactorState* f, int start, int len, int* t0, bool* descending);
 // Launches whatever is queued (device buffers are then current on the stream).
 int fact_sync(FactorState* f);
+// Deferred mode: does any of the k qubits lie in a subsystem with tests
+// pending? fact_settle runs every pending test.
+bool fact_pending_on(const FactorState* f, const int* qubits, int k);
+int fact_settle(FactorState* f);
+// The Z-eigenstate shortcut on its own: restricts the gate (qubits[0..*k),
+// matrix *m) in place and returns true if any operand was dropped; *k = 0
+// when nothing is left to apply. Host only.
+bool fact_reduce(FactorState* f, int* qubits, int* k, std::vector<double>* m);
+// Applies a one-qubit gate to the host copy of q's subsystem (when it is a
+// known one-qubit subsystem); the device amplitudes are not touched.
+void fact_mirror_1q(FactorState* f, int q, const double* m);
 int fact_swap(FactorState* f, int a, int b);       // relabel
 int fact_relabel(FactorState* f, const int* pos);  // label v -> q where pos[q] = v
 int fact_try_separate(FactorState* f, double p, int* n_separated);

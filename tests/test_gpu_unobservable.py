@@ -134,3 +134,28 @@ def test_qft_twice_on_a_ghz_subsystem(qs_lib, dtype):
     want = dense.run_circuit(want, n, dense.qft_gates(n, 2, 9, True))
     assert_parity(st.amplitudes(), want, dtype, "inverse qft on a sub-range")
     st.free()
+
+
+@pytest.mark.parametrize("defer", [0, 1])
+def test_shortcut_after_a_deferred_rounding(qs_lib, defer):
+    """An iSWAP on |00> merges two qubits that stay |00>; the (deferred) test
+    splits qubit 2 back off as exactly |0>, an X makes it |1>, and the CX it
+    then controls must act on its target: the host copy of the split-off
+    qubit has to include the X although the rounding and the X were queued
+    in the same run."""
+    qs = qs_lib
+    n = 5
+    gates = [("iswap", 2, 3), ("u3", 2, math.pi, 0.0, math.pi), ("cx", 2, 4), ("h", 0),
+             ("cx", 0, 1), ("u3", 3, 0.4, 0.1, 0.2), ("cz", 3, 2)]
+    want = dense.run_circuit(dense.zero_state(n), n, gates)
+    saved = qs.tune_get("factor.defer")
+    try:
+        qs.tune_set("factor.defer", defer)
+        st = qs.State(n, C64, factorized=True)
+        st.set_policy(qs.SEP_AFTER_2Q, 0.1)
+        st.run(qs.Circuit(n).add_gates(gates))
+        assert_parity(st.amplitudes(), want, C64, f"defer={defer}")
+        assert st.shortcut_count() >= 2
+        st.free()
+    finally:
+        qs.tune_set("factor.defer", saved)
