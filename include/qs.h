@@ -200,6 +200,15 @@ int qs_try_separate(qs_state* st, double p, int* n_separated);
  * on a dense state, equal or out-of-range qubits. Synchronizes. */
 int qs_try_separate_pair(qs_state* st, int qa, int qb, double p, int* rounded);
 
+/* The host step of the pair rounding, on its own (no device work): the
+ * largest eigenvalue *lambda of the Hermitian part (h + h^H)/2 of the 4x4
+ * complex matrix h (32 doubles, interleaved, row-major) and its unit
+ * eigenvector phi (8 doubles, interleaved), phase-fixed so that its first
+ * component of magnitude above 1e-9 of the largest is real and positive;
+ * cyclic Jacobi rotations on the 8x8 real embedding, float64. QS_E_INVAL for
+ * NULL pointers or non-finite entries. */
+int qs_hermitian4_top(const double* h, double* lambda, double* phi);
+
 /* Mark qubits (bit q of mask) dirty, e.g. to test a state built elsewhere. */
 int qs_mark_dirty(qs_state* st, uint64_t mask);
 

@@ -118,6 +118,7 @@ _SIGS = [
     ("qs_try_separate_pair", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_double,
                                        C.POINTER(C.c_int)]),
     ("qs_shortcut_count", C.c_int, [C.c_void_p, C.POINTER(C.c_uint64)]),
+    ("qs_hermitian4_top", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("qs_mark_dirty", C.c_int, [C.c_void_p, C.c_uint64]),
     ("qs_fidelity_estimate", C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     ("qs_subsystems", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
@@ -170,6 +171,19 @@ def open_library(path: str = LIB_PATH) -> C.CDLL:
         fn.restype = res
         fn.argtypes = args
     return lib
+
+
+def hermitian4_top(h) -> tuple:
+    """The pair rounding's host step (qs_hermitian4_top): the largest
+    eigenvalue of the Hermitian part of a 4x4 complex matrix and its
+    phase-fixed unit eigenvector. Host code only; needs the library, not a GPU."""
+    lib = _lib if _lib is not None else open_library()
+    hm = np.ascontiguousarray(np.asarray(h, dtype=np.complex128).reshape(4, 4))
+    lam = C.c_double()
+    phi = np.zeros(4, dtype=np.complex128)
+    _check(lib, lib.qs_hermitian4_top(_dptr(hm.view(np.float64)), C.byref(lam),
+                                      _dptr(phi.view(np.float64))))
+    return lam.value, phi
 
 
 def load(use_torch_allocator: bool = True) -> C.CDLL:

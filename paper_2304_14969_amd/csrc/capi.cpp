@@ -1025,6 +1025,14 @@ int qs_try_separate_pair(qs_state* st, int qa, int qb, double p, int* rounded) {
   return QS_OK;
 }
 
+int qs_hermitian4_top(const double* h, double* lambda, double* phi) {
+  if (!h || !lambda || !phi) return fail(QS_E_INVAL, "NULL argument");
+  for (int i = 0; i < 32; ++i)
+    if (!std::isfinite(h[i])) return fail(QS_E_INVAL, "non-finite matrix entry");
+  qs::fact_hermitian4_top(h, lambda, phi);
+  return QS_OK;
+}
+
 int qs_try_separate(qs_state* st, double p, int* n_separated) {
   if (int rc = check_state(st)) return rc;
   if (!(p >= 0.0 && p <= 1.0)) return fail(QS_E_INVAL, "p = %g outside [0, 1]", p);

@@ -200,6 +200,46 @@ void jacobi8(double A[8][8], double w[8], double V[8][8]) {
   for (int i = 0; i < 8; ++i) w[i] = A[i][i];
 }
 
+// The largest eigenvalue of the Hermitian 4x4 matrix hr + i hi and its unit
+// eigenvector phi (interleaved), phase-fixed: its first component of
+// magnitude above 1e-9 of the largest is made real and positive.
+void hermitian4_top(const double hr[4][4], const double hi[4][4], double* lam, double phi[8]) {
+  double A[8][8], w[8], V[8][8];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      A[i][j] = hr[i][j];
+      A[i][j + 4] = -hi[i][j];
+      A[i + 4][j] = hi[i][j];
+      A[i + 4][j + 4] = hr[i][j];
+    }
+  jacobi8(A, w, V);
+  int top = 0;
+  for (int i = 1; i < 8; ++i)
+    if (w[i] > w[top]) top = i;
+  *lam = w[top];
+  double mag = 0.0, big = 0.0;
+  for (int m = 0; m < 4; ++m) {
+    phi[2 * m] = V[m][top];
+    phi[2 * m + 1] = V[m + 4][top];
+    mag += phi[2 * m] * phi[2 * m] + phi[2 * m + 1] * phi[2 * m + 1];
+  }
+  mag = std::sqrt(mag);
+  for (int i = 0; i < 8; ++i) phi[i] /= mag;
+  for (int m = 0; m < 4; ++m) big = std::max(big, std::hypot(phi[2 * m], phi[2 * m + 1]));
+  for (int m = 0; m < 4; ++m) {
+    const double r = std::hypot(phi[2 * m], phi[2 * m + 1]);
+    if (r > 1e-9 * big) {
+      const double cr = phi[2 * m] / r, ci = -phi[2 * m + 1] / r;  // conj of the unit phase
+      for (int j = 0; j < 4; ++j) {
+        const double x = phi[2 * j], y = phi[2 * j + 1];
+        phi[2 * j] = x * cr - y * ci;
+        phi[2 * j + 1] = x * ci + y * cr;
+      }
+      break;
+    }
+  }
+}
+
 // Merge subsystem ib into ia (ia's qubits keep their bits); returns the
 // index of the merged subsystem. The caller checked the capacity.
 int merge(FactorState* f, int ia, int ib, int* out) {
@@ -650,48 +690,14 @@ int decide_pair(FactorState* f, int sa, int qa, int qb, int ta, int tb, const do
       hi[mp][m] = -hi[m][mp];
       k += 2;
     }
-  double A[8][8], w[8], V[8][8];
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) {
-      A[i][j] = hr[i][j];
-      A[i][j + 4] = -hi[i][j];
-      A[i + 4][j] = hi[i][j];
-      A[i + 4][j + 4] = hr[i][j];
-    }
-  jacobi8(A, w, V);
-  int top = 0;
-  for (int i = 1; i < 8; ++i)
-    if (w[i] > w[top]) top = i;
-  const double lam = w[top];
+  double lam = 0.0, phi[8];
+  hermitian4_top(hr, hi, &lam, phi);
   const double eps = std::min(std::max(1.0 - lam, 0.0), 0.75);
   const Sub& S = f->subs[sa];
   const int nq = S.nq;
   if (!(eps <= p / 2.0 + f->tau)) {
     record(f, qa, nq, eps, false, qb);
     return QS_OK;
-  }
-  // phi = x + i y from the top eigenvector, unit norm, phase: its first
-  // component of magnitude above 1e-9 of the largest made real and positive
-  double phi[8], mag = 0.0, big = 0.0;
-  for (int m = 0; m < 4; ++m) {
-    phi[2 * m] = V[m][top];
-    phi[2 * m + 1] = V[m + 4][top];
-    mag += phi[2 * m] * phi[2 * m] + phi[2 * m + 1] * phi[2 * m + 1];
-  }
-  mag = std::sqrt(mag);
-  for (double& x : phi) x /= mag;
-  for (int m = 0; m < 4; ++m) big = std::max(big, std::hypot(phi[2 * m], phi[2 * m + 1]));
-  for (int m = 0; m < 4; ++m) {
-    const double r = std::hypot(phi[2 * m], phi[2 * m + 1]);
-    if (r > 1e-9 * big) {
-      const double cr = phi[2 * m] / r, ci = -phi[2 * m + 1] / r;  // conj of the unit phase
-      for (int j = 0; j < 4; ++j) {
-        const double x = phi[2 * j], y = phi[2 * j + 1];
-        phi[2 * j] = x * cr - y * ci;
-        phi[2 * j + 1] = x * ci + y * cr;
-      }
-      break;
-    }
   }
   // <phi|psi> has squared norm lam * tr
   const double scale = 1.0 / std::sqrt(lam * tr);
@@ -732,6 +738,16 @@ int decide_pair(FactorState* f, int sa, int qa, int qb, int ta, int tb, const do
   return QS_OK;
 }
 
+void fact_hermitian4_top(const double* h, double* lam, double* phi) {
+  double hr[4][4], hi[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {  // the Hermitian part (h + h^H) / 2
+      hr[i][j] = 0.5 * (h[2 * (4 * i + j)] + h[2 * (4 * j + i)]);
+      hi[i][j] = 0.5 * (h[2 * (4 * i + j) + 1] - h[2 * (4 * j + i) + 1]);
+    }
+  hermitian4_top(hr, hi, lam, phi);
+}
+
 int fact_test_pair(FactorState* f, int qa, int qb, double p, bool* rounded) {
   *rounded = false;
   int ta = 0, tb = 0;
@@ -742,9 +758,9 @@ int fact_test_pair(FactorState* f, int qa, int qb, double p, bool* rounded) {
   const Sub& S0 = f->subs[sa];
   hipError_t e = f->dtype == QS_C64
                      ? launch_pair_rho(static_cast<const float*>(S0.amps), S0.nq, ta, tb,
-                                       f->scratch, f->dstat, f->stream)
+                                       f->scratch, f->dstat, nullptr, nullptr, 0, 0, f->stream)
                      : launch_pair_rho(static_cast<const double*>(S0.amps), S0.nq, ta, tb,
-                                       f->scratch, f->dstat, f->stream);
+                                       f->scratch, f->dstat, nullptr, nullptr, 0, 0, f->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
   if (int rc = dev_err(e, "pair density")) return rc;
   double st[16];
@@ -1269,10 +1285,19 @@ int flush_round(FactorState* f, bool* any) {
   }
   // small subsystems: one launch over a table in a pinned slot; when that
   // launch is the whole round, its completion flag replaces the stream sync
-  bool only_small = true;
-  for (const Item& it : items)
-    if (it.G == 0 || f->subs[it.si].nq > kBlochBatchQubits) only_small = false;
-  const bool signal = only_small && g_done_flag && signal_ready(f);
+  bool only_small = true, all_small = true;  // (only_small: and no pair test)
+  int npair = 0;
+  for (const Item& it : items) {
+    if (f->subs[it.si].nq > kBlochBatchQubits) all_small = false;
+    if (it.G == 0) {
+      only_small = false;
+      ++npair;
+    }
+  }
+  only_small = only_small && all_small;
+  // one-workgroup launches only: each workgroup counts itself, the last one
+  // raises the flag
+  const bool signal = all_small && g_done_flag && signal_ready(f);
   // The queued operations (the merges and projections that produced the
   // subsystems about to be swept) run in the sweep's launch when every one of
   // them writes a small subsystem of this round, which it then precedes in
@@ -1320,16 +1345,15 @@ int flush_round(FactorState* f, bool* any) {
     for (size_t k = 0; k < f->qops.size(); ++k) fill_op(f->qops[k], &hops[k]);
   }
   hipError_t e = hipSuccess;
-  unsigned seq = 0;
+  unsigned seq = 0, target = 0;
+  unsigned* counter = nullptr;
+  if (signal) {
+    seq = ++f->sig_seq;
+    f->sig_total += unsigned(nsmall + npair);
+    counter = f->sig_count;
+    target = f->sig_total;
+  }
   if (nsmall) {
-    unsigned* counter = nullptr;
-    unsigned target = 0;
-    if (signal) {
-      seq = ++f->sig_seq;
-      f->sig_total += unsigned(nsmall);
-      counter = f->sig_count;
-      target = f->sig_total;
-    }
     e = fuse ? launch_ops_bloch(static_cast<const BlochItem<R>*>(host),
                                 static_cast<const BlochItem<R>*>(dev), nsmall, hops,
                                 reinterpret_cast<const FactOp<R>*>(static_cast<char*>(dev) + kOpsAt),
@@ -1347,7 +1371,7 @@ int flush_round(FactorState* f, bool* any) {
     const R* a = static_cast<const R*>(S.amps);
     if (items[i].G == 0) {
       e = launch_pair_rho(a, S.nq, items[i].t[0], items[i].t[1], f->scratch, f->dstat + i * kRow,
-                          f->stream);
+                          counter, f->sig_dev, target, seq, f->stream);
       continue;
     }
     if (S.nq <= kBlochBatchQubits) continue;
@@ -1357,7 +1381,7 @@ int flush_round(FactorState* f, bool* any) {
                                  f->stream);
   }
   if (int rc = dev_err(e, "bloch")) return rc;
-  if (signal && nsmall) {
+  if (signal) {
     if (int rc = wait_signal(f, seq)) return rc;
   } else if (int rc = dev_err(hipStreamSynchronize(f->stream), "bloch")) {
     return rc;

@@ -195,6 +195,10 @@ int fact_try_separate(FactorState* f, double p, int* n_separated);
 // their reduced density matrix; at eps_B <= p/2 (+ tau) the pair becomes its
 // own subsystem (qa at bit 0) and the rest of its old subsystem is dirty.
 int fact_test_pair(FactorState* f, int qa, int qb, double p, bool* rounded);
+// The pair rounding's host step: the largest eigenvalue and its phase-fixed
+// unit eigenvector of the Hermitian part of the 4x4 matrix h (interleaved,
+// row-major), by cyclic Jacobi rotations on the 8x8 real embedding.
+void fact_hermitian4_top(const double* h, double* lam, double* phi);
 int fact_gather(FactorState* f, const uint64_t* idx, uint64_t m, double* out);
 int fact_norm(FactorState* f, double* out);
 // Dense copy in `dense` (2^n amplitudes of the same precision); perm_out[q]

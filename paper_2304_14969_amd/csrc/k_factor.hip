@@ -389,7 +389,7 @@ struct MatArg4 {
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_pair_rho(const R* __restrict__ a, uint64_t groups,
                                                      int t1, int t2, double* __restrict__ partial,
-                                                     double* __restrict__ out) {
+                                                     double* __restrict__ out, DoneSignal sig) {
   __shared__ double sh[16 * kBlock];
   double v[16];
 #pragma unroll
@@ -425,6 +425,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_rho(const R* __restrict__ a, ui
       for (int k = 0; k < 16; ++k) partial[k * gridDim.x + blockIdx.x] = v[k];
     }
   }
+  if (gridDim.x == 1) signal_done(sig);  // (launches of several workgroups pass no signal)
 }
 
 // b[u] = scale * sum_m conj(phi_m) a[u with bits t1, t2 set to m] (m = bit t1
@@ -629,17 +630,19 @@ hipError_t launch_fact_1q_batch(const Fact1qItem<R>* host_items, const Fact1qIte
 
 template <typename R>
 hipError_t launch_pair_rho(const R* a, int nq, int t1, int t2, double* scratch, double* out,
+                           unsigned* counter, unsigned* flag, unsigned target, unsigned seq,
                            hipStream_t s) {
   if (nq < 2 || t1 == t2 || t1 < 0 || t2 < 0 || t1 >= nq || t2 >= nq) return hipErrorInvalidValue;
   const uint64_t groups = uint64_t(1) << (nq - 2);
   if ((groups << 2) <= 2 * kSmallPairs) {
     hipLaunchKernelGGL(k_pair_rho<R>, dim3(1), dim3(kBlock), 0, s, a, groups, t1, t2, nullptr,
-                       out);
+                       out, DoneSignal{counter, flag, target, seq});
     return hipGetLastError();
   }
+  if (counter) return hipErrorInvalidValue;  // no signal from a multi-workgroup reduction
   const unsigned nb = red_blocks(groups);
   hipLaunchKernelGGL(k_pair_rho<R>, dim3(nb), dim3(kBlock), 0, s, a, groups, t1, t2, scratch + 8,
-                     nullptr);
+                     nullptr, DoneSignal{nullptr, nullptr, 0, 0});
   hipLaunchKernelGGL(k_sum_rows<16>, dim3(1), dim3(kBlock), 0, s, scratch + 8, int(nb), out);
   return hipGetLastError();
 }
@@ -797,6 +800,7 @@ hipError_t launch_gather_mul(const R* a, const uint64_t* idx, uint64_t m, Perm64
                                           unsigned*, unsigned*, unsigned, unsigned,          \
                                           hipStream_t);                                      \
   template hipError_t launch_pair_rho<R>(const R*, int, int, int, double*, double*,         \
+                                         unsigned*, unsigned*, unsigned, unsigned,          \
                                          hipStream_t);                                      \
   template hipError_t launch_decompose_pair<R>(R*, const R*, int, int, int, const double*,  \
                                                double, R*, hipStream_t);                    \

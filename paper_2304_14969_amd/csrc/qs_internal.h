@@ -106,8 +106,12 @@ hipError_t launch_bloch_multi(const R* a, int nq, const int* bits, int G, double
 // qubits at bits t1 != t2 of a subsystem of nq >= 2 qubits, in float64, to
 // out[16] (rho_00..rho_33, then Re/Im of rho_01, 02, 03, 12, 13, 23; index m
 // = bit t1 + 2 bit t2); scratch as for launch_bloch.
+// counter / flag / target / seq: the completion signal of launch_bloch_batch,
+// only for subsystems of at most 2^15 amplitudes (one workgroup; counter =
+// nullptr otherwise).
 template <typename R>
 hipError_t launch_pair_rho(const R* a, int nq, int t1, int t2, double* scratch, double* out,
+                           unsigned* counter, unsigned* flag, unsigned target, unsigned seq,
                            hipStream_t s);
 // b (nq - 2 qubits) = scale * <phi| a over bits t1, t2 (the two bits removed,
 // the others in order), and pair (2 qubits) = phi; nq >= 3.

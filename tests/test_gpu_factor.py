@@ -431,3 +431,46 @@ def test_operations_fused_with_their_sweeps(qs_lib, dtype):
     for a, b in zip(*out):
         assert len(a[0]) > 20 and a[0] == b[0] and a[1] == b[1]
         np.testing.assert_array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_execution_switches_do_not_change_results(qs_lib, dtype):
+    """Every execution switch of the factorized mode off, then each one on by
+    itself, then all on (deferral, fused operations, kernel-argument tables,
+    flag waits, batched one-qubit runs), on a circuit with controlled gates on
+    basis-state qubits (the shortcut) under the pair policy: the same attempt
+    log, F and ket every time."""
+    qs = qs_lib
+    n = 14
+    g = np.random.default_rng(5)
+    gates = [("u3", q, math.pi, 0.0, math.pi) for q in range(0, n, 3)]   # some |1> qubits
+    for _ in range(20):  # on basis states, then on what they leave
+        a, b = (int(v) for v in g.choice(n, 2, replace=False))
+        gates.append(("ctrl", [a], int(g.integers(0, 2)), b, *g.uniform(0, 2 * math.pi, 3)))
+    gates += workloads.pair_chain_circuit(n, 3, 11)
+    gates += workloads.random_circuit(n, 3, 13)
+    keys = ("factor.defer", "factor.fuse_ops", "factor.kernarg_tables", "factor.done_flag",
+            "factor.batch_1q")
+    saved = {k: qs.tune_get(k) for k in keys}
+    settings = [dict.fromkeys(keys, 0)] + [dict(dict.fromkeys(keys, 0), **{k: 1}) for k in keys]
+    settings.append(dict.fromkeys(keys, 1))
+    runs = []
+    try:
+        for cfg in settings:
+            for k, v in cfg.items():
+                qs.tune_set(k, v)
+            st = qs.State(n, dtype, factorized=True)
+            st.set_policy(qs.SEP_AFTER_2Q_PAIRS, 0.15)
+            st.record_attempts()
+            st.run(qs.Circuit(n).add_gates(gates))
+            runs.append((st.attempts(), st.fidelity_estimate(), st.amplitudes(),
+                         st.shortcut_count()))
+            st.free()
+    finally:
+        for k, v in saved.items():
+            qs.tune_set(k, v)
+    base = runs[0]
+    assert len(base[0]) > 20 and base[3] > 0
+    for r in runs[1:]:
+        assert r[0] == base[0] and r[1] == base[1] and r[3] == base[3]
+        np.testing.assert_allclose(r[2], base[2], rtol=0, atol=1e-12 if dtype == C128 else 2e-7)
