@@ -435,11 +435,13 @@ def test_operations_fused_with_their_sweeps(qs_lib, dtype):
 
 @pytest.mark.parametrize("dtype", [C64, C128])
 def test_execution_switches_do_not_change_results(qs_lib, dtype):
-    """Every execution switch of the factorized mode off, then each one on by
-    itself, then all on (deferral, fused operations, kernel-argument tables,
-    flag waits, batched one-qubit runs), on a circuit with controlled gates on
-    basis-state qubits (the shortcut) under the pair policy: the same attempt
-    log, F and ket every time."""
+    """The execution switches of the factorized mode that reuse the same
+    kernels' arithmetic (deferral, fused operations, kernel-argument tables,
+    flag waits) all off, each on by itself, and all on, on a circuit with
+    controlled gates on basis-state qubits (the shortcut) under the pair
+    policy: the same attempt log, F and ket every time. Batched one-qubit runs
+    change the arithmetic on subsystems past 2^12 amplitudes (tile passes):
+    the same decisions, eps to rounding."""
     qs = qs_lib
     n = 14
     g = np.random.default_rng(5)
@@ -449,11 +451,13 @@ def test_execution_switches_do_not_change_results(qs_lib, dtype):
         gates.append(("ctrl", [a], int(g.integers(0, 2)), b, *g.uniform(0, 2 * math.pi, 3)))
     gates += workloads.pair_chain_circuit(n, 3, 11)
     gates += workloads.random_circuit(n, 3, 13)
-    keys = ("factor.defer", "factor.fuse_ops", "factor.kernarg_tables", "factor.done_flag",
-            "factor.batch_1q")
+    exact_keys = ("factor.defer", "factor.fuse_ops", "factor.kernarg_tables", "factor.done_flag")
+    keys = exact_keys + ("factor.batch_1q",)
     saved = {k: qs.tune_get(k) for k in keys}
-    settings = [dict.fromkeys(keys, 0)] + [dict(dict.fromkeys(keys, 0), **{k: 1}) for k in keys]
-    settings.append(dict.fromkeys(keys, 1))
+    on = dict.fromkeys(keys, 1)
+    off = dict(dict.fromkeys(exact_keys, 0), **{"factor.batch_1q": 1})
+    settings = [off] + [dict(off, **{k: 1}) for k in exact_keys] + [on,
+                                                                     dict(on, **{"factor.batch_1q": 0})]
     runs = []
     try:
         for cfg in settings:
@@ -471,6 +475,11 @@ def test_execution_switches_do_not_change_results(qs_lib, dtype):
             qs.tune_set(k, v)
     base = runs[0]
     assert len(base[0]) > 20 and base[3] > 0
-    for r in runs[1:]:
+    for r in runs[1:-1]:
         assert r[0] == base[0] and r[1] == base[1] and r[3] == base[3]
-        np.testing.assert_allclose(r[2], base[2], rtol=0, atol=1e-12 if dtype == C128 else 2e-7)
+        np.testing.assert_array_equal(r[2], base[2])
+    last = runs[-1]  # batched one-qubit runs off
+    assert [x[:2] + x[3:] for x in last[0]] == [x[:2] + x[3:] for x in base[0]]
+    assert max(abs(x[2] - y[2]) for x, y in zip(last[0], base[0])) <= (1e-10 if dtype == C128 else 1e-5)
+    assert abs(last[1] - base[1]) <= 1e-6 * base[1]
+    np.testing.assert_allclose(last[2], base[2], rtol=0, atol=1e-10 if dtype == C128 else 2e-6)
