@@ -307,6 +307,27 @@ int qs_proposer_stats(const qs_state* st, uint64_t* skipped, uint64_t* fallback_
  * due. *count receives the number of operands dropped so far. */
 int qs_shortcut_count(const qs_state* st, uint64_t* count);
 
+/* Held gates (Table I: controlled phases and inversions buffered and moved
+ * around H; "factor.hold"). In qs_run on a factorized state with no
+ * separation policy, a two-qubit gate that is a controlled phase (control 1:
+ * diag(d0, d1) on the target) or inversion ([[0, d0], [d1, 0]]) between two
+ * subsystems is held back instead of merging them. The state is the held
+ * gates applied to the subsystems' ket; held gates commute with each other.
+ * A later one-qubit gate on a held gate's target conjugates its matrix (H
+ * turns a controlled Z into a controlled X), a diagonal one on its control
+ * passes, a phase with d0 = 1 is symmetric; two held gates on the same
+ * control and target multiply (a controlled Z twice cancels). A gate that
+ * does not commute applies the held gate first, as does the end of the run;
+ * a held gate is applied with the Z-eigenstate shortcut and with the
+ * kickback shortcut: a controlled M whose target is a one-qubit subsystem in
+ * an eigenstate of M (eigenvalue l, at most 1e-24 of the weight off it)
+ * acts as diag(1, l) on its control (a controlled X onto |->: a Z on the
+ * control). Entries within 1e-13 of zero or one are taken as such when
+ * products are classified. The result is the circuit's state (to that
+ * rounding). *held receives the gates held so far, *removed those that never
+ * caused a merge of their own (folded, cancelled or reduced to one qubit). */
+int qs_held_count(const qs_state* st, uint64_t* held, uint64_t* removed);
+
 /* ------------------------------------------------------------ circuits */
 
 /* A circuit is a host-side gate list on n qubits that is fused into dense
@@ -489,6 +510,8 @@ int qs_check(qs_state* st, double tol);
  *                    run of consecutive one-qubit gates in one launch over
  *                    the subsystems of at most 2^12 amplitudes (one
  *                    workgroup per subsystem); 0: one launch per gate;
+ *   "factor.hold"    1 (default): the held gates described at qs_held_count;
+ *                    0: every such gate merges its operands at once;
  *   "fused.mfma"     1 (default): complex64 blocks of 4 or 5 qubits run on the
  *                    matrix cores when their geometry fits; 0: vector FMA.
  * QS_E_INVAL for an unknown key or a value out of range. */

@@ -118,6 +118,7 @@ _SIGS = [
     ("qs_try_separate_pair", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_double,
                                        C.POINTER(C.c_int)]),
     ("qs_shortcut_count", C.c_int, [C.c_void_p, C.POINTER(C.c_uint64)]),
+    ("qs_held_count", C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     ("qs_hermitian4_top", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("qs_mark_dirty", C.c_int, [C.c_void_p, C.c_uint64]),
     ("qs_fidelity_estimate", C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
@@ -640,6 +641,13 @@ class State:
         v = C.c_uint64()
         _check(self.lib, self.lib.qs_shortcut_count(self.h, C.byref(v)))
         return v.value
+
+    def held_count(self):
+        """(gates held back between subsystems, those of them that never
+        caused a merge of their own) so far."""
+        a, b = C.c_uint64(), C.c_uint64()
+        _check(self.lib, self.lib.qs_held_count(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def mark_dirty(self, mask: int):
         _check(self.lib, self.lib.qs_mark_dirty(self.h, int(mask)))

@@ -313,6 +313,9 @@ int qs_tune_set(const char* key, int64_t value) {
   } else if (!std::strcmp(key, "factor.fuse_ops")) {
     if (value < 0 || value > 1) return fail(QS_E_INVAL, "factor.fuse_ops must be 0 or 1");
     qs::g_fuse_ops = int(value);
+  } else if (!std::strcmp(key, "factor.hold")) {
+    if (value < 0 || value > 1) return fail(QS_E_INVAL, "factor.hold must be 0 or 1");
+    qs::g_hold = int(value);
   } else if (!std::strcmp(key, "factor.done_flag")) {
     if (value < 0 || value > 1) return fail(QS_E_INVAL, "factor.done_flag must be 0 or 1");
     qs::g_done_flag = int(value);
@@ -352,6 +355,7 @@ int qs_tune_get(const char* key, int64_t* value) {
   else if (!std::strcmp(key, "factor.kernarg_tables")) *value = qs::g_kernarg_tables;
   else if (!std::strcmp(key, "factor.done_flag")) *value = qs::g_done_flag;
   else if (!std::strcmp(key, "factor.fuse_ops")) *value = qs::g_fuse_ops;
+  else if (!std::strcmp(key, "factor.hold")) *value = qs::g_hold;
   else if (!std::strcmp(key, "factor.tile_1q")) *value = qs::g_tile_1q;
   else if (!std::strcmp(key, "tile.mfma")) *value = g_tile_mfma;
   else if (!std::strcmp(key, "qft.col_max")) *value = g_qft_tune.col_max;
@@ -912,6 +916,118 @@ int qs_run(qs_state* st, qs_circuit* c) {
       qs::fact_mirror_1q(f, q, g8);
       return QS_OK;
     };
+    // Exact runs hold controlled phases and inversions between two
+    // subsystems back (Table I: buffered and moved around H) while later
+    // gates commute with them. The state is then the held gates applied to
+    // the subsystems' ket (with the queued one-qubit run); held gates commute
+    // with each other, so any of them may be applied first. Each is applied
+    // with the shortcuts when a gate does not commute with it and at the end.
+    const bool hold = qs::g_hold && f->policy == QS_SEP_NONE;
+    std::vector<qs::HeldGate>& held = f->held;
+    held.clear();
+    auto apply_held = [&](const qs::HeldGate& hg) -> int {
+      if (int rc = flush_1q()) return rc;
+      int q2[2] = {hg.c, hg.t}, k2 = 2;
+      std::vector<double> h2(32);
+      qs::held_matrix(hg, h2.data());
+      qs::fact_reduce(f, q2, &k2, &h2);
+      if (k2 == 2) qs::fact_kickback(f, q2, &k2, &h2);
+      if (k2 < 2) ++f->held_removed;  // no merge after all
+      if (k2 == 0) return QS_OK;
+      return qs::fact_apply(f, q2, k2, h2.data());
+    };
+    auto apply_held_on = [&](const int* qq, int k, const qs::HeldGate* with) -> int {
+      for (size_t i = 0; i < held.size();) {
+        const qs::HeldGate& hg = held[i];
+        bool on = false;
+        for (int j = 0; j < k; ++j) on |= hg.c == qq[j] || hg.t == qq[j];
+        if (on && !(with && qs::held_commute(*with, hg))) {
+          const qs::HeldGate x = hg;
+          held.erase(held.begin() + long(i));
+          if (int rc = apply_held(x)) return rc;
+          continue;
+        }
+        ++i;
+      }
+      return QS_OK;
+    };
+    // a one-qubit gate moves in front of the held gates on its qubit (which
+    // it conjugates), or the ones it cannot pass are applied first
+    auto hold_1q = [&](int q, const double* u) -> int {
+      for (size_t i = 0; i < held.size();) {
+        qs::HeldGate& hg = held[i];
+        if ((hg.c == q || hg.t == q) && !qs::held_pass_1q(&hg, q, u)) {
+          const qs::HeldGate x = hg;
+          held.erase(held.begin() + long(i));
+          if (int rc = apply_held(x)) return rc;
+          continue;
+        }
+        ++i;
+      }
+      return push_1q(q, u);
+    };
+    // a controlled phase or inversion that commutes with every held gate on
+    // its qubits (the others applied first) and spans two subsystems is held,
+    // folded into a held gate on the same control and target if there is one;
+    // returns 1 when the gate was taken
+    auto hold_2q = [&](const int* qq, const std::vector<double>& gm, int* taken) -> int {
+      *taken = 0;
+      qs::HeldGate g;
+      if (!qs::held_classify(gm.data(), qq, &g)) return apply_held_on(qq, 2, nullptr);
+      if (int rc = apply_held_on(qq, 2, &g)) return rc;
+      if (qs::fact_sub_of(f, g.c) == qs::fact_sub_of(f, g.t)) return QS_OK;
+      int q2[2] = {g.c, g.t}, k2 = 2;
+      std::vector<double> h2(32);
+      qs::held_matrix(g, h2.data());
+      if (qs::fact_reduce(f, q2, &k2, &h2) || qs::fact_kickback(f, q2, &k2, &h2)) {
+        *taken = 1;  // applied to the ket at once: one qubit or nothing
+        return k2 == 0 ? QS_OK : push_1q(q2[0], h2.data());
+      }
+      *taken = 1;
+      ++f->held_in;
+      for (size_t i = 0; i < held.size(); ++i) {
+        qs::HeldGate& hg = held[i];
+        if (hg.c != g.c || hg.t != g.t) continue;
+        // g after hg: the target matrices multiply
+        const std::complex<double> A[4] = {g.inv ? 0.0 : g.d0, g.inv ? g.d0 : 0.0,
+                                           g.inv ? g.d1 : 0.0, g.inv ? 0.0 : g.d1};
+        const std::complex<double> B[4] = {hg.inv ? 0.0 : hg.d0, hg.inv ? hg.d0 : 0.0,
+                                           hg.inv ? hg.d1 : 0.0, hg.inv ? 0.0 : hg.d1};
+        double p4[32];
+        qs::HeldGate x;
+        x.c = g.c;
+        x.t = g.t;
+        std::fill(p4, p4 + 32, 0.0);
+        p4[0] = p4[20] = 1.0;
+        for (int r = 0; r < 2; ++r)
+          for (int cc = 0; cc < 2; ++cc) {
+            const std::complex<double> v = A[2 * r] * B[cc] + A[2 * r + 1] * B[2 + cc];
+            const int e = 4 * (1 + 2 * r) + (1 + 2 * cc);
+            p4[2 * e] = v.real();
+            p4[2 * e + 1] = v.imag();
+          }
+        const int qc[2] = {g.c, g.t};
+        if (!qs::held_classify(p4, qc, &x)) {  // (a product of two such is one)
+          const qs::HeldGate old = hg;
+          held.erase(held.begin() + long(i));
+          if (int rc = apply_held(old)) return rc;
+          return apply_held(g);
+        }
+        held.erase(held.begin() + long(i));
+        ++f->held_removed;  // g folded in
+        if (!x.inv && std::abs(x.d0 - x.d1) <= 1e-13) {
+          // control 1: a global phase d0 on the target = diag(1, d0) on the control
+          ++f->held_removed;
+          if (std::abs(x.d0 - 1.0) <= 1e-13) return QS_OK;  // cancelled
+          const double u[8] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0, x.d0.real(), x.d0.imag()};
+          return push_1q(x.c, u);
+        }
+        held.push_back(x);
+        return QS_OK;
+      }
+      held.push_back(g);
+      return QS_OK;
+    };
     auto apply_all = [&]() -> int {
       for (const auto& g : c->gates) {
         m.resize(2 * g.m.size());
@@ -926,14 +1042,33 @@ int qs_run(qs_state* st, qs_circuit* c) {
             if (int rc = flush_1q()) return rc;
             if (int rc = qs::fact_settle(f)) return rc;
           }
+          if (hold) {
+            int taken = 0;
+            if (k == 2) {
+              if (int rc = hold_2q(qq, m, &taken)) return rc;
+            } else if (int rc = apply_held_on(qq, k, nullptr)) {
+              return rc;
+            }
+            if (taken) continue;
+          }
           if (qs::fact_reduce(f, qq, &k, &m) && k == 0) continue;
+          // (a gate reduced here already commutes with every held gate)
+          if (k == 1) {
+            if (int rc = push_1q(qq[0], m.data())) return rc;
+            continue;
+          }
         }
         if (k == 1) {
-          if (int rc = push_1q(qq[0], m.data())) return rc;
+          if (int rc = hold ? hold_1q(qq[0], m.data()) : push_1q(qq[0], m.data())) return rc;
           continue;
         }
         if (int rc = flush_1q()) return rc;
         if (int rc = qs::fact_apply(f, qq, k, m.data())) return rc;
+      }
+      while (!held.empty()) {
+        const qs::HeldGate x = held.front();
+        held.erase(held.begin());
+        if (int rc = apply_held(x)) return rc;
       }
       return flush_1q();
     };
@@ -1165,6 +1300,14 @@ int qs_shortcut_count(const qs_state* st, uint64_t* count) {
   if (int rc = check_state(st)) return rc;
   if (!count) return fail(QS_E_INVAL, "count is NULL");
   *count = st->fact ? st->fact->shortcuts : 0;
+  return QS_OK;
+}
+
+int qs_held_count(const qs_state* st, uint64_t* held, uint64_t* removed) {
+  if (int rc = check_state(st)) return rc;
+  if (!held || !removed) return fail(QS_E_INVAL, "held or removed is NULL");
+  *held = st->fact ? st->fact->held_in : 0;
+  *removed = st->fact ? st->fact->held_removed : 0;
   return QS_OK;
 }
 

@@ -40,6 +40,7 @@ int g_unobservable = 1;
 int g_kernarg_tables = 1;
 int g_done_flag = 1;
 int g_fuse_ops = 1;
+int g_hold = 1;
 
 void* device_alloc(size_t bytes);
 void device_free(void* p);
@@ -945,6 +946,170 @@ bool fact_reduce(FactorState* f, int* qubits, int* k, std::vector<double>* m) {
   }
   if (changed && is_identity(*m, *k)) *k = 0;
   return changed;
+}
+
+namespace {
+
+using cd = std::complex<double>;
+
+// Entries below this (relative to the largest) count as zero when a product
+// of unitaries is classified; it bounds the change a classification makes.
+constexpr double kHeldTol = 1e-13;
+
+// Is the 4x4 gate m (local bits 0, 1) the identity where local bit cl is 0,
+// with no entry between cl = 0 and cl = 1? M receives the block where cl = 1
+// (rows, columns by the other bit).
+bool controlled_block(const double* m, int cl, cd M[4]) {
+  const int tl = 1 - cl;
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) {
+      const cd v(m[2 * (4 * r + c)], m[2 * (4 * r + c) + 1]);
+      const int cr = (r >> cl) & 1, cc = (c >> cl) & 1;
+      if (cr != cc) {
+        if (std::abs(v) > kHeldTol) return false;
+      } else if (cr == 0) {
+        const double want = ((r >> tl) & 1) == ((c >> tl) & 1) ? 1.0 : 0.0;
+        if (std::abs(v - want) > kHeldTol) return false;
+      } else {
+        M[2 * ((r >> tl) & 1) + ((c >> tl) & 1)] = v;
+      }
+    }
+  return true;
+}
+
+// M as a held gate's matrix: diagonal or anti-diagonal after snapping
+// entries below the tolerance to zero.
+bool phase_or_inversion(cd M[4], bool* inv, cd* d0, cd* d1) {
+  double big = 0.0;
+  for (int i = 0; i < 4; ++i) big = std::max(big, std::abs(M[i]));
+  for (int i = 0; i < 4; ++i)
+    if (std::abs(M[i]) <= kHeldTol * big) M[i] = 0.0;
+  if (M[1] == 0.0 && M[2] == 0.0) {
+    *inv = false;
+    *d0 = M[0];
+    *d1 = M[3];
+    return true;
+  }
+  if (M[0] == 0.0 && M[3] == 0.0) {
+    *inv = true;
+    *d0 = M[1];
+    *d1 = M[2];
+    return true;
+  }
+  return false;
+}
+
+void held_block(const HeldGate& g, cd M[4]) {
+  if (g.inv) {
+    M[0] = 0.0, M[1] = g.d0, M[2] = g.d1, M[3] = 0.0;
+  } else {
+    M[0] = g.d0, M[1] = 0.0, M[2] = 0.0, M[3] = g.d1;
+  }
+}
+
+}  // namespace
+
+bool held_classify(const double* m, const int* qubits, HeldGate* g) {
+  for (int cl = 0; cl < 2; ++cl) {
+    cd M[4];
+    if (!controlled_block(m, cl, M)) continue;
+    HeldGate h;
+    if (!phase_or_inversion(M, &h.inv, &h.d0, &h.d1)) return false;
+    h.c = qubits[cl];
+    h.t = qubits[1 - cl];
+    *g = h;
+    return true;
+  }
+  return false;
+}
+
+bool held_commute(const HeldGate& a, const HeldGate& b) {
+  const bool share = a.c == b.c || a.c == b.t || a.t == b.c || a.t == b.t;
+  if (!share || (!a.inv && !b.inv)) return true;  // disjoint, or both diagonal
+  if (a.c == b.c && a.t == b.t) {                  // one pair, one orientation
+    cd A[4], B[4];
+    held_block(a, A);
+    held_block(b, B);
+    for (int r = 0; r < 2; ++r)
+      for (int c = 0; c < 2; ++c) {
+        const cd ab = A[2 * r] * B[c] + A[2 * r + 1] * B[2 + c];
+        const cd ba = B[2 * r] * A[c] + B[2 * r + 1] * A[2 + c];
+        if (std::abs(ab - ba) > kHeldTol) return false;
+      }
+    return true;
+  }
+  if (a.c == b.t && a.t == b.c) return false;  // one of them an inversion
+  if (a.c == b.c) return true;                 // one control, two targets
+  if (a.t == b.t)  // one target: two inversions [[0,x0],[x1,0]] commute iff a0 b1 = b0 a1
+    return a.inv && b.inv && std::abs(a.d0 * b.d1 - b.d0 * a.d1) <= kHeldTol;
+  if (a.c == b.t) return !b.inv;  // b acts on a's control
+  return !a.inv;                  // a.t == b.c: a acts on b's control
+}
+
+bool held_pass_1q(HeldGate* g, int q, const double* u) {
+  const cd U[4] = {{u[0], u[1]}, {u[2], u[3]}, {u[4], u[5]}, {u[6], u[7]}};
+  HeldGate h = *g;
+  if (q == h.c) {
+    // a diagonal u keeps the control's projectors
+    if (std::abs(U[1]) <= kHeldTol && std::abs(U[2]) <= kHeldTol) return true;
+    // a phase with d0 = 1 is diag(1, 1, 1, d1): symmetric, so q may be its target
+    if (h.inv || std::abs(h.d0 - 1.0) > kHeldTol) return false;
+    std::swap(h.c, h.t);
+  }
+  if (q != h.t) return false;
+  // u (control 1: M) = (control 1: u M u^dagger) u
+  cd M[4], T[4], R[4];
+  held_block(h, M);
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c) T[2 * r + c] = U[2 * r] * M[c] + U[2 * r + 1] * M[2 + c];
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c)
+      R[2 * r + c] = T[2 * r] * std::conj(U[2 * c]) + T[2 * r + 1] * std::conj(U[2 * c + 1]);
+  if (!phase_or_inversion(R, &h.inv, &h.d0, &h.d1)) return false;
+  *g = h;
+  return true;
+}
+
+void held_matrix(const HeldGate& g, double* m) {
+  // local bit 0 = control, bit 1 = target
+  std::fill(m, m + 32, 0.0);
+  m[2 * (4 * 0 + 0)] = 1.0;
+  m[2 * (4 * 2 + 2)] = 1.0;
+  cd M[4];
+  held_block(g, M);
+  for (int tr = 0; tr < 2; ++tr)
+    for (int tc = 0; tc < 2; ++tc) {
+      const int e = 4 * (1 + 2 * tr) + (1 + 2 * tc);
+      m[2 * e] = M[2 * tr + tc].real();
+      m[2 * e + 1] = M[2 * tr + tc].imag();
+    }
+}
+
+int fact_sub_of(const FactorState* f, int q) { return find(f, q, nullptr); }
+
+bool fact_kickback(FactorState* f, int* qubits, int* k, std::vector<double>* m) {
+  if (*k != 2 || !g_unobservable) return false;
+  for (int cl = 0; cl < 2; ++cl) {
+    cd M[4];
+    if (!controlled_block(m->data(), cl, M)) continue;
+    const int si = find(f, qubits[1 - cl], nullptr);
+    if (si < 0) return false;
+    const Sub& S = f->subs[si];
+    if (S.nq != 1 || !S.known) continue;
+    const cd h0(S.h[0], S.h[1]), h1(S.h[2], S.h[3]);
+    const double nn = std::norm(h0) + std::norm(h1);
+    if (!(nn > 0.0)) continue;
+    const cd m0 = M[0] * h0 + M[1] * h1, m1 = M[2] * h0 + M[3] * h1;
+    const cd lam = (std::conj(h0) * m0 + std::conj(h1) * m1) / nn;
+    if (std::norm(m0 - lam * h0) + std::norm(m1 - lam * h1) > 1e-24 * nn) continue;
+    const int c = qubits[cl];
+    qubits[0] = c;
+    *k = std::abs(lam - 1.0) <= 1e-12 ? 0 : 1;
+    m->assign({1.0, 0.0, 0.0, 0.0, 0.0, 0.0, lam.real(), lam.imag()});
+    ++f->shortcuts;
+    return true;
+  }
+  return false;
 }
 
 bool fact_pending_on(const FactorState* f, const int* qubits, int k) {

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <complex>
 #include <cstdint>
 #include <vector>
 
@@ -23,6 +24,15 @@ struct Sub {
   // gates); it decides the Z-eigenstate shortcuts
   bool known = false;
   double h[4] = {0, 0, 0, 0};
+};
+
+// A controlled gate held back instead of merging its two subsystems: when
+// qubit c is 1, qubit t takes diag(d0, d1) (a phase, inv false) or
+// [[0, d0], [d1, 0]] (an inversion, inv true).
+struct HeldGate {
+  int c = 0, t = 0;
+  bool inv = false;
+  std::complex<double> d0{1.0, 0.0}, d1{1.0, 0.0};
 };
 
 struct FactorState {
@@ -118,6 +128,10 @@ struct FactorState {
   uint64_t deferred = 0;        // dirty qubits skipped on the network's advice
   uint64_t skipped = 0, fallback_tests = 0;
   uint64_t shortcuts = 0;  // operands dropped by the Z-eigenstate shortcut
+  // controlled phases and inversions held back between subsystems during one
+  // qs_run (the state is these gates applied to the subsystems' ket)
+  std::vector<HeldGate> held;
+  uint64_t held_in = 0, held_removed = 0;
   // set while the one-qubit gates being applied are already in the host
   // copies of the one-qubit subsystems (qs_run updates them as it queues)
   bool mirrors_ahead = false;
@@ -148,6 +162,12 @@ extern int g_done_flag;
 // Process-wide: queued operations run in the launch of the sweeps that read
 // their results (1, default) or in a launch of their own (0).
 extern int g_fuse_ops;
+// Process-wide: in qs_run on a factorized state with no separation policy,
+// controlled phases and inversions between two subsystems are held back and
+// moved past later gates where they commute (one-qubit gates on their target
+// conjugate them, so H turns a controlled Z into a controlled X), merging
+// only when a gate does not commute or the run ends (1, default); 0: off.
+extern int g_hold;
 
 // The 32 proposal features of qubit q (threshold p) from the bookkeeping.
 void fact_features(const FactorState* f, int q, double p, float* out);
@@ -184,6 +204,25 @@ int fact_settle(FactorState* f);
 // matrix *m) in place and returns true if any operand was dropped; *k = 0
 // when nothing is left to apply. Host only.
 bool fact_reduce(FactorState* f, int* qubits, int* k, std::vector<double>* m);
+// A two-qubit gate (4x4, interleaved, local bit j = qubits[j]) that is a
+// controlled gate whose target matrix is M, with its target a known one-qubit
+// subsystem in an eigenstate of M (eigenvalue lambda, up to a relative weight
+// of 1e-24 off it), acts as diag(1, lambda) on the control alone: restricted
+// in place (*k = 1) and true. Host only.
+bool fact_kickback(FactorState* f, int* qubits, int* k, std::vector<double>* m);
+// Held gates (host only). held_classify: is the 4x4 gate m on (q0, q1) a
+// controlled phase or inversion (g set, control taken as q0 where both read
+// so)? held_commute: do two held gates commute? held_pass_1q: moves the
+// one-qubit gate u on q (a qubit of g) to before g, updating g (u on the
+// target conjugates M; on the control u must be diagonal, or g a symmetric
+// phase that is re-read with q as target); false (g unchanged) when the
+// result is no phase or inversion. held_matrix: the 4x4 on (g.c, g.t).
+bool held_classify(const double* m, const int* qubits, HeldGate* g);
+bool held_commute(const HeldGate& a, const HeldGate& b);
+bool held_pass_1q(HeldGate* g, int q, const double* u);
+void held_matrix(const HeldGate& g, double* m);
+// Index of the subsystem holding qubit q, or -1.
+int fact_sub_of(const FactorState* f, int q);
 // Applies a one-qubit gate to the host copy of q's subsystem (when it is a
 // known one-qubit subsystem); the device amplitudes are not touched.
 void fact_mirror_1q(FactorState* f, int q, const double* m);

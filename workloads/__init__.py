@@ -191,3 +191,53 @@ def pair_chain_circuit(n: int, layers: int, seed: int, theta_max: float = 0.3) -
         for k in range(0, n - 2, 2):
             gates += [("ctrl", [k + 1], 1, k + 2, float(th[k // 2]), 0.0, 0.0), cx(k + 2, k + 3)]
     return gates
+
+
+# X, Y, Z with exact entries, as "mat" gates
+PAULI_MATS = (((0, 1), (1, 0)), ((0, -1j), (1j, 0)), ((1, 0), (0, -1)))
+
+
+def held_gate_mix(n: int, count: int, seed: int) -> list:
+    """Gate sequence dominated by the forms a factorized engine can hold back
+    between subsystems (controlled phases and inversions: CZ, CX, CY, CP) and
+    by the one-qubit gates that move them (H, Pauli gates, phase gates as U3
+    with theta = 0), with a few general U3 and anti-controlled X gates that do
+    not commute with them; for parity tests of that bookkeeping."""
+    g = rng(seed)
+    gates: list = []
+    for _ in range(count):
+        u = g.random()
+        q = int(g.integers(0, n))
+        if u < 0.30:
+            gates.append(("h", q))
+        elif u < 0.40:
+            gates.append(("mat", [q], PAULI_MATS[int(g.integers(0, 3))]))
+        elif u < 0.48:
+            gates.append(("u3", q, 0.0, 0.0, float(g.uniform(0.0, TWO_PI))))
+        elif u < 0.52:
+            t, p, l = g.uniform(0.0, TWO_PI, 3)
+            gates.append(("u3", q, float(t), float(p), float(l)))
+        else:
+            a, b = (int(v) for v in g.choice(n, 2, replace=False))
+            k = ("cz", "cx", "cy", "cp", "cp", "ax")[int(g.integers(0, 6))]
+            if k == "cp":
+                th = float(np.pi / 4 * int(g.integers(1, 8))) if g.random() < 0.5 \
+                    else float(g.uniform(0.0, TWO_PI))
+                gates.append(("cp", a, b, th))
+            else:
+                gates.append((k, a, b))
+    return gates
+
+
+def phase_kickback_circuit(n: int, seed: int):
+    """Bernstein-Vazirani circuit on n qubits: an ancilla (qubit n - 1) in
+    |->, every data qubit in |+>, a CX from each data qubit whose secret bit
+    is 1 onto the ancilla, then H on the data qubits, which then hold the
+    secret. Returns (gates, secret)."""
+    g = rng(seed)
+    secret = [int(v) for v in g.integers(0, 2, n - 1)]
+    anc = n - 1
+    gates: list = [("mat", [anc], PAULI_MATS[0])] + [("h", q) for q in range(n)]
+    gates += [("cx", q, anc) for q in range(n - 1) if secret[q]]
+    gates += [("h", q) for q in range(n - 1)]
+    return gates, secret
