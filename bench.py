@@ -271,6 +271,56 @@ def bench_qft_factorized(qs, workloads, np, torch) -> dict:
     return out
 
 
+def bench_held(qs, workloads, np, torch) -> dict:
+    """Held controlled phases and inversions (factor.hold) in exact factorized
+    runs, on and off: Bernstein-Vazirani circuits (every CX lands on an
+    ancilla in |->) and a mix of controlled phases, inversions and the
+    one-qubit gates that move them; cap 2^30 amplitudes, complex64."""
+    out = {"workload": "exact factorized runs, complex64, cap 2^30: Bernstein-Vazirani "
+                       "(n - 1 data qubits, ancilla in |->); held_gate_mix (2000 gates)"}
+    saved = qs.tune_get("factor.hold")
+
+    def run(n, gates, hold, reps):
+        qs.tune_set("factor.hold", hold)
+        ts, info = [], {}
+        for _ in range(reps):
+            st = qs.State(n, qs.C64, factorized=True, max_amps=2 ** 30)
+            c = qs.Circuit(n).add_gates(gates)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            try:
+                st.run(c)
+                torch.cuda.synchronize()
+            except qs.CapacityError as e:
+                info = {"completed": False, "error": str(e)[:80]}
+                st.free()
+                c.free()
+                break
+            ts.append(time.perf_counter() - t0)
+            subs = st.subsystems()
+            held, removed = st.held_count()
+            info = {"completed": True, "largest_subsystem": max(len(x) for x in subs),
+                    "subsystems": len(subs), "held": held, "removed": removed,
+                    "shortcuts": st.shortcut_count()}
+            st.free()
+            c.free()
+        if ts:
+            info["ms_median"] = round(float(np.median(ts)) * 1e3, 3)
+        return info
+
+    try:
+        for n in (24, 40, 55):
+            gates, secret = workloads.phase_kickback_circuit(n, n)
+            for hold in (1, 0):
+                out[f"bv_n{n}_hold{hold}"] = dict(run(n, gates, hold, 5), ones=sum(secret))
+        gates = workloads.held_gate_mix(24, 2000, 7)
+        for hold in (1, 0):
+            out[f"mix_n24_hold{hold}"] = run(24, gates, hold, 3)
+    finally:
+        qs.tune_set("factor.hold", saved)
+    return out
+
+
 def bench_batch(qs, workloads, torch, count: int = 1024, seed: int = 300, depth: int = 8) -> dict:
     """Many small random circuits (12-20 qubits) in one arena: batched tile
     passes (one launch per pass index over all kets), batched fused blocks
@@ -374,7 +424,8 @@ def main() -> int:
     ap.add_argument("--quick", action="store_true",
                     help="only the QFT (skip the circuit, approximate, batch and validation runs)")
     ap.add_argument("--section", action="append", default=[],
-                    choices=["circuit", "approx", "pairs", "qft_factorized", "batch", "validation",
+                    choices=["circuit", "approx", "pairs", "qft_factorized", "held", "batch",
+                             "validation",
                              "depth_sweep", "heat_maps"],
                     help="run only these secondary sections (repeatable; default: all)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -508,8 +559,8 @@ def main() -> int:
     if not args.quick:
         from paper_2304_14969_amd import protocol
         sec = {}
-        want = set(args.section) or {"circuit", "approx", "pairs", "qft_factorized", "batch",
-                                     "validation"}
+        want = set(args.section) or {"circuit", "approx", "pairs", "qft_factorized", "held",
+                                     "batch", "validation"}
         if "circuit" in want:
             sec["circuit_n32"] = bench_circuit(qs, workloads, torch)
         if "approx" in want:
@@ -519,6 +570,8 @@ def main() -> int:
             sec["pair_chain54"] = bench_pairs(qs, workloads, np, torch)
         if "qft_factorized" in want:
             sec["qft_factorized"] = bench_qft_factorized(qs, workloads, np, torch)
+        if "held" in want:
+            sec["held"] = bench_held(qs, workloads, np, torch)
         if "batch" in want:
             sec["batch1024"] = bench_batch(qs, workloads, torch)
         if "validation" in want:
