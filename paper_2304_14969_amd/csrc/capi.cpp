@@ -975,7 +975,7 @@ int qs_run(qs_state* st, qs_circuit* c) {
       qs::HeldGate g;
       if (!qs::held_classify(gm.data(), qq, &g)) return apply_held_on(qq, 2, nullptr);
       if (int rc = apply_held_on(qq, 2, &g)) return rc;
-      if (qs::fact_sub_of(f, g.c) == qs::fact_sub_of(f, g.t)) return QS_OK;
+      // (both shortcuts need an operand that is a subsystem of its own)
       int q2[2] = {g.c, g.t}, k2 = 2;
       std::vector<double> h2(32);
       qs::held_matrix(g, h2.data());
@@ -983,6 +983,7 @@ int qs_run(qs_state* st, qs_circuit* c) {
         *taken = 1;  // applied to the ket at once: one qubit or nothing
         return k2 == 0 ? QS_OK : push_1q(q2[0], h2.data());
       }
+      if (qs::fact_sub_of(f, g.c) == qs::fact_sub_of(f, g.t)) return QS_OK;
       *taken = 1;
       ++f->held_in;
       for (size_t i = 0; i < held.size(); ++i) {
@@ -1043,6 +1044,18 @@ int qs_run(qs_state* st, qs_circuit* c) {
             if (int rc = qs::fact_settle(f)) return rc;
           }
           if (hold) {
+            // with no held gate on its qubits the gate commutes with all of
+            // them, and the shortcut may take it at once
+            bool touched = false;
+            for (const auto& hg : held)
+              for (int j = 0; j < k; ++j) touched |= hg.c == qq[j] || hg.t == qq[j];
+            if (!touched && qs::fact_reduce(f, qq, &k, &m)) {
+              if (k == 0) continue;
+              if (k == 1) {
+                if (int rc = push_1q(qq[0], m.data())) return rc;
+                continue;
+              }
+            }
             int taken = 0;
             if (k == 2) {
               if (int rc = hold_2q(qq, m, &taken)) return rc;

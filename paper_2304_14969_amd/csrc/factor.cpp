@@ -966,10 +966,10 @@ bool controlled_block(const double* m, int cl, cd M[4]) {
       const cd v(m[2 * (4 * r + c)], m[2 * (4 * r + c) + 1]);
       const int cr = (r >> cl) & 1, cc = (c >> cl) & 1;
       if (cr != cc) {
-        if (std::abs(v) > kHeldTol) return false;
+        if (std::norm(v) > kHeldTol * kHeldTol) return false;
       } else if (cr == 0) {
         const double want = ((r >> tl) & 1) == ((c >> tl) & 1) ? 1.0 : 0.0;
-        if (std::abs(v - want) > kHeldTol) return false;
+        if (std::norm(v - want) > kHeldTol * kHeldTol) return false;
       } else {
         M[2 * ((r >> tl) & 1) + ((c >> tl) & 1)] = v;
       }
