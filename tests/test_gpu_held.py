@@ -144,3 +144,33 @@ def test_holding_is_off_under_a_separation_policy(qs_lib):
     want = dense.run_circuit(dense.zero_state(n), n, gates)
     assert compare(st.amplitudes(), want, C128)["infidelity"] <= 1e-3
     st.free()
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_held_gates_with_relabels_and_wider_gates(qs_lib, dtype):
+    """The gate mix with SWAPs (relabels of the circuit's positions), iSWAPs
+    (two-qubit gates that are neither phase nor inversion) and random
+    three-qubit unitaries (which apply the held gates on all three qubits
+    first) interleaved: the oracle's ket."""
+    qs = qs_lib
+    n = 9
+    g = np.random.default_rng(17)
+    gates = []
+    for i, gate in enumerate(workloads.held_gate_mix(n, 240, 17)):
+        gates.append(gate)
+        if i % 15 == 7:
+            a, b = (int(v) for v in g.choice(n, 2, replace=False))
+            gates.append(("swap", a, b))
+        if i % 40 == 20:
+            a, b = (int(v) for v in g.choice(n, 2, replace=False))
+            gates.append(("iswap", a, b))
+        if i % 60 == 30:
+            qs3 = [int(v) for v in g.choice(n, 3, replace=False)]
+            z = g.normal(size=(8, 8)) + 1j * g.normal(size=(8, 8))
+            u, _ = np.linalg.qr(z)
+            gates.append(("mat", qs3, u))
+    want = dense.run_circuit(dense.zero_state(n), n, gates)
+    st = _run(qs, n, dtype, gates, 1)
+    assert_parity(st.amplitudes(), want, dtype, "relabels and wider gates")
+    assert st.held_count()[0] > 0
+    st.free()
