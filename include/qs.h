@@ -391,7 +391,11 @@ int qs_circuit_info(const qs_circuit* c, int* ngates, int* nblocks, int* max_k);
 int qs_circuit_block(const qs_circuit* c, int i, int* k, int* qubits, double* m);
 /* Apply a circuit to a state of the same width (plans it first if needed).
  * Block matrices are uploaded once per precision and kept with the circuit.
- * Complex64 blocks of 4-5 qubits run on the matrix cores. */
+ * Complex64 blocks of 4-5 qubits run on the matrix cores. A factorized state
+ * takes the gates one by one under its separation policy (see
+ * qs_held_count for the gates an exact run holds back); when a gate fails
+ * there (QS_E_CAPACITY: a merge past the state's cap), the gates before it
+ * are applied, held gates are dropped, and the state is not the circuit's. */
 int qs_run(qs_state* st, qs_circuit* c);
 
 /* ------------------------------------------------------------ batches */
