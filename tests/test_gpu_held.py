@@ -174,3 +174,19 @@ def test_held_gates_with_relabels_and_wider_gates(qs_lib, dtype):
     assert_parity(st.amplitudes(), want, dtype, "relabels and wider gates")
     assert st.held_count()[0] > 0
     st.free()
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_kickback_onto_y_eigenstates(qs_lib, dtype):
+    """A CY onto |+i> (eigenvalue +1) disappears, a CY onto |-i> (eigenvalue
+    -1) is a Z on its control: no merge, the oracle's ket."""
+    qs = qs_lib
+    n = 4
+    gates = [("h", 0), ("h", 1), ("u3", 1, 0.0, 0.0, math.pi / 2), ("cy", 0, 1),
+             ("h", 3), ("h", 2), ("u3", 2, 0.0, 0.0, -math.pi / 2), ("cy", 3, 2), ("h", 3)]
+    want = dense.run_circuit(dense.zero_state(n), n, gates)
+    st = _run(qs, n, dtype, gates, 1)
+    assert_parity(st.amplitudes(), want, dtype, "cy kickback")
+    assert sorted(len(s) for s in st.subsystems()) == [1] * n
+    assert st.shortcut_count() == 2 and st.held_count() == (0, 0)
+    st.free()
