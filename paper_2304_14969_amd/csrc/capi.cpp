@@ -969,7 +969,7 @@ int qs_run(qs_state* st, qs_circuit* c) {
     // a controlled phase or inversion that commutes with every held gate on
     // its qubits (the others applied first) and spans two subsystems is held,
     // folded into a held gate on the same control and target if there is one;
-    // returns 1 when the gate was taken
+    // *taken = 1 when the gate needs nothing more (held, folded or reduced)
     auto hold_2q = [&](const int* qq, const std::vector<double>& gm, int* taken) -> int {
       *taken = 0;
       qs::HeldGate g;
