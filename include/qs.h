@@ -316,7 +316,8 @@ int qs_shortcut_count(const qs_state* st, uint64_t* count);
  * A later one-qubit gate on a held gate's target conjugates its matrix (H
  * turns a controlled Z into a controlled X), a diagonal one on its control
  * passes, a phase with d0 = 1 is symmetric; two held gates on the same
- * control and target multiply (a controlled Z twice cancels). A gate that
+ * control and target (or two such phases on one pair, either way round)
+ * multiply (a controlled Z twice cancels). A gate that
  * does not commute applies the held gate first, as does the end of the run;
  * a held gate is applied with the Z-eigenstate shortcut and with the
  * kickback shortcut: a controlled M whose target is a one-qubit subsystem in

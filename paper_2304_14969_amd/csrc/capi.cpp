@@ -988,6 +988,11 @@ int qs_run(qs_state* st, qs_circuit* c) {
       ++f->held_in;
       for (size_t i = 0; i < held.size(); ++i) {
         qs::HeldGate& hg = held[i];
+        // phases with d0 = 1 are symmetric: one on the reversed pair is read
+        // with this orientation
+        if (hg.c == g.t && hg.t == g.c && !hg.inv && !g.inv &&
+            std::abs(hg.d0 - 1.0) <= 1e-13 && std::abs(g.d0 - 1.0) <= 1e-13)
+          std::swap(hg.c, hg.t);
         if (hg.c != g.c || hg.t != g.t) continue;
         // g after hg: the target matrices multiply
         const std::complex<double> A[4] = {g.inv ? 0.0 : g.d0, g.inv ? g.d0 : 0.0,

@@ -51,12 +51,13 @@ def test_held_gate_mix_matches_the_oracle(qs_lib, dtype, seed):
 def test_cancelling_and_conjugated_pairs(qs_lib, dtype):
     """|+>^6; CZ(0,1) twice cancels; CZ(2,3), H(3), CX(2,3): H turns the held
     CZ into a CX, which the second CX cancels; CP(4,5, pi/4) then
-    CP(4,5, -pi/4) cancels; no subsystem ever merges."""
+    CP(5,4, -pi/4) (the same phase read from the other side) cancels; no
+    subsystem ever merges."""
     qs = qs_lib
     n = 6
     gates = [("h", q) for q in range(n)]
     gates += [("cz", 0, 1), ("cz", 0, 1), ("cz", 2, 3), ("h", 3), ("cx", 2, 3),
-              ("cp", 4, 5, math.pi / 4), ("cp", 4, 5, -math.pi / 4)]
+              ("cp", 4, 5, math.pi / 4), ("cp", 5, 4, -math.pi / 4)]
     want = dense.run_circuit(dense.zero_state(n), n, gates)
     st = _run(qs, n, dtype, gates, 1)
     assert_parity(st.amplitudes(), want, dtype, "held pairs")
