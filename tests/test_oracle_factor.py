@@ -222,3 +222,74 @@ def test_decisions_obey_rule_and_F_nonincreasing():
     for att in st.log:
         assert att.rounded == (att.eps <= 0.05 + factor.TAU)
     assert abs(dense.norm2(st.expand()) - 1) < 1e-12
+
+
+def load_schedule_cases(name):
+    """Parse the hand-worked schedule cases (format in the file's header)."""
+    cases, cur = [], None
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.split("#", 1)[0].split()
+            if not line:
+                continue
+            kind, args = line[0], line[1:]
+            if kind == "case":
+                cur = {"name": args[0], "n": int(args[1]), "p": float(args[2]),
+                       "amps": {}, "atts": [], "F": None}
+                cases.append(cur)
+            elif kind == "amp":
+                cur["amps"][int(args[0])] = float(args[1])
+            elif kind == "att":
+                cur["atts"].append((int(args[0]), int(args[1]), bool(int(args[2])), float(args[3])))
+            elif kind == "F":
+                cur["F"] = float(args[0])
+    return cases
+
+
+@pytest.mark.parametrize("case", load_schedule_cases("sdrp_schedule.txt"), ids=lambda c: c["name"])
+def test_golden_schedule_order(case):
+    """The attempt sequence (qubit, n_S, rounded, eps) of the dirty-set
+    schedule inside one subsystem, worked by hand (Sec. III-A, Eq. sdrp)."""
+    n = case["n"]
+    amps = np.zeros(2 ** n, dtype=complex)
+    for idx, w in case["amps"].items():
+        amps[idx] = math.sqrt(w)
+    st = factor.FactorizedState(n)
+    st.subs = [factor.Sub(list(range(n)), amps)]
+    st.dirty = set(range(n))
+    st.try_separate(case["p"])
+    got = [(a.qubit, a.n_sub, a.rounded) for a in st.log]
+    assert got == [(q, ns, r) for q, ns, r, _ in case["atts"]]
+    for a, (_, _, _, e) in zip(st.log, case["atts"]):
+        assert a.eps == pytest.approx(e, abs=1e-12)
+    assert st.F == pytest.approx(case["F"], abs=1e-12)
+    assert not st.dirty
+
+
+def fixed_point_violations(family, seeds=range(40),
+                           ps=(0.05, 0.15, 0.25, 0.35, 0.45, 0.55, 0.65, 0.75, 0.85, 0.95)):
+    """Runs whose end state still holds a testable qubit: one with eps <= p/2
+    inside a multi-qubit subsystem. eps is taken from the SVD of the qubit /
+    rest bipartition, not from the oracle's Bloch vector."""
+    bad = []
+    for seed in seeds:
+        gates = (workloads.random_circuit(8, 4, 1000 + seed) if family == "matching"
+                 else workloads.grid_circuit(2, 4, 4, 1000 + seed))
+        for p in ps:
+            st = factor.FactorizedState(8).run(gates, p)
+            for S in st.subs:
+                nq = len(S.qubits)
+                if nq < 2:
+                    continue
+                for t in range(nq):
+                    if svd_eps(S.amps, nq, t) <= p / 2.0 + factor.TAU - 1e-10:
+                        bad.append((seed, p, S.qubits[t]))
+    return bad
+
+
+@pytest.mark.parametrize("family", ["matching", "grid"])
+def test_schedule_reaches_fixed_point(family):
+    """After a run no rounding is left undone: every qubit that shares a
+    subsystem with others has eps > p/2 (Eq. sdrp). The dirty-set schedule is
+    exhaustive only if every co-member of a rounded qubit is retested."""
+    assert fixed_point_violations(family) == []

@@ -1,5 +1,6 @@
 """Pins of the FP64 proposal-network oracle: central finite differences of the
-loss, closed-form special cases and the first Adam step."""
+loss, closed-form special cases, the first Adam step, Adam over five steps
+of a constant gradient and two steps worked by hand."""
 import math
 
 import numpy as np
@@ -84,3 +85,41 @@ def test_training_reduces_loss_on_separable_labels():
     for step in range(1, 201):
         mlp.adam_step(p, mlp.backward(p, x, y), m, v, step, lr=1e-2)
     assert mlp.loss(p, x, y) < 0.3 * l0
+
+
+def test_adam_constant_gradient_moves_lr_each_step():
+    """With the same gradient every step the bias-corrected moments equal g and
+    g^2 exactly (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so each of the
+    steps moves every parameter by lr * sign(g) when eps = 0."""
+    p = mlp.init_params(7)
+    x = np.random.default_rng(8).standard_normal((16, 32))
+    y = (np.arange(16) % 2).astype(float)
+    g = mlp.backward(p, x, y)
+    m = {k: np.zeros(s) for k, s in mlp.SHAPES}
+    v = {k: np.zeros(s) for k, s in mlp.SHAPES}
+    for step in range(1, 6):
+        before = {k: p[k].copy() for k in p}
+        mlp.adam_step(p, g, m, v, step=step, lr=1e-3, eps=0.0)
+        for k, _ in mlp.SHAPES:
+            nz = g[k] != 0
+            np.testing.assert_allclose((before[k] - p[k])[nz], 1e-3 * np.sign(g[k][nz]),
+                                       rtol=1e-9)
+
+
+def test_adam_two_steps_by_hand():
+    """Every parameter 0.5, gradient 1 then -2, lr 0.1, b1 0.9, b2 0.999, eps 0.
+    Step 1: m = 0.1, v = 0.001, corrected 1 and 1, so 0.5 -> 0.4.
+    Step 2: m = 0.09 - 0.2 = -0.11, v = 0.000999 + 0.004 = 0.004999;
+    corrected m = -0.11/0.19 = -11/19, v = 0.004999/0.001999 = 4999/1999;
+    0.4 -> 0.4 + (11/190) * sqrt(1999/4999) = 0.43661035270358456."""
+    p = {k: np.full(s, 0.5) for k, s in mlp.SHAPES}
+    m = {k: np.zeros(s) for k, s in mlp.SHAPES}
+    v = {k: np.zeros(s) for k, s in mlp.SHAPES}
+    mlp.adam_step(p, {k: np.full(s, 1.0) for k, s in mlp.SHAPES}, m, v, 1,
+                  lr=0.1, eps=0.0)
+    for k, _ in mlp.SHAPES:
+        np.testing.assert_allclose(p[k], 0.4, rtol=1e-14)
+    mlp.adam_step(p, {k: np.full(s, -2.0) for k, s in mlp.SHAPES}, m, v, 2,
+                  lr=0.1, eps=0.0)
+    for k, _ in mlp.SHAPES:
+        np.testing.assert_allclose(p[k], 0.43661035270358456, rtol=1e-14)

@@ -188,3 +188,41 @@ def test_projection_without_conjugate_phi_is_caught(monkeypatch):
         return b / math.sqrt(float(np.vdot(b, b).real))
     monkeypatch.setattr(factor, "project_out_pair", bad)
     _fails(tp.test_projection_overlap_is_dominant_weight, 1)
+
+
+# ------------------------------------------------------------ schedule and optimizer
+def test_rest_not_marked_dirty_after_rounding_is_caught(monkeypatch):
+    good = factor.FactorizedState.test_qubit
+
+    def bad(self, q, p):
+        before = set(self.dirty)
+        rounded = good(self, q, p)
+        if rounded:
+            self.dirty = before - {q}  # the co-members keep their old marks
+        return rounded
+    monkeypatch.setattr(factor.FactorizedState, "test_qubit", bad)
+    assert tf.fixed_point_violations("matching") + tf.fixed_point_violations("grid")
+
+
+def test_highest_dirty_first_is_caught(monkeypatch):
+    def bad(self, p):
+        count = 0
+        while self.dirty:
+            count += int(self.test_qubit(max(self.dirty), p))
+        return count
+    monkeypatch.setattr(factor.FactorizedState, "try_separate", bad)
+    for case in tf.load_schedule_cases("sdrp_schedule.txt"):
+        _fails(tf.test_golden_schedule_order, case)
+
+
+def test_adam_without_momentum_accumulation_is_caught(monkeypatch):
+    def bad(params, grads, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        for k, _ in mlp.SHAPES:
+            m[k] = (1.0 - b1) * grads[k]  # the b1 * m term dropped
+            v[k] = b2 * v[k] + (1.0 - b2) * grads[k] ** 2
+            mh = m[k] / (1.0 - b1 ** step)
+            vh = v[k] / (1.0 - b2 ** step)
+            params[k] = params[k] - lr * mh / (np.sqrt(vh) + eps)
+    monkeypatch.setattr(mlp, "adam_step", bad)
+    _fails(tm.test_adam_constant_gradient_moves_lr_each_step)
+    _fails(tm.test_adam_two_steps_by_hand)
