@@ -136,6 +136,39 @@ def bench_circuit(qs, workloads, torch, n: int = 32, layers: int = 10, seed: int
     return out
 
 
+def bench_qft_sizes(qs, workloads, torch, sizes=range(28, 33), steps: int = 5) -> dict:
+    """Exact QFT at 28 to 32 qubits (complex64, 2 to 32 GiB): time per
+    transform, passes, and each pass kernel's average time and GB/s. The
+    state is made dense by transforming a basis state first (pass times do
+    not depend on the values)."""
+    out = {"workload": "exact QFT on n = 28 ... 32 qubits, complex64 (2 - 32 GiB), dense state "
+                       "(QFT of a basis state, x from seed n), resident in HBM"}
+    for n in sizes:
+        st = qs.State(n, qs.C64)
+        st.set_basis(workloads.basis_index(n, n))
+        st.qft()
+        st.qft()
+        stream = torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        st.profile_start()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            st.qft()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        prof = st.profile_stop()
+        ms = e0.elapsed_time(e1) / steps
+        passes = sum(v["launches"] for v in prof.values()) / steps
+        total = sum(v["bytes"] for v in prof.values()) / steps
+        out[f"n{n}"] = {"ms_per_qft": round(ms, 4), "passes": passes,
+                        "hbm_GBps_effective": round(total / (ms * 1e-3) / 1e9, 1),
+                        "kernels": _kernel_rates(prof), "norm_after": st.norm()}
+        st.free()
+        print(f"qft sizes: n={n} done ({ms:.3f} ms per transform)", file=sys.stderr, flush=True)
+    return out
+
+
 def bench_approx(qs, workloads, protocol, np, family: str, p_cmp: float = 0.6,
                  test_seeds=range(10), train_seeds=range(10000, 10060),
                  train_ps=(0.7, 0.6, 0.5), min_qubits: int = 12) -> dict:
@@ -424,7 +457,7 @@ def main() -> int:
     ap.add_argument("--quick", action="store_true",
                     help="only the QFT (skip the circuit, approximate, batch and validation runs)")
     ap.add_argument("--section", action="append", default=[],
-                    choices=["circuit", "approx", "pairs", "qft_factorized", "held", "batch",
+                    choices=["qft_sizes", "circuit", "approx", "pairs", "qft_factorized", "held", "batch",
                              "validation",
                              "depth_sweep", "heat_maps"],
                     help="run only these secondary sections (repeatable; default: all)")
@@ -559,8 +592,10 @@ def main() -> int:
     if not args.quick:
         from paper_2304_14969_amd import protocol
         sec = {}
-        want = set(args.section) or {"circuit", "approx", "pairs", "qft_factorized", "held",
+        want = set(args.section) or {"qft_sizes", "circuit", "approx", "pairs", "qft_factorized", "held",
                                      "batch", "validation"}
+        if "qft_sizes" in want:
+            sec["qft_sizes"] = bench_qft_sizes(qs, workloads, torch)
         if "circuit" in want:
             sec["circuit_n32"] = bench_circuit(qs, workloads, torch)
         if "approx" in want:

@@ -225,10 +225,12 @@ def dft_entries(a, n, js, chunk: int = 1 << 22) -> np.ndarray:
 
 
 def qft_basis_entries(n, x, js) -> np.ndarray:
-    """The transform of the basis state |x>: 2^{-n/2} e^{2 pi i x j / 2^n}."""
+    """The transform of the basis state |x>: 2^{-n/2} e^{2 pi i x j / 2^n}.
+    The phase x j mod 2^n is taken on Python integers (exact at any n; the
+    product overflows 64 bits at n = 32)."""
     N = 1 << n
-    j = np.asarray(js, dtype=np.int64)
-    ph = ((int(x) * j) % N).astype(np.float64) * (2.0 * np.pi / N)
+    ph = np.array([(int(x) * int(j)) % N for j in np.asarray(js).ravel()],
+                  dtype=np.float64) * (2.0 * np.pi / N)
     return np.exp(1j * ph) / np.sqrt(N)
 
 

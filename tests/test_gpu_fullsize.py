@@ -1,8 +1,11 @@
 """Checks at the benchmark's full sizes, in the launch configuration bench.py
 times: QFT on 27 qubits (complex64) against single outputs of the oracle's
-direct definition and the basis-state closed form; the 32-qubit random circuit
-followed by its inverse; 54-qubit approximate runs against the invariants
-that hold at any size."""
+direct definition and the basis-state closed form; the QFT on 28 to 32 qubits
+(up to 32 GiB) against the closed form in both stored orientations, and at 28
+against single outputs of the direct definition; the QFT on 24 qubits against
+the oracle's whole vector with the benchmark's pass kinds; the 32-qubit
+random circuit followed by its inverse; 54-qubit approximate runs against the
+invariants that hold at any size."""
 import math
 
 import numpy as np
@@ -60,6 +63,91 @@ def test_qft27_gaussian_spot_checks_and_roundtrip(qs_lib):
         assert np.abs(got - want).max() / np.abs(want).max() <= 1e-4
         st.qft(inverse=True)
         idx = sample_indices(N27, 4096, 2)
+        back = st.gather(idx)
+        assert np.abs(back - a[idx.astype(np.int64)]).max() <= 1e-5
+        assert abs(st.norm() - 1.0) < 1e-5
+
+
+def test_qft24_gaussian_full_vector(qs_lib):
+    """Every output of the QFT of a 24-qubit complex Gaussian state against
+    the oracle's gate-by-gate circuit (Sec. II-E), with the default pass plan
+    (12-bit contiguous tile, then two 6-bit strided passes) and with a 9-bit
+    tile, which leaves the benchmark's 8- and 7-bit strided passes (the same
+    kernels bench.py times at 27 qubits)."""
+    from parity import assert_parity
+    qs = qs_lib
+    n = 24
+    a = workloads.gaussian_state(n, 0)
+    want = dense.qft(a, n)
+    saved = qs.tune_get("qft.lds_bits")
+    try:
+        for lds_bits in (saved, 9):
+            qs.tune_set("qft.lds_bits", lds_bits)
+            with qs.State(n, C64) as st:
+                st.set_amplitudes(a)
+                st.qft()
+                got = st.amplitudes()
+            r = assert_parity(got, want, C64, f"qft24 lds_bits={lds_bits}")
+            assert r["max_rel"] <= 1e-4, r
+    finally:
+        qs.tune_set("qft.lds_bits", saved)
+
+
+@pytest.mark.parametrize("n", [28, 29, 30, 31, 32])
+def test_qft_large_basis_closed_form_both_orientations(qs_lib, n):
+    """QFT|x> = 2^{-n/2} e^{2 pi i x y / 2^n} at 28-32 qubits (complex64, up
+    to 32 GiB), sampled at 4,100 outputs. The transform leaves the range stored
+    bit-reversed, so the second forward transform runs the reversed-order
+    passes; QFT^2 |x> = |-x mod 2^n> exactly. The two inverse transforms then
+    return to QFT|x> (natural order) and to |x>."""
+    qs = qs_lib
+    N = 1 << n
+    x = workloads.basis_index(n, n)
+    idx = sample_indices(n, 4096, n)
+    want = dense.qft_basis_entries(n, x, idx)
+
+    def check_closed_form(st, what):
+        got = st.gather(idx)
+        err = np.abs(got - want)
+        assert err.max() <= 1e-5, (what, err.max())
+        assert err.max() / np.abs(want).max() <= 1e-4, (what, err.max())
+
+    def check_basis(st, y, what):
+        probe = np.concatenate([[y], idx[idx != y]]).astype(np.uint64)
+        got = st.gather(probe)
+        assert abs(got[0] - 1.0) <= 1e-5, (what, got[0])
+        assert np.abs(got[1:]).max() <= 1e-5, (what, np.abs(got[1:]).max())
+
+    with qs.State(n, C64) as st:
+        st.set_basis(x)
+        st.qft()
+        check_closed_form(st, "QFT|x>")
+        assert abs(st.norm() - 1.0) < 1e-5
+        st.qft()
+        check_basis(st, (N - x) % N, "QFT^2|x>")
+        st.qft(inverse=True)
+        check_closed_form(st, "QFT^-1 QFT^2|x>")
+        st.qft(inverse=True)
+        check_basis(st, x, "QFT^-2 QFT^2|x>")
+        assert abs(st.norm() - 1.0) < 1e-5
+
+
+def test_qft28_gaussian_spot_checks_and_roundtrip(qs_lib):
+    """28 qubits, complex Gaussian input: 8 outputs against the direct sum
+    of Eq. dft, then QFT^-1 brings the input back (4,100 sampled entries)."""
+    qs = qs_lib
+    n = 28
+    a = workloads.gaussian_state(n, 1)
+    js = [0, 1, 2, 3, 777777, 2 ** 27 + 5, 2 ** 28 - 2, 2 ** 28 - 1]
+    want = dense.dft_entries(a, n, js)
+    with qs.State(n, C64) as st:
+        st.set_amplitudes(a)
+        st.qft()
+        got = st.gather(np.array(js, dtype=np.uint64))
+        assert np.abs(got - want).max() <= 1e-5
+        assert np.abs(got - want).max() / np.abs(want).max() <= 1e-4
+        st.qft(inverse=True)
+        idx = sample_indices(n, 4096, 3)
         back = st.gather(idx)
         assert np.abs(back - a[idx.astype(np.int64)]).max() <= 1e-5
         assert abs(st.norm() - 1.0) < 1e-5
