@@ -18,11 +18,11 @@ Readings (each also listed with the design notes):
     as sqrt(1 - eps), the normalized form consistent with eps = (1-|r|)/2 and
     with the per-rounding fidelity 1 - eps.
   * The rounding condition is the inclusive eps <= p/2 of Eq. sdrp (not the
-    "eps_j <= p" of Sec. III-B, nor the strict inequality of Fig. 2's caption).
-    "eps = 0 up to machine precision" adds a tolerance tau: round when
-    eps <= p/2 + tau (tau = 1e-12 here).
-  * When and in what order the test runs is not stated ("proactively and
-    reactively", Table I). Only a two-qubit gate's operands and the remaining
+    eps_j <= p written in Sec. III-B, nor the strict inequality of Fig. 2's
+    caption). Sec. III-A treats eps as zero to within rounding, which adds a
+    tolerance tau: round when eps <= p/2 + tau (tau = 1e-12 here).
+  * When and in what order the test runs is not stated (Table I says only that
+    the state is decomposed both ahead of need and on demand). Only a two-qubit gate's operands and the remaining
     members of a subsystem that just lost a qubit can have a changed reduced
     state, so after every multi-qubit gate those qubits are marked dirty and
     the lowest-numbered dirty qubit is tested until none is left.
@@ -73,6 +73,7 @@ class Attempt:
     eps: float
     rounded: bool
     pair: int = -1  # the second qubit of a two-qubit attempt
+    gates: int = 0  # multi-qubit gates applied before this attempt
 
 
 @dataclass
@@ -172,6 +173,7 @@ class FactorizedState:
     # with the rule's own decision; used to replay another run's decisions
     # where eps lies within rounding distance of the threshold
     decide: object = None
+    gates_applied: int = 0  # multi-qubit gates applied so far
 
     def __post_init__(self):
         if not self.subs:
@@ -230,6 +232,7 @@ class FactorizedState:
         qubits, m = dense.gate_matrix(g)
         self.apply(qubits, m)
         if len(qubits) >= 2:
+            self.gates_applied += 1
             self.dirty.update(qubits)
 
     # -------------------------------------------------------------- SDRP
@@ -253,10 +256,10 @@ class FactorizedState:
             S.qubits, S.amps = others, rest
             self.subs.append(Sub([q], phi))
             self.F *= (1.0 - eps)
-            self.log.append(Attempt(q, nq, eps, True))
+            self.log.append(Attempt(q, nq, eps, True, gates=self.gates_applied))
             self.dirty.update(others)
             return True
-        self.log.append(Attempt(q, nq, eps, False))
+        self.log.append(Attempt(q, nq, eps, False, gates=self.gates_applied))
         return False
 
     def test_pair(self, qa: int, qb: int, p: float) -> bool:
@@ -274,7 +277,7 @@ class FactorizedState:
         rounds = eps <= p / 2.0 + self.tau
         if self.decide is not None:
             rounds = bool(self.decide(qa, nq, eps, rounds))
-        self.log.append(Attempt(qa, nq, eps, rounds, pair=qb))
+        self.log.append(Attempt(qa, nq, eps, rounds, pair=qb, gates=self.gates_applied))
         if not rounds:
             return False
         rest = project_out_pair(S.amps, nq, ta, tb, phi)
@@ -303,6 +306,33 @@ class FactorizedState:
                 self.try_separate(p)
                 if pairs and len(qubits) == 2 and self.test_pair(qubits[0], qubits[1], p):
                     self.try_separate(p)
+        return self
+
+    def run_tests_as_logged(self, gates, p: float, tests):
+        """Apply a gate list, making exactly the one-qubit attempts listed in
+        `tests`, in their order: (k, q) tests qubit q after the k-th
+        multi-qubit gate of the list and before the next one. This replays
+        another schedule (such as a learned proposal's, which tests some
+        dirty qubits, skips others and tests those later) with this oracle's
+        own arithmetic; the decision on each attempt is the rounding rule's
+        (or the decide hook's). The dirty set is kept but not consulted."""
+        tests = list(tests)
+        pos = 0
+
+        def due(k):
+            nonlocal pos
+            while pos < len(tests) and tests[pos][0] == k:
+                self.test_qubit(tests[pos][1], p)
+                pos += 1
+
+        due(self.gates_applied)
+        for g in gates:
+            self.apply_gate(g)
+            if len(dense.gate_matrix(g)[0]) >= 2:
+                due(self.gates_applied)
+        if pos != len(tests):
+            raise ValueError(f"attempt {pos} of {len(tests)} is not at a multi-qubit gate "
+                             f"boundary of the list")
         return self
 
     # -------------------------------------------------------------- readout

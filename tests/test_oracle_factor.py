@@ -293,3 +293,58 @@ def test_schedule_reaches_fixed_point(family):
     subsystem with others has eps > p/2 (Eq. sdrp). The dirty-set schedule is
     exhaustive only if every co-member of a rounded qubit is retested."""
     assert fixed_point_violations(family) == []
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_logged_schedule_replays_itself(seed):
+    """Replaying a plain run's own attempts (their gate counts and qubits)
+    with run_tests_as_logged repeats the run: the same attempts, the same
+    fidelity estimate and the same ket."""
+    n, p = 8, 0.3
+    gates = workloads.random_circuit(n, 5, 40 + seed)
+    a = factor.FactorizedState(n).run(gates, p)
+    assert any(x.rounded for x in a.log) and len(a.log) > 10
+    sched = [(x.gates, x.qubit) for x in a.log]
+    # the counts are those of the multi-qubit gates that preceded each attempt
+    assert all(0 < k <= sum(1 for g in gates if len(dense.gate_matrix(g)[0]) >= 2)
+               for k, _ in sched)
+    assert [k for k, _ in sched] == sorted(k for k, _ in sched)
+    b = factor.FactorizedState(n).run_tests_as_logged(gates, p, sched)
+    assert [(x.qubit, x.n_sub, x.eps, x.rounded, x.gates) for x in b.log] == \
+        [(x.qubit, x.n_sub, x.eps, x.rounded, x.gates) for x in a.log]
+    assert b.F == a.F
+    assert np.array_equal(b.expand(), a.expand())
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_any_logged_schedule_is_exact_at_p_zero(seed):
+    """At p = 0 only exactly separable qubits are rounded, so any choice of
+    tests (here a random subset of qubits after each multi-qubit gate, in
+    random order, including qubits not touched by the gate) leaves the
+    circuit's ket (Sec. II-A: the factorized form is exact); testing nothing
+    keeps F = 1 and the ket too, at any p."""
+    n = 8
+    gates = workloads.random_circuit(n, 4, seed)
+    # an early CZ between freshly rotated qubits leaves many separable moments
+    want = dense.run_circuit(dense.zero_state(n), n, gates)
+    g = np.random.default_rng(seed)
+    k_total = sum(1 for gg in gates if len(dense.gate_matrix(gg)[0]) >= 2)
+    sched = []
+    for k in range(1, k_total + 1):
+        for q in g.permutation(n)[: int(g.integers(0, 4))]:
+            sched.append((k, int(q)))
+    s = factor.FactorizedState(n, tau=1e-12).run_tests_as_logged(gates, 0.0, sched)
+    assert abs(abs(np.vdot(s.expand(), want)) - 1.0) < 1e-10
+    assert s.F > 1 - 1e-10
+    none = factor.FactorizedState(n).run_tests_as_logged(gates, 0.9, [])
+    assert none.F == 1.0 and not none.log
+    assert np.abs(none.expand() - want).max() < 1e-12
+
+
+def test_logged_schedule_outside_the_list_is_refused():
+    n = 4
+    gates = [("h", 0), ("cz", 0, 1), ("h", 2), ("cz", 2, 3)]
+    with pytest.raises(ValueError):
+        factor.FactorizedState(n).run_tests_as_logged(gates, 0.1, [(3, 0)])
+    with pytest.raises(ValueError):  # counts must not go back
+        factor.FactorizedState(n).run_tests_as_logged(gates, 0.1, [(2, 0), (1, 1)])
