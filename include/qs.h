@@ -122,16 +122,30 @@ int qs_apply_ctrl(qs_state* st, const int* ctrls, int nctrl, uint64_t ctrl_value
  * e^{i theta} (the controlled R_Z-type phase of the QFT circuit, Sec. II-E). */
 int qs_apply_cphase(qs_state* st, int a, int b, double theta);
 
-/* SWAP of qubits a and b in O(1) by exchanging their labels (Table I: "SWAP
- * gate is constant complexity"). Amplitudes are moved only when a later call
+/* SWAP of qubits a and b in O(1) by exchanging their labels (a constant-cost
+ * SWAP, Table I). Amplitudes are moved only when a later call
  * needs the identity labelling (readout, QFT on a permuted range). */
 int qs_apply_swap(qs_state* st, int a, int b);
 
 /* Dense k-qubit block (1 <= k <= QS_MAX_FUSED): m is 2^k x 2^k complex
  * (2*4^k doubles), row/column bit j <-> qubits[j]. For every assignment of the
  * other n-k bits, the 2^k amplitudes that differ only in `qubits` are
- * multiplied by m. Blocks of k >= 4 run on the FP32/FP64 matrix cores. */
+ * multiplied by m. Complex64 blocks of 4 or 5 qubits run on the FP32 matrix
+ * cores ("fused.mfma"); other widths and complex128 blocks on vector FMA. */
 int qs_apply_fused(qs_state* st, const int* qubits, int k, const double* m);
+
+/* A named gate (QS_GATE_* below) built in float64 inside the library and
+ * applied with the calls above: one-qubit kinds with qs_apply_1q, CP and CZ
+ * with qs_apply_cphase (CZ = CP(pi)), SWAP as a relabelling, iSWAP as a
+ * two-qubit block, CX/CY/AX/AY/AZ as qs_apply_ctrl with one control
+ * (qubits = {control, target}). QS_GATE_CU3 takes nq - 1 controls then the
+ * target (2 <= nq <= 9) and params = {theta, phi, lambda, v}, v a mask of
+ * the required control values (bit j for qubits[j]; v = 1 is a plain control
+ * when nq = 2). params: U3 {theta, phi, lambda} (Sec. III-C), CP {theta},
+ * else unused (may be NULL). QS_E_INVAL for an unknown kind, a wrong qubit
+ * count, a repeated or out-of-range qubit, or a missing or non-finite
+ * parameter, before any device work. */
+int qs_apply_gate(qs_state* st, int kind, const int* qubits, int nq, const double* params);
 
 /* Quantum Fourier transform (Eq. dft, omega = e^{+2 pi i / N}) on qubits
  * start .. start+len-1, including the final bit reversal (done as a
@@ -146,13 +160,13 @@ int qs_qft(qs_state* st, int start, int len, int inverse);
 /* ------------------------------------------------------------ approximate mode (Sec. III) */
 
 /* A factorized state keeps the ket as a tensor product of kets on disjoint
- * qubit subsets ("as factorized as possible", Sec. II-A). Each subsystem is a
+ * qubit subsets, split as far as the state allows (Sec. II-A). Each subsystem is a
  * separate device buffer of 2^k amplitudes. A gate on qubits of different
  * subsystems first merges them (Kronecker product; the first operand's qubits
  * keep their bit positions). The one-qubit Schmidt test (Sec. III-A) computes
  * the Bloch vector r of a qubit's reduced state in float64, eps = (1-|r|)/2,
  * and, when eps <= p/2 (Eq. sdrp, plus a tolerance of 1e-6 for complex64 /
- * 1e-12 for complex128 standing for "eps = 0 up to machine precision"),
+ * 1e-12 for complex128: exact separability tested to within rounding, Sec. III-A),
  * projects the qubit on the dominant eigenvector phi of its reduced state,
  * moves it into a one-qubit subsystem and multiplies the fidelity estimate by
  * 1 - eps (Eq. fid_model). */
@@ -170,6 +184,10 @@ typedef struct {
   double eps;        /* (1 - |r|)/2, or 1 - lambda_max for a pair (float64) */
   int32_t rounded;   /* 1 if the qubit (pair) was separated */
   int32_t pair;      /* 0: one-qubit attempt; else 1 + the pair's second qubit */
+  uint64_t gates;    /* multi-qubit gates applied to the state before this test:
+                        the test sees the state after that many of them (its
+                        place in the circuit, whether it ran at once or later
+                        in a deferred flush) */
 } qs_attempt;
 
 /* Factorized state of n qubits (1 <= n <= 63), every qubit its own |0>

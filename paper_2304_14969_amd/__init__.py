@@ -10,7 +10,6 @@ from __future__ import annotations
 
 import atexit
 import ctypes as C
-import math
 import os
 import weakref
 
@@ -61,7 +60,7 @@ _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 
 class Attempt(C.Structure):
     _fields_ = [("qubit", C.c_int32), ("n_sub", C.c_int32), ("eps", C.c_double),
-                ("rounded", C.c_int32), ("pair", C.c_int32)]
+                ("rounded", C.c_int32), ("pair", C.c_int32), ("gates", C.c_uint64)]
 
 
 class TrainCfg(C.Structure):
@@ -93,6 +92,8 @@ _SIGS = [
     ("qs_apply_cphase", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_double]),
     ("qs_apply_swap", C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     ("qs_apply_fused", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_double)]),
+    ("qs_apply_gate", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.c_int,
+                                C.POINTER(C.c_double)]),
     ("qs_qft", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
     ("qs_amplitudes", C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_int]),
     ("qs_amplitudes_gather", C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.c_uint64,
@@ -682,6 +683,12 @@ class State:
         return [(a.qubit, a.n_sub, a.eps, bool(a.rounded)) if a.pair == 0 else
                 (a.qubit, a.n_sub, a.eps, bool(a.rounded), a.pair - 1) for a in self._log[:n]]
 
+    def attempt_gates(self) -> list:
+        """For each attempt of attempts(): the number of multi-qubit gates
+        applied before it (where in the circuit the test looked at the state)."""
+        n = min(self._log_count.value, len(self._log)) if self._log is not None else 0
+        return [int(a.gates) for a in self._log[:n]]
+
     def record_features(self, cap: int = 1 << 20):
         """Record the 32 proposal features of every attempt (call after
         record_attempts; rows align with attempts())."""
@@ -729,42 +736,32 @@ class State:
 
 # ------------------------------------------------------------------ gate lists
 
-_H = np.array([[1, 1], [1, -1]], dtype=np.complex128) / math.sqrt(2.0)
-
-
-def u3_matrix(theta: float, phi: float, lam: float) -> np.ndarray:
-    """U(theta, phi, lambda) of Sec. III-C, built in float64 on the host."""
-    c, s = math.cos(theta / 2), math.sin(theta / 2)
-    return np.array([[c, -complex(math.cos(lam), math.sin(lam)) * s],
-                     [complex(math.cos(phi), math.sin(phi)) * s,
-                      complex(math.cos(phi + lam), math.sin(phi + lam)) * c]], dtype=np.complex128)
-
-
-_CZ = np.diag([1, 1, 1, -1]).astype(np.complex128)
-_ISWAP = np.array([[1, 0, 0, 0], [0, 0, 1j, 0], [0, 1j, 0, 0], [0, 0, 0, 1]], dtype=np.complex128)
-
 
 def apply_gate(st: State, g):
-    """Dispatch one gate tuple (the workloads gate-list format) to the library."""
+    """Dispatch one gate tuple (the workloads gate-list format) to the
+    library; every matrix is built in the library (qs_apply_gate), except the
+    explicit ones of "mat" tuples."""
     k = g[0]
-    if k == "h":
-        st.apply_1q(g[1], _H)
-    elif k == "u3":
-        st.apply_1q(g[1], u3_matrix(g[2], g[3], g[4]))
-    elif k == "cp":
-        st.apply_cphase(g[1], g[2], g[3])
-    elif k == "cz":
-        st.apply_cphase(g[1], g[2], math.pi)
-    elif k == "iswap":
-        st.apply_fused([g[1], g[2]], _ISWAP)
-    elif k == "swap":
-        st.apply_swap(g[1], g[2])
-    elif k == "ctrl":
-        st.apply_ctrl(list(g[1]), g[2], g[3], u3_matrix(g[4], g[5], g[6]))
-    elif k == "mat":
+    if k == "mat":
         st.apply_fused(list(g[1]), g[2])
+        return
+    if k == "ctrl":
+        qubits = list(g[1]) + [g[3]]
+        params = [g[4], g[5], g[6], float(g[2] & ((1 << len(g[1])) - 1))]
+        kind = GATE["cu3"]
+    elif k in ("h", "x", "y", "z"):
+        qubits, params, kind = [g[1]], [], GATE[k]
+    elif k == "u3":
+        qubits, params, kind = [g[1]], list(g[2:5]), GATE[k]
+    elif k == "cp":
+        qubits, params, kind = [g[1], g[2]], [g[3]], GATE[k]
+    elif k in GATE:
+        qubits, params, kind = [g[1], g[2]], [], GATE[k]
     else:
         raise ValueError(f"unknown gate {k!r}")
+    q = (C.c_int * len(qubits))(*qubits)
+    p = (C.c_double * max(1, len(params)))(*params)
+    _check(st.lib, st.lib.qs_apply_gate(st.h, kind, q, len(qubits), p))
 
 
 def run_gates(st: State, gates):

@@ -646,6 +646,68 @@ int qs_apply_swap(qs_state* st, int a, int b) {
   return QS_OK;
 }
 
+int qs_apply_gate(qs_state* st, int kind, const int* qubits, int nq, const double* params) {
+  if (int rc = check_state(st)) return rc;
+  if (!qubits) return fail(QS_E_INVAL, "qubits is NULL");
+  if (kind < QS_GATE_H || kind > QS_GATE_CU3) return fail(QS_E_INVAL, "unknown gate kind %d", kind);
+  const int arity = kind >= QS_GATE_CZ ? 2 : 1;
+  if (kind == QS_GATE_CU3 ? (nq < 2 || nq > 9) : nq != arity)
+    return fail(QS_E_INVAL, "gate kind %d on %d qubits", kind, nq);
+  const int np = kind == QS_GATE_CP ? 1 : kind == QS_GATE_U3 ? 3 : kind == QS_GATE_CU3 ? 4 : 0;
+  if (np > 0) {
+    if (!params) return fail(QS_E_INVAL, "gate kind %d needs parameters", kind);
+    for (int i = 0; i < np; ++i)
+      if (!std::isfinite(params[i])) return fail(QS_E_INVAL, "parameter %d is not finite", i);
+  }
+  auto to8 = [](const std::vector<qs::cd>& u, double* m) {
+    for (int e = 0; e < 4; ++e) {
+      m[2 * e] = u[e].real();
+      m[2 * e + 1] = u[e].imag();
+    }
+  };
+  std::vector<qs::cd> u;
+  int k = 0;
+  double m2[8];
+  switch (kind) {
+    case QS_GATE_SWAP: return qs_apply_swap(st, qubits[0], qubits[1]);
+    case QS_GATE_CP: return qs_apply_cphase(st, qubits[0], qubits[1], params[0]);
+    case QS_GATE_CZ: return qs_apply_cphase(st, qubits[0], qubits[1], 3.14159265358979323846);
+    case QS_GATE_CU3: {
+      const int nctrl = nq - 1;
+      const double v = params[3];
+      if (!(v >= 0.0 && v < std::ldexp(1.0, nctrl) && v == std::floor(v)))
+        return fail(QS_E_INVAL, "control values %g are not a %d-bit mask", v, nctrl);
+      (void)qs::gate_matrix(QS_GATE_U3, 1, params, &u, &k);
+      to8(u, m2);
+      return qs_apply_ctrl(st, qubits, nctrl, uint64_t(v), qubits[nctrl], m2);
+    }
+    default: break;
+  }
+  if (!qs::gate_matrix(kind, arity, params, &u, &k)) return fail(QS_E_INVAL, "gate kind %d", kind);
+  if (k == 1) {
+    to8(u, m2);
+    return qs_apply_1q(st, qubits[0], m2);
+  }
+  if (kind == QS_GATE_ISWAP) {
+    double m4[32];
+    for (int e = 0; e < 16; ++e) {
+      m4[2 * e] = u[e].real();
+      m4[2 * e + 1] = u[e].imag();
+    }
+    return qs_apply_fused(st, qubits, 2, m4);
+  }
+  // CX, CY, AX, AY, AZ: local bit 0 the control, bit 1 the target; the
+  // target's 2x2 sits where the control takes its value cv
+  const int cv = (kind == QS_GATE_CX || kind == QS_GATE_CY) ? 1 : 0;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      const qs::cd x = u[size_t(cv + 2 * i) * 4 + (cv + 2 * j)];
+      m2[2 * (2 * i + j)] = x.real();
+      m2[2 * (2 * i + j) + 1] = x.imag();
+    }
+  return qs_apply_ctrl(st, qubits, 1, uint64_t(cv), qubits[1], m2);
+}
+
 int qs_apply_fused(qs_state* st, const int* qubits, int k, const double* m) {
   if (int rc = check_state(st)) return rc;
   if (!qubits) return fail(QS_E_INVAL, "qubits is NULL");

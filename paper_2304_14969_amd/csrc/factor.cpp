@@ -8,7 +8,8 @@
 //
 // Readings of the paper used here:
 //  * rounding condition: inclusive eps <= p/2 (Eq. sdrp), plus a tolerance tau
-//    for "eps = 0 up to machine precision" (1e-6 for complex64 amplitudes,
+//    that lets exact separability be tested to within rounding, Sec. III-A
+//    (1e-6 for complex64 amplitudes,
 //    whose eps carries ~1e-7 rounding error; 1e-12 for complex128);
 //  * the projection keeps the dominant eigenvector phi of rho_q (the result of
 //    rotating r to the |0> pole, post-selecting and rotating back), with phi_0
@@ -145,7 +146,8 @@ int new_single(FactorState* f, int q, const double amp[4], Sub* out) {
   return QS_OK;
 }
 
-void log_attempt(FactorState* f, int q, int nsub, double eps, bool rounded, int partner = -1) {
+void log_attempt(FactorState* f, int q, int nsub, double eps, bool rounded, int partner,
+                 uint64_t gates) {
   if (!f->log || !f->log_count) return;
   if (*f->log_count < f->log_cap) {
     qs_attempt& a = f->log[*f->log_count];
@@ -154,6 +156,7 @@ void log_attempt(FactorState* f, int q, int nsub, double eps, bool rounded, int 
     a.eps = eps;
     a.rounded = rounded ? 1 : 0;
     a.pair = partner + 1;
+    a.gates = gates;
   }
   ++*f->log_count;
 }
@@ -279,7 +282,7 @@ int merge(FactorState* f, int ia, int ib, int* out) {
 void record(FactorState* f, int q, int nsub, double eps, bool rounded, int partner = -1) {
   if (partner < 0) note_test_impl(f, q, eps, rounded);
   if (f->flushing) {
-    f->pend.push_back({f->cur_phase, q, nsub, eps, rounded, partner});
+    f->pend.push_back({f->cur_phase, q, nsub, eps, rounded, partner, f->cur_gates});
     if (f->feat_log) {
       if (partner >= 0) std::fill(f->cur_feat, f->cur_feat + QS_MLP_INPUTS, 0.0f);
       f->pend_feat.insert(f->pend_feat.end(), f->cur_feat, f->cur_feat + QS_MLP_INPUTS);
@@ -287,7 +290,7 @@ void record(FactorState* f, int q, int nsub, double eps, bool rounded, int partn
     return;
   }
   if (rounded) f->F *= (1.0 - eps);
-  log_attempt(f, q, nsub, eps, rounded, partner);
+  log_attempt(f, q, nsub, eps, rounded, partner, f->gate_count);
 }
 
 // The decision on qubit q at bit t of subsystem si from its Bloch sums
@@ -789,6 +792,7 @@ int exact_retest(FactorState* f, uint64_t mask) {
       if ((mask >> S.q[b]) & 1) {
         S.plain = true;
         S.phase = phase;
+        S.phase_gates = f->gate_count;
         break;
       }
   return flush_pending(f);
@@ -845,6 +849,7 @@ int queue_gate2(FactorState* f, const int* qubits, const double* m) {
   }
   for (int j = 0; j < 2; ++j) f->dirty |= uint64_t(1) << qubits[j];
   S.phase = ++f->phase_next;
+  S.phase_gates = f->gate_count;
   if (f->policy == QS_SEP_AFTER_2Q_PAIRS) {  // its pair test follows its one-qubit tests
     S.pend_a = qubits[0];
     S.pend_b = qubits[1];
@@ -1248,6 +1253,7 @@ int fact_apply(FactorState* f, const int* qubits, int k, const double* m) {
     for (int j = 0; j < k; ++j) f->dirty |= uint64_t(1) << qubits[j];
     if (f->policy != QS_SEP_NONE && f->defer) {
       S.phase = ++f->phase_next;
+      S.phase_gates = f->gate_count;
       return QS_OK;
     }
     if (f->policy != QS_SEP_NONE) {
@@ -1555,6 +1561,7 @@ int flush_round(FactorState* f, bool* any) {
   for (size_t i = 0; i < items.size(); ++i) {
     const Item& it = items[i];
     f->cur_phase = f->subs[it.si].phase;
+    f->cur_gates = f->subs[it.si].phase_gates;
     if (it.G == 0) {
       f->subs[it.si].pend_a = f->subs[it.si].pend_b = -1;
       bool rounded = false;
@@ -1667,7 +1674,7 @@ int flush_pending(FactorState* f) {
       std::memcpy(f->feat_log + *f->log_count * QS_MLP_INPUTS, &f->pend_feat[i * QS_MLP_INPUTS],
                   QS_MLP_INPUTS * sizeof(float));
     if (d.rounded) f->F *= (1.0 - d.eps);
-    log_attempt(f, d.q, d.nsub, d.eps, d.rounded, d.partner);
+    log_attempt(f, d.q, d.nsub, d.eps, d.rounded, d.partner, d.gates);
   }
   f->pend.clear();
   f->pend_feat.clear();

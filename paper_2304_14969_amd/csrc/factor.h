@@ -17,6 +17,7 @@ struct Sub {
   int q[64] = {0};
   void* amps = nullptr;  // 2^nq amplitudes, device, owned
   uint64_t phase = 0;    // deferred separation: the gate its dirty qubits wait on
+  uint64_t phase_gates = 0;  // multi-qubit gates applied when that phase began
   bool plain = false;    // deferred separation: exact tests without the proposer
   int pend_a = -1, pend_b = -1;  // deferred pair policy: the pair test its gate made due
   // one-qubit subsystems: a float64 host copy of the two amplitudes when they
@@ -45,7 +46,7 @@ struct FactorState {
   uint64_t dirty = 0;      // qubits whose reduced state may have changed
   int policy = QS_SEP_NONE;
   double p = 0.0;          // SDRP threshold parameter of the policy
-  double tau = 1e-6;       // "epsilon = 0 up to machine precision"
+  double tau = 1e-6;       // tolerance of the exact-separability test (Sec. III-A)
   qs_attempt* log = nullptr;
   uint64_t log_cap = 0;
   uint64_t* log_count = nullptr;
@@ -66,11 +67,12 @@ struct FactorState {
     int q, nsub;
     double eps;
     bool rounded;
-    int partner;  // a pair attempt's second qubit, else -1
+    int partner;     // a pair attempt's second qubit, else -1
+    uint64_t gates;  // multi-qubit gates applied before the test (its place in the circuit)
   };
   bool defer = false;
   bool flushing = false;
-  uint64_t phase_next = 0, cur_phase = 0;
+  uint64_t phase_next = 0, cur_phase = 0, cur_gates = 0;
   std::vector<Decision> pend;
   std::vector<float> pend_feat;         // features of each held-back attempt (feature log on)
   float cur_feat[QS_MLP_INPUTS] = {0};  // features of the attempt being decided
@@ -119,7 +121,7 @@ struct FactorState {
   int recent[8] = {0};
   int recent_n = 0;
   double recent_eps = -1.0;
-  uint64_t gate_count = 0;
+  uint64_t gate_count = 0;  // multi-qubit gates applied (or queued) so far
   // learned proposal
   qs_mlp* proposer = nullptr;
   double cutoff = 0.5;

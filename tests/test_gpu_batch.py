@@ -58,23 +58,41 @@ def test_batch_graph_replays(qs_lib):
     g.free()
 
 
-def test_batch_1024_circuits(qs_lib):
-    """1024 random circuits of 12-20 qubits, depth 8, in one batched run."""
-    qs = qs_lib
+@pytest.fixture(scope="module")
+def batch1024_oracle():
+    """The 1024-circuit batch (12-20 qubits, depth 8, seed 300) and the
+    oracle's kets of 64 of its circuits: the first 7 of every width from 12 to
+    20 and the last circuit."""
     widths = workloads.batch_widths(1024, 300)
+    gl = [workloads.random_circuit(n, 8, 300 * 1000 + i) for i, n in enumerate(widths)]
+    pick = []
+    for w in range(12, 21):
+        pick += [i for i, n in enumerate(widths) if n == w][:7]
+    pick.append(1023)
+    assert len(set(pick)) == 64 and {widths[i] for i in pick} == set(range(12, 21))
+    want = {i: dense.run_circuit(dense.zero_state(widths[i]), widths[i], gl[i]) for i in pick}
+    return widths, want
+
+
+def check_batch1024(b, widths, want):
+    for i, w in want.items():
+        assert_parity(b.amplitudes(i), w, C64, f"ket {i} n={widths[i]}")
+    for i in range(0, 1024, 61):
+        a = b.amplitudes(i).astype(np.complex128)
+        assert abs(np.vdot(a, a).real - 1) < 1e-4
+
+
+def test_batch_1024_circuits(qs_lib, batch1024_oracle):
+    """1024 random circuits of 12-20 qubits, depth 8, in one batched run; 64
+    kets (every width) in full against the oracle, others normalized."""
+    qs = qs_lib
+    widths, want = batch1024_oracle
     gl, circs = circuits_for(qs, widths, 8, 300)
     b = qs.Batch(widths, C64)
     b.run(circs)
     b.synchronize()
     assert b.info()["launches"] <= 8 * 5 * 10
-    small = [i for i, n in enumerate(widths) if n <= 13][:3]
-    for i in small:
-        n = widths[i]
-        want = dense.run_circuit(dense.zero_state(n), n, gl[i])
-        assert_parity(b.amplitudes(i), want, C64, f"ket {i}")
-    for i in range(0, 1024, 97):
-        a = b.amplitudes(i).astype(np.complex128)
-        assert abs(np.vdot(a, a).real - 1) < 1e-4
+    check_batch1024(b, widths, want)
     b.free()
 
 
@@ -131,23 +149,17 @@ def test_batch_tiles_graph_replays(qs_lib):
     b.free()
 
 
-def test_batch_1024_circuits_tiles(qs_lib):
+def test_batch_1024_circuits_tiles(qs_lib, batch1024_oracle):
     """The 1024-circuit batch with tile passes: a few launches per pass index;
-    sampled kets against the oracle, every ket normalized."""
+    the same 64 kets in full against the oracle."""
     qs = qs_lib
-    widths = workloads.batch_widths(1024, 300)
+    widths, want = batch1024_oracle
     gl, circs = circuits_for(qs, widths, 8, 300)
     b = qs.Batch(widths, C64).use_tiles()
     b.run(circs)
     b.synchronize()
     assert b.info()["launches"] <= 20
-    for i in [i for i, n in enumerate(widths) if n <= 13][:3]:
-        n = widths[i]
-        assert_parity(b.amplitudes(i), dense.run_circuit(dense.zero_state(n), n, gl[i]), C64,
-                      f"ket {i}")
-    for i in range(0, 1024, 61):
-        a = b.amplitudes(i).astype(np.complex128)
-        assert abs(np.vdot(a, a).real - 1) < 1e-4
+    check_batch1024(b, widths, want)
     b.free()
 
 

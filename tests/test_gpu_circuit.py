@@ -117,6 +117,33 @@ def inverse_gates(gates):
     return out
 
 
+@pytest.mark.timeout(1500)
+def test_random_circuit_n26_full_vector_against_oracle(qs_lib):
+    """The exact random-circuit workload (10 layers of U3 on every qubit, then
+    CZ or iSWAP on a seeded random matching; the generator of the 32-qubit
+    benchmark) at 26 qubits, every amplitude against the oracle run gate by
+    gate (about 5 minutes on one host core; 28 qubits would take about 20):
+    tile passes (the benchmark's mode), blocks of at most 4 qubits (its
+    comparison) and blocks of at most 5 (matrix cores for 4-5 qubits)."""
+    qs = qs_lib
+    n = 26
+    gates = workloads.random_circuit(n, 10, 0)
+    want = dense.run_circuit(dense.zero_state(n), n, gates)
+    for mode in ("tiles", 4, 5):
+        c = qs.Circuit(n).add_gates(gates)
+        if mode == "tiles":
+            c.use_tiles()
+        else:
+            c.plan(mode)
+        with qs.State(n, C64) as st:
+            st.run(c)
+            got = st.amplitudes()
+        c.free()
+        r = assert_parity(got, want, C64, f"n=26 {mode}")
+        print(f"n=26 {mode}: {r}")
+        del got
+
+
 @pytest.mark.parametrize("n", [28])
 def test_large_random_circuit_then_inverse(qs_lib, n):
     """At a size the oracle cannot run whole: C followed by C^-1 returns |0...0>

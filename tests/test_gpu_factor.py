@@ -69,6 +69,8 @@ def test_sdrp_decision_replay(qs_lib, n, layers, p, seed):
     att = st.attempts()
     ost = replay(n, gates, p, att, eps_tol=2e-5)
     assert len(att) == len(ost.log)
+    # each attempt at the same place in the circuit (deferred or not)
+    assert st.attempt_gates() == [a.gates for a in ost.log]
     assert sum(a[3] for a in att) == sum(a.rounded for a in ost.log)
     F = st.fidelity_estimate()
     assert abs(F - ost.F) <= 1e-5 * max(ost.F, 1e-3) + 1e-7, (F, ost.F)

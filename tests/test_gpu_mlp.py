@@ -176,3 +176,56 @@ def test_deferred_learned_retests_match_immediate(qs_lib, max_amps):
         assert abs(r["F"] - prod) <= 1e-12 * prod
     assert abs(a["F"] - b["F"]) <= 1e-12 * a["F"]
     net.free()
+
+
+@pytest.mark.parametrize("retest_on_merge", [True, False])
+def test_learned_runs_replay_on_the_oracle(qs_lib, retest_on_merge):
+    """Runs with a trained proposer at 16 qubits against the FP64 oracle. The
+    oracle makes exactly the attempts the GPU logged, at the same places in
+    the circuit (after the same number of multi-qubit gates), computing each
+    eps on its own state: eps must agree, and so must the decisions (where
+    the oracle's eps lies within 1e-5 of the threshold it follows the GPU);
+    then the fidelity estimates and the expanded kets must match. The
+    network skips tests, so the schedule differs from the plain one."""
+    from oracle import factor
+    from paper_2304_14969_amd import protocol
+    from parity import C64, assert_parity
+    from test_gpu_factor import NEAR
+    qs = qs_lib
+    p = 0.2
+    X, y = protocol.collect_attempts(16, [workloads.grid_circuit(4, 4, 7, s)
+                                          for s in range(10000, 10030)], (p,))
+    net, cutoff, _ = protocol.train_proposer(X, y, steps=1000, recall=0.9)
+    skipped = 0
+    for s in range(4):
+        gates = workloads.grid_circuit(4, 4, 7, s)
+        r = protocol.approx_run(16, gates, p, record=True, keep=True, proposer=net,
+                                cutoff=cutoff, retest_on_merge=retest_on_merge)
+        st = r["state"]
+        try:
+            assert r["ok"] and st.shortcut_count() == 0
+            skipped += r["skipped"]
+            att, where = st.attempts(), st.attempt_gates()
+            it = iter(att)
+
+            def decide(q, nsub, eps, rule):
+                gq, gn, geps, grounded = next(it)
+                assert (gq, gn) == (q, nsub)
+                assert abs(geps - eps) <= 2e-5, (geps, eps)
+                if abs(eps - p / 2) < NEAR:
+                    return grounded
+                assert grounded == rule, (q, eps, p)
+                return rule
+
+            ost = factor.FactorizedState(16, decide=decide)
+            ost.run_tests_as_logged(gates, p, [(k, a[0]) for k, a in zip(where, att)])
+            assert next(it, None) is None
+            assert len(ost.log) == len(att)
+            assert abs(r["F"] - ost.F) <= 1e-5 * max(ost.F, 1e-3) + 1e-7, (r["F"], ost.F)
+            assert sorted(len(x) for x in st.subsystems()) == ost.sizes()
+            assert_parity(st.amplitudes(), ost.expand(), C64, f"learned seed {s}")
+        finally:
+            st.free()
+    assert skipped > 0
+    net.free()
+
