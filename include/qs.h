@@ -465,6 +465,20 @@ int qs_amplitudes(qs_state* st, void* host_out, uint64_t count, int out_dtype);
  * (2*m doubles). Synchronizes. */
 int qs_amplitudes_gather(qs_state* st, const uint64_t* idx, uint64_t m, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture that must not call hipMalloc, tight serving loops, harnesses that
+ * forbid allocation): qs_amplitudes_gather on a dense state without any
+ * allocation. The index list and the outputs are staged in a fixed
+ * device-side array of the library (QS_GATHER_NOALLOC_MAX entries: 1.5 MiB
+ * per GPU, held until the process ends), not in memory allocated per call.
+ * m > QS_GATHER_NOALLOC_MAX gives QS_E_INVAL; a factorized state gives
+ * QS_E_UNSUPPORTED (use qs_amplitudes_gather). Same output and argument
+ * rules as qs_amplitudes_gather; synchronizes. Every call on one GPU shares
+ * that staging array, so calls that overlap on one GPU (from several host
+ * threads or streams) race: the caller serializes them. */
+#define QS_GATHER_NOALLOC_MAX 65536
+int qs_amplitudes_gather_noalloc(qs_state* st, const uint64_t* idx, uint64_t m, double* out);
+
 /* |a_x|^2 for every x in index order, accumulated in float64. count = 2^n.
  * Synchronizes. */
 int qs_probs(qs_state* st, double* out, uint64_t count);

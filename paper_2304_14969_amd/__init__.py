@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqs.so")
 
 C64, C128 = 1, 2
+GATHER_NOALLOC_MAX = 65536  # QS_GATHER_NOALLOC_MAX of qs.h
 OK, E_INVAL, E_NOMEM, E_CAPACITY, E_DEVICE, E_NUMERIC, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 MAX_FUSED = 6
 MAX_QUBITS = 34
@@ -98,6 +99,8 @@ _SIGS = [
     ("qs_amplitudes", C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_int]),
     ("qs_amplitudes_gather", C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.c_uint64,
                                        C.POINTER(C.c_double)]),
+    ("qs_amplitudes_gather_noalloc", C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.c_uint64,
+                                               C.POINTER(C.c_double)]),
     ("qs_probs", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_uint64]),
     ("qs_norm", C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     ("qs_check", C.c_int, [C.c_void_p, C.c_double]),
@@ -604,6 +607,16 @@ class State:
         idx = np.ascontiguousarray(np.asarray(idx, dtype=np.uint64))
         out = np.empty(idx.size, dtype=np.complex128)
         _check(self.lib, self.lib.qs_amplitudes_gather(
+            self.h, idx.ctypes.data_as(C.POINTER(C.c_uint64)), idx.size,
+            out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def gather_noalloc(self, idx) -> np.ndarray:
+        """qs_amplitudes_gather_noalloc: at most GATHER_NOALLOC_MAX indices,
+        dense states, no device allocation."""
+        idx = np.ascontiguousarray(np.asarray(idx, dtype=np.uint64))
+        out = np.empty(idx.size, dtype=np.complex128)
+        _check(self.lib, self.lib.qs_amplitudes_gather_noalloc(
             self.h, idx.ctypes.data_as(C.POINTER(C.c_uint64)), idx.size,
             out.ctypes.data_as(C.POINTER(C.c_double))))
         return out

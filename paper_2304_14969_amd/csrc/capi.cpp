@@ -4,6 +4,7 @@
 // float64 and rounding them once to the state's precision.
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -87,6 +88,15 @@ struct qs_state {
   qs::FactorState* fact = nullptr;  // set for factorized (approximate-mode) states
 };
 
+// Staging of qs_amplitudes_gather_noalloc: the index list (uint64) followed
+// by the outputs (complex float64) of at most QS_GATHER_NOALLOC_MAX entries.
+// Each GPU holds its own copy for the life of the process. In host code the
+// array's name is not a device address: kernels and copies get the address
+// that hipGetSymbolAddress returns for the device (noalloc_scratch).
+constexpr uint64_t kNoAllocMax = QS_GATHER_NOALLOC_MAX;
+constexpr size_t kNoAllocIdxBytes = kNoAllocMax * sizeof(uint64_t);
+static __device__ __align__(256) unsigned char scratch[kNoAllocIdxBytes + kNoAllocMax * 2 * sizeof(double)];
+
 namespace {
 
 uint64_t dim(const qs_state* st) { return uint64_t(1) << st->n; }
@@ -108,6 +118,40 @@ int device_error(qs_state* st, hipError_t e, const char* what) {
   if (e == hipSuccess) return QS_OK;
   if (st) st->poisoned = true;
   return fail(QS_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Device address of `scratch` on the GPU that holds the state's amplitudes,
+// looked up once per device with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int noalloc_scratch(qs_state* st, void** out) {
+  hipPointerAttribute_t attr{};
+  hipError_t e = hipPointerGetAttributes(&attr, st->amps);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(QS_E_DEVICE, "locating the state's device: %s", hipGetErrorString(e));
+  }
+  const int dev = attr.device;
+  if (dev < 0 || dev >= kMaxDevices) return fail(QS_E_DEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+    void* p = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(QS_E_DEVICE, "address of the no-allocation staging array: %s",
+                  hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return QS_OK;
 }
 
 int check_qubit(const qs_state* st, int q, const char* name) {
@@ -1522,6 +1566,32 @@ int qs_amplitudes_gather(qs_state* st, const uint64_t* idx, uint64_t m, double* 
   if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
   dev_free(didx);
   dev_free(dout);
+  return device_error(st, e, "gather");
+}
+
+int qs_amplitudes_gather_noalloc(qs_state* st, const uint64_t* idx, uint64_t m, double* out) {
+  if (int rc = check_state(st)) return rc;
+  if (m == 0) return QS_OK;
+  if (!idx || !out) return fail(QS_E_INVAL, "NULL pointer");
+  if (m > kNoAllocMax)
+    return fail(QS_E_INVAL, "%llu indices exceed the no-allocation limit %llu",
+                (unsigned long long)m, (unsigned long long)kNoAllocMax);
+  if (st->fact) return fail(QS_E_UNSUPPORTED, "factorized states: use qs_amplitudes_gather");
+  for (uint64_t j = 0; j < m; ++j)
+    if (idx[j] >= dim(st)) return fail(QS_E_INVAL, "index %llu >= 2^%d", (unsigned long long)idx[j], st->n);
+  void* base = nullptr;
+  if (int rc = noalloc_scratch(st, &base)) return rc;
+  uint64_t* didx = static_cast<uint64_t*>(base);
+  double* dout = reinterpret_cast<double*>(static_cast<char*>(base) + kNoAllocIdxBytes);
+  qs::Perm64 perm{};
+  perm.n = st->n;
+  for (int q = 0; q < st->n; ++q) perm.p[q] = static_cast<int8_t>(st->perm[q]);
+  hipError_t e = hipMemcpyAsync(didx, idx, m * sizeof(uint64_t), hipMemcpyHostToDevice, st->stream);
+  if (e == hipSuccess)
+    e = st->dtype == QS_C64 ? qs::launch_gather(static_cast<const float*>(st->amps), didx, m, perm, dout, st->stream)
+                            : qs::launch_gather(static_cast<const double*>(st->amps), didx, m, perm, dout, st->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, dout, m * 2 * sizeof(double), hipMemcpyDeviceToHost, st->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
   return device_error(st, e, "gather");
 }
 
