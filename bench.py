@@ -29,12 +29,12 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the QFT pass kernels, from two rocprofv3 --pmc runs
 # of `bench.py --quick` (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
 # scaled by what the counter reads for a copy of a known 1 GiB
-# (`bench.py --calibrate-copy`: FETCH_SIZE reads 0.5000 of the bytes copied,
-# WRITE_SIZE 1.0000). Valid only for the kernel source they were taken on.
+# (`bench.py --calibrate-copy`: FETCH_SIZE reads 0.50002 of the bytes copied,
+# WRITE_SIZE 1.00000). Valid only for the kernel source they were taken on.
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_2304_14969_amd", "csrc", "k_qft.hip")
-TRAFFIC = {"sha256": "71bb88caf54716efdeb3576baa8214650392af9f932f731ddd9e0781cbeb7dbf",
-           "bytes_per_launch": {"qft_col8": 2147600082, "qft_col7": 2147570387,
-                                "qft_lds": 2147587282}}
+TRAFFIC = {"sha256": "35b3e250bde12c56a7fbbf1866acb0499f30c757c5b2b4a41eaaf8f52835825b",
+           "bytes_per_launch": {"qft_col8": 2147591986, "qft_col7": 2147599058,
+                                "qft_lds": 2147572435}}
 
 
 def measured_traffic(kernel: str):
@@ -48,32 +48,75 @@ def measured_traffic(kernel: str):
 METRIC = "exact QFT-27 seconds & HBM GB/s; 54q×7-layer approx time at equal fidelity"
 
 
-def cpu_baseline(n: int) -> dict:
-    """FP64 oracle (as is) on the host: one H, one controlled phase and one
-    SWAP at full size, each timed once, scaled by the QFT gate counts."""
+def cpu_baseline(n: int, m: int = 20) -> dict:
+    """The FP64 oracle as it is, timed on one host core (numpy/BLAS limited
+    to one thread): the whole QFT circuit of an m-qubit complex Gaussian
+    state (H and controlled phases gate by gate, the bit reversal as SWAPs
+    that move amplitudes), one warm-up run, then the median of three. Scaled
+    to n qubits by the gate count and the vector length (every oracle gate
+    sweeps the whole vector). Beside it, the per-gate cost at n qubits: one H,
+    one controlled phase and one SWAP on a 2^n vector (median of three
+    each), weighted by the n-qubit gate counts."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     import workloads
     from oracle import dense
 
-    counts = workloads.qft_gate_counts(n)
-    g = np.random.default_rng(1)
-    a = (g.standard_normal(2 ** n) + 1j * g.standard_normal(2 ** n)) / math.sqrt(2 ** (n + 1))
-    t = {}
+    a = workloads.gaussian_state(m, 1)
+    runs = []
     with threadpool_limits(1):
-        for kind, fn in (("h", lambda x: dense.apply_1q(x, n, n - 1, dense.H)),
-                         ("cp", lambda x: dense.apply_cphase(x, n, 3, n - 2, 0.1)),
-                         ("swap", lambda x: dense.apply_swap(x, n, 0, n - 1))):
+        dense.qft(a, m)
+        for _ in range(3):
             t0 = time.perf_counter()
-            fn(a)
-            t[kind] = time.perf_counter() - t0
-    est = sum(counts[k] * t[k] for k in counts)
-    return {"value": est, "unit": "s per QFT-27", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle gates on a 2^{n} complex128 vector, one of each kind timed "
-                       f"once (H {t['h']:.2f} s, CP {t['cp']:.2f} s, SWAP {t['swap']:.2f} s), "
-                       f"scaled by the QFT gate counts {counts['h']} H + {counts['cp']} CP + "
-                       f"{counts['swap']} SWAP; numpy/BLAS limited to 1 thread")}
+            dense.qft(a, m)
+            runs.append(time.perf_counter() - t0)
+    med = sorted(runs)[1]
+    cm, cn = workloads.qft_gate_counts(m), workloads.qft_gate_counts(n)
+    scale = sum(cn.values()) / sum(cm.values()) * 2.0 ** (n - m)
+    g = np.random.default_rng(1)
+    x = (g.standard_normal(2 ** n) + 1j * g.standard_normal(2 ** n)) / math.sqrt(2 ** (n + 1))
+    per = {}
+    with threadpool_limits(1):
+        for kind, fn in (("h", lambda v: dense.apply_1q(v, n, n - 1, dense.H)),
+                         ("cp", lambda v: dense.apply_cphase(v, n, 3, n - 2, 0.1)),
+                         ("swap", lambda v: dense.apply_swap(v, n, 0, n - 1))):
+            ts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                fn(x)
+                ts.append(time.perf_counter() - t0)
+            per[kind] = sorted(ts)[1]
+    del x
+    per_gate = sum(cn[k] * per[k] for k in cn)
+    return {"value": med * scale, "unit": f"s per QFT-{n}", "cores": 1, "kind": "oracle",
+            "host_cpus": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
+            "sample": (f"oracle QFT circuit on a {m}-qubit complex128 Gaussian state, 1 thread: "
+                       f"{med:.3f} s (median of 3 after a warm-up; runs "
+                       f"{', '.join(f'{r:.3f}' for r in runs)}), scaled by the gate count "
+                       f"({sum(cn.values())} / {sum(cm.values())}) and the length 2^{n - m}"),
+            "per_gate_estimate": {"value": per_gate, "h_s": per["h"], "cp_s": per["cp"],
+                                  "swap_s": per["swap"],
+                                  "note": f"one gate of each kind on a 2^{n} vector, median of 3, "
+                                          f"weighted by {cn['h']} H + {cn['cp']} CP + "
+                                          f"{cn['swap']} SWAP"}}
+
+
+def error_vs_oracle(qs, workloads, n: int, a, js=(0, 1, 12345, 2 ** 26 + 3, 2 ** 27 - 1)) -> dict:
+    """One QFT of the benchmark's input on the GPU against single outputs of
+    the oracle's direct sum of Eq. dft (float64)."""
+    import numpy as np
+    from oracle import dense
+
+    js = [j % (2 ** n) for j in js]
+    with qs.State(n, qs.C64) as st:
+        st.set_amplitudes(a)
+        st.qft()
+        got = st.gather(np.array(js, dtype=np.uint64))
+    want = dense.dft_entries(a, n, js)
+    d = np.abs(got - want)
+    return {"outputs": js, "max_abs": float(d.max()), "max_rel": float(d.max() / np.abs(want).max()),
+            "reference": "oracle direct sum of Eq. dft, float64"}
 
 
 def _kernel_rates(prof: dict, flops_of=None) -> dict:
@@ -498,7 +541,6 @@ def main() -> int:
     st = qs.State(n, qs.C64)
     a = workloads.gaussian_state(n, 0)
     st.set_amplitudes(a)
-    del a
     stream = torch.cuda.current_stream()
 
     for _ in range(args.warmup):
@@ -549,7 +591,7 @@ def main() -> int:
     del src, dst
 
     # gate-by-gate QFT for comparison (27 H, 351 CP, 13 relabels)
-    st.set_amplitudes(workloads.gaussian_state(n, 0))
+    st.set_amplitudes(a)
     gates = [g for g in _qft_gates(n)]
     for g in gates:
         qs.apply_gate(st, g)
@@ -618,6 +660,7 @@ def main() -> int:
             sec["heat_maps"] = bench_heat_maps(workloads, protocol)
         out["secondary"] = sec
     if not args.no_cpu:
+        out["error_vs_oracle"] = error_vs_oracle(qs, workloads, n, a)
         out["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(out), flush=True)
     return 0

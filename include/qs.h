@@ -503,8 +503,12 @@ int qs_check(qs_state* st, double tol);
  *                    rows) or 7 (512-byte rows), both 64 KiB tiles; a 7-bit
  *                    pass always has 512-byte rows unless qft.col_rows = 1;
  *   "qft.col_rows"   1: strided passes of 7 bits use 256-byte rows (32 KiB
- *                    tiles); 0 (default): 512-byte rows;
- *   "qft.threads"    thread cap of the LDS tile launches: 256 or 512 (default);
+ *                    tiles); 2: also complex64 passes of 8 bits use 128-byte
+ *                    rows (32 KiB); 0 (default): 512-byte rows for 7 bits,
+ *                    256-byte rows for 8;
+ *   "qft.threads"    thread cap of the LDS tile launches: 256, 512, or 0
+ *                    (default: 512 for strided passes of 8 bits, 256 for
+ *                    the others);
  *   "qft.round_bits" widest in-register round inside an LDS tile: 4 (default)
  *                    or 5 (complex64 only);
  *   "tile.low_bits"  contiguous low bits of a complex64 tile: 5 (default,

@@ -47,7 +47,7 @@ def qft_candidates(n: int):
     or register passes above it, thread cap, in-register round width, and the
     widest strided pass (7 bits with 512-byte rows, 8 with 256-byte rows)."""
     lds = [0] + [b for b in (11, 12) if b <= n]
-    return list(itertools.product(lds, (0, 1), (256, 512), (4, 5), (7, 8)))
+    return list(itertools.product(lds, (0, 1), (0, 256, 512), (4, 5), (7, 8)))
 
 
 def tune_qft(n: int = 27, reps: int = 5, candidates=None) -> dict:

@@ -334,13 +334,14 @@ int qs_tune_set(const char* key, int64_t value) {
     if (value < 0 || value > 1) return fail(QS_E_INVAL, "fused.mfma must be 0 or 1");
     g_fused_mfma = int(value);
   } else if (!std::strcmp(key, "qft.threads")) {
-    if (value != 256 && value != 512) return fail(QS_E_INVAL, "qft.threads must be 256 or 512");
+    if (value != 0 && value != 256 && value != 512)
+      return fail(QS_E_INVAL, "qft.threads must be 0 (by pass width), 256 or 512");
     g_qft_tune.threads = int(value);
   } else if (!std::strcmp(key, "qft.round_bits")) {
     if (value != 4 && value != 5) return fail(QS_E_INVAL, "qft.round_bits must be 4 or 5");
     g_qft_tune.round_bits = int(value);
   } else if (!std::strcmp(key, "qft.col_rows")) {
-    if (value < 0 || value > 1) return fail(QS_E_INVAL, "qft.col_rows must be 0 or 1");
+    if (value < 0 || value > 2) return fail(QS_E_INVAL, "qft.col_rows must be 0, 1 or 2");
     g_qft_tune.col_rows = int(value);
   } else if (!std::strcmp(key, "qft.col_max")) {
     if (value != 7 && value != 8) return fail(QS_E_INVAL, "qft.col_max must be 7 or 8");

@@ -50,12 +50,6 @@ namespace {
 
 constexpr int kBlock = 256;
 
-template <typename R>
-struct Roots32 {
-  R re[32];
-  R im[32];
-};
-
 template <typename R> struct Cx { R r, i; };
 template <typename R> struct Vec8;
 template <> struct Vec8<float> { using T = float2; };
@@ -75,86 +69,112 @@ constexpr int rev_bits(int x, int k) {
   return r;
 }
 
-// Natural order: stages jj = G-1 .. 0 on v[0 .. 2^G) held by one thread.
-// ls = (index bits below lo) >> start, e0 = lo - start.
-template <typename R, int G>
-__device__ __forceinline__ void stages_fwd(Cx<R> (&v)[1 << G], uint64_t ls, int e0, int sign,
-                                           const Roots32<R>& rt) {
-  const R lsr = R(ls);
-  Cx<R> tw[G > 1 ? (1 << (G - 1)) : 1];
+// cos(pi j / 32), j = 0 .. 16 (float64 literals, rounded once to R where used)
+__device__ constexpr double kCos32[17] = {
+    1.0, 0.99518472667219693, 0.98078528040323043, 0.95694033573220882,
+    0.92387953251128674, 0.88192126434835505, 0.83146961230254524, 0.77301045336273699,
+    0.70710678118654757, 0.63439328416364549, 0.55557023301960229, 0.47139673682599781,
+    0.38268343236508984, 0.29028467725446233, 0.19509032201612833, 0.09801714032956077,
+    0.0};
+
+// x * e^{i pi SIGN k / 2^b} for 0 <= k < 2^b <= 32, with k and b known at
+// compile time once the butterfly loops are unrolled: nothing for k = 0, a
+// swap for pi/2, a complex product with literal constants otherwise.
+template <typename R, int SIGN>
+__device__ __forceinline__ Cx<R> rot(Cx<R> x, int k, int b) {
+  if (k == 0) return x;
+  const int a = k << (5 - b);  // angle in units of pi/32, in (0, 32)
+  if (a == 16) return SIGN > 0 ? Cx<R>{-x.i, x.r} : Cx<R>{x.i, -x.r};
+  const R c = R(a < 16 ? kCos32[a] : -kCos32[32 - a]);
+  const R s = R(SIGN) * R(a < 16 ? kCos32[16 - a] : kCos32[a - 16]);
+  return {x.r * c - x.i * s, x.r * s + x.i * c};
+}
+
+// The butterflies of G consecutive stages on the 2^G amplitudes of one thread
+// with the twiddles of the bits inside the group only (constants).
+// Natural order: stages jj = G-1 .. 0; stage jj is the butterfly on bit jj,
+// then e^{i pi u / 2^jj} on the amplitudes with bit jj set, u = bits below jj.
+// Bit-reversed order: stages jj = 0 .. G-1; the twiddle is
+// e^{i pi sum_{d>=1} bit(jj+d) / 2^d} over the bits above jj.
+template <typename R, int G, bool REV, int SIGN>
+__device__ __forceinline__ void local_stages(Cx<R> (&v)[1 << G]) {
 #pragma unroll
-  for (int jj = G - 1; jj >= 0; --jj) {
-    R s, c;
-    sc_pi(lsr * R(sign) * ldexp(R(1), -(e0 + jj)), &s, &c);
-    const Cx<R> w{c, s};
-#pragma unroll
-    for (int k = 0; k < (1 << jj); ++k) {
-      const int idx = k << (5 - jj);
-      tw[k] = cmul(Cx<R>{rt.re[idx], R(sign) * rt.im[idx]}, w);
-    }
+  for (int t = 0; t < G; ++t) {
+    const int jj = REV ? t : G - 1 - t;
 #pragma unroll
     for (int m = 0; m < (1 << G); ++m) {
       if (m & (1 << jj)) continue;
       const int m1 = m | (1 << jj);
       const Cx<R> x = v[m], y = v[m1];
       v[m] = {x.r + y.r, x.i + y.i};
-      v[m1] = cmul(Cx<R>{x.r - y.r, x.i - y.i}, tw[m & ((1 << jj) - 1)]);
+      const Cx<R> d{x.r - y.r, x.i - y.i};
+      if (REV) {
+        const int kb = G - 1 - jj;  // bits above jj
+        v[m1] = rot<R, SIGN>(d, rev_bits(m >> (jj + 1), kb), kb);
+      } else {
+        v[m1] = rot<R, SIGN>(d, m & ((1 << jj) - 1), jj);
+      }
     }
   }
 }
 
-// Bit-reversed order: stages jj = 0 .. G-1. hx = the range bits above the
-// pass, bit-reversed (H of them).
-template <typename R, int G>
-__device__ __forceinline__ void stages_rev(Cx<R> (&v)[1 << G], uint64_t hx, int H, int sign,
-                                           const Roots32<R>& rt) {
-  const R hxr = R(hx);
-  Cx<R> tw[G > 1 ? (1 << (G - 1)) : 1];
+// The twiddles of the bits outside the group. Each stage's factor from those
+// bits multiplies the amplitudes with the stage's own bit set and commutes
+// with the group's later butterflies (they act on other bits), so all of them
+// are applied after the butterflies: amplitude m gets w^e(m), with
+// e(m) = m bit-reversed (natural order) or m (bit-reversed order), and
+// w = e^{i pi SIGN f} from one sincospi of an exact argument f. The powers
+// are built by squaring and by one more factor w (at most 2 G products).
+template <typename R, int G, bool REV>
+__device__ __forceinline__ void outer_twiddles(Cx<R> (&v)[1 << G], R f) {
+  R s, c;
+  sc_pi(f, &s, &c);
+  Cx<R> pw[1 << G];
+  pw[1] = {c, s};
 #pragma unroll
-  for (int jj = 0; jj < G; ++jj) {
-    R s = 0, c = 1;
-    if (H > 0) sc_pi(hxr * R(sign) * ldexp(R(1), -(H - 1 + G - jj)), &s, &c);
-    const Cx<R> w{c, s};
-    const int kb = G - 1 - jj;  // pass bits above jj
+  for (int k = 2; k < (1 << G); ++k)
+    pw[k] = (k & 1) ? cmul(pw[k - 1], pw[1]) : cmul(pw[k >> 1], pw[k >> 1]);
 #pragma unroll
-    for (int k = 0; k < (1 << kb); ++k) {
-      const int idx = kb > 0 ? (rev_bits(k, kb) << (5 - kb)) : 0;
-      tw[k] = cmul(Cx<R>{rt.re[idx], R(sign) * rt.im[idx]}, w);
-    }
-#pragma unroll
-    for (int m = 0; m < (1 << G); ++m) {
-      if (m & (1 << jj)) continue;
-      const int m1 = m | (1 << jj);
-      const Cx<R> x = v[m], y = v[m1];
-      v[m] = {x.r + y.r, x.i + y.i};
-      v[m1] = cmul(Cx<R>{x.r - y.r, x.i - y.i}, tw[m >> (jj + 1)]);
-    }
-  }
+  for (int m = 1; m < (1 << G); ++m) v[m] = cmul(v[m], pw[REV ? m : rev_bits(m, G)]);
 }
 
 // Stages of the bits [lo, lo+G) for the amplitudes of one thread; xg is the
 // global index of its element 0.
-template <typename R, int G, bool REV>
-__device__ __forceinline__ void pass_stages(Cx<R> (&v)[1 << G], uint64_t xg, int start, int len,
-                                            int lo, int sign, const Roots32<R>& rt) {
+template <typename R, int G, bool REV, int SIGN>
+__device__ __forceinline__ void pass_stages_s(Cx<R> (&v)[1 << G], uint64_t xg, int start,
+                                              int len, int lo) {
+  local_stages<R, G, REV, SIGN>(v);
   if constexpr (REV) {
+    // bits above the group, bit-reversed: hx / 2^H is their binary fraction
     const int H = start + len - lo - G;
-    uint64_t hx = 0;
     if (H > 0) {
       const uint64_t hf = (xg >> (lo + G)) & ((uint64_t(1) << H) - 1);
-      hx = __builtin_bitreverse64(hf) >> (64 - H);
+      const uint64_t hx = __builtin_bitreverse64(hf) >> (64 - H);
+      outer_twiddles<R, G, REV>(v, R(SIGN) * R(hx) * ldexp(R(1), -(H + G - 1)));
     }
-    stages_rev<R, G>(v, hx, H, sign, rt);
   } else {
-    const uint64_t ls = (xg & ((uint64_t(1) << lo) - 1)) >> start;
-    stages_fwd<R, G>(v, ls, lo - start, sign, rt);
+    // range bits below the group: ls / 2^(lo-start) is their binary fraction
+    const int e0 = lo - start;
+    if (e0 > 0) {
+      const uint64_t ls = (xg & ((uint64_t(1) << lo) - 1)) >> start;
+      outer_twiddles<R, G, REV>(v, R(SIGN) * R(ls) * ldexp(R(1), -(e0 + G - 1)));
+    }
   }
+}
+
+template <typename R, int G, bool REV>
+__device__ __forceinline__ void pass_stages(Cx<R> (&v)[1 << G], uint64_t xg, int start, int len,
+                                            int lo, int sign) {
+  if (sign > 0)
+    pass_stages_s<R, G, REV, 1>(v, xg, start, len, lo);
+  else
+    pass_stages_s<R, G, REV, -1>(v, xg, start, len, lo);
 }
 
 // ------------------------------------------------------------------ register pass
 template <typename R, int G, bool REV>
 __global__ void __launch_bounds__(kBlock) k_qft_reg(R* __restrict__ a, int n, int start, int len,
-                                                    int lo, int sign, R scale, Roots32<R> rt) {
+                                                    int lo, int sign, R scale) {
   using V = typename Vec8<R>::T;
   const uint64_t total = uint64_t(1) << (n - G);
   for (uint64_t r = uint64_t(blockIdx.x) * kBlock + threadIdx.x; r < total;
@@ -169,7 +189,7 @@ __global__ void __launch_bounds__(kBlock) k_qft_reg(R* __restrict__ a, int n, in
       const V t = p[m * stride];
       v[m] = {t.x, t.y};
     }
-    pass_stages<R, G, REV>(v, base, start, len, lo, sign, rt);
+    pass_stages<R, G, REV>(v, base, start, len, lo, sign);
 #pragma unroll
     for (int m = 0; m < (1 << G); ++m) {
       V t;
@@ -199,14 +219,14 @@ __device__ __forceinline__ int lds_pos(int x) { return PAD ? x + (x >> 4) : x; }
 // differ in those bits. Entry (tile index) -> global index via `glob`.
 template <typename R, int W, bool REV, bool PAD, int NT, typename Glob>
 __device__ __forceinline__ void tile_round(Cx<R>* sm, int TB, int b0, int start, int len,
-                                           int glo, int sign, const Roots32<R>& rt, Glob glob) {
+                                           int glo, int sign, Glob glob) {
   const int cols = 1 << (TB - W);
   for (int q = threadIdx.x; q < cols; q += NT) {
     const int x0 = (q & ((1 << b0) - 1)) | ((q >> b0) << (b0 + W));
     Cx<R> v[1 << W];
 #pragma unroll
     for (int m = 0; m < (1 << W); ++m) v[m] = sm[lds_pos<PAD>(x0 | (m << b0))];
-    pass_stages<R, W, REV>(v, glob(x0), start, len, glo, sign, rt);
+    pass_stages<R, W, REV>(v, glob(x0), start, len, glo, sign);
 #pragma unroll
     for (int m = 0; m < (1 << W); ++m) sm[lds_pos<PAD>(x0 | (m << b0))] = v[m];
   }
@@ -226,7 +246,7 @@ __host__ __device__ constexpr int round_width(int bits, int wmax) {
 // when bit-reversed.
 template <typename R, bool REV, bool PAD, int NT, int WMAX, typename Glob>
 __device__ __forceinline__ void tile_rounds(Cx<R>* sm, int TB, int b_lo, int b_hi, int glo_base,
-                                            int start, int len, int sign, const Roots32<R>& rt,
+                                            int start, int len, int sign,
                                             Glob glob) {
   const int bits = b_hi - b_lo;
   const int rounds = round_count(bits, WMAX);
@@ -240,13 +260,13 @@ __device__ __forceinline__ void tile_rounds(Cx<R>* sm, int TB, int b_lo, int b_h
     const int b0 = top - w;
     const int glo = glo_base + (b0 - b_lo);
     switch (w) {
-      case 1: tile_round<R, 1, REV, PAD, NT>(sm, TB, b0, start, len, glo, sign, rt, glob); break;
-      case 2: tile_round<R, 2, REV, PAD, NT>(sm, TB, b0, start, len, glo, sign, rt, glob); break;
-      case 3: tile_round<R, 3, REV, PAD, NT>(sm, TB, b0, start, len, glo, sign, rt, glob); break;
-      case 4: tile_round<R, 4, REV, PAD, NT>(sm, TB, b0, start, len, glo, sign, rt, glob); break;
+      case 1: tile_round<R, 1, REV, PAD, NT>(sm, TB, b0, start, len, glo, sign, glob); break;
+      case 2: tile_round<R, 2, REV, PAD, NT>(sm, TB, b0, start, len, glo, sign, glob); break;
+      case 3: tile_round<R, 3, REV, PAD, NT>(sm, TB, b0, start, len, glo, sign, glob); break;
+      case 4: tile_round<R, 4, REV, PAD, NT>(sm, TB, b0, start, len, glo, sign, glob); break;
       default:
         if constexpr (WMAX >= 5)
-          tile_round<R, 5, REV, PAD, NT>(sm, TB, b0, start, len, glo, sign, rt, glob);
+          tile_round<R, 5, REV, PAD, NT>(sm, TB, b0, start, len, glo, sign, glob);
         break;
     }
     __syncthreads();
@@ -258,8 +278,7 @@ __device__ __forceinline__ void tile_rounds(Cx<R>* sm, int TB, int b_lo, int b_h
 // two waves per SIMD (at most 256 VGPRs) keeps both resident.
 template <typename R, int T, bool REV, int NT, int WMAX>
 __global__ void __launch_bounds__(NT, sizeof(R) == 4 ? 2 : 1)
-    k_qft_lds(R* __restrict__ a, int start, int len, int lo, int hi, int sign, R scale,
-              Roots32<R> rt) {
+    k_qft_lds(R* __restrict__ a, int start, int len, int lo, int hi, int sign, R scale) {
   extern __shared__ unsigned char smraw[];
   Cx<R>* sm = reinterpret_cast<Cx<R>*>(smraw);
   using V = typename Vec16<R>::T;
@@ -282,7 +301,7 @@ __global__ void __launch_bounds__(NT, sizeof(R) == 4 ? 2 : 1)
     }
   }
   __syncthreads();
-  tile_rounds<R, REV, true, NT, WMAX>(sm, T, lo, hi, lo, start, len, sign, rt,
+  tile_rounds<R, REV, true, NT, WMAX>(sm, T, lo, hi, lo, start, len, sign,
                                       [tile_base](int x) { return tile_base | uint64_t(x); });
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
@@ -303,7 +322,7 @@ __global__ void __launch_bounds__(NT, sizeof(R) == 4 ? 2 : 1)
 // (global bits [0, C)), C <= lo. Tile index = row * 2^C + column.
 template <typename R, int G, int C, bool REV, int NT, int WMAX>
 __global__ void __launch_bounds__(NT) k_qft_col(R* __restrict__ a, int start, int len, int lo,
-                                                int sign, R scale, Roots32<R> rt) {
+                                                int sign, R scale) {
   extern __shared__ unsigned char smraw[];
   Cx<R>* sm = reinterpret_cast<Cx<R>*>(smraw);
   using V = typename Vec16<R>::T;
@@ -338,7 +357,7 @@ __global__ void __launch_bounds__(NT) k_qft_col(R* __restrict__ a, int start, in
     }
   }
   __syncthreads();
-  tile_rounds<R, REV, false, NT, WMAX>(sm, TB, C, TB, lo, start, len, sign, rt, glob);
+  tile_rounds<R, REV, false, NT, WMAX>(sm, TB, C, TB, lo, start, len, sign, glob);
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     const int e = threadIdx.x + k * NT;
@@ -358,17 +377,6 @@ __global__ void __launch_bounds__(NT) k_qft_col(R* __restrict__ a, int start, in
   }
 }
 
-template <typename R>
-Roots32<R> make_roots() {
-  Roots32<R> rt;
-  for (int k = 0; k < 32; ++k) {
-    // e^{i pi k / 32}, evaluated in float64 and rounded once
-    const double ang = 3.14159265358979323846 * double(k) / 32.0;
-    rt.re[k] = static_cast<R>(cos(ang));
-    rt.im[k] = static_cast<R>(sin(ang));
-  }
-  return rt;
-}
 
 // Tile shapes: the contiguous tile has 2^13 complex64 / 2^12 complex128
 // entries (64 KiB plus padding); the strided tile 2^7 rows x 64 (complex64)
@@ -398,18 +406,18 @@ void allow_lds(K kernel, size_t bytes) {
 
 template <typename R, int G, bool REV>
 hipError_t launch_reg(R* a, int n, int start, int len, int lo, int sign, R scale,
-                      const Roots32<R>& rt, hipStream_t s) {
+                      hipStream_t s) {
   const uint64_t threads = uint64_t(1) << (n - G);
   const uint64_t want = (threads + kBlock - 1) / kBlock, cap = uint64_t(1) << 20;
   const unsigned grid = static_cast<unsigned>(want < cap ? want : cap);
   hipLaunchKernelGGL((k_qft_reg<R, G, REV>), dim3(grid), dim3(kBlock), 0, s, a, n, start, len, lo,
-                     sign, scale, rt);
+                     sign, scale);
   return hipGetLastError();
 }
 
 template <typename R, int G, int C, bool REV, int CAP, int WMAX>
 hipError_t launch_col_cfg(R* a, int n, int start, int len, int lo, int sign, R scale,
-                          const Roots32<R>& rt, hipStream_t s) {
+                          hipStream_t s) {
   if (lo < C || n < lo + G) return hipErrorInvalidValue;
   constexpr int NT =
       tile_threads(G + C, (1 << (G + C)) / Vec16<R>::AMPS, round_width(G, WMAX), CAP);
@@ -417,20 +425,20 @@ hipError_t launch_col_cfg(R* a, int n, int start, int len, int lo, int sign, R s
   auto kern = k_qft_col<R, G, C, REV, NT, WMAX>;
   allow_lds(kern, bytes);
   const unsigned grid = static_cast<unsigned>(uint64_t(1) << (n - G - C));
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), bytes, s, a, start, len, lo, sign, scale, rt);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), bytes, s, a, start, len, lo, sign, scale);
   return hipGetLastError();
 }
 
 template <typename R, int T, bool REV, int CAP, int WMAX>
 hipError_t launch_lds_cfg(R* a, int n, int start, int len, int lo, int hi, int sign, R scale,
-                          const Roots32<R>& rt, hipStream_t s) {
+                          hipStream_t s) {
   constexpr int VEC = (1 << T) / Vec16<R>::AMPS > 0 ? (1 << T) / Vec16<R>::AMPS : 1;
   constexpr int NT = tile_threads(T, VEC, round_width(T, WMAX), CAP);
   const size_t bytes = size_t((1 << T) + ((1 << T) >> 4)) * 2 * sizeof(R);
   auto kern = k_qft_lds<R, T, REV, NT, WMAX>;
   allow_lds(kern, bytes);
   const unsigned grid = static_cast<unsigned>(uint64_t(1) << (n - T));
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), bytes, s, a, start, len, lo, hi, sign, scale, rt);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), bytes, s, a, start, len, lo, hi, sign, scale);
   return hipGetLastError();
 }
 
@@ -439,58 +447,66 @@ hipError_t launch_lds_cfg(R* a, int n, int start, int len, int lo, int hi, int s
 // tiles always use cap 256 and rounds of 4.
 template <typename R, int G, int C, bool REV>
 hipError_t launch_col_c(R* a, int n, int start, int len, int lo, int sign, R scale,
-                        const Roots32<R>& rt, const QftTuning& tune, hipStream_t s) {
-  if (G < 5 || (tune.threads < 512 && tune.round_bits < 5))
-    return launch_col_cfg<R, G, C, REV, 256, 4>(a, n, start, len, lo, sign, scale, rt, s);
-  if (tune.threads >= 512 && tune.round_bits >= 5)
-    return launch_col_cfg<R, G, C, REV, 512, 5>(a, n, start, len, lo, sign, scale, rt, s);
-  if (tune.threads >= 512)
-    return launch_col_cfg<R, G, C, REV, 512, 4>(a, n, start, len, lo, sign, scale, rt, s);
-  return launch_col_cfg<R, G, C, REV, 256, 5>(a, n, start, len, lo, sign, scale, rt, s);
+                        const QftTuning& tune, hipStream_t s) {
+  // thread cap: the knob, or (0) 512 for passes of 8 bits and 256 otherwise
+  const int cap = tune.threads > 0 ? tune.threads : (G == 8 ? 512 : 256);
+  if (G < 5 || (cap < 512 && tune.round_bits < 5))
+    return launch_col_cfg<R, G, C, REV, 256, 4>(a, n, start, len, lo, sign, scale, s);
+  if (cap >= 512 && tune.round_bits >= 5)
+    return launch_col_cfg<R, G, C, REV, 512, 5>(a, n, start, len, lo, sign, scale, s);
+  if (cap >= 512)
+    return launch_col_cfg<R, G, C, REV, 512, 4>(a, n, start, len, lo, sign, scale, s);
+  return launch_col_cfg<R, G, C, REV, 256, 5>(a, n, start, len, lo, sign, scale, s);
 }
 
 // Strided tiles of 2^G rows x 2^C columns: 512-byte rows (64 KiB at G = 7),
-// or 256-byte rows for G = 8 (64 KiB) and, with qft.col_rows = 1, for G = 7
-// (32 KiB, more workgroups per CU).
+// or 256-byte rows for G = 8 (64 KiB) and, with qft.col_rows >= 1, for G = 7
+// (32 KiB, more workgroups per CU); qft.col_rows = 2 also gives complex64
+// passes of 8 bits 128-byte rows (32 KiB).
 template <typename R, int G, bool REV>
 hipError_t launch_col(R* a, int n, int start, int len, int lo, int sign, R scale,
-                      const Roots32<R>& rt, const QftTuning& tune, hipStream_t s) {
+                      const QftTuning& tune, hipStream_t s) {
   constexpr int CB = col_bits<R>();
-  if constexpr (G == 8)
-    return launch_col_c<R, G, CB - 1, REV>(a, n, start, len, lo, sign, scale, rt, tune, s);
+  if constexpr (G == 8) {
+    if constexpr (sizeof(R) == 4)
+      if (tune.col_rows == 2)  // 128-byte rows, 32 KiB tiles
+        return launch_col_c<R, G, CB - 2, REV>(a, n, start, len, lo, sign, scale, tune, s);
+    return launch_col_c<R, G, CB - 1, REV>(a, n, start, len, lo, sign, scale, tune, s);
+  }
   if constexpr (G == 7)
-    if (tune.col_rows == 1)
-      return launch_col_c<R, G, CB - 1, REV>(a, n, start, len, lo, sign, scale, rt, tune, s);
-  return launch_col_c<R, G, CB, REV>(a, n, start, len, lo, sign, scale, rt, tune, s);
+    if (tune.col_rows >= 1)
+      return launch_col_c<R, G, CB - 1, REV>(a, n, start, len, lo, sign, scale, tune, s);
+  return launch_col_c<R, G, CB, REV>(a, n, start, len, lo, sign, scale, tune, s);
 }
 
 template <typename R, int T, bool REV>
 hipError_t launch_lds_t(R* a, int n, int start, int len, int lo, int hi, int sign, R scale,
-                        const Roots32<R>& rt, const QftTuning& tune, hipStream_t s) {
+                        const QftTuning& tune, hipStream_t s) {
   // complex128 stays at rounds of 4 bits: 32 double-precision amplitudes per
   // thread would leave one wave per SIMD
-  if (T < 11 || sizeof(R) == 8 || (tune.threads < 512 && tune.round_bits < 5))
-    return launch_lds_cfg<R, T, REV, 256, 4>(a, n, start, len, lo, hi, sign, scale, rt, s);
-  if (tune.threads >= 512 && tune.round_bits >= 5)
-    return launch_lds_cfg<R, T, REV, 512, 5>(a, n, start, len, lo, hi, sign, scale, rt, s);
-  if (tune.threads >= 512)
-    return launch_lds_cfg<R, T, REV, 512, 4>(a, n, start, len, lo, hi, sign, scale, rt, s);
-  return launch_lds_cfg<R, T, REV, 256, 5>(a, n, start, len, lo, hi, sign, scale, rt, s);
+  const int cap = tune.threads > 0 ? tune.threads : 256;
+  if (T < 11 || sizeof(R) == 8 || (cap < 512 && tune.round_bits < 5))
+    return launch_lds_cfg<R, T, REV, 256, 4>(a, n, start, len, lo, hi, sign, scale, s);
+  if (cap >= 512 && tune.round_bits >= 5)
+    return launch_lds_cfg<R, T, REV, 512, 5>(a, n, start, len, lo, hi, sign, scale, s);
+  if (cap >= 512)
+    return launch_lds_cfg<R, T, REV, 512, 4>(a, n, start, len, lo, hi, sign, scale, s);
+  return launch_lds_cfg<R, T, REV, 256, 5>(a, n, start, len, lo, hi, sign, scale, s);
 }
 
 template <typename R, bool REV>
 hipError_t launch_lds(R* a, int n, int T, int start, int len, int lo, int hi, int sign, R scale,
-                      const Roots32<R>& rt, const QftTuning& tune, hipStream_t s) {
+                      const QftTuning& tune, hipStream_t s) {
   switch (T) {
 #define QS_LDS_CASE(t) \
-  case t: return launch_lds_t<R, t, REV>(a, n, start, len, lo, hi, sign, scale, rt, tune, s);
+  case t: return launch_lds_t<R, t, REV>(a, n, start, len, lo, hi, sign, scale, tune, s);
     QS_LDS_CASE(1) QS_LDS_CASE(2) QS_LDS_CASE(3) QS_LDS_CASE(4) QS_LDS_CASE(5) QS_LDS_CASE(6)
     QS_LDS_CASE(7) QS_LDS_CASE(8) QS_LDS_CASE(9) QS_LDS_CASE(10) QS_LDS_CASE(11)
     QS_LDS_CASE(12)
 #undef QS_LDS_CASE
     case 13:
       if constexpr (sizeof(R) == 4)
-        return launch_lds_t<R, 13, REV>(a, n, start, len, lo, hi, sign, scale, rt, tune, s);
+        return launch_lds_t<R, 13, REV>(a, n, start, len, lo, hi, sign, scale, tune, s);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
@@ -499,31 +515,30 @@ hipError_t launch_lds(R* a, int n, int T, int start, int len, int lo, int hi, in
 template <typename R, bool REV>
 hipError_t launch_pass(R* a, int n, int start, int len, const QftPass& ps, int sign,
                        const QftTuning& tune, hipStream_t s) {
-  const Roots32<R> rt = make_roots<R>();
   const R scale = R(ps.scale);
   const int G = ps.hi - ps.lo;
   switch (ps.kind) {
     case QftPass::LDS:
-      return launch_lds<R, REV>(a, n, ps.tile, start, len, ps.lo, ps.hi, sign, scale, rt, tune, s);
+      return launch_lds<R, REV>(a, n, ps.tile, start, len, ps.lo, ps.hi, sign, scale, tune, s);
     case QftPass::COL:
       switch (G) {
-        case 1: return launch_col<R, 1, REV>(a, n, start, len, ps.lo, sign, scale, rt, tune, s);
-        case 2: return launch_col<R, 2, REV>(a, n, start, len, ps.lo, sign, scale, rt, tune, s);
-        case 3: return launch_col<R, 3, REV>(a, n, start, len, ps.lo, sign, scale, rt, tune, s);
-        case 4: return launch_col<R, 4, REV>(a, n, start, len, ps.lo, sign, scale, rt, tune, s);
-        case 5: return launch_col<R, 5, REV>(a, n, start, len, ps.lo, sign, scale, rt, tune, s);
-        case 6: return launch_col<R, 6, REV>(a, n, start, len, ps.lo, sign, scale, rt, tune, s);
-        case 7: return launch_col<R, 7, REV>(a, n, start, len, ps.lo, sign, scale, rt, tune, s);
-        case 8: return launch_col<R, 8, REV>(a, n, start, len, ps.lo, sign, scale, rt, tune, s);
+        case 1: return launch_col<R, 1, REV>(a, n, start, len, ps.lo, sign, scale, tune, s);
+        case 2: return launch_col<R, 2, REV>(a, n, start, len, ps.lo, sign, scale, tune, s);
+        case 3: return launch_col<R, 3, REV>(a, n, start, len, ps.lo, sign, scale, tune, s);
+        case 4: return launch_col<R, 4, REV>(a, n, start, len, ps.lo, sign, scale, tune, s);
+        case 5: return launch_col<R, 5, REV>(a, n, start, len, ps.lo, sign, scale, tune, s);
+        case 6: return launch_col<R, 6, REV>(a, n, start, len, ps.lo, sign, scale, tune, s);
+        case 7: return launch_col<R, 7, REV>(a, n, start, len, ps.lo, sign, scale, tune, s);
+        case 8: return launch_col<R, 8, REV>(a, n, start, len, ps.lo, sign, scale, tune, s);
         default: return hipErrorInvalidValue;
       }
     case QftPass::REG:
       switch (G) {
-        case 1: return launch_reg<R, 1, REV>(a, n, start, len, ps.lo, sign, scale, rt, s);
-        case 2: return launch_reg<R, 2, REV>(a, n, start, len, ps.lo, sign, scale, rt, s);
-        case 3: return launch_reg<R, 3, REV>(a, n, start, len, ps.lo, sign, scale, rt, s);
-        case 4: return launch_reg<R, 4, REV>(a, n, start, len, ps.lo, sign, scale, rt, s);
-        case 5: return launch_reg<R, 5, REV>(a, n, start, len, ps.lo, sign, scale, rt, s);
+        case 1: return launch_reg<R, 1, REV>(a, n, start, len, ps.lo, sign, scale, s);
+        case 2: return launch_reg<R, 2, REV>(a, n, start, len, ps.lo, sign, scale, s);
+        case 3: return launch_reg<R, 3, REV>(a, n, start, len, ps.lo, sign, scale, s);
+        case 4: return launch_reg<R, 4, REV>(a, n, start, len, ps.lo, sign, scale, s);
+        case 5: return launch_reg<R, 5, REV>(a, n, start, len, ps.lo, sign, scale, s);
         default: return hipErrorInvalidValue;
       }
   }

@@ -288,7 +288,7 @@ def test_qft_pass_variants(qs_lib, dtype, high_pass, lds_bits):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("n,lds_bits,col_rows", [(19, 11, 0), (20, 12, 1), (22, 11, 1),
+@pytest.mark.parametrize("n,lds_bits,col_rows", [(19, 11, 0), (20, 12, 1), (22, 11, 1), (20, 12, 2),
                                                  (21, 0, 1)])
 def test_qft_eight_bit_strided_passes(qs_lib, dtype, n, lds_bits, col_rows):
     """Strided passes of 8 row bits (256-byte rows) above a smaller contiguous
@@ -316,3 +316,4 @@ def test_qft_eight_bit_strided_passes(qs_lib, dtype, n, lds_bits, col_rows):
     finally:
         for k, v in saved.items():
             qs.tune_set(k, v)
+
