@@ -273,6 +273,117 @@ def bench_approx(qs, workloads, protocol, np, family: str, p_cmp: float = 0.6,
     return out
 
 
+def test_costs(qs, workloads, np, torch, sizes=(8, 12, 16, 20, 24, 27), reps: int = 5) -> dict:
+    """What one exact separability test and one proposal cost: a factorized
+    state whose qubits all share one entangled subsystem of n_S qubits, every
+    qubit marked dirty, tested at p = 0 (nothing rounds); and one scoring call
+    of the network on 54 rows of features."""
+    out = {}
+    for ns in sizes:
+        # U3 on every qubit, a chain of CZ, U3 again: one entangled subsystem
+        ang = np.random.default_rng(500 + ns).uniform(0.0, 2 * math.pi, (2, ns, 3))
+        gates = ([("u3", q, *map(float, ang[0, q])) for q in range(ns)]
+                 + [("cz", q, q + 1) for q in range(ns - 1)]
+                 + [("u3", q, *map(float, ang[1, q])) for q in range(ns)])
+        ts = []
+        for _ in range(reps):
+            st = qs.State(ns, qs.C64, factorized=True, max_amps=2 ** 30)
+            c = qs.Circuit(ns).add_gates(gates)
+            st.run(c)
+            assert len(st.subsystems()) == 1
+            st.mark_dirty((1 << ns) - 1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st.try_separate(0.0)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) / ns)
+            st.free()
+            c.free()
+        out[f"exact_test_n{ns}_us"] = round(float(np.median(ts)) * 1e6, 2)
+    net = qs.MLP(qs.mlp_init(1))
+    X = np.random.default_rng(2).standard_normal((54, 32)).astype(np.float32)
+    net.forward(X)
+    ts = []
+    for _ in range(20):
+        t0 = time.perf_counter()
+        net.forward(X)
+        ts.append(time.perf_counter() - t0)
+    net.free()
+    out["proposal_54_rows_us"] = round(float(np.median(ts)) * 1e6, 2)
+    return out
+
+
+def bench_learned(qs, workloads, protocol, np, torch, widths=(36, 45, 54), depths=(7, 10),
+                  test_seeds=range(8), rows_target: int = 100000, reps: int = 3) -> dict:
+    """The learned proposal where exact tests are many and large: random
+    circuits (U3 + CZ/iSWAP on a random matching) of 36, 45 and 54 qubits with
+    7 and 10 layers, each held-out circuit at its own smallest completing p
+    (the descending search, cap 2^30). One network is trained on about 1e5
+    attempts of the plain schedule on seeds from 10,000, at thresholds around
+    each configuration's p_min. Both schedules run every test circuit at the
+    same p (median of `reps` runs); reported: completions, mean time, mean
+    log F, exact tests and skipped tests."""
+    out = {"workload": "random circuits (U3 + CZ/iSWAP matching), 36/45/54 qubits, 7 and 10 "
+                       "layers, each at its smallest completing p, cap 2^30, complex64"}
+    gen = {(n, d): (lambda s, n=n, d=d: workloads.random_circuit(n, d, s))
+           for n in widths for d in depths}
+    pmins = {}
+    for key, g in gen.items():
+        pm = []
+        for s in test_seeds:
+            r = protocol.minimum_p(key[0], g(s))
+            pm.append(r["best"]["p"] if r["best"] else None)
+        pmins[key] = pm
+    t0 = time.perf_counter()
+    Xs, ys, rows, seed = [], [], 0, 10000
+    while rows < rows_target:
+        for (n, d), g in gen.items():
+            ok = [p for p in pmins[(n, d)] if p is not None]
+            base = float(np.median(ok)) if ok else 1.0
+            ps = [q for q in (base - 0.05, base, base + 0.05, base + 0.1) if 0.0 < q <= 1.0]
+            X, y = protocol.collect_attempts(n, [g(seed)], ps)
+            Xs.append(X)
+            ys.append(y)
+            rows += len(y)
+        seed += 1
+    X, y = np.concatenate(Xs), np.concatenate(ys)
+    net, cutoff, loss = protocol.train_proposer(X, y, steps=6000, recall=0.97)
+    out["training"] = {"rows": int(len(y)), "positive": round(float(y.mean()), 4),
+                       "seeds": f"10000-{seed - 1}", "loss": round(loss, 4),
+                       "cutoff": round(cutoff, 4),
+                       "collect_and_train_s": round(time.perf_counter() - t0, 1)}
+    for (n, d), g in gen.items():
+        res = {"plain": [], "learned": []}
+        for s, p in zip(test_seeds, pmins[(n, d)]):
+            if p is None:
+                continue
+            gates = g(s)
+            for form in ("plain", "learned"):
+                kw = {} if form == "plain" else {"proposer": net, "cutoff": cutoff}
+                runs = [protocol.approx_run(n, gates, p, record=True, **kw) for _ in range(reps)]
+                r = runs[-1]
+                res[form].append({"ok": all(x["ok"] for x in runs),
+                                  "t": float(np.median([x["time_s"] for x in runs])),
+                                  "F": r["F"], "tests": r["attempts"],
+                                  "skipped": r.get("skipped", 0), "max_sub": r["max_sub"]})
+        row = {"p_min": pmins[(n, d)]}
+        for form, rs in res.items():
+            ok = [x for x in rs if x["ok"]]
+            row[form] = {"completed": len(ok), "of": len(rs),
+                         "time_ms_mean": round(1e3 * float(np.mean([x["t"] for x in rs])), 3)
+                         if rs else None,
+                         "logF_mean": round(float(np.mean([np.log(x["F"]) for x in ok])), 3)
+                         if ok else None,
+                         "exact_tests": sum(x["tests"] for x in rs),
+                         "skipped": sum(x["skipped"] for x in rs),
+                         "max_sub": max((x["max_sub"] for x in rs), default=None)}
+        out[f"n{n}_d{d}"] = row
+        print(f"learned: n={n} d={d} {json.dumps(row)}", file=sys.stderr, flush=True)
+    net.free()
+    out["costs"] = test_costs(qs, workloads, np, torch)
+    return out
+
+
 def bench_pairs(qs, workloads, np, torch, n: int = 54, layers: int = 7, seeds=range(5)) -> dict:
     """Entangled pairs weakly coupled along a chain (the workload of the
     two-qubit rounding): the one-qubit schedule against the pair policy at
@@ -500,7 +611,7 @@ def main() -> int:
     ap.add_argument("--quick", action="store_true",
                     help="only the QFT (skip the circuit, approximate, batch and validation runs)")
     ap.add_argument("--section", action="append", default=[],
-                    choices=["qft_sizes", "circuit", "approx", "pairs", "qft_factorized", "held", "batch",
+                    choices=["qft_sizes", "circuit", "approx", "learned", "pairs", "qft_factorized", "held", "batch",
                              "validation",
                              "depth_sweep", "heat_maps"],
                     help="run only these secondary sections (repeatable; default: all)")
@@ -634,7 +745,7 @@ def main() -> int:
     if not args.quick:
         from paper_2304_14969_amd import protocol
         sec = {}
-        want = set(args.section) or {"qft_sizes", "circuit", "approx", "pairs", "qft_factorized", "held",
+        want = set(args.section) or {"qft_sizes", "circuit", "approx", "learned", "pairs", "qft_factorized", "held",
                                      "batch", "validation"}
         if "qft_sizes" in want:
             sec["qft_sizes"] = bench_qft_sizes(qs, workloads, torch)
@@ -643,6 +754,8 @@ def main() -> int:
         if "approx" in want:
             for fam in ("grid", "matching"):
                 sec[f"approx54_{fam}"] = bench_approx(qs, workloads, protocol, np, fam)
+        if "learned" in want:
+            sec["learned"] = bench_learned(qs, workloads, protocol, np, torch)
         if "pairs" in want:
             sec["pair_chain54"] = bench_pairs(qs, workloads, np, torch)
         if "qft_factorized" in want:
