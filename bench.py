@@ -460,15 +460,18 @@ def bench_qft_factorized(qs, workloads, np, torch) -> dict:
 
 def bench_held(qs, workloads, np, torch) -> dict:
     """Held controlled phases and inversions (factor.hold) in exact factorized
-    runs, on and off: Bernstein-Vazirani circuits (every CX lands on an
+    runs, on and off, and holding with the kickback shortcut off
+    (factor.kickback): Bernstein-Vazirani circuits (every CX lands on an
     ancilla in |->) and a mix of controlled phases, inversions and the
     one-qubit gates that move them; cap 2^30 amplitudes, complex64."""
     out = {"workload": "exact factorized runs, complex64, cap 2^30: Bernstein-Vazirani "
                        "(n - 1 data qubits, ancilla in |->); held_gate_mix (2000 gates)"}
     saved = qs.tune_get("factor.hold")
+    saved_kick = qs.tune_get("factor.kickback")
 
-    def run(n, gates, hold, reps):
+    def run(n, gates, hold, reps, kick=1):
         qs.tune_set("factor.hold", hold)
+        qs.tune_set("factor.kickback", kick)
         ts, info = [], {}
         for _ in range(reps):
             st = qs.State(n, qs.C64, factorized=True, max_amps=2 ** 30)
@@ -500,11 +503,13 @@ def bench_held(qs, workloads, np, torch) -> dict:
             gates, secret = workloads.phase_kickback_circuit(n, n)
             for hold in (1, 0):
                 out[f"bv_n{n}_hold{hold}"] = dict(run(n, gates, hold, 5), ones=sum(secret))
+            out[f"bv_n{n}_hold1_kickback0"] = dict(run(n, gates, 1, 5, kick=0), ones=sum(secret))
         gates = workloads.held_gate_mix(24, 2000, 7)
         for hold in (1, 0):
             out[f"mix_n24_hold{hold}"] = run(24, gates, hold, 3)
     finally:
         qs.tune_set("factor.hold", saved)
+        qs.tune_set("factor.kickback", saved_kick)
     return out
 
 

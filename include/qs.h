@@ -21,7 +21,9 @@
  *  - Gate matrices are host double arrays, complex interleaved (re, im),
  *    row-major. For a k-qubit matrix, row/column bit j belongs to qubits[j].
  *  - After QS_E_DEVICE (a HIP runtime error) the state is poisoned: every
- *    later call on it except qs_free returns QS_E_DEVICE.
+ *    later call on it except qs_free returns QS_E_DEVICE. A factorized run
+ *    that cannot bring its state to a prefix of the circuit poisons it too
+ *    (qs_run).
  */
 #ifndef QS_H
 #define QS_H
@@ -47,7 +49,7 @@ enum {
                             non-finite matrix entry, size mismatch */
   QS_E_NOMEM = -2,       /* device allocation failed; the state is unchanged */
   QS_E_CAPACITY = -3,    /* a merge would exceed the amplitude cap; unchanged */
-  QS_E_DEVICE = -4,      /* HIP runtime error; the state is poisoned */
+  QS_E_DEVICE = -4,      /* HIP runtime error (or a poisoned state) */
   QS_E_NUMERIC = -5,     /* norm drift beyond the tolerance given to qs_check */
   QS_E_UNSUPPORTED = -6  /* valid request this build does not serve */
 };
@@ -414,7 +416,10 @@ int qs_circuit_block(const qs_circuit* c, int i, int* k, int* qubits, double* m)
  * takes the gates one by one under its separation policy (see
  * qs_held_count for the gates an exact run holds back); when a gate fails
  * there (QS_E_CAPACITY: a merge past the state's cap), the gates before it
- * are applied, held gates are dropped, and the state is not the circuit's. */
+ * are applied, the gates still held back among them included, so the state
+ * is that prefix of the circuit; if a held gate cannot be applied either, the
+ * handle is left unusable (every later call but qs_free returns
+ * QS_E_DEVICE). */
 int qs_run(qs_state* st, qs_circuit* c);
 
 /* ------------------------------------------------------------ batches */
@@ -553,6 +558,9 @@ int qs_check(qs_state* st, double tol);
  *                    workgroup per subsystem); 0: one launch per gate;
  *   "factor.hold"    1 (default): the held gates described at qs_held_count;
  *                    0: every such gate merges its operands at once;
+ *   "factor.kickback" 1 (default): a held gate whose target is a one-qubit
+ *                    subsystem in an eigenstate of its matrix acts on its
+ *                    control alone (qs_held_count); 0: off;
  *   "fused.mfma"     1 (default): complex64 blocks of 4 or 5 qubits run on the
  *                    matrix cores when their geometry fits; 0: vector FMA.
  * QS_E_INVAL for an unknown key or a value out of range. */

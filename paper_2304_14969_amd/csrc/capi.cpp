@@ -80,6 +80,7 @@ struct qs_state {
   hipStream_t stream = nullptr;
   int perm[64];          // logical qubit -> physical bit
   bool poisoned = false;
+  const char* poison_why = nullptr;  // set when not a device error poisoned it
   void* mat = nullptr;   // device slot for gate matrices
   double* red = nullptr; // reduction scratch: partials + result
   bool prof = false;
@@ -110,7 +111,9 @@ double ab(const qs_state* st) { return double(amp_bytes(st->dtype)); }
 
 int check_state(const qs_state* st) {
   if (!st) return fail(QS_E_INVAL, "state is NULL");
-  if (st->poisoned) return fail(QS_E_DEVICE, "state is unusable after an earlier device error");
+  if (st->poisoned)
+    return fail(QS_E_DEVICE, "state is unusable after an earlier %s",
+                st->poison_why ? st->poison_why : "device error");
   return QS_OK;
 }
 
@@ -361,6 +364,9 @@ int qs_tune_set(const char* key, int64_t value) {
   } else if (!std::strcmp(key, "factor.hold")) {
     if (value < 0 || value > 1) return fail(QS_E_INVAL, "factor.hold must be 0 or 1");
     qs::g_hold = int(value);
+  } else if (!std::strcmp(key, "factor.kickback")) {
+    if (value < 0 || value > 1) return fail(QS_E_INVAL, "factor.kickback must be 0 or 1");
+    qs::g_kickback = int(value);
   } else if (!std::strcmp(key, "factor.done_flag")) {
     if (value < 0 || value > 1) return fail(QS_E_INVAL, "factor.done_flag must be 0 or 1");
     qs::g_done_flag = int(value);
@@ -401,6 +407,7 @@ int qs_tune_get(const char* key, int64_t* value) {
   else if (!std::strcmp(key, "factor.done_flag")) *value = qs::g_done_flag;
   else if (!std::strcmp(key, "factor.fuse_ops")) *value = qs::g_fuse_ops;
   else if (!std::strcmp(key, "factor.hold")) *value = qs::g_hold;
+  else if (!std::strcmp(key, "factor.kickback")) *value = qs::g_kickback;
   else if (!std::strcmp(key, "factor.tile_1q")) *value = qs::g_tile_1q;
   else if (!std::strcmp(key, "tile.mfma")) *value = g_tile_mfma;
   else if (!std::strcmp(key, "qft.col_max")) *value = g_qft_tune.col_max;
@@ -1197,8 +1204,29 @@ int qs_run(qs_state* st, qs_circuit* c) {
       }
       return flush_1q();
     };
+    // A failed gate leaves the gates before it applied; the gates still held
+    // then are applied too (they commute with each other), so that the state
+    // is that prefix of the circuit. If one of them fails as well, the state
+    // is none of the circuit's and the handle refuses every later call.
+    auto apply_all_or_prefix = [&]() -> int {
+      const int rc = apply_all();
+      if (rc == QS_OK || held.empty()) return rc;
+      const std::string why = g_err;
+      while (!held.empty()) {
+        const qs::HeldGate x = held.front();
+        held.erase(held.begin());
+        if (apply_held(x) != QS_OK || flush_1q() != QS_OK) {
+          held.clear();
+          st->poisoned = true;
+          st->poison_why = "run that failed with gates held back";
+          break;
+        }
+      }
+      g_err = why;
+      return rc;
+    };
     qs::fact_begin_run(f);
-    if (int rc = fact_rc(st, qs::fact_end_run(f, apply_all()))) return rc;
+    if (int rc = fact_rc(st, qs::fact_end_run(f, apply_all_or_prefix()))) return rc;
     return fact_rc(st, qs::fact_relabel(f, c->pos.data()));
   }
   if (c->tiles && !c->gates.empty() &&

@@ -42,6 +42,7 @@ int g_kernarg_tables = 1;
 int g_done_flag = 1;
 int g_fuse_ops = 1;
 int g_hold = 1;
+int g_kickback = 1;
 
 void* device_alloc(size_t bytes);
 void device_free(void* p);
@@ -1093,7 +1094,7 @@ void held_matrix(const HeldGate& g, double* m) {
 int fact_sub_of(const FactorState* f, int q) { return find(f, q, nullptr); }
 
 bool fact_kickback(FactorState* f, int* qubits, int* k, std::vector<double>* m) {
-  if (*k != 2 || !g_unobservable) return false;
+  if (*k != 2 || !g_unobservable || !g_kickback) return false;
   for (int cl = 0; cl < 2; ++cl) {
     cd M[4];
     if (!controlled_block(m->data(), cl, M)) continue;

@@ -170,6 +170,9 @@ extern int g_fuse_ops;
 // conjugate them, so H turns a controlled Z into a controlled X), merging
 // only when a gate does not commute or the run ends (1, default); 0: off.
 extern int g_hold;
+// Process-wide: the kickback shortcut of held gates (fact_kickback; 1,
+// default) or not (0), separately from holding them.
+extern int g_kickback;
 
 // The 32 proposal features of qubit q (threshold p) from the bookkeeping.
 void fact_features(const FactorState* f, int q, double p, float* out);

@@ -191,3 +191,75 @@ def test_kickback_onto_y_eigenstates(qs_lib, dtype):
     assert sorted(len(s) for s in st.subsystems()) == [1] * n
     assert st.shortcut_count() == 2 and st.held_count() == (0, 0)
     st.free()
+
+
+def test_kickback_has_its_own_switch(qs_lib):
+    """factor.kickback = 0 keeps holding on but turns the kickback shortcut
+    off: Bernstein-Vazirani then merges the ancilla with the qubits of the
+    secret, and the ket is still the oracle's."""
+    qs = qs_lib
+    n = 12
+    gates, secret = workloads.phase_kickback_circuit(n, n)
+    want = dense.run_circuit(dense.zero_state(n), n, gates)
+    saved = qs.tune_get("factor.kickback")
+    qs.tune_set("factor.kickback", 0)
+    try:
+        st = _run(qs, n, C128, gates, 1)
+    finally:
+        qs.tune_set("factor.kickback", saved)
+    assert max(len(x) for x in st.subsystems()) == sum(secret) + 1
+    assert_parity(st.amplitudes(), want, C128, "hold on, kickback off")
+    st.free()
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_failed_run_applies_the_held_gates(qs_lib, dtype):
+    """A run that fails (a merge past the cap) with a gate held back leaves
+    the prefix of the circuit before the failing gate, the held gate
+    included; the state stays usable."""
+    qs = qs_lib
+    n = 6
+    prefix = ([("h", q) for q in range(n)] + [("iswap", 0, 1), ("iswap", 1, 2),
+                                               ("cp", 3, 4, 0.7)])
+    gates = prefix + [("iswap", 2, 5), ("h", 0)]
+    saved = qs.tune_get("factor.hold")
+    qs.tune_set("factor.hold", 1)
+    try:
+        st = qs.State(n, dtype, factorized=True, max_amps=2 ** 3)
+        c = qs.Circuit(n).add_gates(gates)
+        with pytest.raises(qs.CapacityError):
+            st.run(c)
+        c.free()
+    finally:
+        qs.tune_set("factor.hold", saved)
+    assert sorted(sorted(s) for s in st.subsystems()) == [[0, 1, 2], [3, 4], [5]]
+    want = dense.run_circuit(dense.zero_state(n), n, prefix)
+    assert_parity(st.amplitudes(), want, dtype, "prefix with the held gate")
+    assert st.fidelity_estimate() == 1.0
+    st.free()
+
+
+def test_failed_run_whose_held_gate_cannot_merge_poisons_the_state(qs_lib):
+    """If a held gate cannot be applied after the failure either (its merge
+    is past the cap too), the state is none of the circuit's: every later call
+    but qs_free is refused."""
+    qs = qs_lib
+    n = 6
+    gates = ([("h", q) for q in range(n)] + [("iswap", 0, 1), ("iswap", 1, 2),
+                                             ("cp", 2, 3, 0.7), ("iswap", 0, 4)])
+    saved = qs.tune_get("factor.hold")
+    qs.tune_set("factor.hold", 1)
+    try:
+        st = qs.State(n, C64, factorized=True, max_amps=2 ** 3)
+        c = qs.Circuit(n).add_gates(gates)
+        with pytest.raises(qs.CapacityError):
+            st.run(c)
+        c.free()
+    finally:
+        qs.tune_set("factor.hold", saved)
+    with pytest.raises(qs.QSError) as e:
+        st.norm()
+    assert e.value.code == -4
+    with pytest.raises(qs.QSError):
+        st.amplitudes()
+    st.free()
