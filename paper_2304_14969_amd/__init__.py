@@ -16,7 +16,9 @@ import weakref
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqs.so")
+# QS_LIB names another build of the library (the sanitized host-code build of
+# the CPU tests); the default is the one next to this file.
+LIB_PATH = os.environ.get("QS_LIB") or os.path.join(HERE, "libqs.so")
 
 C64, C128 = 1, 2
 GATHER_NOALLOC_MAX = 65536  # QS_GATHER_NOALLOC_MAX of qs.h
