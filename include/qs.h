@@ -499,9 +499,14 @@ int qs_check(qs_state* st, double tol);
 
 /* Process-wide knobs of the kernel planners (read by later calls):
  *   "qft.lds_bits"   bits of the contiguous LDS tile of the QFT's low pass:
- *                    12 (default), or up to 13 for complex64 / 12 for
- *                    complex128 (0 = that largest size; larger values are
- *                    clamped to it);
+ *                    1 to 13 for complex64 / 12 for complex128 (larger
+ *                    values are clamped to that); 0 (default): 12, or 11
+ *                    for complex64 states above 256 MiB when that adds no
+ *                    pass;
+ *   "qft.stream"     global accesses of the LDS tile passes: 0 (default)
+ *                    streaming (non-temporal) for states above 256 MiB, plain
+ *                    below (such states partly stay in the last-level
+ *                    cache between passes); 1 always streaming; 2 never;
  *   "qft.high_pass"  passes above that tile: 0 = strided LDS tiles, 1 =
  *                    register passes of up to 5 bits;
  *   "qft.col_max"    most bits of one strided LDS pass: 8 (default; 256-byte

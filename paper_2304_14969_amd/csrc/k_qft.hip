@@ -210,6 +210,35 @@ template <typename R> struct Vec16;
 template <> struct Vec16<float> { using T = float4; static constexpr int AMPS = 2; };
 template <> struct Vec16<double> { using T = double2; static constexpr int AMPS = 1; };
 
+// Streaming 16-byte global accesses: each pass reads and writes every byte
+// once, so both are non-temporal. In whole-state sweeps of the passes' tile
+// shapes this moves 7% more bytes per second than plain accesses (top 8-bit
+// strided tiles 5.15 -> 5.54 TB/s, contiguous 64 KiB tiles 5.43 -> 5.80).
+// Buffer instructions with stores at device or system scope did better still
+// in those sweeps, but not inside the passes (1-3% slower: each access then
+// needs its wave's base address in scalar registers). States that fit the
+// 256 MiB last-level cache keep plain accesses: back-to-back passes find part
+// of the state there, and streaming made the QFT at 22-25 qubits 4-7% slower.
+// The kernels take the choice as a (uniform) argument.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float4 ld_stream(const float4* p) {
+  const f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+  return {t.x, t.y, t.z, t.w};
+}
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+  const f64x2 t = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p));
+  return {t.x, t.y};
+}
+__device__ __forceinline__ void st_stream(float4* p, float4 v) {
+  const f32x4 t = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(t, reinterpret_cast<f32x4*>(p));
+}
+__device__ __forceinline__ void st_stream(double2* p, double2 v) {
+  const f64x2 t = {v.x, v.y};
+  __builtin_nontemporal_store(t, reinterpret_cast<f64x2*>(p));
+}
+
 // LDS position of tile index x; one complex of padding every 16 entries keeps
 // the strided columns of the lowest rounds on distinct banks.
 template <bool PAD>
@@ -278,7 +307,8 @@ __device__ __forceinline__ void tile_rounds(Cx<R>* sm, int TB, int b_lo, int b_h
 // two waves per SIMD (at most 256 VGPRs) keeps both resident.
 template <typename R, int T, bool REV, int NT, int WMAX>
 __global__ void __launch_bounds__(NT, sizeof(R) == 4 ? 2 : 1)
-    k_qft_lds(R* __restrict__ a, int start, int len, int lo, int hi, int sign, R scale) {
+    k_qft_lds(R* __restrict__ a, int start, int len, int lo, int hi, int sign, R scale,
+              int stream) {
   extern __shared__ unsigned char smraw[];
   Cx<R>* sm = reinterpret_cast<Cx<R>*>(smraw);
   using V = typename Vec16<R>::T;
@@ -288,8 +318,13 @@ __global__ void __launch_bounds__(NT, sizeof(R) == 4 ? 2 : 1)
   const uint64_t tile_base = uint64_t(blockIdx.x) << T;
   V* p = reinterpret_cast<V*>(a + 2 * tile_base);
   V buf[NV];
+  if (stream) {
 #pragma unroll
-  for (int k = 0; k < NV; ++k) buf[k] = p[threadIdx.x + k * NT];
+    for (int k = 0; k < NV; ++k) buf[k] = ld_stream(p + threadIdx.x + k * NT);
+  } else {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) buf[k] = p[threadIdx.x + k * NT];
+  }
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     const int x = (threadIdx.x + k * NT) * AP;
@@ -314,15 +349,20 @@ __global__ void __launch_bounds__(NT, sizeof(R) == 4 ? 2 : 1)
       buf[k] = {v0.r * scale, v0.i * scale};
     }
   }
+  if (stream) {
 #pragma unroll
-  for (int k = 0; k < NV; ++k) p[threadIdx.x + k * NT] = buf[k];
+    for (int k = 0; k < NV; ++k) st_stream(p + threadIdx.x + k * NT, buf[k]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) p[threadIdx.x + k * NT] = buf[k];
+  }
 }
 
 // Strided tile: 2^G rows (global bits [lo, lo+G)) x 2^C contiguous columns
 // (global bits [0, C)), C <= lo. Tile index = row * 2^C + column.
 template <typename R, int G, int C, bool REV, int NT, int WMAX>
 __global__ void __launch_bounds__(NT) k_qft_col(R* __restrict__ a, int start, int len, int lo,
-                                                int sign, R scale) {
+                                                int sign, R scale, int stream) {
   extern __shared__ unsigned char smraw[];
   Cx<R>* sm = reinterpret_cast<Cx<R>*>(smraw);
   using V = typename Vec16<R>::T;
@@ -340,10 +380,18 @@ __global__ void __launch_bounds__(NT) k_qft_col(R* __restrict__ a, int start, in
   };
   V* p = reinterpret_cast<V*>(a);
   V buf[NV];
+  if (stream) {
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    const int e = threadIdx.x + k * NT;
-    buf[k] = p[glob((e / VPR) << C | (e % VPR) * AP) / AP];
+    for (int k = 0; k < NV; ++k) {
+      const int e = threadIdx.x + k * NT;
+      buf[k] = ld_stream(p + glob((e / VPR) << C | (e % VPR) * AP) / AP);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int e = threadIdx.x + k * NT;
+      buf[k] = p[glob((e / VPR) << C | (e % VPR) * AP) / AP];
+    }
   }
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
@@ -370,10 +418,18 @@ __global__ void __launch_bounds__(NT) k_qft_col(R* __restrict__ a, int start, in
       buf[k] = {v0.r * scale, v0.i * scale};
     }
   }
+  if (stream) {
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    const int e = threadIdx.x + k * NT;
-    p[glob((e / VPR) << C | (e % VPR) * AP) / AP] = buf[k];
+    for (int k = 0; k < NV; ++k) {
+      const int e = threadIdx.x + k * NT;
+      st_stream(p + glob((e / VPR) << C | (e % VPR) * AP) / AP, buf[k]);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int e = threadIdx.x + k * NT;
+      p[glob((e / VPR) << C | (e % VPR) * AP) / AP] = buf[k];
+    }
   }
 }
 
@@ -415,9 +471,18 @@ hipError_t launch_reg(R* a, int n, int start, int len, int lo, int sign, R scale
   return hipGetLastError();
 }
 
+// Streaming accesses (qft.stream: 0 when the state exceeds the last-level
+// cache, 1 always, 2 never).
+template <typename R>
+int stream_policy(int n, const QftTuning& tune) {
+  if (tune.stream == 1) return 1;
+  if (tune.stream == 2) return 0;
+  return (uint64_t(2 * sizeof(R)) << n) > (uint64_t(256) << 20) ? 1 : 0;
+}
+
 template <typename R, int G, int C, bool REV, int CAP, int WMAX>
 hipError_t launch_col_cfg(R* a, int n, int start, int len, int lo, int sign, R scale,
-                          hipStream_t s) {
+                          int stream, hipStream_t s) {
   if (lo < C || n < lo + G) return hipErrorInvalidValue;
   constexpr int NT =
       tile_threads(G + C, (1 << (G + C)) / Vec16<R>::AMPS, round_width(G, WMAX), CAP);
@@ -425,20 +490,21 @@ hipError_t launch_col_cfg(R* a, int n, int start, int len, int lo, int sign, R s
   auto kern = k_qft_col<R, G, C, REV, NT, WMAX>;
   allow_lds(kern, bytes);
   const unsigned grid = static_cast<unsigned>(uint64_t(1) << (n - G - C));
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), bytes, s, a, start, len, lo, sign, scale);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), bytes, s, a, start, len, lo, sign, scale, stream);
   return hipGetLastError();
 }
 
 template <typename R, int T, bool REV, int CAP, int WMAX>
 hipError_t launch_lds_cfg(R* a, int n, int start, int len, int lo, int hi, int sign, R scale,
-                          hipStream_t s) {
+                          int stream, hipStream_t s) {
   constexpr int VEC = (1 << T) / Vec16<R>::AMPS > 0 ? (1 << T) / Vec16<R>::AMPS : 1;
   constexpr int NT = tile_threads(T, VEC, round_width(T, WMAX), CAP);
   const size_t bytes = size_t((1 << T) + ((1 << T) >> 4)) * 2 * sizeof(R);
   auto kern = k_qft_lds<R, T, REV, NT, WMAX>;
   allow_lds(kern, bytes);
   const unsigned grid = static_cast<unsigned>(uint64_t(1) << (n - T));
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), bytes, s, a, start, len, lo, hi, sign, scale);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), bytes, s, a, start, len, lo, hi, sign, scale,
+                     stream);
   return hipGetLastError();
 }
 
@@ -450,13 +516,14 @@ hipError_t launch_col_c(R* a, int n, int start, int len, int lo, int sign, R sca
                         const QftTuning& tune, hipStream_t s) {
   // thread cap: the knob, or (0) 512 for passes of 8 bits and 256 otherwise
   const int cap = tune.threads > 0 ? tune.threads : (G == 8 ? 512 : 256);
+  const int st = stream_policy<R>(n, tune);
   if (G < 5 || (cap < 512 && tune.round_bits < 5))
-    return launch_col_cfg<R, G, C, REV, 256, 4>(a, n, start, len, lo, sign, scale, s);
+    return launch_col_cfg<R, G, C, REV, 256, 4>(a, n, start, len, lo, sign, scale, st, s);
   if (cap >= 512 && tune.round_bits >= 5)
-    return launch_col_cfg<R, G, C, REV, 512, 5>(a, n, start, len, lo, sign, scale, s);
+    return launch_col_cfg<R, G, C, REV, 512, 5>(a, n, start, len, lo, sign, scale, st, s);
   if (cap >= 512)
-    return launch_col_cfg<R, G, C, REV, 512, 4>(a, n, start, len, lo, sign, scale, s);
-  return launch_col_cfg<R, G, C, REV, 256, 5>(a, n, start, len, lo, sign, scale, s);
+    return launch_col_cfg<R, G, C, REV, 512, 4>(a, n, start, len, lo, sign, scale, st, s);
+  return launch_col_cfg<R, G, C, REV, 256, 5>(a, n, start, len, lo, sign, scale, st, s);
 }
 
 // Strided tiles of 2^G rows x 2^C columns: 512-byte rows (64 KiB at G = 7),
@@ -485,13 +552,14 @@ hipError_t launch_lds_t(R* a, int n, int start, int len, int lo, int hi, int sig
   // complex128 stays at rounds of 4 bits: 32 double-precision amplitudes per
   // thread would leave one wave per SIMD
   const int cap = tune.threads > 0 ? tune.threads : 256;
+  const int st = stream_policy<R>(n, tune);
   if (T < 11 || sizeof(R) == 8 || (cap < 512 && tune.round_bits < 5))
-    return launch_lds_cfg<R, T, REV, 256, 4>(a, n, start, len, lo, hi, sign, scale, s);
+    return launch_lds_cfg<R, T, REV, 256, 4>(a, n, start, len, lo, hi, sign, scale, st, s);
   if (cap >= 512 && tune.round_bits >= 5)
-    return launch_lds_cfg<R, T, REV, 512, 5>(a, n, start, len, lo, hi, sign, scale, s);
+    return launch_lds_cfg<R, T, REV, 512, 5>(a, n, start, len, lo, hi, sign, scale, st, s);
   if (cap >= 512)
-    return launch_lds_cfg<R, T, REV, 512, 4>(a, n, start, len, lo, hi, sign, scale, s);
-  return launch_lds_cfg<R, T, REV, 256, 5>(a, n, start, len, lo, hi, sign, scale, s);
+    return launch_lds_cfg<R, T, REV, 512, 4>(a, n, start, len, lo, hi, sign, scale, st, s);
+  return launch_lds_cfg<R, T, REV, 256, 5>(a, n, start, len, lo, hi, sign, scale, st, s);
 }
 
 template <typename R, bool REV>
@@ -567,12 +635,24 @@ template hipError_t launch_qft_pass<double>(double*, int, int, int, const QftPas
 template <typename R>
 int qft_plan(int n, int start, int len, bool rev, const QftTuning& tune, QftPass* out,
              int max_passes) {
-  int T = tune.lds_bits > 0 ? tune.lds_bits : lds_bits<R>();
-  if (T > lds_bits<R>()) T = lds_bits<R>();
-  if (T > n) T = n;
   const bool use_reg = tune.high_kind == 1;
   const int wmax = use_reg ? kRegMax : (tune.col_max == 8 ? kColMax8 : kColMax);
   const int top = start + len;
+  // passes of the plan with a contiguous tile of t bits
+  auto pass_count = [&](int t) {
+    int lo = start > t ? start : t;
+    if (!use_reg && lo < col_bits<R>()) lo = col_bits<R>();
+    return (top > lo ? (top - lo + wmax - 1) / wmax : 0) + (start < lo ? 1 : 0);
+  };
+  // contiguous tile bits: the knob, or (0) 12; complex64 states larger than
+  // the last-level cache take 11 when that adds no pass (the 11-bit tile runs
+  // more workgroups per CU: 6.2 against 5.8 TB/s at 27 qubits)
+  int T = tune.lds_bits > 0 ? tune.lds_bits : 12;
+  if (T > lds_bits<R>()) T = lds_bits<R>();
+  if (tune.lds_bits == 0 && sizeof(R) == 4 && (uint64_t(8) << n) > (uint64_t(256) << 20) &&
+      pass_count(11) <= pass_count(12))
+    T = 11;
+  if (T > n) T = n;
   int reg_lo = start > T ? start : T;
   if (!use_reg && reg_lo < col_bits<R>()) reg_lo = col_bits<R>();
   int np = 0;

@@ -291,13 +291,15 @@ struct QftPass {
 
 // Process-wide tuning knobs of the pass planner.
 struct QftTuning {
-  int lds_bits = 12;  // contiguous tile bits (0: the largest per precision, 13 / 12)
+  int lds_bits = 0;   // contiguous tile bits (0: by size, 12 or 11; at most 13 / 12)
   int high_kind = 0;  // passes above the tile: 0 strided LDS tiles, 1 registers
   int threads = 0;    // thread cap of the LDS tile launches: 256, 512, or 0 = by pass width
   int round_bits = 4; // widest register round inside an LDS tile (4 or 5)
   int col_max = 8;    // most bits of a strided LDS pass: 7 (512-byte rows) or 8 (256-byte)
   int col_rows = 0;   // 1: 7-bit strided passes with 256-byte rows (32 KiB tiles);
                       // 2: also 8-bit ones with 128-byte rows (complex64)
+  int stream = 0;     // streaming (non-temporal) accesses of the LDS tile passes:
+                      // 0 when the state exceeds the last-level cache, 1 always, 2 never
 };
 
 // `rev` = the range is stored bit-reversed (after an earlier transform's

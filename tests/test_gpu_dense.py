@@ -260,7 +260,7 @@ def test_error_codes(qs_lib):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("high_pass,lds_bits", [(0, 0), (1, 0), (0, 9), (1, 10), (0, 12), (0, 7),
+@pytest.mark.parametrize("high_pass,lds_bits", [(0, 0), (1, 13), (0, 9), (1, 10), (0, 12), (0, 7),
                                                (0, 13)])
 def test_qft_pass_variants(qs_lib, dtype, high_pass, lds_bits):
     """Every planner variant (LDS tile size, strided-LDS or register passes
@@ -289,7 +289,7 @@ def test_qft_pass_variants(qs_lib, dtype, high_pass, lds_bits):
 
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("n,lds_bits,col_rows", [(19, 11, 0), (20, 12, 1), (22, 11, 1), (20, 12, 2),
-                                                 (21, 0, 1)])
+                                                 (21, 13, 1)])
 def test_qft_eight_bit_strided_passes(qs_lib, dtype, n, lds_bits, col_rows):
     """Strided passes of 8 row bits (256-byte rows) above a smaller contiguous
     tile: sampled outputs against the oracle's DFT entries (Eq. dft), then
@@ -317,3 +317,35 @@ def test_qft_eight_bit_strided_passes(qs_lib, dtype, n, lds_bits, col_rows):
         for k, v in saved.items():
             qs.tune_set(k, v)
 
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,lds_bits", [(17, 0), (19, 11), (20, 12), (21, 13), (22, 10)])
+def test_qft_streaming_accesses(qs_lib, dtype, n, lds_bits):
+    """qft.stream = 1: the LDS tile passes with non-temporal loads and stores
+    (by default only for states above 256 MiB) against the oracle, forward in
+    both storage orientations and the inverse; every result bit for bit equal
+    to the plain accesses' (qft.stream = 2)."""
+    qs = qs_lib
+    a = workloads.gaussian_state(n, 1700 + n)
+    saved = {k: qs.tune_get(k) for k in ("qft.stream", "qft.lds_bits")}
+    qs.tune_set("qft.lds_bits", lds_bits)
+    try:
+        runs = {}
+        for stream in (1, 2):
+            qs.tune_set("qft.stream", stream)
+            with fresh(qs, n, dtype, a) as st:
+                out = []
+                for inv in (False, False, True, True):
+                    st.qft(inverse=inv)
+                    out.append(st.amplitudes(np.complex64 if dtype == C64 else np.complex128))
+            runs[stream] = out
+        for k in range(4):
+            assert np.array_equal(runs[1][k], runs[2][k]), f"step {k}"
+        want = dense.qft(a, n)
+        assert_parity(runs[1][0], want, dtype, f"stream n={n} T={lds_bits}")
+        assert_parity(runs[1][1], dense.qft(want, n), dtype, "second transform")
+        assert_parity(runs[1][3], a, dtype, "roundtrip")
+    finally:
+        for k, v in saved.items():
+            qs.tune_set(k, v)
