@@ -507,6 +507,13 @@ int qs_check(qs_state* st, double tol);
  *                    streaming (non-temporal) for states above 256 MiB, plain
  *                    below (such states partly stay in the last-level
  *                    cache between passes); 1 always streaming; 2 never;
+ *   "sweep.stream"   global accesses of the gate sweeps, fused blocks and
+ *                    tile passes: 0 (default) streaming (non-temporal) for
+ *                    states above 256 MiB when every wave access covers
+ *                    contiguous runs of at least 64 bytes (the lowest bit
+ *                    the sweep fixes is high enough), plain otherwise; 1
+ *                    always streaming; 2 never. Results are the same either
+ *                    way, bit for bit;
  *   "qft.high_pass"  passes above that tile: 0 = strided LDS tiles, 1 =
  *                    register passes of up to 5 bits;
  *   "qft.col_max"    most bits of one strided LDS pass: 8 (default; 256-byte

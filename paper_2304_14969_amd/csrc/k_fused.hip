@@ -28,7 +28,7 @@ struct Block6 {
   int sorted[6];  // the same bits ascending
 };
 
-template <typename R, int K>
+template <typename R, int K, bool NT>
 __global__ void __launch_bounds__(kBlock) k_fused_vec(R* __restrict__ a, uint64_t groups, Block6 b,
                                                       const R* __restrict__ mat) {
   constexpr int D = 1 << K;
@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(kBlock) k_fused_vec(R* __restrict__ a, uint64_
 #pragma unroll
       for (int j = 0; j < K; ++j) o |= uint64_t((c >> j) & 1) << b.q[j];
       off[c] = base | o;
-      v[c] = {a[2 * off[c]], a[2 * off[c] + 1]};
+      ld_amp<NT>(a + 2 * off[c], &v[c].r, &v[c].i);
     }
 #pragma unroll
     for (int r = 0; r < D; ++r) {
@@ -56,11 +56,10 @@ __global__ void __launch_bounds__(kBlock) k_fused_vec(R* __restrict__ a, uint64_
 #pragma unroll
       for (int c = 0; c < D; ++c) {
         const Cx<R> m = M[r * D + c];
-        yr += m.r * v[c].r - m.i * v[c].i;
-        yi += m.r * v[c].i + m.i * v[c].r;
+        yr = fmadd(m.r, v[c].r, fmadd(-m.i, v[c].i, yr));
+        yi = fmadd(m.r, v[c].i, fmadd(m.i, v[c].r, yi));
       }
-      a[2 * off[r]] = yr;
-      a[2 * off[r] + 1] = yi;
+      st_amp<NT>(a + 2 * off[r], yr, yi);
     }
   }
 }
@@ -72,7 +71,7 @@ struct MatArg {
   R v[2 << (2 * K)];
 };
 
-template <typename R, int K>
+template <typename R, int K, bool NT>
 __global__ void __launch_bounds__(kBlock) k_fused_arg(R* __restrict__ a, uint64_t groups, Block6 b,
                                                       MatArg<R, K> mat) {
   constexpr int D = 1 << K;
@@ -89,7 +88,7 @@ __global__ void __launch_bounds__(kBlock) k_fused_arg(R* __restrict__ a, uint64_
 #pragma unroll
       for (int j = 0; j < K; ++j) o |= uint64_t((c >> j) & 1) << b.q[j];
       off[c] = base | o;
-      v[c] = {a[2 * off[c]], a[2 * off[c] + 1]};
+      ld_amp<NT>(a + 2 * off[c], &v[c].r, &v[c].i);
     }
 #pragma unroll
     for (int r = 0; r < D; ++r) {
@@ -97,11 +96,10 @@ __global__ void __launch_bounds__(kBlock) k_fused_arg(R* __restrict__ a, uint64_
 #pragma unroll
       for (int c = 0; c < D; ++c) {
         const R mr = mat.v[2 * (r * D + c)], mi = mat.v[2 * (r * D + c) + 1];
-        yr += mr * v[c].r - mi * v[c].i;
-        yi += mr * v[c].i + mi * v[c].r;
+        yr = fmadd(mr, v[c].r, fmadd(-mi, v[c].i, yr));
+        yi = fmadd(mr, v[c].i, fmadd(mi, v[c].r, yi));
       }
-      a[2 * off[r]] = yr;
-      a[2 * off[r] + 1] = yi;
+      st_amp<NT>(a + 2 * off[r], yr, yi);
     }
   }
 }
@@ -129,8 +127,12 @@ hipError_t launch_arg(R* a, int n, const Block6& b, const double* m, hipStream_t
   MatArg<R, K> mat;
   for (int i = 0; i < (2 << (2 * K)); ++i) mat.v[i] = static_cast<R>(m[i]);
   const uint64_t groups = uint64_t(1) << (n - K);
-  hipLaunchKernelGGL((k_fused_arg<R, K>), dim3(fused_grid(groups)), dim3(kBlock), 0, s, a, groups,
-                     b, mat);
+  if (stream_sweep(n, 2 * sizeof(R), b.sorted[0]))
+    hipLaunchKernelGGL((k_fused_arg<R, K, true>), dim3(fused_grid(groups)), dim3(kBlock), 0, s, a,
+                       groups, b, mat);
+  else
+    hipLaunchKernelGGL((k_fused_arg<R, K, false>), dim3(fused_grid(groups)), dim3(kBlock), 0, s, a,
+                       groups, b, mat);
   return hipGetLastError();
 }
 
@@ -139,7 +141,12 @@ hipError_t launch_k(R* a, int n, const Block6& b, const R* mat, hipStream_t s) {
   const uint64_t groups = uint64_t(1) << (n - K);
   const uint64_t want = (groups + kBlock - 1) / kBlock, cap = uint64_t(1) << 20;
   const unsigned grid = static_cast<unsigned>(want < cap ? want : cap);
-  hipLaunchKernelGGL((k_fused_vec<R, K>), dim3(grid), dim3(kBlock), 0, s, a, groups, b, mat);
+  if (stream_sweep(n, 2 * sizeof(R), b.sorted[0]))
+    hipLaunchKernelGGL((k_fused_vec<R, K, true>), dim3(grid), dim3(kBlock), 0, s, a, groups, b,
+                       mat);
+  else
+    hipLaunchKernelGGL((k_fused_vec<R, K, false>), dim3(grid), dim3(kBlock), 0, s, a, groups, b,
+                       mat);
   return hipGetLastError();
 }
 

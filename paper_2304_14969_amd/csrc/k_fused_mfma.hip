@@ -37,7 +37,7 @@ __device__ __forceinline__ int insert_zero32(int x, int pos) {
   return lo | ((x ^ lo) << 1);
 }
 
-template <int K>
+template <int K, bool NT>
 __global__ void __launch_bounds__(kThreads) k_fused_mfma(float* __restrict__ a, FusedGeom g,
                                                          const float* __restrict__ mat) {
   constexpr int D = 1 << K;           // block dimension
@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(kThreads) k_fused_mfma(float* __restrict__ a, 
   for (int v = 0; v < NV; ++v) {
     const int e = threadIdx.x + v * kThreads;
     const int t = ((e >> vrow) << C) | ((e & ((1 << vrow) - 1)) << 1);
-    buf[v] = *reinterpret_cast<const float4*>(a + 2 * glob(t));
+    buf[v] = ld16<NT>(reinterpret_cast<const float4*>(a + 2 * glob(t)));
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(kThreads) k_fused_mfma(float* __restrict__ a, 
     const int e = threadIdx.x + v * kThreads;
     const int t = ((e >> vrow) << C) | ((e & ((1 << vrow) - 1)) << 1);
     const float2 x0 = sm[t], x1 = sm[t + 1];
-    *reinterpret_cast<float4*>(a + 2 * glob(t)) = make_float4(x0.x, x0.y, x1.x, x1.y);
+    st16<NT>(reinterpret_cast<float4*>(a + 2 * glob(t)), make_float4(x0.x, x0.y, x1.x, x1.y));
   }
 }
 
@@ -180,10 +180,10 @@ hipError_t launch_fused_mfma(float* a, int n, const int* qubits, int k, const fl
   if ((k != 4 && k != 5) || !fused_geometry(n, qubits, k, &g)) return hipErrorNotSupported;
   const uint64_t tiles = uint64_t(1) << (n - g.C - g.h);
   if (tiles > 0x7fffffffu) return hipErrorNotSupported;
-  if (k == 4)
-    hipLaunchKernelGGL(k_fused_mfma<4>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, a, g, mat);
-  else
-    hipLaunchKernelGGL(k_fused_mfma<5>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, a, g, mat);
+  const bool nt = stream_sweep(n, 8, g.C);  // rows of 2^C contiguous amplitudes
+  auto kern = k == 4 ? (nt ? k_fused_mfma<4, true> : k_fused_mfma<4, false>)
+                     : (nt ? k_fused_mfma<5, true> : k_fused_mfma<5, false>);
+  hipLaunchKernelGGL(kern, dim3(unsigned(tiles)), dim3(kThreads), 0, s, a, g, mat);
   return hipGetLastError();
 }
 

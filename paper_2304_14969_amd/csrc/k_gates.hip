@@ -28,12 +28,13 @@ __device__ __forceinline__ uint64_t insert_zeros(uint64_t x, const BitSet16& b) 
   return x;
 }
 
+// y = m x on one amplitude pair, as a fixed chain of fused multiply-adds
 template <typename R>
 __device__ __forceinline__ void mat2_apply(const Mat2<R>& m, R& x0r, R& x0i, R& x1r, R& x1i) {
-  const R y0r = m.re[0] * x0r - m.im[0] * x0i + m.re[1] * x1r - m.im[1] * x1i;
-  const R y0i = m.re[0] * x0i + m.im[0] * x0r + m.re[1] * x1i + m.im[1] * x1r;
-  const R y1r = m.re[2] * x0r - m.im[2] * x0i + m.re[3] * x1r - m.im[3] * x1i;
-  const R y1i = m.re[2] * x0i + m.im[2] * x0r + m.re[3] * x1i + m.im[3] * x1r;
+  const R y0r = fmadd(m.re[0], x0r, fmadd(-m.im[0], x0i, fmadd(m.re[1], x1r, -m.im[1] * x1i)));
+  const R y0i = fmadd(m.re[0], x0i, fmadd(m.im[0], x0r, fmadd(m.re[1], x1i, m.im[1] * x1r)));
+  const R y1r = fmadd(m.re[2], x0r, fmadd(-m.im[2], x0i, fmadd(m.re[3], x1r, -m.im[3] * x1i)));
+  const R y1i = fmadd(m.re[2], x0i, fmadd(m.im[2], x0r, fmadd(m.re[3], x1i, m.im[3] * x1r)));
   x0r = y0r; x0i = y0i; x1r = y1r; x1i = y1i;
 }
 
@@ -48,48 +49,51 @@ inline unsigned grid_for(uint64_t units) {
 
 // ------------------------------------------------------------------ 1q
 // c64, target bit t >= 1: a unit is two adjacent pairs (i, i+1) x (bit t).
+template <bool NT>
 __global__ void __launch_bounds__(kBlock) k_1q_f_vec(float* __restrict__ a, uint64_t units,
                                                      int t, Mat2<float> m) {
   QS_STRIDE_LOOP(u, units) {
     const uint64_t i0 = insert_zero(u << 1, t);
     float4* p0 = reinterpret_cast<float4*>(a + 2 * i0);
     float4* p1 = reinterpret_cast<float4*>(a + 2 * (i0 + (uint64_t(1) << t)));
-    float4 x = *p0, y = *p1;
+    float4 x = ld16<NT>(p0), y = ld16<NT>(p1);
     mat2_apply(m, x.x, x.y, y.x, y.y);
     mat2_apply(m, x.z, x.w, y.z, y.w);
-    *p0 = x;
-    *p1 = y;
+    st16<NT>(p0, x);
+    st16<NT>(p1, y);
   }
 }
 
 // c64, target bit 0: both amplitudes of a pair are in one 16-byte vector.
+template <bool NT>
 __global__ void __launch_bounds__(kBlock) k_1q_f_bit0(float* __restrict__ a, uint64_t units,
                                                       Mat2<float> m) {
   QS_STRIDE_LOOP(u, units) {
     float4* p = reinterpret_cast<float4*>(a + 4 * u);
-    float4 x = *p;
+    float4 x = ld16<NT>(p);
     mat2_apply(m, x.x, x.y, x.z, x.w);
-    *p = x;
+    st16<NT>(p, x);
   }
 }
 
 // c128: a unit is one pair.
+template <bool NT>
 __global__ void __launch_bounds__(kBlock) k_1q_d(double* __restrict__ a, uint64_t units, int t,
                                                  Mat2<double> m) {
   QS_STRIDE_LOOP(u, units) {
     const uint64_t i0 = insert_zero(u, t);
     double2* p0 = reinterpret_cast<double2*>(a + 2 * i0);
     double2* p1 = reinterpret_cast<double2*>(a + 2 * (i0 + (uint64_t(1) << t)));
-    double2 x = *p0, y = *p1;
+    double2 x = ld16<NT>(p0), y = ld16<NT>(p1);
     mat2_apply(m, x.x, x.y, y.x, y.y);
-    *p0 = x;
-    *p1 = y;
+    st16<NT>(p0, x);
+    st16<NT>(p1, y);
   }
 }
 
 // ------------------------------------------------------------------ controlled
 // Vector path (no fixed bit below the vector width): one unit = Vec16 amps.
-template <typename R>
+template <typename R, bool NT>
 __global__ void __launch_bounds__(kBlock) k_ctrl_vec(R* __restrict__ a, uint64_t units,
                                                      BitSet16 fixed, uint64_t set_mask, int tbit,
                                                      Mat2<R> m) {
@@ -99,35 +103,37 @@ __global__ void __launch_bounds__(kBlock) k_ctrl_vec(R* __restrict__ a, uint64_t
     const uint64_t i0 = insert_zeros(u * AP, fixed) | set_mask;
     V* p0 = reinterpret_cast<V*>(a + 2 * i0);
     V* p1 = reinterpret_cast<V*>(a + 2 * (i0 | (uint64_t(1) << tbit)));
-    V x = *p0, y = *p1;
+    V x = ld16<NT>(p0), y = ld16<NT>(p1);
     if constexpr (AP == 2) {
       mat2_apply(m, x.x, x.y, y.x, y.y);
       mat2_apply(m, x.z, x.w, y.z, y.w);
     } else {
       mat2_apply(m, x.x, x.y, y.x, y.y);
     }
-    *p0 = x;
-    *p1 = y;
+    st16<NT>(p0, x);
+    st16<NT>(p1, y);
   }
 }
 
 // Scalar path (a fixed bit is bit 0): one pair per thread.
-template <typename R>
+template <typename R, bool NT>
 __global__ void __launch_bounds__(kBlock) k_ctrl_scalar(R* __restrict__ a, uint64_t units,
                                                         BitSet16 fixed, uint64_t set_mask,
                                                         int tbit, Mat2<R> m) {
   QS_STRIDE_LOOP(u, units) {
     const uint64_t i0 = insert_zeros(u, fixed) | set_mask;
     const uint64_t i1 = i0 | (uint64_t(1) << tbit);
-    R x0r = a[2 * i0], x0i = a[2 * i0 + 1], x1r = a[2 * i1], x1i = a[2 * i1 + 1];
+    R x0r, x0i, x1r, x1i;
+    ld_amp<NT>(a + 2 * i0, &x0r, &x0i);
+    ld_amp<NT>(a + 2 * i1, &x1r, &x1i);
     mat2_apply(m, x0r, x0i, x1r, x1i);
-    a[2 * i0] = x0r; a[2 * i0 + 1] = x0i;
-    a[2 * i1] = x1r; a[2 * i1 + 1] = x1i;
+    st_amp<NT>(a + 2 * i0, x0r, x0i);
+    st_amp<NT>(a + 2 * i1, x1r, x1i);
   }
 }
 
 // ------------------------------------------------------------------ phase
-template <typename R>
+template <typename R, bool NT>
 __global__ void __launch_bounds__(kBlock) k_cphase_vec(R* __restrict__ a, uint64_t units,
                                                        BitSet16 fixed, uint64_t set_mask, R cr,
                                                        R ci) {
@@ -136,29 +142,29 @@ __global__ void __launch_bounds__(kBlock) k_cphase_vec(R* __restrict__ a, uint64
   QS_STRIDE_LOOP(u, units) {
     const uint64_t i = insert_zeros(u * AP, fixed) | set_mask;
     V* p = reinterpret_cast<V*>(a + 2 * i);
-    V x = *p;
+    V x = ld16<NT>(p);
     R t;
-    t = x.x * cr - x.y * ci; x.y = x.x * ci + x.y * cr; x.x = t;
-    if constexpr (AP == 2) { t = x.z * cr - x.w * ci; x.w = x.z * ci + x.w * cr; x.z = t; }
-    *p = x;
+    t = fmadd(x.x, cr, -x.y * ci); x.y = fmadd(x.x, ci, x.y * cr); x.x = t;
+    if constexpr (AP == 2) { t = fmadd(x.z, cr, -x.w * ci); x.w = fmadd(x.z, ci, x.w * cr); x.z = t; }
+    st16<NT>(p, x);
   }
 }
 
-template <typename R>
+template <typename R, bool NT>
 __global__ void __launch_bounds__(kBlock) k_cphase_scalar(R* __restrict__ a, uint64_t units,
                                                           BitSet16 fixed, uint64_t set_mask,
                                                           R cr, R ci) {
   QS_STRIDE_LOOP(u, units) {
     const uint64_t i = insert_zeros(u, fixed) | set_mask;
-    const R xr = a[2 * i], xi = a[2 * i + 1];
-    a[2 * i] = xr * cr - xi * ci;
-    a[2 * i + 1] = xr * ci + xi * cr;
+    R xr, xi;
+    ld_amp<NT>(a + 2 * i, &xr, &xi);
+    st_amp<NT>(a + 2 * i, fmadd(xr, cr, -xi * ci), fmadd(xr, ci, xi * cr));
   }
 }
 
 // ------------------------------------------------------------------ bit swap
 // Exchange the amplitudes at base|2^lo and base|2^hi (bits lo < hi).
-template <typename R>
+template <typename R, bool NT>
 __global__ void __launch_bounds__(kBlock) k_bitswap_vec(R* __restrict__ a, uint64_t units,
                                                         BitSet16 fixed, int lo, int hi) {
   using V = typename Vec16<R>::T;
@@ -167,23 +173,23 @@ __global__ void __launch_bounds__(kBlock) k_bitswap_vec(R* __restrict__ a, uint6
     const uint64_t b = insert_zeros(u * AP, fixed);
     V* p0 = reinterpret_cast<V*>(a + 2 * (b | (uint64_t(1) << lo)));
     V* p1 = reinterpret_cast<V*>(a + 2 * (b | (uint64_t(1) << hi)));
-    const V x = *p0, y = *p1;
-    *p0 = y;
-    *p1 = x;
+    const V x = ld16<NT>(p0), y = ld16<NT>(p1);
+    st16<NT>(p0, y);
+    st16<NT>(p1, x);
   }
 }
 
-template <typename R>
+template <typename R, bool NT>
 __global__ void __launch_bounds__(kBlock) k_bitswap_scalar(R* __restrict__ a, uint64_t units,
                                                            BitSet16 fixed, int lo, int hi) {
   QS_STRIDE_LOOP(u, units) {
     const uint64_t b = insert_zeros(u, fixed);
     const uint64_t i0 = b | (uint64_t(1) << lo), i1 = b | (uint64_t(1) << hi);
-    const R xr = a[2 * i0], xi = a[2 * i0 + 1];
-    a[2 * i0] = a[2 * i1];
-    a[2 * i0 + 1] = a[2 * i1 + 1];
-    a[2 * i1] = xr;
-    a[2 * i1 + 1] = xi;
+    R xr, xi, yr, yi;
+    ld_amp<NT>(a + 2 * i0, &xr, &xi);
+    ld_amp<NT>(a + 2 * i1, &yr, &yi);
+    st_amp<NT>(a + 2 * i0, yr, yi);
+    st_amp<NT>(a + 2 * i1, xr, xi);
   }
 }
 
@@ -232,15 +238,32 @@ constexpr int log_amps() { return Vec16<R>::AMPS == 2 ? 1 : 0; }
 
 }  // namespace
 
+// sweep.stream: 0 streaming accesses for states above the last-level cache,
+// 1 always, 2 never
+int g_sweep_stream = 0;
+
 // ------------------------------------------------------------------ launchers
+namespace {
+// Every sweep streams its state when stream_sweep says so (states above the
+// last-level cache): kt is the streaming instantiation, kf the plain one.
+template <typename KT, typename KF, typename... Args>
+void launch_nt(bool nt, KT kt, KF kf, unsigned grid, hipStream_t s, Args... args) {
+  if (nt)
+    hipLaunchKernelGGL(kt, dim3(grid), dim3(kBlock), 0, s, args...);
+  else
+    hipLaunchKernelGGL(kf, dim3(grid), dim3(kBlock), 0, s, args...);
+}
+}  // namespace
+
 template <>
 hipError_t launch_apply_1q<float>(float* a, int n, int t, const Mat2<float>& m, hipStream_t s) {
+  const bool nt = stream_sweep(n, 8, t == 0 ? 6 : t);
   if (t == 0) {
     const uint64_t units = uint64_t(1) << (n - 1);
-    hipLaunchKernelGGL(k_1q_f_bit0, dim3(grid_for(units)), dim3(kBlock), 0, s, a, units, m);
+    launch_nt(nt, k_1q_f_bit0<true>, k_1q_f_bit0<false>, grid_for(units), s, a, units, m);
   } else {
     const uint64_t units = uint64_t(1) << (n - 2);
-    hipLaunchKernelGGL(k_1q_f_vec, dim3(grid_for(units)), dim3(kBlock), 0, s, a, units, t, m);
+    launch_nt(nt, k_1q_f_vec<true>, k_1q_f_vec<false>, grid_for(units), s, a, units, t, m);
   }
   return hipGetLastError();
 }
@@ -249,7 +272,8 @@ template <>
 hipError_t launch_apply_1q<double>(double* a, int n, int t, const Mat2<double>& m,
                                    hipStream_t s) {
   const uint64_t units = uint64_t(1) << (n - 1);
-  hipLaunchKernelGGL(k_1q_d, dim3(grid_for(units)), dim3(kBlock), 0, s, a, units, t, m);
+  launch_nt(stream_sweep(n, 16, t), k_1q_d<true>, k_1q_d<false>, grid_for(units), s, a, units,
+            t, m);
   return hipGetLastError();
 }
 
@@ -257,14 +281,15 @@ template <typename R>
 hipError_t launch_apply_ctrl(R* a, int n, const BitSet16& fixed, uint64_t set_mask, int tbit,
                              const Mat2<R>& m, hipStream_t s) {
   const int free_bits = n - fixed.n;
+  const bool nt = stream_sweep(n, 2 * sizeof(R), fixed.pos[0]);
   if (fixed.pos[0] >= log_amps<R>() && free_bits >= log_amps<R>()) {
     const uint64_t units = (uint64_t(1) << free_bits) / Vec16<R>::AMPS;
-    hipLaunchKernelGGL(k_ctrl_vec<R>, dim3(grid_for(units)), dim3(kBlock), 0, s, a, units, fixed,
-                       set_mask, tbit, m);
+    launch_nt(nt, k_ctrl_vec<R, true>, k_ctrl_vec<R, false>, grid_for(units), s,
+              a, units, fixed, set_mask, tbit, m);
   } else {
     const uint64_t units = uint64_t(1) << free_bits;
-    hipLaunchKernelGGL(k_ctrl_scalar<R>, dim3(grid_for(units)), dim3(kBlock), 0, s, a, units,
-                       fixed, set_mask, tbit, m);
+    launch_nt(nt, k_ctrl_scalar<R, true>, k_ctrl_scalar<R, false>, grid_for(units), s,
+              a, units, fixed, set_mask, tbit, m);
   }
   return hipGetLastError();
 }
@@ -274,14 +299,15 @@ hipError_t launch_cphase(R* a, int n, int qa, int qb, R cr, R ci, hipStream_t s)
   const BitSet16 fixed = sorted_bits({qa, qb});
   const uint64_t set_mask = (uint64_t(1) << qa) | (uint64_t(1) << qb);
   const int free_bits = n - 2;
+  const bool nt = stream_sweep(n, 2 * sizeof(R), fixed.pos[0]);
   if (fixed.pos[0] >= log_amps<R>() && free_bits >= log_amps<R>()) {
     const uint64_t units = (uint64_t(1) << free_bits) / Vec16<R>::AMPS;
-    hipLaunchKernelGGL(k_cphase_vec<R>, dim3(grid_for(units)), dim3(kBlock), 0, s, a, units,
-                       fixed, set_mask, cr, ci);
+    launch_nt(nt, k_cphase_vec<R, true>, k_cphase_vec<R, false>, grid_for(units), s,
+              a, units, fixed, set_mask, cr, ci);
   } else {
     const uint64_t units = uint64_t(1) << free_bits;
-    hipLaunchKernelGGL(k_cphase_scalar<R>, dim3(grid_for(units)), dim3(kBlock), 0, s, a, units,
-                       fixed, set_mask, cr, ci);
+    launch_nt(nt, k_cphase_scalar<R, true>, k_cphase_scalar<R, false>, grid_for(units), s,
+              a, units, fixed, set_mask, cr, ci);
   }
   return hipGetLastError();
 }
@@ -291,14 +317,15 @@ hipError_t launch_bitswap(R* a, int n, int qa, int qb, hipStream_t s) {
   const int lo = qa < qb ? qa : qb, hi = qa < qb ? qb : qa;
   const BitSet16 fixed = sorted_bits({lo, hi});
   const int free_bits = n - 2;
+  const bool nt = stream_sweep(n, 2 * sizeof(R), lo);
   if (lo >= log_amps<R>() && free_bits >= log_amps<R>()) {
     const uint64_t units = (uint64_t(1) << free_bits) / Vec16<R>::AMPS;
-    hipLaunchKernelGGL(k_bitswap_vec<R>, dim3(grid_for(units)), dim3(kBlock), 0, s, a, units,
-                       fixed, lo, hi);
+    launch_nt(nt, k_bitswap_vec<R, true>, k_bitswap_vec<R, false>, grid_for(units), s,
+              a, units, fixed, lo, hi);
   } else {
     const uint64_t units = uint64_t(1) << free_bits;
-    hipLaunchKernelGGL(k_bitswap_scalar<R>, dim3(grid_for(units)), dim3(kBlock), 0, s, a, units,
-                       fixed, lo, hi);
+    launch_nt(nt, k_bitswap_scalar<R, true>, k_bitswap_scalar<R, false>, grid_for(units), s,
+              a, units, fixed, lo, hi);
   }
   return hipGetLastError();
 }

@@ -220,24 +220,6 @@ template <> struct Vec16<double> { using T = double2; static constexpr int AMPS 
 // 256 MiB last-level cache keep plain accesses: back-to-back passes find part
 // of the state there, and streaming made the QFT at 22-25 qubits 4-7% slower.
 // The kernels take the choice as a (uniform) argument.
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ float4 ld_stream(const float4* p) {
-  const f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
-  return {t.x, t.y, t.z, t.w};
-}
-__device__ __forceinline__ double2 ld_stream(const double2* p) {
-  const f64x2 t = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p));
-  return {t.x, t.y};
-}
-__device__ __forceinline__ void st_stream(float4* p, float4 v) {
-  const f32x4 t = {v.x, v.y, v.z, v.w};
-  __builtin_nontemporal_store(t, reinterpret_cast<f32x4*>(p));
-}
-__device__ __forceinline__ void st_stream(double2* p, double2 v) {
-  const f64x2 t = {v.x, v.y};
-  __builtin_nontemporal_store(t, reinterpret_cast<f64x2*>(p));
-}
 
 // LDS position of tile index x; one complex of padding every 16 entries keeps
 // the strided columns of the lowest rounds on distinct banks.
@@ -320,7 +302,7 @@ __global__ void __launch_bounds__(NT, sizeof(R) == 4 ? 2 : 1)
   V buf[NV];
   if (stream) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) buf[k] = ld_stream(p + threadIdx.x + k * NT);
+    for (int k = 0; k < NV; ++k) buf[k] = ld16<true>(p + threadIdx.x + k * NT);
   } else {
 #pragma unroll
     for (int k = 0; k < NV; ++k) buf[k] = p[threadIdx.x + k * NT];
@@ -351,7 +333,7 @@ __global__ void __launch_bounds__(NT, sizeof(R) == 4 ? 2 : 1)
   }
   if (stream) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) st_stream(p + threadIdx.x + k * NT, buf[k]);
+    for (int k = 0; k < NV; ++k) st16<true>(p + threadIdx.x + k * NT, buf[k]);
   } else {
 #pragma unroll
     for (int k = 0; k < NV; ++k) p[threadIdx.x + k * NT] = buf[k];
@@ -384,7 +366,7 @@ __global__ void __launch_bounds__(NT) k_qft_col(R* __restrict__ a, int start, in
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       const int e = threadIdx.x + k * NT;
-      buf[k] = ld_stream(p + glob((e / VPR) << C | (e % VPR) * AP) / AP);
+      buf[k] = ld16<true>(p + glob((e / VPR) << C | (e % VPR) * AP) / AP);
     }
   } else {
 #pragma unroll
@@ -422,7 +404,7 @@ __global__ void __launch_bounds__(NT) k_qft_col(R* __restrict__ a, int start, in
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       const int e = threadIdx.x + k * NT;
-      st_stream(p + glob((e / VPR) << C | (e % VPR) * AP) / AP, buf[k]);
+      st16<true>(p + glob((e / VPR) << C | (e % VPR) * AP) / AP, buf[k]);
     }
   } else {
 #pragma unroll

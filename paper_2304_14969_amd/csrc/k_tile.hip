@@ -31,7 +31,7 @@ __device__ __forceinline__ int lds_pos(int x) { return x + (x >> 4); }
 
 template <typename R>
 __device__ __forceinline__ Cx<R> cmac(Cx<R> acc, Cx<R> a, Cx<R> b) {
-  return {acc.r + a.r * b.r - a.i * b.i, acc.i + a.r * b.i + a.i * b.r};
+  return {fmadd(a.r, b.r, fmadd(-a.i, b.i, acc.r)), fmadd(a.r, b.i, fmadd(a.i, b.r, acc.i))};
 }
 
 // 2x2 matrix (row-major, interleaved) on round bit J.
@@ -101,7 +101,7 @@ __device__ __forceinline__ void apply_gate(Cx<R> (&v)[kV], int code, const R* __
   }
 }
 
-template <typename R, int C, int H>
+template <typename R, int C, int H, bool STREAM>
 __global__ void __launch_bounds__(1 << (C + H - kW))
     k_tile_pass(R* __restrict__ a, TileRows rows, const int4* __restrict__ rounds, int nrounds,
                 const int2* __restrict__ gates, const R* __restrict__ mats) {
@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(1 << (C + H - kW))
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     const int e = threadIdx.x + k * NT;
-    buf[k] = p[glob(e / VPR, (e % VPR) * AP) / AP];
+    buf[k] = ld16<STREAM>(p + glob(e / VPR, (e % VPR) * AP) / AP);
   }
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(1 << (C + H - kW))
     } else {
       o = {v0.r, v0.i};
     }
-    p[glob(e / VPR, (e % VPR) * AP) / AP] = o;
+    st16<STREAM>(p + glob(e / VPR, (e % VPR) * AP) / AP, o);
   }
 }
 
@@ -195,7 +195,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // One tile of a matrix-core pass: `base` is the global index of tile entry 0
 // (zeros at the low bits and the row bits), `rows` the row bits.
-template <int C, int H>
+template <int C, int H, bool STREAM>
 __device__ __forceinline__ void tile_mfma_body(float* __restrict__ a, uint64_t base,
                                                const TileRows& rows,
                                                const int4* __restrict__ rounds, int nrounds,
@@ -236,7 +236,7 @@ __device__ __forceinline__ void tile_mfma_body(float* __restrict__ a, uint64_t b
   {
     float4 buf[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) buf[k] = p4[glob_k(k) / 2];
+    for (int k = 0; k < NV; ++k) buf[k] = ld16<STREAM>(p4 + glob_k(k) / 2);
     // an empty use of the matrix after the tile loads are issued: it anchors
     // the matrix loads ahead of them (they complete first, in order)
 #pragma unroll
@@ -300,11 +300,11 @@ __device__ __forceinline__ void tile_mfma_body(float* __restrict__ a, uint64_t b
     const int e = threadIdx.x + k * NT;
     const int x = ((e / VPR) << C) | (e % VPR) * 2;
     const float2 v0 = sm[lds_pos(x)], v1 = sm[lds_pos(x + 1)];
-    p4[glob_k(k) / 2] = make_float4(v0.x, v0.y, v1.x, v1.y);
+    st16<STREAM>(p4 + glob_k(k) / 2, make_float4(v0.x, v0.y, v1.x, v1.y));
   }
 }
 
-template <int C, int H>
+template <int C, int H, bool STREAM>
 __global__ void __launch_bounds__(1 << (C + H - kW))
     k_tile_mfma(float* __restrict__ a, TileRows rows, const int4* __restrict__ rounds,
                 int nrounds, const float* __restrict__ amats) {
@@ -312,7 +312,7 @@ __global__ void __launch_bounds__(1 << (C + H - kW))
   uint64_t base = uint64_t(blockIdx.x) << C;
 #pragma unroll
   for (int j = 0; j < H; ++j) base = insert_zero(base, rows.b[j]);
-  tile_mfma_body<C, H>(a, base, rows, rounds, nrounds, amats);
+  tile_mfma_body<C, H, STREAM>(a, base, rows, rounds, nrounds, amats);
 }
 
 // Many kets at once: workgroup -> item by binary search over the items'
@@ -332,7 +332,8 @@ __global__ void __launch_bounds__(1 << (C + H - kW))
   uint64_t base = (b - it.first_tile) << C;
 #pragma unroll
   for (int j = 0; j < H; ++j) base = insert_zero(base, it.rows.b[j]);
-  tile_mfma_body<C, H>(arena + 2 * it.amp_off, base, it.rows, rounds + it.r0, it.nr, amats);
+  tile_mfma_body<C, H, false>(arena + 2 * it.amp_off, base, it.rows, rounds + it.r0, it.nr,
+                              amats);
 }
 
 }  // namespace
@@ -348,7 +349,7 @@ hipError_t launch_mfma_c(float* a, int n, const TileRows& rows, const void* roun
       return hipErrorInvalidValue;
   const size_t bytes = size_t((1 << TB) + ((1 << TB) >> 4)) * sizeof(float2);
   const uint64_t tiles = uint64_t(1) << (n - TB);
-  auto kern = k_tile_mfma<C, H>;
+  auto kern = stream_sweep(n, 8, C) ? k_tile_mfma<C, H, true> : k_tile_mfma<C, H, false>;
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
   hipLaunchKernelGGL(kern, dim3(unsigned(tiles)), dim3(1 << (TB - kW)), bytes, s, a, rows,
@@ -386,7 +387,8 @@ hipError_t launch_pass_c(R* a, int n, const TileRows& rows, const void* rounds, 
     if (rows.b[j] < C || rows.b[j] >= n || (j > 0 && rows.b[j] <= rows.b[j - 1]))
       return hipErrorInvalidValue;
   const size_t bytes = size_t((1 << TB) + ((1 << TB) >> 4)) * 2 * sizeof(R);
-  auto kern = k_tile_pass<R, C, H>;
+  auto kern = stream_sweep(n, 2 * sizeof(R), C) ? k_tile_pass<R, C, H, true>
+                                                : k_tile_pass<R, C, H, false>;
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
   const unsigned grid = unsigned(uint64_t(1) << (n - TB));

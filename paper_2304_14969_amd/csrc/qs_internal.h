@@ -21,6 +21,117 @@ struct BitSet16 {
   int pos[16];
 };
 
+// ---------------------------------------------------------------- streaming accesses
+// Whole-state sweeps read and write every byte once. For states larger than
+// the 256 MiB last-level cache, non-temporal (streaming) loads and stores move
+// 3-9% more bytes per second in sweeps whose waves touch contiguous runs of
+// at least 64 bytes (30 qubits: a one-qubit gate on bit 0 6.36 against 5.91
+// TB/s). With shorter runs (a gate bit below 64 bytes of amplitudes) the
+// partial-line streaming writes cost more than they save (a controlled phase
+// on bits 2 and 17: 2.13 against 1.63 ms), and smaller states keep plain
+// accesses, since back-to-back sweeps then find part of the state in that
+// cache (streaming made the QFT at 22-25 qubits 4-7% slower).
+extern int g_sweep_stream;  // knob sweep.stream: 0 by size and run length, 1 always, 2 never
+// n-qubit state of amp_bytes per amplitude, the lowest bit the sweep's
+// indexing fixes at low_bit (runs of amp_bytes << low_bit contiguous bytes)
+inline bool stream_sweep(int n, size_t amp_bytes, int low_bit) {
+  if (g_sweep_stream == 1) return true;
+  if (g_sweep_stream == 2) return false;
+  return (uint64_t(amp_bytes) << n) > (uint64_t(256) << 20) &&
+         (low_bit >= 6 || (uint64_t(amp_bytes) << low_bit) >= 64);
+}
+
+// Fused multiply-add, written out where a sweep's results must not depend on
+// which products the compiler chooses to contract (so that its streaming
+// and plain forms agree bit for bit).
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+typedef float qs_f32x2 __attribute__((ext_vector_type(2)));
+typedef float qs_f32x4 __attribute__((ext_vector_type(4)));
+typedef double qs_f64x2 __attribute__((ext_vector_type(2)));
+
+// 16-byte loads and stores, non-temporal when NT
+template <bool NT>
+__device__ __forceinline__ float4 ld16(const float4* p) {
+  if constexpr (NT) {
+    const qs_f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const qs_f32x4*>(p));
+    return {t.x, t.y, t.z, t.w};
+  } else {
+    return *p;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ double2 ld16(const double2* p) {
+  if constexpr (NT) {
+    const qs_f64x2 t = __builtin_nontemporal_load(reinterpret_cast<const qs_f64x2*>(p));
+    return {t.x, t.y};
+  } else {
+    return *p;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ void st16(float4* p, float4 v) {
+  if constexpr (NT) {
+    const qs_f32x4 t = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(t, reinterpret_cast<qs_f32x4*>(p));
+  } else {
+    *p = v;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ void st16(double2* p, double2 v) {
+  if constexpr (NT) {
+    const qs_f64x2 t = {v.x, v.y};
+    __builtin_nontemporal_store(t, reinterpret_cast<qs_f64x2*>(p));
+  } else {
+    *p = v;
+  }
+}
+// one interleaved complex amplitude (8 or 16 bytes) at p = &re
+template <bool NT>
+__device__ __forceinline__ void ld_amp(const float* p, float* re, float* im) {
+  if constexpr (NT) {
+    const qs_f32x2 t = __builtin_nontemporal_load(reinterpret_cast<const qs_f32x2*>(p));
+    *re = t.x;
+    *im = t.y;
+  } else {
+    *re = p[0];
+    *im = p[1];
+  }
+}
+template <bool NT>
+__device__ __forceinline__ void ld_amp(const double* p, double* re, double* im) {
+  if constexpr (NT) {
+    const qs_f64x2 t = __builtin_nontemporal_load(reinterpret_cast<const qs_f64x2*>(p));
+    *re = t.x;
+    *im = t.y;
+  } else {
+    *re = p[0];
+    *im = p[1];
+  }
+}
+template <bool NT>
+__device__ __forceinline__ void st_amp(float* p, float re, float im) {
+  if constexpr (NT) {
+    const qs_f32x2 t = {re, im};
+    __builtin_nontemporal_store(t, reinterpret_cast<qs_f32x2*>(p));
+  } else {
+    p[0] = re;
+    p[1] = im;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ void st_amp(double* p, double re, double im) {
+  if constexpr (NT) {
+    const qs_f64x2 t = {re, im};
+    __builtin_nontemporal_store(t, reinterpret_cast<qs_f64x2*>(p));
+  } else {
+    p[0] = re;
+    p[1] = im;
+  }
+}
+
 // ---------------------------------------------------------------- gates
 // Each launcher enqueues on `s` and returns the launch status.
 template <typename R>

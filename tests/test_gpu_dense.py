@@ -349,3 +349,55 @@ def test_qft_streaming_accesses(qs_lib, dtype, n, lds_bits):
     finally:
         for k, v in saved.items():
             qs.tune_set(k, v)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_sweeps_streaming_accesses(qs_lib, dtype):
+    """sweep.stream = 1: gate sweeps, fused blocks of 1 to 6 qubits (vector and
+    matrix-core forms), planned circuits of fused blocks and tile passes with
+    non-temporal loads and stores (by default only for states above 256 MiB),
+    each bit for bit equal to the plain accesses' result (sweep.stream = 2)
+    and against the oracle."""
+    qs = qs_lib
+    n = 14
+    a = workloads.gaussian_state(n, 1900)
+    soup = workloads.random_gate_soup(n, 300, 9)
+    circ = workloads.random_circuit(n, 6, 5)
+    g = np.random.default_rng(77)
+    blocks = [([int(v) for v in g.choice(n, k, replace=False)], haar(2 ** k, 60 + k))
+              for k in range(1, 7)] + [([3, 2, 1, 0], haar(16, 70))]
+    saved = qs.tune_get("sweep.stream")
+    try:
+        out = {}
+        for stream in (1, 2):
+            qs.tune_set("sweep.stream", stream)
+            res = []
+            with fresh(qs, n, dtype, a) as st:
+                qs.run_gates(st, soup)
+                res.append(st.amplitudes())
+                for qubits, m in blocks:
+                    st.apply_fused(qubits, m)
+                res.append(st.amplitudes())
+            for mode in ("blocks3", "blocks5", "tiles"):
+                c = qs.Circuit(n).add_gates(circ)
+                if mode == "tiles":
+                    c.use_tiles()
+                else:
+                    c.plan(int(mode[-1]))
+                with fresh(qs, n, dtype) as st:
+                    st.run(c)
+                    res.append(st.amplitudes())
+                c.free()
+            out[stream] = res
+        for k, (x, y) in enumerate(zip(out[1], out[2])):
+            assert np.array_equal(x, y), f"result {k} differs between the access forms"
+        want = dense.run_circuit(a, n, soup)
+        assert_parity(out[1][0], want, dtype, "soup")
+        for qubits, m in blocks:
+            want = dense.apply_matrix(want, n, qubits, m)
+        assert_parity(out[1][1], want, dtype, "fused blocks")
+        want = dense.run_circuit(dense.zero_state(n), n, circ)
+        for k in (2, 3, 4):
+            assert_parity(out[1][k], want, dtype, f"circuit form {k}")
+    finally:
+        qs.tune_set("sweep.stream", saved)
