@@ -32,9 +32,8 @@ HBM_PEAK_GBS = 8000.0
 # (`bench.py --calibrate-copy`: FETCH_SIZE reads 0.50002 of the bytes copied,
 # WRITE_SIZE 1.00000). Valid only for the kernel source they were taken on.
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_2304_14969_amd", "csrc", "k_qft.hip")
-TRAFFIC = {"sha256": "35b3e250bde12c56a7fbbf1866acb0499f30c757c5b2b4a41eaaf8f52835825b",
-           "bytes_per_launch": {"qft_col8": 2147591986, "qft_col7": 2147599058,
-                                "qft_lds": 2147572435}}
+TRAFFIC = {"sha256": "102fdb9f6a607cbaeabd9b75cb8f3992976ff571dbb56b25ab51ee5c72cb2ec0",
+           "bytes_per_launch": {"qft_col8": 2147868289, "qft_lds": 2147589714}}
 
 
 def measured_traffic(kernel: str):
@@ -176,6 +175,61 @@ def bench_circuit(qs, workloads, torch, n: int = 32, layers: int = 10, seed: int
         c.free()
     st.free()
     out["s"] = out["tiles"]["s"]
+    return out
+
+
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def bench_sweeps(qs, np, torch, n: int = 30, reps: int = 6) -> dict:
+    """Per-gate sweeps and fused blocks on an n-qubit complex64 state (8 GiB at
+    30): average launch time, algorithmic bytes per second (every amplitude
+    the gate changes read and written once) against the 8 TB/s peak, and for
+    the matrix-core blocks flops against the FP32 matrix peak. Gates with a
+    control or phase bit below bit 3 change amplitudes in runs shorter than a
+    64-byte segment, so their sweeps move whole segments for part of them."""
+    def haar(d, seed):
+        g = np.random.default_rng(seed)
+        z = (g.standard_normal((d, d)) + 1j * g.standard_normal((d, d))) / math.sqrt(2)
+        q, r = np.linalg.qr(z)
+        return q * (np.diag(r) / np.abs(np.diag(r)))
+
+    H = np.array([[1, 1], [1, -1]]) / math.sqrt(2)
+    X = np.array([[0, 1], [1, 0]])
+    st = qs.State(n, qs.C64)
+    st.set_basis(1)
+    ops = [("1q bit 0", lambda: st.apply_1q(0, H)), ("1q bit 1", lambda: st.apply_1q(1, H)),
+           ("1q bit 15", lambda: st.apply_1q(15, H)), (f"1q bit {n - 1}", lambda: st.apply_1q(n - 1, H)),
+           ("cx 5 -> 22", lambda: st.apply_ctrl([5], 1, 22, X)),
+           ("cx 1 -> 22", lambda: st.apply_ctrl([1], 1, 22, X)),
+           ("cphase 5,17", lambda: st.apply_cphase(5, 17, 0.3)),
+           ("cphase 2,17", lambda: st.apply_cphase(2, 17, 0.3)),
+           ("fused 2 (4, 21)", lambda: st.apply_fused([4, 21], haar(4, 1))),
+           ("fused 3 (6, 13, 25)", lambda: st.apply_fused([6, 13, 25], haar(8, 2))),
+           ("fused 4 (2, 8, 19, 27)", lambda: st.apply_fused([2, 8, 19, 27], haar(16, 3))),
+           ("fused 5 (0, 6, 13, 22, 28)", lambda: st.apply_fused([0, 6, 13, 22, 28], haar(32, 4)))]
+    out = {"workload": f"one gate or fused block at a time on n={n} qubits, complex64 "
+                       f"({2 ** n * 8 / 2 ** 30:g} GiB)", "peak_GBps": HBM_PEAK_GBS, "gates": {}}
+    for name, fn in ops:
+        fn()
+        torch.cuda.synchronize()
+        st.profile_start()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        prof = st.profile_stop()
+        (kname, v), = prof.items()
+        avg = v["total_ms"] / v["launches"]
+        gbps = v["bytes"] / v["launches"] / (avg * 1e-3) / 1e9
+        row = {"kernel": kname, "avg_ms": round(avg, 4), "GBps": round(gbps, 1),
+               "frac": round(gbps / HBM_PEAK_GBS, 3)}
+        if kname.endswith("_mfma"):
+            k = int(kname[5])
+            tflops = 8.0 * 2 ** k * 2 ** n / (avg * 1e-3) / 1e12
+            row["TFLOPs"] = round(tflops, 2)
+            row["mfma_frac"] = round(tflops / FP32_MFMA_PEAK_TFLOPS, 3)
+        out["gates"][name] = row
+    st.free()
     return out
 
 
@@ -616,7 +670,8 @@ def main() -> int:
     ap.add_argument("--quick", action="store_true",
                     help="only the QFT (skip the circuit, approximate, batch and validation runs)")
     ap.add_argument("--section", action="append", default=[],
-                    choices=["qft_sizes", "circuit", "approx", "learned", "pairs", "qft_factorized", "held", "batch",
+                    choices=["qft_sizes", "sweeps", "circuit", "approx", "learned", "pairs", "qft_factorized",
+                             "held", "batch",
                              "validation",
                              "depth_sweep", "heat_maps"],
                     help="run only these secondary sections (repeatable; default: all)")
@@ -750,10 +805,12 @@ def main() -> int:
     if not args.quick:
         from paper_2304_14969_amd import protocol
         sec = {}
-        want = set(args.section) or {"qft_sizes", "circuit", "approx", "learned", "pairs", "qft_factorized", "held",
-                                     "batch", "validation"}
+        want = set(args.section) or {"qft_sizes", "sweeps", "circuit", "approx", "learned", "pairs",
+                                     "qft_factorized", "held", "batch", "validation"}
         if "qft_sizes" in want:
             sec["qft_sizes"] = bench_qft_sizes(qs, workloads, torch)
+        if "sweeps" in want:
+            sec["sweeps_n30"] = bench_sweeps(qs, np, torch)
         if "circuit" in want:
             sec["circuit_n32"] = bench_circuit(qs, workloads, torch)
         if "approx" in want:
