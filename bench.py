@@ -32,8 +32,8 @@ HBM_PEAK_GBS = 8000.0
 # (`bench.py --calibrate-copy`: FETCH_SIZE reads 0.50002 of the bytes copied,
 # WRITE_SIZE 1.00000). Valid only for the kernel source they were taken on.
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_2304_14969_amd", "csrc", "k_qft.hip")
-TRAFFIC = {"sha256": "102fdb9f6a607cbaeabd9b75cb8f3992976ff571dbb56b25ab51ee5c72cb2ec0",
-           "bytes_per_launch": {"qft_col8": 2147868289, "qft_lds": 2147589714}}
+TRAFFIC = {"sha256": "47d3b224782c6c39ccf0f8e107722aa845f847277499b099837777bc60862c31",
+           "bytes_per_launch": {"qft_col8": 2147844379, "qft_lds": 2147584957}}
 
 
 def measured_traffic(kernel: str):

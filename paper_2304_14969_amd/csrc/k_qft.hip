@@ -24,17 +24,20 @@
 // a binary fraction of the bits above it. Both cost one sweep per pass, so
 // back-to-back transforms never move data for the relabelling.
 //
-// Twiddles. Inside a pass the twiddle of the stage at bit lo+jj factors into
-// a root of unity fixed by the pass-local bits (a 32-entry table computed in
-// float64 on the host) times a per-thread factor of the bits outside the pass,
-// computed once per thread and stage with sincospi of an argument in [0, 1):
-// an integer of the range bits outside the pass times a power of two. The
-// argument is exact while that integer has at most 24 significant bits (in
-// float32; 53 in float64), which holds for ranges of up to 24 qubits plus the
-// width of the pass. In longer float32 ranges the integer is rounded once, a
-// relative error of at most 2^-24 on an argument below 1, so the phase is off
-// by less than pi * 2^-24 (1.9e-7 rad), the size of the rounding of the sine
-// and cosine themselves.
+// Twiddles. Inside a round of W consecutive bits, the twiddle of each stage
+// factors into a root of unity fixed by the round's own bits and a factor of
+// the bits outside the round. The roots are compile-time constants once the
+// butterfly loops are unrolled (nothing for a zero angle, a swap for pi/2, a
+// product with literal cosines otherwise). The outside factors commute with
+// the round's later butterflies, so they are applied once after them: the
+// amplitude at round index m gets w^e(m) (e(m) = m bit-reversed in natural
+// order, m in bit-reversed order), w from one sincospi of an argument in
+// [0, 1), an integer of the range bits outside the round times a power of
+// two, and its powers by squaring. The argument is exact while that integer
+// has at most 24 significant bits (in float32; 53 in float64); in longer
+// float32 ranges it is rounded once, a phase error below pi * 2^-24
+// (1.9e-7 rad), the size of the rounding of the sine and cosine themselves;
+// the powers add at most 2W roundings.
 //
 // Scaling. The butterflies are unscaled (x+y, x-y); each pass multiplies by an
 // exact power of two so that the passes together scale by 2^(-len/2) (one
