@@ -2,8 +2,9 @@
 // the gates of a pass.
 //
 // A tile is 2^(C+H) amplitudes: the contiguous low bits [0, C) (rows of 2^C
-// amplitudes, 512 bytes) and H row bits chosen by the planner (complex64:
-// C = 6, H = 7, 64 KiB; complex128: C = 5, H = 7, 64 KiB). The tile is staged
+// amplitudes) and H = 7 row bits chosen by the planner (complex64: C = 5 by
+// default, 256-byte rows and 32 KiB tiles, 4 or 6 by knob; complex128: C = 5,
+// 512-byte rows, 64 KiB). The tile is staged
 // in LDS (one complex of padding every 16 entries) and transformed round by
 // round, each round acting on 4 tile bits. Complex64 rounds are dense 4-qubit
 // blocks on the matrix cores (k_tile_mfma); complex128 rounds (k_tile_pass)
