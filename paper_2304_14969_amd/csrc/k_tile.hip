@@ -268,6 +268,11 @@ __device__ __forceinline__ void tile_mfma_body(float* __restrict__ a, uint64_t b
     for (int m = 0; m < kV; ++m)
       dep[m] = lds_pos(((m & 1) << b0) | (((m >> 1) & 1) << b1) | (((m >> 2) & 1) << b2) |
                        (((m >> 3) & 1) << b3));
+    // the output rows of this half of the wavefront hold round-local indices
+    // j + 2p (j with bit 1 clear); lds_pos adds over disjoint bits, so their
+    // offsets are dep[j] plus that of bit 1 for p = 1 (a lane-dependent index
+    // into dep[] would compile to a compare-and-select chain per write)
+    const int pofs = p ? dep[2] : 0;
 #pragma unroll
     for (int ch = 0; ch < CHUNKS; ++ch) {
       int x0 = (wave * CHUNKS + ch) * 32 + (lane & 31);
@@ -282,15 +287,11 @@ __device__ __forceinline__ void tile_mfma_body(float* __restrict__ a, uint64_t b
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[ks], smf[2 * (px + dep[ks]) + p], acc, 0, 0,
                                                    0);
       // D layout: register e -> row 8 (e / 4) + 4 p + e % 4 of the embedded
-      // output; e even and e + 1 are the real and imaginary part of one row.
-      // (Choosing each write's offset once per round between the two halves
-      // of the wavefront, instead of this per-lane indexing, was measured
-      // slower: 22.3 against 20.7 ms per 32-qubit pass.)
+      // output; e even and e + 1 are the real and imaginary part of one row,
+      // round-local index 4 (e / 4) + 2 p + (e / 2) % 2.
 #pragma unroll
-      for (int e = 0; e < 16; e += 2) {
-        const int i = 8 * (e >> 2) + 4 * p + (e & 3);
-        sm[px + dep[i >> 1]] = make_float2(acc[e], acc[e + 1]);
-      }
+      for (int e = 0; e < 16; e += 2)
+        sm[px + dep[4 * (e >> 2) + ((e >> 1) & 1)] + pofs] = make_float2(acc[e], acc[e + 1]);
     }
 #pragma unroll
     for (int ks = 0; ks < kV; ++ks) A[ks] = An[ks];
