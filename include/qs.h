@@ -507,6 +507,11 @@ int qs_check(qs_state* st, double tol);
  *                    streaming (non-temporal) for states above 256 MiB, plain
  *                    below (such states partly stay in the last-level
  *                    cache between passes); 1 always streaming; 2 never;
+ *   "gate.shuffle_bits" complex64 one-qubit gates on bits 1 .. this value (at
+ *                    most 6; default 6) hold contiguous amplitudes per lane and
+ *                    exchange the partners (target bit flipped) by wavefront
+ *                    shuffles; 0: strided pairs for every bit above 0. Same
+ *                    results bit for bit;
  *   "sweep.stream"   global accesses of the gate sweeps, fused blocks and
  *                    tile passes: 0 (default) streaming (non-temporal) for
  *                    states above 256 MiB when every wave access covers

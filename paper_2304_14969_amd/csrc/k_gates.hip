@@ -76,6 +76,44 @@ __global__ void __launch_bounds__(kBlock) k_1q_f_bit0(float* __restrict__ a, uin
   }
 }
 
+// c64, target bit 1 <= t <= 6 with wavefront shuffles: a unit is one 16-byte
+// vector (amplitudes 2u, 2u + 1), so every wave instruction covers 1 KiB
+// contiguously; the amplitudes with bit t flipped sit 2^(t-1) lanes away in
+// the same wave and come over with cross-lane shuffles. Each lane computes
+// the rows of its own amplitudes (the same fused multiply-adds as
+// mat2_apply). Needs units a multiple of 2^t (all partners in the launch).
+template <bool NT>
+__global__ void __launch_bounds__(kBlock) k_1q_f_shfl(float* __restrict__ a, uint64_t units,
+                                                      int t, Mat2<float> m) {
+  const int d = 1 << (t - 1);
+  QS_STRIDE_LOOP(u, units) {
+    float4* p = reinterpret_cast<float4*>(a) + u;
+    const float4 x = ld16<NT>(p);
+    float4 y;
+    y.x = __shfl_xor(x.x, d);
+    y.y = __shfl_xor(x.y, d);
+    y.z = __shfl_xor(x.z, d);
+    y.w = __shfl_xor(x.w, d);
+    float4 o;
+    if ((u >> (t - 1)) & 1) {  // bit t set: rows 1, partner holds the bit-0 amplitudes
+      float r0 = y.x, i0 = y.y, r1 = x.x, i1 = x.y;
+      mat2_apply(m, r0, i0, r1, i1);
+      o.x = r1; o.y = i1;
+      r0 = y.z; i0 = y.w; r1 = x.z; i1 = x.w;
+      mat2_apply(m, r0, i0, r1, i1);
+      o.z = r1; o.w = i1;
+    } else {
+      float r0 = x.x, i0 = x.y, r1 = y.x, i1 = y.y;
+      mat2_apply(m, r0, i0, r1, i1);
+      o.x = r0; o.y = i0;
+      r0 = x.z; i0 = x.w; r1 = y.z; i1 = y.w;
+      mat2_apply(m, r0, i0, r1, i1);
+      o.z = r0; o.w = i0;
+    }
+    st16<NT>(p, o);
+  }
+}
+
 // c128: a unit is one pair.
 template <bool NT>
 __global__ void __launch_bounds__(kBlock) k_1q_d(double* __restrict__ a, uint64_t units, int t,
@@ -241,6 +279,11 @@ constexpr int log_amps() { return Vec16<R>::AMPS == 2 ? 1 : 0; }
 // sweep.stream: 0 streaming accesses for states above the last-level cache,
 // 1 always, 2 never
 int g_sweep_stream = 0;
+// gate.shuffle_bits: complex64 one-qubit gates on bits 1 .. this (at most 6)
+// exchange partner amplitudes by wavefront shuffles (0: never). At 30 qubits
+// they run at the rate of a gate on bit 0 (6.3-6.4 TB/s) where strided pairs
+// reach 5.5-5.6 (bits 1-3) and 6.0 TB/s (bits 4-6).
+int g_shuffle_bits = 6;
 
 // ------------------------------------------------------------------ launchers
 namespace {
@@ -257,6 +300,13 @@ void launch_nt(bool nt, KT kt, KF kf, unsigned grid, hipStream_t s, Args... args
 
 template <>
 hipError_t launch_apply_1q<float>(float* a, int n, int t, const Mat2<float>& m, hipStream_t s) {
+  if (t >= 1 && t <= g_shuffle_bits && n >= 7) {
+    // contiguous vectors, partners by shuffle: streams like bit 0
+    const uint64_t units = uint64_t(1) << (n - 1);
+    launch_nt(stream_sweep(n, 8, 6), k_1q_f_shfl<true>, k_1q_f_shfl<false>, grid_for(units), s,
+              a, units, t, m);
+    return hipGetLastError();
+  }
   const bool nt = stream_sweep(n, 8, t == 0 ? 6 : t);
   if (t == 0) {
     const uint64_t units = uint64_t(1) << (n - 1);

@@ -401,3 +401,36 @@ def test_sweeps_streaming_accesses(qs_lib, dtype):
             assert_parity(out[1][k], want, dtype, f"circuit form {k}")
     finally:
         qs.tune_set("sweep.stream", saved)
+
+
+@pytest.mark.parametrize("n", [7, 8, 12, 15])
+def test_1q_wavefront_shuffles(qs_lib, n):
+    """gate.shuffle_bits = 6: complex64 one-qubit gates on bits 1-6 with each
+    lane holding contiguous amplitudes and the partners (target bit flipped)
+    exchanged by cross-lane shuffles, in the plain and the streaming access
+    form: bit for bit equal to the strided pairs' result, and against the
+    oracle, for every target bit (7 qubits: exactly one wavefront)."""
+    qs = qs_lib
+    a = workloads.gaussian_state(n, 2100 + n)
+    g = np.random.default_rng(n)
+    gates = [(t, haar(2, 80 + t)) for t in range(1, 7)] * 2
+    g.shuffle(gates)
+    saved = {k: qs.tune_get(k) for k in ("gate.shuffle_bits", "sweep.stream")}
+    try:
+        out = {}
+        for shuffle, stream in ((0, 2), (6, 2), (6, 1)):
+            qs.tune_set("gate.shuffle_bits", shuffle)
+            qs.tune_set("sweep.stream", stream)
+            with fresh(qs, n, C64, a) as st:
+                for t, m in gates:
+                    st.apply_1q(t, m)
+                out[(shuffle, stream)] = st.amplitudes(np.complex64)
+        assert np.array_equal(out[(0, 2)], out[(6, 2)]), "shuffles differ from strided pairs"
+        assert np.array_equal(out[(6, 2)], out[(6, 1)]), "streaming form differs"
+        want = a
+        for t, m in gates:
+            want = dense.apply_1q(want, n, t, m)
+        assert_parity(out[(6, 1)].astype(np.complex128), want, C64, f"shuffles n={n}")
+    finally:
+        for k, v in saved.items():
+            qs.tune_set(k, v)
