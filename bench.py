@@ -185,9 +185,11 @@ def bench_sweeps(qs, np, torch, n: int = 30, reps: int = 6) -> dict:
     """Per-gate sweeps and fused blocks on an n-qubit complex64 state (8 GiB at
     30): average launch time, algorithmic bytes per second (every amplitude
     the gate changes read and written once) against the 8 TB/s peak, and for
-    the matrix-core blocks flops against the FP32 matrix peak. Gates with a
-    control or phase bit below bit 3 change amplitudes in runs shorter than a
-    64-byte segment, so their sweeps move whole segments for part of them."""
+    the matrix-core blocks flops against the FP32 matrix peak. One-qubit gates
+    on bits 1-6 exchange partners by wavefront shuffles, from bit 7 on they
+    read strided pairs. Gates with a control or phase bit below bit 3 change
+    amplitudes in runs shorter than a 64-byte segment, so their sweeps move
+    whole segments for part of them."""
     def haar(d, seed):
         g = np.random.default_rng(seed)
         z = (g.standard_normal((d, d)) + 1j * g.standard_normal((d, d))) / math.sqrt(2)
@@ -199,6 +201,8 @@ def bench_sweeps(qs, np, torch, n: int = 30, reps: int = 6) -> dict:
     st = qs.State(n, qs.C64)
     st.set_basis(1)
     ops = [("1q bit 0", lambda: st.apply_1q(0, H)), ("1q bit 1", lambda: st.apply_1q(1, H)),
+           ("1q bit 3", lambda: st.apply_1q(3, H)), ("1q bit 6", lambda: st.apply_1q(6, H)),
+           ("1q bit 7", lambda: st.apply_1q(7, H)),
            ("1q bit 15", lambda: st.apply_1q(15, H)), (f"1q bit {n - 1}", lambda: st.apply_1q(n - 1, H)),
            ("cx 5 -> 22", lambda: st.apply_ctrl([5], 1, 22, X)),
            ("cx 1 -> 22", lambda: st.apply_ctrl([1], 1, 22, X)),
