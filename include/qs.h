@@ -512,6 +512,11 @@ int qs_check(qs_state* st, double tol);
  *                    exchange the partners (target bit flipped) by wavefront
  *                    shuffles; 0: strided pairs for every bit above 0. Same
  *                    results bit for bit;
+ *   "gate.dense_ctrl" 1 (default): a singly controlled complex64 gate whose
+ *                    control is on bit 0, 1 or 2 sweeps the whole state (as a
+ *                    one-qubit gate on the target, the matrix applied where the
+ *                    control matches); 0: only the half it changes. Same
+ *                    results bit for bit;
  *   "sweep.stream"   global accesses of the gate sweeps, fused blocks and
  *                    tile passes: 0 (default) streaming (non-temporal) for
  *                    states above 256 MiB when every wave access covers

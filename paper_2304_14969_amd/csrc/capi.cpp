@@ -346,6 +346,9 @@ int qs_tune_set(const char* key, int64_t value) {
   } else if (!std::strcmp(key, "qft.col_rows")) {
     if (value < 0 || value > 2) return fail(QS_E_INVAL, "qft.col_rows must be 0, 1 or 2");
     g_qft_tune.col_rows = int(value);
+  } else if (!std::strcmp(key, "gate.dense_ctrl")) {
+    if (value < 0 || value > 1) return fail(QS_E_INVAL, "gate.dense_ctrl must be 0 or 1");
+    qs::g_dense_ctrl = int(value);
   } else if (!std::strcmp(key, "gate.shuffle_bits")) {
     if (value < 0 || value > 6) return fail(QS_E_INVAL, "gate.shuffle_bits must be in [0, 6]");
     qs::g_shuffle_bits = int(value);
@@ -424,6 +427,7 @@ int qs_tune_get(const char* key, int64_t* value) {
   else if (!std::strcmp(key, "qft.stream")) *value = g_qft_tune.stream;
   else if (!std::strcmp(key, "sweep.stream")) *value = qs::g_sweep_stream;
   else if (!std::strcmp(key, "gate.shuffle_bits")) *value = qs::g_shuffle_bits;
+  else if (!std::strcmp(key, "gate.dense_ctrl")) *value = qs::g_dense_ctrl;
   else if (!std::strcmp(key, "tile.low_bits")) *value = qs::g_tile_low_c64;
   else return fail(QS_E_INVAL, "unknown tuning key '%s'", key);
   return QS_OK;

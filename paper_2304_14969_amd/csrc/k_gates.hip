@@ -49,29 +49,34 @@ inline unsigned grid_for(uint64_t units) {
 
 // ------------------------------------------------------------------ 1q
 // c64, target bit t >= 1: a unit is two adjacent pairs (i, i+1) x (bit t).
-template <bool NT>
+// CTRL: a singly controlled gate swept densely (every pair read and written,
+// the matrix applied where index & cmask == cval), for controls whose bit
+// leaves runs too short for the sparse sweep.
+template <bool NT, bool CTRL = false>
 __global__ void __launch_bounds__(kBlock) k_1q_f_vec(float* __restrict__ a, uint64_t units,
-                                                     int t, Mat2<float> m) {
+                                                     int t, Mat2<float> m, uint64_t cmask,
+                                                     uint64_t cval) {
   QS_STRIDE_LOOP(u, units) {
     const uint64_t i0 = insert_zero(u << 1, t);
     float4* p0 = reinterpret_cast<float4*>(a + 2 * i0);
     float4* p1 = reinterpret_cast<float4*>(a + 2 * (i0 + (uint64_t(1) << t)));
     float4 x = ld16<NT>(p0), y = ld16<NT>(p1);
-    mat2_apply(m, x.x, x.y, y.x, y.y);
-    mat2_apply(m, x.z, x.w, y.z, y.w);
+    if (!CTRL || (i0 & cmask) == cval) mat2_apply(m, x.x, x.y, y.x, y.y);
+    if (!CTRL || ((i0 + 1) & cmask) == cval) mat2_apply(m, x.z, x.w, y.z, y.w);
     st16<NT>(p0, x);
     st16<NT>(p1, y);
   }
 }
 
 // c64, target bit 0: both amplitudes of a pair are in one 16-byte vector.
-template <bool NT>
+template <bool NT, bool CTRL = false>
 __global__ void __launch_bounds__(kBlock) k_1q_f_bit0(float* __restrict__ a, uint64_t units,
-                                                      Mat2<float> m) {
+                                                      Mat2<float> m, uint64_t cmask,
+                                                      uint64_t cval) {
   QS_STRIDE_LOOP(u, units) {
     float4* p = reinterpret_cast<float4*>(a + 4 * u);
     float4 x = ld16<NT>(p);
-    mat2_apply(m, x.x, x.y, x.z, x.w);
+    if (!CTRL || ((2 * u) & cmask) == cval) mat2_apply(m, x.x, x.y, x.z, x.w);
     st16<NT>(p, x);
   }
 }
@@ -82,9 +87,10 @@ __global__ void __launch_bounds__(kBlock) k_1q_f_bit0(float* __restrict__ a, uin
 // the same wave and come over with cross-lane shuffles. Each lane computes
 // the rows of its own amplitudes (the same fused multiply-adds as
 // mat2_apply). Needs units a multiple of 2^t (all partners in the launch).
-template <bool NT>
+template <bool NT, bool CTRL = false>
 __global__ void __launch_bounds__(kBlock) k_1q_f_shfl(float* __restrict__ a, uint64_t units,
-                                                      int t, Mat2<float> m) {
+                                                      int t, Mat2<float> m, uint64_t cmask,
+                                                      uint64_t cval) {
   const int d = 1 << (t - 1);
   QS_STRIDE_LOOP(u, units) {
     float4* p = reinterpret_cast<float4*>(a) + u;
@@ -109,6 +115,10 @@ __global__ void __launch_bounds__(kBlock) k_1q_f_shfl(float* __restrict__ a, uin
       r0 = x.z; i0 = x.w; r1 = y.z; i1 = y.w;
       mat2_apply(m, r0, i0, r1, i1);
       o.z = r0; o.w = i0;
+    }
+    if (CTRL) {  // amplitudes 2u, 2u + 1 keep their value where the control does not match
+      if (((2 * u) & cmask) != cval) { o.x = x.x; o.y = x.y; }
+      if (((2 * u + 1) & cmask) != cval) { o.z = x.z; o.w = x.w; }
     }
     st16<NT>(p, o);
   }
@@ -284,6 +294,9 @@ int g_sweep_stream = 0;
 // they run at the rate of a gate on bit 0 (6.3-6.4 TB/s) where strided pairs
 // reach 5.5-5.6 (bits 1-3) and 6.0 TB/s (bits 4-6).
 int g_shuffle_bits = 6;
+// gate.dense_ctrl: singly controlled complex64 gates with the control below
+// bit 3 swept densely (1) or sparsely (0)
+int g_dense_ctrl = 1;
 
 // ------------------------------------------------------------------ launchers
 namespace {
@@ -304,16 +317,18 @@ hipError_t launch_apply_1q<float>(float* a, int n, int t, const Mat2<float>& m, 
     // contiguous vectors, partners by shuffle: streams like bit 0
     const uint64_t units = uint64_t(1) << (n - 1);
     launch_nt(stream_sweep(n, 8, 6), k_1q_f_shfl<true>, k_1q_f_shfl<false>, grid_for(units), s,
-              a, units, t, m);
+              a, units, t, m, uint64_t(0), uint64_t(0));
     return hipGetLastError();
   }
   const bool nt = stream_sweep(n, 8, t == 0 ? 6 : t);
   if (t == 0) {
     const uint64_t units = uint64_t(1) << (n - 1);
-    launch_nt(nt, k_1q_f_bit0<true>, k_1q_f_bit0<false>, grid_for(units), s, a, units, m);
+    launch_nt(nt, k_1q_f_bit0<true>, k_1q_f_bit0<false>, grid_for(units), s, a, units, m,
+              uint64_t(0), uint64_t(0));
   } else {
     const uint64_t units = uint64_t(1) << (n - 2);
-    launch_nt(nt, k_1q_f_vec<true>, k_1q_f_vec<false>, grid_for(units), s, a, units, t, m);
+    launch_nt(nt, k_1q_f_vec<true>, k_1q_f_vec<false>, grid_for(units), s, a, units, t, m,
+              uint64_t(0), uint64_t(0));
   }
   return hipGetLastError();
 }
@@ -327,9 +342,43 @@ hipError_t launch_apply_1q<double>(double* a, int n, int t, const Mat2<double>& 
   return hipGetLastError();
 }
 
+// A singly controlled complex64 gate whose control bit is below 3: the sparse
+// sweep would touch 16-32-byte pieces of the half it changes, and the memory
+// system move whole segments around them anyway, so the whole state is swept
+// as for a one-qubit gate on the target (contiguous, streaming) with the
+// matrix applied where the control matches. At 30 qubits: control 0-2,
+// target 22: 3.1 against 3.4 ms; control 1, target 0: 2.7 against 3.3 ms.
+// With the control at bit 3 or above the sparse sweep reads the changed half
+// in long runs whatever the target (control 22, target 0-2: 1.5 against
+// 2.7 ms dense) and is kept.
+bool ctrl_dense(float* a, int n, const BitSet16& fixed, uint64_t set_mask, int tbit,
+                const Mat2<float>& m, hipStream_t s) {
+  if (!g_dense_ctrl || fixed.n != 2 || n < 7) return false;
+  const int cbit = fixed.pos[0] == tbit ? fixed.pos[1] : fixed.pos[0];
+  if (cbit >= 3) return false;
+  const uint64_t cmask = uint64_t(1) << cbit, cval = set_mask & cmask;
+  const bool nt = stream_sweep(n, 8, 6);
+  if (tbit == 0) {
+    const uint64_t units = uint64_t(1) << (n - 1);
+    launch_nt(nt, k_1q_f_bit0<true, true>, k_1q_f_bit0<false, true>, grid_for(units), s, a,
+              units, m, cmask, cval);
+  } else if (tbit <= g_shuffle_bits) {
+    const uint64_t units = uint64_t(1) << (n - 1);
+    launch_nt(nt, k_1q_f_shfl<true, true>, k_1q_f_shfl<false, true>, grid_for(units), s, a,
+              units, tbit, m, cmask, cval);
+  } else {
+    const uint64_t units = uint64_t(1) << (n - 2);
+    launch_nt(nt, k_1q_f_vec<true, true>, k_1q_f_vec<false, true>, grid_for(units), s, a,
+              units, tbit, m, cmask, cval);
+  }
+  return true;
+}
+
 template <typename R>
 hipError_t launch_apply_ctrl(R* a, int n, const BitSet16& fixed, uint64_t set_mask, int tbit,
                              const Mat2<R>& m, hipStream_t s) {
+  if constexpr (sizeof(R) == 4)
+    if (ctrl_dense(a, n, fixed, set_mask, tbit, m, s)) return hipGetLastError();
   const int free_bits = n - fixed.n;
   const bool nt = stream_sweep(n, 2 * sizeof(R), fixed.pos[0]);
   if (fixed.pos[0] >= log_amps<R>() && free_bits >= log_amps<R>()) {

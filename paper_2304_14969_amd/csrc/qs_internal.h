@@ -33,6 +33,7 @@ struct BitSet16 {
 // cache (streaming made the QFT at 22-25 qubits 4-7% slower).
 extern int g_sweep_stream;  // knob sweep.stream: 0 by size and run length, 1 always, 2 never
 extern int g_shuffle_bits;  // knob gate.shuffle_bits: one-qubit gates on bits 1 .. this by shuffles
+extern int g_dense_ctrl;    // knob gate.dense_ctrl: low-bit singly controlled gates swept densely
 // n-qubit state of amp_bytes per amplitude, the lowest bit the sweep's
 // indexing fixes at low_bit (runs of amp_bytes << low_bit contiguous bytes)
 inline bool stream_sweep(int n, size_t amp_bytes, int low_bit) {

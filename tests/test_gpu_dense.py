@@ -434,3 +434,37 @@ def test_1q_wavefront_shuffles(qs_lib, n):
     finally:
         for k, v in saved.items():
             qs.tune_set(k, v)
+
+
+@pytest.mark.parametrize("n", [7, 9, 13])
+def test_ctrl_dense_low_bits(qs_lib, n):
+    """gate.dense_ctrl = 1: singly controlled complex64 gates whose control is
+    below bit 3 swept densely (the whole state, the matrix applied where the
+    control matches; targets on bit 0, by shuffles, or strided), in both
+    access forms, among gates with high controls that keep the sparse sweep:
+    bit for bit equal to the sparse sweeps and against the oracle, for
+    controls and anti-controls."""
+    qs = qs_lib
+    a = workloads.gaussian_state(n, 2300 + n)
+    cases = [(0, 1, 5), (1, 1, n - 1), (2, 0, 4), (1, 0, 0), (0, 1, 3), (n - 1, 1, 1),
+             (n - 2, 0, 0), (2, 1, 6), (0, 0, n - 1)]
+    mats = [haar(2, 90 + k) for k in range(len(cases))]
+    saved = {k: qs.tune_get(k) for k in ("gate.dense_ctrl", "sweep.stream")}
+    try:
+        out = {}
+        for dense_on, stream in ((0, 2), (1, 2), (1, 1)):
+            qs.tune_set("gate.dense_ctrl", dense_on)
+            qs.tune_set("sweep.stream", stream)
+            with fresh(qs, n, C64, a) as st:
+                for (c, cv, t), m in zip(cases, mats):
+                    st.apply_ctrl([c], cv, t, m)
+                out[(dense_on, stream)] = st.amplitudes(np.complex64)
+        assert np.array_equal(out[(0, 2)], out[(1, 2)]), "dense and sparse sweeps differ"
+        assert np.array_equal(out[(1, 2)], out[(1, 1)]), "streaming form differs"
+        want = a
+        for (c, cv, t), m in zip(cases, mats):
+            want = dense.apply_ctrl(want, n, [c], cv, t, m)
+        assert_parity(out[(1, 1)].astype(np.complex128), want, C64, f"dense ctrl n={n}")
+    finally:
+        for k, v in saved.items():
+            qs.tune_set(k, v)

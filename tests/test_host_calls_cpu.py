@@ -111,7 +111,7 @@ def test_every_knob_round_trips(qs):
             "factor.unobservable": (0, 1, 2), "factor.done_flag": (0, 1, 2),
             "factor.fuse_ops": (0, 1, 2), "factor.kernarg_tables": (0, 1, 2),
             "factor.hold": (0, 1, 2), "factor.kickback": (0, 1, 2), "qft.stream": (1, 2, 3), "sweep.stream": (1, 2, 3),
-            "gate.shuffle_bits": (0, 6, 7)}
+            "gate.shuffle_bits": (0, 6, 7), "gate.dense_ctrl": (0, 1, 2)}
     for key, (a, b, bad) in keys.items():
         saved = get(key)
         try:
