@@ -129,11 +129,12 @@ int prepare_tiles(qs_batch* b, qs_circuit* const* circs, std::vector<char>* use_
     round_base[i] = nround;
     for (const auto& r : plans[i]->rounds) {
       rtab.push_back(r.bits[0] | (r.bits[1] << 8) | (r.bits[2] << 16) | (r.bits[3] << 24));
-      rtab.push_back(nround * 1024);
+      rtab.push_back(nround * qs::kRoundOperands);
       rtab.push_back(0);
       rtab.push_back(0);
-      emb.resize(size_t(nround + 1) * 1024);
-      qs::embed_round(plans[i]->mats.data() + r.mat, emb.data() + size_t(nround) * 1024);
+      emb.resize(size_t(nround + 1) * qs::kRoundOperands);
+      qs::embed_round(plans[i]->mats.data() + r.mat,
+                      emb.data() + size_t(nround) * qs::kRoundOperands);
       ++nround;
     }
   }

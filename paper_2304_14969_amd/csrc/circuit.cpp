@@ -363,7 +363,7 @@ void tile_tables(const TilePlan& pl, bool c64, std::vector<unsigned char>* out, 
   for (size_t ri = 0; ri < pl.rounds.size(); ++ri) {
     const auto& r = pl.rounds[ri];
     tab.push_back(r.bits[0] | (r.bits[1] << 8) | (r.bits[2] << 16) | (r.bits[3] << 24));
-    tab.push_back(dense ? int32_t(ri * 1024) : r.g0);
+    tab.push_back(dense ? int32_t(ri * kRoundOperands) : r.g0);
     tab.push_back(r.ng);
     tab.push_back(0);
   }
@@ -375,18 +375,19 @@ void tile_tables(const TilePlan& pl, bool c64, std::vector<unsigned char>* out, 
     }
   const size_t esz = c64 ? sizeof(float) : sizeof(double);
   const size_t emb_at = (tab.size() * sizeof(int32_t) + 255) / 256 * 256;
-  // dense rounds: each round's 32x32 real embedding in lane order, then the
+  // dense rounds: each round's matrix-core operands in lane order, then the
   // matrices of the block steps; sparse rounds: every matrix as is
-  const size_t emb = dense ? pl.rounds.size() * 1024 * sizeof(float) : 0;
+  const size_t emb = dense ? pl.rounds.size() * kRoundOperands * sizeof(float) : 0;
   const size_t total = emb_at + emb + 2 * pl.mats.size() * esz;
   out->assign(total, 0);
   unsigned char* host = out->data();
   std::memcpy(host, tab.data(), tab.size() * sizeof(int32_t));
   if (dense) {
-    std::vector<float> A(1024);
+    std::vector<float> A(kRoundOperands);
     for (size_t ri = 0; ri < pl.rounds.size(); ++ri) {
       embed_round(pl.mats.data() + pl.rounds[ri].mat, A.data());
-      std::memcpy(host + emb_at + ri * 1024 * sizeof(float), A.data(), 1024 * sizeof(float));
+      std::memcpy(host + emb_at + ri * kRoundOperands * sizeof(float), A.data(),
+                  kRoundOperands * sizeof(float));
     }
   }
   for (size_t i = 0; i < pl.mats.size(); ++i) {
@@ -404,13 +405,12 @@ void tile_tables(const TilePlan& pl, bool c64, std::vector<unsigned char>* out, 
 }
 
 void embed_round(const cd* u, float* out) {
-  for (int ks = 0; ks < 16; ++ks)
+  for (int s4 = 0; s4 < 4; ++s4)
     for (int lane = 0; lane < 64; ++lane) {
-      const int row = lane & 31, pp = lane >> 5;
-      const cd x = u[(row >> 1) * 16 + ks];
-      const double v = (row & 1) == 0 ? (pp == 0 ? x.real() : -x.imag())
-                                      : (pp == 0 ? x.imag() : x.real());
-      out[ks * 64 + lane] = float(v);
+      const cd x = u[(lane % 16) * 16 + 4 * s4 + lane / 16];
+      out[(3 * s4 + 0) * 64 + lane] = float(x.real());
+      out[(3 * s4 + 1) * 64 + lane] = float(x.imag());
+      out[(3 * s4 + 2) * 64 + lane] = float(x.real() + x.imag());
     }
 }
 

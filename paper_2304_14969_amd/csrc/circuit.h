@@ -93,10 +93,11 @@ TilePlan plan_tiles(const std::vector<Gate>& gates, int n, int C, int H, int W, 
 void tile_tables(const TilePlan& pl, bool c64, std::vector<unsigned char>* out, size_t* gates_off,
                  size_t* mats_off, size_t* emb_off);
 
-// The operand a matrix-core round reads: the 32 x 32 real embedding
-// [[Re U, -Im U], [Im U, Re U]] (interleaved rows and columns) of a 16 x 16
-// complex round matrix u, in lane order: out[ks * 64 + lane] =
-// Uemb[lane % 32][2 ks + lane / 32].
+// The operands a matrix-core round reads, for the three real products of
+// Re U X_r, Im U X_i and (Re U + Im U)(X_r + X_i) of a 16 x 16 complex round
+// matrix u (16 x 16 x 4 MFMA A-operand layout): out[(3 s + c) * 64 + lane] =
+// W_c[lane % 16][4 s + lane / 16] with W_0 = Re U, W_1 = Im U,
+// W_2 = Re U + Im U (summed in float64), s = 0 .. 3.
 void embed_round(const cd* u, float* out);
 
 }  // namespace qs

@@ -7,8 +7,10 @@
 // 512-byte rows, 64 KiB). The tile is staged
 // in LDS (one complex of padding every 16 entries) and transformed round by
 // round, each round acting on 4 tile bits. Complex64 rounds are dense 4-qubit
-// blocks on the matrix cores (k_tile_mfma); complex128 rounds (k_tile_pass)
-// gather, per thread, the 16 amplitudes that differ in the round's bits and
+// blocks on the matrix cores (k_tile_mfma), each complex product as three
+// real ones (Re U X_r, Im U X_i and (Re U + Im U)(X_r + X_i), 16 x 16 x 4
+// MFMAs: 3/4 of the flops of the 32 x 32 real embedding); complex128 rounds
+// (k_tile_pass) gather, per thread, the 16 amplitudes that differ in the round's bits and
 // apply the round's one- and two-qubit gates in registers (the gate's bits
 // inside the round select a compile-time form).
 #include "qs_internal.h"
@@ -192,7 +194,10 @@ __global__ void __launch_bounds__(1 << (C + H - kW))
 // group, lane / 32 = real or imaginary part), one K-step per input amplitude.
 // `amats` holds each round's embedding in lane order: entry ks * 64 + lane =
 // Uemb[lane % 32][2 ks + lane / 32].
-typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+// matrix-core operands of a round per lane: Re U, Im U, Re U + Im U for 4 K-steps
+constexpr int kOps = 12;
+static_assert(kOps * 64 == kRoundOperands, "round operand layout");
 
 // One tile of a matrix-core pass: `base` is the global index of tile entry 0
 // (zeros at the low bits and the row bits), `rows` the row bits.
@@ -213,7 +218,6 @@ __device__ __forceinline__ void tile_mfma_body(float* __restrict__ a, uint64_t b
   static_assert(RT * VPR == NT && RTB <= H, "tile shape");
   extern __shared__ unsigned char smraw[];
   float2* sm = reinterpret_cast<float2*>(smraw);
-  const float* smf = reinterpret_cast<const float*>(smraw);
   const int r0 = int(threadIdx.x) / VPR;
   uint64_t off_t = base | uint64_t((int(threadIdx.x) % VPR) * 2);
 #pragma unroll
@@ -226,13 +230,14 @@ __device__ __forceinline__ void tile_mfma_body(float* __restrict__ a, uint64_t b
     return g;
   };
   float4* p4 = reinterpret_cast<float4*>(a);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, p = lane >> 5;
-  // this lane's part of the first round's embedded matrix, issued before the
-  // tile so that its latency hides behind the tile's (the scheduling barrier
-  // keeps the compiler from sinking these loads to their first use)
-  float A[kV];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, col = lane & 15;
+  // this lane's part of the first round's operands, issued before the tile so
+  // that its latency hides behind the tile's (the scheduling barrier keeps
+  // the compiler from sinking these loads to their first use)
+  float A[kOps];
 #pragma unroll
-  for (int ks = 0; ks < kV; ++ks) A[ks] = amats[rounds[0].y + ks * 64 + lane];
+  for (int k = 0; k < kOps; ++k) A[k] = amats[rounds[0].y + k * 64 + lane];
   __builtin_amdgcn_sched_barrier(0);
   {
     float4 buf[NV];
@@ -241,7 +246,7 @@ __device__ __forceinline__ void tile_mfma_body(float* __restrict__ a, uint64_t b
     // an empty use of the matrix after the tile loads are issued: it anchors
     // the matrix loads ahead of them (they complete first, in order)
 #pragma unroll
-    for (int ks = 0; ks < kV; ++ks) asm volatile("" ::"v"(A[ks]));
+    for (int k = 0; k < kOps; ++k) asm volatile("" ::"v"(A[k]));
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       const int e = threadIdx.x + k * NT;
@@ -255,46 +260,62 @@ __device__ __forceinline__ void tile_mfma_body(float* __restrict__ a, uint64_t b
     const int4 rd = rounds[r];
     const int b0 = rd.x & 255, b1 = (rd.x >> 8) & 255, b2 = (rd.x >> 16) & 255,
               b3 = (rd.x >> 24) & 255;
-    // the next round's matrix is loaded while this round computes (kept here
-    // by the scheduling barrier; left to itself the compiler sinks the loads
-    // to the end of the round and the next round waits for them)
-    float An[kV];
+    // the next round's operands are loaded while this round computes (kept
+    // here by the scheduling barrier; left to itself the compiler sinks the
+    // loads to the end of the round and the next round waits for them)
+    float An[kOps];
     const int offn = rounds[r + 1 < nrounds ? r + 1 : r].y;
 #pragma unroll
-    for (int ks = 0; ks < kV; ++ks) An[ks] = amats[offn + ks * 64 + lane];
+    for (int k = 0; k < kOps; ++k) An[k] = amats[offn + k * 64 + lane];
     __builtin_amdgcn_sched_barrier(0);
     int dep[kV];  // LDS offset of round-local index m (the round bits and padding)
 #pragma unroll
     for (int m = 0; m < kV; ++m)
       dep[m] = lds_pos(((m & 1) << b0) | (((m >> 1) & 1) << b1) | (((m >> 2) & 1) << b2) |
                        (((m >> 3) & 1) << b3));
-    // the output rows of this half of the wavefront hold round-local indices
-    // j + 2p (j with bit 1 clear); lds_pos adds over disjoint bits, so their
-    // offsets are dep[j] plus that of bit 1 for p = 1 (a lane-dependent index
-    // into dep[] would compile to a compare-and-select chain per write)
-    const int pofs = p ? dep[2] : 0;
+    // lane (q, col) reads input index 4 s + q and writes output index 4 q + i;
+    // lds_pos adds over disjoint bits, so these offsets are dep[4 s] + qin and
+    // dep[i] + qout with per-lane qin = dep[q], qout = dep[4 q] (a
+    // lane-dependent index into dep[] would compile to select chains)
+    const int qin = ((q & 1) ? dep[1] : 0) + ((q & 2) ? dep[2] : 0);
+    const int qout = ((q & 1) ? dep[4] : 0) + ((q & 2) ? dep[8] : 0);
 #pragma unroll
     for (int ch = 0; ch < CHUNKS; ++ch) {
-      int x0 = (wave * CHUNKS + ch) * 32 + (lane & 31);
-      x0 = int(insert_zero(uint64_t(x0), b0));
-      x0 = int(insert_zero(uint64_t(x0), b1));
-      x0 = int(insert_zero(uint64_t(x0), b2));
-      x0 = int(insert_zero(uint64_t(x0), b3));
-      const int px = lds_pos(x0);  // the round bits and the rest are disjoint
-      f32x16 acc = f32x16{};
+      int px[2];  // LDS offset of this lane's group in each 16-group block
 #pragma unroll
-      for (int ks = 0; ks < kV; ++ks)
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[ks], smf[2 * (px + dep[ks]) + p], acc, 0, 0,
-                                                   0);
-      // D layout: register e -> row 8 (e / 4) + 4 p + e % 4 of the embedded
-      // output; e even and e + 1 are the real and imaginary part of one row,
-      // round-local index 4 (e / 4) + 2 p + (e / 2) % 2.
+      for (int bk = 0; bk < 2; ++bk) {
+        int x0 = (wave * CHUNKS + ch) * 32 + 16 * bk + col;
+        x0 = int(insert_zero(uint64_t(x0), b0));
+        x0 = int(insert_zero(uint64_t(x0), b1));
+        x0 = int(insert_zero(uint64_t(x0), b2));
+        x0 = int(insert_zero(uint64_t(x0), b3));
+        px[bk] = lds_pos(x0);
+      }
+      // three real 16 x 16 products per block: Re U X_r, Im U X_i,
+      // (Re U + Im U)(X_r + X_i), K = 16 in 4 steps of 4
+      f32x4 p1[2] = {f32x4{}, f32x4{}}, p2[2] = {f32x4{}, f32x4{}}, p3[2] = {f32x4{}, f32x4{}};
 #pragma unroll
-      for (int e = 0; e < 16; e += 2)
-        sm[px + dep[4 * (e >> 2) + ((e >> 1) & 1)] + pofs] = make_float2(acc[e], acc[e + 1]);
+      for (int s4 = 0; s4 < 4; ++s4) {
+#pragma unroll
+        for (int bk = 0; bk < 2; ++bk) {
+          const float2 v = sm[px[bk] + dep[4 * s4] + qin];
+          p1[bk] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[3 * s4], v.x, p1[bk], 0, 0, 0);
+          p2[bk] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[3 * s4 + 1], v.y, p2[bk], 0, 0, 0);
+          p3[bk] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[3 * s4 + 2], v.x + v.y, p3[bk], 0, 0,
+                                                         0);
+        }
+      }
+      // D layout: register i -> output row 4 q + i of group col;
+      // Y = (p1 - p2) + i (p3 - p1 - p2)
+#pragma unroll
+      for (int bk = 0; bk < 2; ++bk)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          sm[px[bk] + dep[i] + qout] =
+              make_float2(p1[bk][i] - p2[bk][i], p3[bk][i] - (p1[bk][i] + p2[bk][i]));
     }
 #pragma unroll
-    for (int ks = 0; ks < kV; ++ks) A[ks] = An[ks];
+    for (int k = 0; k < kOps; ++k) A[k] = An[k];
     __syncthreads();
   }
 #pragma unroll

@@ -381,9 +381,12 @@ struct TileItem {
 };
 hipError_t launch_tile_mfma_batch(float* arena, const TileItem* items, int nitems, uint64_t tiles,
                                   const void* rounds, const float* amats, hipStream_t s);
+// Floats of one dense round's matrix-core operands: for each of 4 K-steps the
+// lane's entries of Re U, Im U and Re U + Im U (12 per lane, 64 lanes).
+constexpr int kRoundOperands = 768;
 // Complex64 pass with dense 4-qubit rounds on the matrix cores: `rounds`
-// int4 {bits packed 8 per byte, offset of the round's embedded matrix in
-// amats (1024 floats, lane order), 0, 0}.
+// int4 {bits packed 8 per byte, offset of the round's operands in amats
+// (kRoundOperands floats, lane order), 0, 0}.
 hipError_t launch_tile_mfma(float* a, int n, int low_bits, const TileRows& rows,
                             const void* rounds, int nrounds, const float* amats, hipStream_t s);
 
