@@ -2,28 +2,30 @@
 //
 // For every assignment of the n-k bits outside the block (a "group"), the 2^k
 // amplitudes of the group are multiplied by the block's complex matrix U. Over
-// a tile of groups this is a complex GEMM Y = U V with V = 2^k rows x groups.
-// It runs as a real GEMM with the interleaved embedding
-//   row 2r+q of the output (q = 0 real, 1 imaginary part of output row r),
-//   column 2c+p of the input (p = 0 real, 1 imaginary part of input row c),
-//   Uemb[2r][2c] = Re U, Uemb[2r][2c+1] = -Im U,
-//   Uemb[2r+1][2c] = Im U, Uemb[2r+1][2c+1] = Re U,
-// on v_mfma_f32_32x32x2f32: one K-step of 2 covers (Re, Im) of one input row,
-// so a wavefront's B operand is 32 whole amplitudes read from LDS.
+// a tile of groups this is a complex product Y = U X with X = 2^k rows x
+// groups, computed as three real products on v_mfma_f32_16x16x4f32:
+//   P1 = Re U X_r,  P2 = Im U X_i,  P3 = (Re U + Im U)(X_r + X_i),
+//   Re Y = P1 - P2,  Im Y = P3 - P1 - P2
+// (3/4 of the matrix flops of the real embedding [[Re U, -Im U], [Im U,
+// Re U]]). One instruction multiplies 16 output rows by 4 input rows for 16
+// groups: lane (q, col) = (lane / 16, lane % 16) supplies U[16 rb + col][4 s +
+// q] as the A operand and input row 4 s + q of group col as the B operand,
+// one 8-byte LDS read per input amplitude feeding all three products, and
+// gets output rows 16 rb + 4 q + i (i < 4) of group col back.
 //
 // Tile: the contiguous low bits [0, C) plus the block's bits at or above C.
 // C is chosen so that the tile holds 128 groups; every tile row is 2^C >= 128
 // contiguous amplitudes (>= 1 KiB), loaded and stored with 16-byte vectors.
-// Each of the 4 wavefronts of a workgroup owns 32 of the 128 groups: it holds
-// its rows of Uemb in VGPRs (the A operand, the same for every group), runs
-// the 2^k K-steps per 32-row block of the output, and writes the results into
-// its own LDS columns, which only it reads.
+// Each of the 4 wavefronts of a workgroup owns 32 of the 128 groups, in two
+// blocks of 16, and writes its results into the LDS entries of its own groups,
+// which only it reads. The matrix is staged in LDS of its own (8 KiB at
+// k = 5, XOR-swizzled rows), from which each lane picks its operands.
 #include "qs_internal.h"
 
 namespace qs {
 namespace {
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;  // 4 wavefronts
 constexpr int kGroupBits = 7;  // 128 groups per tile
@@ -38,22 +40,30 @@ __device__ __forceinline__ int insert_zero32(int x, int pos) {
 }
 
 template <int K, bool NT>
-__global__ void __launch_bounds__(kThreads) k_fused_mfma(float* __restrict__ a, FusedGeom g,
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+k_fused_mfma(float* __restrict__ a, FusedGeom g,
                                                          const float* __restrict__ mat) {
   constexpr int D = 1 << K;           // block dimension
-  constexpr int MB = 2 * D / 32;      // 32-row blocks of the embedded output
+  constexpr int RB = D / 16;          // 16-row blocks of the output
+  constexpr int S4 = D / 4;           // K-steps of 4 input rows
+  constexpr int BKT = RB == 1 ? 2 : 1;  // 16-group blocks in flight per wave
   constexpr int TB = K + kGroupBits;  // tile bits
+  // 32 KiB tile + 8 KiB matrix for k = 5: four workgroups fill a CU's LDS
   __shared__ float2 sm[1 << TB];
-  __shared__ int toff[D];             // tile offset of block row c
+  __shared__ float2 smat[D * D];
   const int C = g.C, h = g.h;
-
-  // tile offsets of the block rows
-  for (int c = threadIdx.x; c < D; c += kThreads) {
+  // tile offset of block row c (block bit j at tile bit tpos[j]); block rows
+  // with disjoint bit sets have OR-able offsets
+  auto toff = [&](int c) {
     int t = 0;
 #pragma unroll
     for (int j = 0; j < K; ++j) t |= ((c >> j) & 1) << g.tpos[j];
-    toff[c] = t;
-  }
+    return t;
+  };
+  // matrix entry (r, c) lives at r D + (c ^ 4 (r mod D/4)): the 16 rows x 4
+  // columns an operand read touches fall in distinct LDS banks
+  auto mpos = [](int r, int c) { return r * D + (c ^ (4 * (r & (D / 4 - 1)))); };
+
   // global index of tile entry t: low C bits in place, tile bit C+i -> qhi[i],
   // the workgroup index fills the remaining bits
   uint64_t ob = uint64_t(blockIdx.x) << C;
@@ -64,7 +74,15 @@ __global__ void __launch_bounds__(kThreads) k_fused_mfma(float* __restrict__ a, 
     return x;
   };
 
-  // load the tile: 2^h rows of 2^C amplitudes, two amplitudes per vector
+  // the matrix first, then the tile: 2^h rows of 2^C amplitudes, two
+  // amplitudes per vector (the matrix loads complete first)
+  constexpr int NM = (D * D + kThreads - 1) / kThreads;
+  float2 mreg[NM];
+#pragma unroll
+  for (int v = 0; v < NM; ++v) {
+    const int e = threadIdx.x + v * kThreads;
+    if (e < D * D) mreg[v] = reinterpret_cast<const float2*>(mat)[e];
+  }
   constexpr int NV = (1 << TB) / 2 / kThreads;
   float4 buf[NV];
   const int vrow = C - 1;  // log2 vectors per row
@@ -75,53 +93,75 @@ __global__ void __launch_bounds__(kThreads) k_fused_mfma(float* __restrict__ a, 
     buf[v] = ld16<NT>(reinterpret_cast<const float4*>(a + 2 * glob(t)));
   }
 #pragma unroll
+  for (int v = 0; v < NM; ++v) {
+    const int e = threadIdx.x + v * kThreads;
+    if (e < D * D) smat[mpos(e / D, e % D)] = mreg[v];
+  }
+#pragma unroll
   for (int v = 0; v < NV; ++v) {
     const int e = threadIdx.x + v * kThreads;
     const int t = ((e >> vrow) << C) | ((e & ((1 << vrow) - 1)) << 1);
     sm[t] = make_float2(buf[v].x, buf[v].y);
     sm[t + 1] = make_float2(buf[v].z, buf[v].w);
   }
-
-  // A operand: lane holds Uemb[32 mb + lane%32][2 ks + lane/32]
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int p = lane >> 5;
-  float A[MB][D];
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb) {
-    const int i = 32 * mb + (lane & 31);
-    const int r = i >> 1, q = i & 1;
-#pragma unroll
-    for (int ks = 0; ks < D; ++ks) {
-      const float ur = mat[2 * (r * D + ks)], ui = mat[2 * (r * D + ks) + 1];
-      A[mb][ks] = q == 0 ? (p == 0 ? ur : -ui) : (p == 0 ? ui : ur);
-    }
-  }
   __syncthreads();
 
-  // this lane's group: tile index of its base (zeros at the block's low bits)
-  int tb = wave * 32 + (lane & 31);
-  for (int i = 0; i < g.nlow; ++i) tb = insert_zero32(tb, g.lowblk[i]);
-
-  f32x16 acc[MB];
+  // this lane's operands: W_c[16 rb + col][4 s + q] for W_0 = Re U,
+  // W_1 = Im U, W_2 = Re U + Im U
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, col = lane & 15;
+  float A[3][RB][S4];
 #pragma unroll
-  for (int mb = 0; mb < MB; ++mb) acc[mb] = f32x16{};
+  for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-  for (int ks = 0; ks < D; ++ks) {
-    const float2 v = sm[tb | toff[ks]];
-    const float b = p ? v.y : v.x;
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-      acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[mb][ks], b, acc[mb], 0, 0, 0);
-  }
-  // D layout: lane, register e -> column lane%32, row 8*(e/4) + 4*(lane/32) + e%4;
-  // registers e and e+1 (e even) are the real and imaginary part of one output row
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb) {
-#pragma unroll
-    for (int e = 0; e < 16; e += 2) {
-      const int i = 32 * mb + 8 * (e >> 2) + 4 * p + (e & 3);
-      sm[tb | toff[i >> 1]] = make_float2(acc[mb][e], acc[mb][e + 1]);
+    for (int s = 0; s < S4; ++s) {
+      const float2 u = smat[mpos(16 * rb + col, 4 * s + q)];
+      A[0][rb][s] = u.x;
+      A[1][rb][s] = u.y;
+      A[2][rb][s] = u.x + u.y;
     }
+  const int qin = toff(q), qout = toff(4 * q);
+
+#pragma unroll
+  for (int b0 = 0; b0 < 2; b0 += BKT) {
+    int px[BKT];  // tile index of this lane's group in each block (zeros at the block's low bits)
+#pragma unroll
+    for (int j = 0; j < BKT; ++j) {
+      int tb = wave * 32 + 16 * (b0 + j) + col;
+      for (int i = 0; i < g.nlow; ++i) tb = insert_zero32(tb, g.lowblk[i]);
+      px[j] = tb | qin;
+    }
+    f32x4 p1[BKT][RB], p2[BKT][RB], p3[BKT][RB];
+#pragma unroll
+    for (int j = 0; j < BKT; ++j)
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) p1[j][rb] = p2[j][rb] = p3[j][rb] = f32x4{};
+#pragma unroll
+    for (int s = 0; s < S4; ++s) {
+      const int ks = toff(4 * s);
+#pragma unroll
+      for (int j = 0; j < BKT; ++j) {
+        const float2 v = sm[px[j] | ks];
+        const float vs = v.x + v.y;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          p1[j][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[0][rb][s], v.x, p1[j][rb], 0, 0, 0);
+          p2[j][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[1][rb][s], v.y, p2[j][rb], 0, 0, 0);
+          p3[j][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[2][rb][s], vs, p3[j][rb], 0, 0, 0);
+        }
+      }
+    }
+    // D layout: register i -> output row 16 rb + 4 q + i of group col
+#pragma unroll
+    for (int j = 0; j < BKT; ++j)
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const f32x4 x1 = p1[j][rb], x2 = p2[j][rb], x3 = p3[j][rb];
+          sm[(px[j] ^ qin) | qout | toff(16 * rb + i)] =
+              make_float2(x1[i] - x2[i], x3[i] - (x1[i] + x2[i]));
+        }
   }
   __syncthreads();
 

@@ -176,7 +176,7 @@ struct FusedGeom {
 };
 bool fused_geometry(int n, const int* qubits, int k, FusedGeom* g);
 
-// complex64 block of k = 4 or 5 qubits on v_mfma_f32_32x32x2f32; returns
+// complex64 block of k = 4 or 5 qubits on v_mfma_f32_16x16x4f32; returns
 // hipErrorNotSupported when the state is too small for the tile.
 hipError_t launch_fused_mfma(float* amps, int n, const int* qubits, int k, const float* mat,
                              hipStream_t s);
