@@ -20,6 +20,17 @@
 // blocks of 16, and writes its results into the LDS entries of its own groups,
 // which only it reads. The matrix is staged in LDS of its own (8 KiB at
 // k = 5, XOR-swizzled rows), from which each lane picks its operands.
+//
+// Which LDS banks a wavefront's 64 input reads hit depends on where the
+// block's bits fall in the tile (with the block on bits 0-4 all 16 groups of a
+// read share one bank pair). For such 5-qubit blocks the SWZ form keeps tile
+// index x at LDS entry x ^ ((x >> swz) & 15), a bijection (swz >= 4) that is
+// linear over XOR, so a lane's entry is its own part XOR a uniform part; the
+// host picks swz (fused_geometry) and keeps the plain layout wherever it
+// already spreads the reads (the extra index work costs more than spreading
+// the output writes, which nothing waits for, saves).
+#include <algorithm>
+
 #include "qs_internal.h"
 
 namespace qs {
@@ -39,7 +50,7 @@ __device__ __forceinline__ int insert_zero32(int x, int pos) {
   return lo | ((x ^ lo) << 1);
 }
 
-template <int K, bool NT>
+template <int K, bool NT, bool SWZ>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_fused_mfma(float* __restrict__ a, FusedGeom g,
                                                          const float* __restrict__ mat) {
@@ -49,9 +60,10 @@ k_fused_mfma(float* __restrict__ a, FusedGeom g,
   constexpr int BKT = RB == 1 ? 2 : 1;  // 16-group blocks in flight per wave
   constexpr int TB = K + kGroupBits;  // tile bits
   // 32 KiB tile + 8 KiB matrix for k = 5: four workgroups fill a CU's LDS
-  __shared__ float2 sm[1 << TB];
+  __shared__ __align__(16) float2 sm[1 << TB];
   __shared__ float2 smat[D * D];
-  const int C = g.C, h = g.h;
+  const int C = g.C, h = g.h, swz = g.swz;
+  auto lp = [&](int x) { return SWZ ? x ^ ((x >> swz) & 15) : x; };
   // tile offset of block row c (block bit j at tile bit tpos[j]); block rows
   // with disjoint bit sets have OR-able offsets
   auto toff = [&](int c) {
@@ -97,12 +109,14 @@ k_fused_mfma(float* __restrict__ a, FusedGeom g,
     const int e = threadIdx.x + v * kThreads;
     if (e < D * D) smat[mpos(e / D, e % D)] = mreg[v];
   }
+  // entries t and t + 1 (t even) land at lp(t) and lp(t) ^ 1: one 16-byte
+  // write, its halves swapped when lp(t) is odd
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const int e = threadIdx.x + v * kThreads;
-    const int t = ((e >> vrow) << C) | ((e & ((1 << vrow) - 1)) << 1);
-    sm[t] = make_float2(buf[v].x, buf[v].y);
-    sm[t + 1] = make_float2(buf[v].z, buf[v].w);
+    const int t = lp(((e >> vrow) << C) | ((e & ((1 << vrow) - 1)) << 1));
+    const float4 x = buf[v];
+    reinterpret_cast<float4*>(sm)[t >> 1] = (t & 1) ? make_float4(x.z, x.w, x.x, x.y) : x;
   }
   __syncthreads();
 
@@ -124,12 +138,15 @@ k_fused_mfma(float* __restrict__ a, FusedGeom g,
 
 #pragma unroll
   for (int b0 = 0; b0 < 2; b0 += BKT) {
-    int px[BKT];  // tile index of this lane's group in each block (zeros at the block's low bits)
+    // LDS entries of this lane's input row q and output row 4 q of its group
+    // in each block (the group's tile index has zeros at the block's bits)
+    int pin[BKT], pout[BKT];
 #pragma unroll
     for (int j = 0; j < BKT; ++j) {
       int tb = wave * 32 + 16 * (b0 + j) + col;
       for (int i = 0; i < g.nlow; ++i) tb = insert_zero32(tb, g.lowblk[i]);
-      px[j] = tb | qin;
+      pin[j] = lp(tb | qin);
+      pout[j] = lp(tb | qout);
     }
     f32x4 p1[BKT][RB], p2[BKT][RB], p3[BKT][RB];
 #pragma unroll
@@ -138,10 +155,10 @@ k_fused_mfma(float* __restrict__ a, FusedGeom g,
       for (int rb = 0; rb < RB; ++rb) p1[j][rb] = p2[j][rb] = p3[j][rb] = f32x4{};
 #pragma unroll
     for (int s = 0; s < S4; ++s) {
-      const int ks = toff(4 * s);
+      const int ks = lp(toff(4 * s));
 #pragma unroll
       for (int j = 0; j < BKT; ++j) {
-        const float2 v = sm[px[j] | ks];
+        const float2 v = sm[pin[j] ^ ks];
         const float vs = v.x + v.y;
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
@@ -159,7 +176,7 @@ k_fused_mfma(float* __restrict__ a, FusedGeom g,
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const f32x4 x1 = p1[j][rb], x2 = p2[j][rb], x3 = p3[j][rb];
-          sm[(px[j] ^ qin) | qout | toff(16 * rb + i)] =
+          sm[pout[j] ^ lp(toff(16 * rb + i))] =
               make_float2(x1[i] - x2[i], x3[i] - (x1[i] + x2[i]));
         }
   }
@@ -170,11 +187,65 @@ k_fused_mfma(float* __restrict__ a, FusedGeom g,
   for (int v = 0; v < NV; ++v) {
     const int e = threadIdx.x + v * kThreads;
     const int t = ((e >> vrow) << C) | ((e & ((1 << vrow) - 1)) << 1);
-    const float2 x0 = sm[t], x1 = sm[t + 1];
-    st16<NT>(reinterpret_cast<float4*>(a + 2 * glob(t)), make_float4(x0.x, x0.y, x1.x, x1.y));
+    const int l = lp(t);
+    const float4 x = reinterpret_cast<const float4*>(sm)[l >> 1];
+    st16<NT>(reinterpret_cast<float4*>(a + 2 * glob(t)), (l & 1) ? make_float4(x.z, x.w, x.x, x.y) : x);
   }
 }
 
+}  // namespace
+
+namespace {
+// Cost of one wavefront LDS access of 8-byte entries: 32 banks of 4 bytes,
+// so entry x occupies bank pair x mod 16; distinct entries on one pair are
+// served one after another (the wavefront takes at least 4 such steps).
+int lds_steps(const int* entry) {
+  int cnt[16] = {}, seen[64], ns = 0;
+  int worst = 0;
+  for (int l = 0; l < 64; ++l) {
+    bool dup = false;
+    for (int i = 0; i < ns && !dup; ++i) dup = seen[i] == entry[l];
+    if (dup) continue;
+    seen[ns++] = entry[l];
+    worst = std::max(worst, ++cnt[entry[l] & 15]);
+  }
+  return worst;
+}
+
+// The swizzle shift for a block's tile (16: none): among none and 4..11, the
+// one whose input reads take the fewest bank steps, then whose output writes
+// do; none whenever it reads as well as the best. Uniform bits (wavefront,
+// group block, K-step, output row) XOR every lane's entry with the same
+// value, which permutes the bank pairs, so one read and one write of
+// wavefront 0 decide. 4-qubit blocks keep the plain layout: eight of their
+// workgroups share a CU and hide the conflicts (swizzling measured slower).
+int lds_swizzle(const FusedGeom& g) {
+  if (g.k != 5) return 16;
+  auto toff = [&](int c) {
+    int t = 0;
+    for (int j = 0; j < g.k; ++j) t |= ((c >> j) & 1) << g.tpos[j];
+    return t;
+  };
+  int best = 16, best_cost = 1 << 30, plain_reads = 0;
+  for (int sw : {16, 4, 5, 6, 7, 8, 9, 10, 11}) {
+    int rd[64], wr[64];
+    for (int lane = 0; lane < 64; ++lane) {
+      const int q = lane >> 4, col = lane & 15;
+      int tb = col;
+      for (int i = 0; i < g.nlow; ++i) {
+        const int lo = tb & ((1 << g.lowblk[i]) - 1);
+        tb = lo | ((tb ^ lo) << 1);
+      }
+      const int xr = tb | toff(q), xw = tb | toff(4 * q);
+      rd[lane] = xr ^ ((xr >> sw) & 15);
+      wr[lane] = xw ^ ((xw >> sw) & 15);
+    }
+    const int reads = lds_steps(rd), cost = 64 * reads + lds_steps(wr);
+    if (sw == 16) plain_reads = reads;
+    if (cost < best_cost) best = sw, best_cost = cost;
+  }
+  return best_cost / 64 == plain_reads ? 16 : best;
+}
 }  // namespace
 
 // Tile geometry for a block on `qubits` (k of them) in an n-qubit state, or
@@ -211,6 +282,7 @@ bool fused_geometry(int n, const int* qubits, int k, FusedGeom* g) {
       g->tpos[j] = C + rank;
     }
   }
+  g->swz = lds_swizzle(*g);
   return true;
 }
 
@@ -221,8 +293,13 @@ hipError_t launch_fused_mfma(float* a, int n, const int* qubits, int k, const fl
   const uint64_t tiles = uint64_t(1) << (n - g.C - g.h);
   if (tiles > 0x7fffffffu) return hipErrorNotSupported;
   const bool nt = stream_sweep(n, 8, g.C);  // rows of 2^C contiguous amplitudes
-  auto kern = k == 4 ? (nt ? k_fused_mfma<4, true> : k_fused_mfma<4, false>)
-                     : (nt ? k_fused_mfma<5, true> : k_fused_mfma<5, false>);
+  const bool sw = g.swz < 16;
+  decltype(&k_fused_mfma<4, true, true>) kern;
+  if (k == 4)
+    kern = nt ? k_fused_mfma<4, true, false> : k_fused_mfma<4, false, false>;
+  else
+    kern = nt ? (sw ? k_fused_mfma<5, true, true> : k_fused_mfma<5, true, false>)
+              : (sw ? k_fused_mfma<5, false, true> : k_fused_mfma<5, false, false>);
   hipLaunchKernelGGL(kern, dim3(unsigned(tiles)), dim3(kThreads), 0, s, a, g, mat);
   return hipGetLastError();
 }

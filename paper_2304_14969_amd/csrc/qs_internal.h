@@ -173,6 +173,7 @@ struct FusedGeom {
   int qhi[6];
   int tpos[6];
   int lowblk[6];
+  int swz;  // LDS entry of tile index x: x ^ ((x >> swz) & 15) (swz >= 16: x)
 };
 bool fused_geometry(int n, const int* qubits, int k, FusedGeom* g);
 

@@ -60,6 +60,29 @@ def test_mfma_blocks_every_position(qs_lib, mfma):
         qs.tune_set("fused.mfma", 1)
 
 
+def test_mfma_blocks_random_positions(qs_lib):
+    """4- and 5-qubit matrix-core blocks on 40 random qubit sets of a 13-qubit
+    state, each against the oracle: where the block's bits fall decides the
+    tile's LDS layout, and for 5-qubit blocks with conflicting reads the
+    swizzled form and its shift (4-7 among these sets)."""
+    qs = qs_lib
+    n = 13
+    rng = np.random.default_rng(5)
+    a = workloads.gaussian_state(n, 22)
+    with qs.State(n, C64) as st:
+        for i in range(40):
+            k = 4 + (i % 2)
+            qq = [int(x) for x in rng.choice(n, size=k, replace=False)]
+            m = haar(2 ** k, 100 + i)
+            st.set_amplitudes(a)
+            st.profile_start()
+            st.apply_fused(qq, m)
+            assert f"fused{k}_mfma" in st.profile_stop(), qq
+            r = assert_parity(st.amplitudes(), dense.apply_matrix(a, n, qq, m), C64, f"block {i} on {qq}")
+            assert r["max_rel"] < 1e-5, (qq, r)
+
+
+
 def test_swaps_in_circuit_and_relabel(qs_lib):
     qs = qs_lib
     n = 13
