@@ -131,21 +131,22 @@ def _kernel_rates(prof: dict, flops_of=None) -> dict:
 
 
 def bench_circuit(qs, workloads, torch, n: int = 32, layers: int = 10, seed: int = 0,
-                  kmax: int = 4) -> dict:
+                  kmaxes=(4, 5)) -> dict:
     """Exact random circuit (U3 on every qubit, then CZ/iSWAP on a random
     matching, per layer): tile passes (several gates per HBM sweep, rounds of
     dense 4-qubit blocks on the matrix cores), and for comparison one sweep
-    per fused block of at most kmax qubits."""
+    per fused block of at most kmax qubits, for each kmax in kmaxes."""
     gates = workloads.random_circuit(n, layers, seed)
     st = qs.State(n, qs.C64)
     out = {"workload": f"random circuit n={n}, {layers} layers (U3 + CZ/iSWAP matching), "
                        f"seed {seed}, complex64", "gates": len(gates)}
-    for mode in ("tiles", "blocks"):
+    for mode in ("tiles",) + tuple(kmaxes):
         c = qs.Circuit(n).add_gates(gates)
         if mode == "tiles":
             c.use_tiles()
             ti = c.tile_info(qs.C64)
         else:
+            kmax = mode
             c.plan(kmax)
         st.set_basis(0)
         st.run(c)
@@ -179,6 +180,7 @@ def bench_circuit(qs, workloads, torch, n: int = 32, layers: int = 10, seed: int
 
 
 FP32_MFMA_PEAK_TFLOPS = 157.3
+FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
 def bench_sweeps(qs, np, torch, n: int = 30, reps: int = 6) -> dict:
@@ -213,26 +215,40 @@ def bench_sweeps(qs, np, torch, n: int = 30, reps: int = 6) -> dict:
            ("fused 4 (2, 8, 19, 27)", lambda: st.apply_fused([2, 8, 19, 27], haar(16, 3))),
            ("fused 5 (0, 6, 13, 22, 28)", lambda: st.apply_fused([0, 6, 13, 22, 28], haar(32, 4)))]
     out = {"workload": f"one gate or fused block at a time on n={n} qubits, complex64 "
-                       f"({2 ** n * 8 / 2 ** 30:g} GiB)", "peak_GBps": HBM_PEAK_GBS, "gates": {}}
-    for name, fn in ops:
-        fn()
-        torch.cuda.synchronize()
-        st.profile_start()
-        for _ in range(reps):
+                       f"({2 ** n * 8 / 2 ** 30:g} GiB); the c128 rows on n={n - 1} qubits, "
+                       f"complex128 (the same bytes)", "peak_GBps": HBM_PEAK_GBS, "gates": {}}
+
+    def measure(st, nq, ops, prefix, mfma_peak):
+        for name, fn in ops:
             fn()
-        torch.cuda.synchronize()
-        prof = st.profile_stop()
-        (kname, v), = prof.items()
-        avg = v["total_ms"] / v["launches"]
-        gbps = v["bytes"] / v["launches"] / (avg * 1e-3) / 1e9
-        row = {"kernel": kname, "avg_ms": round(avg, 4), "GBps": round(gbps, 1),
-               "frac": round(gbps / HBM_PEAK_GBS, 3)}
-        if kname.endswith("_mfma"):
-            k = int(kname[5])
-            tflops = 8.0 * 2 ** k * 2 ** n / (avg * 1e-3) / 1e12
-            row["TFLOPs"] = round(tflops, 2)
-            row["mfma_frac"] = round(tflops / FP32_MFMA_PEAK_TFLOPS, 3)
-        out["gates"][name] = row
+            torch.cuda.synchronize()
+            st.profile_start()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            prof = st.profile_stop()
+            (kname, v), = prof.items()
+            avg = v["total_ms"] / v["launches"]
+            gbps = v["bytes"] / v["launches"] / (avg * 1e-3) / 1e9
+            row = {"kernel": kname, "avg_ms": round(avg, 4), "GBps": round(gbps, 1),
+                   "frac": round(gbps / HBM_PEAK_GBS, 3)}
+            if kname.endswith("_mfma"):
+                k = int(kname[5])
+                tflops = 8.0 * 2 ** k * 2 ** nq / (avg * 1e-3) / 1e12
+                row["TFLOPs"] = round(tflops, 2)
+                row["mfma_frac"] = round(tflops / mfma_peak, 3)
+            out["gates"][prefix + name] = row
+
+    measure(st, n, ops, "", FP32_MFMA_PEAK_TFLOPS)
+    st.free()
+    # complex128 blocks run on the FP64 matrix cores
+    st = qs.State(n - 1, qs.C128)
+    st.set_basis(1)
+    ops = [("1q bit 5", lambda: st.apply_1q(5, H)),
+           ("fused 3 (6, 13, 25)", lambda: st.apply_fused([6, 13, 25], haar(8, 2))),
+           ("fused 4 (2, 8, 19, 27)", lambda: st.apply_fused([2, 8, 19, 27], haar(16, 3))),
+           ("fused 5 (0, 6, 13, 22, 28)", lambda: st.apply_fused([0, 6, 13, 22, 28], haar(32, 4)))]
+    measure(st, n - 1, ops, "c128 ", FP64_MFMA_PEAK_TFLOPS)
     st.free()
     return out
 

@@ -132,8 +132,11 @@ int qs_apply_swap(qs_state* st, int a, int b);
 /* Dense k-qubit block (1 <= k <= QS_MAX_FUSED): m is 2^k x 2^k complex
  * (2*4^k doubles), row/column bit j <-> qubits[j]. For every assignment of the
  * other n-k bits, the 2^k amplitudes that differ only in `qubits` are
- * multiplied by m. Complex64 blocks of 4 or 5 qubits run on the FP32 matrix
- * cores ("fused.mfma"); other widths and complex128 blocks on vector FMA. */
+ * multiplied by m. Blocks of 4 or 5 qubits run on the matrix cores
+ * ("fused.mfma": FP32 for complex64, FP64 for complex128) once the state
+ * holds a full tile (2^k x 128 amplitudes in complex64, 2^k x 64 in
+ * complex128, more when the block has low bits); other widths and smaller
+ * states on vector FMA. */
 int qs_apply_fused(qs_state* st, const int* qubits, int k, const double* m);
 
 /* A named gate (QS_GATE_* below) built in float64 inside the library and
@@ -412,7 +415,7 @@ int qs_circuit_info(const qs_circuit* c, int* ngates, int* nblocks, int* max_k);
 int qs_circuit_block(const qs_circuit* c, int i, int* k, int* qubits, double* m);
 /* Apply a circuit to a state of the same width (plans it first if needed).
  * Block matrices are uploaded once per precision and kept with the circuit.
- * Complex64 blocks of 4-5 qubits run on the matrix cores. A factorized state
+ * Blocks of 4-5 qubits run on the matrix cores. A factorized state
  * takes the gates one by one under its separation policy (see
  * qs_held_count for the gates an exact run holds back); when a gate fails
  * there (QS_E_CAPACITY: a merge past the state's cap), the gates before it
@@ -583,8 +586,9 @@ int qs_check(qs_state* st, double tol);
  *   "factor.kickback" 1 (default): a held gate whose target is a one-qubit
  *                    subsystem in an eigenstate of its matrix acts on its
  *                    control alone (qs_held_count); 0: off;
- *   "fused.mfma"     1 (default): complex64 blocks of 4 or 5 qubits run on the
- *                    matrix cores when their geometry fits; 0: vector FMA.
+ *   "fused.mfma"     1 (default): blocks of 4 or 5 qubits run on the matrix
+ *                    cores (FP32 for complex64, FP64 for complex128) when
+ *                    their geometry fits; 0: vector FMA.
  * QS_E_INVAL for an unknown key or a value out of range. */
 int qs_tune_set(const char* key, int64_t value);
 int qs_tune_get(const char* key, int64_t* value);

@@ -37,7 +37,7 @@ qs_free_fn g_free = nullptr;
 void* g_user = nullptr;
 int g_live_states = 0;
 qs::QftTuning g_qft_tune;
-int g_fused_mfma = 1;  // complex64 blocks of 4-5 qubits on the matrix cores
+int g_fused_mfma = 1;  // blocks of 4-5 qubits on the matrix cores (FP32 / FP64)
 int g_tile_mfma = 1;   // complex64 tile passes with dense rounds on the matrix cores
 
 void* dev_alloc(size_t bytes) {
@@ -211,24 +211,30 @@ struct ProfScope {
 };
 
 // Dense block on physical bits phys[0..k) with a device matrix in the state's
-// precision: complex64 blocks of 4 or 5 qubits go to the matrix cores when the
-// state holds a full tile, everything else to the vector-FMA kernel.
+// precision: blocks of 4 or 5 qubits go to the matrix cores (FP32 for
+// complex64, FP64 for complex128) when the state holds a full tile,
+// everything else to the vector-FMA kernel.
 hipError_t launch_block(qs_state* st, const int* phys, int k, const void* dmat) {
   static const char* names[] = {"", "fused1", "fused2", "fused3", "fused4", "fused5", "fused6"};
   static const char* mnames[] = {"", "", "", "", "fused4_mfma", "fused5_mfma", ""};
   const double bytes = 2.0 * std::ldexp(1.0, st->n) * ab(st);
+  qs::FusedGeom geom;
+  const bool mfma = g_fused_mfma && (k == 4 || k == 5) &&
+                    qs::fused_geometry(st->n, phys, k, &geom, int(ab(st)));
   if (st->dtype == QS_C64) {
-    if (g_fused_mfma && (k == 4 || k == 5)) {
-      qs::FusedGeom geom;
-      if (qs::fused_geometry(st->n, phys, k, &geom)) {
-        ProfScope ps(st, mnames[k], bytes);
-        return qs::launch_fused_mfma(static_cast<float*>(st->amps), st->n, phys, k,
-                                     static_cast<const float*>(dmat), st->stream);
-      }
+    if (mfma) {
+      ProfScope ps(st, mnames[k], bytes);
+      return qs::launch_fused_mfma(static_cast<float*>(st->amps), st->n, phys, k,
+                                   static_cast<const float*>(dmat), st->stream);
     }
     ProfScope ps(st, names[k], bytes);
     return qs::launch_apply_fused(static_cast<float*>(st->amps), st->n, phys, k,
                                   static_cast<const float*>(dmat), st->stream);
+  }
+  if (mfma) {
+    ProfScope ps(st, mnames[k], bytes);
+    return qs::launch_fused_mfma(static_cast<double*>(st->amps), st->n, phys, k,
+                                 static_cast<const double*>(dmat), st->stream);
   }
   ProfScope ps(st, names[k], bytes);
   return qs::launch_apply_fused(static_cast<double*>(st->amps), st->n, phys, k,

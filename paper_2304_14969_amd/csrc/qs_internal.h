@@ -175,11 +175,14 @@ struct FusedGeom {
   int lowblk[6];
   int swz;  // LDS entry of tile index x: x ^ ((x >> swz) & 15) (swz >= 16: x)
 };
-bool fused_geometry(int n, const int* qubits, int k, FusedGeom* g);
+bool fused_geometry(int n, const int* qubits, int k, FusedGeom* g, int amp_bytes);
 
-// complex64 block of k = 4 or 5 qubits on v_mfma_f32_16x16x4f32; returns
+// block of k = 4 or 5 qubits on the matrix cores (v_mfma_f32_16x16x4f32 for
+// complex64, v_mfma_f64_16x16x4f64 for complex128); returns
 // hipErrorNotSupported when the state is too small for the tile.
 hipError_t launch_fused_mfma(float* amps, int n, const int* qubits, int k, const float* mat,
+                             hipStream_t s);
+hipError_t launch_fused_mfma(double* amps, int n, const int* qubits, int k, const double* mat,
                              hipStream_t s);
 
 // ---------------------------------------------------------------- batches

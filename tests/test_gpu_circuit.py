@@ -32,16 +32,18 @@ def test_random_circuit_fused(qs_lib, dtype, kmax, n):
         assert_parity(st.amplitudes(), want, dtype, f"n={n} kmax={kmax}")
 
 
+@pytest.mark.parametrize("dtype", [C64, C128])
 @pytest.mark.parametrize("mfma", [0, 1])
-def test_mfma_blocks_every_position(qs_lib, mfma):
+def test_mfma_blocks_every_position(qs_lib, mfma, dtype):
     """k = 4, 5 blocks on low, high, mixed and bit-0 positions; the matrix-core
-    kernel (mfma=1) and the vector-FMA kernel (mfma=0) both match."""
+    kernel (mfma=1: FP32 or FP64 matrix cores) and the vector-FMA kernel
+    (mfma=0) both match."""
     qs = qs_lib
     n = 14
     a = workloads.gaussian_state(n, 21)
     qs.tune_set("fused.mfma", mfma)
     try:
-        with qs.State(n, C64) as st:
+        with qs.State(n, dtype) as st:
             st.set_amplitudes(a)
             want = a
             sets = [[0, 1, 2, 3], [13, 12, 11, 10], [3, 9, 0, 12], [1, 5, 8, 11, 13],
@@ -55,21 +57,23 @@ def test_mfma_blocks_every_position(qs_lib, mfma):
             st.apply_fused([2, 4, 6, 8, 10], haar(32, 99))
             want = dense.apply_matrix(want, n, [2, 4, 6, 8, 10], haar(32, 99))
             assert prof_want in st.profile_stop()
-            assert_parity(st.amplitudes(), want, C64, f"mfma={mfma}")
+            assert_parity(st.amplitudes(), want, dtype, f"mfma={mfma}")
     finally:
         qs.tune_set("fused.mfma", 1)
 
 
-def test_mfma_blocks_random_positions(qs_lib):
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_mfma_blocks_random_positions(qs_lib, dtype):
     """4- and 5-qubit matrix-core blocks on 40 random qubit sets of a 13-qubit
     state, each against the oracle: where the block's bits fall decides the
-    tile's LDS layout, and for 5-qubit blocks with conflicting reads the
-    swizzled form and its shift (4-7 among these sets)."""
+    tile's LDS layout, and for complex64 5-qubit blocks with conflicting reads
+    the swizzled form and its shift (4-7 among these sets)."""
     qs = qs_lib
     n = 13
     rng = np.random.default_rng(5)
     a = workloads.gaussian_state(n, 22)
-    with qs.State(n, C64) as st:
+    rel = 1e-5 if dtype == C64 else 1e-12
+    with qs.State(n, dtype) as st:
         for i in range(40):
             k = 4 + (i % 2)
             qq = [int(x) for x in rng.choice(n, size=k, replace=False)]
@@ -78,8 +82,8 @@ def test_mfma_blocks_random_positions(qs_lib):
             st.profile_start()
             st.apply_fused(qq, m)
             assert f"fused{k}_mfma" in st.profile_stop(), qq
-            r = assert_parity(st.amplitudes(), dense.apply_matrix(a, n, qq, m), C64, f"block {i} on {qq}")
-            assert r["max_rel"] < 1e-5, (qq, r)
+            r = assert_parity(st.amplitudes(), dense.apply_matrix(a, n, qq, m), dtype, f"block {i} on {qq}")
+            assert r["max_rel"] < rel, (qq, r)
 
 
 
