@@ -544,6 +544,8 @@ int qs_check(qs_state* st, double tol);
  *   "tile.low_bits"  contiguous low bits of a complex64 tile: 5 (default,
  *                    256-byte rows, 32 KiB tiles, four workgroups per CU),
  *                    6 (512-byte rows, 64 KiB) or 4 (128-byte rows, 16 KiB);
+ *                    complex128 tiles always have 16-amplitude (256-byte)
+ *                    rows, 32 KiB;
  *   "tile.mfma"      1 (default): complex64 tile passes run their rounds as
  *                    dense 4-qubit blocks on the matrix cores (any gate of at
  *                    most 4 qubits joins a pass); 0: one- and two-qubit gates

@@ -3,8 +3,8 @@
 //
 // A tile is 2^(C+H) amplitudes: the contiguous low bits [0, C) (rows of 2^C
 // amplitudes) and H = 7 row bits chosen by the planner (complex64: C = 5 by
-// default, 256-byte rows and 32 KiB tiles, 4 or 6 by knob; complex128: C = 5,
-// 512-byte rows, 64 KiB). The tile is staged
+// default, 256-byte rows and 32 KiB tiles, 4 or 6 by knob; complex128: C = 4,
+// 256-byte rows, 32 KiB). The tile is staged
 // in LDS (one complex of padding every 16 entries) and transformed round by
 // round, each round acting on 4 tile bits. Complex64 rounds are dense 4-qubit
 // blocks on the matrix cores (k_tile_mfma), each complex product as three
@@ -393,11 +393,13 @@ hipError_t launch_tile_mfma(float* a, int n, int low_bits, const TileRows& rows,
 }
 
 // complex64 (dtype 1): rows of 2^g_tile_low_c64 amplitudes (4: 128 bytes, 5:
-// 256 bytes, 6: 512 bytes); complex128: 32 (512 bytes). Rows of 32 complex64
+// 256 bytes, 6: 512 bytes); complex128: 16 (256 bytes). Rows of 32 complex64
 // amplitudes measured fastest for 10-layer random circuits (a 32 KiB tile
-// leaves room for four workgroups per CU, against two 64 KiB ones).
+// leaves room for four workgroups per CU, against two 64 KiB ones); for
+// complex128, rows of 16 (32 KiB tiles) took 4% less time per circuit than
+// rows of 32 (64 KiB), one more pass at 7% less time each.
 int g_tile_low_c64 = 5;
-int tile_low_bits(int dtype) { return dtype == 1 ? g_tile_low_c64 : 5; }
+int tile_low_bits(int dtype) { return dtype == 1 ? g_tile_low_c64 : 4; }
 
 namespace {
 template <typename R, int C>
