@@ -52,6 +52,9 @@ __global__ void __launch_bounds__(kBlock) k_fused_vec(R* __restrict__ a, uint64_
     }
 #pragma unroll
     for (int r = 0; r < D; ++r) {
+      // complex128: read the matrix row by row (left to itself the compiler
+      // holds all of M in registers, 256 VGPRs at k = 3, one wave per SIMD)
+      if constexpr (sizeof(R) == 8) asm volatile("" ::: "memory");
       R yr = 0, yi = 0;
 #pragma unroll
       for (int c = 0; c < D; ++c) {
