@@ -629,14 +629,34 @@ int qft_plan(int n, int start, int len, bool rev, const QftTuning& tune, QftPass
     if (!use_reg && lo < col_bits<R>()) lo = col_bits<R>();
     return (top > lo ? (top - lo + wmax - 1) / wmax : 0) + (start < lo ? 1 : 0);
   };
+  // whether the strided passes above a t-bit tile include a 7-bit one (their
+  // widths differ by at most one)
+  auto col_has7 = [&](int t) {
+    int lo = start > t ? start : t;
+    if (use_reg) return false;
+    if (lo < col_bits<R>()) lo = col_bits<R>();
+    const int w = top > lo ? top - lo : 0;
+    if (w == 0) return false;
+    const int p = (w + wmax - 1) / wmax;
+    return w / p == 7 || (w + p - 1) / p == 7;
+  };
   // contiguous tile bits: the knob, or (0) 12; complex64 states larger than
   // the last-level cache take 11 when that adds no pass (the 11-bit tile runs
-  // more workgroups per CU: 6.2 against 5.8 TB/s at 27 qubits)
+  // more workgroups per CU: 6.2 against 5.8 TB/s at 27 qubits); complex128
+  // ones take 11 (the 12-bit complex128 tile ran at 4.0, the 11-bit one at
+  // 5.0 TB/s at 29 qubits), or 10 when that adds no pass and leaves no 7-bit
+  // strided pass (4.4 against 5.4-5.7 TB/s for 6- and 8-bit ones): a 26-qubit
+  // transform 1.21 instead of 1.57 ms, a 29-qubit one 12.5 instead of 13.5
+  const bool big = (uint64_t(2 * sizeof(R)) << n) > (uint64_t(256) << 20);
   int T = tune.lds_bits > 0 ? tune.lds_bits : 12;
   if (T > lds_bits<R>()) T = lds_bits<R>();
-  if (tune.lds_bits == 0 && sizeof(R) == 4 && (uint64_t(8) << n) > (uint64_t(256) << 20) &&
-      pass_count(11) <= pass_count(12))
+  if (tune.lds_bits == 0 && big && sizeof(R) == 4 && pass_count(11) <= pass_count(12)) T = 11;
+  if (tune.lds_bits == 0 && big && sizeof(R) == 8) {
     T = 11;
+    if (pass_count(10) < pass_count(11) ||
+        (pass_count(10) == pass_count(11) && col_has7(11) && !col_has7(10)))
+      T = 10;
+  }
   if (T > n) T = n;
   int reg_lo = start > T ? start : T;
   if (!use_reg && reg_lo < col_bits<R>()) reg_lo = col_bits<R>();
