@@ -531,11 +531,12 @@ int qs_check(qs_state* st, double tol);
  *                    register passes of up to 5 bits;
  *   "qft.col_max"    most bits of one strided LDS pass: 8 (default; 256-byte
  *                    rows) or 7 (512-byte rows), both 64 KiB tiles; a 7-bit
- *                    pass always has 512-byte rows unless qft.col_rows = 1;
+ *                    complex64 pass always has 512-byte rows unless
+ *                    qft.col_rows = 1 (complex128 ones have 256-byte rows);
  *   "qft.col_rows"   1: strided passes of 7 bits use 256-byte rows (32 KiB
  *                    tiles); 2: also complex64 passes of 8 bits use 128-byte
- *                    rows (32 KiB); 0 (default): 512-byte rows for 7 bits,
- *                    256-byte rows for 8;
+ *                    rows (32 KiB); 0 (default): 512-byte rows for 7 bits
+ *                    (complex128: 256), 256-byte rows for 8;
  *   "qft.threads"    thread cap of the LDS tile launches: 256, 512, or 0
  *                    (default: 512 for strided passes of 8 bits, 256 for
  *                    the others);

@@ -512,9 +512,10 @@ hipError_t launch_col_c(R* a, int n, int start, int len, int lo, int sign, R sca
 }
 
 // Strided tiles of 2^G rows x 2^C columns: 512-byte rows (64 KiB at G = 7),
-// or 256-byte rows for G = 8 (64 KiB) and, with qft.col_rows >= 1, for G = 7
-// (32 KiB, more workgroups per CU); qft.col_rows = 2 also gives complex64
-// passes of 8 bits 128-byte rows (32 KiB).
+// or 256-byte rows for G = 8 (64 KiB) and, for complex128 or with
+// qft.col_rows >= 1, for G = 7 (32 KiB, more workgroups per CU: a complex128
+// 7-bit pass at 30 qubits 7.06 against 8.33 ms); qft.col_rows = 2 also gives
+// complex64 passes of 8 bits 128-byte rows (32 KiB).
 template <typename R, int G, bool REV>
 hipError_t launch_col(R* a, int n, int start, int len, int lo, int sign, R scale,
                       const QftTuning& tune, hipStream_t s) {
@@ -526,7 +527,7 @@ hipError_t launch_col(R* a, int n, int start, int len, int lo, int sign, R scale
     return launch_col_c<R, G, CB - 1, REV>(a, n, start, len, lo, sign, scale, tune, s);
   }
   if constexpr (G == 7)
-    if (tune.col_rows >= 1)
+    if (sizeof(R) == 8 || tune.col_rows >= 1)
       return launch_col_c<R, G, CB - 1, REV>(a, n, start, len, lo, sign, scale, tune, s);
   return launch_col_c<R, G, CB, REV>(a, n, start, len, lo, sign, scale, tune, s);
 }
@@ -629,34 +630,16 @@ int qft_plan(int n, int start, int len, bool rev, const QftTuning& tune, QftPass
     if (!use_reg && lo < col_bits<R>()) lo = col_bits<R>();
     return (top > lo ? (top - lo + wmax - 1) / wmax : 0) + (start < lo ? 1 : 0);
   };
-  // whether the strided passes above a t-bit tile include a 7-bit one (their
-  // widths differ by at most one)
-  auto col_has7 = [&](int t) {
-    int lo = start > t ? start : t;
-    if (use_reg) return false;
-    if (lo < col_bits<R>()) lo = col_bits<R>();
-    const int w = top > lo ? top - lo : 0;
-    if (w == 0) return false;
-    const int p = (w + wmax - 1) / wmax;
-    return w / p == 7 || (w + p - 1) / p == 7;
-  };
   // contiguous tile bits: the knob, or (0) 12; complex64 states larger than
   // the last-level cache take 11 when that adds no pass (the 11-bit tile runs
-  // more workgroups per CU: 6.2 against 5.8 TB/s at 27 qubits); complex128
-  // ones take 11 (the 12-bit complex128 tile ran at 4.0, the 11-bit one at
-  // 5.0 TB/s at 29 qubits), or 10 when that adds no pass and leaves no 7-bit
-  // strided pass (4.4 against 5.4-5.7 TB/s for 6- and 8-bit ones): a 26-qubit
-  // transform 1.21 instead of 1.57 ms, a 29-qubit one 12.5 instead of 13.5
+  // more workgroups per CU: 6.2 against 5.8 TB/s at 27 qubits), complex128
+  // ones always (the 12-bit complex128 tile, 64 KiB, ran at 4.0, the 11-bit
+  // one at 5.0 TB/s at 29 qubits; a 26-qubit transform 1.18 instead of
+  // 1.57 ms, a 29-qubit one 12.5 instead of 13.5)
   const bool big = (uint64_t(2 * sizeof(R)) << n) > (uint64_t(256) << 20);
   int T = tune.lds_bits > 0 ? tune.lds_bits : 12;
   if (T > lds_bits<R>()) T = lds_bits<R>();
-  if (tune.lds_bits == 0 && big && sizeof(R) == 4 && pass_count(11) <= pass_count(12)) T = 11;
-  if (tune.lds_bits == 0 && big && sizeof(R) == 8) {
-    T = 11;
-    if (pass_count(10) < pass_count(11) ||
-        (pass_count(10) == pass_count(11) && col_has7(11) && !col_has7(10)))
-      T = 10;
-  }
+  if (tune.lds_bits == 0 && big && (sizeof(R) == 8 || pass_count(11) <= pass_count(12))) T = 11;
   if (T > n) T = n;
   int reg_lo = start > T ? start : T;
   if (!use_reg && reg_lo < col_bits<R>()) reg_lo = col_bits<R>();
