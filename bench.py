@@ -32,8 +32,8 @@ HBM_PEAK_GBS = 8000.0
 # (`bench.py --calibrate-copy`: FETCH_SIZE reads 0.50002 of the bytes copied,
 # WRITE_SIZE 1.00000). Valid only for the kernel source they were taken on.
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_2304_14969_amd", "csrc", "k_qft.hip")
-TRAFFIC = {"sha256": "47d3b224782c6c39ccf0f8e107722aa845f847277499b099837777bc60862c31",
-           "bytes_per_launch": {"qft_col8": 2147844379, "qft_lds": 2147584957}}
+TRAFFIC = {"sha256": "520832e791190b013b4035e0ae100f64b1a51a8c2b966522abec2112a7e844bb",
+           "bytes_per_launch": {"qft_col8": 2147830219, "qft_lds": 2147588925}}
 
 
 def measured_traffic(kernel: str):
