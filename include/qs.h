@@ -395,12 +395,12 @@ int qs_circuit_plan(qs_circuit* c, int kmax);
 /* Run this circuit on dense states as tile passes (on != 0) instead of
  * fused blocks. A pass reads and writes the ket once for every one- and
  * two-qubit gate it holds: a tile is the contiguous low bits (complex64:
- * "tile.low_bits", 5 by default; complex128: 5) plus 7 bits chosen per pass, and the passes
+ * "tile.low_bits", 5 by default; complex128: 4) plus 7 bits chosen per pass, and the passes
  * are planned on the state's physical bits at the first run (re-planned when
  * the state's labelling differs). Gates too wide for a round (more than 4
  * qubits with "tile.mfma" on, more than 2 otherwise or for complex128) run
- * as dense blocks between passes. States with fewer qubits than a tile (13 / 12) use
- * fused blocks. Same results as the block path up to float rounding order. */
+ * as dense blocks between passes. States with fewer qubits than a tile (its
+ * low bits + 7) use fused blocks. Same results as the block path up to float rounding order. */
 int qs_circuit_use_tiles(qs_circuit* c, int on);
 /* Tile plan of the circuit for a state in the identity labelling (current
  * "tile.*" knobs): passes,
