@@ -1010,11 +1010,11 @@ int run_tiles(qs_state* st, qs_circuit* c) {
 
 }  // namespace
 
-// Runs a circuit on a dense state as tile passes (when chosen and the state
-// has at least one tile's bits) or as planned blocks (planned with the
-// default block width first if needed), one sweep each; the circuit's SWAP
-// renaming is then folded into the state's labels. Factorized states apply
-// the gates one by one.
+// Runs a circuit on a dense state as tile passes (unless blocks were chosen;
+// the state must hold one tile's bits) or as planned blocks (planned with
+// the default block width first if needed), one sweep each; the circuit's
+// SWAP renaming is then folded into the state's labels. Factorized states
+// apply the gates one by one.
 int qs_run(qs_state* st, qs_circuit* c) {
   if (int rc = check_state(st)) return rc;
   if (!c) return fail(QS_E_INVAL, "circuit is NULL");
@@ -1251,7 +1251,7 @@ int qs_run(qs_state* st, qs_circuit* c) {
     if (int rc = fact_rc(st, qs::fact_end_run(f, apply_all_or_prefix()))) return rc;
     return fact_rc(st, qs::fact_relabel(f, c->pos.data()));
   }
-  if (c->tiles && !c->gates.empty() &&
+  if (c->tiles != 0 && !c->gates.empty() &&
       st->n >= qs::tile_low_bits(st->dtype) + qs::kTileRowBits) {
     if (int rc = run_tiles(st, c)) return rc;
     int np[64];

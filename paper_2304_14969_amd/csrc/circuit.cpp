@@ -516,12 +516,13 @@ int qs_circuit_plan(qs_circuit* c, int kmax) {
   c->kmax = kmax;
   c->blocks = qs::fuse(c->gates, c->n, kmax);
   c->planned = true;
+  if (c->tiles < 0) c->tiles = 0;  // planning blocks asks for blocks
   return QS_OK;
 }
 
 int qs_circuit_use_tiles(qs_circuit* c, int on) {
   if (!c) return cfail(QS_E_INVAL, "circuit is NULL");
-  c->tiles = on != 0;
+  c->tiles = on != 0 ? 1 : 0;
   return QS_OK;
 }
 

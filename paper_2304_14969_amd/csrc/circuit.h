@@ -113,8 +113,10 @@ struct qs_circuit {
   // device copies of the block matrices, per precision (owned)
   void* dmat[2] = {nullptr, nullptr};
   std::vector<size_t> off[2];   // element offset of each block's matrix
-  // tile passes (dense runs), planned per precision and physical labelling
-  bool tiles = false;
+  // tile passes (dense runs), planned per precision and physical labelling:
+  // 1 on, 0 off (qs_circuit_use_tiles(c, 0), or blocks planned with
+  // qs_circuit_plan before any choice), -1 not chosen (on)
+  int tiles = -1;
   struct TileCache {
     std::vector<int> key;  // physical bit of every virtual position
     qs::TilePlan plan;

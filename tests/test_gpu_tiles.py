@@ -104,3 +104,31 @@ def test_tiles_agree_with_blocks_at_28(qs_lib, tile_mode):
         assert abs(abs(a.inner(b)) - 1.0) < 1e-5
     ct.free()
     cb.free()
+
+
+@pytest.mark.parametrize("dtype,n", [(C64, 14), (C128, 12), (C64, 9)])
+def test_default_run_mode(qs_lib, dtype, n):
+    """A circuit run without qs_circuit_plan or qs_circuit_use_tiles takes
+    tile passes when the state holds a tile (12 qubits in complex64, 11 in
+    complex128), fused blocks below that; blocks planned before any choice,
+    or tiles switched off, run as blocks; switching tiles on after planning
+    runs tiles. Every form against the oracle."""
+    qs = qs_lib
+    gates = workloads.random_circuit(n, 4, 60 + n)
+    want = dense.run_circuit(dense.zero_state(n), n, gates)
+    tiles_fit = n >= (12 if dtype == C64 else 11)
+    cases = [("default", lambda c: c, tiles_fit),
+             ("plan", lambda c: c.plan(4), False),
+             ("tiles off", lambda c: c.use_tiles(False), False),
+             ("plan then tiles", lambda c: c.plan(4).use_tiles(), tiles_fit),
+             ("tiles then plan", lambda c: c.use_tiles().plan(4), tiles_fit)]
+    for name, setup, expect_tiles in cases:
+        c = setup(qs.Circuit(n).add_gates(gates))
+        with qs.State(n, dtype) as st:
+            st.profile_start()
+            st.run(c)
+            prof = st.profile_stop()
+            ran_tiles = any(k.startswith("tile_") for k in prof)
+            assert ran_tiles == expect_tiles, (name, sorted(prof))
+            assert_parity(st.amplitudes(), want, dtype, name)
+        c.free()
