@@ -337,14 +337,51 @@ TilePlan plan_tiles(const std::vector<Gate>& gates, int n, int C, int H, int W, 
         r.mat = plan.mats.size();
         plan.mats.insert(plan.mats.end(), u.begin(), u.end());
       } else {
+        // one-qubit gates folded into the round's two-qubit gates: into the
+        // last two-qubit gate on their bit (from the left) when there is one,
+        // else into the next (from the right); one-qubit products on bits no
+        // two-qubit gate of the round touches stay one-qubit gates (they
+        // commute with the rest of the round)
+        struct Out { int kind, j1, j2; std::vector<cd> m; };
+        std::vector<Out> outg;
+        std::vector<int> last(W, -1);            // per round bit: its last two-qubit gate
+        std::vector<std::vector<cd>> pend(W);    // per round bit: pending one-qubit product
         for (int gi : grp) {
           const Gate& g = gates[pass[gi]];
+          const int j1 = int(std::find(rb.begin(), rb.end(), tq[gi][0]) - rb.begin());
+          if (g.k == 1) {
+            if (last[j1] >= 0) {
+              Out& o = outg[size_t(last[j1])];
+              const int at = o.j1 == j1 ? 0 : 1;
+              left_apply(o.m, 2, g.m, 1, &at);
+            } else {
+              if (pend[j1].empty()) pend[j1] = eye(1);
+              const int at = 0;
+              left_apply(pend[j1], 1, g.m, 1, &at);
+            }
+            continue;
+          }
+          const int j2 = int(std::find(rb.begin(), rb.end(), tq[gi][1]) - rb.begin());
+          std::vector<cd> m = eye(2);
+          const int bit0 = 0, bit1 = 1, both[2] = {0, 1};
+          if (!pend[j1].empty()) left_apply(m, 2, pend[j1], 1, &bit0);
+          if (!pend[j2].empty()) left_apply(m, 2, pend[j2], 1, &bit1);
+          left_apply(m, 2, g.m, 2, both);
+          pend[j1].clear();
+          pend[j2].clear();
+          last[j1] = last[j2] = int(outg.size());
+          outg.push_back({2, j1, j2, std::move(m)});
+        }
+        for (int j = 0; j < W; ++j)
+          if (!pend[j].empty()) outg.push_back({1, j, 0, std::move(pend[j])});
+        r.ng = int(outg.size());
+        for (Out& o : outg) {
           TileGate tg;
-          tg.kind = g.k;
-          tg.j1 = int(std::find(rb.begin(), rb.end(), tq[gi][0]) - rb.begin());
-          tg.j2 = g.k == 2 ? int(std::find(rb.begin(), rb.end(), tq[gi][1]) - rb.begin()) : 0;
+          tg.kind = o.kind;
+          tg.j1 = o.j1;
+          tg.j2 = o.j2;
           tg.mat = plan.mats.size();
-          plan.mats.insert(plan.mats.end(), g.m.begin(), g.m.end());
+          plan.mats.insert(plan.mats.end(), o.m.begin(), o.m.end());
           plan.gates.push_back(tg);
         }
       }
