@@ -188,7 +188,7 @@ int prepare(qs_batch* b, qs_circuit* const* circs, int kmax) {
     for (int q = 0; q < c->n; ++q)
       if (c->pos[q] != q) return bfail(QS_E_UNSUPPORTED, "batched circuits cannot contain SWAP gates");
     if (!c->planned || c->kmax != kmax)
-      if (int rc = qs_circuit_plan(c, kmax)) return rc;
+      if (int rc = qs::circuit_plan_blocks(c, kmax)) return rc;
     for (const auto& blk : c->blocks)
       if (blk.k > 5) return bfail(QS_E_UNSUPPORTED, "batched blocks have at most 5 qubits");
   }

@@ -1260,7 +1260,7 @@ int qs_run(qs_state* st, qs_circuit* c) {
     return QS_OK;
   }
   if (!c->planned)
-    if (int rc = qs_circuit_plan(c, c->kmax)) return rc;
+    if (int rc = qs::circuit_plan_blocks(c, c->kmax)) return rc;
   const int prec = st->dtype == QS_C64 ? 0 : 1;
   if (!c->dmat[prec] && !c->blocks.empty()) {
     size_t total = 0;

@@ -473,6 +473,21 @@ int cfail(int code, const char* fmt, ...) {
 }
 }  // namespace
 
+namespace qs {
+// The block plan alone: what a dense run without tiles or a batch needs,
+// without the caller's choice of run mode that qs_circuit_plan records.
+int circuit_plan_blocks(qs_circuit* c, int kmax) {
+  if (!c) return cfail(QS_E_INVAL, "circuit is NULL");
+  if (kmax == 0) kmax = 5;
+  if (kmax < 1 || kmax > QS_MAX_FUSED) return cfail(QS_E_INVAL, "kmax = %d outside [1, %d]", kmax, QS_MAX_FUSED);
+  circuit_invalidate(c);
+  c->kmax = kmax;
+  c->blocks = fuse(c->gates, c->n, kmax);
+  c->planned = true;
+  return QS_OK;
+}
+}  // namespace qs
+
 extern "C" {
 
 int qs_circuit_create(int n, qs_circuit** out) {
@@ -545,14 +560,9 @@ int qs_circuit_add_matrix(qs_circuit* c, const int* qubits, int k, const double*
   return add_checked(c, qubits, k, std::move(mm));
 }
 
+
 int qs_circuit_plan(qs_circuit* c, int kmax) {
-  if (!c) return cfail(QS_E_INVAL, "circuit is NULL");
-  if (kmax == 0) kmax = 5;
-  if (kmax < 1 || kmax > QS_MAX_FUSED) return cfail(QS_E_INVAL, "kmax = %d outside [1, %d]", kmax, QS_MAX_FUSED);
-  qs::circuit_invalidate(c);
-  c->kmax = kmax;
-  c->blocks = qs::fuse(c->gates, c->n, kmax);
-  c->planned = true;
+  if (int rc = qs::circuit_plan_blocks(c, kmax)) return rc;
   if (c->tiles < 0) c->tiles = 0;  // planning blocks asks for blocks
   return QS_OK;
 }

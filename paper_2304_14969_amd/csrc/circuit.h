@@ -100,6 +100,11 @@ void tile_tables(const TilePlan& pl, bool c64, std::vector<unsigned char>* out, 
 // W_2 = Re U + Im U (summed in float64), s = 0 .. 3.
 void embed_round(const cd* u, float* out);
 
+// Fuse a circuit's gates into blocks of at most kmax qubits (0 = 5) without
+// recording a choice of run mode (internal planning; qs_circuit_plan does
+// record it).
+int circuit_plan_blocks(qs_circuit* c, int kmax);
+
 }  // namespace qs
 
 struct qs_circuit {

@@ -112,7 +112,8 @@ def test_default_run_mode(qs_lib, dtype, n):
     tile passes when the state holds a tile (12 qubits in complex64, 11 in
     complex128), fused blocks below that; blocks planned before any choice,
     or tiles switched off, run as blocks; switching tiles on after planning
-    runs tiles. Every form against the oracle."""
+    runs tiles; the library's own block planning (a batch run of the same
+    circuit first) leaves the choice open. Every form against the oracle."""
     qs = qs_lib
     gates = workloads.random_circuit(n, 4, 60 + n)
     want = dense.run_circuit(dense.zero_state(n), n, gates)
@@ -121,7 +122,16 @@ def test_default_run_mode(qs_lib, dtype, n):
              ("plan", lambda c: c.plan(4), False),
              ("tiles off", lambda c: c.use_tiles(False), False),
              ("plan then tiles", lambda c: c.plan(4).use_tiles(), tiles_fit),
-             ("tiles then plan", lambda c: c.use_tiles().plan(4), tiles_fit)]
+             ("tiles then plan", lambda c: c.use_tiles().plan(4), tiles_fit),
+             ("after a batch run", lambda c: batch_first(c), tiles_fit)]
+
+    def batch_first(c):
+        b = qs.Batch([n], dtype)
+        b.run([c], 4)
+        assert_parity(b.amplitudes(0), want, dtype, "batch")
+        b.free()
+        return c
+
     for name, setup, expect_tiles in cases:
         c = setup(qs.Circuit(n).add_gates(gates))
         with qs.State(n, dtype) as st:
