@@ -455,12 +455,14 @@ int qs_batch_run(qs_batch* b, qs_circuit* const* circuits, int kmax);
  * launches the graph. The graph is kept until the next run or capture. */
 int qs_batch_capture(qs_batch* b, qs_circuit* const* circuits, int kmax);
 int qs_batch_replay(qs_batch* b);
-/* on != 0: complex64 kets of at least 12 qubits run their circuits as tile
- * passes (as qs_circuit_use_tiles, tiles of 5 low + 7 chosen bits, dense
- * 4-qubit rounds on the matrix cores), batched as one launch per pass index
- * over every ket that has that pass; other kets (fewer qubits, complex128,
- * gates of more than 4 qubits) keep the block launches. Drops a prepared
- * run or graph; applies to the next run or capture. */
+/* on != 0 (the default): complex64 kets of at least 12 qubits run their
+ * circuits as tile passes (as qs_circuit_use_tiles, tiles of 5 low + 7 chosen
+ * bits, dense 4-qubit rounds on the matrix cores), batched as one launch per
+ * pass index over every ket that has that pass; other kets (fewer qubits,
+ * complex128, gates of more than 4 qubits) keep the block launches (1024
+ * circuits of 12-20 qubits: 12.0-12.4 ms against 27.4 ms with blocks
+ * only). on = 0: blocks for every ket. Drops a prepared run or graph;
+ * applies to the next run or capture. */
 int qs_batch_use_tiles(qs_batch* b, int on);
 /* Launches per run of the last prepared run and arena size in amplitudes. */
 int qs_batch_info(const qs_batch* b, int* launches, uint64_t* total_amps);

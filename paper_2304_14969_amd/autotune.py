@@ -114,9 +114,11 @@ def tune_fusion(n: int, gates, kmaxes=(3, 4, 5), tile_bits=(4, 5, 6), reps: int 
 
 
 def tune_batch(widths, circuits, kmaxes=(2, 3, 4, 5), reps: int = 3) -> dict:
-    """Fastest block width for batched runs of these circuits."""
+    """Fastest block width for batched runs of these circuits (every ket on
+    blocks: tile passes off)."""
     import torch
     b = Batch(widths, C64, stream=torch.cuda.Stream())
+    b.use_tiles(False)
     results = []
     try:
         for kmax in kmaxes:

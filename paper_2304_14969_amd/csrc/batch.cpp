@@ -60,7 +60,7 @@ struct qs_batch {
   // tables of the last prepared run
   qs::BatchItem* d_items = nullptr;
   void* d_mats = nullptr;
-  bool tiles = false;                 // complex64 kets of >= 12 qubits as tile passes
+  bool tiles = true;                  // complex64 kets of >= 12 qubits as tile passes
   qs::TileItem* d_titems = nullptr;   // tile items of every pass launch
   // what the prepared tables were built from: the circuits, their generations,
   // kmax and the tile switch (a run with the same reuses them)
